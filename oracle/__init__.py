@@ -1,0 +1,214 @@
+"""ctypes binding of the CPU oracle (test infrastructure only).
+
+Only tests/, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  It wraps liboracle.so, a plain single-threaded C
+implementation of the DSMC particle loop that shares no code with the GPU
+library.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import LIB, build as _build
+
+_lib = None
+
+STAGE_MOVE, STAGE_INJECT, STAGE_SORT, STAGE_COLLIDE, STAGE_SAMPLE = 1, 2, 4, 8, 16
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB):
+        _build()
+    lib = C.CDLL(LIB)
+    P = C.c_void_p
+    d, i, u32, i64 = C.c_double, C.c_int, C.c_uint32, C.c_int64
+    lib.oracle_create.restype = P
+    lib.oracle_create.argtypes = [i, P, i, P, i, P, P, P, i, P, P, P, P, P,
+                                  d, d, d, d, d, d, u32, u32, i, i, i, i]
+    lib.oracle_last_error.restype = C.c_char_p
+    lib.oracle_destroy.argtypes = [P]
+    lib.oracle_init_fill.argtypes = [P, d, d, P]
+    lib.oracle_step.argtypes = [P, i]
+    lib.oracle_step_stages.argtypes = [P, i]
+    lib.oracle_num_particles.restype = i64
+    lib.oracle_num_particles.argtypes = [P]
+    lib.oracle_get_particles.argtypes = [P, P, P, P, P]
+    lib.oracle_set_particles.argtypes = [P, i64, P, P, P, P, u32, u32]
+    lib.oracle_get_smax.argtypes = [P, P]
+    lib.oracle_set_smax.argtypes = [P, P]
+    lib.oracle_step_index.restype = u32
+    lib.oracle_step_index.argtypes = [P]
+    lib.oracle_next_pid.restype = u32
+    lib.oracle_next_pid.argtypes = [P]
+    lib.oracle_get_pair_counts.argtypes = [P, P, P]
+    lib.oracle_get_counters.argtypes = [P, P]
+    lib.oracle_get_sums.argtypes = [P, i, P]
+    lib.oracle_num_steady.restype = i64
+    lib.oracle_num_steady.argtypes = [P]
+    lib.oracle_set_local_acc.argtypes = [P, P]
+    lib.oracle_fields.argtypes = [P, i, P]
+    lib.oracle_get_volumes.argtypes = [P, P]
+    lib.oracle_get_neighbours.argtypes = [P, P]
+    lib.oracle_get_tets.argtypes = [P, P]
+    lib.oracle_num_faces.argtypes = [P]
+    lib.oracle_trace_one.argtypes = [P, P, P, i, u32, u32, d]
+    lib.oracle_philox.argtypes = [P, P, P]
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def philox(ctr, key):
+    lib = _load()
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib.oracle_philox(_p(c), _p(k), _p(out))
+    return out
+
+
+class Oracle:
+    """One oracle simulation built from a workloads.Workload."""
+
+    def __init__(self, wl, fill=True):
+        lib = _load()
+        self.lib = lib
+        m, sp, run = wl.mesh, wl.species, wl.run
+        self._keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a
+
+        xyz = arr(m.xyz, np.float64)
+        tets = arr(m.tets, np.int32)
+        bf = arr(m.bfaces, np.int32)
+        bg = arr(m.bgroup, np.int32)
+        bp = arr(m.bpartner, np.int32) if m.bpartner is not None else None
+        bcs = wl.boundaries
+        gk = arr([b.kind for b in bcs], np.int32)
+        gT = arr([b.T for b in bcs], np.float64)
+        gu = arr([b.u for b in bcs], np.float64)
+        gn = arr([b.n for b in bcs], np.float64)
+        gs = arr([b.shift for b in bcs], np.float64)
+        self.nt = int(tets.shape[0])
+        self.h = lib.oracle_create(
+            int(xyz.shape[0]), _p(xyz), self.nt, _p(tets), int(bf.shape[0]), _p(bf), _p(bg), _p(bp),
+            len(bcs), _p(gk), _p(gT), _p(gu), _p(gn), _p(gs),
+            sp.mass, sp.d_ref, sp.omega, sp.T_ref, run.F_N, run.dt,
+            run.seed & 0xFFFFFFFF, run.case_id, run.vel_fp32, run.n_ss, run.n_a, run.ewma_on)
+        if not self.h:
+            raise ValueError("oracle_create: " + lib.oracle_last_error().decode())
+        self.wl = wl
+        if fill:
+            u0 = np.asarray(run.u0, dtype=np.float64)
+            lib.oracle_init_fill(self.h, run.n0, run.T0, _p(u0))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.oracle_destroy(self.h)
+            self.h = None
+
+    # -- stepping ---------------------------------------------------------
+    def step(self, n=1):
+        self.lib.oracle_step(self.h, n)
+
+    def step_stages(self, mask):
+        self.lib.oracle_step_stages(self.h, mask)
+
+    # -- state -------------------------------------------------------------
+    @property
+    def np(self):
+        return int(self.lib.oracle_num_particles(self.h))
+
+    def particles(self):
+        n = self.np
+        x = np.zeros((n, 3)); v = np.zeros((n, 3))
+        c = np.zeros(n, np.int32); p = np.zeros(n, np.uint32)
+        self.lib.oracle_get_particles(self.h, _p(x), _p(v), _p(c), _p(p))
+        return dict(x=x, v=v, cell=c, pid=p)
+
+    def set_particles(self, x, v, cell, pid, step, next_pid):
+        x = np.ascontiguousarray(x, np.float64); v = np.ascontiguousarray(v, np.float64)
+        cell = np.ascontiguousarray(cell, np.int32); pid = np.ascontiguousarray(pid, np.uint32)
+        r = self.lib.oracle_set_particles(self.h, len(cell), _p(x), _p(v), _p(cell), _p(pid),
+                                          step, next_pid)
+        if r != 0:
+            raise ValueError(self.lib.oracle_last_error().decode())
+
+    def smax(self):
+        o = np.zeros(self.nt)
+        self.lib.oracle_get_smax(self.h, _p(o))
+        return o
+
+    def set_smax(self, a):
+        a = np.ascontiguousarray(a, np.float64)
+        self.lib.oracle_set_smax(self.h, _p(a))
+
+    @property
+    def step_index(self):
+        return int(self.lib.oracle_step_index(self.h))
+
+    @property
+    def next_pid(self):
+        return int(self.lib.oracle_next_pid(self.h))
+
+    def pair_counts(self):
+        a = np.zeros(self.nt, np.int32); b = np.zeros(self.nt, np.int32)
+        self.lib.oracle_get_pair_counts(self.h, _p(a), _p(b))
+        return a, b
+
+    def counters(self):
+        o = np.zeros(5, np.int64)
+        self.lib.oracle_get_counters(self.h, _p(o))
+        return dict(zip(["hops", "wall_hits", "injected", "removed", "lost"], o.tolist()))
+
+    def sums(self, which=0):
+        o = np.zeros((self.nt, 13))
+        self.lib.oracle_get_sums(self.h, which, _p(o))
+        return o
+
+    @property
+    def n_steady(self):
+        return int(self.lib.oracle_num_steady(self.h))
+
+    def set_local_acc(self, flags):
+        f = np.ascontiguousarray(flags, np.uint8)
+        self.lib.oracle_set_local_acc(self.h, _p(f))
+
+    def fields(self, which=0):
+        o = np.zeros((self.nt, 15))
+        self.lib.oracle_fields(self.h, which, _p(o))
+        return o
+
+    def volumes(self):
+        o = np.zeros(self.nt)
+        self.lib.oracle_get_volumes(self.h, _p(o))
+        return o
+
+    def neighbours(self):
+        o = np.zeros((self.nt, 4), np.int32)
+        self.lib.oracle_get_neighbours(self.h, _p(o))
+        return o
+
+    def tets(self):
+        o = np.zeros((self.nt, 4), np.int32)
+        self.lib.oracle_get_tets(self.h, _p(o))
+        return o
+
+    @property
+    def n_faces(self):
+        return int(self.lib.oracle_num_faces(self.h))
+
+    def trace_one(self, x, v, cell, pid, step, t):
+        x = np.array(x, np.float64); v = np.array(v, np.float64)
+        c = self.lib.oracle_trace_one(self.h, _p(x), _p(v), int(cell), pid, step, t)
+        return c, x, v

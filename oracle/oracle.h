@@ -1,0 +1,88 @@
+/*
+ * Plain CPU oracle of the DSMC particle loop (test infrastructure only).
+ *
+ * This library is a slow, single-threaded, obviously-sequential statement of
+ * what the GPU path computes.  It is used only by the test-suite, the smoke
+ * check and the CPU-baseline leg of the benchmark; the product path never
+ * links, loads or calls it.  It shares no code with the GPU library: both are
+ * written independently from the paper (DSMC step splitting, section 2.1;
+ * cell sampling, eq. dsmc_temperatures; exponential averaging,
+ * eq. exponential_average_moments_ch3; steady average,
+ * eq. steady_average_moments_ch3) and from the written arithmetic contracts
+ * for geometry, random numbers and operation order.
+ *
+ * Units are SI.  Every floating-point operation is a separate IEEE binary64
+ * operation (built with -ffp-contract=off, no fast-math).
+ */
+#ifndef DSMC_ORACLE_H
+#define DSMC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct osim osim;
+
+enum { O_BC_DIFFUSE = 0, O_BC_SPECULAR = 1, O_BC_INFLOW = 2, O_BC_OUTFLOW = 3, O_BC_PERIODIC = 4 };
+enum { O_STAGE_MOVE = 1, O_STAGE_INJECT = 2, O_STAGE_SORT = 4, O_STAGE_COLLIDE = 8, O_STAGE_SAMPLE = 16 };
+
+/* Philox4x32-10 block (counter ctr[4], key key[2]) -> out[4]. */
+void oracle_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Build the simulation: mesh, boundary groups, species and run parameters.
+ * Returns NULL on an invalid mesh (message via oracle_last_error()). */
+osim* oracle_create(int nv, const double* xyz, int nt, const int* tet,
+                    int nb, const int* bface, const int* bgroup, const int* bpartner,
+                    int ng, const int* g_kind, const double* g_T, const double* g_u,
+                    const double* g_n, const double* g_shift,
+                    double mass, double d_ref, double omega, double T_ref,
+                    double F_N, double dt, uint32_t seed, uint32_t case_id,
+                    int vel_fp32, int n_ss, int n_a, int ewma_on);
+const char* oracle_last_error(void);
+void oracle_destroy(osim*);
+
+/* Initial equilibrium fill at (n0, T0, u0); also sets (sigma c)_max. */
+int oracle_init_fill(osim*, double n0, double T0, const double* u0);
+
+/* Advance n steps (all stages), or one step restricted to a stage mask. */
+int oracle_step(osim*, int n);
+int oracle_step_stages(osim*, int mask);
+
+/* State in (cell, pid) order. */
+int64_t oracle_num_particles(const osim*);
+void oracle_get_particles(const osim*, double* x, double* v, int* cell, uint32_t* pid);
+int oracle_set_particles(osim*, int64_t np, const double* x, const double* v,
+                         const int* cell, const uint32_t* pid, uint32_t step, uint32_t next_pid);
+void oracle_get_smax(const osim*, double* out);
+void oracle_set_smax(osim*, const double* in);
+uint32_t oracle_step_index(const osim*);
+uint32_t oracle_next_pid(const osim*);
+
+/* Per-cell candidate / accepted pair counts of the last collide stage. */
+void oracle_get_pair_counts(const osim*, int* ncand, int* nacc);
+/* counters: hops, wall hits, injected, removed (outflow), lost */
+void oracle_get_counters(const osim*, int64_t out[5]);
+
+/* Moment sums [nt][13]: S0, S1(3), S2(xx,yy,zz,xy,xz,yz), S3(3).
+ * which: 0 steady accumulator (sum over sampled steps), 1 EWMA, 2 last step. */
+void oracle_get_sums(const osim*, int which, double* out);
+int64_t oracle_num_steady(const osim*);
+void oracle_set_local_acc(osim*, const unsigned char* flags);
+/* fields [nt][15]: n, rho, u(3), T, sigma(xx,yy,zz,xy,xz,yz), q(3) */
+void oracle_fields(const osim*, int which, double* out);
+
+/* Geometry accessors for the tests. */
+void oracle_get_volumes(const osim*, double* vol);
+void oracle_get_neighbours(const osim*, int* nbr /* [nt][4], -1-bface on the boundary */);
+void oracle_get_tets(const osim*, int* tv /* [nt][4] reoriented */);
+int oracle_num_faces(const osim*);
+
+/* Trace one particle for time t from (x, v) in cell with the given pid/step;
+ * returns the final cell (-1 if deleted) and writes x, v. */
+int oracle_trace_one(osim*, double* x, double* v, int cell, uint32_t pid, uint32_t step, double t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,312 @@
+"""Seeded synthetic inputs: tetrahedral meshes, boundary tables and run
+parameters for the lid-driven cavity (paper section 5.1), the free-molecular
+plate problems used as pins, and an open box with freestream inflow.
+
+This module holds no part of the method's arithmetic: it only builds input
+arrays (vertex coordinates, tet connectivity, boundary triangles and their
+groups) and the scalar parameters a caller passes in.  Both the GPU path and
+the CPU oracle consume its output.
+
+Gas and reference scales follow the paper's statement of the problem: the
+global Knudsen number of eq. (kn_definition_stability) with L0 the cavity
+side, and the mean collision time tau = mu/p of section 2.1; the time step is
+a fixed fraction of tau.
+"""
+from dataclasses import dataclass, field
+import itertools
+import math
+
+import numpy as np
+
+KB = 1.380649e-23
+
+# boundary kinds (same numbering as the C interfaces)
+BC_DIFFUSE, BC_SPECULAR, BC_INFLOW, BC_OUTFLOW, BC_PERIODIC = 0, 1, 2, 3, 4
+
+
+@dataclass
+class Species:
+    mass: float = 6.63e-26      # argon
+    d_ref: float = 4.17e-10
+    omega: float = 0.81
+    T_ref: float = 273.0
+    alpha: float = 1.0          # 1 = VHS
+
+    def mu(self, T):
+        """VHS viscosity at temperature T (power law in T with index omega,
+        coefficient from the hard-sphere-like reference diameter)."""
+        m, d, w = self.mass, self.d_ref, self.omega
+        mu_ref = 15.0 * math.sqrt(math.pi * m * KB * self.T_ref) / (
+            2.0 * math.pi * d * d * (5.0 - 2.0 * w) * (7.0 - 2.0 * w))
+        return mu_ref * (T / self.T_ref) ** w
+
+
+@dataclass
+class Boundary:
+    kind: int
+    T: float = 273.0
+    u: tuple = (0.0, 0.0, 0.0)
+    n: float = 0.0              # inflow number density
+    shift: tuple = (0.0, 0.0, 0.0)  # periodic translation onto the partner face
+
+
+@dataclass
+class Mesh:
+    xyz: np.ndarray             # [nv,3] float64
+    tets: np.ndarray            # [nt,4] int32
+    bfaces: np.ndarray          # [nb,3] int32
+    bgroup: np.ndarray          # [nb] int32
+    bpartner: np.ndarray = None  # [nb] int32 or None
+    h: float = 0.0
+
+    @property
+    def n_tets(self):
+        return int(self.tets.shape[0])
+
+
+@dataclass
+class Run:
+    n0: float
+    T0: float
+    u0: tuple
+    F_N: float
+    dt: float
+    seed: int = 0
+    case_id: int = 0
+    vel_fp32: int = 1
+    n_ss: int = 0
+    n_a: int = 1000
+    ewma_on: int = 0
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: Mesh
+    species: Species
+    boundaries: list
+    run: Run
+    steps: int = 1
+    info: dict = field(default_factory=dict)
+
+
+# ---------------------------------------------------------------------------
+# Kuhn-split box
+# ---------------------------------------------------------------------------
+def _kuhn_tets(nx, ny, nz):
+    """Each hex cell split into 6 tets along the main diagonal: for each
+    permutation of the axes, walk from the min corner to the max corner."""
+    vid = lambda i, j, k: (i * (ny + 1) + j) * (nz + 1) + k
+    I, J, K = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    I, J, K = I.ravel(), J.ravel(), K.ravel()
+    out = []
+    for perm in itertools.permutations(range(3)):
+        pts = [np.zeros(3, dtype=np.int64)]
+        for ax in perm:
+            p = pts[-1].copy()
+            p[ax] += 1
+            pts.append(p)
+        out.append(np.stack([vid(I + p[0], J + p[1], K + p[2]) for p in pts], axis=1))
+    # order: hex-major, then permutation
+    tets = np.stack(out, axis=1).reshape(-1, 4)
+    return tets.astype(np.int32)
+
+
+def _box_boundary(tets, xyz, lo, hi, tol):
+    """Exterior triangles (faces used by one tet) and their side group:
+    0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+."""
+    faces = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]],
+                            tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]])
+    key = np.sort(faces, axis=1)
+    _, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+    ext = faces[cnt[inv.ravel()] == 1]
+    c = xyz[ext].mean(axis=1)
+    grp = np.full(len(ext), -1, dtype=np.int32)
+    for ax in range(3):
+        grp[np.abs(c[:, ax] - lo[ax]) < tol] = 2 * ax
+        grp[np.abs(c[:, ax] - hi[ax]) < tol] = 2 * ax + 1
+    assert (grp >= 0).all()
+    return ext.astype(np.int32), grp
+
+
+def kuhn_box(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), jitter=0.0, seed=0,
+             periodic_axes=()):
+    """Box [lo,hi] meshed as nx*ny*nz hexes x 6 Kuhn tets.  ``jitter`` moves
+    interior vertices by uniform +-jitter*h per coordinate, vertices on one
+    box face only tangentially, and leaves edge and corner vertices fixed; a
+    vertex is redrawn while any of its tets falls below 5% of the nominal
+    volume.  ``periodic_axes`` pairs the faces on opposite sides of the
+    listed axes (translation partners); jitter must then be 0."""
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    n = np.array([nx, ny, nz])
+    hv = (hi - lo) / n
+    gi = [np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1)]
+    I, J, K = np.meshgrid(*gi, indexing="ij")
+    idx = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1)
+    xyz = lo + idx * hv
+    # exact end coordinates
+    for ax in range(3):
+        xyz[idx[:, ax] == n[ax], ax] = hi[ax]
+    tets = _kuhn_tets(nx, ny, nz)
+    h = float(hv.min())
+    if jitter > 0:
+        assert not periodic_axes
+        rng = np.random.default_rng(seed)
+        on_face = (idx == 0) | (idx == n)          # per-axis boundary flags
+        nbnd = on_face.sum(axis=1)
+        movable = nbnd <= 1
+        vol0 = np.prod(hv) / 6.0
+
+        def vols(x):
+            a, b, c, d = (x[tets[:, i]] for i in range(4))
+            return np.abs(np.einsum("ij,ij->i", b - a, np.cross(c - a, d - a))) / 6.0
+
+        base = xyz.copy()
+        disp = rng.uniform(-jitter, jitter, size=xyz.shape) * hv
+        disp[on_face] = 0.0                          # no normal motion on a box face
+        disp[~movable] = 0.0
+        xyz = base + disp
+        for _ in range(100):
+            bad_t = np.nonzero(vols(xyz) < 0.05 * vol0)[0]
+            if len(bad_t) == 0:
+                break
+            bad_v = np.unique(tets[bad_t].ravel())
+            bad_v = bad_v[movable[bad_v]]
+            d = rng.uniform(-jitter, jitter, size=(len(bad_v), 3)) * hv
+            d[on_face[bad_v]] = 0.0
+            xyz[bad_v] = base[bad_v] + d
+        else:
+            raise RuntimeError("jitter could not reach the minimum tet volume")
+    bfaces, bgroup = _box_boundary(tets, xyz, lo, hi, 1e-9 * float((hi - lo).max()))
+    partner = None
+    if periodic_axes:
+        partner = np.full(len(bfaces), -1, dtype=np.int32)
+        for ax in periodic_axes:
+            for side_lo, side_hi in [(2 * ax, 2 * ax + 1)]:
+                a = np.nonzero(bgroup == side_lo)[0]
+                b = np.nonzero(bgroup == side_hi)[0]
+                # map each vertex on the hi side to its translate on the lo side
+                ka = np.sort(_grid_keys(idx[bfaces[a]], ax, n), axis=1)
+                kb = np.sort(_grid_keys(idx[bfaces[b]], ax, n, to_lo=True), axis=1)
+                da = {tuple(r): i for r, i in zip(ka.tolist(), a.tolist())}
+                for r, i in zip(kb.tolist(), b.tolist()):
+                    j = da[tuple(r)]
+                    partner[i] = j
+                    partner[j] = i
+        assert (partner[np.isin(bgroup, [2 * a for a in periodic_axes] +
+                                [2 * a + 1 for a in periodic_axes])] >= 0).all()
+    return Mesh(xyz=np.ascontiguousarray(xyz), tets=np.ascontiguousarray(tets),
+                bfaces=np.ascontiguousarray(bfaces), bgroup=np.ascontiguousarray(bgroup),
+                bpartner=partner, h=h)
+
+
+def _grid_keys(ijk, ax, n, to_lo=False):
+    """Integer key of each face vertex with the periodic axis coordinate
+    dropped (so a face and its translate share keys)."""
+    ijk = ijk.copy()
+    if to_lo:
+        ijk[..., ax] = 0
+    other = [a for a in range(3) if a != ax]
+    return ijk[..., other[0]] * (n[other[1]] + 1) + ijk[..., other[1]]
+
+
+# ---------------------------------------------------------------------------
+# Reference scales
+# ---------------------------------------------------------------------------
+def n0_from_kn(sp: Species, Kn, T0, L0=1.0):
+    """Number density for a global Knudsen number (eq. kn_definition_stability):
+    Kn = mu0/(p0 L0) sqrt(pi R T0 / 2)."""
+    R = KB / sp.mass
+    p0 = sp.mu(T0) * math.sqrt(math.pi * R * T0 / 2.0) / (Kn * L0)
+    return p0 / (KB * T0)
+
+
+def tau_from_kn(sp: Species, Kn, T0, L0=1.0):
+    """Mean collision time tau = mu/p (section 2.1) at the reference state."""
+    R = KB / sp.mass
+    return Kn * L0 / math.sqrt(math.pi * R * T0 / 2.0)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+def cavity(n_hex=6, Kn=1.0, ppc=20, jitter=0.0, lid_speed=50.0, T0=273.0, seed=0,
+           vel_fp32=1, steps=500, n_ss=200, mesh_seed=0, ewma_on=0, n_a=1000):
+    """3D lid-driven cavity on [0,1]^3: all walls diffuse at T0, the y=1 lid
+    moving at lid_speed in +x.  Initial equilibrium at rest (section 5.1)."""
+    sp = Species()
+    mesh = kuhn_box(n_hex, n_hex, n_hex, jitter=jitter, seed=mesh_seed)
+    n0 = n0_from_kn(sp, Kn, T0)
+    dt = 0.2 * tau_from_kn(sp, Kn, T0)
+    F_N = n0 * 1.0 / (ppc * mesh.n_tets)
+    bcs = [Boundary(BC_DIFFUSE, T0)] * 6
+    bcs = list(bcs)
+    bcs[3] = Boundary(BC_DIFFUSE, T0, (lid_speed, 0.0, 0.0))
+    run = Run(n0=n0, T0=T0, u0=(0.0, 0.0, 0.0), F_N=F_N, dt=dt, seed=seed, vel_fp32=vel_fp32,
+              n_ss=n_ss, n_a=n_a, ewma_on=ewma_on)
+    return Workload(f"cavity_{n_hex}^3x6_Kn{Kn:g}", mesh, sp, bcs, run, steps,
+                    dict(Kn=Kn, n_hex=n_hex, ppc=ppc, lid_speed=lid_speed, jitter=jitter))
+
+
+def cavity_small():
+    """Lid-driven cavity, 6^3 hexes x 6 tets (1,296 tets), Kn=1, 20 particles
+    per cell, FP64 velocities, 500 steps with the last 300 sampled."""
+    return cavity(n_hex=6, Kn=1.0, ppc=20, vel_fp32=0, steps=500, n_ss=200)
+
+
+def cavity_large(steps=20000, n_ss=10000):
+    """Lid-driven cavity, 40^3 hexes x 6 tets (384,000 tets) with +-10%
+    vertex jitter, Kn=0.1, 30 particles per cell (11.52M particles), FP32
+    velocities, FP64 positions and moments."""
+    return cavity(n_hex=40, Kn=0.1, ppc=30, jitter=0.1, vel_fp32=1, steps=steps, n_ss=n_ss)
+
+
+def closed_box(n_hex=4, kind=BC_SPECULAR, Kn=1.0, ppc=20, T0=273.0, vel_fp32=0, seed=0,
+               Tw=None):
+    """Closed unit box at rest with all six walls of one kind."""
+    sp = Species()
+    mesh = kuhn_box(n_hex, n_hex, n_hex)
+    n0 = n0_from_kn(sp, Kn, T0)
+    dt = 0.2 * tau_from_kn(sp, Kn, T0)
+    F_N = n0 / (ppc * mesh.n_tets)
+    bcs = [Boundary(kind, T0 if Tw is None else Tw)] * 6
+    run = Run(n0=n0, T0=T0, u0=(0.0, 0.0, 0.0), F_N=F_N, dt=dt, seed=seed, vel_fp32=vel_fp32)
+    return Workload("closed_box", mesh, sp, list(bcs), run, 1)
+
+
+def plates(n=(4, 8, 4), H=1.0, U=0.0, T1=273.0, T2=273.0, n0=1e18, ppc=20, dt=None,
+           seed=0, periodic=True, vel_fp32=0):
+    """Two diffuse plates at y=0 (T1, moving -U/2 in x) and y=H (T2, +U/2),
+    periodic (or specular) in x and z.  Collisionless limit via a negligible
+    cross-section is the caller's choice of species."""
+    sp = Species()
+    mesh = kuhn_box(*n, hi=(1.0, H, 1.0), periodic_axes=(0, 2) if periodic else ())
+    F_N = n0 * H / (ppc * mesh.n_tets)
+    side = BC_PERIODIC if periodic else BC_SPECULAR
+    bcs = [Boundary(side, 0.0, shift=(1.0, 0.0, 0.0)), Boundary(side, 0.0, shift=(-1.0, 0.0, 0.0)),
+           Boundary(BC_DIFFUSE, T1, (-U / 2, 0.0, 0.0)), Boundary(BC_DIFFUSE, T2, (U / 2, 0.0, 0.0)),
+           Boundary(side, 0.0, shift=(0.0, 0.0, 1.0)), Boundary(side, 0.0, shift=(0.0, 0.0, -1.0))]
+    T0 = 0.5 * (T1 + T2)
+    if dt is None:
+        dt = 0.25 * (H / n[1]) / math.sqrt(2 * KB * T0 / sp.mass)
+    run = Run(n0=n0, T0=T0, u0=(0.0, 0.0, 0.0), F_N=F_N, dt=dt, seed=seed, vel_fp32=vel_fp32)
+    return Workload("plates", mesh, sp, bcs, run, 1)
+
+
+def open_box(n=(6, 4, 4), lo=(-2.0, -2.0, -2.0), hi=(4.0, 2.0, 2.0), T=200.0, u=2634.66,
+             Kn=0.05, ppc=10, seed=0, vel_fp32=1, dt=None):
+    """Box with freestream inflow on five faces (x-, y-, y+, z-, z+) and a
+    vacuum outflow at x+, filled with the freestream; cross-section
+    parameters are those of argon, Kn referred to a 1 m length."""
+    sp = Species()
+    mesh = kuhn_box(*n, lo=lo, hi=hi)
+    n_inf = n0_from_kn(sp, Kn, T)
+    vol = float(np.prod(np.asarray(hi) - np.asarray(lo)))
+    F_N = n_inf * vol / (ppc * mesh.n_tets)
+    if dt is None:
+        dt = 0.2 * mesh.h / u
+    inflow = Boundary(BC_INFLOW, T, (u, 0.0, 0.0), n=n_inf)
+    bcs = [inflow, Boundary(BC_OUTFLOW, T), inflow, inflow, inflow, inflow]
+    run = Run(n0=n_inf, T0=T, u0=(u, 0.0, 0.0), F_N=F_N, dt=dt, seed=seed, vel_fp32=vel_fp32)
+    return Workload("open_box", mesh, sp, bcs, run, 1, dict(n_inf=n_inf, u=u, T=T))

@@ -1,0 +1,123 @@
+"""Pins of the oracle's mesh preprocessing and face-to-face tracking.
+
+Independent checks: volumes against the box volume, face pairing against
+a counting argument, and a brute-force barycentric point location over all
+tets for the end point of traced trajectories."""
+import numpy as np
+import pytest
+
+from paper_2607_08195_amd import workloads as W
+from oracle import Oracle
+
+
+def _bary_all(xyz, tets, pts):
+    """Barycentric coordinates of every point in every tet: [npts, ntets, 4]."""
+    a, b, c, d = (xyz[tets[:, i]] for i in range(4))
+    T = np.stack([b - a, c - a, d - a], axis=2)            # [nt,3,3]
+    Tinv = np.linalg.inv(T)
+    rel = pts[:, None, :] - a[None, :, :]                   # [np,nt,3]
+    l123 = np.einsum("tij,ptj->pti", Tinv, rel)
+    l0 = 1.0 - l123.sum(axis=2)
+    return np.concatenate([l0[..., None], l123], axis=2)
+
+
+@pytest.mark.parametrize("jitter", [0.0, 0.1])
+def test_volumes_and_faces(jitter):
+    wl = W.cavity(n_hex=5, jitter=jitter, ppc=2)
+    o = Oracle(wl, fill=False)
+    vol = o.volumes()
+    assert (vol > 0).all()
+    assert abs(vol.sum() - 1.0) < 1e-14
+    nbr = o.neighbours()
+    nt = o.nt
+    nb = len(wl.mesh.bfaces)
+    assert nb == 6 * 2 * 5 * 5
+    assert (nbr < 0).sum() == nb
+    assert o.n_faces == (4 * nt + nb) // 2
+    # symmetric neighbour relation
+    for t in range(nt):
+        for f in range(4):
+            u = nbr[t, f]
+            if u >= 0:
+                assert t in nbr[u]
+    # every boundary face index appears once
+    b = -1 - nbr[nbr < 0]
+    assert sorted(b.tolist()) == list(range(nb))
+
+
+def test_invalid_mesh_rejected():
+    wl = W.cavity(n_hex=2, ppc=2)
+    wl.mesh.bfaces = wl.mesh.bfaces[:-1].copy()
+    wl.mesh.bgroup = wl.mesh.bgroup[:-1].copy()
+    with pytest.raises(ValueError):
+        Oracle(wl, fill=False)
+
+
+@pytest.mark.parametrize("jitter,kind", [(0.0, W.BC_SPECULAR), (0.1, W.BC_SPECULAR), (0.1, W.BC_DIFFUSE)])
+def test_trace_end_point_brute_force(jitter, kind):
+    """>= 1e5 random trajectories in a closed box: the final tet contains the
+    end point (all barycentric weights >= -1e-12), and no other tet strictly
+    contains it."""
+    n = 3
+    wl = W.cavity(n_hex=n, jitter=jitter, ppc=2, mesh_seed=4)
+    for i in range(6):
+        wl.boundaries[i] = W.Boundary(kind, 273.0)
+    o = Oracle(wl, fill=False)
+    xyz, tets = wl.mesh.xyz, o.tets()
+    rng = np.random.default_rng(7)
+    N = 100000
+    cells = rng.integers(0, o.nt, N)
+    w = rng.dirichlet(np.ones(4), N)
+    starts = np.einsum("pk,pkj->pj", w, xyz[tets[cells]])
+    dirs = rng.normal(size=(N, 3))
+    speed = 400.0
+    vels = dirs * speed
+    ts = rng.uniform(0, 3.0 / speed, N)   # up to three box lengths of travel
+    ends = np.zeros((N, 3))
+    endc = np.zeros(N, np.int64)
+    for k in range(N):
+        c, x, _ = o.trace_one(starts[k], vels[k], cells[k], k, 1, ts[k])
+        ends[k] = x
+        endc[k] = c
+    assert (endc >= 0).all()
+    for lo in range(0, N, 5000):
+        sl = slice(lo, lo + 5000)
+        lam = _bary_all(xyz, tets, ends[sl])
+        own = lam[np.arange(lam.shape[0]), endc[sl]]
+        assert (own >= -1e-12).all()
+        strict = (lam > 1e-9).all(axis=2)
+        strict[np.arange(lam.shape[0]), endc[sl]] = False
+        assert not strict.any()
+
+
+def test_ballistic_exact_within_cell_and_close_across():
+    wl = W.cavity(n_hex=3, ppc=2)
+    o = Oracle(wl, fill=False)
+    xyz, tets = wl.mesh.xyz, o.tets()
+    rng = np.random.default_rng(3)
+    for k in range(2000):
+        c = int(rng.integers(0, o.nt))
+        w = rng.dirichlet(np.ones(4))
+        x0 = w @ xyz[tets[c]]
+        v = rng.normal(size=3) * 300.0
+        t = 1e-7
+        c1, x, _ = o.trace_one(x0, v, c, k, 1, t)
+        if c1 == c:
+            assert np.array_equal(x, x0 + v * t)   # same operation order, bitwise
+        t = 2e-4
+        c1, x, v1 = o.trace_one(x0, v, c, k, 1, t)
+        if np.array_equal(v1, v):  # no wall reflection on the way
+            assert np.allclose(x, x0 + v * t, rtol=0, atol=1e-12)
+
+
+def test_specular_preserves_speed():
+    wl = W.closed_box(n_hex=3, kind=W.BC_SPECULAR)
+    o = Oracle(wl, fill=False)
+    xyz, tets = wl.mesh.xyz, o.tets()
+    rng = np.random.default_rng(5)
+    for k in range(3000):
+        c = int(rng.integers(0, o.nt))
+        x0 = rng.dirichlet(np.ones(4)) @ xyz[tets[c]]
+        v = rng.normal(size=3) * 300.0
+        c1, x, v1 = o.trace_one(x0, v, c, k, 1, 0.02)
+        assert abs(np.linalg.norm(v1) - np.linalg.norm(v)) <= 1e-13 * np.linalg.norm(v)
