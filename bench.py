@@ -1,0 +1,153 @@
+"""Benchmark of the DSMC step on one MI355X.
+
+A step is one pass of the whole per-step path (move with boundary
+interactions, freestream injection, counting sort by cell, NTC/VHS
+collisions, cell moment sampling) over the particle set.  Default workload:
+the lid-driven cavity on 40^3 hexes x 6 jittered tets (384,000 tets),
+Kn = 0.1, 30 particles per cell (11.52M particles), FP32 velocity storage,
+FP64 positions, arithmetic and moments.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic HBM bytes per particle (or per cell) of each kernel, for the
+# FP32-velocity layout: x,y,z f64 (24) + v f32 (12) + cell i32 (4) + pid u32 (4).
+#  move:     read x,v,cell,pid (44); write x,cell,rank (32); + v (12) per wall hit
+#  scatter:  read x,v,cell,pid,rank (48); write x,v,cell,pid (44)
+#  collide:  read v,pid (16); write v of collided particles (12 per particle touched);
+#            per cell: offsets (4), smax/counters (16), steady sums read+write (208)
+#  scan:     per cell: counts read twice (8), offsets write (4)
+B_MOVE, B_WALL = 76.0, 12.0
+B_SCATTER = 92.0
+B_COLLIDE_P, B_COLLIDE_TOUCH, B_COLLIDE_CELL = 16.0, 12.0, 228.0
+B_SCAN_CELL = 12.0
+
+# rocprofv3 --pmc measurements of the move kernel (FETCH_SIZE + WRITE_SIZE per
+# dispatch, scaled by the copy-kernel calibration) and the source digest they
+# were taken on; the traffic figure is reported only while the digest matches.
+TRAFFIC = None
+
+
+def _kernel_digest():
+    h = hashlib.sha256()
+    for f in ["kernels.hip", "device_common.h", "kernels.h"]:
+        h.update(open(os.path.join(ROOT, "paper_2607_08195_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(wl, steps):
+    """The oracle as it stands, single-threaded, on a bounded sample of the
+    same workload: `steps` steps from its initial fill."""
+    from oracle import Oracle
+    o = Oracle(wl)
+    n = o.np
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return dict(value=n * steps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"{wl.name}: {steps} steps from the initial fill ({n * steps:.3g} particle-steps, "
+                       f"{dt:.1f} s, 1 thread)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="cavity_large", choices=["cavity_large", "cavity_small"])
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a "
+              "design note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2607_08195_amd import dsmc, workloads as W
+
+    wl = W.cavity_large() if args.workload == "cavity_large" else W.cavity_small()
+    sim = dsmc.Simulation(wl)
+    np0 = sim.stats()["n_particles"]
+    sim.step(args.warmup)
+    sim.sync()
+    s0 = sim.stats()
+    torch.cuda.synchronize()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sim.profile_read()
+    sim.profile(False)
+    s1 = sim.stats()
+    elapsed = t1 - t0
+    npart = 0.5 * (s0["n_particles"] + s1["n_particles"])
+    psteps = npart * args.steps
+    value = psteps / elapsed
+    walls_pp = (s1["wall_hits"] - s0["wall_hits"]) / psteps
+    hops_pp = (s1["hops"] - s0["hops"]) / psteps
+    nt = sim.nt
+    _, nacc = sim.pair_counts()
+    touched_pp = 2.0 * nacc.sum() / max(npart, 1)
+
+    per_launch = {}
+    for name, (ms, cnt) in prof.items():
+        if cnt:
+            per_launch[name] = ms / cnt
+    bytes_launch = {
+        "move": npart * (B_MOVE + B_WALL * walls_pp),
+        "scatter": npart * B_SCATTER,
+        "collide_sample": npart * (B_COLLIDE_P + B_COLLIDE_TOUCH * touched_pp) + nt * B_COLLIDE_CELL,
+        "scan": nt * B_SCAN_CELL,
+    }
+    gbs = {k: bytes_launch[k] / (per_launch[k] * 1e-3) / 1e9 for k in bytes_launch if k in per_launch}
+    dominant = max((k for k in bytes_launch if k in per_launch), key=lambda k: per_launch[k])
+    step_bytes = sum(bytes_launch.values())
+    peak = 8000.0
+    digest = _kernel_digest()
+    traffic = None
+    if TRAFFIC and TRAFFIC.get("digest") == digest and TRAFFIC.get("kernel") == dominant:
+        traffic = TRAFFIC["bytes_per_launch"]
+    roofline = dict(bound="hbm", kernel=dominant, achieved=round(gbs[dominant], 1), peak=peak, unit="GB/s",
+                    frac=round(gbs[dominant] / peak, 4), traffic=traffic)
+
+    out = {
+        "metric": "particle-steps/s",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "tets": nt, "particles": int(np0),
+                   "Kn": wl.info.get("Kn"), "velocity_storage": "f32" if wl.run.vel_fp32 else "f64"},
+        "step_algorithmic_GBps": round(step_bytes / (elapsed / args.steps) / 1e9, 1),
+        "hops_per_particle_step": round(hops_pp, 3),
+        "kernel_ms": {k: round(v, 4) for k, v in per_launch.items()},
+        "kernel_GBps": {k: round(v, 1) for k, v in gbs.items()},
+        "roofline": roofline,
+        "kernel_digest": digest,
+    }
+    sim.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

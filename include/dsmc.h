@@ -1,0 +1,216 @@
+/*
+ * dsmc.h — C ABI of the MI355X (gfx950) DSMC particle loop.
+ *
+ * The library advances a direct simulation Monte Carlo gas on an
+ * unstructured tetrahedral mesh, one time step at a time, following the
+ * step splitting of the paper's section 2.1 (particles are moved, then
+ * pairs are selected and collided within each cell) and the cell sampling
+ * of eq. (dsmc_temperatures), with the moving average of
+ * eq. (exponential_average_moments_ch3) and the steady average of
+ * eq. (steady_average_moments_ch3) from section 3.1.  Particle state is the
+ * (x, v; N_eff) of eq. (dsmc_particle_state) for a monatomic gas.
+ *
+ * Conventions
+ *  - Every call returns a dsmc_status: 0 on success, negative on error.
+ *    No C++ exception crosses this boundary.  dsmc_last_error() gives a
+ *    message for the last failing call on a context.
+ *  - Units are SI (m, s, kg, K).  Host pointers are plain C arrays in the
+ *    row-major layouts stated per argument.
+ *  - Input descriptors are borrowed for the duration of the call only: the
+ *    library copies what it needs.  Output buffers belong to the caller.
+ *  - A context owns all device memory it allocates (through the caller's
+ *    allocator when one is given) and releases it in dsmc_destroy().
+ *  - Work is enqueued asynchronously on the context's HIP stream.  Calls
+ *    that return host data synchronise that stream.  Device-side faults
+ *    (capacity overflow, lost particles) are latched and reported by the
+ *    next synchronising call (dsmc_stats, dsmc_get_state, dsmc_sample,
+ *    dsmc_sync).  After DSMC_E_CAPACITY or DSMC_E_DEVICE only
+ *    dsmc_destroy() is valid.
+ *  - One context per host thread; distinct contexts are independent.
+ */
+#ifndef DSMC_H
+#define DSMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dsmc_ctx_s* dsmc_ctx;
+
+typedef enum {
+    DSMC_OK = 0,
+    DSMC_E_INVALID = -1,       /* bad argument or call order */
+    DSMC_E_MESH = -2,          /* degenerate tet, unmatched boundary triangle, non-manifold face */
+    DSMC_E_OOM = -3,           /* device allocation failed */
+    DSMC_E_DEVICE = -4,        /* HIP runtime error */
+    DSMC_E_CAPACITY = -5,      /* particle store would overflow */
+    DSMC_E_LOST = -6,          /* (reported in counters; not returned by dsmc_step) */
+    DSMC_E_NOT_CONVERGED = -7  /* reserved for the coupling solve */
+} dsmc_status;
+
+/* Tetrahedral mesh (paper section 4.1: cells and faces of the local mesh).
+ * xyz      [n_vertices][3]  vertex coordinates (m)
+ * tet_vtx  [n_tets][4]      vertex indices, any orientation
+ * bface_vtx   [n_bfaces][3] boundary triangles (each must match exactly one
+ *                           exterior tet face)
+ * bface_group [n_bfaces]    index into the boundary table of dsmc_init
+ * bface_partner [n_bfaces]  periodic partner triangle, or -1; may be NULL */
+typedef struct {
+    int32_t n_vertices;
+    const double* xyz;
+    int32_t n_tets;
+    const int32_t* tet_vtx;
+    int32_t n_bfaces;
+    const int32_t* bface_vtx;
+    const int32_t* bface_group;
+    const int32_t* bface_partner;
+} dsmc_mesh_desc;
+
+/* Variable hard sphere species (paper section 5: VHS collision model,
+ * power-law viscosity index omega).  alpha must be 1 (VHS scattering). */
+typedef struct {
+    double mass;     /* kg */
+    double d_ref;    /* reference diameter, m */
+    double omega;    /* viscosity index */
+    double T_ref;    /* reference temperature of d_ref, K */
+    double alpha;    /* scattering parameter; only 1 is supported */
+} dsmc_species_desc;
+
+typedef enum {
+    DSMC_BC_DIFFUSE = 0,   /* full accommodation at (T, u) (paper section 5) */
+    DSMC_BC_SPECULAR = 1,  /* mirror reflection */
+    DSMC_BC_INFLOW = 2,    /* freestream (n, T, u) enters; leaving particles are removed */
+    DSMC_BC_OUTFLOW = 3,   /* vacuum: leaving particles are removed */
+    DSMC_BC_PERIODIC = 4   /* translate by shift onto the partner triangle */
+} dsmc_bc_kind;
+
+typedef struct {
+    int32_t kind;     /* dsmc_bc_kind */
+    double T;         /* wall or freestream temperature, K */
+    double u[3];      /* wall or freestream velocity, m/s */
+    double n;         /* freestream number density (INFLOW), m^-3 */
+    double shift[3];  /* translation onto the partner face (PERIODIC), m */
+} dsmc_boundary_desc;
+
+/* Optional device allocator; alloc returns NULL on failure. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} dsmc_allocator;
+
+typedef struct {
+    double n0;            /* initial number density, m^-3 */
+    double T0;            /* initial temperature, K */
+    double u0[3];         /* initial bulk velocity, m/s */
+    double F_N;           /* real molecules per simulation particle (N_eff) */
+    double dt;            /* time step, s */
+    uint64_t seed;        /* low 32 bits key the generator */
+    uint32_t case_id;     /* second key word of the generator */
+    int32_t vel_fp64;     /* 1: store velocities in FP64; 0: FP32 storage */
+    int32_t n_ss;         /* steps discarded before the steady average */
+    int32_t n_a;          /* effective samples of the moving average */
+    int32_t ewma_on;      /* 1: keep the moving-average accumulator */
+    int32_t fill;         /* 1: equilibrium fill at (n0, T0, u0); 0: empty */
+    int64_t capacity;     /* particle store size; 0 chooses 2x the count at n0 */
+    void* hip_stream;     /* hipStream_t to enqueue on; NULL = null stream */
+    const dsmc_allocator* allocator; /* NULL = hipMalloc / hipFree */
+} dsmc_run_desc;
+
+/* Build the device mesh image, boundary tables and particle store, and
+ * (with run->fill) perform the initial equilibrium fill.  On success *out
+ * is a new context; on failure *out is NULL and the status says why. */
+dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_species_desc* species,
+                      int32_t n_bc, const dsmc_boundary_desc* bcs, const dsmc_run_desc* run);
+
+/* Advance n_steps time steps: move (with boundary interactions) ->
+ * freestream injection -> counting sort by cell -> NTC collisions ->
+ * sampling.  Asynchronous. */
+dsmc_status dsmc_step(dsmc_ctx ctx, int32_t n_steps);
+
+/* One step restricted to the stages in mask (1 move, 2 inject, 4 sort,
+ * 8 collide, 16 sample); for stage-level testing. */
+dsmc_status dsmc_step_stages(dsmc_ctx ctx, int32_t mask);
+
+enum { DSMC_SAMPLE_STEADY = 0, DSMC_SAMPLE_EWMA = 1 };
+
+/* Cell fields from an accumulator (eq. dsmc_temperatures over the sampled
+ * steps): out[n_tets][15] = n, rho, u(3), T, sigma(xx,yy,zz,xy,xz,yz),
+ * q(3).  Cells without samples give NaN.  out is a host pointer unless
+ * out_on_device is 1.  Synchronises. */
+dsmc_status dsmc_sample(dsmc_ctx ctx, int32_t which, double* out, int32_t out_on_device);
+
+/* Raw moment sums out[n_tets][13] = S0, S1(3), S2(xx,yy,zz,xy,xz,yz), S3(3)
+ * of an accumulator, and the number of steps summed (steady) into
+ * *n_samples.  Synchronises. */
+dsmc_status dsmc_get_sums(dsmc_ctx ctx, int32_t which, double* out, int64_t* n_samples);
+
+/* Particle state.  dsmc_get_state fills n_particles, step and next_pid; the
+ * arrays (host, may be NULL) receive the particles in (cell, pid) order:
+ * x[n][3], v[n][3] (FP64), cell[n], pid[n], and smax[n_tets] the per-cell
+ * (sigma_T c_r)_max.  dsmc_set_state replaces the state (particles in any
+ * order); smax may be NULL to keep the current values. */
+typedef struct {
+    int64_t n_particles;
+    double* x;
+    double* v;
+    int32_t* cell;
+    uint32_t* pid;
+    double* smax;
+    uint32_t step;
+    uint32_t next_pid;
+} dsmc_state;
+
+dsmc_status dsmc_get_state(dsmc_ctx ctx, dsmc_state* state);
+dsmc_status dsmc_set_state(dsmc_ctx ctx, const dsmc_state* state);
+
+/* Per-cell candidate and accepted pair counts of the last collide stage
+ * (host arrays [n_tets]).  Synchronises. */
+dsmc_status dsmc_get_pair_counts(dsmc_ctx ctx, int32_t* ncand, int32_t* nacc);
+
+/* Cumulative counters.  Synchronises and reports latched device errors. */
+typedef struct {
+    int64_t n_particles;
+    int64_t hops;        /* face events (crossings and boundary interactions) */
+    int64_t wall_hits;   /* diffuse and specular reflections */
+    int64_t injected;
+    int64_t removed;     /* left through inflow/outflow faces */
+    int64_t lost;        /* exceeded the hop limit and were deleted */
+    uint32_t step;
+} dsmc_counters;
+dsmc_status dsmc_stats(dsmc_ctx ctx, dsmc_counters* out);
+
+/* Wait for all work enqueued on the context; reports latched errors. */
+dsmc_status dsmc_sync(dsmc_ctx ctx);
+
+/* Per-cell local-accumulation flags (host array [n_tets] of 0/1): flagged
+ * cells average their moving-average accumulator cumulatively
+ * (section 3.2). */
+dsmc_status dsmc_set_local_acc(dsmc_ctx ctx, const uint8_t* flags);
+
+/* Per-kernel timing of the step's kernels with HIP events on the context's
+ * stream.  dsmc_profile(ctx, 1) starts recording (and resets), 0 stops.
+ * dsmc_profile_read writes for each kernel slot: total milliseconds and
+ * launch count; names via dsmc_profile_name.  Returns the slot count. */
+dsmc_status dsmc_profile(dsmc_ctx ctx, int32_t enable);
+int32_t dsmc_profile_read(dsmc_ctx ctx, double* total_ms, int64_t* launches, int32_t max_slots);
+const char* dsmc_profile_name(int32_t slot);
+
+/* Philox4x32-10 evaluated on the device for n counters ctr[n][4] under
+ * key[2]; out[n][4] (host arrays).  Known-answer check of the generator. */
+dsmc_status dsmc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n);
+
+/* Plain device copy of `bytes` between two device buffers on the context
+ * stream (HBM bandwidth calibration of the traffic counters). */
+dsmc_status dsmc_device_copy(dsmc_ctx ctx, void* dst, const void* src, size_t bytes);
+
+const char* dsmc_last_error(dsmc_ctx ctx);
+void dsmc_destroy(dsmc_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSMC_H */

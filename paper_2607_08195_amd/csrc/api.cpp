@@ -1,0 +1,747 @@
+// C ABI of the DSMC library: context lifetime, device memory, the per-step
+// launch sequence, state import/export and statistics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/dsmc.h"
+#include "kernels.h"
+#include "mesh.h"
+
+using namespace dsmcx;
+
+namespace {
+
+enum Slot { kSlotBegin = 0, kSlotMove, kSlotInject, kSlotScan, kSlotScatter, kSlotCollide, kNumSlots };
+const char* kSlotNames[kNumSlots] = {"begin", "move", "inject", "scan", "scatter", "collide_sample"};
+
+struct Buf {
+    double* x = nullptr;
+    double* y = nullptr;
+    double* z = nullptr;
+    void* vx = nullptr;
+    void* vy = nullptr;
+    void* vz = nullptr;
+    int32_t* cell = nullptr;
+    uint32_t* pid = nullptr;
+};
+
+template <class VT>
+PartDev<VT> as_dev(const Buf& b) {
+    return PartDev<VT>{b.x, b.y, b.z, (VT*)b.vx, (VT*)b.vy, (VT*)b.vz, b.cell, b.pid};
+}
+
+std::string g_global_error;
+
+}  // namespace
+
+struct dsmc_ctx_s {
+    hipStream_t stream = nullptr;
+    dsmc_allocator alloc{};
+    bool has_alloc = false;
+    std::vector<void*> owned;
+    std::string err;
+    bool broken = false;
+
+    HostMesh hm;
+    int nt = 0, nb = 0;
+    // species / run
+    double mass = 0, dref = 0, omega = 0, Tref = 0, K = 0, ex = 0;
+    double FN = 0, dt = 0, n0 = 0, T0 = 0, u0[3] = {0, 0, 0};
+    RngKey key{0, 0};
+    int vel64 = 0, n_ss = 0, n_a = 1000, ewma_on = 0;
+    int64_t cap = 0;
+    // device mesh
+    MeshDev mesh{};
+    double4* d_plane = nullptr;
+    int32_t* d_nbr = nullptr;
+    double* d_vol = nullptr;
+    int32_t* d_bf_group = nullptr;
+    int32_t* d_bf_pcode = nullptr;
+    double* d_bf_frame = nullptr;
+    GroupDev* d_groups = nullptr;
+    int4* d_tv = nullptr;
+    double* d_xyz = nullptr;
+    // inflow
+    InflowDev inflow{};
+    int32_t* d_fcount = nullptr;
+    int32_t* d_foff = nullptr;
+    int64_t max_inject = 0;
+    // particles
+    Buf A, B;
+    uint32_t* d_rank = nullptr;
+    int32_t* d_perm = nullptr;
+    // cells
+    int32_t* d_counts = nullptr;
+    int32_t* d_offsets = nullptr;
+    int32_t* d_blocksums = nullptr;
+    double* d_smax = nullptr;
+    int32_t* d_ncand = nullptr;
+    int32_t* d_nacc = nullptr;
+    double* d_acc = nullptr;
+    double* d_ewma = nullptr;
+    int32_t* d_ewma_m = nullptr;
+    uint8_t* d_local = nullptr;
+    Scalars* d_sc = nullptr;
+    Counters* d_ctr = nullptr;
+    // host view
+    int64_t np_bound = 0;
+    // profiling
+    bool profiling = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+    std::vector<hipEvent_t> ev_pool;
+};
+
+namespace {
+
+dsmc_status fail(dsmc_ctx c, dsmc_status s, const std::string& msg) {
+    if (c) c->err = msg; else g_global_error = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, call)                                                                     \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            if (ctx) (ctx)->broken = true;                                                     \
+            return fail(ctx, DSMC_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+        }                                                                                      \
+    } while (0)
+
+void* dev_alloc(dsmc_ctx c, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void* p = nullptr;
+    if (c->has_alloc) {
+        p = c->alloc.alloc(bytes, c->alloc.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) c->owned.push_back(p);
+    return p;
+}
+
+template <class T>
+bool alloc_n(dsmc_ctx c, T*& p, size_t n) {
+    p = (T*)dev_alloc(c, sizeof(T) * n);
+    return p != nullptr;
+}
+
+bool alloc_buf(dsmc_ctx c, Buf& b, int64_t cap, int vel64) {
+    const size_t vs = vel64 ? sizeof(double) : sizeof(float);
+    return alloc_n(c, b.x, cap) && alloc_n(c, b.y, cap) && alloc_n(c, b.z, cap) &&
+           (b.vx = dev_alloc(c, vs * cap)) && (b.vy = dev_alloc(c, vs * cap)) &&
+           (b.vz = dev_alloc(c, vs * cap)) && alloc_n(c, b.cell, cap) && alloc_n(c, b.pid, cap);
+}
+
+hipEvent_t get_event(dsmc_ctx c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Timed {
+    dsmc_ctx c;
+    int slot;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(dsmc_ctx c_, int s) : c(c_), slot(s) {
+        if (c->profiling) {
+            a = get_event(c);
+            b = get_event(c);
+            if (a) hipEventRecord(a, c->stream);
+        }
+    }
+    ~Timed() {
+        if (c->profiling && a && b) {
+            hipEventRecord(b, c->stream);
+            c->ev_used.push_back({slot, {a, b}});
+        }
+    }
+};
+
+// the exact particle count and latched flags (synchronises)
+dsmc_status sync_scalars(dsmc_ctx c, Scalars* out) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    Scalars s;
+    HIP_TRY(c, hipMemcpy(&s, c->d_sc, sizeof s, hipMemcpyDeviceToHost));
+    c->np_bound = s.np;
+    if (out) *out = s;
+    if (s.flags & kFlagCapacity) {
+        c->broken = true;
+        return fail(c, DSMC_E_CAPACITY, "particle store capacity exceeded");
+    }
+    return DSMC_OK;
+}
+
+template <class VT>
+dsmc_status run_step(dsmc_ctx c, int mask) {
+    const bool mv = mask & 1, inj = (mask & 2) && c->inflow.n > 0, srt = mask & 4, col = mask & 8,
+               smp = mask & 16;
+    if ((col || smp) && mv && !srt) return fail(c, DSMC_E_INVALID, "collide/sample after move needs sort");
+    const int64_t need = c->np_bound + (inj ? c->max_inject : 0);
+    if (need > c->cap) {
+        dsmc_status st = sync_scalars(c, nullptr);
+        if (st != DSMC_OK) return st;
+        if (c->np_bound + (inj ? c->max_inject : 0) > c->cap)
+            return fail(c, DSMC_E_CAPACITY, "particle store capacity would be exceeded");
+    }
+    hipStream_t s = c->stream;
+    PartDev<VT> a = as_dev<VT>(c->A), b = as_dev<VT>(c->B);
+    {
+        Timed t(c, kSlotBegin);
+        launch_begin(s, c->d_counts, c->nt, c->d_sc, smp ? 1 : 0, c->n_ss);
+    }
+    if (mv) {
+        Timed t(c, kSlotMove);
+        launch_move<VT>(s, c->mesh, a, c->d_sc, c->d_counts, c->d_rank, c->d_ctr, c->key, c->dt, c->np_bound);
+    }
+    if (inj) {
+        Timed t(c, kSlotInject);
+        launch_inject_count(s, c->inflow, c->d_sc, c->key, c->d_fcount);
+        launch_scan(s, c->d_fcount, c->inflow.n, c->d_foff, c->d_blocksums, c->d_sc, kScanInject);
+        launch_inject_emit<VT>(s, c->mesh, c->inflow, a, c->d_sc, c->d_foff, c->d_counts, c->d_rank, c->d_ctr,
+                               c->key, c->dt, c->cap, c->max_inject);
+    }
+    if (srt) {
+        if (!mv && !inj) launch_count(s, a.cell, c->d_sc, c->d_counts, c->d_rank, c->np_bound);
+        {
+            Timed t(c, kSlotScan);
+            launch_scan(s, c->d_counts, c->nt, c->d_offsets, c->d_blocksums, c->d_sc, kScanCells);
+        }
+        {
+            Timed t(c, kSlotScatter);
+            launch_scatter<VT>(s, a, b, c->d_sc, c->d_offsets, c->d_rank, need, c->cap);
+        }
+        std::swap(c->A, c->B);
+        a = as_dev<VT>(c->A);
+        c->np_bound = need;
+    }
+    if (col || smp) {
+        Timed t(c, kSlotCollide);
+        CollideParams cp;
+        cp.nt = c->nt; cp.n_ss = c->n_ss; cp.n_a = c->n_a; cp.ewma_on = c->ewma_on;
+        cp.key = c->key; cp.FN = c->FN; cp.dt = c->dt; cp.K = c->K; cp.ex = c->ex;
+        cp.vol = c->d_vol; cp.smax = c->d_smax; cp.ncand = c->d_ncand; cp.nacc = c->d_nacc;
+        cp.acc = c->d_acc; cp.ewma = c->d_ewma; cp.ewma_m = c->d_ewma_m; cp.local_acc = c->d_local;
+        launch_collide_sample<VT>(s, a, c->d_offsets, cp, c->d_sc, c->d_perm, col ? 1 : 0, smp ? 1 : 0);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        c->broken = true;
+        return fail(c, DSMC_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    return DSMC_OK;
+}
+
+dsmc_status step_any(dsmc_ctx c, int mask) {
+    return c->vel64 ? run_step<double>(c, mask) : run_step<float>(c, mask);
+}
+
+template <class VT>
+void fill_dispatch(dsmc_ctx c, double sig) {
+    launch_init_fill<VT>(c->stream, c->d_tv, c->d_xyz, c->nt, c->d_offsets, as_dev<VT>(c->A), c->key, sig,
+                         c->u0, c->cap, c->d_sc);
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_species_desc* sp, int32_t n_bc,
+                      const dsmc_boundary_desc* bcs, const dsmc_run_desc* run) {
+    if (!out) return fail(nullptr, DSMC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!mesh || !sp || !run || (n_bc > 0 && !bcs) || n_bc < 0)
+        return fail(nullptr, DSMC_E_INVALID, "NULL descriptor");
+    if (sp->alpha != 1.0) return fail(nullptr, DSMC_E_INVALID, "only VHS scattering (alpha = 1) is supported");
+    if (!(sp->mass > 0) || !(sp->d_ref > 0) || !(sp->T_ref > 0) || !(run->F_N > 0) || !(run->dt > 0))
+        return fail(nullptr, DSMC_E_INVALID, "non-positive physical parameter");
+    if (run->n_a < 1) return fail(nullptr, DSMC_E_INVALID, "n_a must be >= 1");
+    for (int g = 0; g < n_bc; ++g)
+        if (bcs[g].kind < 0 || bcs[g].kind > 4) return fail(nullptr, DSMC_E_INVALID, "bad boundary kind");
+
+    dsmc_ctx c = new dsmc_ctx_s();
+    c->stream = (hipStream_t)run->hip_stream;
+    if (run->allocator) {
+        if (!run->allocator->alloc || !run->allocator->free) {
+            delete c;
+            return fail(nullptr, DSMC_E_INVALID, "allocator callbacks missing");
+        }
+        c->alloc = *run->allocator;
+        c->has_alloc = true;
+    }
+    std::string merr = build_mesh(c->hm, mesh->n_vertices, mesh->xyz, mesh->n_tets, mesh->tet_vtx, mesh->n_bfaces,
+                                  mesh->bface_vtx, mesh->bface_group, mesh->bface_partner, n_bc);
+    if (!merr.empty()) {
+        delete c;
+        return fail(nullptr, DSMC_E_MESH, merr);
+    }
+    HostMesh& hm = c->hm;
+    c->nt = hm.nt;
+    c->nb = hm.nb;
+    for (int b = 0; b < hm.nb; ++b)
+        if (bcs[hm.bf_group[b]].kind == DSMC_BC_PERIODIC && hm.bf_partner[b] < 0) {
+            delete c;
+            return fail(nullptr, DSMC_E_MESH, "periodic boundary face without partner");
+        }
+
+    c->mass = sp->mass; c->dref = sp->d_ref; c->omega = sp->omega; c->Tref = sp->T_ref;
+    const double mr = sp->mass / 2.0;
+    c->K = ((M_PI * sp->d_ref) * sp->d_ref) * std::pow(((2.0 * kBoltzmann) * sp->T_ref) / mr, sp->omega - 0.5) /
+           std::tgamma(2.5 - sp->omega);
+    c->ex = 1.0 - sp->omega;
+    c->FN = run->F_N; c->dt = run->dt; c->n0 = run->n0; c->T0 = run->T0;
+    for (int i = 0; i < 3; ++i) c->u0[i] = run->u0[i];
+    c->key = RngKey{(uint32_t)(run->seed & 0xFFFFFFFFu), run->case_id};
+    c->vel64 = run->vel_fp64 ? 1 : 0;
+    c->n_ss = run->n_ss; c->n_a = run->n_a; c->ewma_on = run->ewma_on ? 1 : 0;
+
+    // expected particle count at n0 sizes the default capacity
+    double fill_total = 0;
+    for (int t = 0; t < hm.nt; ++t) fill_total += (run->n0 * hm.vol[t]) / run->F_N + 1.0;
+    c->cap = run->capacity > 0 ? run->capacity : std::max<int64_t>(1024, (int64_t)(2.0 * fill_total) + 1024);
+    if (c->cap >= ((int64_t)1 << 31) - 1) {
+        delete c;
+        return fail(nullptr, DSMC_E_INVALID, "capacity above 2^31 - 1");
+    }
+
+    // ---- inflow faces --------------------------------------------------
+    std::vector<int32_t> in_bf, in_tc;
+    std::vector<double> in_cst;
+    for (int b = 0; b < hm.nb; ++b) {
+        const dsmc_boundary_desc& g = bcs[hm.bf_group[b]];
+        if (g.kind != DSMC_BC_INFLOW) continue;
+        const double* fr = &hm.bf_frame[9 * (size_t)b];
+        const double* nin = fr;
+        const double* t1 = fr + 3;
+        const double* t2 = fr + 6;
+        const double T = g.T;
+        const double beta = std::sqrt(((2.0 * kBoltzmann) * T) / sp->mass);
+        const double sig = std::sqrt((kBoltzmann * T) / sp->mass);
+        const double un = g.u[0] * nin[0] + g.u[1] * nin[1] + g.u[2] * nin[2];
+        const double a = un / beta;
+        const double f1 = std::sqrt((kBoltzmann * T) / ((2.0 * M_PI) * sp->mass));
+        const double f2 = std::exp(-(a * a)) + (DSMC_SQRT_PI * a) * (1.0 + std::erf(a));
+        const double flux = (g.n * f1) * f2;
+        const double mean = ((flux * hm.bf_area[b]) * run->dt) / run->F_N;
+        double cst[kInflowStride];
+        cst[0] = mean; cst[1] = a; cst[2] = beta; cst[3] = sig;
+        cst[4] = g.u[0] * t1[0] + g.u[1] * t1[1] + g.u[2] * t1[2];
+        cst[5] = g.u[0] * t2[0] + g.u[1] * t2[1] + g.u[2] * t2[2];
+        for (int i = 0; i < 9; ++i) cst[6 + i] = fr[i];
+        for (int v = 0; v < 3; ++v)
+            for (int i = 0; i < 3; ++i) cst[15 + 3 * v + i] = hm.xyz[3 * (size_t)hm.bf_vtx[3 * (size_t)b + v] + i];
+        in_cst.insert(in_cst.end(), cst, cst + kInflowStride);
+        in_bf.push_back(b);
+        in_tc.push_back((hm.bf_tet[b] << 2) | hm.bf_lf[b]);
+        c->max_inject += (int64_t)std::floor(mean) + 1;
+    }
+
+    // ---- device allocations --------------------------------------------
+    const int nt = hm.nt, nb = hm.nb;
+    const int nblk_cells = (nt + kScanBlock) / kScanBlock + 1;
+    const int nin = (int)in_bf.size();
+    bool ok = alloc_n(c, c->d_plane, 4 * (size_t)nt) && alloc_n(c, c->d_nbr, 4 * (size_t)nt) &&
+              alloc_n(c, c->d_vol, nt) && alloc_n(c, c->d_bf_group, nb + 1) && alloc_n(c, c->d_bf_pcode, nb + 1) &&
+              alloc_n(c, c->d_bf_frame, 9 * (size_t)nb + 9) && alloc_n(c, c->d_groups, n_bc + 1) &&
+              alloc_n(c, c->d_tv, nt) && alloc_n(c, c->d_xyz, 3 * (size_t)hm.nv) &&
+              alloc_n(c, c->d_counts, nt + 1) && alloc_n(c, c->d_offsets, nt + 1) &&
+              alloc_n(c, c->d_blocksums, std::max(nblk_cells, (nin + kScanBlock) / kScanBlock + 1)) &&
+              alloc_n(c, c->d_smax, nt) && alloc_n(c, c->d_ncand, nt) && alloc_n(c, c->d_nacc, nt) &&
+              alloc_n(c, c->d_acc, (size_t)kNMom * nt) && alloc_n(c, c->d_ewma, (size_t)kNMom * nt) &&
+              alloc_n(c, c->d_ewma_m, nt) && alloc_n(c, c->d_local, nt) && alloc_n(c, c->d_sc, 1) &&
+              alloc_n(c, c->d_ctr, 1) && alloc_n(c, c->d_fcount, nin + 1) && alloc_n(c, c->d_foff, nin + 1);
+    int32_t* d_in_bf = nullptr;
+    int32_t* d_in_tc = nullptr;
+    double* d_in_cst = nullptr;
+    ok = ok && alloc_n(c, d_in_bf, nin + 1) && alloc_n(c, d_in_tc, nin + 1) &&
+         alloc_n(c, d_in_cst, (size_t)kInflowStride * nin + 1);
+    ok = ok && alloc_buf(c, c->A, c->cap, c->vel64) && alloc_buf(c, c->B, c->cap, c->vel64) &&
+         alloc_n(c, c->d_rank, c->cap) && alloc_n(c, c->d_perm, c->cap);
+    if (!ok) {
+        dsmc_destroy(c);
+        return fail(nullptr, DSMC_E_OOM, "device allocation failed");
+    }
+
+    // ---- uploads -------------------------------------------------------
+    std::vector<int32_t> pcode(nb + 1, -1);
+    for (int b = 0; b < nb; ++b) {
+        const int p = hm.bf_partner[b];
+        if (p >= 0) pcode[b] = (hm.bf_tet[p] << 2) | hm.bf_lf[p];
+    }
+    std::vector<GroupDev> groups(n_bc + 1);
+    for (int g = 0; g < n_bc; ++g) {
+        GroupDev& d = groups[g];
+        d.kind = bcs[g].kind;
+        d.pad = 0;
+        d.beta = std::sqrt(((2.0 * kBoltzmann) * bcs[g].T) / sp->mass);
+        d.sw = std::sqrt((kBoltzmann * bcs[g].T) / sp->mass);
+        for (int i = 0; i < 3; ++i) {
+            d.u[i] = bcs[g].u[i];
+            d.shift[i] = bcs[g].shift[i];
+        }
+    }
+    hipStream_t s = c->stream;
+#define UP(dst, src, bytes) HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s))
+    UP(c->d_plane, hm.plane.data(), sizeof(double) * 16 * (size_t)nt);
+    UP(c->d_nbr, hm.nbr.data(), sizeof(int32_t) * 4 * (size_t)nt);
+    UP(c->d_vol, hm.vol.data(), sizeof(double) * nt);
+    if (nb) {
+        UP(c->d_bf_group, hm.bf_group.data(), sizeof(int32_t) * nb);
+        UP(c->d_bf_frame, hm.bf_frame.data(), sizeof(double) * 9 * (size_t)nb);
+    }
+    UP(c->d_bf_pcode, pcode.data(), sizeof(int32_t) * (nb + 1));
+    UP(c->d_groups, groups.data(), sizeof(GroupDev) * (n_bc + 1));
+    UP(c->d_tv, hm.tv.data(), sizeof(int32_t) * 4 * (size_t)nt);
+    UP(c->d_xyz, hm.xyz.data(), sizeof(double) * 3 * (size_t)hm.nv);
+    if (nin) {
+        UP(d_in_bf, in_bf.data(), sizeof(int32_t) * nin);
+        UP(d_in_tc, in_tc.data(), sizeof(int32_t) * nin);
+        UP(d_in_cst, in_cst.data(), sizeof(double) * in_cst.size());
+    }
+    Scalars sc0{};
+    Counters ct0{};
+    UP(c->d_sc, &sc0, sizeof sc0);
+    UP(c->d_ctr, &ct0, sizeof ct0);
+    HIP_TRY(c, hipStreamSynchronize(s));  // host vectors above are temporaries
+    c->mesh.nt = nt;
+    c->mesh.plane = c->d_plane;
+    c->mesh.nbr = c->d_nbr;
+    c->mesh.vol = c->d_vol;
+    c->mesh.bf_group = c->d_bf_group;
+    c->mesh.bf_pcode = c->d_bf_pcode;
+    c->mesh.bf_frame = c->d_bf_frame;
+    c->mesh.groups = c->d_groups;
+    c->mesh.mass = sp->mass;
+    c->inflow.n = nin;
+    c->inflow.bface = d_in_bf;
+    c->inflow.tcode = d_in_tc;
+    c->inflow.consts = d_in_cst;
+
+    // cell state
+    const double eq = (((2.0 * DSMC_SQRT_PI) * sp->d_ref) * sp->d_ref) * std::sqrt(((2.0 * kBoltzmann) * sp->T_ref) / mr) *
+                      std::pow(run->T0 / sp->T_ref, 1.0 - sp->omega);
+    launch_fill_f64(s, c->d_smax, 2.0 * eq, nt);
+    launch_fill_i32(s, c->d_ncand, 0, nt);
+    launch_fill_i32(s, c->d_nacc, 0, nt);
+    launch_fill_f64(s, c->d_acc, 0.0, (int64_t)kNMom * nt);
+    launch_fill_f64(s, c->d_ewma, 0.0, (int64_t)kNMom * nt);
+    launch_fill_i32(s, c->d_ewma_m, 0, nt);
+    HIP_TRY(c, hipMemsetAsync(c->d_local, 0, nt, s));
+    launch_fill_i32(s, c->d_offsets, 0, nt + 1);
+
+    if (run->fill) {
+        launch_init_count(s, c->d_vol, nt, run->n0, run->F_N, c->key, c->d_counts);
+        launch_scan(s, c->d_counts, nt, c->d_offsets, c->d_blocksums, c->d_sc, kScanInit);
+        const double sig = std::sqrt((kBoltzmann * run->T0) / sp->mass);
+        if (c->vel64) fill_dispatch<double>(c, sig); else fill_dispatch<float>(c, sig);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        std::string m = std::string("kernel launch: ") + hipGetErrorString(e);
+        dsmc_destroy(c);
+        return fail(nullptr, DSMC_E_DEVICE, m);
+    }
+    dsmc_status st = sync_scalars(c, nullptr);
+    if (st != DSMC_OK) {
+        std::string m = c->err;
+        dsmc_destroy(c);
+        return fail(nullptr, st, m);
+    }
+    *out = c;
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_step(dsmc_ctx c, int32_t n) {
+    if (!c || n < 0) return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
+    for (int i = 0; i < n; ++i) {
+        dsmc_status s = step_any(c, 31);
+        if (s != DSMC_OK) return s;
+    }
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_step_stages(dsmc_ctx c, int32_t mask) {
+    if (!c || mask < 0 || mask > 31) return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
+    return step_any(c, mask);
+}
+
+dsmc_status dsmc_sync(dsmc_ctx c) {
+    if (!c) return fail(c, DSMC_E_INVALID, "NULL context");
+    return sync_scalars(c, nullptr);
+}
+
+dsmc_status dsmc_sample(dsmc_ctx c, int32_t which, double* out, int32_t out_on_device) {
+    if (!c || !out || (which != DSMC_SAMPLE_STEADY && which != DSMC_SAMPLE_EWMA))
+        return fail(c, DSMC_E_INVALID, "bad arguments");
+    Scalars sc;
+    dsmc_status st = sync_scalars(c, &sc);
+    if (st != DSMC_OK) return st;
+    const double ns = which == DSMC_SAMPLE_STEADY ? (double)sc.n_steady : 1.0;
+    const double* src = which == DSMC_SAMPLE_STEADY ? c->d_acc : c->d_ewma;
+    double* dout = out;
+    double* tmp = nullptr;
+    if (!out_on_device) {
+        if (!alloc_n(c, tmp, 15 * (size_t)c->nt)) return fail(c, DSMC_E_OOM, "device allocation failed");
+        dout = tmp;
+    }
+    launch_fields(c->stream, src, c->nt, ns, c->mass, c->FN, c->d_vol, dout);
+    HIP_TRY(c, hipGetLastError());
+    if (!out_on_device) {
+        HIP_TRY(c, hipMemcpyAsync(out, tmp, sizeof(double) * 15 * (size_t)c->nt, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (tmp) {
+        auto it = std::find(c->owned.begin(), c->owned.end(), (void*)tmp);
+        if (it != c->owned.end()) c->owned.erase(it);
+        if (c->has_alloc) c->alloc.free(tmp, c->alloc.user); else hipFree(tmp);
+    }
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_get_sums(dsmc_ctx c, int32_t which, double* out, int64_t* n_samples) {
+    if (!c || !out || (which != DSMC_SAMPLE_STEADY && which != DSMC_SAMPLE_EWMA))
+        return fail(c, DSMC_E_INVALID, "bad arguments");
+    Scalars sc;
+    dsmc_status st = sync_scalars(c, &sc);
+    if (st != DSMC_OK) return st;
+    std::vector<double> h((size_t)kNMom * c->nt);
+    HIP_TRY(c, hipMemcpy(h.data(), which == DSMC_SAMPLE_STEADY ? c->d_acc : c->d_ewma, sizeof(double) * h.size(),
+                         hipMemcpyDeviceToHost));
+    for (int t = 0; t < c->nt; ++t)
+        for (int k = 0; k < kNMom; ++k) out[(size_t)kNMom * t + k] = h[(size_t)k * c->nt + t];
+    if (n_samples) *n_samples = sc.n_steady;
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_get_state(dsmc_ctx c, dsmc_state* st) {
+    if (!c || !st) return fail(c, DSMC_E_INVALID, "bad arguments");
+    Scalars sc;
+    dsmc_status s = sync_scalars(c, &sc);
+    if (s != DSMC_OK) return s;
+    const int64_t n = sc.np;
+    st->n_particles = n;
+    st->step = sc.step;
+    st->next_pid = sc.next_pid;
+    if (st->smax) HIP_TRY(c, hipMemcpy(st->smax, c->d_smax, sizeof(double) * c->nt, hipMemcpyDeviceToHost));
+    if (!st->x && !st->v && !st->cell && !st->pid) return DSMC_OK;
+    std::vector<double> x(n), y(n), z(n), vx(n), vy(n), vz(n);
+    std::vector<int32_t> cell(n);
+    std::vector<uint32_t> pid(n);
+    HIP_TRY(c, hipMemcpy(x.data(), c->A.x, 8 * n, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(y.data(), c->A.y, 8 * n, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(z.data(), c->A.z, 8 * n, hipMemcpyDeviceToHost));
+    if (c->vel64) {
+        HIP_TRY(c, hipMemcpy(vx.data(), c->A.vx, 8 * n, hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(vy.data(), c->A.vy, 8 * n, hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(vz.data(), c->A.vz, 8 * n, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> f(n);
+        HIP_TRY(c, hipMemcpy(f.data(), c->A.vx, 4 * n, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) vx[i] = f[i];
+        HIP_TRY(c, hipMemcpy(f.data(), c->A.vy, 4 * n, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) vy[i] = f[i];
+        HIP_TRY(c, hipMemcpy(f.data(), c->A.vz, 4 * n, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) vz[i] = f[i];
+    }
+    HIP_TRY(c, hipMemcpy(cell.data(), c->A.cell, 4 * n, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(pid.data(), c->A.pid, 4 * n, hipMemcpyDeviceToHost));
+    std::vector<int64_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+        if (cell[a] != cell[b]) return cell[a] < cell[b];
+        return pid[a] < pid[b];
+    });
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t i = idx[k];
+        if (st->x) { st->x[3 * k] = x[i]; st->x[3 * k + 1] = y[i]; st->x[3 * k + 2] = z[i]; }
+        if (st->v) { st->v[3 * k] = vx[i]; st->v[3 * k + 1] = vy[i]; st->v[3 * k + 2] = vz[i]; }
+        if (st->cell) st->cell[k] = cell[i];
+        if (st->pid) st->pid[k] = pid[i];
+    }
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_set_state(dsmc_ctx c, const dsmc_state* st) {
+    if (!c || !st || st->n_particles < 0 || (st->n_particles > 0 && (!st->x || !st->v || !st->cell || !st->pid)))
+        return fail(c, DSMC_E_INVALID, "bad arguments");
+    const int64_t n = st->n_particles;
+    if (n > c->cap) return fail(c, DSMC_E_CAPACITY, "state larger than the particle store");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::vector<int64_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    for (int64_t i = 0; i < n; ++i)
+        if (st->cell[i] < 0 || st->cell[i] >= c->nt) return fail(c, DSMC_E_INVALID, "particle cell out of range");
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+        if (st->cell[a] != st->cell[b]) return st->cell[a] < st->cell[b];
+        return st->pid[a] < st->pid[b];
+    });
+    std::vector<double> x(n), y(n), z(n), vx(n), vy(n), vz(n);
+    std::vector<int32_t> cell(n), counts(c->nt + 1, 0);
+    std::vector<uint32_t> pid(n);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t i = idx[k];
+        x[k] = st->x[3 * i]; y[k] = st->x[3 * i + 1]; z[k] = st->x[3 * i + 2];
+        vx[k] = st->v[3 * i]; vy[k] = st->v[3 * i + 1]; vz[k] = st->v[3 * i + 2];
+        cell[k] = st->cell[i]; pid[k] = st->pid[i];
+        counts[cell[k] + 1]++;
+    }
+    for (int t = 0; t < c->nt; ++t) counts[t + 1] += counts[t];
+    HIP_TRY(c, hipMemcpy(c->A.x, x.data(), 8 * n, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->A.y, y.data(), 8 * n, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->A.z, z.data(), 8 * n, hipMemcpyHostToDevice));
+    if (c->vel64) {
+        HIP_TRY(c, hipMemcpy(c->A.vx, vx.data(), 8 * n, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->A.vy, vy.data(), 8 * n, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->A.vz, vz.data(), 8 * n, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> f(n);
+        for (int64_t i = 0; i < n; ++i) f[i] = (float)vx[i];
+        HIP_TRY(c, hipMemcpy(c->A.vx, f.data(), 4 * n, hipMemcpyHostToDevice));
+        for (int64_t i = 0; i < n; ++i) f[i] = (float)vy[i];
+        HIP_TRY(c, hipMemcpy(c->A.vy, f.data(), 4 * n, hipMemcpyHostToDevice));
+        for (int64_t i = 0; i < n; ++i) f[i] = (float)vz[i];
+        HIP_TRY(c, hipMemcpy(c->A.vz, f.data(), 4 * n, hipMemcpyHostToDevice));
+    }
+    HIP_TRY(c, hipMemcpy(c->A.cell, cell.data(), 4 * n, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->A.pid, pid.data(), 4 * n, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_offsets, counts.data(), 4 * (c->nt + 1), hipMemcpyHostToDevice));
+    if (st->smax) HIP_TRY(c, hipMemcpy(c->d_smax, st->smax, sizeof(double) * c->nt, hipMemcpyHostToDevice));
+    Scalars sc;
+    HIP_TRY(c, hipMemcpy(&sc, c->d_sc, sizeof sc, hipMemcpyDeviceToHost));
+    sc.np = n;
+    sc.n_entries = n;
+    sc.step = st->step;
+    sc.next_pid = st->next_pid;
+    sc.ninj = 0;
+    HIP_TRY(c, hipMemcpy(c->d_sc, &sc, sizeof sc, hipMemcpyHostToDevice));
+    c->np_bound = n;
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_get_pair_counts(dsmc_ctx c, int32_t* ncand, int32_t* nacc) {
+    if (!c) return fail(c, DSMC_E_INVALID, "NULL context");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (ncand) HIP_TRY(c, hipMemcpy(ncand, c->d_ncand, 4 * (size_t)c->nt, hipMemcpyDeviceToHost));
+    if (nacc) HIP_TRY(c, hipMemcpy(nacc, c->d_nacc, 4 * (size_t)c->nt, hipMemcpyDeviceToHost));
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_stats(dsmc_ctx c, dsmc_counters* out) {
+    if (!c || !out) return fail(c, DSMC_E_INVALID, "bad arguments");
+    Scalars sc;
+    dsmc_status st = sync_scalars(c, &sc);
+    Counters ct;
+    HIP_TRY(c, hipMemcpy(&ct, c->d_ctr, sizeof ct, hipMemcpyDeviceToHost));
+    out->n_particles = sc.np;
+    out->hops = (int64_t)ct.hops;
+    out->wall_hits = (int64_t)ct.walls;
+    out->injected = (int64_t)ct.injected;
+    out->removed = (int64_t)ct.removed;
+    out->lost = (int64_t)ct.lost;
+    out->step = sc.step;
+    return st;
+}
+
+dsmc_status dsmc_set_local_acc(dsmc_ctx c, const uint8_t* flags) {
+    if (!c || !flags) return fail(c, DSMC_E_INVALID, "bad arguments");
+    HIP_TRY(c, hipMemcpyAsync(c->d_local, flags, c->nt, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_profile(dsmc_ctx c, int32_t enable) {
+    if (!c) return fail(c, DSMC_E_INVALID, "NULL context");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto& u : c->ev_used) {
+        c->ev_pool.push_back(u.second.first);
+        c->ev_pool.push_back(u.second.second);
+    }
+    c->ev_used.clear();
+    c->profiling = enable != 0;
+    return DSMC_OK;
+}
+
+int32_t dsmc_profile_read(dsmc_ctx c, double* total_ms, int64_t* launches, int32_t max_slots) {
+    if (!c) return -1;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return -1;
+    std::vector<double> ms(kNumSlots, 0.0);
+    std::vector<int64_t> cnt(kNumSlots, 0);
+    for (auto& u : c->ev_used) {
+        float t = 0;
+        if (hipEventElapsedTime(&t, u.second.first, u.second.second) == hipSuccess) {
+            ms[u.first] += t;
+            cnt[u.first] += 1;
+        }
+    }
+    for (int i = 0; i < std::min<int>(max_slots, kNumSlots); ++i) {
+        if (total_ms) total_ms[i] = ms[i];
+        if (launches) launches[i] = cnt[i];
+    }
+    return kNumSlots;
+}
+
+const char* dsmc_profile_name(int32_t slot) {
+    return (slot >= 0 && slot < kNumSlots) ? kSlotNames[slot] : "";
+}
+
+dsmc_status dsmc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n) {
+    if (!ctr || !key || !out || n < 0) return fail(nullptr, DSMC_E_INVALID, "bad arguments");
+    if (n == 0) return DSMC_OK;
+    uint32_t* d_in = nullptr;
+    uint32_t* d_out = nullptr;
+    if (hipMalloc(&d_in, 16 * n) != hipSuccess) return fail(nullptr, DSMC_E_OOM, "hipMalloc failed");
+    if (hipMalloc(&d_out, 16 * n) != hipSuccess) {
+        hipFree(d_in);
+        return fail(nullptr, DSMC_E_OOM, "hipMalloc failed");
+    }
+    dsmc_status st = DSMC_OK;
+    if (hipMemcpy(d_in, ctr, 16 * n, hipMemcpyHostToDevice) != hipSuccess) st = DSMC_E_DEVICE;
+    if (st == DSMC_OK) {
+        launch_philox(nullptr, d_in, key[0], key[1], d_out, n);
+        if (hipGetLastError() != hipSuccess || hipMemcpy(out, d_out, 16 * n, hipMemcpyDeviceToHost) != hipSuccess)
+            st = DSMC_E_DEVICE;
+    }
+    hipFree(d_in);
+    hipFree(d_out);
+    if (st != DSMC_OK) return fail(nullptr, st, "device Philox failed");
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_device_copy(dsmc_ctx c, void* dst, const void* src, size_t bytes) {
+    if (!c || !dst || !src || (bytes % 16) != 0) return fail(c, DSMC_E_INVALID, "bad arguments (bytes % 16)");
+    launch_copy(c->stream, src, dst, bytes);
+    HIP_TRY(c, hipGetLastError());
+    return DSMC_OK;
+}
+
+const char* dsmc_last_error(dsmc_ctx c) { return c ? c->err.c_str() : g_global_error.c_str(); }
+
+void dsmc_destroy(dsmc_ctx c) {
+    if (!c) return;
+    hipStreamSynchronize(c->stream);
+    for (auto& u : c->ev_used) {
+        hipEventDestroy(u.second.first);
+        hipEventDestroy(u.second.second);
+    }
+    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+    for (void* p : c->owned) {
+        if (c->has_alloc) c->alloc.free(p, c->alloc.user); else hipFree(p);
+    }
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+// Device-side building blocks shared by the kernels: the counter-based
+// generator, its transforms and the particle tracking step.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsmcx {
+
+#define DSMC_TWO_PI 6.283185307179586
+#define DSMC_SQRT_PI 1.7724538509055159
+#define DSMC_INV_SQRT2 0.7071067811865476
+#define DSMC_MAX_HOPS 1000
+
+// Stream purposes of the counter layout (subject, step, purpose<<24 | block, block>>24).
+enum : uint32_t {
+    kPurposeInit = 1,
+    kPurposeWall = 2,
+    kPurposeInjectCount = 3,
+    kPurposeNtcCount = 4,
+    kPurposePair = 5,
+    kPurposeScatter = 6,
+    kPurposeRecalibrate = 7,
+    kPurposeMlp = 8,
+    kPurposeInitCount = 9,
+    kPurposeInject = 10,
+};
+
+enum : int { kBcDiffuse = 0, kBcSpecular = 1, kBcInflow = 2, kBcOutflow = 3, kBcPeriodic = 4 };
+
+struct Rand4 {
+    uint32_t w[4];
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplications mixed with the other words and the key; the key
+// advances by the two Weyl constants between rounds.
+__device__ __forceinline__ Rand4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    Rand4 o;
+    o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+    return o;
+}
+
+struct RngKey {
+    uint32_t k0, k1;
+};
+
+__device__ __forceinline__ Rand4 draw(RngKey key, uint32_t subject, uint32_t step, uint32_t purpose,
+                                      uint64_t block) {
+    return philox(subject, step, (purpose << 24) | (uint32_t)(block & 0xFFFFFFu), (uint32_t)(block >> 24),
+                  key.k0, key.k1);
+}
+
+// Uniform in (0,1): 52 random bits k from two words, (k + 1/2) * 2^-52,
+// exact in binary64 and never 0 or 1.
+__device__ __forceinline__ double u01(uint32_t a, uint32_t b) {
+    const uint64_t k = ((uint64_t)(a >> 6) << 26) | (uint64_t)(b >> 6);
+    return ((double)k + 0.5) * 0x1p-52;
+}
+
+// Integer in [0, n) by 32x32 multiply-shift.
+__device__ __forceinline__ uint32_t pick(uint32_t r, uint32_t n) {
+    return (uint32_t)(((uint64_t)r * (uint64_t)n) >> 32);
+}
+
+__device__ __forceinline__ void box_muller(double u1, double u2, double& g1, double& g2) {
+    const double r = sqrt(-2.0 * log(u1));
+    const double a = DSMC_TWO_PI * u2;
+    g1 = r * cos(a);
+    g2 = r * sin(a);
+}
+
+template <class VT>
+__device__ __forceinline__ double round_store(double x) {
+    return (double)(VT)x;
+}
+
+// Boundary group constants on the device.
+struct GroupDev {
+    int kind;
+    int pad;
+    double beta;     // sqrt(2 k T / m)
+    double sw;       // sqrt(k T / m)
+    double u[3];
+    double shift[3];
+};
+
+struct MeshDev {
+    int nt;
+    const double4* plane;    // [nt*4] outward (s n, s d)
+    const int32_t* nbr;      // [nt*4] (tet<<2|lf) or -1-bface
+    const double* vol;       // [nt]
+    const int32_t* bf_group; // [nb]
+    const int32_t* bf_pcode; // [nb] periodic partner (tet<<2|lf) or -1
+    const double* bf_frame;  // [nb][9]
+    const GroupDev* groups;
+    double mass;
+};
+
+struct TraceOut {
+    int status;   // 0 alive, 1 removed through an open face, 2 lost
+    int hops;
+    int walls;
+};
+
+// Face-to-face tracking of one particle for time t (the exit test is the
+// same arithmetic as the plane contract: den = N.v, lambda = (D - N.x)/den
+// over faces with den > 0 other than the entry face, clamped at 0, minimum
+// with ties to the lowest local face).
+template <class VT>
+__device__ __forceinline__ TraceOut trace(const MeshDev& m, double& x0, double& x1, double& x2,
+                                          double& v0, double& v1, double& v2, int& cell, int entry,
+                                          uint32_t pid, uint32_t step, RngKey key, double t) {
+    TraceOut out{0, 0, 0};
+    int c = cell;
+    int nhop = 0;
+    int hits = 0;
+    for (;;) {
+        int fb = -1;
+        double lb = 0.0;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            if (f == entry) continue;
+            const double4 pl = m.plane[4 * c + f];
+            const double den = pl.x * v0 + pl.y * v1 + pl.z * v2;
+            if (den > 0) {
+                double lam = (pl.w - (pl.x * x0 + pl.y * x1 + pl.z * x2)) / den;
+                if (lam < 0) lam = 0;
+                if (fb < 0 || lam < lb) {
+                    fb = f;
+                    lb = lam;
+                }
+            }
+        }
+        if (fb < 0 || lb >= t) {
+            x0 = x0 + v0 * t;
+            x1 = x1 + v1 * t;
+            x2 = x2 + v2 * t;
+            break;
+        }
+        x0 = x0 + v0 * lb;
+        x1 = x1 + v1 * lb;
+        x2 = x2 + v2 * lb;
+        t = t - lb;
+        ++nhop;
+        if (nhop > DSMC_MAX_HOPS) {
+            out.status = 2;
+            break;
+        }
+        const int code = m.nbr[4 * c + fb];
+        if (code >= 0) {
+            c = code >> 2;
+            entry = code & 3;
+            continue;
+        }
+        const int bf = -1 - code;
+        const GroupDev& g = m.groups[m.bf_group[bf]];
+        if (g.kind == kBcDiffuse) {
+            const Rand4 r0 = draw(key, pid, step, kPurposeWall, (uint64_t)(2 * hits));
+            const Rand4 r1 = draw(key, pid, step, kPurposeWall, (uint64_t)(2 * hits + 1));
+            const double ua = u01(r0.w[0], r0.w[1]);
+            const double ub = u01(r0.w[2], r0.w[3]);
+            const double uc = u01(r1.w[0], r1.w[1]);
+            const double vn = g.beta * sqrt(-log(ua));
+            double g1, g2;
+            box_muller(ub, uc, g1, g2);
+            const double* fr = m.bf_frame + 9 * (size_t)bf;
+            v0 = round_store<VT>((vn * fr[0] + g.sw * (g1 * fr[3] + g2 * fr[6])) + g.u[0]);
+            v1 = round_store<VT>((vn * fr[1] + g.sw * (g1 * fr[4] + g2 * fr[7])) + g.u[1]);
+            v2 = round_store<VT>((vn * fr[2] + g.sw * (g1 * fr[5] + g2 * fr[8])) + g.u[2]);
+            ++hits;
+            ++out.walls;
+            entry = fb;
+        } else if (g.kind == kBcSpecular) {
+            const double4 pl = m.plane[4 * c + fb];
+            const double vn = pl.x * v0 + pl.y * v1 + pl.z * v2;
+            const double nn = pl.x * pl.x + pl.y * pl.y + pl.z * pl.z;
+            const double f2 = 2.0 * (vn / nn);
+            v0 = round_store<VT>(v0 - f2 * pl.x);
+            v1 = round_store<VT>(v1 - f2 * pl.y);
+            v2 = round_store<VT>(v2 - f2 * pl.z);
+            ++out.walls;
+            entry = fb;
+        } else if (g.kind == kBcPeriodic) {
+            x0 = x0 + g.shift[0];
+            x1 = x1 + g.shift[1];
+            x2 = x2 + g.shift[2];
+            const int pc = m.bf_pcode[bf];
+            c = pc >> 2;
+            entry = pc & 3;
+        } else {
+            out.status = 1;
+            break;
+        }
+    }
+    out.hops = nhop;
+    cell = c;
+    return out;
+}
+
+}  // namespace dsmcx

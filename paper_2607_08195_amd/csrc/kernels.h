@@ -1,0 +1,105 @@
+// Device data structures and kernel launch wrappers of the DSMC step.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace dsmcx {
+
+constexpr double kBoltzmannDev = 1.380649e-23;
+constexpr int kNMom = 13;               // S0, S1(3), S2(6), S3(3)
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanBlock = kScanThreads * kScanItems;
+constexpr int kCollideLanes = 64;       // one wave, one lane per cell
+constexpr int kCollideCap = 2048;       // particles of one 64-cell chunk staged in LDS
+constexpr int kInflowStride = 24;       // doubles per inflow face
+enum { kScanPlain = 0, kScanCells = 1, kScanInject = 2, kScanInit = 3 };
+enum { kFlagCapacity = 1 };
+
+// Particle store, structure of arrays.
+template <class VT>
+struct PartDev {
+    double* x;
+    double* y;
+    double* z;
+    VT* vx;
+    VT* vy;
+    VT* vz;
+    int32_t* cell;
+    uint32_t* pid;
+};
+
+// Device-resident scalars of the step (read by kernels, never by the host
+// inside a step).
+struct Scalars {
+    int64_t np;         // particles in the sorted buffer
+    int64_t n_entries;  // entries of the unsorted buffer (np + injected) to scatter
+    int64_t n_steady;   // steps summed into the steady accumulator
+    uint32_t step;      // current step index
+    uint32_t next_pid;
+    int32_t ninj;       // particles injected this step
+    int32_t flags;
+};
+
+struct Counters {
+    unsigned long long hops, walls, injected, removed, lost;
+};
+
+// Inflow faces: consts[j][24] = mean count, speed ratio a, beta, sigma,
+// tangential mean (2), inward normal (3), t1 (3), t2 (3), vertices A,B,C (9).
+struct InflowDev {
+    int n;
+    const int32_t* bface;   // boundary face index (generator subject)
+    const int32_t* tcode;   // (tet << 2 | local face) owning the face
+    const double* consts;
+};
+
+struct CollideParams {
+    int nt;
+    int n_ss, n_a, ewma_on;
+    RngKey key;
+    double FN, dt, K, ex;
+    const double* vol;
+    double* smax;
+    int32_t* ncand;
+    int32_t* nacc;
+    double* acc;        // [13][nt] steady sums
+    double* ewma;       // [13][nt] moving average
+    int32_t* ewma_m;    // [nt] samples seen
+    const uint8_t* local_acc;
+};
+
+void launch_begin(hipStream_t s, int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss);
+void launch_init_count(hipStream_t s, const double* vol, int nt, double n0, double FN, RngKey key,
+                       int32_t* counts);
+template <class VT>
+void launch_init_fill(hipStream_t s, const int4* tv, const double* xyz, int nt, const int32_t* offsets,
+                      PartDev<VT> p, RngKey key, double sig, const double* u0, int64_t cap, Scalars* sc);
+template <class VT>
+void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
+                 uint32_t* rank, Counters* ctr, RngKey key, double dt, int64_t np_bound);
+void launch_count(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
+                  int64_t np_bound);
+void launch_inject_count(hipStream_t s, const InflowDev& in, const Scalars* sc, RngKey key, int32_t* fcount);
+template <class VT>
+void launch_inject_emit(hipStream_t s, const MeshDev& m, const InflowDev& in, PartDev<VT> p, Scalars* sc,
+                        const int32_t* foff, int32_t* counts, uint32_t* rank, Counters* ctr, RngKey key,
+                        double dt, int64_t cap, int64_t max_inject);
+void launch_scan(hipStream_t s, const int32_t* in, int64_t n, int32_t* out, int32_t* blocksums, Scalars* sc,
+                 int mode);
+template <class VT>
+void launch_scatter(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalars* sc, const int32_t* offsets,
+                    const uint32_t* rank, int64_t bound, int64_t cap);
+template <class VT>
+void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
+                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample);
+void launch_fields(hipStream_t s, const double* sums, int nt, double ns, double mass, double FN,
+                   const double* vol, double* out);
+void launch_philox(hipStream_t s, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n);
+void launch_copy(hipStream_t s, const void* src, void* dst, size_t bytes);
+void launch_fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n);
+void launch_fill_f64(hipStream_t s, double* p, double v, int64_t n);
+
+}  // namespace dsmcx

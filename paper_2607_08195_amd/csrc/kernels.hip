@@ -1,0 +1,778 @@
+// HIP kernels of the DSMC step for gfx950 (wave64, 256 CUs on 8 XCDs).
+//
+// Per step (paper section 2.1: move, then select and collide pairs per
+// cell; sampling per eq. dsmc_temperatures after the collisions):
+//   k_begin          clear cell histogram, advance the device step counter
+//   k_move           face-to-face tracking of every particle + histogram
+//   k_inject_*       freestream particles on inflow faces (count, emit+trace)
+//   k_scan_*         exclusive prefix of the cell histogram -> cell offsets
+//   k_scatter        counting-sort scatter into the other particle buffer
+//   k_collide_sample one lane per cell: rank the cell's particles by pid,
+//                    NTC/VHS collisions and FP64 moment sums, in LDS
+#include "kernels.h"
+
+namespace dsmcx {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
+// XCD walks one contiguous slice of the particle range (its L2 then holds
+// the mesh neighbourhood of that slice).  gridDim.x is a multiple of 8.
+__device__ __forceinline__ int64_t xcd_block() {
+    const int64_t per = gridDim.x >> 3;
+    return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum four counters over the block and add them to global counters.
+__device__ __forceinline__ void block_counters(int a, int b, int c, int d, unsigned long long* ga,
+                                               unsigned long long* gb, unsigned long long* gc,
+                                               unsigned long long* gd) {
+    __shared__ int red[4][16];
+    a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); d = wave_sum(d);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { red[0][w] = a; red[1][w] = b; red[2][w] = c; red[3][w] = d; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        int s[4] = {0, 0, 0, 0};
+        for (int k = 0; k < nw; ++k)
+            for (int j = 0; j < 4; ++j) s[j] += red[j][k];
+        if (s[0]) atomicAdd(ga, (unsigned long long)s[0]);
+        if (s[1]) atomicAdd(gb, (unsigned long long)s[1]);
+        if (s[2]) atomicAdd(gc, (unsigned long long)s[2]);
+        if (s[3]) atomicAdd(gd, (unsigned long long)s[3]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// step bookkeeping
+// ---------------------------------------------------------------------------
+__global__ void k_begin(int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= nt) counts[i] = 0;
+    if (i == 0) {
+        const uint32_t s = sc->step + 1;
+        sc->step = s;
+        sc->ninj = 0;
+        if (do_sample && (int64_t)s > (int64_t)n_ss) sc->n_steady += 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// initial fill
+// ---------------------------------------------------------------------------
+__global__ void k_init_count(const double* vol, int nt, double n0, double FN, RngKey key,
+                             int32_t* counts) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const double mean = (n0 * vol[t]) / FN;
+    const Rand4 r = draw(key, (uint32_t)t, 0u, kPurposeInitCount, 0);
+    counts[t] = (int32_t)floor(mean + u01(r.w[0], r.w[1]));
+}
+
+template <class VT>
+__global__ void k_init_fill(const int4* tv, const double* xyz, int nt, const int32_t* offsets,
+                            PartDev<VT> p, RngKey key, double sig, double u0x, double u0y, double u0z,
+                            int64_t cap, Scalars* sc) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const int4 q = tv[t];
+    const double* A = xyz + 3 * (size_t)q.x;
+    const double* B = xyz + 3 * (size_t)q.y;
+    const double* C = xyz + 3 * (size_t)q.z;
+    const double* D = xyz + 3 * (size_t)q.w;
+    const int64_t a = offsets[t], b = offsets[t + 1];
+    if (b > cap) {
+        if (t == 0) atomicOr(&sc->flags, kFlagCapacity);
+        return;
+    }
+    for (int64_t k = a; k < b; ++k) {
+        const uint32_t id = (uint32_t)k;
+        double u[8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const Rand4 r = draw(key, id, 0u, kPurposeInit, (uint64_t)j);
+            u[2 * j] = u01(r.w[0], r.w[1]);
+            u[2 * j + 1] = u01(r.w[2], r.w[3]);
+        }
+        double s1 = u[0], s2 = u[1], s3 = u[2], tmp;
+        if (s1 > s2) { tmp = s1; s1 = s2; s2 = tmp; }
+        if (s2 > s3) { tmp = s2; s2 = s3; s3 = tmp; }
+        if (s1 > s2) { tmp = s1; s1 = s2; s2 = tmp; }
+        const double w0 = s1, w1 = s2 - s1, w2 = s3 - s2, w3 = 1.0 - s3;
+        p.x[k] = ((w0 * A[0] + w1 * B[0]) + w2 * C[0]) + w3 * D[0];
+        p.y[k] = ((w0 * A[1] + w1 * B[1]) + w2 * C[1]) + w3 * D[1];
+        p.z[k] = ((w0 * A[2] + w1 * B[2]) + w2 * C[2]) + w3 * D[2];
+        double g1, g2, g3, g4;
+        box_muller(u[3], u[4], g1, g2);
+        box_muller(u[5], u[6], g3, g4);
+        p.vx[k] = (VT)(u0x + sig * g1);
+        p.vy[k] = (VT)(u0y + sig * g2);
+        p.vz[k] = (VT)(u0z + sig * g3);
+        p.cell[k] = t;
+        p.pid[k] = id;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// move
+// ---------------------------------------------------------------------------
+template <class VT>
+__global__ __launch_bounds__(256) void k_move(MeshDev m, PartDev<VT> p, const Scalars* sc,
+                                             int32_t* counts, uint32_t* rank, Counters* ctr,
+                                             RngKey key, double dt) {
+    const int64_t i = xcd_block() * 256 + threadIdx.x;
+    const int64_t n = sc->np;
+    int hops = 0, walls = 0, rem = 0, lost = 0;
+    if (i < n) {
+        int c = p.cell[i];
+        double x0 = p.x[i], x1 = p.y[i], x2 = p.z[i];
+        const double v0i = (double)p.vx[i], v1i = (double)p.vy[i], v2i = (double)p.vz[i];
+        double v0 = v0i, v1 = v1i, v2 = v2i;
+        const uint32_t pid = p.pid[i];
+        const TraceOut o = trace<VT>(m, x0, x1, x2, v0, v1, v2, c, -1, pid, sc->step, key, dt);
+        hops = o.hops;
+        walls = o.walls;
+        p.x[i] = x0;
+        p.y[i] = x1;
+        p.z[i] = x2;
+        if (o.walls) {
+            p.vx[i] = (VT)v0;
+            p.vy[i] = (VT)v1;
+            p.vz[i] = (VT)v2;
+        }
+        if (o.status == 0) {
+            p.cell[i] = c;
+            rank[i] = (uint32_t)atomicAdd(&counts[c], 1);
+        } else {
+            p.cell[i] = -1;
+            rem = o.status == 1;
+            lost = o.status == 2;
+        }
+    }
+    block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
+}
+
+// Histogram of the current cells (sort without a preceding move).
+__global__ void k_count(const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc->np) return;
+    const int c = cell[i];
+    if (c >= 0) rank[i] = (uint32_t)atomicAdd(&counts[c], 1);
+}
+
+// ---------------------------------------------------------------------------
+// freestream injection
+// ---------------------------------------------------------------------------
+__global__ void k_inject_count(const InflowDev in, const Scalars* sc, RngKey key, int32_t* fcount) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= in.n) return;
+    const double* cst = in.consts + (size_t)kInflowStride * j;
+    const Rand4 r = draw(key, (uint32_t)in.bface[j], sc->step, kPurposeInjectCount, 0);
+    fcount[j] = (int32_t)floor(cst[0] + u01(r.w[0], r.w[1]));
+}
+
+// Normal speed ratio z > 0 with density proportional to z exp(-(z-a)^2).
+__device__ double flux_normal(double a, RngKey key, uint32_t bf, uint32_t step, uint64_t k) {
+    if (a == 0.0) {
+        const Rand4 r = draw(key, bf, step, kPurposeInject, (k << 6) | 3u);
+        return sqrt(-log(u01(r.w[0], r.w[1])));
+    }
+    for (int tr = 0; tr < 30; ++tr) {
+        const Rand4 r0 = draw(key, bf, step, kPurposeInject, (k << 6) | (uint64_t)(3 + 2 * tr));
+        const Rand4 r1 = draw(key, bf, step, kPurposeInject, (k << 6) | (uint64_t)(4 + 2 * tr));
+        const double ua = u01(r0.w[0], r0.w[1]), ub = u01(r0.w[2], r0.w[3]);
+        const double uc = u01(r1.w[0], r1.w[1]), ud = u01(r1.w[2], r1.w[3]);
+        if (a > 0) {
+            const double pa = (a * DSMC_SQRT_PI) / ((a * DSMC_SQRT_PI) + 1.0);
+            double w;
+            if (ua < pa) {
+                double g1, g2;
+                box_muller(ub, uc, g1, g2);
+                w = g1 * DSMC_INV_SQRT2;
+            } else {
+                const double rr = sqrt(-log(ub));
+                w = uc < 0.5 ? rr : -rr;
+            }
+            const double z = a + w;
+            if (z > 0 && ud * (a + fabs(w)) < z) return z;
+        } else {
+            const double w = sqrt(a * a - log(ub));
+            const double z = a + w;
+            if (ud * w < z) return z;
+        }
+    }
+    return a > 0 ? a : 0.5;
+}
+
+template <class VT>
+__global__ __launch_bounds__(256) void k_inject_emit(MeshDev m, const InflowDev in, PartDev<VT> p,
+                                                    Scalars* sc, const int32_t* foff, int32_t* counts,
+                                                    uint32_t* rank, Counters* ctr, RngKey key, double dt,
+                                                    int64_t cap) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = foff[in.n];
+    int hops = 0, walls = 0, rem = 0, lost = 0, made = 0;
+    if (idx < total) {
+        // face j: the last with foff[j] <= idx
+        int lo = 0, hi = in.n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (foff[mid] <= idx) lo = mid; else hi = mid - 1;
+        }
+        const int j = lo;
+        const int64_t k = idx - foff[j];
+        const double* cst = in.consts + (size_t)kInflowStride * j;
+        const uint32_t bf = (uint32_t)in.bface[j];
+        const uint32_t step = sc->step;
+        const uint64_t kb = (uint64_t)k << 6;
+        Rand4 r = draw(key, bf, step, kPurposeInject, kb | 0u);
+        double r1 = u01(r.w[0], r.w[1]), r2 = u01(r.w[2], r.w[3]);
+        if (r1 + r2 > 1.0) { r1 = 1.0 - r1; r2 = 1.0 - r2; }
+        r = draw(key, bf, step, kPurposeInject, kb | 1u);
+        const double ut = u01(r.w[0], r.w[1]);
+        r = draw(key, bf, step, kPurposeInject, kb | 2u);
+        double g1, g2;
+        box_muller(u01(r.w[0], r.w[1]), u01(r.w[2], r.w[3]), g1, g2);
+        const double z = flux_normal(cst[1], key, bf, step, (uint64_t)k);
+        const double vn = cst[2] * z;
+        const double vt1 = cst[3] * g1 + cst[4];
+        const double vt2 = cst[3] * g2 + cst[5];
+        const double* nin = cst + 6;
+        const double* t1 = cst + 9;
+        const double* t2 = cst + 12;
+        const double* A = cst + 15;
+        const double* B = cst + 18;
+        const double* C = cst + 21;
+        double x0 = (A[0] + r1 * (B[0] - A[0])) + r2 * (C[0] - A[0]);
+        double x1 = (A[1] + r1 * (B[1] - A[1])) + r2 * (C[1] - A[1]);
+        double x2 = (A[2] + r1 * (B[2] - A[2])) + r2 * (C[2] - A[2]);
+        double v0 = round_store<VT>((vn * nin[0] + vt1 * t1[0]) + vt2 * t2[0]);
+        double v1 = round_store<VT>((vn * nin[1] + vt1 * t1[1]) + vt2 * t2[1]);
+        double v2 = round_store<VT>((vn * nin[2] + vt1 * t1[2]) + vt2 * t2[2]);
+        const uint32_t pid = sc->next_pid + (uint32_t)idx;
+        const int code = in.tcode[j];
+        int c = code >> 2;
+        made = 1;
+        const TraceOut o = trace<VT>(m, x0, x1, x2, v0, v1, v2, c, code & 3, pid, step, key, ut * dt);
+        hops = o.hops;
+        walls = o.walls;
+        const int64_t slot = sc->np + idx;
+        if (slot >= cap) {
+            atomicOr(&sc->flags, kFlagCapacity);
+        } else {
+            p.x[slot] = x0; p.y[slot] = x1; p.z[slot] = x2;
+            p.vx[slot] = (VT)v0; p.vy[slot] = (VT)v1; p.vz[slot] = (VT)v2;
+            p.pid[slot] = pid;
+            if (o.status == 0) {
+                p.cell[slot] = c;
+                rank[slot] = (uint32_t)atomicAdd(&counts[c], 1);
+            } else {
+                p.cell[slot] = -1;
+                rem = o.status == 1;
+                lost = o.status == 2;
+            }
+        }
+    }
+    block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
+    // injected count
+    const int s = wave_sum(made);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&ctr->injected, (unsigned long long)s);
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 counts[n] -> offsets[n+1]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// block-wide exclusive scan over blockDim.x (<= 1024) threads; returns the
+// exclusive prefix of v and writes the block total to *total.
+__device__ __forceinline__ int block_excl_scan(int v, int* total) {
+    __shared__ int ws[17];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int inc = wave_incl_scan(v);
+    if (lane == 63) ws[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int k = 0; k < nw; ++k) {
+            const int t = ws[k];
+            ws[k] = acc;
+            acc += t;
+        }
+        ws[16] = acc;
+    }
+    __syncthreads();
+    const int res = ws[w] + inc - v;
+    *total = ws[16];
+    __syncthreads();
+    return res;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* in, int64_t n,
+                                                              int32_t* blocksums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    int s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    int total;
+    block_excl_scan(s, &total);
+    if (threadIdx.x == 0) blocksums[blockIdx.x] = total;
+}
+
+// Single workgroup: exclusive scan of the block sums; the grand total
+// updates the device scalars according to mode.
+__global__ __launch_bounds__(1024) void k_scan_top(int32_t* blocksums, int nblk, Scalars* sc, int mode,
+                                                   int32_t* tail) {
+    int carry = 0;
+    for (int base = 0; base < nblk; base += 1024) {
+        const int i = base + threadIdx.x;
+        const int v = i < nblk ? blocksums[i] : 0;
+        int total;
+        const int ex = block_excl_scan(v, &total);
+        if (i < nblk) blocksums[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        *tail = carry;
+        if (mode == kScanCells) {
+            const int64_t ninj = sc->ninj;
+            sc->n_entries = sc->np + ninj;
+            sc->next_pid += (uint32_t)ninj;
+            sc->np = carry;
+        } else if (mode == kScanInject) {
+            sc->ninj = carry;
+        } else if (mode == kScanInit) {
+            sc->np = carry;
+            sc->n_entries = carry;
+            sc->next_pid = (uint32_t)carry;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const int32_t* in, int64_t n,
+                                                            const int32_t* blocksums, int32_t* out) {
+    __shared__ int buf[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+        buf[k * kScanThreads + threadIdx.x] = i < n ? in[i] : 0;
+    }
+    __syncthreads();
+    // each thread owns kScanItems consecutive entries
+    int loc[kScanItems];
+    int s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        loc[k] = s;
+        s += buf[threadIdx.x * kScanItems + k];
+    }
+    int total;
+    const int ex = block_excl_scan(s, &total);
+    const int off = blocksums[blockIdx.x] + ex;
+    __syncthreads();
+    for (int k = 0; k < kScanItems; ++k) buf[threadIdx.x * kScanItems + k] = off + loc[k];
+    __syncthreads();
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (i < n) out[i] = buf[k * kScanThreads + threadIdx.x];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// counting-sort scatter
+// ---------------------------------------------------------------------------
+template <class VT>
+__global__ __launch_bounds__(256) void k_scatter(PartDev<VT> src, PartDev<VT> dst, const Scalars* sc,
+                                                const int32_t* offsets, const uint32_t* rank, int64_t cap) {
+    const int64_t i = xcd_block() * 256 + threadIdx.x;
+    if (i >= sc->n_entries || i >= cap) return;
+    const int c = src.cell[i];
+    if (c < 0) return;
+    const int64_t d = (int64_t)offsets[c] + rank[i];
+    dst.x[d] = src.x[i];
+    dst.y[d] = src.y[i];
+    dst.z[d] = src.z[i];
+    dst.vx[d] = src.vx[i];
+    dst.vy[d] = src.vy[i];
+    dst.vz[d] = src.vz[i];
+    dst.cell[d] = c;
+    dst.pid[d] = src.pid[i];
+}
+
+// ---------------------------------------------------------------------------
+// collisions and sampling
+// ---------------------------------------------------------------------------
+// Access to the velocities of one cell in logical (pid) order.
+template <class VT>
+struct LdsCell {
+    VT* v0; VT* v1; VT* v2;
+    const uint16_t* ord;
+    uint8_t* touch;
+    int s0;
+    __device__ __forceinline__ void get(int k, double& a, double& b, double& c) const {
+        const int l = ord[s0 + k];
+        a = (double)v0[l]; b = (double)v1[l]; c = (double)v2[l];
+    }
+    __device__ __forceinline__ void put(int k, double a, double b, double c) const {
+        const int l = ord[s0 + k];
+        v0[l] = (VT)a; v1[l] = (VT)b; v2[l] = (VT)c;
+        touch[l] = 1;
+    }
+};
+
+template <class VT>
+struct GlobalCell {
+    VT* v0; VT* v1; VT* v2;
+    const int32_t* perm;   // logical -> physical
+    int64_t s0;
+    __device__ __forceinline__ void get(int k, double& a, double& b, double& c) const {
+        const int64_t l = perm[s0 + k];
+        a = (double)v0[l]; b = (double)v1[l]; c = (double)v2[l];
+    }
+    __device__ __forceinline__ void put(int k, double a, double b, double c) const {
+        const int64_t l = perm[s0 + k];
+        v0[l] = (VT)a; v1[l] = (VT)b; v2[l] = (VT)c;
+    }
+};
+
+template <class Acc>
+__device__ __forceinline__ void ntc_cell(const Acc& cv, int N, int c, const CollideParams& cp,
+                                         uint32_t step, double* smax, int32_t* ncand, int32_t* nacc) {
+    int M = 0, acc = 0;
+    if (N >= 2) {
+        const double sm = smax[c];
+        const Rand4 r = draw(cp.key, (uint32_t)c, step, kPurposeNtcCount, 0);
+        const double Nd = (double)N;
+        const double mean = ((((0.5 * Nd) * (Nd - 1.0)) * cp.FN) * sm) * cp.dt / cp.vol[c];
+        M = (int)floor(mean + u01(r.w[0], r.w[1]));
+        double seen = 0.0;
+        for (int k = 0; k < M; ++k) {
+            const Rand4 w = draw(cp.key, (uint32_t)c, step, kPurposePair, (uint64_t)k);
+            const uint32_t i = pick(w.w[0], (uint32_t)N);
+            uint32_t j = pick(w.w[1], (uint32_t)(N - 1));
+            if (j >= i) ++j;
+            const double U = u01(w.w[2], w.w[3]);
+            double a0, a1, a2, b0, b1, b2;
+            cv.get((int)i, a0, a1, a2);
+            cv.get((int)j, b0, b1, b2);
+            const double gx = a0 - b0, gy = a1 - b1, gz = a2 - b2;
+            const double cr2 = gx * gx + gy * gy + gz * gz;
+            const double sc = cp.K * pow(cr2, cp.ex);
+            if (sc > seen) seen = sc;
+            if (!(U < sc / sm)) continue;
+            ++acc;
+            const Rand4 q = draw(cp.key, (uint32_t)c, step, kPurposeScatter, (uint64_t)k);
+            const double cx = 2.0 * u01(q.w[0], q.w[1]) - 1.0;
+            const double sx = sqrt(1.0 - cx * cx);
+            const double eps = DSMC_TWO_PI * u01(q.w[2], q.w[3]);
+            const double cr = sqrt(cr2);
+            const double gp0 = cr * cx;
+            const double gp1 = cr * (sx * cos(eps));
+            const double gp2 = cr * (sx * sin(eps));
+            const double cm0 = 0.5 * (a0 + b0), cm1 = 0.5 * (a1 + b1), cm2 = 0.5 * (a2 + b2);
+            const double h0 = 0.5 * gp0, h1 = 0.5 * gp1, h2 = 0.5 * gp2;
+            cv.put((int)i, cm0 + h0, cm1 + h1, cm2 + h2);
+            cv.put((int)j, cm0 - h0, cm1 - h1, cm2 - h2);
+        }
+        if (seen > sm) smax[c] = seen;
+    }
+    ncand[c] = M;
+    nacc[c] = acc;
+}
+
+template <class Acc>
+__device__ __forceinline__ void sample_cell(const Acc& cv, int N, int c, const CollideParams& cp,
+                                            uint32_t step) {
+    double S[kNMom];
+#pragma unroll
+    for (int k = 0; k < kNMom; ++k) S[k] = 0.0;
+    for (int k = 0; k < N; ++k) {
+        double vx, vy, vz;
+        cv.get(k, vx, vy, vz);
+        const double v2 = vx * vx + vy * vy + vz * vz;
+        S[0] += 1.0;
+        S[1] += vx; S[2] += vy; S[3] += vz;
+        S[4] += vx * vx; S[5] += vy * vy; S[6] += vz * vz;
+        S[7] += vx * vy; S[8] += vx * vz; S[9] += vy * vz;
+        S[10] += vx * v2; S[11] += vy * v2; S[12] += vz * v2;
+    }
+    const int64_t nt = cp.nt;
+    if ((int64_t)step > (int64_t)cp.n_ss) {
+#pragma unroll
+        for (int k = 0; k < kNMom; ++k) cp.acc[k * nt + c] += S[k];
+    }
+    if (cp.ewma_on) {
+        const int m = cp.ewma_m[c] + 1;
+        cp.ewma_m[c] = m;
+        const int n = (cp.local_acc[c] || m < cp.n_a) ? m : cp.n_a;
+        const double wo = (double)(n - 1) / (double)n;
+        const double wn = 1.0 / (double)n;
+#pragma unroll
+        for (int k = 0; k < kNMom; ++k) {
+            double* e = cp.ewma + k * nt + c;
+            *e = wo * *e + wn * S[k];
+        }
+    }
+}
+
+template <class VT>
+__global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p, const int32_t* offsets,
+                                                                  CollideParams cp, const Scalars* sc,
+                                                                  int32_t* perm, int do_collide,
+                                                                  int do_sample) {
+    __shared__ VT sv0[kCollideCap];
+    __shared__ VT sv1[kCollideCap];
+    __shared__ VT sv2[kCollideCap];
+    __shared__ uint32_t spid[kCollideCap];
+    __shared__ uint16_t sord[kCollideCap];
+    __shared__ uint8_t stouch[kCollideCap];
+    const int nt = cp.nt;
+    const int lane = threadIdx.x;
+    const int c0 = blockIdx.x * kCollideLanes;
+    const int c = c0 + lane;
+    const int cend = min(c0 + kCollideLanes, nt);
+    const int64_t a = offsets[c0];
+    const int64_t n = (int64_t)offsets[cend] - a;
+    const uint32_t step = sc->step;
+    if (n <= kCollideCap) {
+        for (int64_t i = lane; i < n; i += kCollideLanes) {
+            sv0[i] = p.vx[a + i];
+            sv1[i] = p.vy[a + i];
+            sv2[i] = p.vz[a + i];
+            spid[i] = p.pid[a + i];
+            stouch[i] = 0;
+        }
+        __syncthreads();
+        if (c < nt) {
+            const int s0 = (int)(offsets[c] - a);
+            const int N = offsets[c + 1] - offsets[c];
+            // logical order: rank of each particle's pid within the cell
+            for (int k = 0; k < N; ++k) {
+                const uint32_t pk = spid[s0 + k];
+                int r = 0;
+                for (int q = 0; q < N; ++q) r += spid[s0 + q] < pk;
+                sord[s0 + r] = (uint16_t)(s0 + k);
+            }
+            LdsCell<VT> cv{sv0, sv1, sv2, sord, stouch, s0};
+            if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
+            if (do_sample) sample_cell(cv, N, c, cp, step);
+        }
+        __syncthreads();
+        for (int64_t i = lane; i < n; i += kCollideLanes) {
+            if (stouch[i]) {
+                p.vx[a + i] = sv0[i];
+                p.vy[a + i] = sv1[i];
+                p.vz[a + i] = sv2[i];
+            }
+        }
+    } else if (c < nt) {
+        // dense chunk: logical order through a global permutation
+        const int64_t s0 = offsets[c];
+        const int N = offsets[c + 1] - offsets[c];
+        for (int k = 0; k < N; ++k) {
+            const uint32_t pk = p.pid[s0 + k];
+            int r = 0;
+            for (int q = 0; q < N; ++q) r += p.pid[s0 + q] < pk;
+            perm[s0 + r] = (int32_t)(s0 + k);
+        }
+        GlobalCell<VT> cv{p.vx, p.vy, p.vz, perm, s0};
+        if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
+        if (do_sample) sample_cell(cv, N, c, cp, step);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fields from moment sums (eq. dsmc_temperatures over accumulated samples)
+// ---------------------------------------------------------------------------
+__global__ void k_fields(const double* sums, int nt, double ns, double mass, double FN, const double* vol,
+                         double* out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nt) return;
+    double S[kNMom];
+    for (int k = 0; k < kNMom; ++k) S[k] = sums[(int64_t)k * nt + c];
+    double* o = out + 15 * (size_t)c;
+    if (!(S[0] > 0) || !(ns > 0)) {
+        for (int k = 0; k < 15; ++k) o[k] = __builtin_nan("");
+        return;
+    }
+    const double n = (FN * (S[0] / ns)) / vol[c];
+    const double rho = mass * n;
+    const double u0 = S[1] / S[0], u1 = S[2] / S[0], u2 = S[3] / S[0];
+    const double Cxx = S[4] / S[0] - u0 * u0, Cyy = S[5] / S[0] - u1 * u1, Czz = S[6] / S[0] - u2 * u2;
+    const double Cxy = S[7] / S[0] - u0 * u1, Cxz = S[8] / S[0] - u0 * u2, Cyz = S[9] / S[0] - u1 * u2;
+    const double Ckk = Cxx + Cyy + Czz;
+    o[0] = n; o[1] = rho; o[2] = u0; o[3] = u1; o[4] = u2;
+    o[5] = (mass * Ckk) / (3.0 * kBoltzmannDev);
+    o[6] = rho * (Cxx - Ckk / 3.0);
+    o[7] = rho * (Cyy - Ckk / 3.0);
+    o[8] = rho * (Czz - Ckk / 3.0);
+    o[9] = rho * Cxy;
+    o[10] = rho * Cxz;
+    o[11] = rho * Cyz;
+    const double S2kk = S[4] + S[5] + S[6];
+    const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+    const double uS0 = u0 * S[4] + u1 * S[7] + u2 * S[8];
+    const double uS1 = u0 * S[7] + u1 * S[5] + u2 * S[9];
+    const double uS2 = u0 * S[8] + u1 * S[9] + u2 * S[6];
+    o[12] = (rho / 2.0) * (((S[10] - 2.0 * uS0) - u0 * S2kk) + 2.0 * S[0] * u0 * uu) / S[0];
+    o[13] = (rho / 2.0) * (((S[11] - 2.0 * uS1) - u1 * S2kk) + 2.0 * S[0] * u1 * uu) / S[0];
+    o[14] = (rho / 2.0) * (((S[12] - 2.0 * uS2) - u2 * S2kk) + 2.0 * S[0] * u2 * uu) / S[0];
+}
+
+// ---------------------------------------------------------------------------
+// utilities
+// ---------------------------------------------------------------------------
+__global__ void k_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Rand4 r = philox(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);
+    for (int k = 0; k < 4; ++k) out[4 * i + k] = r.w[k];
+}
+
+__global__ void k_copy16(const uint4* src, uint4* dst, int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f64(double* p, double v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// explicit instantiations through launch wrappers
+// ---------------------------------------------------------------------------
+#define GRID(n, b) dim3((unsigned)(((n) + (b)-1) / (b)))
+
+static inline unsigned grid8(int64_t n, int b) {
+    int64_t g = (n + b - 1) / b;
+    g = (g + 7) / 8 * 8;
+    return (unsigned)(g > 0 ? g : 8);
+}
+
+void launch_begin(hipStream_t s, int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss) {
+    hipLaunchKernelGGL(k_begin, GRID(nt + 1, 256), dim3(256), 0, s, counts, nt, sc, do_sample, n_ss);
+}
+
+void launch_init_count(hipStream_t s, const double* vol, int nt, double n0, double FN, RngKey key,
+                       int32_t* counts) {
+    hipLaunchKernelGGL(k_init_count, GRID(nt, 256), dim3(256), 0, s, vol, nt, n0, FN, key, counts);
+}
+
+template <class VT>
+void launch_init_fill(hipStream_t s, const int4* tv, const double* xyz, int nt, const int32_t* offsets,
+                      PartDev<VT> p, RngKey key, double sig, const double* u0, int64_t cap, Scalars* sc) {
+    hipLaunchKernelGGL(k_init_fill<VT>, GRID(nt, 128), dim3(128), 0, s, tv, xyz, nt, offsets, p, key, sig,
+                       u0[0], u0[1], u0[2], cap, sc);
+}
+
+template <class VT>
+void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
+                 uint32_t* rank, Counters* ctr, RngKey key, double dt, int64_t np_bound) {
+    hipLaunchKernelGGL(k_move<VT>, dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p, sc, counts, rank, ctr,
+                       key, dt);
+}
+
+void launch_count(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
+                  int64_t np_bound) {
+    hipLaunchKernelGGL(k_count, GRID(np_bound > 0 ? np_bound : 1, 256), dim3(256), 0, s, cell, sc, counts,
+                       rank);
+}
+
+void launch_inject_count(hipStream_t s, const InflowDev& in, const Scalars* sc, RngKey key, int32_t* fcount) {
+    hipLaunchKernelGGL(k_inject_count, GRID(in.n, 256), dim3(256), 0, s, in, sc, key, fcount);
+}
+
+template <class VT>
+void launch_inject_emit(hipStream_t s, const MeshDev& m, const InflowDev& in, PartDev<VT> p, Scalars* sc,
+                        const int32_t* foff, int32_t* counts, uint32_t* rank, Counters* ctr, RngKey key,
+                        double dt, int64_t cap, int64_t max_inject) {
+    hipLaunchKernelGGL(k_inject_emit<VT>, GRID(max_inject > 0 ? max_inject : 1, 256), dim3(256), 0, s, m, in,
+                       p, sc, foff, counts, rank, ctr, key, dt, cap);
+}
+
+void launch_scan(hipStream_t s, const int32_t* in, int64_t n, int32_t* out, int32_t* blocksums, Scalars* sc,
+                 int mode) {
+    const int nblk = (int)((n + kScanBlock - 1) / kScanBlock);
+    const int nb = nblk > 0 ? nblk : 1;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, in, n, blocksums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, blocksums, nb, sc, mode, out + n);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, in, n, blocksums, out);
+}
+
+template <class VT>
+void launch_scatter(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalars* sc, const int32_t* offsets,
+                    const uint32_t* rank, int64_t bound, int64_t cap) {
+    hipLaunchKernelGGL(k_scatter<VT>, dim3(grid8(bound, 256)), dim3(256), 0, s, src, dst, sc, offsets, rank, cap);
+}
+
+template <class VT>
+void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
+                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample) {
+    const int nchunk = (cp.nt + kCollideLanes - 1) / kCollideLanes;
+    hipLaunchKernelGGL(k_collide_sample<VT>, dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc, perm,
+                       do_collide, do_sample);
+}
+
+void launch_fields(hipStream_t s, const double* sums, int nt, double ns, double mass, double FN,
+                   const double* vol, double* out) {
+    hipLaunchKernelGGL(k_fields, GRID(nt, 256), dim3(256), 0, s, sums, nt, ns, mass, FN, vol, out);
+}
+
+void launch_philox(hipStream_t s, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n) {
+    hipLaunchKernelGGL(k_philox, GRID(n, 256), dim3(256), 0, s, ctr, k0, k1, out, n);
+}
+
+void launch_copy(hipStream_t s, const void* src, void* dst, size_t bytes) {
+    const int64_t n16 = (int64_t)(bytes / 16);
+    hipLaunchKernelGGL(k_copy16, dim3(2048), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n16);
+}
+
+void launch_fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_i32, GRID(n, 256), dim3(256), 0, s, p, v, n);
+}
+
+void launch_fill_f64(hipStream_t s, double* p, double v, int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_f64, GRID(n, 256), dim3(256), 0, s, p, v, n);
+}
+
+#define INSTANTIATE(VT)                                                                                      \
+    template void launch_init_fill<VT>(hipStream_t, const int4*, const double*, int, const int32_t*,       \
+                                       PartDev<VT>, RngKey, double, const double*, int64_t, Scalars*);      \
+    template void launch_move<VT>(hipStream_t, const MeshDev&, PartDev<VT>, const Scalars*, int32_t*,       \
+                                  uint32_t*, Counters*, RngKey, double, int64_t);                           \
+    template void launch_inject_emit<VT>(hipStream_t, const MeshDev&, const InflowDev&, PartDev<VT>,        \
+                                         Scalars*, const int32_t*, int32_t*, uint32_t*, Counters*, RngKey,  \
+                                         double, int64_t, int64_t);                                         \
+    template void launch_scatter<VT>(hipStream_t, PartDev<VT>, PartDev<VT>, const Scalars*, const int32_t*, \
+                                     const uint32_t*, int64_t, int64_t);                                           \
+    template void launch_collide_sample<VT>(hipStream_t, PartDev<VT>, const int32_t*, const CollideParams&, \
+                                            const Scalars*, int32_t*, int, int);
+
+INSTANTIATE(float)
+INSTANTIATE(double)
+
+}  // namespace dsmcx

@@ -1,0 +1,273 @@
+"""Thin Python binding of libdsmc.so (include/dsmc.h).
+
+Argument marshalling only: every stage of the DSMC step runs in the HIP
+kernels of the library.  PyTorch provides the device memory (through the
+library's allocator callback, backed by torch's caching allocator) and the
+HIP stream.  If the library is not built this module raises at import.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdsmc.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2607_08195_amd.build.build() "
+                      "(or __graft_entry__.build()) first")
+_lib = C.CDLL(LIB_PATH)
+
+STAGE_MOVE, STAGE_INJECT, STAGE_SORT, STAGE_COLLIDE, STAGE_SAMPLE = 1, 2, 4, 8, 16
+SAMPLE_STEADY, SAMPLE_EWMA = 0, 1
+STATUS = {0: "OK", -1: "INVALID", -2: "MESH", -3: "OOM", -4: "DEVICE", -5: "CAPACITY", -6: "LOST",
+          -7: "NOT_CONVERGED"}
+
+P = C.c_void_p
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("xyz", P), ("n_tets", C.c_int32), ("tet_vtx", P),
+                ("n_bfaces", C.c_int32), ("bface_vtx", P), ("bface_group", P), ("bface_partner", P)]
+
+
+class SpeciesDesc(C.Structure):
+    _fields_ = [("mass", C.c_double), ("d_ref", C.c_double), ("omega", C.c_double), ("T_ref", C.c_double),
+                ("alpha", C.c_double)]
+
+
+class BoundaryDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("T", C.c_double), ("u", C.c_double * 3), ("n", C.c_double),
+                ("shift", C.c_double * 3)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", P)]
+
+
+class RunDesc(C.Structure):
+    _fields_ = [("n0", C.c_double), ("T0", C.c_double), ("u0", C.c_double * 3), ("F_N", C.c_double),
+                ("dt", C.c_double), ("seed", C.c_uint64), ("case_id", C.c_uint32), ("vel_fp64", C.c_int32),
+                ("n_ss", C.c_int32), ("n_a", C.c_int32), ("ewma_on", C.c_int32), ("fill", C.c_int32),
+                ("capacity", C.c_int64), ("hip_stream", P), ("allocator", C.POINTER(Allocator))]
+
+
+class State(C.Structure):
+    _fields_ = [("n_particles", C.c_int64), ("x", P), ("v", P), ("cell", P), ("pid", P), ("smax", P),
+                ("step", C.c_uint32), ("next_pid", C.c_uint32)]
+
+
+class Counters(C.Structure):
+    _fields_ = [("n_particles", C.c_int64), ("hops", C.c_int64), ("wall_hits", C.c_int64),
+                ("injected", C.c_int64), ("removed", C.c_int64), ("lost", C.c_int64), ("step", C.c_uint32)]
+
+
+ctx_t = P
+_lib.dsmc_init.argtypes = [C.POINTER(ctx_t), C.POINTER(MeshDesc), C.POINTER(SpeciesDesc), C.c_int32,
+                           C.POINTER(BoundaryDesc), C.POINTER(RunDesc)]
+_lib.dsmc_step.argtypes = [ctx_t, C.c_int32]
+_lib.dsmc_step_stages.argtypes = [ctx_t, C.c_int32]
+_lib.dsmc_sample.argtypes = [ctx_t, C.c_int32, P, C.c_int32]
+_lib.dsmc_get_sums.argtypes = [ctx_t, C.c_int32, P, C.POINTER(C.c_int64)]
+_lib.dsmc_get_state.argtypes = [ctx_t, C.POINTER(State)]
+_lib.dsmc_set_state.argtypes = [ctx_t, C.POINTER(State)]
+_lib.dsmc_get_pair_counts.argtypes = [ctx_t, P, P]
+_lib.dsmc_stats.argtypes = [ctx_t, C.POINTER(Counters)]
+_lib.dsmc_sync.argtypes = [ctx_t]
+_lib.dsmc_set_local_acc.argtypes = [ctx_t, P]
+_lib.dsmc_profile.argtypes = [ctx_t, C.c_int32]
+_lib.dsmc_profile_read.argtypes = [ctx_t, P, P, C.c_int32]
+_lib.dsmc_profile_read.restype = C.c_int32
+_lib.dsmc_profile_name.argtypes = [C.c_int32]
+_lib.dsmc_profile_name.restype = C.c_char_p
+_lib.dsmc_philox.argtypes = [P, P, P, C.c_int64]
+_lib.dsmc_device_copy.argtypes = [ctx_t, P, P, C.c_size_t]
+_lib.dsmc_last_error.argtypes = [ctx_t]
+_lib.dsmc_last_error.restype = C.c_char_p
+_lib.dsmc_destroy.argtypes = [ctx_t]
+for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_state",
+           "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
+           "dsmc_profile", "dsmc_philox", "dsmc_device_copy"]:
+    getattr(_lib, _f).restype = C.c_int32
+
+EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_state",
+            "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
+            "dsmc_profile", "dsmc_profile_read", "dsmc_profile_name", "dsmc_philox", "dsmc_device_copy",
+            "dsmc_last_error", "dsmc_destroy"]
+
+
+class DsmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(P)
+
+
+def _check(status, ctx=None):
+    if status != 0:
+        raise DsmcError(status, _lib.dsmc_last_error(ctx).decode())
+
+
+def philox(ctr, key):
+    """Philox4x32-10 on the device for counters ctr[n,4] and key[2]."""
+    c = np.ascontiguousarray(np.atleast_2d(ctr), dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros_like(c)
+    _check(_lib.dsmc_philox(_p(c), _p(k), _p(out), c.shape[0]))
+    return out
+
+
+class _TorchAllocator:
+    """Device memory from torch's caching allocator, handed to the library
+    through its allocator callback."""
+
+    def __init__(self, device, stream):
+        self.device = device
+        self.stream = stream
+
+        def _alloc(nbytes, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:
+                return None
+
+        def _free(ptr, user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._a = ALLOC_FN(_alloc)
+        self._f = FREE_FN(_free)
+        self.desc = Allocator(self._a, self._f, None)
+
+
+class Simulation:
+    """A DSMC run on one GPU, built from a workloads.Workload."""
+
+    def __init__(self, wl, device=0, capacity=0, fill=True, stream=None, torch_memory=True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the DSMC library runs on the GPU only")
+        self.device = device
+        torch.cuda.set_device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        m, sp, run = wl.mesh, wl.species, wl.run
+        self._keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a
+
+        xyz = arr(m.xyz, np.float64)
+        tets = arr(m.tets, np.int32)
+        bf = arr(m.bfaces, np.int32)
+        bg = arr(m.bgroup, np.int32)
+        bp = arr(m.bpartner, np.int32) if m.bpartner is not None else None
+        md = MeshDesc(xyz.shape[0], _p(xyz), tets.shape[0], _p(tets), bf.shape[0], _p(bf), _p(bg), _p(bp))
+        sd = SpeciesDesc(sp.mass, sp.d_ref, sp.omega, sp.T_ref, sp.alpha)
+        bcs = (BoundaryDesc * len(wl.boundaries))()
+        for i, b in enumerate(wl.boundaries):
+            bcs[i] = BoundaryDesc(b.kind, b.T, (C.c_double * 3)(*b.u), b.n, (C.c_double * 3)(*b.shift))
+        self._alloc = _TorchAllocator(device, self.stream) if torch_memory else None
+        rd = RunDesc(run.n0, run.T0, (C.c_double * 3)(*run.u0), run.F_N, run.dt, run.seed, run.case_id,
+                     0 if run.vel_fp32 else 1, run.n_ss, run.n_a, run.ewma_on, 1 if fill else 0, capacity,
+                     P(self.stream.cuda_stream), C.pointer(self._alloc.desc) if self._alloc else None)
+        self.ctx = ctx_t()
+        _check(_lib.dsmc_init(C.byref(self.ctx), C.byref(md), C.byref(sd), len(wl.boundaries), bcs, C.byref(rd)))
+        self.nt = int(tets.shape[0])
+        self.wl = wl
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            _lib.dsmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _c(self, status):
+        _check(status, self.ctx)
+
+    # -- stepping --------------------------------------------------------
+    def step(self, n=1):
+        self._c(_lib.dsmc_step(self.ctx, n))
+
+    def step_stages(self, mask):
+        self._c(_lib.dsmc_step_stages(self.ctx, mask))
+
+    def sync(self):
+        self._c(_lib.dsmc_sync(self.ctx))
+
+    # -- outputs ---------------------------------------------------------
+    def fields(self, which=SAMPLE_STEADY, on_device=False):
+        if on_device:
+            out = torch.empty((self.nt, 15), dtype=torch.float64, device=f"cuda:{self.device}")
+            self._c(_lib.dsmc_sample(self.ctx, which, P(out.data_ptr()), 1))
+            return out
+        out = np.zeros((self.nt, 15))
+        self._c(_lib.dsmc_sample(self.ctx, which, _p(out), 0))
+        return out
+
+    def sums(self, which=SAMPLE_STEADY):
+        out = np.zeros((self.nt, 13))
+        ns = C.c_int64()
+        self._c(_lib.dsmc_get_sums(self.ctx, which, _p(out), C.byref(ns)))
+        return out, int(ns.value)
+
+    def state(self, particles=True):
+        st = State()
+        smax = np.zeros(self.nt)
+        st.smax = _p(smax)
+        self._c(_lib.dsmc_get_state(self.ctx, C.byref(st)))
+        n = int(st.n_particles)
+        res = dict(n=n, step=int(st.step), next_pid=int(st.next_pid), smax=smax)
+        if particles:
+            x = np.zeros((n, 3)); v = np.zeros((n, 3))
+            c = np.zeros(n, np.int32); p = np.zeros(n, np.uint32)
+            st.x, st.v, st.cell, st.pid = _p(x), _p(v), _p(c), _p(p)
+            self._c(_lib.dsmc_get_state(self.ctx, C.byref(st)))
+            res.update(x=x, v=v, cell=c, pid=p)
+        return res
+
+    def set_state(self, x, v, cell, pid, step, next_pid, smax=None):
+        x = np.ascontiguousarray(x, np.float64); v = np.ascontiguousarray(v, np.float64)
+        cell = np.ascontiguousarray(cell, np.int32); pid = np.ascontiguousarray(pid, np.uint32)
+        sm = np.ascontiguousarray(smax, np.float64) if smax is not None else None
+        st = State(len(cell), _p(x), _p(v), _p(cell), _p(pid), _p(sm), step, next_pid)
+        self._c(_lib.dsmc_set_state(self.ctx, C.byref(st)))
+
+    def pair_counts(self):
+        a = np.zeros(self.nt, np.int32); b = np.zeros(self.nt, np.int32)
+        self._c(_lib.dsmc_get_pair_counts(self.ctx, _p(a), _p(b)))
+        return a, b
+
+    def stats(self):
+        c = Counters()
+        self._c(_lib.dsmc_stats(self.ctx, C.byref(c)))
+        return dict(n_particles=c.n_particles, hops=c.hops, wall_hits=c.wall_hits, injected=c.injected,
+                    removed=c.removed, lost=c.lost, step=c.step)
+
+    def set_local_acc(self, flags):
+        f = np.ascontiguousarray(flags, np.uint8)
+        self._c(_lib.dsmc_set_local_acc(self.ctx, _p(f)))
+
+    # -- profiling -------------------------------------------------------
+    def profile(self, enable=True):
+        self._c(_lib.dsmc_profile(self.ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        ms = np.zeros(16); cnt = np.zeros(16, np.int64)
+        n = _lib.dsmc_profile_read(self.ctx, _p(ms), _p(cnt), 16)
+        return {_lib.dsmc_profile_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+    def device_copy(self, dst, src, nbytes):
+        self._c(_lib.dsmc_device_copy(self.ctx, P(dst), P(src), nbytes))
