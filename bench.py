@@ -56,6 +56,24 @@ def cpu_baseline(wl, steps):
                        f"{dt:.1f} s, 1 thread)")
 
 
+def calibrate_copy(dsmc, W, nbytes=2 << 30, reps=10):
+    """A plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters
+    per dispatch divided by nbytes give the counter scale factors."""
+    import torch
+    sim = dsmc.Simulation(W.cavity(n_hex=2, ppc=2))
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    sim.device_copy(dst.data_ptr(), src.data_ptr(), nbytes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.device_copy(dst.data_ptr(), src.data_ptr(), nbytes)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_each_way": nbytes, "ms": dt * 1e3, "GBps_read_plus_write": 2 * nbytes / dt / 1e9}))
+    sim.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +82,8 @@ def main():
     ap.add_argument("--workload", default="cavity_large", choices=["cavity_large", "cavity_small"])
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="time a plain device copy of 2 GiB (HBM calibration of the traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a "
@@ -74,6 +94,8 @@ def main():
     import torch
     from paper_2607_08195_amd import dsmc, workloads as W
 
+    if args.calibrate_copy:
+        return calibrate_copy(dsmc, W)
     wl = W.cavity_large() if args.workload == "cavity_large" else W.cavity_small()
     sim = dsmc.Simulation(wl)
     np0 = sim.stats()["n_particles"]

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -68,6 +69,8 @@ struct dsmc_ctx_s {
     GroupDev* d_groups = nullptr;
     int4* d_tv = nullptr;
     double* d_xyz = nullptr;
+    int32_t* d_orig = nullptr;      // internal cell -> caller's cell id
+    int32_t* d_cell_tmp = nullptr;  // [nt+1] scratch of the initial fill
     // inflow
     InflowDev inflow{};
     int32_t* d_fcount = nullptr;
@@ -77,6 +80,7 @@ struct dsmc_ctx_s {
     Buf A, B;
     uint32_t* d_rank = nullptr;
     int32_t* d_perm = nullptr;
+    WallQueue wq{nullptr, nullptr, nullptr};
     // cells
     int32_t* d_counts = nullptr;
     int32_t* d_offsets = nullptr;
@@ -90,6 +94,14 @@ struct dsmc_ctx_s {
     uint8_t* d_local = nullptr;
     Scalars* d_sc = nullptr;
     Counters* d_ctr = nullptr;
+    int32_t* d_counts_orig = nullptr;  // [nt] scratch of the initial fill
+    // tuning choices
+    int move_variant = kMoveDefer6;
+    int move_batch = 0;
+    int collide_variant = kCollideGlobal;
+    int sort_variant = kSortGather;
+    int32_t* d_sortperm = nullptr;
+    bool reorder = true;
     // host view
     int64_t np_bound = 0;
     // profiling
@@ -203,7 +215,8 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
     }
     if (mv) {
         Timed t(c, kSlotMove);
-        launch_move<VT>(s, c->mesh, a, c->d_sc, c->d_counts, c->d_rank, c->d_ctr, c->key, c->dt, c->np_bound);
+        launch_move<VT>(s, c->mesh, a, c->d_sc, c->d_counts, c->d_rank, c->d_ctr, c->key, c->dt, c->np_bound,
+                        c->move_variant, c->move_batch, c->wq);
     }
     if (inj) {
         Timed t(c, kSlotInject);
@@ -220,7 +233,7 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
         }
         {
             Timed t(c, kSlotScatter);
-            launch_scatter<VT>(s, a, b, c->d_sc, c->d_offsets, c->d_rank, need, c->cap);
+            launch_scatter<VT>(s, a, b, c->d_sc, c->d_offsets, c->d_rank, need, c->cap, c->d_sortperm, c->sort_variant);
         }
         std::swap(c->A, c->B);
         a = as_dev<VT>(c->A);
@@ -233,7 +246,9 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
         cp.key = c->key; cp.FN = c->FN; cp.dt = c->dt; cp.K = c->K; cp.ex = c->ex;
         cp.vol = c->d_vol; cp.smax = c->d_smax; cp.ncand = c->d_ncand; cp.nacc = c->d_nacc;
         cp.acc = c->d_acc; cp.ewma = c->d_ewma; cp.ewma_m = c->d_ewma_m; cp.local_acc = c->d_local;
-        launch_collide_sample<VT>(s, a, c->d_offsets, cp, c->d_sc, c->d_perm, col ? 1 : 0, smp ? 1 : 0);
+        cp.orig = c->d_orig;
+        launch_collide_sample<VT>(s, a, c->d_offsets, cp, c->d_sc, c->d_perm, col ? 1 : 0, smp ? 1 : 0,
+                                  c->collide_variant);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -247,10 +262,39 @@ dsmc_status step_any(dsmc_ctx c, int mask) {
     return c->vel64 ? run_step<double>(c, mask) : run_step<float>(c, mask);
 }
 
+// Tuning overrides from the environment: DSMC_MOVE (lane, lane6, lane8,
+// batched), DSMC_MOVE_BATCH, DSMC_REORDER (0/1).
+void read_tuning(dsmc_ctx c) {
+    if (const char* v = std::getenv("DSMC_MOVE")) {
+        std::string s(v);
+        if (s == "lane") c->move_variant = kMoveLane;
+        else if (s == "lane6") c->move_variant = kMoveLaneW6;
+        else if (s == "lane8") c->move_variant = kMoveLaneW8;
+        else if (s == "batched") c->move_variant = kMoveBatched;
+        else if (s == "defer6") c->move_variant = kMoveDefer6;
+        else if (s == "defer8") c->move_variant = kMoveDefer8;
+        else if (s == "defer4") c->move_variant = kMoveDefer4;
+        else if (s == "defer5") c->move_variant = kMoveDefer5;
+        else if (s == "refill5") c->move_variant = kMoveRefill5;
+        else if (s == "refill6") c->move_variant = kMoveRefill6;
+        else if (s == "pool128") c->move_variant = kMovePool128;
+        else if (s == "pool256") c->move_variant = kMovePool256;
+    }
+    if (const char* v = std::getenv("DSMC_MOVE_BATCH")) c->move_batch = std::max(64, std::atoi(v) / 64 * 64);
+    if (const char* v = std::getenv("DSMC_REORDER")) c->reorder = std::atoi(v) != 0;
+    if (const char* v = std::getenv("DSMC_SORT")) c->sort_variant = std::string(v) == "scatter" ? kSortScatter : kSortGather;
+    if (const char* v = std::getenv("DSMC_COLLIDE")) {
+        std::string s(v);
+        if (s == "lds") c->collide_variant = kCollideLds;
+        else if (s == "global") c->collide_variant = kCollideGlobal;
+        else if (s == "global8") c->collide_variant = kCollideGlobal8;
+    }
+}
+
 template <class VT>
 void fill_dispatch(dsmc_ctx c, double sig) {
-    launch_init_fill<VT>(c->stream, c->d_tv, c->d_xyz, c->nt, c->d_offsets, as_dev<VT>(c->A), c->key, sig,
-                         c->u0, c->cap, c->d_sc);
+    launch_init_fill<VT>(c->stream, c->d_tv, c->d_xyz, c->nt, c->d_offsets, c->d_orig, c->d_cell_tmp,
+                         as_dev<VT>(c->A), c->key, sig, c->u0, c->cap, c->d_sc);
 }
 
 }  // namespace
@@ -288,6 +332,13 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
         return fail(nullptr, DSMC_E_MESH, merr);
     }
     HostMesh& hm = c->hm;
+    read_tuning(c);
+    if (c->reorder) reorder_cells(hm);
+    else {
+        hm.orig.resize(hm.nt);
+        std::iota(hm.orig.begin(), hm.orig.end(), 0);
+        hm.inv = hm.orig;
+    }
     c->nt = hm.nt;
     c->nb = hm.nb;
     for (int b = 0; b < hm.nb; ++b)
@@ -356,6 +407,8 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
               alloc_n(c, c->d_vol, nt) && alloc_n(c, c->d_bf_group, nb + 1) && alloc_n(c, c->d_bf_pcode, nb + 1) &&
               alloc_n(c, c->d_bf_frame, 9 * (size_t)nb + 9) && alloc_n(c, c->d_groups, n_bc + 1) &&
               alloc_n(c, c->d_tv, nt) && alloc_n(c, c->d_xyz, 3 * (size_t)hm.nv) &&
+              alloc_n(c, c->d_orig, nt) && alloc_n(c, c->d_cell_tmp, nt + 1) &&
+              alloc_n(c, c->d_counts_orig, nt + 1) &&
               alloc_n(c, c->d_counts, nt + 1) && alloc_n(c, c->d_offsets, nt + 1) &&
               alloc_n(c, c->d_blocksums, std::max(nblk_cells, (nin + kScanBlock) / kScanBlock + 1)) &&
               alloc_n(c, c->d_smax, nt) && alloc_n(c, c->d_ncand, nt) && alloc_n(c, c->d_nacc, nt) &&
@@ -368,7 +421,8 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     ok = ok && alloc_n(c, d_in_bf, nin + 1) && alloc_n(c, d_in_tc, nin + 1) &&
          alloc_n(c, d_in_cst, (size_t)kInflowStride * nin + 1);
     ok = ok && alloc_buf(c, c->A, c->cap, c->vel64) && alloc_buf(c, c->B, c->cap, c->vel64) &&
-         alloc_n(c, c->d_rank, c->cap) && alloc_n(c, c->d_perm, c->cap);
+         alloc_n(c, c->d_rank, c->cap) && alloc_n(c, c->d_perm, c->cap) && alloc_n(c, c->d_sortperm, c->cap) &&
+         alloc_n(c, c->wq.idx, c->cap) && alloc_n(c, c->wq.t, c->cap) && alloc_n(c, c->wq.meta, c->cap);
     if (!ok) {
         dsmc_destroy(c);
         return fail(nullptr, DSMC_E_OOM, "device allocation failed");
@@ -405,6 +459,7 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     UP(c->d_groups, groups.data(), sizeof(GroupDev) * (n_bc + 1));
     UP(c->d_tv, hm.tv.data(), sizeof(int32_t) * 4 * (size_t)nt);
     UP(c->d_xyz, hm.xyz.data(), sizeof(double) * 3 * (size_t)hm.nv);
+    UP(c->d_orig, hm.orig.data(), sizeof(int32_t) * nt);
     if (nin) {
         UP(d_in_bf, in_bf.data(), sizeof(int32_t) * nin);
         UP(d_in_tc, in_tc.data(), sizeof(int32_t) * nin);
@@ -442,7 +497,9 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     launch_fill_i32(s, c->d_offsets, 0, nt + 1);
 
     if (run->fill) {
-        launch_init_count(s, c->d_vol, nt, run->n0, run->F_N, c->key, c->d_counts);
+        // counts per cell; particle ids follow the caller's cell order
+        launch_init_count(s, c->d_vol, c->d_orig, nt, run->n0, run->F_N, c->key, c->d_counts, c->d_counts_orig);
+        launch_scan(s, c->d_counts_orig, nt, c->d_cell_tmp, c->d_blocksums, c->d_sc, kScanPlain);
         launch_scan(s, c->d_counts, nt, c->d_offsets, c->d_blocksums, c->d_sc, kScanInit);
         const double sig = std::sqrt((kBoltzmann * run->T0) / sp->mass);
         if (c->vel64) fill_dispatch<double>(c, sig); else fill_dispatch<float>(c, sig);
@@ -498,7 +555,7 @@ dsmc_status dsmc_sample(dsmc_ctx c, int32_t which, double* out, int32_t out_on_d
         if (!alloc_n(c, tmp, 15 * (size_t)c->nt)) return fail(c, DSMC_E_OOM, "device allocation failed");
         dout = tmp;
     }
-    launch_fields(c->stream, src, c->nt, ns, c->mass, c->FN, c->d_vol, dout);
+    launch_fields(c->stream, src, c->nt, ns, c->mass, c->FN, c->d_vol, c->d_orig, dout);
     HIP_TRY(c, hipGetLastError());
     if (!out_on_device) {
         HIP_TRY(c, hipMemcpyAsync(out, tmp, sizeof(double) * 15 * (size_t)c->nt, hipMemcpyDeviceToHost, c->stream));
@@ -522,7 +579,7 @@ dsmc_status dsmc_get_sums(dsmc_ctx c, int32_t which, double* out, int64_t* n_sam
     HIP_TRY(c, hipMemcpy(h.data(), which == DSMC_SAMPLE_STEADY ? c->d_acc : c->d_ewma, sizeof(double) * h.size(),
                          hipMemcpyDeviceToHost));
     for (int t = 0; t < c->nt; ++t)
-        for (int k = 0; k < kNMom; ++k) out[(size_t)kNMom * t + k] = h[(size_t)k * c->nt + t];
+        for (int k = 0; k < kNMom; ++k) out[(size_t)kNMom * c->hm.orig[t] + k] = h[(size_t)k * c->nt + t];
     if (n_samples) *n_samples = sc.n_steady;
     return DSMC_OK;
 }
@@ -536,7 +593,11 @@ dsmc_status dsmc_get_state(dsmc_ctx c, dsmc_state* st) {
     st->n_particles = n;
     st->step = sc.step;
     st->next_pid = sc.next_pid;
-    if (st->smax) HIP_TRY(c, hipMemcpy(st->smax, c->d_smax, sizeof(double) * c->nt, hipMemcpyDeviceToHost));
+    if (st->smax) {
+        std::vector<double> sm(c->nt);
+        HIP_TRY(c, hipMemcpy(sm.data(), c->d_smax, sizeof(double) * c->nt, hipMemcpyDeviceToHost));
+        for (int t = 0; t < c->nt; ++t) st->smax[c->hm.orig[t]] = sm[t];
+    }
     if (!st->x && !st->v && !st->cell && !st->pid) return DSMC_OK;
     std::vector<double> x(n), y(n), z(n), vx(n), vy(n), vz(n);
     std::vector<int32_t> cell(n);
@@ -559,6 +620,7 @@ dsmc_status dsmc_get_state(dsmc_ctx c, dsmc_state* st) {
     }
     HIP_TRY(c, hipMemcpy(cell.data(), c->A.cell, 4 * n, hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(pid.data(), c->A.pid, 4 * n, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i) cell[i] = c->hm.orig[cell[i]];
     std::vector<int64_t> idx(n);
     std::iota(idx.begin(), idx.end(), 0);
     std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
@@ -585,8 +647,10 @@ dsmc_status dsmc_set_state(dsmc_ctx c, const dsmc_state* st) {
     std::iota(idx.begin(), idx.end(), 0);
     for (int64_t i = 0; i < n; ++i)
         if (st->cell[i] < 0 || st->cell[i] >= c->nt) return fail(c, DSMC_E_INVALID, "particle cell out of range");
+    const std::vector<int32_t>& inv = c->hm.inv;
     std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
-        if (st->cell[a] != st->cell[b]) return st->cell[a] < st->cell[b];
+        const int32_t ca = inv[st->cell[a]], cb = inv[st->cell[b]];
+        if (ca != cb) return ca < cb;
         return st->pid[a] < st->pid[b];
     });
     std::vector<double> x(n), y(n), z(n), vx(n), vy(n), vz(n);
@@ -596,7 +660,7 @@ dsmc_status dsmc_set_state(dsmc_ctx c, const dsmc_state* st) {
         const int64_t i = idx[k];
         x[k] = st->x[3 * i]; y[k] = st->x[3 * i + 1]; z[k] = st->x[3 * i + 2];
         vx[k] = st->v[3 * i]; vy[k] = st->v[3 * i + 1]; vz[k] = st->v[3 * i + 2];
-        cell[k] = st->cell[i]; pid[k] = st->pid[i];
+        cell[k] = inv[st->cell[i]]; pid[k] = st->pid[i];
         counts[cell[k] + 1]++;
     }
     for (int t = 0; t < c->nt; ++t) counts[t + 1] += counts[t];
@@ -619,7 +683,11 @@ dsmc_status dsmc_set_state(dsmc_ctx c, const dsmc_state* st) {
     HIP_TRY(c, hipMemcpy(c->A.cell, cell.data(), 4 * n, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->A.pid, pid.data(), 4 * n, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->d_offsets, counts.data(), 4 * (c->nt + 1), hipMemcpyHostToDevice));
-    if (st->smax) HIP_TRY(c, hipMemcpy(c->d_smax, st->smax, sizeof(double) * c->nt, hipMemcpyHostToDevice));
+    if (st->smax) {
+        std::vector<double> sm(c->nt);
+        for (int t = 0; t < c->nt; ++t) sm[t] = st->smax[c->hm.orig[t]];
+        HIP_TRY(c, hipMemcpy(c->d_smax, sm.data(), sizeof(double) * c->nt, hipMemcpyHostToDevice));
+    }
     Scalars sc;
     HIP_TRY(c, hipMemcpy(&sc, c->d_sc, sizeof sc, hipMemcpyDeviceToHost));
     sc.np = n;
@@ -635,8 +703,15 @@ dsmc_status dsmc_set_state(dsmc_ctx c, const dsmc_state* st) {
 dsmc_status dsmc_get_pair_counts(dsmc_ctx c, int32_t* ncand, int32_t* nacc) {
     if (!c) return fail(c, DSMC_E_INVALID, "NULL context");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (ncand) HIP_TRY(c, hipMemcpy(ncand, c->d_ncand, 4 * (size_t)c->nt, hipMemcpyDeviceToHost));
-    if (nacc) HIP_TRY(c, hipMemcpy(nacc, c->d_nacc, 4 * (size_t)c->nt, hipMemcpyDeviceToHost));
+    std::vector<int32_t> h(c->nt);
+    if (ncand) {
+        HIP_TRY(c, hipMemcpy(h.data(), c->d_ncand, 4 * (size_t)c->nt, hipMemcpyDeviceToHost));
+        for (int t = 0; t < c->nt; ++t) ncand[c->hm.orig[t]] = h[t];
+    }
+    if (nacc) {
+        HIP_TRY(c, hipMemcpy(h.data(), c->d_nacc, 4 * (size_t)c->nt, hipMemcpyDeviceToHost));
+        for (int t = 0; t < c->nt; ++t) nacc[c->hm.orig[t]] = h[t];
+    }
     return DSMC_OK;
 }
 
@@ -658,7 +733,9 @@ dsmc_status dsmc_stats(dsmc_ctx c, dsmc_counters* out) {
 
 dsmc_status dsmc_set_local_acc(dsmc_ctx c, const uint8_t* flags) {
     if (!c || !flags) return fail(c, DSMC_E_INVALID, "bad arguments");
-    HIP_TRY(c, hipMemcpyAsync(c->d_local, flags, c->nt, hipMemcpyHostToDevice, c->stream));
+    std::vector<uint8_t> f(c->nt);
+    for (int t = 0; t < c->nt; ++t) f[t] = flags[c->hm.orig[t]] ? 1 : 0;
+    HIP_TRY(c, hipMemcpyAsync(c->d_local, f.data(), c->nt, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return DSMC_OK;
 }

@@ -213,4 +213,122 @@ __device__ __forceinline__ TraceOut trace(const MeshDev& m, double& x0, double& 
     return out;
 }
 
+// State of one particle being tracked by a lane of the batched move kernel.
+struct Walker {
+    double x0, x1, x2, v0, v1, v2, t;
+    int c, entry, nhop, hits, walls;
+    uint32_t pid;
+};
+
+// One exit test of a walker (and the crossing or boundary interaction it
+// leads to).  Returns -1 while the walker is still in flight, 0 when it has
+// used up its time (alive), 1 when it left through an open face, 2 when it
+// exceeded the hop limit.  Faces are visited in ascending local index, the
+// entry face skipped, so ties resolve to the lowest index as in trace().
+// One face of the exit test, branch-free: lambda = (D - N.x) / (N.v) is
+// computed for every face and kept only for a face other than the entry
+// face with N.v > 0; clamped at 0; the running minimum keeps the lowest
+// face index on ties because faces are visited in ascending order.
+__device__ __forceinline__ void exit_candidate(const double4& pl, int f, const Walker& w, int& fb, double& lb) {
+    const double den = pl.x * w.v0 + pl.y * w.v1 + pl.z * w.v2;
+    double lam = (pl.w - (pl.x * w.x0 + pl.y * w.x1 + pl.z * w.x2)) / den;
+    lam = lam < 0 ? 0.0 : lam;
+    const bool ok = (f != w.entry) && (den > 0);
+    const bool take = ok && (fb < 0 || lam < lb);
+    fb = take ? f : fb;
+    lb = take ? lam : lb;
+}
+
+// Diffuse re-emission of a walker that has just reached boundary face bf
+// through local face fb (the wall becomes its entry face).
+template <class VT>
+__device__ __forceinline__ void diffuse_reemit(const MeshDev& m, Walker& w, int bf, int fb, uint32_t step,
+                                               RngKey key) {
+    const GroupDev& g = m.groups[m.bf_group[bf]];
+    const Rand4 r0 = draw(key, w.pid, step, kPurposeWall, (uint64_t)(2 * w.hits));
+    const Rand4 r1 = draw(key, w.pid, step, kPurposeWall, (uint64_t)(2 * w.hits + 1));
+    const double ua = u01(r0.w[0], r0.w[1]);
+    const double ub = u01(r0.w[2], r0.w[3]);
+    const double uc = u01(r1.w[0], r1.w[1]);
+    const double vn = g.beta * sqrt(-log(ua));
+    double g1, g2;
+    box_muller(ub, uc, g1, g2);
+    const double* fr = m.bf_frame + 9 * (size_t)bf;
+    w.v0 = round_store<VT>((vn * fr[0] + g.sw * (g1 * fr[3] + g2 * fr[6])) + g.u[0]);
+    w.v1 = round_store<VT>((vn * fr[1] + g.sw * (g1 * fr[4] + g2 * fr[7])) + g.u[1]);
+    w.v2 = round_store<VT>((vn * fr[2] + g.sw * (g1 * fr[5] + g2 * fr[8])) + g.u[2]);
+    ++w.hits;
+    ++w.walls;
+    w.entry = fb;
+}
+
+constexpr int kHopWallPending = 3;
+
+// With DEFER, reaching a diffuse wall stops the walker there and returns
+// kHopWallPending (the re-emission is left to a later pass); the walker's
+// entry holds the wall's local face.
+template <class VT, bool DEFER = false>
+__device__ __forceinline__ int hop_once(const MeshDev& m, Walker& w, uint32_t step, RngKey key) {
+    const int base = 4 * w.c;
+    // all four planes and neighbour codes of the cell in flight at once
+    const double4 p0 = m.plane[base + 0];
+    const double4 p1 = m.plane[base + 1];
+    const double4 p2 = m.plane[base + 2];
+    const double4 p3 = m.plane[base + 3];
+    const int4 nb4 = *reinterpret_cast<const int4*>(m.nbr + base);
+    int fb = -1;
+    double lb = 0.0;
+    exit_candidate(p0, 0, w, fb, lb);
+    exit_candidate(p1, 1, w, fb, lb);
+    exit_candidate(p2, 2, w, fb, lb);
+    exit_candidate(p3, 3, w, fb, lb);
+    if (fb < 0 || lb >= w.t) {
+        w.x0 = w.x0 + w.v0 * w.t;
+        w.x1 = w.x1 + w.v1 * w.t;
+        w.x2 = w.x2 + w.v2 * w.t;
+        return 0;
+    }
+    w.x0 = w.x0 + w.v0 * lb;
+    w.x1 = w.x1 + w.v1 * lb;
+    w.x2 = w.x2 + w.v2 * lb;
+    w.t = w.t - lb;
+    ++w.nhop;
+    if (w.nhop > DSMC_MAX_HOPS) return 2;
+    const int code = fb == 0 ? nb4.x : fb == 1 ? nb4.y : fb == 2 ? nb4.z : nb4.w;
+    if (code >= 0) {
+        w.c = code >> 2;
+        w.entry = code & 3;
+        return -1;
+    }
+    const int bf = -1 - code;
+    const GroupDev& g = m.groups[m.bf_group[bf]];
+    if (g.kind == kBcDiffuse) {
+        if (DEFER) {
+            w.entry = fb;
+            return kHopWallPending;
+        }
+        diffuse_reemit<VT>(m, w, bf, fb, step, key);
+    } else if (g.kind == kBcSpecular) {
+        const double4 pl = fb == 0 ? p0 : fb == 1 ? p1 : fb == 2 ? p2 : p3;
+        const double vn = pl.x * w.v0 + pl.y * w.v1 + pl.z * w.v2;
+        const double nn = pl.x * pl.x + pl.y * pl.y + pl.z * pl.z;
+        const double f2 = 2.0 * (vn / nn);
+        w.v0 = round_store<VT>(w.v0 - f2 * pl.x);
+        w.v1 = round_store<VT>(w.v1 - f2 * pl.y);
+        w.v2 = round_store<VT>(w.v2 - f2 * pl.z);
+        ++w.walls;
+        w.entry = fb;
+    } else if (g.kind == kBcPeriodic) {
+        w.x0 = w.x0 + g.shift[0];
+        w.x1 = w.x1 + g.shift[1];
+        w.x2 = w.x2 + g.shift[2];
+        const int pc = m.bf_pcode[bf];
+        w.c = pc >> 2;
+        w.entry = pc & 3;
+    } else {
+        return 1;
+    }
+    return -1;
+}
+
 }  // namespace dsmcx

@@ -12,11 +12,19 @@ constexpr int kNMom = 13;               // S0, S1(3), S2(6), S3(3)
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanBlock = kScanThreads * kScanItems;
+constexpr int kMoveBatch = 512;        // particles per wave in the move kernel
 constexpr int kCollideLanes = 64;       // one wave, one lane per cell
 constexpr int kCollideCap = 2048;       // particles of one 64-cell chunk staged in LDS
+constexpr int kCollideCapG = 4096;      // particles of one chunk ranked in LDS (order-only variant)
 constexpr int kInflowStride = 24;       // doubles per inflow face
 enum { kScanPlain = 0, kScanCells = 1, kScanInject = 2, kScanInit = 3 };
 enum { kFlagCapacity = 1 };
+// move kernel variants (tuning choice)
+enum { kMoveLane = 0, kMoveLaneW6 = 1, kMoveLaneW8 = 2, kMoveBatched = 3, kMoveDefer6 = 4, kMoveDefer8 = 5, kMoveDefer4 = 6,
+       kMoveDefer5 = 7, kMoveRefill5 = 8, kMoveRefill6 = 9,
+       kMovePool128 = 10, kMovePool256 = 11 };
+enum { kCollideLds = 0, kCollideGlobal = 1, kCollideGlobal8 = 2 };
+enum { kSortScatter = 0, kSortGather = 1 };
 
 // Particle store, structure of arrays.
 template <class VT>
@@ -41,6 +49,14 @@ struct Scalars {
     uint32_t next_pid;
     int32_t ninj;       // particles injected this step
     int32_t flags;
+    int64_t n_wall;     // particles parked at a diffuse wall this step
+};
+
+// Particles parked at a diffuse wall by the deferring move kernel.
+struct WallQueue {
+    int32_t* idx;    // particle index
+    double* t;       // remaining time
+    int32_t* meta;   // entry face | hits << 2 | hops << 12 | walls << 22
 };
 
 struct Counters {
@@ -69,17 +85,20 @@ struct CollideParams {
     double* ewma;       // [13][nt] moving average
     int32_t* ewma_m;    // [nt] samples seen
     const uint8_t* local_acc;
+    const int32_t* orig;  // [nt] caller's cell id (generator subject)
 };
 
 void launch_begin(hipStream_t s, int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss);
-void launch_init_count(hipStream_t s, const double* vol, int nt, double n0, double FN, RngKey key,
-                       int32_t* counts);
+void launch_init_count(hipStream_t s, const double* vol, const int32_t* orig, int nt, double n0, double FN,
+                       RngKey key, int32_t* counts, int32_t* counts_orig);
 template <class VT>
 void launch_init_fill(hipStream_t s, const int4* tv, const double* xyz, int nt, const int32_t* offsets,
-                      PartDev<VT> p, RngKey key, double sig, const double* u0, int64_t cap, Scalars* sc);
+                      const int32_t* orig, const int32_t* pid_base, PartDev<VT> p, RngKey key, double sig,
+                      const double* u0, int64_t cap, Scalars* sc);
 template <class VT>
 void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
-                 uint32_t* rank, Counters* ctr, RngKey key, double dt, int64_t np_bound);
+                 uint32_t* rank, Counters* ctr, RngKey key, double dt, int64_t np_bound, int variant, int batch,
+                 WallQueue wq);
 void launch_count(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
                   int64_t np_bound);
 void launch_inject_count(hipStream_t s, const InflowDev& in, const Scalars* sc, RngKey key, int32_t* fcount);
@@ -91,12 +110,12 @@ void launch_scan(hipStream_t s, const int32_t* in, int64_t n, int32_t* out, int3
                  int mode);
 template <class VT>
 void launch_scatter(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalars* sc, const int32_t* offsets,
-                    const uint32_t* rank, int64_t bound, int64_t cap);
+                    const uint32_t* rank, int64_t bound, int64_t cap, int32_t* perm, int variant);
 template <class VT>
 void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
-                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample);
+                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant);
 void launch_fields(hipStream_t s, const double* sums, int nt, double ns, double mass, double FN,
-                   const double* vol, double* out);
+                   const double* vol, const int32_t* orig, double* out);
 void launch_philox(hipStream_t s, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n);
 void launch_copy(hipStream_t s, const void* src, void* dst, size_t bytes);
 void launch_fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n);

@@ -61,6 +61,7 @@ __global__ void k_begin(int32_t* counts, int nt, Scalars* sc, int do_sample, int
         const uint32_t s = sc->step + 1;
         sc->step = s;
         sc->ninj = 0;
+        sc->n_wall = 0;
         if (do_sample && (int64_t)s > (int64_t)n_ss) sc->n_steady += 1;
     }
 }
@@ -68,19 +69,22 @@ __global__ void k_begin(int32_t* counts, int nt, Scalars* sc, int do_sample, int
 // ---------------------------------------------------------------------------
 // initial fill
 // ---------------------------------------------------------------------------
-__global__ void k_init_count(const double* vol, int nt, double n0, double FN, RngKey key,
-                             int32_t* counts) {
+__global__ void k_init_count(const double* vol, const int32_t* orig, int nt, double n0, double FN, RngKey key,
+                             int32_t* counts, int32_t* counts_orig) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
     const double mean = (n0 * vol[t]) / FN;
-    const Rand4 r = draw(key, (uint32_t)t, 0u, kPurposeInitCount, 0);
-    counts[t] = (int32_t)floor(mean + u01(r.w[0], r.w[1]));
+    const int o = orig[t];
+    const Rand4 r = draw(key, (uint32_t)o, 0u, kPurposeInitCount, 0);
+    const int32_t cnt = (int32_t)floor(mean + u01(r.w[0], r.w[1]));
+    counts[t] = cnt;
+    counts_orig[o] = cnt;
 }
 
 template <class VT>
 __global__ void k_init_fill(const int4* tv, const double* xyz, int nt, const int32_t* offsets,
-                            PartDev<VT> p, RngKey key, double sig, double u0x, double u0y, double u0z,
-                            int64_t cap, Scalars* sc) {
+                            const int32_t* orig, const int32_t* pid_base, PartDev<VT> p, RngKey key, double sig,
+                            double u0x, double u0y, double u0z, int64_t cap, Scalars* sc) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
     const int4 q = tv[t];
@@ -93,8 +97,9 @@ __global__ void k_init_fill(const int4* tv, const double* xyz, int nt, const int
         if (t == 0) atomicOr(&sc->flags, kFlagCapacity);
         return;
     }
+    const int64_t pb = pid_base[orig[t]];
     for (int64_t k = a; k < b; ++k) {
-        const uint32_t id = (uint32_t)k;
+        const uint32_t id = (uint32_t)(pb + (k - a));
         double u[8];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -124,38 +129,387 @@ __global__ void k_init_fill(const int4* tv, const double* xyz, int nt, const int
 // ---------------------------------------------------------------------------
 // move
 // ---------------------------------------------------------------------------
-template <class VT>
-__global__ __launch_bounds__(256) void k_move(MeshDev m, PartDev<VT> p, const Scalars* sc,
-                                             int32_t* counts, uint32_t* rank, Counters* ctr,
-                                             RngKey key, double dt) {
+// One particle per lane, tracked to the end of its step.  WPE bounds the
+// register budget (waves per SIMD) the compiler must fit.
+template <class VT, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_move_lane(MeshDev m, PartDev<VT> p, const Scalars* sc,
+                                                      int32_t* counts, uint32_t* rank, Counters* ctr,
+                                                      RngKey key, double dt) {
     const int64_t i = xcd_block() * 256 + threadIdx.x;
     const int64_t n = sc->np;
     int hops = 0, walls = 0, rem = 0, lost = 0;
     if (i < n) {
-        int c = p.cell[i];
-        double x0 = p.x[i], x1 = p.y[i], x2 = p.z[i];
-        const double v0i = (double)p.vx[i], v1i = (double)p.vy[i], v2i = (double)p.vz[i];
-        double v0 = v0i, v1 = v1i, v2 = v2i;
-        const uint32_t pid = p.pid[i];
-        const TraceOut o = trace<VT>(m, x0, x1, x2, v0, v1, v2, c, -1, pid, sc->step, key, dt);
-        hops = o.hops;
-        walls = o.walls;
-        p.x[i] = x0;
-        p.y[i] = x1;
-        p.z[i] = x2;
-        if (o.walls) {
-            p.vx[i] = (VT)v0;
-            p.vy[i] = (VT)v1;
-            p.vz[i] = (VT)v2;
+        Walker w;
+        w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
+        w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
+        w.c = p.cell[i]; w.pid = p.pid[i]; w.t = dt;
+        w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0;
+        const uint32_t step = sc->step;
+        int st;
+        do {
+            st = hop_once<VT>(m, w, step, key);
+        } while (st < 0);
+        hops = w.nhop;
+        walls = w.walls;
+        p.x[i] = w.x0; p.y[i] = w.x1; p.z[i] = w.x2;
+        if (w.walls) {
+            p.vx[i] = (VT)w.v0; p.vy[i] = (VT)w.v1; p.vz[i] = (VT)w.v2;
         }
-        if (o.status == 0) {
-            p.cell[i] = c;
-            rank[i] = (uint32_t)atomicAdd(&counts[c], 1);
+        if (st == 0) {
+            p.cell[i] = w.c;
+            rank[i] = (uint32_t)atomicAdd(&counts[w.c], 1);
         } else {
             p.cell[i] = -1;
-            rem = o.status == 1;
-            lost = o.status == 2;
+            rem = st == 1;
+            lost = st == 2;
         }
+    }
+    block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
+}
+
+// One particle per lane; a particle that reaches a diffuse wall is parked at
+// the wall (position, cell and remaining time) in a queue, so the costly
+// re-emission sampling does not diverge the hop loop.  k_move_walls then
+// re-emits the queued particles and finishes their step.
+template <class VT, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_move_defer(
+    MeshDev m, PartDev<VT> p, Scalars* sc, int32_t* counts, uint32_t* rank, Counters* ctr, RngKey key,
+    double dt, WallQueue q) {
+    const int64_t i = xcd_block() * 256 + threadIdx.x;
+    const int64_t n = sc->np;
+    int hops = 0, walls = 0, rem = 0, lost = 0;
+    bool park = false;
+    Walker w;
+    if (i < n) {
+        w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
+        w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
+        w.c = p.cell[i]; w.pid = p.pid[i]; w.t = dt;
+        w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0;
+        const uint32_t step = sc->step;
+        int st;
+        do {
+            st = hop_once<VT, true>(m, w, step, key);
+        } while (st < 0);
+        p.x[i] = w.x0; p.y[i] = w.x1; p.z[i] = w.x2;
+        if (st == kHopWallPending) {
+            park = true;
+            p.cell[i] = w.c;
+        } else {
+            hops = w.nhop;
+            walls = w.walls;
+            if (w.walls) {
+                p.vx[i] = (VT)w.v0; p.vy[i] = (VT)w.v1; p.vz[i] = (VT)w.v2;
+            }
+            if (st == 0) {
+                p.cell[i] = w.c;
+                rank[i] = (uint32_t)atomicAdd(&counts[w.c], 1);
+            } else {
+                p.cell[i] = -1;
+                rem = st == 1;
+                lost = st == 2;
+            }
+        }
+    }
+    // wave-aggregated push of parked particles
+    const uint64_t pm = __ballot(park);
+    if (pm) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)pm) - 1;
+        int64_t base = 0;
+        if (lane == leader) base = (int64_t)atomicAdd((unsigned long long*)&sc->n_wall, (unsigned long long)__popcll(pm));
+        base = __shfl(base, leader, 64);
+        if (park) {
+            const int64_t slot = base + __popcll(pm & ((1ull << lane) - 1ull));
+            q.idx[slot] = (int32_t)i;
+            q.t[slot] = w.t;
+            q.meta[slot] = (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22);
+        }
+    }
+    block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
+}
+
+// Batched move with lane refill and parked diffuse walls: each wave owns
+// `batch` consecutive particles; a lane whose particle is done (or parked)
+// takes the next untouched particle of the batch.
+template <class VT, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_move_refill(
+    MeshDev m, PartDev<VT> p, Scalars* sc, int32_t* counts, uint32_t* rank, Counters* ctr, RngKey key,
+    double dt, WallQueue q, int batch) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t wv = xcd_block() * 4 + (threadIdx.x >> 6);
+    const int64_t n = sc->np;
+    const int64_t lo = wv * (int64_t)batch;
+    const int64_t hi = min(lo + (int64_t)batch, n);
+    const uint32_t step = sc->step;
+    int hops = 0, walls = 0, rem = 0, lost = 0;
+    int64_t next = lo + 64;
+    int64_t i = lo + lane;
+    bool active = i < hi;
+    Walker w;
+    w.x0 = w.x1 = w.x2 = w.v0 = w.v1 = w.v2 = w.t = 0.0;
+    w.c = 0; w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0; w.pid = 0;
+    if (active) {
+        w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
+        w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
+        w.c = p.cell[i]; w.pid = p.pid[i]; w.t = dt;
+    }
+    while (__ballot(active) != 0ull) {
+        int st = -1;
+        if (active) st = hop_once<VT, true>(m, w, step, key);
+        const bool done = active && st >= 0;
+        const bool park = done && st == kHopWallPending;
+        if (done) {
+            p.x[i] = w.x0; p.y[i] = w.x1; p.z[i] = w.x2;
+            if (park) {
+                p.cell[i] = w.c;
+            } else {
+                if (w.walls) {
+                    p.vx[i] = (VT)w.v0; p.vy[i] = (VT)w.v1; p.vz[i] = (VT)w.v2;
+                }
+                if (st == 0) {
+                    p.cell[i] = w.c;
+                    rank[i] = (uint32_t)atomicAdd(&counts[w.c], 1);
+                } else {
+                    p.cell[i] = -1;
+                    rem += st == 1;
+                    lost += st == 2;
+                }
+                hops += w.nhop;
+                walls += w.walls;
+            }
+        }
+        const uint64_t pm = __ballot(park);
+        if (pm) {
+            const int leader = __ffsll((unsigned long long)pm) - 1;
+            int64_t base = 0;
+            if (lane == leader)
+                base = (int64_t)atomicAdd((unsigned long long*)&sc->n_wall, (unsigned long long)__popcll(pm));
+            base = __shfl(base, leader, 64);
+            if (park) {
+                const int64_t slot = base + __popcll(pm & below);
+                q.idx[slot] = (int32_t)i;
+                q.t[slot] = w.t;
+                q.meta[slot] = (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22);
+            }
+        }
+        const uint64_t dm = __ballot(done);
+        if (done) {
+            const int64_t ni = next + __popcll(dm & below);
+            active = ni < hi;
+            if (active) {
+                i = ni;
+                w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
+                w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
+                w.c = p.cell[i]; w.pid = p.pid[i]; w.t = dt;
+                w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0;
+            }
+        }
+        next += __popcll(dm);
+    }
+    block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
+}
+
+// Pooled move: each wave stages its batch of POOL consecutive particles in
+// LDS with one coalesced load; its lanes take particles from the pool as they
+// finish (so lanes stay busy although hop counts differ), leave the results
+// in the pool, and the wave writes the pool back, with the histogram
+// atomics, in one coalesced pass at the end.  Diffuse walls are parked for
+// k_move_walls.
+template <class VT, int WPE, int POOL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_move_pool(
+    MeshDev m, PartDev<VT> p, Scalars* sc, int32_t* counts, uint32_t* rank, Counters* ctr, RngKey key,
+    double dt, WallQueue q) {
+    __shared__ double sx[4][POOL], sy[4][POOL], sz[4][POOL];
+    __shared__ VT svx[4][POOL], svy[4][POOL], svz[4][POOL];
+    __shared__ int32_t scell[4][POOL];
+    __shared__ uint32_t spid[4][POOL];
+    __shared__ uint8_t sstate[4][POOL];   // bit0: velocity changed, bit1: parked
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t wv = xcd_block() * 4 + wid;
+    const int64_t n = sc->np;
+    const int64_t lo = wv * (int64_t)POOL;
+    const int cnt = (int)max((int64_t)0, min((int64_t)POOL, n - lo));
+    for (int k = lane; k < cnt; k += 64) {
+        sx[wid][k] = p.x[lo + k]; sy[wid][k] = p.y[lo + k]; sz[wid][k] = p.z[lo + k];
+        svx[wid][k] = p.vx[lo + k]; svy[wid][k] = p.vy[lo + k]; svz[wid][k] = p.vz[lo + k];
+        scell[wid][k] = p.cell[lo + k]; spid[wid][k] = p.pid[lo + k];
+    }
+    __syncthreads();
+    const uint32_t step = sc->step;
+    int hops = 0, walls = 0, rem = 0, lost = 0;
+    int next = 64;
+    int j = lane;
+    bool active = j < cnt;
+    Walker w;
+    w.x0 = w.x1 = w.x2 = w.v0 = w.v1 = w.v2 = w.t = 0.0;
+    w.c = 0; w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0; w.pid = 0;
+    if (active) {
+        w.x0 = sx[wid][j]; w.x1 = sy[wid][j]; w.x2 = sz[wid][j];
+        w.v0 = (double)svx[wid][j]; w.v1 = (double)svy[wid][j]; w.v2 = (double)svz[wid][j];
+        w.c = scell[wid][j]; w.pid = spid[wid][j]; w.t = dt;
+    }
+    while (__ballot(active) != 0ull) {
+        int st = -1;
+        if (active) st = hop_once<VT, true>(m, w, step, key);
+        const bool done = active && st >= 0;
+        const bool park = done && st == kHopWallPending;
+        if (done) {
+            sx[wid][j] = w.x0; sy[wid][j] = w.x1; sz[wid][j] = w.x2;
+            uint8_t flags = park ? 2 : 0;
+            if (!park) {
+                if (w.walls) {
+                    svx[wid][j] = (VT)w.v0; svy[wid][j] = (VT)w.v1; svz[wid][j] = (VT)w.v2;
+                    flags |= 1;
+                }
+                rem += st == 1;
+                lost += st == 2;
+                hops += w.nhop;
+                walls += w.walls;
+            }
+            scell[wid][j] = (st == 0 || park) ? w.c : -1;
+            sstate[wid][j] = flags;
+        }
+        const uint64_t pm = __ballot(park);
+        if (pm) {
+            const int leader = __ffsll((unsigned long long)pm) - 1;
+            int64_t base = 0;
+            if (lane == leader)
+                base = (int64_t)atomicAdd((unsigned long long*)&sc->n_wall, (unsigned long long)__popcll(pm));
+            base = __shfl(base, leader, 64);
+            if (park) {
+                const int64_t slot = base + __popcll(pm & below);
+                q.idx[slot] = (int32_t)(lo + j);
+                q.t[slot] = w.t;
+                q.meta[slot] = (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22);
+            }
+        }
+        const uint64_t dm = __ballot(done);
+        if (done) {
+            const int nj = next + __popcll(dm & below);
+            active = nj < cnt;
+            if (active) {
+                j = nj;
+                w.x0 = sx[wid][j]; w.x1 = sy[wid][j]; w.x2 = sz[wid][j];
+                w.v0 = (double)svx[wid][j]; w.v1 = (double)svy[wid][j]; w.v2 = (double)svz[wid][j];
+                w.c = scell[wid][j]; w.pid = spid[wid][j]; w.t = dt;
+                w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0;
+            }
+        }
+        next += __popcll(dm);
+    }
+    // write the pool back: positions, changed velocities, cells, ranks
+    for (int k = lane; k < cnt; k += 64) {
+        const int64_t i = lo + k;
+        const uint8_t f = sstate[wid][k];
+        const int cc = scell[wid][k];
+        p.x[i] = sx[wid][k]; p.y[i] = sy[wid][k]; p.z[i] = sz[wid][k];
+        if (f & 1) {
+            p.vx[i] = svx[wid][k]; p.vy[i] = svy[wid][k]; p.vz[i] = svz[wid][k];
+        }
+        p.cell[i] = cc;
+        if (!(f & 2) && cc >= 0) rank[i] = (uint32_t)atomicAdd(&counts[cc], 1);
+    }
+    block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
+}
+
+template <class VT>
+__global__ __launch_bounds__(256) void k_move_walls(MeshDev m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
+                                                   uint32_t* rank, Counters* ctr, RngKey key, WallQueue q) {
+    const int64_t nq = sc->n_wall;
+    const uint32_t step = sc->step;
+    int hops = 0, walls = 0, rem = 0, lost = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nq; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q.idx[e];
+        const int meta = q.meta[e];
+        Walker w;
+        w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
+        w.c = p.cell[i]; w.pid = p.pid[i]; w.t = q.t[e];
+        w.entry = meta & 3; w.hits = (meta >> 2) & 1023; w.nhop = (meta >> 12) & 1023; w.walls = (meta >> 22) & 1023;
+        const int bf = -1 - m.nbr[4 * w.c + w.entry];
+        diffuse_reemit<VT>(m, w, bf, w.entry, step, key);
+        int st;
+        do {
+            st = hop_once<VT, false>(m, w, step, key);
+        } while (st < 0);
+        hops += w.nhop;
+        walls += w.walls;
+        p.x[i] = w.x0; p.y[i] = w.x1; p.z[i] = w.x2;
+        p.vx[i] = (VT)w.v0; p.vy[i] = (VT)w.v1; p.vz[i] = (VT)w.v2;
+        if (st == 0) {
+            p.cell[i] = w.c;
+            rank[i] = (uint32_t)atomicAdd(&counts[w.c], 1);
+        } else {
+            p.cell[i] = -1;
+            rem += st == 1;
+            lost += st == 2;
+        }
+    }
+    block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
+}
+
+// Each wave owns a batch of `batch` consecutive particles.  A lane tracks
+// one particle hop by hop; when its particle is done the lane writes it back
+// and takes the next untouched particle of the batch, so lanes stay busy
+// while hop counts differ from particle to particle.
+template <class VT>
+__global__ __launch_bounds__(256) void k_move(MeshDev m, PartDev<VT> p, const Scalars* sc,
+                                             int32_t* counts, uint32_t* rank, Counters* ctr,
+                                             RngKey key, double dt, int batch) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t wv = xcd_block() * 4 + (threadIdx.x >> 6);
+    const int64_t n = sc->np;
+    const int64_t lo = wv * (int64_t)batch;
+    const int64_t hi = min(lo + (int64_t)batch, n);
+    const uint32_t step = sc->step;
+    int hops = 0, walls = 0, rem = 0, lost = 0;
+    int64_t next = lo + 64;
+    int64_t i = lo + lane;
+    bool active = i < hi;
+    Walker w;
+    w.x0 = w.x1 = w.x2 = w.v0 = w.v1 = w.v2 = w.t = 0.0;
+    w.c = 0; w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0; w.pid = 0;
+    if (active) {
+        w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
+        w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
+        w.c = p.cell[i]; w.pid = p.pid[i]; w.t = dt;
+    }
+    while (__ballot(active) != 0ull) {
+        int st = -1;
+        if (active) st = hop_once<VT>(m, w, step, key);
+        const bool done = active && st >= 0;
+        if (done) {
+            p.x[i] = w.x0; p.y[i] = w.x1; p.z[i] = w.x2;
+            if (w.walls) {
+                p.vx[i] = (VT)w.v0; p.vy[i] = (VT)w.v1; p.vz[i] = (VT)w.v2;
+            }
+            if (st == 0) {
+                p.cell[i] = w.c;
+                rank[i] = (uint32_t)atomicAdd(&counts[w.c], 1);
+            } else {
+                p.cell[i] = -1;
+                rem += st == 1;
+                lost += st == 2;
+            }
+            hops += w.nhop;
+            walls += w.walls;
+        }
+        const uint64_t dm = __ballot(done);
+        if (done) {
+            const int64_t ni = next + __popcll(dm & below);
+            active = ni < hi;
+            if (active) {
+                i = ni;
+                w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
+                w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
+                w.c = p.cell[i]; w.pid = p.pid[i]; w.t = dt;
+                w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0;
+            }
+        }
+        next += __popcll(dm);
     }
     block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
 }
@@ -417,6 +771,35 @@ __global__ __launch_bounds__(256) void k_scatter(PartDev<VT> src, PartDev<VT> ds
     dst.pid[d] = src.pid[i];
 }
 
+// Gather form of the counting sort: k_perm writes, for every destination
+// slot, the index of the particle that lands there (4-byte scattered
+// stores); k_gather then fills the sorted buffer slot by slot (coalesced
+// stores, gathered loads from the spatially local source buffer).
+__global__ __launch_bounds__(256) void k_perm(const int32_t* cell, const Scalars* sc, const int32_t* offsets,
+                                             const uint32_t* rank, int32_t* perm, int64_t cap) {
+    const int64_t i = xcd_block() * 256 + threadIdx.x;
+    if (i >= sc->n_entries || i >= cap) return;
+    const int c = cell[i];
+    if (c < 0) return;
+    perm[(int64_t)offsets[c] + rank[i]] = (int32_t)i;
+}
+
+template <class VT>
+__global__ __launch_bounds__(256) void k_gather(PartDev<VT> src, PartDev<VT> dst, const Scalars* sc,
+                                               const int32_t* perm) {
+    const int64_t k = xcd_block() * 256 + threadIdx.x;
+    if (k >= sc->np) return;
+    const int64_t i = perm[k];
+    dst.x[k] = src.x[i];
+    dst.y[k] = src.y[i];
+    dst.z[k] = src.z[i];
+    dst.vx[k] = src.vx[i];
+    dst.vy[k] = src.vy[i];
+    dst.vz[k] = src.vz[i];
+    dst.cell[k] = src.cell[i];
+    dst.pid[k] = src.pid[i];
+}
+
 // ---------------------------------------------------------------------------
 // collisions and sampling
 // ---------------------------------------------------------------------------
@@ -453,19 +836,36 @@ struct GlobalCell {
     }
 };
 
+template <class VT>
+struct LdsOrderCell {
+    VT* v0; VT* v1; VT* v2;
+    const uint16_t* ord;   // sorted position -> slot relative to the chunk start
+    int s0;
+    int64_t a;             // chunk start in the particle arrays
+    __device__ __forceinline__ void get(int k, double& x, double& y, double& z) const {
+        const int64_t l = a + ord[s0 + k];
+        x = (double)v0[l]; y = (double)v1[l]; z = (double)v2[l];
+    }
+    __device__ __forceinline__ void put(int k, double x, double y, double z) const {
+        const int64_t l = a + ord[s0 + k];
+        v0[l] = (VT)x; v1[l] = (VT)y; v2[l] = (VT)z;
+    }
+};
+
 template <class Acc>
 __device__ __forceinline__ void ntc_cell(const Acc& cv, int N, int c, const CollideParams& cp,
                                          uint32_t step, double* smax, int32_t* ncand, int32_t* nacc) {
     int M = 0, acc = 0;
     if (N >= 2) {
         const double sm = smax[c];
-        const Rand4 r = draw(cp.key, (uint32_t)c, step, kPurposeNtcCount, 0);
+        const uint32_t subj = (uint32_t)cp.orig[c];
+        const Rand4 r = draw(cp.key, subj, step, kPurposeNtcCount, 0);
         const double Nd = (double)N;
         const double mean = ((((0.5 * Nd) * (Nd - 1.0)) * cp.FN) * sm) * cp.dt / cp.vol[c];
         M = (int)floor(mean + u01(r.w[0], r.w[1]));
         double seen = 0.0;
         for (int k = 0; k < M; ++k) {
-            const Rand4 w = draw(cp.key, (uint32_t)c, step, kPurposePair, (uint64_t)k);
+            const Rand4 w = draw(cp.key, subj, step, kPurposePair, (uint64_t)k);
             const uint32_t i = pick(w.w[0], (uint32_t)N);
             uint32_t j = pick(w.w[1], (uint32_t)(N - 1));
             if (j >= i) ++j;
@@ -479,7 +879,7 @@ __device__ __forceinline__ void ntc_cell(const Acc& cv, int N, int c, const Coll
             if (sc > seen) seen = sc;
             if (!(U < sc / sm)) continue;
             ++acc;
-            const Rand4 q = draw(cp.key, (uint32_t)c, step, kPurposeScatter, (uint64_t)k);
+            const Rand4 q = draw(cp.key, subj, step, kPurposeScatter, (uint64_t)k);
             const double cx = 2.0 * u01(q.w[0], q.w[1]) - 1.0;
             const double sx = sqrt(1.0 - cx * cx);
             const double eps = DSMC_TWO_PI * u01(q.w[2], q.w[3]);
@@ -553,6 +953,7 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
     const int64_t n = (int64_t)offsets[cend] - a;
     const uint32_t step = sc->step;
     if (n <= kCollideCap) {
+#pragma unroll 4
         for (int64_t i = lane; i < n; i += kCollideLanes) {
             sv0[i] = p.vx[a + i];
             sv1[i] = p.vy[a + i];
@@ -564,12 +965,18 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
         if (c < nt) {
             const int s0 = (int)(offsets[c] - a);
             const int N = offsets[c + 1] - offsets[c];
-            // logical order: rank of each particle's pid within the cell
+            // logical order: insertion sort of the cell's pids (sord maps the
+            // sorted position to the staged slot)
             for (int k = 0; k < N; ++k) {
-                const uint32_t pk = spid[s0 + k];
-                int r = 0;
-                for (int q = 0; q < N; ++q) r += spid[s0 + q] < pk;
-                sord[s0 + r] = (uint16_t)(s0 + k);
+                const uint32_t key = spid[s0 + k];
+                int j = k;
+                while (j > 0 && spid[s0 + j - 1] > key) {
+                    spid[s0 + j] = spid[s0 + j - 1];
+                    sord[s0 + j] = sord[s0 + j - 1];
+                    --j;
+                }
+                spid[s0 + j] = key;
+                sord[s0 + j] = (uint16_t)(s0 + k);
             }
             LdsCell<VT> cv{sv0, sv1, sv2, sord, stouch, s0};
             if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
@@ -599,16 +1006,74 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
     }
 }
 
+// Variant with only the pid ranking staged in LDS (6 bytes per particle,
+// up to kCollideCapG per 64-cell chunk); the velocities stay in global
+// memory and are reached through the logical order, so several waves fit on
+// a CU.  Ranks are computed one particle per lane (independent LDS reads
+// that pipeline), the collisions and sums one cell per lane.
+template <class VT, int WPE>
+__global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(WPE))) void k_collide_sample_g(
+    PartDev<VT> p, const int32_t* offsets, CollideParams cp, const Scalars* sc, int32_t* perm, int do_collide,
+    int do_sample) {
+    __shared__ uint32_t spid[kCollideCapG];
+    __shared__ uint16_t sord[kCollideCapG];
+    __shared__ int32_t soff[kCollideLanes + 1];
+    const int nt = cp.nt;
+    const int lane = threadIdx.x;
+    const int c0 = blockIdx.x * kCollideLanes;
+    const int c = c0 + lane;
+    const int64_t a = offsets[c0];
+    soff[lane] = offsets[min(c0 + lane, nt)] - (int32_t)a;
+    if (lane == 0) soff[kCollideLanes] = offsets[min(c0 + kCollideLanes, nt)] - (int32_t)a;
+    const int64_t n = (int64_t)offsets[min(c0 + kCollideLanes, nt)] - a;
+    const uint32_t step = sc->step;
+    if (n <= kCollideCapG) {
+#pragma unroll 4
+        for (int64_t i = lane; i < n; i += kCollideLanes) spid[i] = p.pid[a + i];
+        __syncthreads();
+        for (int i = lane; i < (int)n; i += kCollideLanes) {
+            const int k = p.cell[a + i] - c0;
+            const int s0 = soff[k];
+            const int N = soff[k + 1] - s0;
+            const uint32_t pk = spid[i];
+            int r = 0;
+#pragma unroll 4
+            for (int q = 0; q < N; ++q) r += spid[s0 + q] < pk ? 1 : 0;
+            sord[s0 + r] = (uint16_t)i;
+        }
+        __syncthreads();
+        if (c < nt) {
+            const int s0 = soff[lane];
+            const int N = soff[lane + 1] - s0;
+            LdsOrderCell<VT> cv{p.vx, p.vy, p.vz, sord, s0, a};
+            if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
+            if (do_sample) sample_cell(cv, N, c, cp, step);
+        }
+    } else if (c < nt) {
+        const int64_t s0 = offsets[c];
+        const int N = offsets[c + 1] - offsets[c];
+        for (int k = 0; k < N; ++k) {
+            const uint32_t pk = p.pid[s0 + k];
+            int r = 0;
+            for (int q = 0; q < N; ++q) r += p.pid[s0 + q] < pk;
+            perm[s0 + r] = (int32_t)(s0 + k);
+        }
+        GlobalCell<VT> cv{p.vx, p.vy, p.vz, perm, s0};
+        if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
+        if (do_sample) sample_cell(cv, N, c, cp, step);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // fields from moment sums (eq. dsmc_temperatures over accumulated samples)
 // ---------------------------------------------------------------------------
 __global__ void k_fields(const double* sums, int nt, double ns, double mass, double FN, const double* vol,
-                         double* out) {
+                         const int32_t* orig, double* out) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nt) return;
     double S[kNMom];
     for (int k = 0; k < kNMom; ++k) S[k] = sums[(int64_t)k * nt + c];
-    double* o = out + 15 * (size_t)c;
+    double* o = out + 15 * (size_t)orig[c];
     if (!(S[0] > 0) || !(ns > 0)) {
         for (int k = 0; k < 15; ++k) o[k] = __builtin_nan("");
         return;
@@ -677,23 +1142,88 @@ void launch_begin(hipStream_t s, int32_t* counts, int nt, Scalars* sc, int do_sa
     hipLaunchKernelGGL(k_begin, GRID(nt + 1, 256), dim3(256), 0, s, counts, nt, sc, do_sample, n_ss);
 }
 
-void launch_init_count(hipStream_t s, const double* vol, int nt, double n0, double FN, RngKey key,
-                       int32_t* counts) {
-    hipLaunchKernelGGL(k_init_count, GRID(nt, 256), dim3(256), 0, s, vol, nt, n0, FN, key, counts);
+void launch_init_count(hipStream_t s, const double* vol, const int32_t* orig, int nt, double n0, double FN,
+                       RngKey key, int32_t* counts, int32_t* counts_orig) {
+    hipLaunchKernelGGL(k_init_count, GRID(nt, 256), dim3(256), 0, s, vol, orig, nt, n0, FN, key, counts,
+                       counts_orig);
 }
 
 template <class VT>
 void launch_init_fill(hipStream_t s, const int4* tv, const double* xyz, int nt, const int32_t* offsets,
-                      PartDev<VT> p, RngKey key, double sig, const double* u0, int64_t cap, Scalars* sc) {
-    hipLaunchKernelGGL(k_init_fill<VT>, GRID(nt, 128), dim3(128), 0, s, tv, xyz, nt, offsets, p, key, sig,
-                       u0[0], u0[1], u0[2], cap, sc);
+                      const int32_t* orig, const int32_t* pid_base, PartDev<VT> p, RngKey key, double sig,
+                      const double* u0, int64_t cap, Scalars* sc) {
+    hipLaunchKernelGGL(k_init_fill<VT>, GRID(nt, 128), dim3(128), 0, s, tv, xyz, nt, offsets, orig, pid_base, p,
+                       key, sig, u0[0], u0[1], u0[2], cap, sc);
 }
 
 template <class VT>
 void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
-                 uint32_t* rank, Counters* ctr, RngKey key, double dt, int64_t np_bound) {
-    hipLaunchKernelGGL(k_move<VT>, dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p, sc, counts, rank, ctr,
-                       key, dt);
+                 uint32_t* rank, Counters* ctr, RngKey key, double dt, int64_t np_bound, int variant, int batch,
+                 WallQueue wq) {
+    switch (variant) {
+    case kMoveBatched: {
+        const int b = batch > 0 ? batch : kMoveBatch;
+        hipLaunchKernelGGL(k_move<VT>, dim3(grid8(np_bound, 4 * b)), dim3(256), 0, s, m, p, sc, counts, rank,
+                           ctr, key, dt, b);
+        break;
+    }
+    case kMoveLaneW8:
+        hipLaunchKernelGGL((k_move_lane<VT, 8>), dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p, sc, counts,
+                           rank, ctr, key, dt);
+        break;
+    case kMoveLaneW6:
+        hipLaunchKernelGGL((k_move_lane<VT, 6>), dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p, sc, counts,
+                           rank, ctr, key, dt);
+        break;
+    case kMoveDefer4:
+    case kMoveDefer5:
+    case kMoveDefer6:
+    case kMoveDefer8: {
+        const dim3 g(grid8(np_bound, 256));
+        if (variant == kMoveDefer4)
+            hipLaunchKernelGGL((k_move_defer<VT, 4>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr, key,
+                               dt, wq);
+        else if (variant == kMoveDefer5)
+            hipLaunchKernelGGL((k_move_defer<VT, 5>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr, key,
+                               dt, wq);
+        else if (variant == kMoveDefer6)
+            hipLaunchKernelGGL((k_move_defer<VT, 6>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr, key,
+                               dt, wq);
+        else
+            hipLaunchKernelGGL((k_move_defer<VT, 8>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr, key,
+                               dt, wq);
+        hipLaunchKernelGGL(k_move_walls<VT>, dim3(1024), dim3(256), 0, s, m, p, sc, counts, rank, ctr, key, wq);
+        break;
+    }
+    case kMovePool128:
+    case kMovePool256: {
+        if (variant == kMovePool128)
+            hipLaunchKernelGGL((k_move_pool<VT, 6, 128>), dim3(grid8(np_bound, 4 * 128)), dim3(256), 0, s, m, p,
+                               (Scalars*)sc, counts, rank, ctr, key, dt, wq);
+        else
+            hipLaunchKernelGGL((k_move_pool<VT, 4, 256>), dim3(grid8(np_bound, 4 * 256)), dim3(256), 0, s, m, p,
+                               (Scalars*)sc, counts, rank, ctr, key, dt, wq);
+        hipLaunchKernelGGL(k_move_walls<VT>, dim3(1024), dim3(256), 0, s, m, p, sc, counts, rank, ctr, key, wq);
+        break;
+    }
+    case kMoveRefill5:
+    case kMoveRefill6: {
+        const int b = batch > 0 ? batch : kMoveBatch;
+        const dim3 g(grid8(np_bound, 4 * b));
+        if (variant == kMoveRefill5)
+            hipLaunchKernelGGL((k_move_refill<VT, 5>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr, key,
+                               dt, wq, b);
+        else
+            hipLaunchKernelGGL((k_move_refill<VT, 6>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr, key,
+                               dt, wq, b);
+        hipLaunchKernelGGL(k_move_walls<VT>, dim3(1024), dim3(256), 0, s, m, p, sc, counts, rank, ctr, key, wq);
+        break;
+    }
+    default:
+        hipLaunchKernelGGL((k_move_lane<VT, 1>), dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p, sc, counts,
+                           rank, ctr, key, dt);
+        break;
+    }
 }
 
 void launch_count(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
@@ -725,21 +1255,33 @@ void launch_scan(hipStream_t s, const int32_t* in, int64_t n, int32_t* out, int3
 
 template <class VT>
 void launch_scatter(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalars* sc, const int32_t* offsets,
-                    const uint32_t* rank, int64_t bound, int64_t cap) {
-    hipLaunchKernelGGL(k_scatter<VT>, dim3(grid8(bound, 256)), dim3(256), 0, s, src, dst, sc, offsets, rank, cap);
+                    const uint32_t* rank, int64_t bound, int64_t cap, int32_t* perm, int variant) {
+    if (variant == kSortGather) {
+        hipLaunchKernelGGL(k_perm, dim3(grid8(bound, 256)), dim3(256), 0, s, src.cell, sc, offsets, rank, perm, cap);
+        hipLaunchKernelGGL(k_gather<VT>, dim3(grid8(bound, 256)), dim3(256), 0, s, src, dst, sc, perm);
+    } else {
+        hipLaunchKernelGGL(k_scatter<VT>, dim3(grid8(bound, 256)), dim3(256), 0, s, src, dst, sc, offsets, rank, cap);
+    }
 }
 
 template <class VT>
 void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
-                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample) {
+                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant) {
     const int nchunk = (cp.nt + kCollideLanes - 1) / kCollideLanes;
-    hipLaunchKernelGGL(k_collide_sample<VT>, dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc, perm,
-                       do_collide, do_sample);
+    if (variant == kCollideGlobal)
+        hipLaunchKernelGGL((k_collide_sample_g<VT, 4>), dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc,
+                           perm, do_collide, do_sample);
+    else if (variant == kCollideGlobal8)
+        hipLaunchKernelGGL((k_collide_sample_g<VT, 8>), dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc,
+                           perm, do_collide, do_sample);
+    else
+        hipLaunchKernelGGL(k_collide_sample<VT>, dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc, perm,
+                           do_collide, do_sample);
 }
 
 void launch_fields(hipStream_t s, const double* sums, int nt, double ns, double mass, double FN,
-                   const double* vol, double* out) {
-    hipLaunchKernelGGL(k_fields, GRID(nt, 256), dim3(256), 0, s, sums, nt, ns, mass, FN, vol, out);
+                   const double* vol, const int32_t* orig, double* out) {
+    hipLaunchKernelGGL(k_fields, GRID(nt, 256), dim3(256), 0, s, sums, nt, ns, mass, FN, vol, orig, out);
 }
 
 void launch_philox(hipStream_t s, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n) {
@@ -761,16 +1303,17 @@ void launch_fill_f64(hipStream_t s, double* p, double v, int64_t n) {
 
 #define INSTANTIATE(VT)                                                                                      \
     template void launch_init_fill<VT>(hipStream_t, const int4*, const double*, int, const int32_t*,       \
-                                       PartDev<VT>, RngKey, double, const double*, int64_t, Scalars*);      \
+                                       const int32_t*, const int32_t*, PartDev<VT>, RngKey, double,         \
+                                       const double*, int64_t, Scalars*);                                   \
     template void launch_move<VT>(hipStream_t, const MeshDev&, PartDev<VT>, const Scalars*, int32_t*,       \
-                                  uint32_t*, Counters*, RngKey, double, int64_t);                           \
+                                  uint32_t*, Counters*, RngKey, double, int64_t, int, int, WallQueue);      \
     template void launch_inject_emit<VT>(hipStream_t, const MeshDev&, const InflowDev&, PartDev<VT>,        \
                                          Scalars*, const int32_t*, int32_t*, uint32_t*, Counters*, RngKey,  \
                                          double, int64_t, int64_t);                                         \
     template void launch_scatter<VT>(hipStream_t, PartDev<VT>, PartDev<VT>, const Scalars*, const int32_t*, \
-                                     const uint32_t*, int64_t, int64_t);                                           \
+                                     const uint32_t*, int64_t, int64_t, int32_t*, int);                                           \
     template void launch_collide_sample<VT>(hipStream_t, PartDev<VT>, const int32_t*, const CollideParams&, \
-                                            const Scalars*, int32_t*, int, int);
+                                            const Scalars*, int32_t*, int, int, int);
 
 INSTANTIATE(float)
 INSTANTIATE(double)

@@ -198,4 +198,65 @@ std::string build_mesh(HostMesh& m, int nv, const double* xyz, int nt, const int
     return std::string();
 }
 
+namespace {
+inline uint64_t spread3(uint64_t v) {
+    v &= 0x1FFFFFull;
+    v = (v | (v << 32)) & 0x1F00000000FFFFull;
+    v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+}  // namespace
+
+void reorder_cells(HostMesh& m) {
+    const int nt = m.nt;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    std::vector<double> cen(3 * (size_t)nt);
+    for (int t = 0; t < nt; ++t)
+        for (int i = 0; i < 3; ++i) {
+            double s = 0;
+            for (int k = 0; k < 4; ++k) s += m.xyz[3 * (size_t)m.tv[4 * (size_t)t + k] + i];
+            cen[3 * (size_t)t + i] = 0.25 * s;
+            lo[i] = std::min(lo[i], cen[3 * (size_t)t + i]);
+            hi[i] = std::max(hi[i], cen[3 * (size_t)t + i]);
+        }
+    double ext = 0;
+    for (int i = 0; i < 3; ++i) ext = std::max(ext, hi[i] - lo[i]);
+    if (!(ext > 0)) ext = 1;
+    std::vector<uint64_t> key(nt);
+    for (int t = 0; t < nt; ++t) {
+        uint64_t k = 0;
+        for (int i = 0; i < 3; ++i) {
+            double q = (cen[3 * (size_t)t + i] - lo[i]) / ext * 2097151.0;
+            uint64_t qi = (uint64_t)std::min(2097151.0, std::max(0.0, q));
+            k |= spread3(qi) << i;
+        }
+        key[t] = k;
+    }
+    m.orig.resize(nt);
+    std::iota(m.orig.begin(), m.orig.end(), 0);
+    std::stable_sort(m.orig.begin(), m.orig.end(), [&](int a, int b) { return key[a] < key[b]; });
+    m.inv.assign(nt, 0);
+    for (int t = 0; t < nt; ++t) m.inv[m.orig[t]] = t;
+    std::vector<int32_t> tv(4 * (size_t)nt), nbr(4 * (size_t)nt);
+    std::vector<double> vol(nt), plane(16 * (size_t)nt);
+    for (int t = 0; t < nt; ++t) {
+        const int o = m.orig[t];
+        for (int k = 0; k < 4; ++k) {
+            tv[4 * (size_t)t + k] = m.tv[4 * (size_t)o + k];
+            const int code = m.nbr[4 * (size_t)o + k];
+            nbr[4 * (size_t)t + k] = code >= 0 ? ((m.inv[code >> 2] << 2) | (code & 3)) : code;
+        }
+        vol[t] = m.vol[o];
+        for (int k = 0; k < 16; ++k) plane[16 * (size_t)t + k] = m.plane[16 * (size_t)o + k];
+    }
+    m.tv.swap(tv);
+    m.nbr.swap(nbr);
+    m.vol.swap(vol);
+    m.plane.swap(plane);
+    for (int b = 0; b < m.nb; ++b) m.bf_tet[b] = m.inv[m.bf_tet[b]];
+}
+
 }  // namespace dsmcx

@@ -25,6 +25,9 @@ struct HostMesh {
     std::vector<double> bf_area;    // [nb]
     std::vector<double> bf_nraw;    // [nb][3] unnormalised face normal (p<q<r cross product)
     std::vector<double> bf_sign;    // [nb] +1 if bf_nraw points out of the domain
+    // cell renumbering for locality: internal (device) id -> caller's id and back
+    std::vector<int32_t> orig;      // [nt]
+    std::vector<int32_t> inv;       // [nt]
 };
 
 // Returns an empty string on success, otherwise the reason the mesh is
@@ -33,5 +36,10 @@ struct HostMesh {
 std::string build_mesh(HostMesh& m, int nv, const double* xyz, int nt, const int32_t* tet,
                        int nb, const int32_t* bface, const int32_t* bgroup,
                        const int32_t* bpartner, int ngroups);
+
+// Renumber the tets along a Morton (Z-order) curve of their centroids so
+// that cells close in space are close in memory; fills orig/inv.  Only
+// internal numbering changes: every interface keeps the caller's ids.
+void reorder_cells(HostMesh& m);
 
 }  // namespace dsmcx
