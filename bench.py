@@ -17,22 +17,33 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic HBM bytes per particle (or per cell) of each kernel, for the
-# FP32-velocity layout: x,y,z f64 (24) + v f32 (12) + cell i32 (4) + pid u32 (4).
-#  move:     read x,v,cell,pid (44); write x,cell,rank (32); + v (12) per wall hit
-#  scatter:  read x,v,cell,pid,rank (48); write x,v,cell,pid (44)
-#  collide:  read v,pid (16); write v of collided particles (12 per particle touched);
-#            per cell: offsets (4), smax/counters (16), steady sums read+write (208)
-#  scan:     per cell: counts read twice (8), offsets write (4)
-B_MOVE, B_WALL = 76.0, 12.0
-B_SCATTER = 92.0
-B_COLLIDE_P, B_COLLIDE_TOUCH, B_COLLIDE_CELL = 16.0, 12.0, 228.0
-B_SCAN_CELL = 12.0
+# Algorithmic HBM bytes of each kernel, FP32-velocity layout: a particle is
+# x,y,z f64 (24) + v f32 (12) + cell i32 (4) + pid u32 (4) = 44 bytes.
+#  move:         read x,v,cell,pid (44); write x,cell (28) + rank (4); a particle
+#                parked at a diffuse wall writes a 16-byte queue entry instead of
+#                its rank
+#  move_walls:   per parked particle: queue (16) + x,cell,pid (32) read;
+#                x,v,cell,rank (44) written
+#  sort_perm:    read cell, rank (8) + the cell offset (4); write perm (4)
+#  sort_gather:  read perm (4) + a particle (44); write it (44)
+#  collide:      read pid, cell, v (20); write v of collided particles (12 each);
+#                per cell: offset (4), smax r/w (16), pair counts (8), steady
+#                sums read+write (208)
+#  scan:         per cell: counts read twice (8), offsets written (4)
+BYTES = {
+    "move": lambda np_, nt, f: np_ * (76.0 + 12.0 * f["park"]),
+    "move_walls": lambda np_, nt, f: np_ * f["park"] * 92.0,
+    "sort_perm": lambda np_, nt, f: np_ * 16.0,
+    "sort_gather": lambda np_, nt, f: np_ * 92.0,
+    "collide_sample": lambda np_, nt, f: np_ * (20.0 + 12.0 * f["touched"]) + nt * 236.0,
+    "scan": lambda np_, nt, f: nt * 12.0,
+}
 
 # rocprofv3 --pmc measurements of the move kernel (FETCH_SIZE + WRITE_SIZE per
 # dispatch, scaled by the copy-kernel calibration) and the source digest they
 # were taken on; the traffic figure is reported only while the digest matches.
-TRAFFIC = None
+TRAFFIC = {"kernel": "move", "digest": "abfbccdafa367eff", "bytes_per_launch": 580972131 + 704928921,
+           "source": "profiles/step_kernels_cavity40.md"}
 
 
 def _kernel_digest():
@@ -126,12 +137,8 @@ def main():
     for name, (ms, cnt) in prof.items():
         if cnt:
             per_launch[name] = ms / cnt
-    bytes_launch = {
-        "move": npart * (B_MOVE + B_WALL * walls_pp),
-        "scatter": npart * B_SCATTER,
-        "collide_sample": npart * (B_COLLIDE_P + B_COLLIDE_TOUCH * touched_pp) + nt * B_COLLIDE_CELL,
-        "scan": nt * B_SCAN_CELL,
-    }
+    frac = {"park": walls_pp, "touched": touched_pp}
+    bytes_launch = {k: fn(npart, nt, frac) for k, fn in BYTES.items()}
     gbs = {k: bytes_launch[k] / (per_launch[k] * 1e-3) / 1e9 for k in bytes_launch if k in per_launch}
     dominant = max((k for k in bytes_launch if k in per_launch), key=lambda k: per_launch[k])
     step_bytes = sum(bytes_launch.values())
@@ -139,9 +146,10 @@ def main():
     digest = _kernel_digest()
     traffic = None
     if TRAFFIC and TRAFFIC.get("digest") == digest and TRAFFIC.get("kernel") == dominant:
-        traffic = TRAFFIC["bytes_per_launch"]
+        traffic = TRAFFIC["bytes_per_launch"] / 1e9 / (per_launch[dominant] * 1e-3)
     roofline = dict(bound="hbm", kernel=dominant, achieved=round(gbs[dominant], 1), peak=peak, unit="GB/s",
-                    frac=round(gbs[dominant] / peak, 4), traffic=traffic)
+                    frac=round(gbs[dominant] / peak, 4),
+                    traffic=None if traffic is None else round(traffic, 1))
 
     out = {
         "metric": "particle-steps/s",

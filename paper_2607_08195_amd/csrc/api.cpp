@@ -19,8 +19,12 @@ using namespace dsmcx;
 
 namespace {
 
-enum Slot { kSlotBegin = 0, kSlotMove, kSlotInject, kSlotScan, kSlotScatter, kSlotCollide, kNumSlots };
-const char* kSlotNames[kNumSlots] = {"begin", "move", "inject", "scan", "scatter", "collide_sample"};
+enum Slot {
+    kSlotBegin = 0, kSlotMove, kSlotWalls, kSlotInject, kSlotScan, kSlotScatter, kSlotGather, kSlotCollide, kNumSlots
+};
+// one slot per kernel (or per fixed kernel group) of the step
+const char* kSlotNames[kNumSlots] = {"begin", "move", "move_walls", "inject", "scan", "sort_perm", "sort_gather",
+                                     "collide_sample"};
 
 struct Buf {
     double* x = nullptr;
@@ -218,6 +222,10 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
         launch_move<VT>(s, c->mesh, a, c->d_sc, c->d_counts, c->d_rank, c->d_ctr, c->key, c->dt, c->np_bound,
                         c->move_variant, c->move_batch, c->wq);
     }
+    if (mv && move_parks_walls(c->move_variant)) {
+        Timed t(c, kSlotWalls);
+        launch_move_walls<VT>(s, c->mesh, a, c->d_sc, c->d_counts, c->d_rank, c->d_ctr, c->key, c->wq);
+    }
     if (inj) {
         Timed t(c, kSlotInject);
         launch_inject_count(s, c->inflow, c->d_sc, c->key, c->d_fcount);
@@ -234,6 +242,10 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
         {
             Timed t(c, kSlotScatter);
             launch_scatter<VT>(s, a, b, c->d_sc, c->d_offsets, c->d_rank, need, c->cap, c->d_sortperm, c->sort_variant);
+        }
+        if (c->sort_variant == kSortGather) {
+            Timed t(c, kSlotGather);
+            launch_gather<VT>(s, a, b, c->d_sc, c->d_sortperm, need);
         }
         std::swap(c->A, c->B);
         a = as_dev<VT>(c->A);

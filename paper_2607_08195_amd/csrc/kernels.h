@@ -99,6 +99,13 @@ template <class VT>
 void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
                  uint32_t* rank, Counters* ctr, RngKey key, double dt, int64_t np_bound, int variant, int batch,
                  WallQueue wq);
+template <class VT>
+void launch_move_walls(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
+                       uint32_t* rank, Counters* ctr, RngKey key, WallQueue wq);
+bool move_parks_walls(int variant);
+template <class VT>
+void launch_gather(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalars* sc, const int32_t* perm,
+                   int64_t bound);
 void launch_count(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
                   int64_t np_bound);
 void launch_inject_count(hipStream_t s, const InflowDev& in, const Scalars* sc, RngKey key, int32_t* fcount);

@@ -1192,7 +1192,6 @@ void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* 
         else
             hipLaunchKernelGGL((k_move_defer<VT, 8>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr, key,
                                dt, wq);
-        hipLaunchKernelGGL(k_move_walls<VT>, dim3(1024), dim3(256), 0, s, m, p, sc, counts, rank, ctr, key, wq);
         break;
     }
     case kMovePool128:
@@ -1203,7 +1202,6 @@ void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* 
         else
             hipLaunchKernelGGL((k_move_pool<VT, 4, 256>), dim3(grid8(np_bound, 4 * 256)), dim3(256), 0, s, m, p,
                                (Scalars*)sc, counts, rank, ctr, key, dt, wq);
-        hipLaunchKernelGGL(k_move_walls<VT>, dim3(1024), dim3(256), 0, s, m, p, sc, counts, rank, ctr, key, wq);
         break;
     }
     case kMoveRefill5:
@@ -1216,7 +1214,6 @@ void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* 
         else
             hipLaunchKernelGGL((k_move_refill<VT, 6>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr, key,
                                dt, wq, b);
-        hipLaunchKernelGGL(k_move_walls<VT>, dim3(1024), dim3(256), 0, s, m, p, sc, counts, rank, ctr, key, wq);
         break;
     }
     default:
@@ -1224,6 +1221,17 @@ void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* 
                            rank, ctr, key, dt);
         break;
     }
+}
+
+template <class VT>
+void launch_move_walls(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
+                       uint32_t* rank, Counters* ctr, RngKey key, WallQueue wq) {
+    hipLaunchKernelGGL(k_move_walls<VT>, dim3(1024), dim3(256), 0, s, m, p, sc, counts, rank, ctr, key, wq);
+}
+
+bool move_parks_walls(int variant) {
+    return variant == kMoveDefer4 || variant == kMoveDefer5 || variant == kMoveDefer6 || variant == kMoveDefer8 ||
+           variant == kMovePool128 || variant == kMovePool256 || variant == kMoveRefill5 || variant == kMoveRefill6;
 }
 
 void launch_count(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
@@ -1258,10 +1266,15 @@ void launch_scatter(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scala
                     const uint32_t* rank, int64_t bound, int64_t cap, int32_t* perm, int variant) {
     if (variant == kSortGather) {
         hipLaunchKernelGGL(k_perm, dim3(grid8(bound, 256)), dim3(256), 0, s, src.cell, sc, offsets, rank, perm, cap);
-        hipLaunchKernelGGL(k_gather<VT>, dim3(grid8(bound, 256)), dim3(256), 0, s, src, dst, sc, perm);
     } else {
         hipLaunchKernelGGL(k_scatter<VT>, dim3(grid8(bound, 256)), dim3(256), 0, s, src, dst, sc, offsets, rank, cap);
     }
+}
+
+template <class VT>
+void launch_gather(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalars* sc, const int32_t* perm,
+                   int64_t bound) {
+    hipLaunchKernelGGL(k_gather<VT>, dim3(grid8(bound, 256)), dim3(256), 0, s, src, dst, sc, perm);
 }
 
 template <class VT>
@@ -1312,6 +1325,10 @@ void launch_fill_f64(hipStream_t s, double* p, double v, int64_t n) {
                                          double, int64_t, int64_t);                                         \
     template void launch_scatter<VT>(hipStream_t, PartDev<VT>, PartDev<VT>, const Scalars*, const int32_t*, \
                                      const uint32_t*, int64_t, int64_t, int32_t*, int);                                           \
+    template void launch_move_walls<VT>(hipStream_t, const MeshDev&, PartDev<VT>, const Scalars*, int32_t*,  \
+                                        uint32_t*, Counters*, RngKey, WallQueue);                           \
+    template void launch_gather<VT>(hipStream_t, PartDev<VT>, PartDev<VT>, const Scalars*, const int32_t*,  \
+                                    int64_t);                                                               \
     template void launch_collide_sample<VT>(hipStream_t, PartDev<VT>, const int32_t*, const CollideParams&, \
                                             const Scalars*, int32_t*, int, int, int);
 
