@@ -57,8 +57,38 @@ def _load():
     lib.oracle_num_faces.argtypes = [P]
     lib.oracle_trace_one.argtypes = [P, P, P, i, u32, u32, d]
     lib.oracle_philox.argtypes = [P, P, P]
+    lib.oracle_set_reference.argtypes = [P, d, d, P]
+    for name in ["oracle_dig_sampled", "oracle_get_mprev"]:
+        getattr(lib, name).argtypes = [P, P]
+    lib.oracle_dig_gradients.argtypes = [P, P, P]
+    lib.oracle_dig_nsf.argtypes = [P, P, P, P]
+    lib.oracle_dig_kn_cell.argtypes = [P, P, d, P]
+    lib.oracle_dig_gate.argtypes = [P, P, P, P, d, i, P]
+    lib.oracle_dig_solve.argtypes = [P, P, P, P, P]
+    lib.oracle_dig_residual.argtypes = [P, P, P, P]
+    lib.oracle_dig_feedback.argtypes = [P, P, P, P]
+    lib.oracle_dig_couple.argtypes = [P, P, P]
     _lib = lib
     return lib
+
+
+class DigParams(C.Structure):
+    _fields_ = [("kn_max", C.c_double), ("passes", C.c_int), ("n_m", C.c_int), ("eps_m", C.c_double),
+                ("cfl", C.c_double), ("L0", C.c_double), ("feedback", C.c_int), ("global_dt", C.c_int)]
+
+
+class DigReport(C.Structure):
+    _fields_ = [("iters", C.c_int), ("residual", C.c_double), ("converged", C.c_int), ("failed", C.c_int),
+                ("n_rejected", C.c_int), ("n_reconstructed", C.c_int), ("n_unreached", C.c_int),
+                ("np_before", C.c_int64), ("np_after", C.c_int64)]
+
+
+def dig_params(kn_max=1.0, passes=3, n_m=200, eps_m=1e-6, cfl=0.5, L0=1.0, feedback=1, global_dt=0):
+    return DigParams(kn_max, passes, n_m, eps_m, cfl, L0, feedback, global_dt)
+
+
+def _report_dict(r):
+    return {k: getattr(r, k) for k, _ in DigReport._fields_}
 
 
 def _p(a):
@@ -212,3 +242,67 @@ class Oracle:
         x = np.array(x, np.float64); v = np.array(v, np.float64)
         c = self.lib.oracle_trace_one(self.h, _p(x), _p(v), int(cell), pid, step, t)
         return c, x, v
+
+    # -- DIG coupling ------------------------------------------------------
+    def set_reference(self, n0, T0, u0=(0.0, 0.0, 0.0)):
+        u = np.asarray(u0, np.float64)
+        self.lib.oracle_set_reference(self.h, n0, T0, _p(u))
+
+    def dig_sampled(self):
+        o = np.zeros((self.nt, 14))
+        self.lib.oracle_dig_sampled(self.h, _p(o))
+        return o
+
+    def dig_gradients(self, prim):
+        prim = np.ascontiguousarray(prim, np.float64)
+        o = np.zeros((self.nt, 12))
+        self.lib.oracle_dig_gradients(self.h, _p(prim), _p(o))
+        return o
+
+    def dig_nsf(self, prim, grad):
+        prim = np.ascontiguousarray(prim, np.float64); grad = np.ascontiguousarray(grad, np.float64)
+        o = np.zeros((self.nt, 9))
+        self.lib.oracle_dig_nsf(self.h, _p(prim), _p(grad), _p(o))
+        return o
+
+    def dig_kn_cell(self, prim, L0=1.0):
+        prim = np.ascontiguousarray(prim, np.float64)
+        o = np.zeros(self.nt)
+        self.lib.oracle_dig_kn_cell(self.h, _p(prim), L0, _p(o))
+        return o
+
+    def dig_gate(self, prim, hot, kn, kn_max, passes):
+        prim = np.array(prim, np.float64, order="C"); hot = np.array(hot, np.float64, order="C")
+        kn = np.ascontiguousarray(kn, np.float64)
+        st = np.zeros(self.nt, np.int32)
+        self.lib.oracle_dig_gate(self.h, _p(prim), _p(hot), _p(kn), kn_max, passes, _p(st))
+        return prim, hot, st
+
+    def dig_solve(self, prim, hot, **kw):
+        prim = np.array(prim, np.float64, order="C"); hot = np.ascontiguousarray(hot, np.float64)
+        prm = dig_params(**kw)
+        rep = DigReport()
+        self.lib.oracle_dig_solve(self.h, _p(prim), _p(hot), C.byref(prm), C.byref(rep))
+        return prim, _report_dict(rep)
+
+    def dig_residual(self, prim, hot):
+        prim = np.ascontiguousarray(prim, np.float64); hot = np.ascontiguousarray(hot, np.float64)
+        o = np.zeros((self.nt, 5))
+        self.lib.oracle_dig_residual(self.h, _p(prim), _p(hot), _p(o))
+        return o
+
+    def dig_feedback(self, prim_old, prim_new, state):
+        a = np.ascontiguousarray(prim_old, np.float64); b = np.ascontiguousarray(prim_new, np.float64)
+        st = np.ascontiguousarray(state, np.int32)
+        self.lib.oracle_dig_feedback(self.h, _p(a), _p(b), _p(st))
+
+    def dig_couple(self, **kw):
+        prm = dig_params(**kw)
+        rep = DigReport()
+        self.lib.oracle_dig_couple(self.h, C.byref(prm), C.byref(rep))
+        return _report_dict(rep)
+
+    def mprev(self):
+        o = np.zeros((self.nt, 5))
+        self.lib.oracle_get_mprev(self.h, _p(o))
+        return o

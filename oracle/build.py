@@ -10,9 +10,9 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose=False):
-    src = os.path.join(HERE, "dsmc_oracle.c")
+    srcs = [os.path.join(HERE, f) for f in ("dsmc_oracle.c", "dig_oracle.c")]
     cmd = ["gcc", "-std=c11", "-D_GNU_SOURCE", "-O2", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", LIB + ".tmp", src, "-lm"]
+           "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", LIB + ".tmp", *srcs, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

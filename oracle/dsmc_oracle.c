@@ -20,60 +20,12 @@
  *    the design notes, so that an independent implementation can agree
  *    bit-for-bit on integer outcomes.
  */
-#include "oracle.h"
-
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
-#define KB 1.380649e-23
-#define TWO_PI 6.283185307179586
-#define SQRT_PI 1.7724538509055159
-#define INV_SQRT2 0.7071067811865476
-#define MAX_HOPS 1000
-#define NMOM 13
-
-enum { P_INIT = 1, P_WALL = 2, P_INJCOUNT = 3, P_NTCCOUNT = 4, P_PAIR = 5, P_SCATTER = 6,
-       P_INITCOUNT = 9, P_INJECT = 10 };
-
-struct osim {
-    /* species */
-    double m, dref, omega, Tref, K, ex;
-    /* run */
-    double FN, dt;
-    uint32_t seed, case_id;
-    int vel_fp32, n_ss, n_a, ewma_on;
-    /* mesh */
-    int nv, nt, nb, nf;
-    double* xyz;
-    int* tv;          /* [nt][4] reoriented */
-    double* vol;      /* [nt] */
-    int* tf_face;     /* [nt][4] face id */
-    double* tf_s;     /* [nt][4] +1 if the face normal points out of this tet */
-    int* tf_nbr;      /* [nt][4] neighbour tet, or -1-bface */
-    int* tf_nlf;      /* [nt][4] neighbour's local face index */
-    double* fn;       /* [nf][3] unnormalised face normal */
-    double* fd;       /* [nf] plane offset */
-    int* fvert;       /* [nf][3] sorted global vertex ids */
-    int* bf_tet; int* bf_lf; int* bf_group; int* bf_partner; int* bf_face;
-    double* bf_nin; double* bf_t1; double* bf_t2; double* bf_area;
-    /* groups */
-    int ng; int* g_kind; double* g_T; double* g_u; double* g_n; double* g_shift;
-    /* per inflow face */
-    double* in_mean; double* in_a; double* in_beta; double* in_sig; double* in_ut1; double* in_ut2;
-    /* particles, kept in (cell, pid) order after the sort stage */
-    int64_t np, cap;
-    double* x; double* v; int* cell; uint32_t* pid;
-    uint32_t next_pid, step;
-    /* per cell */
-    double* smax; int* ncand; int* nacc; int64_t* start;
-    double* acc; int64_t n_steady;
-    double* ewma; int* ewma_m; unsigned char* local_acc;
-    double* inst;
-    /* counters */
-    int64_t hops, walls, injected, removed, lost;
-};
+#include "oracle_internal.h"
 
 static char g_err[512];
 const char* oracle_last_error(void) { return g_err; }
@@ -171,7 +123,8 @@ void oracle_destroy(osim* s) {
                     s->bf_nin, s->bf_t1, s->bf_t2, s->bf_area, s->g_kind, s->g_T, s->g_u, s->g_n,
                     s->g_shift, s->in_mean, s->in_a, s->in_beta, s->in_sig, s->in_ut1, s->in_ut2,
                     s->x, s->v, s->cell, s->pid, s->smax, s->ncand, s->nacc, s->start, s->acc,
-                    s->ewma, s->ewma_m, s->local_acc, s->inst};
+                    s->ewma, s->ewma_m, s->local_acc, s->inst, s->cen, s->fcen, s->fnu, s->farea,
+                    s->lsq, s->mprev};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i) free(ptrs[i]);
     free(s);
 }
@@ -493,6 +446,8 @@ int oracle_init_fill(osim* s, double n0, double T0, const double* u0) {
     s->np = total;
     s->next_pid = (uint32_t)total;
     s->step = 0;
+    s->ref_n = n0; s->ref_T = T0;
+    for (int i = 0; i < 3; ++i) s->ref_u[i] = u0[i];
     /* (sigma c)_max = 2 <sigma_T c_r> at equilibrium T0 */
     double mr = s->m / 2.0;
     double eq = (((2.0 * SQRT_PI) * s->dref) * s->dref) * sqrt(((2.0 * KB) * s->Tref) / mr) *
@@ -888,3 +843,13 @@ void oracle_get_volumes(const osim* s, double* vol) { memcpy(vol, s->vol, sizeof
 void oracle_get_neighbours(const osim* s, int* nbr) { memcpy(nbr, s->tf_nbr, sizeof(int) * 4 * (size_t)s->nt); }
 void oracle_get_tets(const osim* s, int* tv) { memcpy(tv, s->tv, sizeof(int) * 4 * (size_t)s->nt); }
 int oracle_num_faces(const osim* s) { return s->nf; }
+
+void o_draw(const osim* s, uint32_t subject, uint32_t step, uint32_t purpose, uint64_t block, uint32_t out[4]) {
+    draw(s, subject, step, purpose, block, out);
+}
+double o_u01(uint32_t a, uint32_t b) { return u01(a, b); }
+uint32_t o_pick(uint32_t r, uint32_t n) { return pick(r, n); }
+double o_to_store(const osim* s, double x) { return to_store(s, x); }
+void o_sort(osim* s) { stage_sort(s); }
+void o_reserve(osim* s, int64_t need) { reserve(s, need); }
+void o_set_err(const char* m) { set_err(m); }

@@ -82,6 +82,59 @@ int oracle_num_faces(const osim*);
  * returns the final cell (-1 if deleted) and writes x, v. */
 int oracle_trace_one(osim*, double* x, double* v, int cell, uint32_t pid, uint32_t step, double t);
 
+/* ------------------------------------------------------------------ */
+/* DIG coupling (paper sections 2.2 and 3, Algorithm 1).               */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    double kn_max;  /* admissibility threshold on the cell Knudsen number */
+    int passes;     /* neighbour reconstruction passes */
+    int n_m;        /* maximum macroscopic iterations */
+    double eps_m;   /* relative residual tolerance */
+    double cfl;     /* pseudo-time CFL number */
+    double L0;      /* reference length of the Knudsen number */
+    int feedback;   /* 1: adjust the particles to the macroscopic solution */
+    int global_dt;  /* 1: one pseudo-time step for all cells (conservative) */
+} odig_params;
+
+typedef struct {
+    int iters;
+    double residual;   /* last relative density residual */
+    int converged;
+    int failed;        /* non-physical state: feedback skipped */
+    int n_rejected;    /* cells failing the admissibility criterion */
+    int n_reconstructed;
+    int n_unreached;
+    int64_t np_before, np_after;
+} odig_report;
+
+/* Reference state (n0, T0, u0) used by the admissibility criterion and as the
+ * initial macroscopic state; set by oracle_init_fill or explicitly. */
+void oracle_set_reference(osim*, double n0, double T0, const double* u0);
+
+/* Sampled macroscopic state of every cell from the moving-average sums:
+ * out[nt][14] = rho, u(3), T, sigma(6), q(3); NaN for cells without samples. */
+void oracle_dig_sampled(osim*, double* out);
+/* Least-squares gradients of u and T: grad[nt][12] = du_i/dx_j (row-major), dT/dx_j,
+ * from prim[nt][5] = rho, u(3), T. */
+void oracle_dig_gradients(osim*, const double* prim, double* grad);
+/* NSF stress and heat flux from prim and its gradients: out[nt][9]. */
+void oracle_dig_nsf(osim*, const double* prim, const double* grad, double* out);
+/* Cell Knudsen number Kn_Delta for prim: out[nt]. */
+void oracle_dig_kn_cell(osim*, const double* prim, double L0, double* out);
+/* Admissibility gate + reconstruction passes on (prim[nt][5], hot[nt][9]) in
+ * place; state[nt] out: 0 admissible, 1 reconstructed, 2 unreached (kept
+ * the previous macroscopic state, HoT = 0). */
+void oracle_dig_gate(osim*, double* prim, double* hot, const double* kn, double kn_max, int passes, int* state);
+/* Macroscopic synthetic solve from prim (in/out) with frozen hot. */
+int oracle_dig_solve(osim*, double* prim, const double* hot, const odig_params*, odig_report*);
+/* Residual of the discrete macroscopic equations at prim: out[nt][5]. */
+void oracle_dig_residual(osim*, const double* prim, const double* hot, double* out);
+/* Particle feedback from (prim_old -> prim_new) on cells with state <= 1. */
+void oracle_dig_feedback(osim*, const double* prim_old, const double* prim_new, const int* state);
+/* One outer coupling cycle after the DSMC steps of the window. */
+int oracle_dig_couple(osim*, const odig_params*, odig_report*);
+void oracle_get_mprev(const osim*, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,227 @@
+"""Pins of the oracle's DIG coupling pieces (sections 2.2 and 3, Algorithm 1):
+least-squares gradients exact on linear fields, the NSF relations on
+hand-built velocity and temperature gradients, the cell Knudsen number of
+eq. (cell_kn_stability) at the reference state, equal-weight multi-pass
+reconstruction against an independent breadth-first computation, the
+finite-volume residual at a uniform state, mass conservation, the continuum
+Couette profile, and the particle feedback map."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2607_08195_amd import workloads as W
+from oracle import Oracle, STAGE_SORT
+
+KB = 1.380649e-23
+
+
+def _centroids(wl, o):
+    return wl.mesh.xyz[o.tets()].mean(axis=1)
+
+
+def test_lsq_gradients_exact_for_linear_fields():
+    wl = W.cavity(n_hex=4, jitter=0.1, ppc=2, mesh_seed=3)
+    o = Oracle(wl, fill=False)
+    x = _centroids(wl, o)
+    rho = 1e-6 * (1 + 0.1 * x[:, 0])
+    U = np.array([[2.0, 3.0, -1.0], [0.5, -4.0, 2.0], [1.0, 1.0, 6.0]])
+    u = x @ U.T + 10.0
+    gT = np.array([5.0, -2.0, 7.0])
+    T = 300 + x @ gT
+    prim = np.column_stack([rho, u, T])
+    g = o.dig_gradients(prim)
+    interior = (o.neighbours() >= 0).all(axis=1)
+    assert interior.sum() > 20
+    assert np.allclose(g[interior, :9], np.tile(U.ravel(), (interior.sum(), 1)), rtol=0, atol=1e-10)
+    assert np.allclose(g[interior, 9:], np.tile(gT, (interior.sum(), 1)), rtol=0, atol=1e-9)
+
+
+def test_nsf_relations_by_hand():
+    wl = W.cavity(n_hex=1, ppc=2)
+    o = Oracle(wl, fill=False)
+    sp = wl.species
+    T = 350.0
+    mu = sp.mu(T)
+    kappa = 15.0 / 4.0 * KB / sp.mass * mu
+    prim = np.tile([1e-6, 0, 0, 0, T], (o.nt, 1))
+    grad = np.zeros((o.nt, 12))
+    gam = 120.0
+    grad[0, 1] = gam              # du_x/dy: pure shear
+    grad[1, 0], grad[1, 4] = 30.0, -30.0   # u = (e x, -e y, 0): planar extension
+    grad[2, 0] = grad[2, 4] = grad[2, 8] = 7.0   # isotropic expansion
+    grad[3, 9:] = [10.0, -20.0, 5.0]
+    out = o.dig_nsf(prim, grad)
+    assert np.allclose(out[0], [0, 0, 0, -mu * gam, 0, 0, 0, 0, 0], rtol=1e-13, atol=0)
+    assert np.allclose(out[1], [-2 * mu * 30, 2 * mu * 30, 0, 0, 0, 0, 0, 0, 0], rtol=1e-13, atol=1e-30)
+    assert np.allclose(out[2], 0, atol=1e-12 * mu * 7)
+    assert np.allclose(out[3, 6:], -kappa * np.array([10.0, -20.0, 5.0]), rtol=1e-13)
+
+
+@pytest.mark.parametrize("Kn", [0.01, 0.1, 1.0])
+def test_cell_knudsen_number_at_reference_state(Kn):
+    wl = W.cavity(n_hex=3, Kn=Kn, ppc=2, jitter=0.1)
+    o = Oracle(wl, fill=False)
+    o.set_reference(wl.run.n0, wl.run.T0)
+    prim = np.tile([wl.species.mass * wl.run.n0, 0, 0, 0, wl.run.T0], (o.nt, 1))
+    kn = o.dig_kn_cell(prim, L0=1.0)
+    dc = 2 * (3 * o.volumes() / (4 * math.pi)) ** (1 / 3)
+    assert np.allclose(kn, Kn / dc, rtol=1e-12)
+    # doubling the density halves the local mean free path
+    prim2 = prim.copy(); prim2[:, 0] *= 2
+    assert np.allclose(o.dig_kn_cell(prim2), kn / 2, rtol=1e-12)
+
+
+def _bfs_reconstruct(nbr, prim, hot, avail0, passes, mprev):
+    nt = len(prim)
+    prim = prim.copy(); hot = hot.copy()
+    avail = avail0.copy()
+    state = np.where(avail0, 0, 2)
+    for _ in range(passes):
+        new_avail = avail.copy()
+        newp, newh = {}, {}
+        for c in range(nt):
+            if avail[c]:
+                continue
+            ns = [n for n in nbr[c] if n >= 0 and avail[n]]
+            if ns:
+                newp[c] = prim[ns].mean(axis=0)
+                newh[c] = hot[ns].mean(axis=0)
+                new_avail[c] = True
+                state[c] = 1
+        for c in newp:
+            prim[c] = newp[c]; hot[c] = newh[c]
+        avail = new_avail
+    for c in range(nt):
+        if state[c] == 2:
+            prim[c] = mprev[c]; hot[c] = 0
+    return prim, hot, state
+
+
+@pytest.mark.parametrize("passes", [1, 2, 3])
+def test_reconstruction_layers_against_breadth_first(passes):
+    wl = W.kuhn_box(6, 1, 1, hi=(6.0, 1.0, 1.0))
+    work = W.cavity(n_hex=1, ppc=2)
+    work.mesh = wl
+    o = Oracle(work, fill=False)
+    o.set_reference(work.run.n0, work.run.T0)
+    x = _centroids(work, o)
+    rng = np.random.default_rng(1)
+    prim = np.column_stack([rng.uniform(1, 2, o.nt), rng.normal(size=(o.nt, 3)), rng.uniform(250, 300, o.nt)])
+    hot = rng.normal(size=(o.nt, 9))
+    kn = np.where(x[:, 0] > 2.0, 10.0, 0.1)
+    p, h, st = o.dig_gate(prim, hot, kn, 1.0, passes)
+    mprev = np.tile([work.species.mass * work.run.n0, 0, 0, 0, work.run.T0], (o.nt, 1))
+    ep, eh, est = _bfs_reconstruct(o.neighbours(), prim, hot, kn <= 1.0, passes, mprev)
+    assert np.array_equal(st, est)
+    assert (st == 1).any() and ((st == 2).any() or passes == 3)
+    assert np.allclose(p, ep, rtol=1e-14) and np.allclose(h, eh, rtol=1e-14)
+
+
+def _uniform(wl, o):
+    return np.tile([wl.species.mass * wl.run.n0, 0.0, 0.0, 0.0, wl.run.T0], (o.nt, 1))
+
+
+def test_fv_uniform_state_is_a_fixed_point():
+    wl = W.closed_box(n_hex=4, kind=W.BC_DIFFUSE)
+    wl.mesh = W.kuhn_box(4, 4, 4, jitter=0.1, seed=2)
+    o = Oracle(wl, fill=False)
+    o.set_reference(wl.run.n0, wl.run.T0)
+    prim = _uniform(wl, o)
+    R = o.dig_residual(prim, np.zeros((o.nt, 9)))
+    p0 = wl.run.n0 * KB * wl.run.T0
+    area = 1.0 / 16
+    assert np.abs(R[:, 0]).max() == 0.0
+    assert np.abs(R[:, 1:4]).max() <= 1e-13 * p0 * area
+    assert np.abs(R[:, 4]).max() == 0.0
+
+
+def test_fv_conserves_mass_with_a_global_step():
+    wl = W.closed_box(n_hex=4, kind=W.BC_DIFFUSE)
+    o = Oracle(wl, fill=False)
+    o.set_reference(wl.run.n0, wl.run.T0)
+    rng = np.random.default_rng(0)
+    prim = _uniform(wl, o)
+    prim[:, 0] *= 1 + 0.05 * rng.standard_normal(o.nt)
+    prim[:, 1:4] = 20 * rng.standard_normal((o.nt, 3))
+    vol = o.volumes()
+    m0 = (prim[:, 0] * vol).sum()
+    out, rep = o.dig_solve(prim, np.zeros((o.nt, 9)), n_m=60, eps_m=0.0, cfl=0.5, global_dt=1)
+    assert rep["iters"] == 60 and not rep["failed"]
+    assert abs((out[:, 0] * vol).sum() / m0 - 1) < 1e-12
+
+
+@pytest.mark.slow
+def test_fv_continuum_couette_profile():
+    U, Tw, H = 200.0, 273.0, 1.0
+    wl = W.plates(n=(2, 10, 2), U=U, T1=Tw, T2=Tw, n0=1e21, periodic=True)
+    o = Oracle(wl, fill=False)
+    o.set_reference(wl.run.n0, Tw)
+    prim = _uniform(wl, o)
+    out, rep = o.dig_solve(prim, np.zeros((o.nt, 9)), n_m=6000, eps_m=1e-10, cfl=1.5)
+    assert not rep["failed"] and rep["residual"] < 1e-3, rep
+    y = _centroids(wl, o)[:, 1]
+    assert np.allclose(out[:, 1], U * (y / H - 0.5), atol=0.01 * U)
+    assert np.allclose(out[:, 2:4], 0, atol=5e-3 * U)     # tet discretisation noise
+    sp = wl.species
+    mu = sp.mu(Tw)
+    kap = 15 / 4 * KB / sp.mass * mu
+    rise = mu * U * U / (2 * kap) * (y / H) * (1 - y / H)
+    assert np.allclose(out[:, 4] - Tw, rise, atol=0.2 * rise.max())
+
+
+def _one_cell(vel_fp32=0):
+    wl = W.closed_box(n_hex=1, kind=W.BC_SPECULAR, vel_fp32=vel_fp32)
+    o = Oracle(wl, fill=False)
+    o.set_reference(wl.run.n0, wl.run.T0)
+    return wl, o
+
+
+def test_feedback_identity_and_shift_scale():
+    wl, o = _one_cell()
+    rng = np.random.default_rng(5)
+    n = 40
+    v = rng.normal(size=(n, 3)) * 200 + [30, -10, 5]
+    xc = _centroids(wl, o)[0]
+    o.set_particles(np.tile(xc, (n, 1)), v, np.zeros(n, np.int32), np.arange(n, dtype=np.uint32), 7, n)
+    mean = v.mean(axis=0)
+    T = wl.species.mass * ((v - mean) ** 2).sum(axis=1).mean() / (3 * KB)
+    old = np.tile([1.0, *mean, T], (o.nt, 1))
+    state = np.zeros(o.nt, np.int32)
+    o.dig_feedback(old, old, state)
+    p = o.particles()
+    assert len(p["pid"]) == n
+    assert np.allclose(p["v"], v, rtol=0, atol=1e-12 * 300)
+    new = old.copy()
+    new[0, 1:4] = [-50.0, 20.0, 0.0]
+    new[0, 4] = 4 * T
+    new[0, 0] = 2.0      # twice the density: exactly twice the particles
+    o.dig_feedback(old, new, state)
+    p = o.particles()
+    assert len(p["pid"]) == 2 * n
+    orig = p["pid"] < n
+    vv = p["v"][orig]
+    assert np.allclose(vv.mean(axis=0), new[0, 1:4], atol=1e-9)
+    assert np.isclose(wl.species.mass * ((vv - vv.mean(0)) ** 2).sum(1).mean() / (3 * KB), 4 * T, rtol=1e-12)
+    assert sorted(p["pid"][~orig].tolist()) == list(range(n, 2 * n))
+    # clones lie inside the cell
+    xyz = wl.mesh.xyz[o.tets()[0]]
+    T3 = np.stack([xyz[1] - xyz[0], xyz[2] - xyz[0], xyz[3] - xyz[0]], axis=1)
+    lam = np.linalg.solve(T3, (p["x"][~orig] - xyz[0]).T).T
+    assert (lam >= -1e-12).all() and (lam.sum(1) <= 1 + 1e-12).all()
+    # half the density: exactly half the particles
+    newer = new.copy(); newer[0, 0] = 1.0
+    o.dig_feedback(new, newer, state)
+    assert o.np == n
+
+
+def test_couple_runs_on_the_small_cavity():
+    wl = W.cavity(n_hex=6, Kn=0.1, ppc=20, vel_fp32=0, ewma_on=1, n_a=50)
+    o = Oracle(wl)
+    o.step(50)
+    rep = o.dig_couple(kn_max=1.0, n_m=50)
+    assert not rep["failed"] and rep["iters"] == 50
+    assert rep["n_rejected"] < o.nt
+    m = o.mprev()
+    assert np.isfinite(m).all() and (m[:, 0] > 0).all() and (m[:, 4] > 0).all()
+    assert abs(o.np / rep["np_before"] - 1) < 0.02
