@@ -1,0 +1,117 @@
+/*
+ * dig.h — C ABI of the DIG coupling step on top of a dsmc_ctx.
+ *
+ * One outer cycle of the paper's Algorithm 1 (section 3): after a window of
+ * DSMC steps, the moving-average sums of every cell give the sampled
+ * low-order state M^{k+1/2} = (rho, u, T) (eq. sampled_macro_state_ch3) and
+ * the sampled stress and heat flux; the higher-order terms (HoT) are their
+ * difference from the NSF relations evaluated with that state and its
+ * gradients (eq. nsf_heat_flux, eq. hot_extraction_ch3).  Cells whose local
+ * Knudsen number (eq. cell_kn_stability) exceeds the threshold are rebuilt
+ * from admissible face neighbours over several passes and switch to local
+ * accumulation (section 3.2).  The macroscopic equations (eq. macro,
+ * monatomic) are then solved towards steady state with the HoT frozen
+ * (eq. hot_used_in_macro_solver_ch3), stopping at the relative residual
+ * eps_m or after n_m iterations, and the particles are adjusted to the new
+ * state M^{k+1} (Algorithm 1, feedback step).
+ *
+ * The paper leaves the finite-volume discretisation and the particle
+ * feedback map to other work; this library implements:
+ *  - cell-centred finite volumes on the tets with weighted least-squares
+ *    gradients (weights 1/|dx|^2 over face neighbours; a diffuse wall
+ *    contributes its velocity and temperature at the face centroid),
+ *    linear face reconstruction, a central inviscid flux with scalar
+ *    dissipation scaled by min(1, max(Mach, 0.05)), NSF viscous fluxes from
+ *    averaged gradients with a jump correction along the centroid connector
+ *    plus the face average of the frozen HoT, no-slip walls (wall HoT from
+ *    the adjacent cell), Dirichlet freestream at inflow faces and zero
+ *    gradient at outflow faces;
+ *  - explicit three-stage pseudo-time marching (stage weights 1/3, 1/2, 1)
+ *    with the local step cfl V / sum_f A (|u.n| + c + viscous rate);
+ *  - feedback per admissible or reconstructed cell: velocities shifted and
+ *    scaled, v' = u_new + sqrt(T_new / T_old) (v - u_old); particle count
+ *    scaled to floor(N rho_new / rho_old + U) by deleting particles chosen
+ *    one at a time among the remaining (pid order) or by cloning random
+ *    particles to uniform positions in the cell with new pids; re-sorted.
+ *
+ * Conventions are those of dsmc.h: status codes, SI units, host arrays in
+ * the caller's cell numbering ([n_tets][k] row-major), calls synchronise
+ * the context's stream.  Random numbers of the feedback use generator
+ * purpose 7 with the caller's cell id as subject and the current step.
+ */
+#ifndef DSMC_DIG_H
+#define DSMC_DIG_H
+
+#include "dsmc.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double kn_max;      /* admissibility threshold on Kn_Delta (eq. cell_kn_stability) */
+    int32_t passes;     /* neighbour reconstruction passes (section 3.2) */
+    int32_t n_m;        /* maximum macroscopic iterations (Algorithm 1) */
+    double eps_m;       /* relative residual tolerance of the macroscopic solve */
+    double cfl;         /* pseudo-time CFL number */
+    double L0;          /* reference length of the Knudsen number, m */
+    int32_t feedback;   /* 1: adjust the particles to M^{k+1} */
+    int32_t global_dt;  /* 1: one pseudo-time step for all cells */
+} dig_params;
+
+typedef struct {
+    int32_t iters;           /* completed macroscopic iterations */
+    double residual;         /* last density residual norm over the first one */
+    int32_t converged;       /* residual <= eps_m reached */
+    int32_t failed;          /* a non-physical state appeared: feedback skipped */
+    int32_t n_rejected;      /* cells failing the admissibility criterion */
+    int32_t n_reconstructed; /* rejected cells rebuilt from neighbours */
+    int32_t n_unreached;     /* rejected cells keeping M^k with zero HoT */
+    int64_t np_before, np_after;
+} dig_report;
+
+/* One coupling cycle (Algorithm 1) on the context's current moving-average
+ * sums and particles.  Skips the solve and the feedback when every cell is
+ * rejected or the solve fails (report says which).  Sets the local
+ * accumulation flags of rejected cells.  DSMC_E_CAPACITY if the clones of
+ * the feedback would overflow the particle store (state left unchanged). */
+dsmc_status dig_couple(dsmc_ctx ctx, const dig_params* params, dig_report* report);
+
+/* Per-cell arrays of the last dig_couple, in caller cell order:
+ *  DIG_OUT_SAMPLED [n][14] rho, u(3), T, sigma(6), q(3) of the moving average (NaN: no samples)
+ *  DIG_OUT_HALF    [n][5]  M^{k+1/2} after the gate and reconstruction
+ *  DIG_OUT_NEW     [n][5]  M^{k+1} from the macroscopic solve
+ *  DIG_OUT_HOT     [n][9]  frozen HoT (sigma xx,yy,zz,xy,xz,yz; q) after reconstruction
+ *  DIG_OUT_KN      [n]     Kn_Delta of the sampled state (inf: no samples)
+ *  DIG_OUT_STATE   [n]     int32: 0 admissible, 1 reconstructed, 2 unreached
+ *  DIG_OUT_MPREV   [n][5]  the state M^k kept for unreached cells */
+enum {
+    DIG_OUT_SAMPLED = 0, DIG_OUT_HALF = 1, DIG_OUT_NEW = 2, DIG_OUT_HOT = 3,
+    DIG_OUT_KN = 4, DIG_OUT_STATE = 5, DIG_OUT_MPREV = 6
+};
+dsmc_status dig_get(dsmc_ctx ctx, int32_t which, void* out);
+
+/* Residual of the discrete macroscopic equations (eq. macro with frozen
+ * HoT) at prim[n][5] = rho, u(3), T: out[n][5] = sum over the cell's faces
+ * of the numerical flux times the face area (mass, momentum, energy). */
+dsmc_status dig_residual(dsmc_ctx ctx, const double* prim, const double* hot, double* out);
+
+/* Macroscopic solve alone from prim[n][5] (in/out) with frozen hot[n][9];
+ * uses n_m, eps_m, cfl and global_dt of params. */
+dsmc_status dig_solve(dsmc_ctx ctx, double* prim, const double* hot, const dig_params* params,
+                      dig_report* report);
+
+/* Particle feedback alone: from prim_old[n][5] to prim_new[n][5] on cells
+ * with state[n] <= 1; re-sorts.  DSMC_E_CAPACITY as for dig_couple. */
+dsmc_status dig_feedback(dsmc_ctx ctx, const double* prim_old, const double* prim_new, const int32_t* state,
+                         int64_t* np_after);
+
+/* Replace the sums of an accumulator (DSMC_SAMPLE_STEADY or
+ * DSMC_SAMPLE_EWMA) by sums[n][13] (layout of dsmc_get_sums); restarts or
+ * checkpoints the moving average. */
+dsmc_status dsmc_set_sums(dsmc_ctx ctx, int32_t which, const double* sums);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSMC_DIG_H */

@@ -50,6 +50,7 @@ def _load():
     lib.oracle_num_steady.restype = i64
     lib.oracle_num_steady.argtypes = [P]
     lib.oracle_set_local_acc.argtypes = [P, P]
+    lib.oracle_set_sums.argtypes = [P, i, P]
     lib.oracle_fields.argtypes = [P, i, P]
     lib.oracle_get_volumes.argtypes = [P, P]
     lib.oracle_get_neighbours.argtypes = [P, P]
@@ -205,6 +206,11 @@ class Oracle:
         o = np.zeros((self.nt, 13))
         self.lib.oracle_get_sums(self.h, which, _p(o))
         return o
+
+    def set_sums(self, which, sums):
+        a = np.ascontiguousarray(sums, np.float64)
+        assert a.shape == (self.nt, 13)
+        self.lib.oracle_set_sums(self.h, which, _p(a))
 
     @property
     def n_steady(self):

@@ -799,6 +799,11 @@ void oracle_get_sums(const osim* s, int which, double* out) {
 
 int64_t oracle_num_steady(const osim* s) { return s->n_steady; }
 
+void oracle_set_sums(osim* s, int which, const double* in) {
+    double* dst = which == 0 ? s->acc : s->ewma;
+    memcpy(dst, in, sizeof(double) * NMOM * (size_t)s->nt);
+}
+
 void oracle_set_local_acc(osim* s, const unsigned char* flags) {
     memcpy(s->local_acc, flags, (size_t)s->nt);
 }

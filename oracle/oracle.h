@@ -68,6 +68,8 @@ void oracle_get_counters(const osim*, int64_t out[5]);
  * which: 0 steady accumulator (sum over sampled steps), 1 EWMA, 2 last step. */
 void oracle_get_sums(const osim*, int which, double* out);
 int64_t oracle_num_steady(const osim*);
+/* Replace the steady (0) or moving-average (1) sums [nt][13]. */
+void oracle_set_sums(osim*, int which, const double* in);
 void oracle_set_local_acc(osim*, const unsigned char* flags);
 /* fields [nt][15]: n, rho, u(3), T, sigma(xx,yy,zz,xy,xz,yz), q(3) */
 void oracle_fields(const osim*, int which, double* out);

@@ -12,8 +12,7 @@
 #include <vector>
 
 #include "../../include/dsmc.h"
-#include "kernels.h"
-#include "mesh.h"
+#include "context.h"
 
 using namespace dsmcx;
 
@@ -26,109 +25,16 @@ enum Slot {
 const char* kSlotNames[kNumSlots] = {"begin", "move", "move_walls", "inject", "scan", "sort_perm", "sort_gather",
                                      "collide_sample"};
 
-struct Buf {
-    double* x = nullptr;
-    double* y = nullptr;
-    double* z = nullptr;
-    void* vx = nullptr;
-    void* vy = nullptr;
-    void* vz = nullptr;
-    int32_t* cell = nullptr;
-    uint32_t* pid = nullptr;
-};
-
-template <class VT>
-PartDev<VT> as_dev(const Buf& b) {
-    return PartDev<VT>{b.x, b.y, b.z, (VT*)b.vx, (VT*)b.vy, (VT*)b.vz, b.cell, b.pid};
-}
-
 std::string g_global_error;
 
 }  // namespace
 
-struct dsmc_ctx_s {
-    hipStream_t stream = nullptr;
-    dsmc_allocator alloc{};
-    bool has_alloc = false;
-    std::vector<void*> owned;
-    std::string err;
-    bool broken = false;
-
-    HostMesh hm;
-    int nt = 0, nb = 0;
-    // species / run
-    double mass = 0, dref = 0, omega = 0, Tref = 0, K = 0, ex = 0;
-    double FN = 0, dt = 0, n0 = 0, T0 = 0, u0[3] = {0, 0, 0};
-    RngKey key{0, 0};
-    int vel64 = 0, n_ss = 0, n_a = 1000, ewma_on = 0;
-    int64_t cap = 0;
-    // device mesh
-    MeshDev mesh{};
-    double4* d_plane = nullptr;
-    int32_t* d_nbr = nullptr;
-    double* d_vol = nullptr;
-    int32_t* d_bf_group = nullptr;
-    int32_t* d_bf_pcode = nullptr;
-    double* d_bf_frame = nullptr;
-    GroupDev* d_groups = nullptr;
-    int4* d_tv = nullptr;
-    double* d_xyz = nullptr;
-    int32_t* d_orig = nullptr;      // internal cell -> caller's cell id
-    int32_t* d_cell_tmp = nullptr;  // [nt+1] scratch of the initial fill
-    // inflow
-    InflowDev inflow{};
-    int32_t* d_fcount = nullptr;
-    int32_t* d_foff = nullptr;
-    int64_t max_inject = 0;
-    // particles
-    Buf A, B;
-    uint32_t* d_rank = nullptr;
-    int32_t* d_perm = nullptr;
-    WallQueue wq{nullptr, nullptr, nullptr};
-    // cells
-    int32_t* d_counts = nullptr;
-    int32_t* d_offsets = nullptr;
-    int32_t* d_blocksums = nullptr;
-    double* d_smax = nullptr;
-    int32_t* d_ncand = nullptr;
-    int32_t* d_nacc = nullptr;
-    double* d_acc = nullptr;
-    double* d_ewma = nullptr;
-    int32_t* d_ewma_m = nullptr;
-    uint8_t* d_local = nullptr;
-    Scalars* d_sc = nullptr;
-    Counters* d_ctr = nullptr;
-    int32_t* d_counts_orig = nullptr;  // [nt] scratch of the initial fill
-    // tuning choices
-    int move_variant = kMoveDefer6;
-    int move_batch = 0;
-    int collide_variant = kCollideGlobal;
-    int sort_variant = kSortGather;
-    int32_t* d_sortperm = nullptr;
-    bool reorder = true;
-    // host view
-    int64_t np_bound = 0;
-    // profiling
-    bool profiling = false;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
-    std::vector<hipEvent_t> ev_pool;
-};
-
-namespace {
+namespace dsmcx {
 
 dsmc_status fail(dsmc_ctx c, dsmc_status s, const std::string& msg) {
     if (c) c->err = msg; else g_global_error = msg;
     return s;
 }
-
-#define HIP_TRY(ctx, call)                                                                     \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess) {                                                                \
-            if (ctx) (ctx)->broken = true;                                                     \
-            return fail(ctx, DSMC_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
-        }                                                                                      \
-    } while (0)
 
 void* dev_alloc(dsmc_ctx c, size_t bytes) {
     if (bytes == 0) bytes = 16;
@@ -142,11 +48,29 @@ void* dev_alloc(dsmc_ctx c, size_t bytes) {
     return p;
 }
 
-template <class T>
-bool alloc_n(dsmc_ctx c, T*& p, size_t n) {
-    p = (T*)dev_alloc(c, sizeof(T) * n);
-    return p != nullptr;
+void dev_free(dsmc_ctx c, void* p) {
+    if (!p) return;
+    auto it = std::find(c->owned.begin(), c->owned.end(), p);
+    if (it != c->owned.end()) c->owned.erase(it);
+    if (c->has_alloc) c->alloc.free(p, c->alloc.user); else hipFree(p);
 }
+
+dsmc_status sync_scalars(dsmc_ctx c, Scalars* out) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    Scalars s;
+    HIP_TRY(c, hipMemcpy(&s, c->d_sc, sizeof s, hipMemcpyDeviceToHost));
+    c->np_bound = s.np;
+    if (out) *out = s;
+    if (s.flags & kFlagCapacity) {
+        c->broken = true;
+        return fail(c, DSMC_E_CAPACITY, "particle store capacity exceeded");
+    }
+    return DSMC_OK;
+}
+
+}  // namespace dsmcx
+
+namespace {
 
 bool alloc_buf(dsmc_ctx c, Buf& b, int64_t cap, int vel64) {
     const size_t vs = vel64 ? sizeof(double) : sizeof(float);
@@ -184,20 +108,6 @@ struct Timed {
         }
     }
 };
-
-// the exact particle count and latched flags (synchronises)
-dsmc_status sync_scalars(dsmc_ctx c, Scalars* out) {
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    Scalars s;
-    HIP_TRY(c, hipMemcpy(&s, c->d_sc, sizeof s, hipMemcpyDeviceToHost));
-    c->np_bound = s.np;
-    if (out) *out = s;
-    if (s.flags & kFlagCapacity) {
-        c->broken = true;
-        return fail(c, DSMC_E_CAPACITY, "particle store capacity exceeded");
-    }
-    return DSMC_OK;
-}
 
 template <class VT>
 dsmc_status run_step(dsmc_ctx c, int mask) {
@@ -368,6 +278,7 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     for (int i = 0; i < 3; ++i) c->u0[i] = run->u0[i];
     c->key = RngKey{(uint32_t)(run->seed & 0xFFFFFFFFu), run->case_id};
     c->vel64 = run->vel_fp64 ? 1 : 0;
+    c->bcs.assign(bcs, bcs + n_bc);
     c->n_ss = run->n_ss; c->n_a = run->n_a; c->ewma_on = run->ewma_on ? 1 : 0;
 
     // expected particle count at n0 sizes the default capacity
@@ -573,11 +484,7 @@ dsmc_status dsmc_sample(dsmc_ctx c, int32_t which, double* out, int32_t out_on_d
         HIP_TRY(c, hipMemcpyAsync(out, tmp, sizeof(double) * 15 * (size_t)c->nt, hipMemcpyDeviceToHost, c->stream));
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (tmp) {
-        auto it = std::find(c->owned.begin(), c->owned.end(), (void*)tmp);
-        if (it != c->owned.end()) c->owned.erase(it);
-        if (c->has_alloc) c->alloc.free(tmp, c->alloc.user); else hipFree(tmp);
-    }
+    dev_free(c, tmp);
     return DSMC_OK;
 }
 
@@ -822,6 +729,7 @@ const char* dsmc_last_error(dsmc_ctx c) { return c ? c->err.c_str() : g_global_e
 void dsmc_destroy(dsmc_ctx c) {
     if (!c) return;
     hipStreamSynchronize(c->stream);
+    dsmcx::dig_release(c);
     for (auto& u : c->ev_used) {
         hipEventDestroy(u.second.first);
         hipEventDestroy(u.second.second);

@@ -1,0 +1,131 @@
+// Private definition of the library context shared by the C ABI sources.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/dsmc.h"
+#include "kernels.h"
+#include "mesh.h"
+
+namespace dsmcx {
+
+struct Buf {
+    double* x = nullptr;
+    double* y = nullptr;
+    double* z = nullptr;
+    void* vx = nullptr;
+    void* vy = nullptr;
+    void* vz = nullptr;
+    int32_t* cell = nullptr;
+    uint32_t* pid = nullptr;
+};
+
+template <class VT>
+PartDev<VT> as_dev(const Buf& b) {
+    return PartDev<VT>{b.x, b.y, b.z, (VT*)b.vx, (VT*)b.vy, (VT*)b.vz, b.cell, b.pid};
+}
+
+struct DigState;  // coupling state, owned by the context
+void dig_release(dsmc_ctx c);
+
+}  // namespace dsmcx
+
+struct dsmc_ctx_s {
+    hipStream_t stream = nullptr;
+    dsmc_allocator alloc{};
+    bool has_alloc = false;
+    std::vector<void*> owned;
+    std::string err;
+    bool broken = false;
+
+    dsmcx::HostMesh hm;
+    int nt = 0, nb = 0;
+    // species / run
+    double mass = 0, dref = 0, omega = 0, Tref = 0, K = 0, ex = 0;
+    double FN = 0, dt = 0, n0 = 0, T0 = 0, u0[3] = {0, 0, 0};
+    dsmcx::RngKey key{0, 0};
+    int vel64 = 0, n_ss = 0, n_a = 1000, ewma_on = 0;
+    int64_t cap = 0;
+    // device mesh
+    dsmcx::MeshDev mesh{};
+    double4* d_plane = nullptr;
+    int32_t* d_nbr = nullptr;
+    double* d_vol = nullptr;
+    int32_t* d_bf_group = nullptr;
+    int32_t* d_bf_pcode = nullptr;
+    double* d_bf_frame = nullptr;
+    dsmcx::GroupDev* d_groups = nullptr;
+    int4* d_tv = nullptr;
+    double* d_xyz = nullptr;
+    int32_t* d_orig = nullptr;      // internal cell -> caller's cell id
+    int32_t* d_cell_tmp = nullptr;  // [nt+1] scratch of the initial fill
+    // inflow
+    dsmcx::InflowDev inflow{};
+    int32_t* d_fcount = nullptr;
+    int32_t* d_foff = nullptr;
+    int64_t max_inject = 0;
+    // particles
+    dsmcx::Buf A, B;
+    uint32_t* d_rank = nullptr;
+    int32_t* d_perm = nullptr;
+    dsmcx::WallQueue wq{nullptr, nullptr, nullptr};
+    // cells
+    int32_t* d_counts = nullptr;
+    int32_t* d_offsets = nullptr;
+    int32_t* d_blocksums = nullptr;
+    double* d_smax = nullptr;
+    int32_t* d_ncand = nullptr;
+    int32_t* d_nacc = nullptr;
+    double* d_acc = nullptr;
+    double* d_ewma = nullptr;
+    int32_t* d_ewma_m = nullptr;
+    uint8_t* d_local = nullptr;
+    dsmcx::Scalars* d_sc = nullptr;
+    dsmcx::Counters* d_ctr = nullptr;
+    int32_t* d_counts_orig = nullptr;  // [nt] scratch of the initial fill
+    // tuning choices
+    int move_variant = dsmcx::kMoveDefer6;
+    int move_batch = 0;
+    int collide_variant = dsmcx::kCollideGlobal;
+    int sort_variant = dsmcx::kSortGather;
+    int32_t* d_sortperm = nullptr;
+    bool reorder = true;
+    // host view
+    int64_t np_bound = 0;
+    // profiling
+    bool profiling = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+    std::vector<hipEvent_t> ev_pool;
+    // boundary table (copied at init) and the coupling state, built on first use
+    std::vector<dsmc_boundary_desc> bcs;
+    dsmcx::DigState* dig = nullptr;
+};
+
+namespace dsmcx {
+
+dsmc_status fail(dsmc_ctx c, dsmc_status s, const std::string& msg);
+void* dev_alloc(dsmc_ctx c, size_t bytes);
+void dev_free(dsmc_ctx c, void* p);
+
+template <class T>
+bool alloc_n(dsmc_ctx c, T*& p, size_t n) {
+    p = (T*)dev_alloc(c, sizeof(T) * n);
+    return p != nullptr;
+}
+
+// Exact particle count and latched device flags (synchronises).
+dsmc_status sync_scalars(dsmc_ctx c, Scalars* out);
+
+}  // namespace dsmcx
+
+#define HIP_TRY(ctx, call)                                                                            \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ != hipSuccess) {                                                                       \
+            if (ctx) (ctx)->broken = true;                                                            \
+            return ::dsmcx::fail(ctx, DSMC_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+        }                                                                                             \
+    } while (0)

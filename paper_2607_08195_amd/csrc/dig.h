@@ -1,0 +1,93 @@
+// DIG coupling step on the device: sampled macroscopic state, least-squares
+// gradients, NSF relations and higher-order terms, admissibility gate with
+// reconstruction passes, finite-volume pseudo-time solve, particle feedback
+// (section 3, Algorithm 1).  All arrays use the internal cell numbering.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace dsmcx {
+
+constexpr int kDigNV = 5;        // primitive variables: rho, u(3), T
+constexpr int kDigThreads = 256;
+constexpr int kFbLanes = 64;     // one wave per cell in the feedback kernel
+
+// What lies behind a tet face: kind | (neighbour cell or boundary group) << 3.
+enum : int { kLinkInterior = 0, kLinkPeriodic = 1, kLinkWall = 2, kLinkSpecular = 3, kLinkInflow = 4, kLinkOutflow = 5 };
+
+struct DigGroup {
+    double T;
+    double u[3];
+    double rho;  // freestream mass density (inflow)
+};
+
+struct DigGeom {
+    int nt;
+    const double* cen;     // [nt][3] centroid
+    const double* fcen;    // [nt][4][3] face centroid
+    const double* fnu;     // [nt][4][3] outward unit normal
+    const double* farea;   // [nt][4]
+    const double* fdx;     // [nt][4][3] centroid -> neighbour centroid (periodic: shifted) or -> face centroid
+    const int32_t* flink;  // [nt][4]
+    const double* lsq;     // [nt][9] inverse of the weighted least-squares normal matrix
+    const double* vol;     // [nt]
+    const DigGroup* groups;
+    double mass, R, mu_ref, omega, T_ref;
+};
+
+struct DigCtl {
+    double res0, res, dtmin;
+    int conv, failed, iters;
+    int n_rejected, n_reconstructed, n_unreached;
+};
+
+struct DigWork {
+    double* samp;     // [nt][14] rho, u(3), T, sigma(6), q(3) of the moving average; NaN without samples
+    uint8_t* ok;      // [nt] cell has samples
+    double* prim;     // [nt][5] working state; M^{k+1} after the solve
+    double* half;     // [nt][5] M^{k+1/2} after the gate
+    double* hot;      // [nt][9]
+    double* grad;     // [nt][5][3] gradients of the primitives
+    double* kn;       // [nt]
+    uint8_t* avail;   // [nt]
+    uint8_t* navail;  // [nt]
+    double* nprim;    // [nt][5] reconstruction candidates of one pass
+    double* nhot;     // [nt][9]
+    int32_t* state;   // [nt] 0 admissible, 1 reconstructed, 2 unreached
+    double* mprev;    // [nt][5] M^k
+    double* Rs;       // [nt][5] residual
+    double* dt;       // [nt] pseudo-time step
+    double* U0;       // [nt][5] conserved state at the start of an iteration
+    double* stage;    // [nt][5] stage state
+    double* partial;  // [2 * blocks] reduction partials
+    DigCtl* ctl;
+    int32_t* fb_cnt;  // [nt] clones per cell, caller order
+    int32_t* fb_off;  // [nt + 1]
+    int32_t* fb_tgt;  // [nt] target count per internal cell
+};
+
+void launch_dig_sampled(hipStream_t s, const DigGeom& g, const double* ewma, double FN, DigWork w);
+void launch_dig_kn(hipStream_t s, const DigGeom& g, DigWork w, double kn_ref, double T0, double rho0, double L0);
+void launch_dig_gradients(hipStream_t s, const DigGeom& g, const double* prim, double* grad, const DigCtl* ctl);
+void launch_dig_hot(hipStream_t s, const DigGeom& g, DigWork w);
+void launch_dig_gate(hipStream_t s, const DigGeom& g, DigWork w, double kn_max, int passes);
+void launch_dig_ctl_reset(hipStream_t s, DigCtl* ctl);
+void launch_dig_copy(hipStream_t s, const double* src, double* dst, int64_t n);
+void launch_dig_residual(hipStream_t s, const DigGeom& g, const double* prim, const double* hot, const double* grad,
+                         double* Rs, DigWork w, int first, double cfl);
+void launch_dig_iteration(hipStream_t s, const DigGeom& g, DigWork w, double cfl, double eps_m, int global_dt,
+                          int it);
+void launch_dig_set_local(hipStream_t s, const int32_t* state, uint8_t* local, int nt);
+void launch_dig_fb_count(hipStream_t s, const DigGeom& g, DigWork w, const int32_t* offsets, const int32_t* orig,
+                         const Scalars* sc, RngKey key);
+template <class VT>
+void launch_dig_fb_apply(hipStream_t s, DigWork w, PartDev<VT> p, const int32_t* offsets, const int4* tv,
+                         const double* xyz, const int32_t* orig, const Scalars* sc, RngKey key, int32_t* scratch,
+                         uint32_t* bits, int nt, int64_t cap);
+void launch_dig_count_all(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
+                          int64_t bound);
+void launch_fill_u8(hipStream_t s, uint8_t* p, uint8_t v, int64_t n);
+
+}  // namespace dsmcx

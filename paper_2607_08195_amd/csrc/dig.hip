@@ -1,0 +1,835 @@
+// Kernels of the DIG coupling step (section 3, Algorithm 1).
+//
+//   k_dig_sampled   moving-average sums -> sampled (rho, u, T, sigma, q)
+//   k_dig_kn        local Knudsen number of eq. cell_kn_stability
+//   k_dig_grad      weighted least-squares gradients of the primitives
+//   k_dig_hot       NSF stress / heat flux and HoT = sampled - NSF
+//   k_dig_gate_*    admissibility gate and Jacobi reconstruction passes
+//   k_dig_save / k_dig_residual / k_dig_check / k_dig_update / k_dig_commit
+//                   one three-stage pseudo-time iteration of the
+//                   finite-volume macroscopic equations with frozen HoT
+//   k_dig_fb_*      particle feedback: target counts, shift-scale,
+//                   delete / clone
+//
+// One thread per cell except the feedback apply kernel (one wave per cell).
+// Per-cell arithmetic is written as a fixed sequence of IEEE binary64
+// operations (the library is built with contraction off).
+#include "dig.h"
+
+namespace dsmcx {
+
+namespace {
+
+constexpr double kGamma = 5.0 / 3.0;
+constexpr double kMachCut = 0.05;
+
+__device__ __forceinline__ bool stopped(const DigCtl* ctl) { return ctl != nullptr && (ctl->conv | ctl->failed); }
+
+__device__ __forceinline__ double mu_of(const DigGeom& g, double T) { return g.mu_ref * pow(T / g.T_ref, g.omega); }
+__device__ __forceinline__ double kappa_of(const DigGeom& g, double mu) {
+    return 15.0 * kBoltzmannDev * mu / (4.0 * g.mass);
+}
+
+// NSF stress (xx,yy,zz,xy,xz,yz) and Fourier heat flux (eq. nsf_heat_flux)
+// from gu[i][j] = du_i/dx_j and gT at temperature T.
+__device__ void nsf_local(const DigGeom& g, double T, const double* gu, const double* gT, double* out) {
+    const double mu = mu_of(g, T);
+    const double kap = kappa_of(g, mu);
+    const double div = gu[0] + gu[4] + gu[8];
+    const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double e = gu[3 * ii[k] + jj[k]] + gu[3 * jj[k] + ii[k]];
+        if (k < 3) e -= (2.0 / 3.0) * div;
+        out[k] = -mu * e;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) out[6 + j] = -kap * gT[j];
+}
+
+__device__ __forceinline__ void cons_of(const DigGeom& g, const double* P, double* U) {
+    const double uu = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
+    U[0] = P[0];
+    U[1] = P[0] * P[1];
+    U[2] = P[0] * P[2];
+    U[3] = P[0] * P[3];
+    U[4] = P[0] * (1.5 * g.R * P[4] + 0.5 * uu);
+}
+
+__device__ __forceinline__ bool prim_of(const DigGeom& g, const double* U, double* P) {
+    if (!(U[0] > 0)) return false;
+    P[0] = U[0];
+    P[1] = U[1] / U[0];
+    P[2] = U[2] / U[0];
+    P[3] = U[3] / U[0];
+    const double uu = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
+    P[4] = (U[4] / U[0] - 0.5 * uu) / (1.5 * g.R);
+    return P[4] > 0 && isfinite(P[4]);
+}
+
+// Inviscid flux F(P).n of the monatomic Euler part of eq. macro.
+__device__ __forceinline__ void flux_of(const DigGeom& g, const double* P, const double* n, double* F) {
+    const double un = P[1] * n[0] + P[2] * n[1] + P[3] * n[2];
+    const double p = P[0] * g.R * P[4];
+    const double uu = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
+    const double E = 1.5 * g.R * P[4] + 0.5 * uu;
+    F[0] = P[0] * un;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) F[1 + i] = P[0] * P[1 + i] * un + p * n[i];
+    F[4] = (P[0] * E + p) * un;
+}
+
+__device__ __forceinline__ double acoustic_speed(const DigGeom& g, const double* P, const double* n) {
+    return fabs(P[1] * n[0] + P[2] * n[1] + P[3] * n[2]) + sqrt(kGamma * g.R * P[4]);
+}
+
+// Dissipation speed |u.n| + theta c, theta = min(1, max(Mach, 0.05)).
+__device__ __forceinline__ double wave_speed(const DigGeom& g, const double* P, const double* n) {
+    const double c = sqrt(kGamma * g.R * P[4]);
+    const double un = fabs(P[1] * n[0] + P[2] * n[1] + P[3] * n[2]);
+    const double u = sqrt(P[1] * P[1] + P[2] * P[2] + P[3] * P[3]);
+    double th = u / c;
+    if (th < kMachCut) th = kMachCut;
+    if (th > 1.0) th = 1.0;
+    return un + th * c;
+}
+
+// Central flux with scalar dissipation between states L and R.
+__device__ __forceinline__ void central_flux(const DigGeom& g, const double* PL, const double* PR, const double* n,
+                                             double* F, double& lam) {
+    double FL[kDigNV], FR[kDigNV], UL[kDigNV], UR[kDigNV];
+    flux_of(g, PL, n, FL);
+    flux_of(g, PR, n, FR);
+    cons_of(g, PL, UL);
+    cons_of(g, PR, UR);
+    const double aL = wave_speed(g, PL, n), aR = wave_speed(g, PR, n);
+    const double lam_d = aL > aR ? aL : aR;
+#pragma unroll
+    for (int v = 0; v < kDigNV; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam_d * (UR[v] - UL[v]);
+    const double sL = acoustic_speed(g, PL, n), sR = acoustic_speed(g, PR, n);
+    lam = sL > sR ? sL : sR;
+}
+
+// Face gradients of u and T: base gradients plus the correction that makes
+// their component along the connector dx equal the difference quotient.
+__device__ __forceinline__ void face_gradients(const double* gbase, const double* far, const double* near,
+                                               const double* dx, double dl, double* gu, double* gT) {
+#pragma unroll
+    for (int v = 1; v < kDigNV; ++v) {
+        double gf[3], ga = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            gf[j] = gbase[3 * v + j];
+            ga += gf[j] * dx[j] / dl;
+        }
+        const double jump = (far[v] - near[v]) / dl - ga;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gf[j] += jump * dx[j] / dl;
+        if (v < 4) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) gu[3 * (v - 1) + j] = gf[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) gT[j] = gf[j];
+        }
+    }
+}
+
+// Momentum and energy parts of the viscous flux: (sigma + q).n with the
+// face velocity uf doing work.
+__device__ __forceinline__ void add_viscous(const double* vis, const double* n, const double* uf, double* F) {
+    const double S[3][3] = {{vis[0], vis[3], vis[4]}, {vis[3], vis[1], vis[5]}, {vis[4], vis[5], vis[2]}};
+    double work = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double sn = S[i][0] * n[0] + S[i][1] * n[1] + S[i][2] * n[2];
+        F[1 + i] += sn;
+        work += sn * uf[i];
+    }
+    F[4] += work + (vis[6] * n[0] + vis[7] * n[1] + vis[8] * n[2]);
+}
+
+__device__ __forceinline__ double viscous_rate(const DigGeom& g, double T, double rho, double dl) {
+    const double mu = mu_of(g, T);
+    const double dmom = 4.0 * mu / (3.0 * rho), dth = kappa_of(g, mu) / (1.5 * rho * g.R);
+    return 2.0 * (dmom > dth ? dmom : dth) / dl;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ void block_sum_min(double s, double m, double* out_s, double* out_m) {
+    __shared__ double ss[kDigThreads], sm[kDigThreads];
+    const int t = threadIdx.x;
+    ss[t] = s;
+    sm[t] = m;
+    __syncthreads();
+    for (int o = kDigThreads / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            ss[t] += ss[t + o];
+            sm[t] = fmin(sm[t], sm[t + o]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        *out_s = ss[0];
+        *out_m = sm[0];
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// sampled state (eq. sampled_macro_state_ch3 with the cell formulas of
+// eq. dsmc_temperatures applied to the moving-average sums)
+// ---------------------------------------------------------------------------
+__global__ void k_dig_sampled(DigGeom g, const double* ewma, double FN, DigWork w) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt) return;
+    const int nt = g.nt;
+    double S[kNMom];
+#pragma unroll
+    for (int k = 0; k < kNMom; ++k) S[k] = ewma[(int64_t)k * nt + c];
+    double* o = w.samp + 14 * (size_t)c;
+    double* P = w.prim + kDigNV * (size_t)c;
+    if (!(S[0] > 0)) {
+        for (int k = 0; k < 14; ++k) o[k] = __builtin_nan("");
+        for (int v = 0; v < kDigNV; ++v) P[v] = w.mprev[kDigNV * (size_t)c + v];
+        w.ok[c] = 0;
+        return;
+    }
+    const double n = (FN * (S[0] / 1.0)) / g.vol[c];
+    const double rho = g.mass * n;
+    const double u0 = S[1] / S[0], u1 = S[2] / S[0], u2 = S[3] / S[0];
+    const double Cxx = S[4] / S[0] - u0 * u0, Cyy = S[5] / S[0] - u1 * u1, Czz = S[6] / S[0] - u2 * u2;
+    const double Cxy = S[7] / S[0] - u0 * u1, Cxz = S[8] / S[0] - u0 * u2, Cyz = S[9] / S[0] - u1 * u2;
+    const double Ckk = Cxx + Cyy + Czz;
+    const double T = (g.mass * Ckk) / (3.0 * kBoltzmannDev);
+    o[0] = rho; o[1] = u0; o[2] = u1; o[3] = u2; o[4] = T;
+    o[5] = rho * (Cxx - Ckk / 3.0);
+    o[6] = rho * (Cyy - Ckk / 3.0);
+    o[7] = rho * (Czz - Ckk / 3.0);
+    o[8] = rho * Cxy;
+    o[9] = rho * Cxz;
+    o[10] = rho * Cyz;
+    const double S2kk = S[4] + S[5] + S[6];
+    const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+    const double uS0 = u0 * S[4] + u1 * S[7] + u2 * S[8];
+    const double uS1 = u0 * S[7] + u1 * S[5] + u2 * S[9];
+    const double uS2 = u0 * S[8] + u1 * S[9] + u2 * S[6];
+    o[11] = (rho / 2.0) * (((S[10] - 2.0 * uS0) - u0 * S2kk) + 2.0 * S[0] * u0 * uu) / S[0];
+    o[12] = (rho / 2.0) * (((S[11] - 2.0 * uS1) - u1 * S2kk) + 2.0 * S[0] * u1 * uu) / S[0];
+    o[13] = (rho / 2.0) * (((S[12] - 2.0 * uS2) - u2 * S2kk) + 2.0 * S[0] * u2 * uu) / S[0];
+    const bool ok = isfinite(rho) && rho > 0;
+    for (int v = 0; v < kDigNV; ++v) P[v] = ok ? o[v] : w.mprev[kDigNV * (size_t)c + v];
+    w.ok[c] = ok ? 1 : 0;
+}
+
+// Kn_Delta = (Kn (T/T0)^(omega-1/2) / (rho/rho0)) / (d_c / L0), d_c = 2 (3V/4pi)^(1/3)
+// (eq. cell_kn_stability); infinite for cells without samples.
+__global__ void k_dig_kn(DigGeom g, DigWork w, double kn_ref, double T0, double rho0, double L0) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt) return;
+    const double rho = w.prim[kDigNV * (size_t)c], T = w.prim[kDigNV * (size_t)c + 4];
+    const double lam = kn_ref * pow(T / T0, g.omega - 0.5) / (rho / rho0);
+    const double dc = 2.0 * cbrt(3.0 * g.vol[c] / (4.0 * M_PI)) / L0;
+    const double k = lam / dc;
+    const bool fin = rho > 0 && T > 0 && isfinite(k);
+    w.kn[c] = (w.ok[c] && fin) ? k : __builtin_inf();
+}
+
+// Weighted least squares over face neighbours: a diffuse wall contributes
+// its velocity and temperature (and the cell's own density) at the face
+// centroid; specular, inflow and outflow faces contribute nothing.
+__global__ void k_dig_grad(DigGeom g, const double* prim, double* grad, const DigCtl* ctl) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt || stopped(ctl)) return;
+    double pc[kDigNV];
+#pragma unroll
+    for (int v = 0; v < kDigNV; ++v) pc[v] = prim[kDigNV * (size_t)c + v];
+    double b[kDigNV][3];
+#pragma unroll
+    for (int v = 0; v < kDigNV; ++v) b[v][0] = b[v][1] = b[v][2] = 0.0;
+    for (int f = 0; f < 4; ++f) {
+        const int link = g.flink[4 * c + f];
+        const int kind = link & 7, idx = link >> 3;
+        double far[kDigNV];
+        if (kind == kLinkInterior || kind == kLinkPeriodic) {
+#pragma unroll
+            for (int v = 0; v < kDigNV; ++v) far[v] = prim[kDigNV * (size_t)idx + v];
+        } else if (kind == kLinkWall) {
+            const DigGroup& gr = g.groups[idx];
+            far[0] = pc[0];
+            far[1] = gr.u[0]; far[2] = gr.u[1]; far[3] = gr.u[2];
+            far[4] = gr.T;
+        } else {
+            continue;
+        }
+        const double* dx = g.fdx + 12 * (size_t)c + 3 * f;
+        const double d0 = dx[0], d1 = dx[1], d2 = dx[2];
+        const double wgt = 1.0 / (d0 * d0 + d1 * d1 + d2 * d2);
+#pragma unroll
+        for (int v = 0; v < kDigNV; ++v) {
+            const double dphi = far[v] - pc[v];
+            b[v][0] += wgt * d0 * dphi;
+            b[v][1] += wgt * d1 * dphi;
+            b[v][2] += wgt * d2 * dphi;
+        }
+    }
+    const double* L = g.lsq + 9 * (size_t)c;
+    double* o = grad + 15 * (size_t)c;
+#pragma unroll
+    for (int v = 0; v < kDigNV; ++v)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) o[3 * v + i] = L[3 * i] * b[v][0] + L[3 * i + 1] * b[v][1] + L[3 * i + 2] * b[v][2];
+}
+
+// HoT = (sigma, q)_sampled - (sigma, q)_NSF at the sampled state
+// (eq. hot_extraction_ch3); zero for cells without samples.
+__global__ void k_dig_hot(DigGeom g, DigWork w) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt) return;
+    const double* gr = w.grad + 15 * (size_t)c;
+    double nsf[9];
+    nsf_local(g, w.prim[kDigNV * (size_t)c + 4], gr + 3, gr + 12, nsf);
+    const bool ok = w.ok[c];
+    const double* a = w.samp + 14 * (size_t)c;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w.hot[9 * (size_t)c + k] = ok ? a[5 + k] - nsf[k] : 0.0;
+}
+
+// Admissibility (criterion on Kn_Delta) and availability of every cell.
+__global__ void k_dig_gate_init(DigGeom g, DigWork w, double kn_max) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt) return;
+    bool ok = w.kn[c] <= kn_max;
+    for (int v = 0; v < kDigNV && ok; ++v) ok = isfinite(w.prim[kDigNV * (size_t)c + v]);
+    w.avail[c] = ok ? 1 : 0;
+    w.navail[c] = ok ? 1 : 0;
+    w.state[c] = ok ? 0 : 2;
+}
+
+// One reconstruction pass: every unavailable cell with available face
+// neighbours takes their equal-weight mean of M and HoT.  Results become
+// visible to neighbours only in the next pass (k_dig_gate_commit).
+__global__ void k_dig_gate_pass(DigGeom g, DigWork w) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt || w.avail[c]) return;
+    int cnt = 0;
+    double sp[kDigNV] = {0, 0, 0, 0, 0}, sh[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int f = 0; f < 4; ++f) {
+        const int link = g.flink[4 * c + f];
+        const int kind = link & 7, nb = link >> 3;
+        if ((kind != kLinkInterior && kind != kLinkPeriodic) || !w.avail[nb]) continue;
+        ++cnt;
+#pragma unroll
+        for (int v = 0; v < kDigNV; ++v) sp[v] += w.prim[kDigNV * (size_t)nb + v];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) sh[v] += w.hot[9 * (size_t)nb + v];
+    }
+    if (!cnt) return;
+#pragma unroll
+    for (int v = 0; v < kDigNV; ++v) w.nprim[kDigNV * (size_t)c + v] = sp[v] / cnt;
+#pragma unroll
+    for (int v = 0; v < 9; ++v) w.nhot[9 * (size_t)c + v] = sh[v] / cnt;
+    w.navail[c] = 1;
+    w.state[c] = 1;
+}
+
+__global__ void k_dig_gate_commit(DigGeom g, DigWork w) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt) return;
+    if (w.navail[c] && !w.avail[c]) {
+        for (int v = 0; v < kDigNV; ++v) w.prim[kDigNV * (size_t)c + v] = w.nprim[kDigNV * (size_t)c + v];
+        for (int v = 0; v < 9; ++v) w.hot[9 * (size_t)c + v] = w.nhot[9 * (size_t)c + v];
+        w.avail[c] = 1;
+    }
+}
+
+// Unreached cells keep M^k with zero HoT; counts of the report.
+__global__ void k_dig_gate_final(DigGeom g, DigWork w) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    int rej = 0, rec = 0, unr = 0;
+    if (c < g.nt) {
+        const int st = w.state[c];
+        rej = st != 0;
+        rec = st == 1;
+        unr = st == 2;
+        if (st == 2) {
+            for (int v = 0; v < kDigNV; ++v) w.prim[kDigNV * (size_t)c + v] = w.mprev[kDigNV * (size_t)c + v];
+            for (int v = 0; v < 9; ++v) w.hot[9 * (size_t)c + v] = 0.0;
+        }
+    }
+    rej = wave_sum_i(rej);
+    rec = wave_sum_i(rec);
+    unr = wave_sum_i(unr);
+    if ((threadIdx.x & 63) == 0) {
+        if (rej) atomicAdd(&w.ctl->n_rejected, rej);
+        if (rec) atomicAdd(&w.ctl->n_reconstructed, rec);
+        if (unr) atomicAdd(&w.ctl->n_unreached, unr);
+    }
+}
+
+__global__ void k_dig_ctl_reset(DigCtl* ctl) {
+    ctl->res0 = 0.0;
+    ctl->res = 0.0;
+    ctl->dtmin = 0.0;
+    ctl->conv = 0;
+    ctl->failed = 0;
+    ctl->iters = 0;
+    ctl->n_rejected = 0;
+    ctl->n_reconstructed = 0;
+    ctl->n_unreached = 0;
+}
+
+__global__ void k_dig_copy(const double* src, double* dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// finite-volume residual: R_c = sum_f (F_inviscid + F_viscous).n A_f
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kDigThreads) void k_dig_residual(DigGeom g, const double* prim, const double* hot,
+                                                              const double* grad, double* Rs, DigWork w, int first,
+                                                              double cfl) {
+    if (stopped(w.ctl)) return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double r2 = 0.0, dtc = __builtin_inf();
+    if (c < g.nt) {
+        double Pc[kDigNV], gc[15], hc[9];
+#pragma unroll
+        for (int v = 0; v < kDigNV; ++v) Pc[v] = prim[kDigNV * (size_t)c + v];
+#pragma unroll
+        for (int k = 0; k < 15; ++k) gc[k] = grad[15 * (size_t)c + k];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) hc[k] = hot[9 * (size_t)c + k];
+        const double xc[3] = {g.cen[3 * (size_t)c], g.cen[3 * (size_t)c + 1], g.cen[3 * (size_t)c + 2]};
+        double Rc[kDigNV] = {0, 0, 0, 0, 0};
+        double sp = 0.0;
+        for (int f = 0; f < 4; ++f) {
+            const int link = g.flink[4 * c + f];
+            const int kind = link & 7, idx = link >> 3;
+            const size_t fo = 12 * (size_t)c + 3 * f;
+            const double n[3] = {g.fnu[fo], g.fnu[fo + 1], g.fnu[fo + 2]};
+            const double dx[3] = {g.fdx[fo], g.fdx[fo + 1], g.fdx[fo + 2]};
+            const double A = g.farea[4 * (size_t)c + f];
+            double F[kDigNV] = {0, 0, 0, 0, 0};
+            double lam = 0.0, lamv = 0.0;
+            if (kind == kLinkInterior || kind == kLinkPeriodic) {
+                const int nb = idx;
+                double Pn[kDigNV], gn[15];
+#pragma unroll
+                for (int v = 0; v < kDigNV; ++v) Pn[v] = prim[kDigNV * (size_t)nb + v];
+#pragma unroll
+                for (int k = 0; k < 15; ++k) gn[k] = grad[15 * (size_t)nb + k];
+                const double xf[3] = {g.fcen[fo], g.fcen[fo + 1], g.fcen[fo + 2]};
+                double rc[3], rn[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    rc[i] = xf[i] - xc[i];
+                    rn[i] = xf[i] - (xc[i] + dx[i]);
+                }
+                double PL[kDigNV], PR[kDigNV];
+#pragma unroll
+                for (int v = 0; v < kDigNV; ++v) {
+                    PL[v] = Pc[v] + (gc[3 * v] * rc[0] + gc[3 * v + 1] * rc[1] + gc[3 * v + 2] * rc[2]);
+                    PR[v] = Pn[v] + (gn[3 * v] * rn[0] + gn[3 * v + 1] * rn[1] + gn[3 * v + 2] * rn[2]);
+                }
+                if (!(PL[0] > 0 && PL[4] > 0 && PR[0] > 0 && PR[4] > 0)) {
+#pragma unroll
+                    for (int v = 0; v < kDigNV; ++v) {
+                        PL[v] = Pc[v];
+                        PR[v] = Pn[v];
+                    }
+                }
+                central_flux(g, PL, PR, n, F, lam);
+                const double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
+                const double dl = sqrt(d2);
+                double gavg[15];
+#pragma unroll
+                for (int k = 3; k < 15; ++k) gavg[k] = 0.5 * (gc[k] + gn[k]);
+                double gu[9], gT[3];
+                face_gradients(gavg, Pn, Pc, dx, dl, gu, gT);
+                const double Tf = 0.5 * (Pc[4] + Pn[4]);
+                const double rf = 0.5 * (Pc[0] + Pn[0]);
+                double vis[9];
+                nsf_local(g, Tf, gu, gT, vis);
+                const double* hn = hot + 9 * (size_t)nb;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) vis[k] += 0.5 * (hc[k] + hn[k]);
+                const double uf[3] = {0.5 * (Pc[1] + Pn[1]), 0.5 * (Pc[2] + Pn[2]), 0.5 * (Pc[3] + Pn[3])};
+                add_viscous(vis, n, uf, F);
+                lamv = viscous_rate(g, Tf, rf, dl);
+            } else if (kind == kLinkWall || kind == kLinkSpecular) {
+                const double p = Pc[0] * g.R * Pc[4];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) F[1 + i] = p * n[i];
+                lam = acoustic_speed(g, Pc, n);
+                if (kind == kLinkWall) {
+                    const DigGroup& gr = g.groups[idx];
+                    const double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
+                    const double dl = sqrt(d2);
+                    const double wallv[kDigNV] = {Pc[0], gr.u[0], gr.u[1], gr.u[2], gr.T};
+                    double gu[9], gT[3];
+                    face_gradients(gc, wallv, Pc, dx, dl, gu, gT);
+                    double vis[9];
+                    nsf_local(g, gr.T, gu, gT, vis);
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) vis[k] += hc[k];
+                    add_viscous(vis, n, gr.u, F);
+                    lamv = viscous_rate(g, gr.T, Pc[0], dl);
+                }
+            } else if (kind == kLinkInflow) {
+                const DigGroup& gr = g.groups[idx];
+                const double PR[kDigNV] = {gr.rho, gr.u[0], gr.u[1], gr.u[2], gr.T};
+                central_flux(g, Pc, PR, n, F, lam);
+            } else {
+                flux_of(g, Pc, n, F);
+                lam = acoustic_speed(g, Pc, n);
+            }
+#pragma unroll
+            for (int v = 0; v < kDigNV; ++v) Rc[v] += F[v] * A;
+            sp += (lam + lamv) * A;
+        }
+#pragma unroll
+        for (int v = 0; v < kDigNV; ++v) Rs[kDigNV * (size_t)c + v] = Rc[v];
+        if (first) {
+            dtc = cfl * g.vol[c] / sp;
+            w.dt[c] = dtc;
+            r2 = Rc[0] * Rc[0];
+        }
+    }
+    if (first) block_sum_min(r2, dtc, &w.partial[2 * blockIdx.x], &w.partial[2 * blockIdx.x + 1]);
+}
+
+// Density residual norm, first-iteration reference, convergence test and
+// the smallest local step (single workgroup).
+__global__ __launch_bounds__(kDigThreads) void k_dig_check(DigWork w, int nblk, int it, double eps_m) {
+    if (stopped(w.ctl)) return;
+    double s = 0.0, m = __builtin_inf();
+    for (int b = threadIdx.x; b < nblk; b += kDigThreads) {
+        s += w.partial[2 * b];
+        m = fmin(m, w.partial[2 * b + 1]);
+    }
+    __shared__ double tot, mn;
+    block_sum_min(s, m, &tot, &mn);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DigCtl* ctl = w.ctl;
+        const double res = sqrt(tot);
+        ctl->res = res;
+        if (it == 0) ctl->res0 = res;
+        const double res0 = ctl->res0;
+        if (!(res0 > 0) || res <= eps_m * res0) ctl->conv = 1;
+        ctl->dtmin = mn;
+    }
+}
+
+__global__ void k_dig_save(DigGeom g, DigWork w) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt || stopped(w.ctl)) return;
+    double P[kDigNV], U[kDigNV];
+#pragma unroll
+    for (int v = 0; v < kDigNV; ++v) {
+        P[v] = w.prim[kDigNV * (size_t)c + v];
+        w.stage[kDigNV * (size_t)c + v] = P[v];
+    }
+    cons_of(g, P, U);
+#pragma unroll
+    for (int v = 0; v < kDigNV; ++v) w.U0[kDigNV * (size_t)c + v] = U[v];
+}
+
+// Stage update U = U0 - alpha dt / V R(stage).
+__global__ void k_dig_update(DigGeom g, DigWork w, double alpha, int global_dt) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt || stopped(w.ctl)) return;
+    const double dtc = global_dt ? w.ctl->dtmin : w.dt[c];
+    double U[kDigNV];
+#pragma unroll
+    for (int v = 0; v < kDigNV; ++v)
+        U[v] = w.U0[kDigNV * (size_t)c + v] - alpha * dtc / g.vol[c] * w.Rs[kDigNV * (size_t)c + v];
+    double P[kDigNV];
+    if (prim_of(g, U, P)) {
+#pragma unroll
+        for (int v = 0; v < kDigNV; ++v) w.stage[kDigNV * (size_t)c + v] = P[v];
+    } else {
+        if (U[0] > 0) {
+#pragma unroll
+            for (int v = 0; v < kDigNV; ++v) w.stage[kDigNV * (size_t)c + v] = P[v];
+        }
+        atomicOr(&w.ctl->failed, 1);
+    }
+}
+
+__global__ void k_dig_commit(DigGeom g, DigWork w) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt || stopped(w.ctl)) return;
+#pragma unroll
+    for (int v = 0; v < kDigNV; ++v) w.prim[kDigNV * (size_t)c + v] = w.stage[kDigNV * (size_t)c + v];
+    if (c == 0) w.ctl->iters += 1;
+}
+
+__global__ void k_dig_set_local(const int32_t* state, uint8_t* local, int nt) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nt) local[c] = state[c] != 0 ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// particle feedback (Algorithm 1: particles adjusted to M^{k+1})
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool fb_valid(const double* a, const double* b) {
+    return a[0] > 0 && b[0] > 0 && a[4] > 0 && b[4] > 0;
+}
+
+// Target count floor(N rho_new / rho_old + U) of each cell; clone counts
+// in the caller's cell order (new pids follow that order).
+__global__ void k_dig_fb_count(DigGeom g, DigWork w, const int32_t* offsets, const int32_t* orig, const Scalars* sc,
+                               RngKey key) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt) return;
+    const int N = offsets[c + 1] - offsets[c];
+    int T = N;
+    const double* a = w.half + kDigNV * (size_t)c;
+    const double* b = w.prim + kDigNV * (size_t)c;
+    if (w.state[c] <= 1 && N > 0 && fb_valid(a, b)) {
+        const Rand4 r = draw(key, (uint32_t)orig[c], sc->step, kPurposeRecalibrate, 0);
+        double t = floor((double)N * (b[0] / a[0]) + u01(r.w[0], r.w[1]));
+        if (!(t < 1073741824.0)) t = 1073741824.0;
+        T = (int)t;
+    }
+    w.fb_tgt[c] = T;
+    w.fb_cnt[orig[c]] = T > N ? T - N : 0;
+}
+
+// One wave per cell: shift-scale the velocities, rank the particles by pid,
+// then delete (one at a time among the remaining, in pid order) or clone.
+template <class VT>
+__global__ __launch_bounds__(kFbLanes) void k_dig_fb_apply(DigWork w, PartDev<VT> p, const int32_t* offsets,
+                                                           const int4* tv, const double* xyz, const int32_t* orig,
+                                                           const Scalars* sc, RngKey key, int32_t* scratch,
+                                                           uint32_t* bits, int64_t cap) {
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t a0 = offsets[c];
+    const int N = offsets[c + 1] - (int)a0;
+    const double* a = w.half + kDigNV * (size_t)c;
+    const double* b = w.prim + kDigNV * (size_t)c;
+    if (w.state[c] > 1 || N == 0 || !fb_valid(a, b)) return;
+    const double scale = sqrt(b[4] / a[4]);
+    for (int i = lane; i < N; i += kFbLanes) {
+        const int64_t k = a0 + i;
+        p.vx[k] = (VT)(b[1] + scale * ((double)p.vx[k] - a[1]));
+        p.vy[k] = (VT)(b[2] + scale * ((double)p.vy[k] - a[2]));
+        p.vz[k] = (VT)(b[3] + scale * ((double)p.vz[k] - a[3]));
+    }
+    // logical (pid) order of the cell
+    for (int i = lane; i < N; i += kFbLanes) {
+        const uint32_t me = p.pid[a0 + i];
+        int r = 0;
+        for (int j = 0; j < N; ++j) r += p.pid[a0 + j] < me ? 1 : 0;
+        scratch[a0 + r] = (int32_t)(a0 + i);
+    }
+    __syncthreads();
+    const int T = w.fb_tgt[c];
+    const uint32_t subject = (uint32_t)orig[c];
+    const uint32_t step = sc->step;
+    if (T < N) {
+        // Live ranks as a bitmap (in the cell's slice of `bits`); each lane
+        // owns a contiguous run of words and keeps its live count in a
+        // register, so a deletion touches one lane's words only.
+        const int nw = (N + 31) >> 5;
+        const int wpl = (nw + kFbLanes - 1) / kFbLanes;
+        uint32_t* words = bits + a0;
+        int cnt = 0;
+        for (int j = 0; j < wpl; ++j) {
+            const int wi = lane * wpl + j;
+            if (wi < nw) {
+                const uint32_t word = (wi < nw - 1 || (N & 31) == 0) ? 0xFFFFFFFFu : ((1u << (N & 31)) - 1u);
+                words[wi] = word;
+                cnt += __popc(word);
+            }
+        }
+        int rem = N;
+        for (int k = 0; k < N - T; ++k) {
+            const Rand4 r = draw(key, subject, step, kPurposeRecalibrate, (uint64_t)(2 + 2 * k));
+            const int idx = (int)pick(r.w[0], (uint32_t)rem);
+            int inc = cnt;
+            for (int o = 1; o < kFbLanes; o <<= 1) {
+                const int y = __shfl_up(inc, o, kFbLanes);
+                if (lane >= o) inc += y;
+            }
+            const int exc = inc - cnt;
+            if (idx >= exc && idx < inc) {
+                int need = idx - exc;
+                for (int j = 0; j < wpl; ++j) {
+                    const int wi = lane * wpl + j;
+                    if (wi >= nw) break;
+                    const uint32_t word = words[wi];
+                    const int pc = __popc(word);
+                    if (need < pc) {
+                        int bit = 0;
+                        for (; bit < 32; ++bit)
+                            if ((word >> bit) & 1u) {
+                                if (need == 0) break;
+                                --need;
+                            }
+                        words[wi] = word & ~(1u << bit);
+                        p.cell[scratch[a0 + wi * 32 + bit]] = -1;
+                        break;
+                    }
+                    need -= pc;
+                }
+                --cnt;
+            }
+            --rem;
+        }
+    } else if (T > N) {
+        const int4 q = tv[c];
+        const double* A = xyz + 3 * (size_t)q.x;
+        const double* B = xyz + 3 * (size_t)q.y;
+        const double* C = xyz + 3 * (size_t)q.z;
+        const double* D = xyz + 3 * (size_t)q.w;
+        const int64_t base = sc->np + w.fb_off[subject];
+        const uint32_t pid0 = sc->next_pid + (uint32_t)w.fb_off[subject];
+        for (int k = lane; k < T - N; k += kFbLanes) {
+            const Rand4 r1 = draw(key, subject, step, kPurposeRecalibrate, (uint64_t)(2 + 2 * k));
+            const Rand4 r2 = draw(key, subject, step, kPurposeRecalibrate, (uint64_t)(3 + 2 * k));
+            const int src = (int)pick(r1.w[0], (uint32_t)N);
+            const int64_t si = scratch[a0 + src];
+            double u1 = u01(r1.w[2], r1.w[3]), u2 = u01(r2.w[0], r2.w[1]), u3 = u01(r2.w[2], r2.w[3]), t;
+            if (u1 > u2) { t = u1; u1 = u2; u2 = t; }
+            if (u2 > u3) { t = u2; u2 = u3; u3 = t; }
+            if (u1 > u2) { t = u1; u1 = u2; u2 = t; }
+            const double w0 = u1, w1 = u2 - u1, w2 = u3 - u2, w3 = 1.0 - u3;
+            const int64_t d = base + k;
+            if (d >= cap) continue;
+            p.x[d] = ((w0 * A[0] + w1 * B[0]) + w2 * C[0]) + w3 * D[0];
+            p.y[d] = ((w0 * A[1] + w1 * B[1]) + w2 * C[1]) + w3 * D[1];
+            p.z[d] = ((w0 * A[2] + w1 * B[2]) + w2 * C[2]) + w3 * D[2];
+            p.vx[d] = p.vx[si];
+            p.vy[d] = p.vy[si];
+            p.vz[d] = p.vz[si];
+            p.cell[d] = c;
+            p.pid[d] = pid0 + (uint32_t)k;
+        }
+    }
+}
+
+// Histogram of the cells of the sorted particles and of the entries
+// appended after them (feedback clones).
+__global__ void k_dig_count_all(const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc->np + sc->ninj) return;
+    const int c = cell[i];
+    if (c >= 0) rank[i] = (uint32_t)atomicAdd(&counts[c], 1);
+}
+
+__global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+static inline dim3 cells_grid(int64_t n) { return dim3((unsigned)((n + kDigThreads - 1) / kDigThreads)); }
+
+void launch_dig_sampled(hipStream_t s, const DigGeom& g, const double* ewma, double FN, DigWork w) {
+    hipLaunchKernelGGL(k_dig_sampled, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, ewma, FN, w);
+}
+
+void launch_dig_kn(hipStream_t s, const DigGeom& g, DigWork w, double kn_ref, double T0, double rho0, double L0) {
+    hipLaunchKernelGGL(k_dig_kn, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w, kn_ref, T0, rho0, L0);
+}
+
+void launch_dig_gradients(hipStream_t s, const DigGeom& g, const double* prim, double* grad, const DigCtl* ctl) {
+    hipLaunchKernelGGL(k_dig_grad, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, prim, grad, ctl);
+}
+
+void launch_dig_hot(hipStream_t s, const DigGeom& g, DigWork w) {
+    hipLaunchKernelGGL(k_dig_hot, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w);
+}
+
+void launch_dig_gate(hipStream_t s, const DigGeom& g, DigWork w, double kn_max, int passes) {
+    const dim3 gr = cells_grid(g.nt), bl(kDigThreads);
+    hipLaunchKernelGGL(k_dig_gate_init, gr, bl, 0, s, g, w, kn_max);
+    for (int p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL(k_dig_gate_pass, gr, bl, 0, s, g, w);
+        hipLaunchKernelGGL(k_dig_gate_commit, gr, bl, 0, s, g, w);
+    }
+    hipLaunchKernelGGL(k_dig_gate_final, gr, bl, 0, s, g, w);
+}
+
+void launch_dig_ctl_reset(hipStream_t s, DigCtl* ctl) {
+    hipLaunchKernelGGL(k_dig_ctl_reset, dim3(1), dim3(1), 0, s, ctl);
+}
+
+void launch_dig_copy(hipStream_t s, const double* src, double* dst, int64_t n) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_dig_copy, cells_grid(n), dim3(kDigThreads), 0, s, src, dst, n);
+}
+
+void launch_dig_residual(hipStream_t s, const DigGeom& g, const double* prim, const double* hot, const double* grad,
+                         double* Rs, DigWork w, int first, double cfl) {
+    hipLaunchKernelGGL(k_dig_residual, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, prim, hot, grad, Rs, w, first,
+                       cfl);
+}
+
+// One pseudo-time iteration: three stages with weights 1/3, 1/2, 1; the
+// convergence test and the step size come from the first stage.
+void launch_dig_iteration(hipStream_t s, const DigGeom& g, DigWork w, double cfl, double eps_m, int global_dt,
+                          int it) {
+    const dim3 gr = cells_grid(g.nt), bl(kDigThreads);
+    const int nblk = (int)gr.x;
+    const double alpha[3] = {1.0 / 3.0, 0.5, 1.0};
+    hipLaunchKernelGGL(k_dig_save, gr, bl, 0, s, g, w);
+    for (int k = 0; k < 3; ++k) {
+        hipLaunchKernelGGL(k_dig_grad, gr, bl, 0, s, g, (const double*)w.stage, w.grad, (const DigCtl*)w.ctl);
+        hipLaunchKernelGGL(k_dig_residual, gr, bl, 0, s, g, (const double*)w.stage, (const double*)w.hot,
+                           (const double*)w.grad, w.Rs, w, k == 0 ? 1 : 0, cfl);
+        if (k == 0) hipLaunchKernelGGL(k_dig_check, dim3(1), bl, 0, s, w, nblk, it, eps_m);
+        hipLaunchKernelGGL(k_dig_update, gr, bl, 0, s, g, w, alpha[k], global_dt);
+    }
+    hipLaunchKernelGGL(k_dig_commit, gr, bl, 0, s, g, w);
+}
+
+void launch_dig_set_local(hipStream_t s, const int32_t* state, uint8_t* local, int nt) {
+    hipLaunchKernelGGL(k_dig_set_local, cells_grid(nt), dim3(kDigThreads), 0, s, state, local, nt);
+}
+
+void launch_dig_fb_count(hipStream_t s, const DigGeom& g, DigWork w, const int32_t* offsets, const int32_t* orig,
+                         const Scalars* sc, RngKey key) {
+    hipLaunchKernelGGL(k_dig_fb_count, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w, offsets, orig, sc, key);
+}
+
+template <class VT>
+void launch_dig_fb_apply(hipStream_t s, DigWork w, PartDev<VT> p, const int32_t* offsets, const int4* tv,
+                         const double* xyz, const int32_t* orig, const Scalars* sc, RngKey key, int32_t* scratch,
+                         uint32_t* bits, int nt, int64_t cap) {
+    hipLaunchKernelGGL(k_dig_fb_apply<VT>, dim3((unsigned)nt), dim3(kFbLanes), 0, s, w, p, offsets, tv, xyz, orig,
+                       sc, key, scratch, bits, cap);
+}
+
+void launch_dig_count_all(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
+                          int64_t bound) {
+    hipLaunchKernelGGL(k_dig_count_all, cells_grid(bound > 0 ? bound : 1), dim3(kDigThreads), 0, s, cell, sc, counts,
+                       rank);
+}
+
+void launch_fill_u8(hipStream_t s, uint8_t* p, uint8_t v, int64_t n) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_u8, cells_grid(n), dim3(kDigThreads), 0, s, p, v, n);
+}
+
+template void launch_dig_fb_apply<float>(hipStream_t, DigWork, PartDev<float>, const int32_t*, const int4*,
+                                         const double*, const int32_t*, const Scalars*, RngKey, int32_t*, uint32_t*,
+                                         int, int64_t);
+template void launch_dig_fb_apply<double>(hipStream_t, DigWork, PartDev<double>, const int32_t*, const int4*,
+                                          const double*, const int32_t*, const Scalars*, RngKey, int32_t*, uint32_t*,
+                                          int, int64_t);
+
+}  // namespace dsmcx

@@ -1,0 +1,460 @@
+// C ABI of the DIG coupling step (section 3, Algorithm 1): geometry of the
+// macroscopic finite-volume solver, the coupling cycle and its parts.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/dig.h"
+#include "context.h"
+#include "dig.h"
+
+namespace dsmcx {
+
+struct DigState {
+    DigGeom g{};
+    DigWork w{};
+    int nblk = 0;
+};
+
+void dig_release(dsmc_ctx c) {
+    // device arrays belong to the context's allocation list
+    delete c->dig;
+    c->dig = nullptr;
+}
+
+namespace {
+
+constexpr int kPollEvery = 16;  // iterations between convergence polls
+
+struct HostGeom {
+    std::vector<double> cen, fcen, fnu, farea, fdx, lsq;
+    std::vector<int32_t> flink;
+};
+
+// Centroids, face centroids, outward unit normals and areas, the link of
+// every tet face (neighbour across an interior or periodic face, boundary
+// group otherwise) with the connector dx, and the inverse of the weighted
+// least-squares matrix sum_f w dx dx^T (w = 1/|dx|^2) over the faces that
+// carry a gradient value (interior, periodic, diffuse wall).
+void build_geometry(const HostMesh& m, const std::vector<dsmc_boundary_desc>& bcs, HostGeom& G) {
+    const int nt = m.nt;
+    G.cen.assign(3 * (size_t)nt, 0.0);
+    G.fcen.assign(12 * (size_t)nt, 0.0);
+    G.fnu.assign(12 * (size_t)nt, 0.0);
+    G.farea.assign(4 * (size_t)nt, 0.0);
+    G.fdx.assign(12 * (size_t)nt, 0.0);
+    G.lsq.assign(9 * (size_t)nt, 0.0);
+    G.flink.assign(4 * (size_t)nt, 0);
+    const double* X = m.xyz.data();
+    for (int c = 0; c < nt; ++c) {
+        const int32_t* q = &m.tv[4 * (size_t)c];
+        for (int i = 0; i < 3; ++i) {
+            const double a = X[3 * (size_t)q[0] + i], b = X[3 * (size_t)q[1] + i];
+            const double d = X[3 * (size_t)q[2] + i], e = X[3 * (size_t)q[3] + i];
+            G.cen[3 * (size_t)c + i] = (((a + b) + d) + e) * 0.25;
+        }
+        for (int f = 0; f < 4; ++f) {
+            int v[3], j = 0;
+            for (int k = 0; k < 4; ++k)
+                if (k != f) v[j++] = q[k];
+            for (int i = 0; i < 3; ++i)
+                G.fcen[12 * (size_t)c + 3 * f + i] =
+                    ((X[3 * (size_t)v[0] + i] + X[3 * (size_t)v[1] + i]) + X[3 * (size_t)v[2] + i]) / 3.0;
+            const double* pl = &m.plane[16 * (size_t)c + 4 * f];
+            const double nn = std::sqrt(pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2]);
+            for (int i = 0; i < 3; ++i) G.fnu[12 * (size_t)c + 3 * f + i] = pl[i] / nn;
+            G.farea[4 * (size_t)c + f] = 0.5 * nn;
+        }
+    }
+    for (int c = 0; c < nt; ++c) {
+        const double* xc = &G.cen[3 * (size_t)c];
+        for (int f = 0; f < 4; ++f) {
+            const int code = m.nbr[4 * (size_t)c + f];
+            double* dx = &G.fdx[12 * (size_t)c + 3 * f];
+            const double* xf = &G.fcen[12 * (size_t)c + 3 * f];
+            int32_t link;
+            if (code >= 0) {
+                const int nb = code >> 2;
+                for (int i = 0; i < 3; ++i) dx[i] = G.cen[3 * (size_t)nb + i] - xc[i];
+                link = kLinkInterior | (nb << 3);
+            } else {
+                const int bf = -1 - code;
+                const int grp = m.bf_group[bf];
+                const dsmc_boundary_desc& b = bcs[grp];
+                if (b.kind == DSMC_BC_PERIODIC) {
+                    const int pt = m.bf_tet[m.bf_partner[bf]];
+                    for (int i = 0; i < 3; ++i) dx[i] = (G.cen[3 * (size_t)pt + i] - b.shift[i]) - xc[i];
+                    link = kLinkPeriodic | (pt << 3);
+                } else {
+                    for (int i = 0; i < 3; ++i) dx[i] = xf[i] - xc[i];
+                    const int kind = b.kind == DSMC_BC_DIFFUSE    ? kLinkWall
+                                     : b.kind == DSMC_BC_SPECULAR ? kLinkSpecular
+                                     : b.kind == DSMC_BC_INFLOW   ? kLinkInflow
+                                                                  : kLinkOutflow;
+                    link = kind | (grp << 3);
+                }
+            }
+            G.flink[4 * (size_t)c + f] = link;
+        }
+        double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int f = 0; f < 4; ++f) {
+            const int kind = G.flink[4 * (size_t)c + f] & 7;
+            if (kind != kLinkInterior && kind != kLinkPeriodic && kind != kLinkWall) continue;
+            const double* dx = &G.fdx[12 * (size_t)c + 3 * f];
+            const double w = 1.0 / (dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) A[i][j] += w * dx[i] * dx[j];
+        }
+        double* L = &G.lsq[9 * (size_t)c];
+        const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                           A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                           A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+        const double tr = (A[0][0] + A[1][1] + A[2][2]) / 3.0;
+        if (!(std::fabs(det) > 1e-10 * tr * tr * tr)) continue;  // rank-deficient stencil: zero gradient
+        L[0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det;
+        L[1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+        L[2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+        L[3] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / det;
+        L[4] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+        L[5] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+        L[6] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det;
+        L[7] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+        L[8] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+    }
+}
+
+// Viscosity of the VHS gas at T_ref (Chapman-Enskog first approximation).
+double mu_ref_of(dsmc_ctx c) {
+    const double w = c->omega;
+    return 15.0 * std::sqrt(M_PI * c->mass * kBoltzmann * c->Tref) /
+           (2.0 * M_PI * c->dref * c->dref * (5.0 - 2.0 * w) * (7.0 - 2.0 * w));
+}
+
+template <class T>
+dsmc_status upload(dsmc_ctx c, T* dst, const std::vector<T>& src) {
+    HIP_TRY(c, hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, c->stream));
+    return DSMC_OK;
+}
+
+dsmc_status ensure(dsmc_ctx c) {
+    if (c->dig) return DSMC_OK;
+    HostGeom G;
+    build_geometry(c->hm, c->bcs, G);
+    const int nt = c->nt;
+    const int ng = (int)c->bcs.size();
+    DigState* d = new DigState();
+    d->nblk = (nt + kDigThreads - 1) / kDigThreads;
+    double *cen, *fcen, *fnu, *farea, *fdx, *lsq;
+    int32_t* flink;
+    DigGroup* groups;
+    DigWork& w = d->w;
+    bool ok = alloc_n(c, cen, G.cen.size()) && alloc_n(c, fcen, G.fcen.size()) && alloc_n(c, fnu, G.fnu.size()) &&
+              alloc_n(c, farea, G.farea.size()) && alloc_n(c, fdx, G.fdx.size()) && alloc_n(c, lsq, G.lsq.size()) &&
+              alloc_n(c, flink, G.flink.size()) && alloc_n(c, groups, ng + 1);
+    ok = ok && alloc_n(c, w.samp, 14 * (size_t)nt) && alloc_n(c, w.ok, nt) && alloc_n(c, w.prim, 5 * (size_t)nt) &&
+         alloc_n(c, w.half, 5 * (size_t)nt) && alloc_n(c, w.hot, 9 * (size_t)nt) &&
+         alloc_n(c, w.grad, 15 * (size_t)nt) && alloc_n(c, w.kn, nt) && alloc_n(c, w.avail, nt) &&
+         alloc_n(c, w.navail, nt) && alloc_n(c, w.nprim, 5 * (size_t)nt) && alloc_n(c, w.nhot, 9 * (size_t)nt) &&
+         alloc_n(c, w.state, nt) && alloc_n(c, w.mprev, 5 * (size_t)nt) && alloc_n(c, w.Rs, 5 * (size_t)nt) &&
+         alloc_n(c, w.dt, nt) && alloc_n(c, w.U0, 5 * (size_t)nt) && alloc_n(c, w.stage, 5 * (size_t)nt) &&
+         alloc_n(c, w.partial, 2 * (size_t)d->nblk) && alloc_n(c, w.ctl, 1) && alloc_n(c, w.fb_cnt, nt) &&
+         alloc_n(c, w.fb_off, nt + 1) && alloc_n(c, w.fb_tgt, nt);
+    if (!ok) {
+        delete d;
+        return fail(c, DSMC_E_OOM, "device allocation of the coupling state failed");
+    }
+    std::vector<DigGroup> hg(ng + 1);
+    for (int g = 0; g < ng; ++g) {
+        hg[g].T = c->bcs[g].T;
+        for (int i = 0; i < 3; ++i) hg[g].u[i] = c->bcs[g].u[i];
+        hg[g].rho = c->mass * c->bcs[g].n;
+    }
+    std::vector<double> mprev(5 * (size_t)nt);
+    for (int t = 0; t < nt; ++t) {
+        double* p = &mprev[5 * (size_t)t];
+        p[0] = c->mass * c->n0;
+        p[1] = c->u0[0];
+        p[2] = c->u0[1];
+        p[3] = c->u0[2];
+        p[4] = c->T0;
+    }
+    dsmc_status st = DSMC_OK;
+    if (st == DSMC_OK) st = upload(c, cen, G.cen);
+    if (st == DSMC_OK) st = upload(c, fcen, G.fcen);
+    if (st == DSMC_OK) st = upload(c, fnu, G.fnu);
+    if (st == DSMC_OK) st = upload(c, farea, G.farea);
+    if (st == DSMC_OK) st = upload(c, fdx, G.fdx);
+    if (st == DSMC_OK) st = upload(c, lsq, G.lsq);
+    if (st == DSMC_OK) st = upload(c, flink, G.flink);
+    if (st == DSMC_OK) st = upload(c, groups, hg);
+    if (st == DSMC_OK) st = upload(c, w.mprev, mprev);
+    if (st == DSMC_OK) {
+        launch_fill_i32(c->stream, w.state, 0, nt);
+        launch_dig_ctl_reset(c->stream, w.ctl);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) st = fail(c, DSMC_E_DEVICE, "coupling state upload failed");
+    }
+    if (st != DSMC_OK) {
+        delete d;
+        return st;
+    }
+    DigGeom& g = d->g;
+    g.nt = nt;
+    g.cen = cen; g.fcen = fcen; g.fnu = fnu; g.farea = farea; g.fdx = fdx; g.flink = flink; g.lsq = lsq;
+    g.vol = c->d_vol;
+    g.groups = groups;
+    g.mass = c->mass;
+    g.R = kBoltzmann / c->mass;
+    g.mu_ref = mu_ref_of(c);
+    g.omega = c->omega;
+    g.T_ref = c->Tref;
+    c->dig = d;
+    return DSMC_OK;
+}
+
+DigCtl read_ctl(dsmc_ctx c, dsmc_status* st) {
+    DigCtl h{};
+    *st = DSMC_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess ||
+        hipMemcpy(&h, c->dig->w.ctl, sizeof h, hipMemcpyDeviceToHost) != hipSuccess) {
+        c->broken = true;
+        *st = fail(c, DSMC_E_DEVICE, "reading the coupling control block failed");
+    }
+    return h;
+}
+
+dsmc_status check_params(dsmc_ctx c, const dig_params* p) {
+    if (!p) return fail(c, DSMC_E_INVALID, "params is NULL");
+    if (p->passes < 0 || p->n_m < 0 || !(p->cfl > 0) || !(p->L0 > 0) || !(p->eps_m >= 0))
+        return fail(c, DSMC_E_INVALID, "bad coupling parameters");
+    return DSMC_OK;
+}
+
+// Pseudo-time marching from w.prim with w.hot frozen; fills the solve part
+// of the report.
+dsmc_status run_solve(dsmc_ctx c, const dig_params* p, dig_report* r) {
+    DigState* d = c->dig;
+    launch_dig_ctl_reset(c->stream, d->w.ctl);
+    dsmc_status st = DSMC_OK;
+    DigCtl h{};
+    for (int it = 0; it < p->n_m; ++it) {
+        launch_dig_iteration(c->stream, d->g, d->w, p->cfl, p->eps_m, p->global_dt ? 1 : 0, it);
+        if ((it + 1) % kPollEvery == 0 && it + 1 < p->n_m) {
+            HIP_TRY(c, hipGetLastError());
+            h = read_ctl(c, &st);
+            if (st != DSMC_OK) return st;
+            if (h.conv || h.failed) break;
+        }
+    }
+    HIP_TRY(c, hipGetLastError());
+    h = read_ctl(c, &st);
+    if (st != DSMC_OK) return st;
+    r->iters = h.iters;
+    r->residual = h.res0 > 0 ? h.res / h.res0 : 0.0;
+    r->converged = h.conv;
+    r->failed = h.failed;
+    return DSMC_OK;
+}
+
+template <class VT>
+dsmc_status feedback_t(dsmc_ctx c) {
+    DigState* d = c->dig;
+    hipStream_t s = c->stream;
+    const int nt = c->nt;
+    launch_dig_fb_count(s, d->g, d->w, c->d_offsets, c->d_orig, c->d_sc, c->key);
+    launch_scan(s, d->w.fb_cnt, nt, d->w.fb_off, c->d_blocksums, c->d_sc, kScanInject);
+    HIP_TRY(c, hipGetLastError());
+    Scalars sc;
+    dsmc_status st = sync_scalars(c, &sc);
+    if (st != DSMC_OK) return st;
+    const int64_t bound = sc.np + sc.ninj;
+    if (bound > c->cap) {
+        sc.ninj = 0;
+        HIP_TRY(c, hipMemcpy(c->d_sc, &sc, sizeof sc, hipMemcpyHostToDevice));
+        return fail(c, DSMC_E_CAPACITY, "feedback clones would exceed the particle store");
+    }
+    PartDev<VT> a = as_dev<VT>(c->A), b = as_dev<VT>(c->B);
+    launch_dig_fb_apply<VT>(s, d->w, a, c->d_offsets, c->d_tv, c->d_xyz, c->d_orig, c->d_sc, c->key, c->d_perm,
+                            c->d_rank, nt, c->cap);
+    // counting sort of the survivors and the clones
+    launch_fill_i32(s, c->d_counts, 0, nt + 1);
+    launch_dig_count_all(s, a.cell, c->d_sc, c->d_counts, c->d_rank, bound);
+    launch_scan(s, c->d_counts, nt, c->d_offsets, c->d_blocksums, c->d_sc, kScanCells);
+    launch_scatter<VT>(s, a, b, c->d_sc, c->d_offsets, c->d_rank, bound, c->cap, c->d_sortperm, c->sort_variant);
+    if (c->sort_variant == kSortGather) launch_gather<VT>(s, a, b, c->d_sc, c->d_sortperm, bound);
+    std::swap(c->A, c->B);
+    c->np_bound = bound;
+    HIP_TRY(c, hipGetLastError());
+    return sync_scalars(c, nullptr);
+}
+
+dsmc_status run_feedback(dsmc_ctx c) { return c->vel64 ? feedback_t<double>(c) : feedback_t<float>(c); }
+
+// host [nt][k] in caller order <-> device [nt][k] in internal order
+template <class T>
+dsmc_status to_device(dsmc_ctx c, T* dst, const T* src, int k) {
+    const int nt = c->nt;
+    std::vector<T> h((size_t)k * nt);
+    for (int t = 0; t < nt; ++t)
+        for (int j = 0; j < k; ++j) h[(size_t)k * t + j] = src[(size_t)k * c->hm.orig[t] + j];
+    HIP_TRY(c, hipMemcpyAsync(dst, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DSMC_OK;
+}
+
+template <class T>
+dsmc_status to_host(dsmc_ctx c, T* dst, const T* src, int k) {
+    const int nt = c->nt;
+    std::vector<T> h((size_t)k * nt);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(h.data(), src, sizeof(T) * h.size(), hipMemcpyDeviceToHost));
+    for (int t = 0; t < nt; ++t)
+        for (int j = 0; j < k; ++j) dst[(size_t)k * c->hm.orig[t] + j] = h[(size_t)k * t + j];
+    return DSMC_OK;
+}
+
+dsmc_status usable(dsmc_ctx c) {
+    if (!c) return fail(c, DSMC_E_INVALID, "NULL context");
+    if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
+    return ensure(c);
+}
+
+}  // namespace
+}  // namespace dsmcx
+
+using namespace dsmcx;
+
+extern "C" {
+
+dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
+    dsmc_status st = usable(c);
+    if (st != DSMC_OK) return st;
+    if ((st = check_params(c, p)) != DSMC_OK) return st;
+    DigState* d = c->dig;
+    hipStream_t s = c->stream;
+    const int nt = c->nt;
+    Scalars sc;
+    if ((st = sync_scalars(c, &sc)) != DSMC_OK) return st;
+    dig_report r{};
+    r.np_before = sc.np;
+    // reference state of the Knudsen number (eq. cell_kn_stability)
+    const double T0 = c->T0;
+    const double p0 = c->n0 * kBoltzmann * T0;
+    const double R = kBoltzmann / c->mass;
+    const double mu0 = d->g.mu_ref * std::pow(T0 / c->Tref, c->omega);
+    const double kn_ref = mu0 / (p0 * p->L0) * std::sqrt(M_PI * R * T0 / 2.0);
+    const double rho0 = c->mass * c->n0;
+
+    launch_dig_ctl_reset(s, d->w.ctl);
+    launch_dig_sampled(s, d->g, c->d_ewma, c->FN, d->w);
+    launch_dig_kn(s, d->g, d->w, kn_ref, T0, rho0, p->L0);
+    launch_dig_gradients(s, d->g, d->w.prim, d->w.grad, nullptr);
+    launch_dig_hot(s, d->g, d->w);
+    launch_dig_gate(s, d->g, d->w, p->kn_max, p->passes);
+    launch_dig_copy(s, d->w.prim, d->w.half, 5 * (int64_t)nt);
+    HIP_TRY(c, hipGetLastError());
+    DigCtl h = read_ctl(c, &st);
+    if (st != DSMC_OK) return st;
+    r.n_rejected = h.n_rejected;
+    r.n_reconstructed = h.n_reconstructed;
+    r.n_unreached = h.n_unreached;
+    if (r.n_rejected < nt) {
+        if ((st = run_solve(c, p, &r)) != DSMC_OK) return st;
+        if (!r.failed) {
+            if (p->feedback && (st = run_feedback(c)) != DSMC_OK) {
+                if (rep) *rep = r;
+                return st;
+            }
+            launch_dig_copy(s, d->w.prim, d->w.mprev, 5 * (int64_t)nt);
+        }
+    }
+    launch_dig_set_local(s, d->w.state, c->d_local, nt);
+    HIP_TRY(c, hipGetLastError());
+    if ((st = sync_scalars(c, &sc)) != DSMC_OK) return st;
+    r.np_after = sc.np;
+    if (rep) *rep = r;
+    return DSMC_OK;
+}
+
+dsmc_status dig_get(dsmc_ctx c, int32_t which, void* out) {
+    dsmc_status st = usable(c);
+    if (st != DSMC_OK) return st;
+    if (!out) return fail(c, DSMC_E_INVALID, "out is NULL");
+    const DigWork& w = c->dig->w;
+    switch (which) {
+    case DIG_OUT_SAMPLED: return to_host(c, (double*)out, w.samp, 14);
+    case DIG_OUT_HALF: return to_host(c, (double*)out, w.half, 5);
+    case DIG_OUT_NEW: return to_host(c, (double*)out, w.prim, 5);
+    case DIG_OUT_HOT: return to_host(c, (double*)out, w.hot, 9);
+    case DIG_OUT_KN: return to_host(c, (double*)out, w.kn, 1);
+    case DIG_OUT_STATE: return to_host(c, (int32_t*)out, w.state, 1);
+    case DIG_OUT_MPREV: return to_host(c, (double*)out, w.mprev, 5);
+    default: return fail(c, DSMC_E_INVALID, "unknown coupling output");
+    }
+}
+
+dsmc_status dig_residual(dsmc_ctx c, const double* prim, const double* hot, double* out) {
+    dsmc_status st = usable(c);
+    if (st != DSMC_OK) return st;
+    if (!prim || !hot || !out) return fail(c, DSMC_E_INVALID, "NULL array");
+    DigState* d = c->dig;
+    if ((st = to_device(c, d->w.stage, prim, 5)) != DSMC_OK) return st;
+    if ((st = to_device(c, d->w.nhot, hot, 9)) != DSMC_OK) return st;
+    launch_dig_ctl_reset(c->stream, d->w.ctl);
+    launch_dig_gradients(c->stream, d->g, d->w.stage, d->w.grad, d->w.ctl);
+    launch_dig_residual(c->stream, d->g, d->w.stage, d->w.nhot, d->w.grad, d->w.Rs, d->w, 0, 1.0);
+    HIP_TRY(c, hipGetLastError());
+    return to_host(c, out, d->w.Rs, 5);
+}
+
+dsmc_status dig_solve(dsmc_ctx c, double* prim, const double* hot, const dig_params* p, dig_report* rep) {
+    dsmc_status st = usable(c);
+    if (st != DSMC_OK) return st;
+    if ((st = check_params(c, p)) != DSMC_OK) return st;
+    if (!prim || !hot) return fail(c, DSMC_E_INVALID, "NULL array");
+    DigState* d = c->dig;
+    if ((st = to_device(c, d->w.prim, (const double*)prim, 5)) != DSMC_OK) return st;
+    if ((st = to_device(c, d->w.hot, hot, 9)) != DSMC_OK) return st;
+    dig_report r{};
+    if ((st = run_solve(c, p, &r)) != DSMC_OK) return st;
+    if ((st = to_host(c, prim, d->w.prim, 5)) != DSMC_OK) return st;
+    if (rep) *rep = r;
+    return DSMC_OK;
+}
+
+dsmc_status dig_feedback(dsmc_ctx c, const double* prim_old, const double* prim_new, const int32_t* state,
+                         int64_t* np_after) {
+    dsmc_status st = usable(c);
+    if (st != DSMC_OK) return st;
+    if (!prim_old || !prim_new || !state) return fail(c, DSMC_E_INVALID, "NULL array");
+    DigState* d = c->dig;
+    if ((st = to_device(c, d->w.half, prim_old, 5)) != DSMC_OK) return st;
+    if ((st = to_device(c, d->w.prim, prim_new, 5)) != DSMC_OK) return st;
+    if ((st = to_device(c, d->w.state, state, 1)) != DSMC_OK) return st;
+    if ((st = run_feedback(c)) != DSMC_OK) return st;
+    if (np_after) {
+        Scalars sc;
+        if ((st = sync_scalars(c, &sc)) != DSMC_OK) return st;
+        *np_after = sc.np;
+    }
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_set_sums(dsmc_ctx c, int32_t which, const double* sums) {
+    if (!c || !sums || (which != DSMC_SAMPLE_STEADY && which != DSMC_SAMPLE_EWMA))
+        return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
+    const int nt = c->nt;
+    std::vector<double> h((size_t)kNMom * nt);
+    for (int t = 0; t < nt; ++t)
+        for (int k = 0; k < kNMom; ++k) h[(size_t)k * nt + t] = sums[(size_t)kNMom * c->hm.orig[t] + k];
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(which == DSMC_SAMPLE_STEADY ? c->d_acc : c->d_ewma, h.data(), sizeof(double) * h.size(),
+                         hipMemcpyHostToDevice));
+    return DSMC_OK;
+}
+
+}  // extern "C"

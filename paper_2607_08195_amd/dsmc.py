@@ -67,6 +67,29 @@ class Counters(C.Structure):
                 ("injected", C.c_int64), ("removed", C.c_int64), ("lost", C.c_int64), ("step", C.c_uint32)]
 
 
+class DigParams(C.Structure):
+    _fields_ = [("kn_max", C.c_double), ("passes", C.c_int32), ("n_m", C.c_int32), ("eps_m", C.c_double),
+                ("cfl", C.c_double), ("L0", C.c_double), ("feedback", C.c_int32), ("global_dt", C.c_int32)]
+
+
+class DigReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("residual", C.c_double), ("converged", C.c_int32), ("failed", C.c_int32),
+                ("n_rejected", C.c_int32), ("n_reconstructed", C.c_int32), ("n_unreached", C.c_int32),
+                ("np_before", C.c_int64), ("np_after", C.c_int64)]
+
+
+DIG_OUT = {"sampled": (0, 14), "half": (1, 5), "new": (2, 5), "hot": (3, 9), "kn": (4, 1), "state": (5, 1),
+           "mprev": (6, 5)}
+
+
+def dig_params(kn_max=1.0, passes=3, n_m=200, eps_m=1e-6, cfl=0.5, L0=1.0, feedback=1, global_dt=0):
+    return DigParams(kn_max, passes, n_m, eps_m, cfl, L0, feedback, global_dt)
+
+
+def _report(r):
+    return {k: getattr(r, k) for k, _ in DigReport._fields_}
+
+
 ctx_t = P
 _lib.dsmc_init.argtypes = [C.POINTER(ctx_t), C.POINTER(MeshDesc), C.POINTER(SpeciesDesc), C.c_int32,
                            C.POINTER(BoundaryDesc), C.POINTER(RunDesc)]
@@ -90,15 +113,23 @@ _lib.dsmc_device_copy.argtypes = [ctx_t, P, P, C.c_size_t]
 _lib.dsmc_last_error.argtypes = [ctx_t]
 _lib.dsmc_last_error.restype = C.c_char_p
 _lib.dsmc_destroy.argtypes = [ctx_t]
+_lib.dig_couple.argtypes = [ctx_t, C.POINTER(DigParams), C.POINTER(DigReport)]
+_lib.dig_get.argtypes = [ctx_t, C.c_int32, P]
+_lib.dig_residual.argtypes = [ctx_t, P, P, P]
+_lib.dig_solve.argtypes = [ctx_t, P, P, C.POINTER(DigParams), C.POINTER(DigReport)]
+_lib.dig_feedback.argtypes = [ctx_t, P, P, P, C.POINTER(C.c_int64)]
+_lib.dsmc_set_sums.argtypes = [ctx_t, C.c_int32, P]
 for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_state",
            "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
-           "dsmc_profile", "dsmc_philox", "dsmc_device_copy"]:
+           "dsmc_profile", "dsmc_philox", "dsmc_device_copy", "dig_couple", "dig_get", "dig_residual",
+           "dig_solve", "dig_feedback", "dsmc_set_sums"]:
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_state",
             "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
             "dsmc_profile", "dsmc_profile_read", "dsmc_profile_name", "dsmc_philox", "dsmc_device_copy",
-            "dsmc_last_error", "dsmc_destroy"]
+            "dsmc_last_error", "dsmc_destroy", "dig_couple", "dig_get", "dig_residual", "dig_solve",
+            "dig_feedback", "dsmc_set_sums"]
 
 
 class DsmcError(RuntimeError):
@@ -271,3 +302,45 @@ class Simulation:
 
     def device_copy(self, dst, src, nbytes):
         self._c(_lib.dsmc_device_copy(self.ctx, P(dst), P(src), nbytes))
+
+    def set_sums(self, which, sums):
+        a = np.ascontiguousarray(sums, np.float64)
+        if a.shape != (self.nt, 13):
+            raise ValueError("sums must be [n_tets, 13]")
+        self._c(_lib.dsmc_set_sums(self.ctx, which, _p(a)))
+
+    # -- DIG coupling (include/dig.h) ------------------------------------
+    def dig_couple(self, **kw):
+        prm = dig_params(**kw)
+        rep = DigReport()
+        self._c(_lib.dig_couple(self.ctx, C.byref(prm), C.byref(rep)))
+        return _report(rep)
+
+    def dig_get(self, which):
+        code, k = DIG_OUT[which]
+        if which == "state":
+            out = np.zeros(self.nt, np.int32)
+        else:
+            out = np.zeros((self.nt, k)) if k > 1 else np.zeros(self.nt)
+        self._c(_lib.dig_get(self.ctx, code, _p(out)))
+        return out
+
+    def dig_residual(self, prim, hot):
+        prim = np.ascontiguousarray(prim, np.float64); hot = np.ascontiguousarray(hot, np.float64)
+        out = np.zeros((self.nt, 5))
+        self._c(_lib.dig_residual(self.ctx, _p(prim), _p(hot), _p(out)))
+        return out
+
+    def dig_solve(self, prim, hot, **kw):
+        prim = np.array(prim, np.float64, order="C"); hot = np.ascontiguousarray(hot, np.float64)
+        prm = dig_params(**kw)
+        rep = DigReport()
+        self._c(_lib.dig_solve(self.ctx, _p(prim), _p(hot), C.byref(prm), C.byref(rep)))
+        return prim, _report(rep)
+
+    def dig_feedback(self, prim_old, prim_new, state):
+        a = np.ascontiguousarray(prim_old, np.float64); b = np.ascontiguousarray(prim_new, np.float64)
+        st = np.ascontiguousarray(state, np.int32)
+        n = C.c_int64()
+        self._c(_lib.dig_feedback(self.ctx, _p(a), _p(b), _p(st), C.byref(n)))
+        return int(n.value)
