@@ -80,7 +80,7 @@ def test_couple_stages_match_oracle(dsmc, vel_fp32):
     cycle without feedback."""
     wl = _cavity(Kn=0.1, vel_fp32=vel_fp32)
     o, g = _pair(dsmc, wl, steps=40, n_a=50)
-    kw = dict(kn_max=0.25, passes=3, n_m=60, eps_m=1e-8, cfl=0.5, feedback=0)
+    kw = dict(kn_max=0.93, passes=3, n_m=60, eps_m=1e-8, cfl=0.5, feedback=0)
     # oracle stage by stage (its couple runs the same sequence)
     smp = o.dig_sampled()
     rg = g.dig_couple(**kw)
@@ -111,7 +111,7 @@ def test_gate_and_hot_match_oracle(dsmc):
     """M^{k+1/2}, HoT and cell states after the gate, from one state."""
     wl = _cavity(Kn=0.05, n_hex=7, ppc=12, jitter=0.1)
     o, g = _pair(dsmc, wl, steps=25, n_a=30)
-    kw = dict(kn_max=0.2, passes=2, n_m=0, feedback=0)
+    kw = dict(kn_max=0.6, passes=2, n_m=0, feedback=0)
     g.dig_couple(**kw)
     smp = o.dig_sampled()
     ok = np.isfinite(smp[:, 0]) & (smp[:, 0] > 0)
@@ -254,7 +254,7 @@ def test_couple_with_feedback_matches_oracle(dsmc):
     steps after it."""
     wl = _cavity(Kn=0.1, n_hex=6, ppc=20, vel_fp32=0)
     o, g = _pair(dsmc, wl, steps=40, n_a=50)
-    kw = dict(kn_max=0.25, passes=3, n_m=40, eps_m=1e-8, cfl=0.5, feedback=1)
+    kw = dict(kn_max=0.93, passes=3, n_m=40, eps_m=1e-8, cfl=0.5, feedback=1)
     rg = g.dig_couple(**kw)
     ro = o.dig_couple(**kw)
     for k in ["n_rejected", "n_reconstructed", "n_unreached", "iters", "converged", "failed", "np_before",
