@@ -68,6 +68,8 @@ typedef struct {
     int32_t n_reconstructed; /* rejected cells rebuilt from neighbours */
     int32_t n_unreached;     /* rejected cells keeping M^k with zero HoT */
     int64_t np_before, np_after;
+    int32_t n_closure;       /* cells whose HoT came from the learned closure (mlp.h) */
+    int32_t n_fallback;      /* cells with samples that kept the sampled HoT */
 } dig_report;
 
 /* One coupling cycle (Algorithm 1) on the context's current moving-average

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/dsmc.h"
+#include "../../include/mlp.h"
 #include "kernels.h"
 #include "mesh.h"
 
@@ -102,6 +103,8 @@ struct dsmc_ctx_s {
     // boundary table (copied at init) and the coupling state, built on first use
     std::vector<dsmc_boundary_desc> bcs;
     dsmcx::DigState* dig = nullptr;
+    dsmc_mlp closure = nullptr;  // learned HoT closure of the coupling step (not owned)
+    double gate_tol = 0.05;
 };
 
 namespace dsmcx {

@@ -41,6 +41,7 @@ struct DigCtl {
     double res0, res, dtmin;
     int conv, failed, iters;
     int n_rejected, n_reconstructed, n_unreached;
+    int n_closure, n_fallback;
 };
 
 struct DigWork {
@@ -66,6 +67,11 @@ struct DigWork {
     int32_t* fb_cnt;  // [nt] clones per cell, caller order
     int32_t* fb_off;  // [nt + 1]
     int32_t* fb_tgt;  // [nt] target count per internal cell
+    float* cx;        // [nt][13] closure inputs
+    float* ct;        // [nt][9] nondimensional sampled HoT
+    float* cs;        // [nt][9] nondimensional sampled stress and heat flux
+    float* cy;        // [nt][9] closure outputs
+    uint8_t* cvalid;  // [nt]
 };
 
 void launch_dig_sampled(hipStream_t s, const DigGeom& g, const double* ewma, double FN, DigWork w);
@@ -89,5 +95,7 @@ void launch_dig_fb_apply(hipStream_t s, DigWork w, PartDev<VT> p, const int32_t*
 void launch_dig_count_all(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
                           int64_t bound);
 void launch_fill_u8(hipStream_t s, uint8_t* p, uint8_t v, int64_t n);
+void launch_dig_closure_prep(hipStream_t s, const DigGeom& g, DigWork w);
+void launch_dig_closure_gate(hipStream_t s, const DigGeom& g, DigWork w, double tol);
 
 }  // namespace dsmcx

@@ -383,6 +383,8 @@ __global__ void k_dig_ctl_reset(DigCtl* ctl) {
     ctl->n_rejected = 0;
     ctl->n_reconstructed = 0;
     ctl->n_unreached = 0;
+    ctl->n_closure = 0;
+    ctl->n_fallback = 0;
 }
 
 __global__ void k_dig_copy(const double* src, double* dst, int64_t n) {
@@ -734,6 +736,85 @@ __global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// learned closure: inputs, targets and the gate against the sampled HoT
+// ---------------------------------------------------------------------------
+// Per cell with samples: lambda = Kn_Delta d_c (local mean free path);
+// inputs lambda du_i/dx_j / sqrt(RT), lambda dT/dx_j / T, Kn_Delta; targets
+// HoT / p and HoT_q / (p sqrt(RT)); the sampled stress and heat flux in the
+// same units (the gate's scale).
+__global__ void k_dig_closure_prep(DigGeom g, DigWork w) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt) return;
+    const double* P = w.prim + kDigNV * (size_t)c;
+    const double kn = w.kn[c];
+    const double rho = P[0], T = P[4];
+    const bool valid = w.ok[c] && isfinite(kn) && rho > 0 && T > 0;
+    float* x = w.cx + 13 * (size_t)c;
+    float* t = w.ct + 9 * (size_t)c;
+    float* sc = w.cs + 9 * (size_t)c;
+    w.cvalid[c] = valid ? 1 : 0;
+    if (!valid) {
+        for (int k = 0; k < 13; ++k) x[k] = 0.f;
+        for (int k = 0; k < 9; ++k) t[k] = sc[k] = 0.f;
+        return;
+    }
+    const double dc = 2.0 * cbrt(3.0 * g.vol[c] / (4.0 * M_PI));
+    const double lam = kn * dc;
+    const double cs = sqrt(g.R * T);
+    const double p = rho * g.R * T;
+    const double* gr = w.grad + 15 * (size_t)c;
+    for (int k = 0; k < 9; ++k) x[k] = (float)(lam * gr[3 + k] / cs);
+    for (int k = 0; k < 3; ++k) x[9 + k] = (float)(lam * gr[12 + k] / T);
+    x[12] = (float)kn;
+    const double* h = w.hot + 9 * (size_t)c;
+    const double* a = w.samp + 14 * (size_t)c;
+    for (int k = 0; k < 6; ++k) {
+        t[k] = (float)(h[k] / p);
+        sc[k] = (float)(a[5 + k] / p);
+    }
+    for (int k = 6; k < 9; ++k) {
+        t[k] = (float)(h[k] / (p * cs));
+        sc[k] = (float)(a[5 + k] / (p * cs));
+    }
+}
+
+// Take the network's HoT where its distance to the sampled HoT, relative
+// to max(|sampled stress, heat flux|, 1e-3), is at most tol.
+__global__ void k_dig_closure_gate(DigGeom g, DigWork w, double tol) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    int used = 0, fell = 0;
+    if (c < g.nt && w.cvalid[c]) {
+        const float* y = w.cy + 9 * (size_t)c;
+        const float* t = w.ct + 9 * (size_t)c;
+        const float* sc = w.cs + 9 * (size_t)c;
+        double d2 = 0.0, s2 = 0.0;
+        for (int k = 0; k < 9; ++k) {
+            const double d = (double)y[k] - (double)t[k];
+            d2 += d * d;
+            s2 += (double)sc[k] * (double)sc[k];
+        }
+        const double e = sqrt(d2) / fmax(sqrt(s2), 1e-3);
+        if (isfinite(e) && e <= tol) {
+            const double* P = w.prim + kDigNV * (size_t)c;
+            const double p = P[0] * g.R * P[4];
+            const double cs = sqrt(g.R * P[4]);
+            double* h = w.hot + 9 * (size_t)c;
+            for (int k = 0; k < 6; ++k) h[k] = (double)y[k] * p;
+            for (int k = 6; k < 9; ++k) h[k] = (double)y[k] * (p * cs);
+            used = 1;
+        } else {
+            fell = 1;
+        }
+    }
+    used = wave_sum_i(used);
+    fell = wave_sum_i(fell);
+    if ((threadIdx.x & 63) == 0) {
+        if (used) atomicAdd(&w.ctl->n_closure, used);
+        if (fell) atomicAdd(&w.ctl->n_fallback, fell);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
 static inline dim3 cells_grid(int64_t n) { return dim3((unsigned)((n + kDigThreads - 1) / kDigThreads)); }
@@ -818,6 +899,14 @@ void launch_dig_count_all(hipStream_t s, const int32_t* cell, const Scalars* sc,
                           int64_t bound) {
     hipLaunchKernelGGL(k_dig_count_all, cells_grid(bound > 0 ? bound : 1), dim3(kDigThreads), 0, s, cell, sc, counts,
                        rank);
+}
+
+void launch_dig_closure_prep(hipStream_t s, const DigGeom& g, DigWork w) {
+    hipLaunchKernelGGL(k_dig_closure_prep, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w);
+}
+
+void launch_dig_closure_gate(hipStream_t s, const DigGeom& g, DigWork w, double tol) {
+    hipLaunchKernelGGL(k_dig_closure_gate, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w, tol);
 }
 
 void launch_fill_u8(hipStream_t s, uint8_t* p, uint8_t v, int64_t n) {

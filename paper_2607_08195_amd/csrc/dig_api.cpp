@@ -11,6 +11,7 @@
 #include "../../include/dig.h"
 #include "context.h"
 #include "dig.h"
+#include "mlp.h"
 
 namespace dsmcx {
 
@@ -162,7 +163,9 @@ dsmc_status ensure(dsmc_ctx c) {
          alloc_n(c, w.state, nt) && alloc_n(c, w.mprev, 5 * (size_t)nt) && alloc_n(c, w.Rs, 5 * (size_t)nt) &&
          alloc_n(c, w.dt, nt) && alloc_n(c, w.U0, 5 * (size_t)nt) && alloc_n(c, w.stage, 5 * (size_t)nt) &&
          alloc_n(c, w.partial, 2 * (size_t)d->nblk) && alloc_n(c, w.ctl, 1) && alloc_n(c, w.fb_cnt, nt) &&
-         alloc_n(c, w.fb_off, nt + 1) && alloc_n(c, w.fb_tgt, nt);
+         alloc_n(c, w.fb_off, nt + 1) && alloc_n(c, w.fb_tgt, nt) && alloc_n(c, w.cx, 13 * (size_t)nt) &&
+         alloc_n(c, w.ct, 9 * (size_t)nt) && alloc_n(c, w.cs, 9 * (size_t)nt) && alloc_n(c, w.cy, 9 * (size_t)nt) &&
+         alloc_n(c, w.cvalid, nt);
     if (!ok) {
         delete d;
         return fail(c, DSMC_E_OOM, "device allocation of the coupling state failed");
@@ -353,6 +356,11 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
     launch_dig_kn(s, d->g, d->w, kn_ref, T0, rho0, p->L0);
     launch_dig_gradients(s, d->g, d->w.prim, d->w.grad, nullptr);
     launch_dig_hot(s, d->g, d->w);
+    launch_dig_closure_prep(s, d->g, d->w);
+    if (c->closure) {
+        launch_mlp_forward(s, mlp_handle_view(c->closure), d->w.cx, nullptr, nt, d->w.cy);
+        launch_dig_closure_gate(s, d->g, d->w, c->gate_tol);
+    }
     launch_dig_gate(s, d->g, d->w, p->kn_max, p->passes);
     launch_dig_copy(s, d->w.prim, d->w.half, 5 * (int64_t)nt);
     HIP_TRY(c, hipGetLastError());
@@ -361,6 +369,8 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
     r.n_rejected = h.n_rejected;
     r.n_reconstructed = h.n_reconstructed;
     r.n_unreached = h.n_unreached;
+    r.n_closure = h.n_closure;
+    r.n_fallback = h.n_fallback;
     if (r.n_rejected < nt) {
         if ((st = run_solve(c, p, &r)) != DSMC_OK) return st;
         if (!r.failed) {
@@ -440,6 +450,23 @@ dsmc_status dig_feedback(dsmc_ctx c, const double* prim_old, const double* prim_
         if ((st = sync_scalars(c, &sc)) != DSMC_OK) return st;
         *np_after = sc.np;
     }
+    return DSMC_OK;
+}
+
+dsmc_status dig_set_closure(dsmc_ctx c, dsmc_mlp net, double gate_tol) {
+    if (!c || !(gate_tol >= 0)) return fail(c, DSMC_E_INVALID, "bad arguments");
+    c->closure = net;
+    c->gate_tol = gate_tol;
+    return DSMC_OK;
+}
+
+dsmc_status dig_closure_data(dsmc_ctx c, float* x, float* t, uint8_t* valid) {
+    dsmc_status st = usable(c);
+    if (st != DSMC_OK) return st;
+    const DigWork& w = c->dig->w;
+    if (x && (st = to_host(c, x, w.cx, 13)) != DSMC_OK) return st;
+    if (t && (st = to_host(c, t, w.ct, 9)) != DSMC_OK) return st;
+    if (valid && (st = to_host(c, valid, w.cvalid, 1)) != DSMC_OK) return st;
     return DSMC_OK;
 }
 

@@ -75,7 +75,21 @@ class DigParams(C.Structure):
 class DigReport(C.Structure):
     _fields_ = [("iters", C.c_int32), ("residual", C.c_double), ("converged", C.c_int32), ("failed", C.c_int32),
                 ("n_rejected", C.c_int32), ("n_reconstructed", C.c_int32), ("n_unreached", C.c_int32),
-                ("np_before", C.c_int64), ("np_after", C.c_int64)]
+                ("np_before", C.c_int64), ("np_after", C.c_int64), ("n_closure", C.c_int32),
+                ("n_fallback", C.c_int32)]
+
+
+class MlpTrainParams(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64)]
+
+
+class MlpTrainReport(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("loss_first", C.c_double), ("loss_last", C.c_double)]
+
+
+MLP_PARAMS = 35977
+MLP_IN, MLP_OUT = 13, 9
 
 
 DIG_OUT = {"sampled": (0, 14), "half": (1, 5), "new": (2, 5), "hot": (3, 9), "kn": (4, 1), "state": (5, 1),
@@ -119,17 +133,33 @@ _lib.dig_residual.argtypes = [ctx_t, P, P, P]
 _lib.dig_solve.argtypes = [ctx_t, P, P, C.POINTER(DigParams), C.POINTER(DigReport)]
 _lib.dig_feedback.argtypes = [ctx_t, P, P, P, C.POINTER(C.c_int64)]
 _lib.dsmc_set_sums.argtypes = [ctx_t, C.c_int32, P]
+_lib.dsmc_mlp_create.argtypes = [C.POINTER(P), P, C.POINTER(Allocator)]
+_lib.dsmc_mlp_set_weights.argtypes = [P, P]
+_lib.dsmc_mlp_get_weights.argtypes = [P, P]
+_lib.dsmc_mlp_forward.argtypes = [P, P, C.c_int64, P, C.c_int32]
+_lib.dsmc_mlp_backward.argtypes = [P, P, P, C.c_int64, P, C.POINTER(C.c_double)]
+_lib.dsmc_mlp_adam_step.argtypes = [P, P, C.c_float, C.c_float, C.c_float, C.c_float]
+_lib.dsmc_mlp_train.argtypes = [P, P, P, C.c_int64, C.POINTER(MlpTrainParams), C.POINTER(MlpTrainReport)]
+_lib.dsmc_mlp_last_error.argtypes = [P]
+_lib.dsmc_mlp_last_error.restype = C.c_char_p
+_lib.dsmc_mlp_destroy.argtypes = [P]
+_lib.dig_set_closure.argtypes = [ctx_t, P, C.c_double]
+_lib.dig_closure_data.argtypes = [ctx_t, P, P, P]
 for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_state",
            "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
            "dsmc_profile", "dsmc_philox", "dsmc_device_copy", "dig_couple", "dig_get", "dig_residual",
-           "dig_solve", "dig_feedback", "dsmc_set_sums"]:
+           "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
+           "dsmc_mlp_get_weights", "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train",
+           "dig_set_closure", "dig_closure_data"]:
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_state",
             "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
             "dsmc_profile", "dsmc_profile_read", "dsmc_profile_name", "dsmc_philox", "dsmc_device_copy",
             "dsmc_last_error", "dsmc_destroy", "dig_couple", "dig_get", "dig_residual", "dig_solve",
-            "dig_feedback", "dsmc_set_sums"]
+            "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights", "dsmc_mlp_get_weights",
+            "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train", "dsmc_mlp_last_error",
+            "dsmc_mlp_destroy", "dig_set_closure", "dig_closure_data"]
 
 
 class DsmcError(RuntimeError):
@@ -344,3 +374,81 @@ class Simulation:
         n = C.c_int64()
         self._c(_lib.dig_feedback(self.ctx, _p(a), _p(b), _p(st), C.byref(n)))
         return int(n.value)
+
+    def set_closure(self, mlp, gate_tol=0.05):
+        """Attach a trained Mlp as the HoT closure of dig_couple (None detaches)."""
+        self._closure = mlp
+        self._c(_lib.dig_set_closure(self.ctx, mlp.h if mlp is not None else None, gate_tol))
+
+    def closure_data(self):
+        x = np.zeros((self.nt, MLP_IN), np.float32)
+        t = np.zeros((self.nt, MLP_OUT), np.float32)
+        v = np.zeros(self.nt, np.uint8)
+        self._c(_lib.dig_closure_data(self.ctx, _p(x), _p(t), _p(v)))
+        return x, t, v.astype(bool)
+
+
+class Mlp:
+    """The learned HoT closure (include/mlp.h) on one GPU."""
+
+    def __init__(self, device=0, stream=None, torch_memory=True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the MLP kernels run on the GPU only")
+        torch.cuda.set_device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._alloc = _TorchAllocator(device, self.stream) if torch_memory else None
+        self.h = P()
+        st = _lib.dsmc_mlp_create(C.byref(self.h), P(self.stream.cuda_stream),
+                                  C.pointer(self._alloc.desc) if self._alloc else None)
+        if st != 0:
+            raise DsmcError(st, _lib.dsmc_mlp_last_error(None).decode())
+
+    def _c(self, status):
+        if status != 0:
+            raise DsmcError(status, _lib.dsmc_mlp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.dsmc_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, p):
+        a = np.ascontiguousarray(p, np.float32)
+        if a.size != MLP_PARAMS:
+            raise ValueError("expected 35977 parameters")
+        self._c(_lib.dsmc_mlp_set_weights(self.h, _p(a)))
+
+    def get_weights(self):
+        a = np.zeros(MLP_PARAMS, np.float32)
+        self._c(_lib.dsmc_mlp_get_weights(self.h, _p(a)))
+        return a
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, np.float32)
+        y = np.zeros((x.shape[0], MLP_OUT), np.float32)
+        self._c(_lib.dsmc_mlp_forward(self.h, _p(x), x.shape[0], _p(y), 0))
+        return y
+
+    def backward(self, x, t):
+        x = np.ascontiguousarray(x, np.float32); t = np.ascontiguousarray(t, np.float32)
+        g = np.zeros(MLP_PARAMS, np.float32)
+        loss = C.c_double()
+        self._c(_lib.dsmc_mlp_backward(self.h, _p(x), _p(t), x.shape[0], _p(g), C.byref(loss)))
+        return float(loss.value), g
+
+    def adam_step(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        g = np.ascontiguousarray(grad, np.float32)
+        self._c(_lib.dsmc_mlp_adam_step(self.h, _p(g), lr, beta1, beta2, eps))
+
+    def train(self, x, t, steps, batch=0, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
+        x = np.ascontiguousarray(x, np.float32); t = np.ascontiguousarray(t, np.float32)
+        prm = MlpTrainParams(steps, batch, lr, beta1, beta2, eps, seed)
+        rep = MlpTrainReport()
+        self._c(_lib.dsmc_mlp_train(self.h, _p(x), _p(t), x.shape[0], C.byref(prm), C.byref(rep)))
+        return dict(steps=rep.steps, loss_first=rep.loss_first, loss_last=rep.loss_last)
