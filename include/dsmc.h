@@ -207,6 +207,51 @@ dsmc_status dsmc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out,
  * stream (HBM bandwidth calibration of the traffic counters). */
 dsmc_status dsmc_device_copy(dsmc_ctx ctx, void* dst, const void* src, size_t bytes);
 
+/* ---- batches, graphs and kernel schedules ------------------------------ */
+
+/* Many independent cases in one context (a batch): the cases' meshes are
+ * joined into one mesh whose cells never touch across cases, so every
+ * kernel launch of a step advances all cases at once.  meshes[n_cases],
+ * n_bc[n_cases] and runs[n_cases] are per case; bcs holds the boundary
+ * tables of all cases one after the other (case k's groups are numbered
+ * from 0 in its own mesh).  Per case: n0, T0, u0, F_N, dt, seed and case_id
+ * (the generator key (seed, case_id), cell subjects and particle ids are
+ * case-local, so each case evolves as it would in a context of its own).
+ * Batch-wide, from runs[0]: vel_fp64, n_ss, n_a, ewma_on, fill, capacity,
+ * hip_stream, allocator.  Freestream inflow and the coupling step (dig.h)
+ * are not available for a batch.  Every other call works on the joined
+ * mesh: cells are numbered case after case in the callers' order
+ * (dsmc_batch_cases gives the first cell of each case). */
+dsmc_status dsmc_batch_init(dsmc_ctx* out, int32_t n_cases, const dsmc_mesh_desc* meshes,
+                            const dsmc_species_desc* species, const int32_t* n_bc,
+                            const dsmc_boundary_desc* bcs, const dsmc_run_desc* runs);
+/* *n_cases (1 for a plain context) and cell_begin[n_cases + 1]: case k owns
+ * cells cell_begin[k] .. cell_begin[k+1]-1 (cell_begin may be NULL). */
+dsmc_status dsmc_batch_cases(dsmc_ctx ctx, int32_t* n_cases, int32_t* cell_begin);
+
+/* Advance n_steps full steps through a captured HIP graph: two steps are
+ * recorded once (per particle-buffer parity and kernel schedule) and
+ * replayed; an odd remainder runs as an ordinary step.  Kernel grids cover
+ * the whole particle store; the kernels bound themselves by the device
+ * counts.  Needs a non-null hip_stream.  Results equal dsmc_step's. */
+dsmc_status dsmc_graph_step(dsmc_ctx ctx, int32_t n_steps);
+
+/* Kernel schedule: move 0 lane, 1 lane (6 waves/SIMD), 2 lane (8),
+ * 3 batched, 4/5/6/7 parked-wall at 6/8/4/5 waves/SIMD, 8/9 refill,
+ * 10/11 pooled; collide 0 LDS-staged velocities, 1/2 LDS-ranked at
+ * 4/8 waves/SIMD; sort 0 scatter, 1 gather.  Every schedule gives the same
+ * results.  A batch accepts only move 0-2 and 4-7. */
+typedef struct {
+    int32_t move, collide, sort;
+    double move_ms, collide_ms, sort_ms;  /* per step, filled by dsmc_autotune */
+} dsmc_tuning;
+dsmc_status dsmc_get_tuning(dsmc_ctx ctx, dsmc_tuning* t);
+dsmc_status dsmc_set_tuning(dsmc_ctx ctx, const dsmc_tuning* t);
+/* Time each move, collide and sort schedule over trial_steps real steps
+ * (after one warm-up step each) on the current workload and keep the
+ * fastest; the simulation advances by those steps. */
+dsmc_status dsmc_autotune(dsmc_ctx ctx, int32_t trial_steps, dsmc_tuning* chosen);
+
 const char* dsmc_last_error(dsmc_ctx ctx);
 void dsmc_destroy(dsmc_ctx ctx);
 

@@ -95,14 +95,14 @@ struct Timed {
     int slot;
     hipEvent_t a = nullptr, b = nullptr;
     Timed(dsmc_ctx c_, int s) : c(c_), slot(s) {
-        if (c->profiling) {
+        if (c->profiling && !c->capturing) {
             a = get_event(c);
             b = get_event(c);
             if (a) hipEventRecord(a, c->stream);
         }
     }
     ~Timed() {
-        if (c->profiling && a && b) {
+        if (c->profiling && !c->capturing && a && b) {
             hipEventRecord(b, c->stream);
             c->ev_used.push_back({slot, {a, b}});
         }
@@ -114,8 +114,10 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
     const bool mv = mask & 1, inj = (mask & 2) && c->inflow.n > 0, srt = mask & 4, col = mask & 8,
                smp = mask & 16;
     if ((col || smp) && mv && !srt) return fail(c, DSMC_E_INVALID, "collide/sample after move needs sort");
-    const int64_t need = c->np_bound + (inj ? c->max_inject : 0);
-    if (need > c->cap) {
+    // Under graph capture nothing may synchronise: grids cover the whole
+    // store and the kernels bound themselves by the device-side counts.
+    const int64_t need = c->capturing ? c->cap : c->np_bound + (inj ? c->max_inject : 0);
+    if (!c->capturing && need > c->cap) {
         dsmc_status st = sync_scalars(c, nullptr);
         if (st != DSMC_OK) return st;
         if (c->np_bound + (inj ? c->max_inject : 0) > c->cap)
@@ -129,8 +131,8 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
     }
     if (mv) {
         Timed t(c, kSlotMove);
-        launch_move<VT>(s, c->mesh, a, c->d_sc, c->d_counts, c->d_rank, c->d_ctr, c->key, c->dt, c->np_bound,
-                        c->move_variant, c->move_batch, c->wq);
+        launch_move<VT>(s, c->mesh, a, c->d_sc, c->d_counts, c->d_rank, c->d_ctr, c->key, c->dt,
+                        c->capturing ? c->cap : c->np_bound, c->move_variant, c->move_batch, c->wq);
     }
     if (mv && move_parks_walls(c->move_variant)) {
         Timed t(c, kSlotWalls);
@@ -144,7 +146,7 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
                                c->key, c->dt, c->cap, c->max_inject);
     }
     if (srt) {
-        if (!mv && !inj) launch_count(s, a.cell, c->d_sc, c->d_counts, c->d_rank, c->np_bound);
+        if (!mv && !inj) launch_count(s, a.cell, c->d_sc, c->d_counts, c->d_rank, c->capturing ? c->cap : c->np_bound);
         {
             Timed t(c, kSlotScan);
             launch_scan(s, c->d_counts, c->nt, c->d_offsets, c->d_blocksums, c->d_sc, kScanCells);
@@ -169,6 +171,8 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
         cp.vol = c->d_vol; cp.smax = c->d_smax; cp.ncand = c->d_ncand; cp.nacc = c->d_nacc;
         cp.acc = c->d_acc; cp.ewma = c->d_ewma; cp.ewma_m = c->d_ewma_m; cp.local_acc = c->d_local;
         cp.orig = c->d_orig;
+        cp.cell_case = c->d_cell_case;
+        cp.cases = c->d_cases;
         launch_collide_sample<VT>(s, a, c->d_offsets, cp, c->d_sc, c->d_perm, col ? 1 : 0, smp ? 1 : 0,
                                   c->collide_variant);
     }
@@ -213,19 +217,89 @@ void read_tuning(dsmc_ctx c) {
     }
 }
 
+
+int tuning_sig(dsmc_ctx c) { return c->move_variant | (c->collide_variant << 8) | (c->sort_variant << 12); }
+
+void drop_graph(dsmc_ctx_s::Graph& g) {
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    if (g.graph) hipGraphDestroy(g.graph);
+    g = dsmc_ctx_s::Graph{};
+}
+
+// Record two full steps (the buffers swap twice, so a replay leaves them as
+// it found them) into a graph and instantiate it.
+dsmc_status capture_two_steps(dsmc_ctx c, dsmc_ctx_s::Graph& g) {
+    drop_graph(g);
+    const void* a_x = c->A.x;
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    dsmc_status st = step_any(c, 31);
+    if (st == DSMC_OK) st = step_any(c, 31);
+    c->capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    if (st != DSMC_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess || !graph) {
+        c->broken = true;
+        return fail(c, DSMC_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    g.graph = graph;
+    HIP_TRY(c, hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+    g.a_x = a_x;
+    g.sig = tuning_sig(c);
+    return DSMC_OK;
+}
+
+// Mean milliseconds per step of the given profile slots over `steps` steps.
+dsmc_status time_slots(dsmc_ctx c, int steps, std::initializer_list<int> slots, double* ms) {
+    dsmc_status st = step_any(c, 31);  // untimed warm-up with the candidate
+    if (st != DSMC_OK) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto& u : c->ev_used) {
+        c->ev_pool.push_back(u.second.first);
+        c->ev_pool.push_back(u.second.second);
+    }
+    c->ev_used.clear();
+    c->profiling = true;
+    for (int i = 0; i < steps && st == DSMC_OK; ++i) st = step_any(c, 31);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double tot = 0;
+    for (auto& u : c->ev_used) {
+        float t = 0;
+        for (int sl : slots)
+            if (u.first == sl && hipEventElapsedTime(&t, u.second.first, u.second.second) == hipSuccess) tot += t;
+    }
+    c->profiling = false;
+    *ms = tot / std::max(1, steps);
+    return st;
+}
+
 template <class VT>
 void fill_dispatch(dsmc_ctx c, double sig) {
-    launch_init_fill<VT>(c->stream, c->d_tv, c->d_xyz, c->nt, c->d_offsets, c->d_orig, c->d_cell_tmp,
-                         as_dev<VT>(c->A), c->key, sig, c->u0, c->cap, c->d_sc);
+    const int32_t* pid_base = c->d_cell_case ? c->d_counts_orig : c->d_cell_tmp;
+    launch_init_fill<VT>(c->stream, c->d_tv, c->d_xyz, c->nt, c->d_offsets, c->d_orig, pid_base, as_dev<VT>(c->A),
+                         c->key, sig, c->u0, c->cap, c->d_sc, c->d_cell_case, c->d_cases);
 }
+
+// Cases of a batch: per-case run parameters, the case of every cell of the
+// union mesh (caller numbering) and the first cell of each case.
+struct BatchSpec {
+    std::vector<dsmc_run_desc> runs;
+    std::vector<int32_t> tet_case;
+    std::vector<int32_t> cell0;
+};
 
 }  // namespace
 
 // ===========================================================================
-extern "C" {
-
-dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_species_desc* sp, int32_t n_bc,
-                      const dsmc_boundary_desc* bcs, const dsmc_run_desc* run) {
+// Context construction shared by the single-case and the batch entry points.
+// With a batch, `run` carries the batch-wide settings (velocity storage,
+// sampling, capacity, stream, allocator, fill) and bs the per-case ones.
+dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_species_desc* sp, int32_t n_bc,
+                      const dsmc_boundary_desc* bcs, const dsmc_run_desc* run, const BatchSpec* bs) {
     if (!out) return fail(nullptr, DSMC_E_INVALID, "out is NULL");
     *out = nullptr;
     if (!mesh || !sp || !run || (n_bc > 0 && !bcs) || n_bc < 0)
@@ -255,7 +329,7 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     }
     HostMesh& hm = c->hm;
     read_tuning(c);
-    if (c->reorder) reorder_cells(hm);
+    if (c->reorder) reorder_cells(hm, bs ? &bs->tet_case : nullptr);
     else {
         hm.orig.resize(hm.nt);
         std::iota(hm.orig.begin(), hm.orig.end(), 0);
@@ -280,10 +354,17 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     c->vel64 = run->vel_fp64 ? 1 : 0;
     c->bcs.assign(bcs, bcs + n_bc);
     c->n_ss = run->n_ss; c->n_a = run->n_a; c->ewma_on = run->ewma_on ? 1 : 0;
+    if (bs && c->move_variant != kMoveLane && c->move_variant != kMoveLaneW6 && c->move_variant != kMoveLaneW8 &&
+        c->move_variant != kMoveDefer4 && c->move_variant != kMoveDefer5 && c->move_variant != kMoveDefer6 &&
+        c->move_variant != kMoveDefer8)
+        c->move_variant = kMoveDefer6;  // the batch tables are read by the lane and deferring kernels
 
     // expected particle count at n0 sizes the default capacity
     double fill_total = 0;
-    for (int t = 0; t < hm.nt; ++t) fill_total += (run->n0 * hm.vol[t]) / run->F_N + 1.0;
+    for (int t = 0; t < hm.nt; ++t) {
+        const dsmc_run_desc* rc = bs ? &bs->runs[bs->tet_case[t]] : run;
+        fill_total += (rc->n0 * hm.vol[t]) / rc->F_N + 1.0;
+    }
     c->cap = run->capacity > 0 ? run->capacity : std::max<int64_t>(1024, (int64_t)(2.0 * fill_total) + 1024);
     if (c->cap >= ((int64_t)1 << 31) - 1) {
         delete c;
@@ -296,6 +377,10 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     for (int b = 0; b < hm.nb; ++b) {
         const dsmc_boundary_desc& g = bcs[hm.bf_group[b]];
         if (g.kind != DSMC_BC_INFLOW) continue;
+        if (bs) {
+            delete c;
+            return fail(nullptr, DSMC_E_INVALID, "freestream inflow is not supported in a batch");
+        }
         const double* fr = &hm.bf_frame[9 * (size_t)b];
         const double* nin = fr;
         const double* t1 = fr + 3;
@@ -410,7 +495,45 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     // cell state
     const double eq = (((2.0 * DSMC_SQRT_PI) * sp->d_ref) * sp->d_ref) * std::sqrt(((2.0 * kBoltzmann) * sp->T_ref) / mr) *
                       std::pow(run->T0 / sp->T_ref, 1.0 - sp->omega);
-    launch_fill_f64(s, c->d_smax, 2.0 * eq, nt);
+    if (bs) {
+        // per-case table; cell subjects and particle ids are case-local
+        std::vector<CaseDev> cases(bs->runs.size());
+        for (size_t k = 0; k < cases.size(); ++k) {
+            const dsmc_run_desc& r = bs->runs[k];
+            CaseDev& d = cases[k];
+            d.dt = r.dt; d.FN = r.F_N; d.n0 = r.n0; d.T0 = r.T0;
+            d.sig = std::sqrt((kBoltzmann * r.T0) / sp->mass);
+            for (int i = 0; i < 3; ++i) d.u0[i] = r.u0[i];
+            const double eqk = (((2.0 * DSMC_SQRT_PI) * sp->d_ref) * sp->d_ref) *
+                               std::sqrt(((2.0 * kBoltzmann) * sp->T_ref) / mr) * std::pow(r.T0 / sp->T_ref, 1.0 - sp->omega);
+            d.smax0 = 2.0 * eqk;
+            d.k0 = (uint32_t)(r.seed & 0xFFFFFFFFu);
+            d.k1 = r.case_id;
+            d.cell0 = bs->cell0[k];
+            d.pad = 0;
+        }
+        std::vector<int32_t> cc(nt), first(cases.size());
+        for (int t = 0; t < nt; ++t) cc[t] = bs->tet_case[hm.orig[t]];
+        for (size_t k = 0; k < cases.size(); ++k) first[k] = bs->cell0[k];
+        bool okb = alloc_n(c, c->d_cases, cases.size()) && alloc_n(c, c->d_cell_case, nt) &&
+                   alloc_n(c, c->d_case_of_orig, nt) && alloc_n(c, c->d_case_first, cases.size());
+        if (!okb) {
+            dsmc_destroy(c);
+            return fail(nullptr, DSMC_E_OOM, "device allocation failed");
+        }
+        UP(c->d_cases, cases.data(), sizeof(CaseDev) * cases.size());
+        UP(c->d_cell_case, cc.data(), sizeof(int32_t) * nt);
+        UP(c->d_case_of_orig, bs->tet_case.data(), sizeof(int32_t) * nt);
+        UP(c->d_case_first, first.data(), sizeof(int32_t) * first.size());
+        HIP_TRY(c, hipStreamSynchronize(s));
+        c->n_cases = (int)cases.size();
+        c->case_cell0 = bs->cell0;
+        c->mesh.cell_case = c->d_cell_case;
+        c->mesh.cases = c->d_cases;
+        launch_batch_smax(s, c->d_cell_case, c->d_cases, nt, c->d_smax);
+    } else {
+        launch_fill_f64(s, c->d_smax, 2.0 * eq, nt);
+    }
     launch_fill_i32(s, c->d_ncand, 0, nt);
     launch_fill_i32(s, c->d_nacc, 0, nt);
     launch_fill_f64(s, c->d_acc, 0.0, (int64_t)kNMom * nt);
@@ -421,8 +544,11 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
 
     if (run->fill) {
         // counts per cell; particle ids follow the caller's cell order
-        launch_init_count(s, c->d_vol, c->d_orig, nt, run->n0, run->F_N, c->key, c->d_counts, c->d_counts_orig);
+        launch_init_count(s, c->d_vol, c->d_orig, nt, run->n0, run->F_N, c->key, c->d_counts, c->d_counts_orig,
+                          c->d_cell_case, c->d_cases);
         launch_scan(s, c->d_counts_orig, nt, c->d_cell_tmp, c->d_blocksums, c->d_sc, kScanPlain);
+        if (bs)  // particle ids restart in every case: base = prefix - prefix at the case's first cell
+            launch_batch_pid_base(s, c->d_cell_tmp, c->d_case_first, c->d_case_of_orig, nt, c->d_counts_orig);
         launch_scan(s, c->d_counts, nt, c->d_offsets, c->d_blocksums, c->d_sc, kScanInit);
         const double sig = std::sqrt((kBoltzmann * run->T0) / sp->mass);
         if (c->vel64) fill_dispatch<double>(c, sig); else fill_dispatch<float>(c, sig);
@@ -440,6 +566,144 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
         return fail(nullptr, st, m);
     }
     *out = c;
+    return DSMC_OK;
+}
+
+extern "C" {
+
+dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_species_desc* sp, int32_t n_bc,
+                      const dsmc_boundary_desc* bcs, const dsmc_run_desc* run) {
+    return init_impl(out, mesh, sp, n_bc, bcs, run, nullptr);
+}
+
+dsmc_status dsmc_batch_init(dsmc_ctx* out, int32_t n_cases, const dsmc_mesh_desc* meshes,
+                            const dsmc_species_desc* sp, const int32_t* n_bc, const dsmc_boundary_desc* bcs,
+                            const dsmc_run_desc* runs) {
+    if (!out) return fail(nullptr, DSMC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_cases < 1 || !meshes || !sp || !n_bc || !runs) return fail(nullptr, DSMC_E_INVALID, "bad batch arguments");
+    BatchSpec bs;
+    std::vector<double> xyz;
+    std::vector<int32_t> tets, bfv, bgrp, bpart;
+    int32_t nv = 0, nt = 0, nb = 0, ng = 0;
+    std::vector<dsmc_boundary_desc> groups;
+    for (int k = 0; k < n_cases; ++k) {
+        const dsmc_mesh_desc& m = meshes[k];
+        const dsmc_run_desc& r = runs[k];
+        if (m.n_vertices <= 0 || m.n_tets <= 0 || !m.xyz || !m.tet_vtx || (m.n_bfaces > 0 && (!m.bface_vtx || !m.bface_group)))
+            return fail(nullptr, DSMC_E_INVALID, "bad mesh of a batch case");
+        if (!(r.F_N > 0) || !(r.dt > 0)) return fail(nullptr, DSMC_E_INVALID, "non-positive physical parameter");
+        if (n_bc[k] < 0) return fail(nullptr, DSMC_E_INVALID, "bad boundary count");
+        if ((int64_t)nt + m.n_tets >= ((int64_t)1 << 28)) return fail(nullptr, DSMC_E_INVALID, "batch too large");
+        xyz.insert(xyz.end(), m.xyz, m.xyz + 3 * (size_t)m.n_vertices);
+        for (int64_t i = 0; i < 4 * (int64_t)m.n_tets; ++i) tets.push_back(m.tet_vtx[i] + nv);
+        for (int64_t i = 0; i < 3 * (int64_t)m.n_bfaces; ++i) bfv.push_back(m.bface_vtx[i] + nv);
+        for (int64_t i = 0; i < m.n_bfaces; ++i) {
+            bgrp.push_back(m.bface_group[i] + ng);
+            const int32_t pp = m.bface_partner ? m.bface_partner[i] : -1;
+            bpart.push_back(pp >= 0 ? pp + nb : -1);
+        }
+        for (int g = 0; g < n_bc[k]; ++g) groups.push_back(bcs[ng + g]);
+        bs.runs.push_back(r);
+        bs.cell0.push_back(nt);
+        for (int t = 0; t < m.n_tets; ++t) bs.tet_case.push_back(k);
+        nv += m.n_vertices;
+        nt += m.n_tets;
+        nb += m.n_bfaces;
+        ng += n_bc[k];
+    }
+    dsmc_mesh_desc u{nv, xyz.data(), nt, tets.data(), nb, bfv.data(), bgrp.data(), bpart.data()};
+    return init_impl(out, &u, sp, ng, groups.data(), &runs[0], &bs);
+}
+
+dsmc_status dsmc_batch_cases(dsmc_ctx c, int32_t* n_cases, int32_t* cell_begin) {
+    if (!c || !n_cases) return fail(c, DSMC_E_INVALID, "bad arguments");
+    const int n = std::max(1, c->n_cases);
+    *n_cases = n;
+    if (cell_begin) {
+        for (int k = 0; k < n; ++k) cell_begin[k] = c->n_cases ? c->case_cell0[k] : 0;
+        cell_begin[n] = c->nt;
+    }
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_graph_step(dsmc_ctx c, int32_t n) {
+    if (!c || n < 0) return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
+    if (!c->stream) return fail(c, DSMC_E_INVALID, "graph stepping needs a non-null HIP stream");
+    int done = 0;
+    while (done + 2 <= n) {
+        dsmc_ctx_s::Graph* g = nullptr;
+        for (auto& cand : c->graphs)
+            if (cand.exec && cand.a_x == c->A.x && cand.sig == tuning_sig(c)) g = &cand;
+        if (!g) {
+            g = (c->graphs[0].a_x == c->A.x || !c->graphs[0].exec) ? &c->graphs[0] : &c->graphs[1];
+            dsmc_status st = capture_two_steps(c, *g);
+            if (st != DSMC_OK) return st;
+        }
+        HIP_TRY(c, hipGraphLaunch(g->exec, c->stream));
+        done += 2;
+        c->np_bound = c->cap;  // device-side count unknown until the next synchronising call
+    }
+    if (done < n) return step_any(c, 31);
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_get_tuning(dsmc_ctx c, dsmc_tuning* t) {
+    if (!c || !t) return fail(c, DSMC_E_INVALID, "bad arguments");
+    t->move = c->move_variant;
+    t->collide = c->collide_variant;
+    t->sort = c->sort_variant;
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_set_tuning(dsmc_ctx c, const dsmc_tuning* t) {
+    if (!c || !t) return fail(c, DSMC_E_INVALID, "bad arguments");
+    const bool batch_ok = t->move == kMoveLane || t->move == kMoveLaneW6 || t->move == kMoveLaneW8 ||
+                          (t->move >= kMoveDefer6 && t->move <= kMoveDefer5);
+    if (t->move < 0 || t->move > kMovePool256 || t->collide < 0 || t->collide > kCollideGlobal8 || t->sort < 0 ||
+        t->sort > kSortGather || (c->n_cases && !batch_ok))
+        return fail(c, DSMC_E_INVALID, "unknown or unsupported kernel variant");
+    c->move_variant = t->move;
+    c->collide_variant = t->collide;
+    c->sort_variant = t->sort;
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_autotune(dsmc_ctx c, int32_t trial_steps, dsmc_tuning* out) {
+    if (!c || trial_steps < 1) return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
+    const bool was_profiling = c->profiling;
+    dsmc_tuning best{c->move_variant, c->collide_variant, c->sort_variant, 1e300, 1e300, 1e300};
+    const int moves[] = {kMoveDefer4, kMoveDefer5, kMoveDefer6, kMoveDefer8, kMoveLaneW6, kMoveLaneW8};
+    for (int v : moves) {
+        c->move_variant = v;
+        double ms = 0;
+        dsmc_status st = time_slots(c, trial_steps, {kSlotMove, kSlotWalls}, &ms);
+        if (st != DSMC_OK) return st;
+        if (ms < best.move_ms) { best.move_ms = ms; best.move = v; }
+    }
+    c->move_variant = best.move;
+    const int collides[] = {kCollideGlobal, kCollideGlobal8, kCollideLds};
+    for (int v : collides) {
+        c->collide_variant = v;
+        double ms = 0;
+        dsmc_status st = time_slots(c, trial_steps, {kSlotCollide}, &ms);
+        if (st != DSMC_OK) return st;
+        if (ms < best.collide_ms) { best.collide_ms = ms; best.collide = v; }
+    }
+    c->collide_variant = best.collide;
+    const int sorts[] = {kSortGather, kSortScatter};
+    for (int v : sorts) {
+        c->sort_variant = v;
+        double ms = 0;
+        dsmc_status st = time_slots(c, trial_steps, {kSlotScan, kSlotScatter, kSlotGather}, &ms);
+        if (st != DSMC_OK) return st;
+        if (ms < best.sort_ms) { best.sort_ms = ms; best.sort = v; }
+    }
+    c->sort_variant = best.sort;
+    c->profiling = was_profiling;
+    if (out) *out = best;
     return DSMC_OK;
 }
 
@@ -478,7 +742,7 @@ dsmc_status dsmc_sample(dsmc_ctx c, int32_t which, double* out, int32_t out_on_d
         if (!alloc_n(c, tmp, 15 * (size_t)c->nt)) return fail(c, DSMC_E_OOM, "device allocation failed");
         dout = tmp;
     }
-    launch_fields(c->stream, src, c->nt, ns, c->mass, c->FN, c->d_vol, c->d_orig, dout);
+    launch_fields(c->stream, src, c->nt, ns, c->mass, c->FN, c->d_vol, c->d_orig, dout, c->d_cell_case, c->d_cases);
     HIP_TRY(c, hipGetLastError());
     if (!out_on_device) {
         HIP_TRY(c, hipMemcpyAsync(out, tmp, sizeof(double) * 15 * (size_t)c->nt, hipMemcpyDeviceToHost, c->stream));
@@ -730,6 +994,7 @@ void dsmc_destroy(dsmc_ctx c) {
     if (!c) return;
     hipStreamSynchronize(c->stream);
     dsmcx::dig_release(c);
+    for (auto& g : c->graphs) drop_graph(g);
     for (auto& u : c->ev_used) {
         hipEventDestroy(u.second.first);
         hipEventDestroy(u.second.second);

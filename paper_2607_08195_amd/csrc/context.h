@@ -103,6 +103,21 @@ struct dsmc_ctx_s {
     // boundary table (copied at init) and the coupling state, built on first use
     std::vector<dsmc_boundary_desc> bcs;
     dsmcx::DigState* dig = nullptr;
+    // batch of independent cases sharing the mesh (null / 0 for one case)
+    dsmcx::CaseDev* d_cases = nullptr;
+    int32_t* d_cell_case = nullptr;     // internal cell -> case
+    int32_t* d_case_of_orig = nullptr;  // caller cell -> case
+    int32_t* d_case_first = nullptr;    // case -> first caller cell
+    int n_cases = 0;
+    // captured two-step graphs, keyed by the particle buffer current at capture
+    bool capturing = false;
+    struct Graph {
+        const void* a_x = nullptr;
+        int sig = -1;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    } graphs[2];
+    std::vector<int32_t> case_cell0;
     dsmc_mlp closure = nullptr;  // learned HoT closure of the coupling step (not owned)
     double gate_tol = 0.05;
 };

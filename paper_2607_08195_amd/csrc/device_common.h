@@ -100,6 +100,15 @@ struct GroupDev {
     double shift[3];
 };
 
+// Per-case parameters when several independent cases share one mesh (a
+// batch): time step, particle weight, initial state and generator key.
+struct CaseDev {
+    double dt, FN, n0, T0, sig, u0[3], smax0;
+    uint32_t k0, k1;
+    int32_t cell0;  // first cell of the case in the caller's numbering (cell subjects are case-local)
+    int32_t pad;
+};
+
 struct MeshDev {
     int nt;
     const double4* plane;    // [nt*4] outward (s n, s d)
@@ -110,7 +119,20 @@ struct MeshDev {
     const double* bf_frame;  // [nb][9]
     const GroupDev* groups;
     double mass;
+    const int32_t* cell_case;  // [nt] case of each cell (batch), or null
+    const CaseDev* cases;
 };
+
+// Generator key and time step of the case that owns `cell` (batch mode).
+__device__ __forceinline__ void case_params(const int32_t* cell_case, const CaseDev* cases, int cell, RngKey& key,
+                                            double& dt) {
+    if (cell_case) {
+        const CaseDev& cs = cases[cell_case[cell]];
+        key.k0 = cs.k0;
+        key.k1 = cs.k1;
+        dt = cs.dt;
+    }
+}
 
 struct TraceOut {
     int status;   // 0 alive, 1 removed through an open face, 2 lost

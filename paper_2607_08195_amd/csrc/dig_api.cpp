@@ -322,6 +322,7 @@ dsmc_status to_host(dsmc_ctx c, T* dst, const T* src, int k) {
 dsmc_status usable(dsmc_ctx c) {
     if (!c) return fail(c, DSMC_E_INVALID, "NULL context");
     if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
+    if (c->n_cases) return fail(c, DSMC_E_INVALID, "the coupling step is not available for a batch");
     return ensure(c);
 }
 

@@ -86,15 +86,22 @@ struct CollideParams {
     int32_t* ewma_m;    // [nt] samples seen
     const uint8_t* local_acc;
     const int32_t* orig;  // [nt] caller's cell id (generator subject)
+    const int32_t* cell_case;  // batch: [nt] case of each cell, or null
+    const CaseDev* cases;
 };
 
 void launch_begin(hipStream_t s, int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss);
 void launch_init_count(hipStream_t s, const double* vol, const int32_t* orig, int nt, double n0, double FN,
-                       RngKey key, int32_t* counts, int32_t* counts_orig);
+                       RngKey key, int32_t* counts, int32_t* counts_orig, const int32_t* cell_case,
+                       const CaseDev* cases);
 template <class VT>
 void launch_init_fill(hipStream_t s, const int4* tv, const double* xyz, int nt, const int32_t* offsets,
                       const int32_t* orig, const int32_t* pid_base, PartDev<VT> p, RngKey key, double sig,
-                      const double* u0, int64_t cap, Scalars* sc);
+                      const double* u0, int64_t cap, Scalars* sc, const int32_t* cell_case, const CaseDev* cases);
+// batch: case-local particle ids (prefix minus the case's first prefix) and per-case (sigma c)_max
+void launch_batch_pid_base(hipStream_t s, const int32_t* prefix, const int32_t* case_first, const int32_t* case_of_orig,
+                           int nt, int32_t* out);
+void launch_batch_smax(hipStream_t s, const int32_t* cell_case, const CaseDev* cases, int nt, double* smax);
 template <class VT>
 void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
                  uint32_t* rank, Counters* ctr, RngKey key, double dt, int64_t np_bound, int variant, int batch,
@@ -122,7 +129,8 @@ template <class VT>
 void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
                            const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant);
 void launch_fields(hipStream_t s, const double* sums, int nt, double ns, double mass, double FN,
-                   const double* vol, const int32_t* orig, double* out);
+                   const double* vol, const int32_t* orig, double* out, const int32_t* cell_case,
+                   const CaseDev* cases);
 void launch_philox(hipStream_t s, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n);
 void launch_copy(hipStream_t s, const void* src, void* dst, size_t bytes);
 void launch_fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n);

@@ -70,12 +70,21 @@ __global__ void k_begin(int32_t* counts, int nt, Scalars* sc, int do_sample, int
 // initial fill
 // ---------------------------------------------------------------------------
 __global__ void k_init_count(const double* vol, const int32_t* orig, int nt, double n0, double FN, RngKey key,
-                             int32_t* counts, int32_t* counts_orig) {
+                             int32_t* counts, int32_t* counts_orig, const int32_t* cell_case, const CaseDev* cases) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
-    const double mean = (n0 * vol[t]) / FN;
     const int o = orig[t];
-    const Rand4 r = draw(key, (uint32_t)o, 0u, kPurposeInitCount, 0);
+    int subj = o;
+    if (cell_case) {
+        const CaseDev& cs = cases[cell_case[t]];
+        n0 = cs.n0;
+        FN = cs.FN;
+        key.k0 = cs.k0;
+        key.k1 = cs.k1;
+        subj = o - cs.cell0;
+    }
+    const double mean = (n0 * vol[t]) / FN;
+    const Rand4 r = draw(key, (uint32_t)subj, 0u, kPurposeInitCount, 0);
     const int32_t cnt = (int32_t)floor(mean + u01(r.w[0], r.w[1]));
     counts[t] = cnt;
     counts_orig[o] = cnt;
@@ -84,9 +93,19 @@ __global__ void k_init_count(const double* vol, const int32_t* orig, int nt, dou
 template <class VT>
 __global__ void k_init_fill(const int4* tv, const double* xyz, int nt, const int32_t* offsets,
                             const int32_t* orig, const int32_t* pid_base, PartDev<VT> p, RngKey key, double sig,
-                            double u0x, double u0y, double u0z, int64_t cap, Scalars* sc) {
+                            double u0x, double u0y, double u0z, int64_t cap, Scalars* sc, const int32_t* cell_case,
+                            const CaseDev* cases) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
+    if (cell_case) {
+        const CaseDev& cs = cases[cell_case[t]];
+        key.k0 = cs.k0;
+        key.k1 = cs.k1;
+        sig = cs.sig;
+        u0x = cs.u0[0];
+        u0y = cs.u0[1];
+        u0z = cs.u0[2];
+    }
     const int4 q = tv[t];
     const double* A = xyz + 3 * (size_t)q.x;
     const double* B = xyz + 3 * (size_t)q.y;
@@ -126,6 +145,20 @@ __global__ void k_init_fill(const int4* tv, const double* xyz, int nt, const int
     }
 }
 
+// Batch: particle ids restart at 0 in every case (prefix of the counts in
+// the caller's numbering minus the prefix at the case's first cell).
+__global__ void k_batch_pid_base(const int32_t* prefix, const int32_t* case_first, const int32_t* case_of_orig, int nt,
+                                 int32_t* out) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nt) return;
+    out[o] = prefix[o] - prefix[case_first[case_of_orig[o]]];
+}
+
+__global__ void k_batch_smax(const int32_t* cell_case, const CaseDev* cases, int nt, double* smax) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nt) smax[c] = cases[cell_case[c]].smax0;
+}
+
 // ---------------------------------------------------------------------------
 // move
 // ---------------------------------------------------------------------------
@@ -142,12 +175,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         Walker w;
         w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
         w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
-        w.c = p.cell[i]; w.pid = p.pid[i]; w.t = dt;
+        w.c = p.cell[i]; w.pid = p.pid[i];
+        RngKey kp = key;
+        double dtp = dt;
+        case_params(m.cell_case, m.cases, w.c, kp, dtp);
+        w.t = dtp;
         w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0;
         const uint32_t step = sc->step;
         int st;
         do {
-            st = hop_once<VT>(m, w, step, key);
+            st = hop_once<VT>(m, w, step, kp);
         } while (st < 0);
         hops = w.nhop;
         walls = w.walls;
@@ -183,12 +220,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     if (i < n) {
         w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
         w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
-        w.c = p.cell[i]; w.pid = p.pid[i]; w.t = dt;
+        w.c = p.cell[i]; w.pid = p.pid[i];
+        RngKey kp = key;
+        double dtp = dt;
+        case_params(m.cell_case, m.cases, w.c, kp, dtp);
+        w.t = dtp;
         w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0;
         const uint32_t step = sc->step;
         int st;
         do {
-            st = hop_once<VT, true>(m, w, step, key);
+            st = hop_once<VT, true>(m, w, step, kp);
         } while (st < 0);
         p.x[i] = w.x0; p.y[i] = w.x1; p.z[i] = w.x2;
         if (st == kHopWallPending) {
@@ -428,11 +469,14 @@ __global__ __launch_bounds__(256) void k_move_walls(MeshDev m, PartDev<VT> p, co
         w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
         w.c = p.cell[i]; w.pid = p.pid[i]; w.t = q.t[e];
         w.entry = meta & 3; w.hits = (meta >> 2) & 1023; w.nhop = (meta >> 12) & 1023; w.walls = (meta >> 22) & 1023;
+        RngKey kp = key;
+        double dtp = 0.0;
+        case_params(m.cell_case, m.cases, w.c, kp, dtp);
         const int bf = -1 - m.nbr[4 * w.c + w.entry];
-        diffuse_reemit<VT>(m, w, bf, w.entry, step, key);
+        diffuse_reemit<VT>(m, w, bf, w.entry, step, kp);
         int st;
         do {
-            st = hop_once<VT, false>(m, w, step, key);
+            st = hop_once<VT, false>(m, w, step, kp);
         } while (st < 0);
         hops += w.nhop;
         walls += w.walls;
@@ -858,14 +902,24 @@ __device__ __forceinline__ void ntc_cell(const Acc& cv, int N, int c, const Coll
     int M = 0, acc = 0;
     if (N >= 2) {
         const double sm = smax[c];
-        const uint32_t subj = (uint32_t)cp.orig[c];
-        const Rand4 r = draw(cp.key, subj, step, kPurposeNtcCount, 0);
+        uint32_t subj = (uint32_t)cp.orig[c];
+        RngKey key = cp.key;
+        double FN = cp.FN, dt = cp.dt;
+        if (cp.cell_case) {
+            const CaseDev& cs = cp.cases[cp.cell_case[c]];
+            key.k0 = cs.k0;
+            key.k1 = cs.k1;
+            FN = cs.FN;
+            dt = cs.dt;
+            subj -= (uint32_t)cs.cell0;
+        }
+        const Rand4 r = draw(key, subj, step, kPurposeNtcCount, 0);
         const double Nd = (double)N;
-        const double mean = ((((0.5 * Nd) * (Nd - 1.0)) * cp.FN) * sm) * cp.dt / cp.vol[c];
+        const double mean = ((((0.5 * Nd) * (Nd - 1.0)) * FN) * sm) * dt / cp.vol[c];
         M = (int)floor(mean + u01(r.w[0], r.w[1]));
         double seen = 0.0;
         for (int k = 0; k < M; ++k) {
-            const Rand4 w = draw(cp.key, subj, step, kPurposePair, (uint64_t)k);
+            const Rand4 w = draw(key, subj, step, kPurposePair, (uint64_t)k);
             const uint32_t i = pick(w.w[0], (uint32_t)N);
             uint32_t j = pick(w.w[1], (uint32_t)(N - 1));
             if (j >= i) ++j;
@@ -879,7 +933,7 @@ __device__ __forceinline__ void ntc_cell(const Acc& cv, int N, int c, const Coll
             if (sc > seen) seen = sc;
             if (!(U < sc / sm)) continue;
             ++acc;
-            const Rand4 q = draw(cp.key, subj, step, kPurposeScatter, (uint64_t)k);
+            const Rand4 q = draw(key, subj, step, kPurposeScatter, (uint64_t)k);
             const double cx = 2.0 * u01(q.w[0], q.w[1]) - 1.0;
             const double sx = sqrt(1.0 - cx * cx);
             const double eps = DSMC_TWO_PI * u01(q.w[2], q.w[3]);
@@ -1068,9 +1122,10 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
 // fields from moment sums (eq. dsmc_temperatures over accumulated samples)
 // ---------------------------------------------------------------------------
 __global__ void k_fields(const double* sums, int nt, double ns, double mass, double FN, const double* vol,
-                         const int32_t* orig, double* out) {
+                         const int32_t* orig, double* out, const int32_t* cell_case, const CaseDev* cases) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nt) return;
+    if (cell_case) FN = cases[cell_case[c]].FN;
     double S[kNMom];
     for (int k = 0; k < kNMom; ++k) S[k] = sums[(int64_t)k * nt + c];
     double* o = out + 15 * (size_t)orig[c];
@@ -1143,17 +1198,27 @@ void launch_begin(hipStream_t s, int32_t* counts, int nt, Scalars* sc, int do_sa
 }
 
 void launch_init_count(hipStream_t s, const double* vol, const int32_t* orig, int nt, double n0, double FN,
-                       RngKey key, int32_t* counts, int32_t* counts_orig) {
+                       RngKey key, int32_t* counts, int32_t* counts_orig, const int32_t* cell_case,
+                       const CaseDev* cases) {
     hipLaunchKernelGGL(k_init_count, GRID(nt, 256), dim3(256), 0, s, vol, orig, nt, n0, FN, key, counts,
-                       counts_orig);
+                       counts_orig, cell_case, cases);
+}
+
+void launch_batch_pid_base(hipStream_t s, const int32_t* prefix, const int32_t* case_first, const int32_t* case_of_orig,
+                           int nt, int32_t* out) {
+    hipLaunchKernelGGL(k_batch_pid_base, GRID(nt, 256), dim3(256), 0, s, prefix, case_first, case_of_orig, nt, out);
+}
+
+void launch_batch_smax(hipStream_t s, const int32_t* cell_case, const CaseDev* cases, int nt, double* smax) {
+    hipLaunchKernelGGL(k_batch_smax, GRID(nt, 256), dim3(256), 0, s, cell_case, cases, nt, smax);
 }
 
 template <class VT>
 void launch_init_fill(hipStream_t s, const int4* tv, const double* xyz, int nt, const int32_t* offsets,
                       const int32_t* orig, const int32_t* pid_base, PartDev<VT> p, RngKey key, double sig,
-                      const double* u0, int64_t cap, Scalars* sc) {
+                      const double* u0, int64_t cap, Scalars* sc, const int32_t* cell_case, const CaseDev* cases) {
     hipLaunchKernelGGL(k_init_fill<VT>, GRID(nt, 128), dim3(128), 0, s, tv, xyz, nt, offsets, orig, pid_base, p,
-                       key, sig, u0[0], u0[1], u0[2], cap, sc);
+                       key, sig, u0[0], u0[1], u0[2], cap, sc, cell_case, cases);
 }
 
 template <class VT>
@@ -1293,8 +1358,10 @@ void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets,
 }
 
 void launch_fields(hipStream_t s, const double* sums, int nt, double ns, double mass, double FN,
-                   const double* vol, const int32_t* orig, double* out) {
-    hipLaunchKernelGGL(k_fields, GRID(nt, 256), dim3(256), 0, s, sums, nt, ns, mass, FN, vol, orig, out);
+                   const double* vol, const int32_t* orig, double* out, const int32_t* cell_case,
+                   const CaseDev* cases) {
+    hipLaunchKernelGGL(k_fields, GRID(nt, 256), dim3(256), 0, s, sums, nt, ns, mass, FN, vol, orig, out, cell_case,
+                       cases);
 }
 
 void launch_philox(hipStream_t s, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n) {
@@ -1317,7 +1384,7 @@ void launch_fill_f64(hipStream_t s, double* p, double v, int64_t n) {
 #define INSTANTIATE(VT)                                                                                      \
     template void launch_init_fill<VT>(hipStream_t, const int4*, const double*, int, const int32_t*,       \
                                        const int32_t*, const int32_t*, PartDev<VT>, RngKey, double,         \
-                                       const double*, int64_t, Scalars*);                                   \
+                                       const double*, int64_t, Scalars*, const int32_t*, const CaseDev*);   \
     template void launch_move<VT>(hipStream_t, const MeshDev&, PartDev<VT>, const Scalars*, int32_t*,       \
                                   uint32_t*, Counters*, RngKey, double, int64_t, int, int, WallQueue);      \
     template void launch_inject_emit<VT>(hipStream_t, const MeshDev&, const InflowDev&, PartDev<VT>,        \

@@ -210,7 +210,7 @@ inline uint64_t spread3(uint64_t v) {
 }
 }  // namespace
 
-void reorder_cells(HostMesh& m) {
+void reorder_cells(HostMesh& m, const std::vector<int32_t>* group) {
     const int nt = m.nt;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     std::vector<double> cen(3 * (size_t)nt);
@@ -237,7 +237,10 @@ void reorder_cells(HostMesh& m) {
     }
     m.orig.resize(nt);
     std::iota(m.orig.begin(), m.orig.end(), 0);
-    std::stable_sort(m.orig.begin(), m.orig.end(), [&](int a, int b) { return key[a] < key[b]; });
+    std::stable_sort(m.orig.begin(), m.orig.end(), [&](int a, int b) {
+        if (group && (*group)[a] != (*group)[b]) return (*group)[a] < (*group)[b];
+        return key[a] < key[b];
+    });
     m.inv.assign(nt, 0);
     for (int t = 0; t < nt; ++t) m.inv[m.orig[t]] = t;
     std::vector<int32_t> tv(4 * (size_t)nt), nbr(4 * (size_t)nt);

@@ -40,6 +40,8 @@ std::string build_mesh(HostMesh& m, int nv, const double* xyz, int nt, const int
 // Renumber the tets along a Morton (Z-order) curve of their centroids so
 // that cells close in space are close in memory; fills orig/inv.  Only
 // internal numbering changes: every interface keeps the caller's ids.
-void reorder_cells(HostMesh& m);
+// With `group` (one value per tet, caller numbering), tets are ordered by
+// group first, so each group stays contiguous.
+void reorder_cells(HostMesh& m, const std::vector<int32_t>* group = nullptr);
 
 }  // namespace dsmcx

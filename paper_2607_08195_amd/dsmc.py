@@ -67,6 +67,11 @@ class Counters(C.Structure):
                 ("injected", C.c_int64), ("removed", C.c_int64), ("lost", C.c_int64), ("step", C.c_uint32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("move", C.c_int32), ("collide", C.c_int32), ("sort", C.c_int32), ("move_ms", C.c_double),
+                ("collide_ms", C.c_double), ("sort_ms", C.c_double)]
+
+
 class DigParams(C.Structure):
     _fields_ = [("kn_max", C.c_double), ("passes", C.c_int32), ("n_m", C.c_int32), ("eps_m", C.c_double),
                 ("cfl", C.c_double), ("L0", C.c_double), ("feedback", C.c_int32), ("global_dt", C.c_int32)]
@@ -133,6 +138,13 @@ _lib.dig_residual.argtypes = [ctx_t, P, P, P]
 _lib.dig_solve.argtypes = [ctx_t, P, P, C.POINTER(DigParams), C.POINTER(DigReport)]
 _lib.dig_feedback.argtypes = [ctx_t, P, P, P, C.POINTER(C.c_int64)]
 _lib.dsmc_set_sums.argtypes = [ctx_t, C.c_int32, P]
+_lib.dsmc_batch_init.argtypes = [C.POINTER(ctx_t), C.c_int32, C.POINTER(MeshDesc), C.POINTER(SpeciesDesc),
+                                 P, C.POINTER(BoundaryDesc), C.POINTER(RunDesc)]
+_lib.dsmc_batch_cases.argtypes = [ctx_t, C.POINTER(C.c_int32), P]
+_lib.dsmc_graph_step.argtypes = [ctx_t, C.c_int32]
+_lib.dsmc_get_tuning.argtypes = [ctx_t, C.POINTER(Tuning)]
+_lib.dsmc_set_tuning.argtypes = [ctx_t, C.POINTER(Tuning)]
+_lib.dsmc_autotune.argtypes = [ctx_t, C.c_int32, C.POINTER(Tuning)]
 _lib.dsmc_mlp_create.argtypes = [C.POINTER(P), P, C.POINTER(Allocator)]
 _lib.dsmc_mlp_set_weights.argtypes = [P, P]
 _lib.dsmc_mlp_get_weights.argtypes = [P, P]
@@ -150,7 +162,8 @@ for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_ge
            "dsmc_profile", "dsmc_philox", "dsmc_device_copy", "dig_couple", "dig_get", "dig_residual",
            "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
            "dsmc_mlp_get_weights", "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train",
-           "dig_set_closure", "dig_closure_data"]:
+           "dig_set_closure", "dig_closure_data", "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
+           "dsmc_get_tuning", "dsmc_set_tuning", "dsmc_autotune"]:
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_state",
@@ -212,37 +225,54 @@ class Simulation:
     """A DSMC run on one GPU, built from a workloads.Workload."""
 
     def __init__(self, wl, device=0, capacity=0, fill=True, stream=None, torch_memory=True):
+        """wl: one workloads.Workload, or a list of them for a batch of
+        independent cases in one context (species and batch-wide settings
+        from the first)."""
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: the DSMC library runs on the GPU only")
         self.device = device
         torch.cuda.set_device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
-        m, sp, run = wl.mesh, wl.species, wl.run
         self._keep = []
+        cases = list(wl) if isinstance(wl, (list, tuple)) else [wl]
 
         def arr(a, dt):
             a = np.ascontiguousarray(a, dtype=dt)
             self._keep.append(a)
             return a
 
-        xyz = arr(m.xyz, np.float64)
-        tets = arr(m.tets, np.int32)
-        bf = arr(m.bfaces, np.int32)
-        bg = arr(m.bgroup, np.int32)
-        bp = arr(m.bpartner, np.int32) if m.bpartner is not None else None
-        md = MeshDesc(xyz.shape[0], _p(xyz), tets.shape[0], _p(tets), bf.shape[0], _p(bf), _p(bg), _p(bp))
-        sd = SpeciesDesc(sp.mass, sp.d_ref, sp.omega, sp.T_ref, sp.alpha)
-        bcs = (BoundaryDesc * len(wl.boundaries))()
-        for i, b in enumerate(wl.boundaries):
-            bcs[i] = BoundaryDesc(b.kind, b.T, (C.c_double * 3)(*b.u), b.n, (C.c_double * 3)(*b.shift))
+        meshes = (MeshDesc * len(cases))()
+        nbc = np.zeros(len(cases), np.int32)
+        allb = []
+        runs = (RunDesc * len(cases))()
         self._alloc = _TorchAllocator(device, self.stream) if torch_memory else None
-        rd = RunDesc(run.n0, run.T0, (C.c_double * 3)(*run.u0), run.F_N, run.dt, run.seed, run.case_id,
-                     0 if run.vel_fp32 else 1, run.n_ss, run.n_a, run.ewma_on, 1 if fill else 0, capacity,
-                     P(self.stream.cuda_stream), C.pointer(self._alloc.desc) if self._alloc else None)
+        for k, w in enumerate(cases):
+            m, run = w.mesh, w.run
+            xyz = arr(m.xyz, np.float64)
+            tets = arr(m.tets, np.int32)
+            bf = arr(m.bfaces, np.int32)
+            bg = arr(m.bgroup, np.int32)
+            bp = arr(m.bpartner, np.int32) if m.bpartner is not None else None
+            meshes[k] = MeshDesc(xyz.shape[0], _p(xyz), tets.shape[0], _p(tets), bf.shape[0], _p(bf), _p(bg), _p(bp))
+            nbc[k] = len(w.boundaries)
+            allb.extend(w.boundaries)
+            runs[k] = RunDesc(run.n0, run.T0, (C.c_double * 3)(*run.u0), run.F_N, run.dt, run.seed, run.case_id,
+                              0 if run.vel_fp32 else 1, run.n_ss, run.n_a, run.ewma_on, 1 if fill else 0, capacity,
+                              P(self.stream.cuda_stream), C.pointer(self._alloc.desc) if self._alloc else None)
+        bcs = (BoundaryDesc * max(1, len(allb)))()
+        for i, b in enumerate(allb):
+            bcs[i] = BoundaryDesc(b.kind, b.T, (C.c_double * 3)(*b.u), b.n, (C.c_double * 3)(*b.shift))
+        sp = cases[0].species
+        sd = SpeciesDesc(sp.mass, sp.d_ref, sp.omega, sp.T_ref, sp.alpha)
         self.ctx = ctx_t()
-        _check(_lib.dsmc_init(C.byref(self.ctx), C.byref(md), C.byref(sd), len(wl.boundaries), bcs, C.byref(rd)))
-        self.nt = int(tets.shape[0])
+        if len(cases) == 1 and not isinstance(wl, (list, tuple)):
+            _check(_lib.dsmc_init(C.byref(self.ctx), C.byref(meshes[0]), C.byref(sd), int(nbc[0]), bcs,
+                                  C.byref(runs[0])))
+        else:
+            _check(_lib.dsmc_batch_init(C.byref(self.ctx), len(cases), meshes, C.byref(sd), _p(nbc), bcs, runs))
+        self.nt = int(sum(int(w.mesh.tets.shape[0]) for w in cases))
         self.wl = wl
+        self.cases = cases
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -261,6 +291,31 @@ class Simulation:
     # -- stepping --------------------------------------------------------
     def step(self, n=1):
         self._c(_lib.dsmc_step(self.ctx, n))
+
+    def graph_step(self, n=2):
+        """n steps through a captured HIP graph (needs a non-default stream)."""
+        self._c(_lib.dsmc_graph_step(self.ctx, n))
+
+    def case_cells(self):
+        n = C.c_int32()
+        self._c(_lib.dsmc_batch_cases(self.ctx, C.byref(n), None))
+        b = np.zeros(n.value + 1, np.int32)
+        self._c(_lib.dsmc_batch_cases(self.ctx, C.byref(n), _p(b)))
+        return b
+
+    def tuning(self):
+        t = Tuning()
+        self._c(_lib.dsmc_get_tuning(self.ctx, C.byref(t)))
+        return dict(move=t.move, collide=t.collide, sort=t.sort)
+
+    def set_tuning(self, move, collide, sort):
+        t = Tuning(move, collide, sort, 0.0, 0.0, 0.0)
+        self._c(_lib.dsmc_set_tuning(self.ctx, C.byref(t)))
+
+    def autotune(self, trial_steps=3):
+        t = Tuning()
+        self._c(_lib.dsmc_autotune(self.ctx, trial_steps, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
 
     def step_stages(self, mask):
         self._c(_lib.dsmc_step_stages(self.ctx, mask))

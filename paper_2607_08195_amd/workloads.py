@@ -262,6 +262,24 @@ def cavity_large(steps=20000, n_ss=10000):
     return cavity(n_hex=40, Kn=0.1, ppc=30, jitter=0.1, vel_fp32=1, steps=steps, n_ss=n_ss)
 
 
+def cavity_ensemble(n_cases=64, seed=0, n_min=6, n_max=24, ppc=20, vel_fp32=1, case_seed=0):
+    """Independent lid-driven cavities for batched stepping: per case (seeded)
+    Kn log-uniform in [0.01, 1], lid speed uniform in [20, 200] m/s and a
+    mesh of n^3 hexes x 6 tets with n uniform in [n_min, n_max]; case k has
+    generator key (seed, k)."""
+    rng = np.random.default_rng(case_seed)
+    out = []
+    for k in range(n_cases):
+        Kn = float(10.0 ** rng.uniform(-2.0, 0.0))
+        lid = float(rng.uniform(20.0, 200.0))
+        n = int(rng.integers(n_min, n_max + 1))
+        wl = cavity(n_hex=n, Kn=Kn, ppc=ppc, lid_speed=lid, seed=seed, vel_fp32=vel_fp32)
+        wl.run.case_id = k
+        wl.name = f"case{k}_" + wl.name
+        out.append(wl)
+    return out
+
+
 def closed_box(n_hex=4, kind=BC_SPECULAR, Kn=1.0, ppc=20, T0=273.0, vel_fp32=0, seed=0,
                Tw=None):
     """Closed unit box at rest with all six walls of one kind."""
