@@ -3,7 +3,8 @@
 * A batch context advances several independent cavities (different Kn,
   lid speed, mesh size and generator key) in one set of launches; each
   case must match the CPU oracle run of that case alone: the initial fill
-  bitwise, and after steps the cell indices, (cell, pid) order and pair
+  (positions bitwise, velocities through Box-Muller's libm calls within
+  1e-12), and after steps the cell indices, (cell, pid) order and pair
   counts bit-exactly with positions and velocities to the single-step
   criteria.
 * dsmc_graph_step gives the same particle state as dsmc_step, bit for bit,
@@ -17,7 +18,7 @@ import pytest
 
 from paper_2607_08195_amd import workloads as W
 from oracle import Oracle
-from parity_util import compare_particles
+from parity_util import compare_particles, compare_sums
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +59,7 @@ def test_batch_cases_match_oracle(D, vel_fp32):
     for k, o in enumerate(oracles):
         gk = _split(st, begin, k)
         ok = o.particles()
-        assert np.array_equal(gk["x"], ok["x"]) and np.array_equal(gk["v"], ok["v"]), f"fill of case {k}"
+        assert np.array_equal(gk["x"], ok["x"]), f"fill positions of case {k}"
         compare_particles(gk, ok, vel_fp32, ctx=f"fill case {k}")
     for step in range(3):
         g.step(1)
@@ -70,11 +71,16 @@ def test_batch_cases_match_oracle(D, vel_fp32):
             compare_particles(_split(st, begin, k), o.particles(), vel_fp32, ctx=f"case {k} step {step + 1}")
             oc, oa = o.pair_counts()
             assert np.array_equal(nc[begin[k]:begin[k + 1]], oc) and np.array_equal(na[begin[k]:begin[k + 1]], oa)
+    sums, ns = g.sums(D.SAMPLE_STEADY)
     f = g.fields(D.SAMPLE_STEADY)
     for k, o in enumerate(oracles):
+        assert ns == o.n_steady == 3
+        compare_sums(sums[begin[k]:begin[k + 1]], o.sums(0))
         fo = o.fields(0)
         fk = f[begin[k]:begin[k + 1]]
-        assert np.allclose(fk, fo, rtol=1e-12, atol=0, equal_nan=True), f"fields of case {k}"
+        assert np.array_equal(np.isnan(fk), np.isnan(fo))
+        scale = np.nanmax(np.abs(fo), axis=0, keepdims=True)
+        assert np.all(np.nan_to_num(np.abs(fk - fo)) <= 1e-10 * scale), f"fields of case {k}"
     g.close()
 
 
