@@ -88,22 +88,27 @@ def calibrate_copy(dsmc, W, nbytes=2 << 30, reps=10):
 def bench_ensemble(args, dsmc, W):
     """64 independent cavities (Kn log-uniform in [0.01, 1], lid 20-200 m/s,
     6^3-24^3 hexes x 6 tets, 20 particles per cell) advanced together in one
-    context: schedule chosen by the autotuner, steps replayed from captured
-    HIP graphs.  value = particle-steps/s summed over the cases."""
+    context with the schedule the autotuner picks.  value = particle-steps/s
+    summed over the cases, stepping with ordinary launches (one launch per
+    kernel for all cases); the same steps replayed from captured HIP graphs
+    are timed beside it."""
     import torch
     cases = W.cavity_ensemble(64)
     stream = torch.cuda.Stream()
     sim = dsmc.Simulation(cases, stream=stream)
     np0 = sim.stats()["n_particles"]
     tune = sim.autotune(trial_steps=3)
-    sim.graph_step(args.warmup)
-    sim.sync()
-    t0 = time.perf_counter()
-    sim.graph_step(args.steps)
-    sim.sync()
-    t1 = time.perf_counter()
+    timings = {}
+    for mode in ["eager", "graph"]:
+        run = sim.step if mode == "eager" else sim.graph_step
+        run(args.warmup)
+        sim.sync()
+        t0 = time.perf_counter()
+        run(args.steps)
+        sim.sync()
+        timings[mode] = time.perf_counter() - t0
     n1 = sim.stats()["n_particles"]
-    elapsed = t1 - t0
+    elapsed = timings["eager"]
     out = {
         "metric": "particle-steps/s",
         "value": 0.5 * (np0 + n1) * args.steps / elapsed,
@@ -117,10 +122,74 @@ def bench_ensemble(args, dsmc, W):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "cavity_ensemble_64", "cases": len(cases), "tets": sim.nt, "particles": int(np0),
-                   "stepping": "hipGraph, two steps per replay"},
+        "config": {"workload": "cavity_ensemble_64", "cases": len(cases), "tets": sim.nt, "particles": int(np0)},
+        "graph_ms_per_step": 1e3 * timings["graph"] / args.steps,
         "autotuned": tune,
     }
+    sim.close()
+    print(json.dumps(out))
+
+
+def bench_dig(args, dsmc, W, window=50):
+    """DIG-coupled cavity at Kn = 0.01 on the 384,000-tet mesh (30 particles
+    per cell): cycles of `window` DSMC steps followed by one coupling step
+    (sampled state, HoT, gate, learned closure, FV solve, feedback).  The
+    closure network is first trained on the run's own cell data.  --steps
+    counts DSMC steps (rounded to whole windows)."""
+    import torch
+    wl = W.cavity(n_hex=40, Kn=0.01, ppc=30, jitter=0.1, vel_fp32=1, ewma_on=1, n_a=window)
+    sim = dsmc.Simulation(wl)
+    net = dsmc.Mlp()
+    prm = dict(kn_max=1.0, passes=3, n_m=100, eps_m=1e-4, cfl=0.5, feedback=1)
+    sim.step(window)
+    sim.dig_couple(**dict(prm, n_m=0, feedback=0))
+    x, t, v = sim.closure_data()
+    t0 = time.perf_counter()
+    train = net.train(x[v], t[v], steps=200, batch=4096, lr=1e-3, seed=1)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    sim.set_closure(net, gate_tol=0.5)
+    cycles = max(1, args.steps // window)
+    for _ in range(max(1, args.warmup // window)):
+        sim.step(window)
+        sim.dig_couple(**prm)
+    sim.sync()
+    np0 = sim.stats()["n_particles"]
+    t_step = t_couple = 0.0
+    reps = []
+    for _ in range(cycles):
+        a = time.perf_counter()
+        sim.step(window)
+        sim.sync()
+        b = time.perf_counter()
+        reps.append(sim.dig_couple(**prm))
+        c = time.perf_counter()
+        t_step += b - a
+        t_couple += c - b
+    n1 = sim.stats()["n_particles"]
+    elapsed = t_step + t_couple
+    out = {
+        "metric": "particle-steps/s",
+        "value": 0.5 * (np0 + n1) * cycles * window / elapsed,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": cycles * window,
+        "warmup": max(1, args.warmup // window) * window,
+        "ms_per_step": 1e3 * elapsed / (cycles * window),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dig_cavity_40^3x6_Kn0.01", "tets": sim.nt, "particles": int(np0),
+                   "window": window, "coupling": prm},
+        "ms_per_coupling": 1e3 * t_couple / cycles,
+        "ms_per_dsmc_step": 1e3 * t_step / (cycles * window),
+        "closure_training": {"steps": 200, "batch": 4096, "seconds": round(train_s, 3),
+                             "loss_first": train["loss_first"], "loss_last": train["loss_last"]},
+        "last_report": reps[-1],
+    }
+    net.close()
     sim.close()
     print(json.dumps(out))
 
@@ -130,7 +199,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cavity_large", choices=["cavity_large", "cavity_small", "ensemble64"])
+    ap.add_argument("--workload", default="cavity_large", choices=["cavity_large", "cavity_small", "ensemble64", "dig_cavity40"])
     ap.add_argument("--graph", action="store_true", help="step through captured HIP graphs")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
@@ -150,6 +219,8 @@ def main():
         return calibrate_copy(dsmc, W)
     if args.workload == "ensemble64":
         return bench_ensemble(args, dsmc, W)
+    if args.workload == "dig_cavity40":
+        return bench_dig(args, dsmc, W)
     wl = W.cavity_large() if args.workload == "cavity_large" else W.cavity_small()
     sim = dsmc.Simulation(wl)
     np0 = sim.stats()["n_particles"]
