@@ -42,7 +42,7 @@ BYTES = {
 # rocprofv3 --pmc measurements of the move kernel (FETCH_SIZE + WRITE_SIZE per
 # dispatch, scaled by the copy-kernel calibration) and the source digest they
 # were taken on; the traffic figure is reported only while the digest matches.
-TRAFFIC = {"kernel": "move", "digest": "abfbccdafa367eff", "bytes_per_launch": 580972131 + 704928921,
+TRAFFIC = {"kernel": "move", "digest": "c0611575af0cb92b", "bytes_per_launch": 581003081 + 704941768,
            "source": "profiles/step_kernels_cavity40.md"}
 
 
@@ -140,6 +140,7 @@ def bench_dig(args, dsmc, W, window=50):
     wl = W.cavity(n_hex=40, Kn=0.01, ppc=30, jitter=0.1, vel_fp32=1, ewma_on=1, n_a=window)
     sim = dsmc.Simulation(wl)
     net = dsmc.Mlp()
+    net.init_weights(seed=1)
     prm = dict(kn_max=1.0, passes=3, n_m=100, eps_m=1e-4, cfl=0.5, feedback=1)
     sim.step(window)
     sim.dig_couple(**dict(prm, n_m=0, feedback=0))

@@ -62,6 +62,9 @@ typedef struct {
  * zero and persist across dsmc_mlp_train calls (reset by set_weights). */
 dsmc_status dsmc_mlp_create(dsmc_mlp* out, void* hip_stream, const dsmc_allocator* allocator);
 dsmc_status dsmc_mlp_set_weights(dsmc_mlp net, const float* params);
+/* Random initial weights, uniform in (-1, 1) / sqrt(fan_in), zero biases
+ * (generator purpose 8 keyed by (seed, 1), subject = parameter index). */
+dsmc_status dsmc_mlp_init_weights(dsmc_mlp net, uint64_t seed);
 dsmc_status dsmc_mlp_get_weights(dsmc_mlp net, float* params);
 
 /* y[n][9] = network(x[n][13]); x and y are device pointers if on_device. */

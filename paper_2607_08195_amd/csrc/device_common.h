@@ -100,6 +100,30 @@ struct GroupDev {
     double shift[3];
 };
 
+// Slot of a particle in its cell's histogram bin.  Lanes of a wave that
+// land in the same cell take consecutive slots from one atomic add: the
+// first active lane's cell is served per round (at most kRankRounds rounds,
+// so a wave spread over many cells falls back to one atomic per lane).
+// Must be called by every lane of the wave (uniform control flow).
+constexpr int kRankRounds = 4;
+__device__ __forceinline__ uint32_t bin_slot(int32_t* counts, int cell, bool active) {
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = __ballot(active);
+    uint32_t slot = 0;
+    for (int round = 0; round < kRankRounds && pending; ++round) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int c0 = __shfl(cell, leader, 64);
+        const uint64_t same = __ballot(active && cell == c0) & pending;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&counts[c0], __popcll(same));
+        base = __shfl(base, leader, 64);
+        if ((same >> lane) & 1ull) slot = (uint32_t)(base + __popcll(same & ((1ull << lane) - 1ull)));
+        pending &= ~same;
+    }
+    if ((pending >> lane) & 1ull) slot = (uint32_t)atomicAdd(&counts[cell], 1);
+    return slot;
+}
+
 // Per-case parameters when several independent cases share one mesh (a
 // batch): time step, particle weight, initial state and generator key.
 struct CaseDev {

@@ -725,9 +725,9 @@ __global__ __launch_bounds__(kFbLanes) void k_dig_fb_apply(DigWork w, PartDev<VT
 // appended after them (feedback clones).
 __global__ void k_dig_count_all(const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= sc->np + sc->ninj) return;
-    const int c = cell[i];
-    if (c >= 0) rank[i] = (uint32_t)atomicAdd(&counts[c], 1);
+    const int c = i < sc->np + sc->ninj ? cell[i] : -1;
+    const uint32_t slot = bin_slot(counts, c, c >= 0);
+    if (c >= 0) rank[i] = slot;
 }
 
 __global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {

@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                                       RngKey key, double dt) {
     const int64_t i = xcd_block() * 256 + threadIdx.x;
     const int64_t n = sc->np;
-    int hops = 0, walls = 0, rem = 0, lost = 0;
+    int hops = 0, walls = 0, rem = 0, lost = 0, dest = -1;
     if (i < n) {
         Walker w;
         w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
@@ -194,13 +194,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         }
         if (st == 0) {
             p.cell[i] = w.c;
-            rank[i] = (uint32_t)atomicAdd(&counts[w.c], 1);
+            dest = w.c;
         } else {
             p.cell[i] = -1;
             rem = st == 1;
             lost = st == 2;
         }
     }
+    const uint32_t slot = bin_slot(counts, dest, dest >= 0);
+    if (dest >= 0) rank[i] = slot;
     block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
 }
 
@@ -214,7 +216,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     double dt, WallQueue q) {
     const int64_t i = xcd_block() * 256 + threadIdx.x;
     const int64_t n = sc->np;
-    int hops = 0, walls = 0, rem = 0, lost = 0;
+    int hops = 0, walls = 0, rem = 0, lost = 0, dest = -1;
     bool park = false;
     Walker w;
     if (i < n) {
@@ -243,13 +245,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             }
             if (st == 0) {
                 p.cell[i] = w.c;
-                rank[i] = (uint32_t)atomicAdd(&counts[w.c], 1);
+                dest = w.c;
             } else {
                 p.cell[i] = -1;
                 rem = st == 1;
                 lost = st == 2;
             }
         }
+    }
+    {
+        const uint32_t slot = bin_slot(counts, dest, dest >= 0);
+        if (dest >= 0) rank[i] = slot;
     }
     // wave-aggregated push of parked particles
     const uint64_t pm = __ballot(park);
@@ -561,9 +567,9 @@ __global__ __launch_bounds__(256) void k_move(MeshDev m, PartDev<VT> p, const Sc
 // Histogram of the current cells (sort without a preceding move).
 __global__ void k_count(const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= sc->np) return;
-    const int c = cell[i];
-    if (c >= 0) rank[i] = (uint32_t)atomicAdd(&counts[c], 1);
+    const int c = i < sc->np ? cell[i] : -1;
+    const uint32_t slot = bin_slot(counts, c, c >= 0);
+    if (c >= 0) rank[i] = slot;
 }
 
 // ---------------------------------------------------------------------------

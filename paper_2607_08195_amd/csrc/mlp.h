@@ -52,6 +52,7 @@ void launch_mlp_reduce(hipStream_t s, const float* partial, const float* loss_pa
                        double* loss);
 void launch_mlp_adam(hipStream_t s, float* params, const float* grad, float* m, float* v, int step, float lr,
                      float b1, float b2, float eps);
+void launch_mlp_init(hipStream_t s, float* params, RngKey key);
 void launch_mlp_batch(hipStream_t s, RngKey key, uint32_t step, int64_t n, int64_t batch, int32_t* idx);
 
 }  // namespace dsmcx

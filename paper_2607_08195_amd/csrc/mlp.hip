@@ -329,6 +329,24 @@ __global__ void k_mlp_pack(const float* P, uint16_t* out) {
     out[e] = to_bf16(v);
 }
 
+// Initial weights uniform in (-1, 1)/sqrt(fan_in) (purpose 8, block 1,
+// subject = parameter index), biases zero.
+__global__ void k_mlp_init(float* P, RngKey key) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kMlpParams) return;
+    int fan = 0;
+    if (p < kMlpB1) fan = kMlpIn;
+    else if (p >= kMlpW2 && p < kMlpB2) fan = kMlpHid;
+    else if (p >= kMlpW3 && p < kMlpB3) fan = kMlpHid;
+    else if (p >= kMlpW4 && p < kMlpB4) fan = kMlpHid;
+    if (!fan) {
+        P[p] = 0.f;
+        return;
+    }
+    const Rand4 r = draw(key, (uint32_t)p, 0u, kPurposeMlp, 1);
+    P[p] = (float)((2.0 * u01(r.w[0], r.w[1]) - 1.0) / sqrt((double)fan));
+}
+
 // Minibatch of indices in [0, n), drawn with replacement (purpose 8).
 __global__ void k_mlp_batch(RngKey key, uint32_t step, int64_t n, int64_t batch, int32_t* idx) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -384,6 +402,10 @@ void launch_mlp_adam(hipStream_t s, float* params, const float* grad, float* m, 
     const float c2 = (float)(1.0 - std::pow((double)b2, step));
     hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, params, grad, m, v, lr, b1, b2,
                        eps, c1, c2);
+}
+
+void launch_mlp_init(hipStream_t s, float* params, RngKey key) {
+    hipLaunchKernelGGL(k_mlp_init, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, params, key);
 }
 
 void launch_mlp_batch(hipStream_t s, RngKey key, uint32_t step, int64_t n, int64_t batch, int32_t* idx) {

@@ -172,6 +172,19 @@ dsmc_status dsmc_mlp_set_weights(dsmc_mlp n, const float* p) {
     return DSMC_OK;
 }
 
+dsmc_status dsmc_mlp_init_weights(dsmc_mlp n, uint64_t seed) {
+    if (!n) return mfail(n, DSMC_E_INVALID, "bad arguments");
+    std::vector<float> z(kMlpParams, 0.f);
+    launch_mlp_init(n->stream, n->params, RngKey{(uint32_t)(seed & 0xFFFFFFFFu), 1u});
+    MLP_TRY(n, hipMemcpyAsync(n->m, z.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice, n->stream));
+    MLP_TRY(n, hipMemcpyAsync(n->v, z.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice, n->stream));
+    launch_mlp_pack(n->stream, n->params, n->packed);
+    MLP_TRY(n, hipGetLastError());
+    MLP_TRY(n, hipStreamSynchronize(n->stream));
+    n->step = 0;
+    return DSMC_OK;
+}
+
 dsmc_status dsmc_mlp_get_weights(dsmc_mlp n, float* p) {
     if (!n || !p) return mfail(n, DSMC_E_INVALID, "bad arguments");
     MLP_TRY(n, hipStreamSynchronize(n->stream));

@@ -148,6 +148,7 @@ _lib.dsmc_autotune.argtypes = [ctx_t, C.c_int32, C.POINTER(Tuning)]
 _lib.dsmc_mlp_create.argtypes = [C.POINTER(P), P, C.POINTER(Allocator)]
 _lib.dsmc_mlp_set_weights.argtypes = [P, P]
 _lib.dsmc_mlp_get_weights.argtypes = [P, P]
+_lib.dsmc_mlp_init_weights.argtypes = [P, C.c_uint64]
 _lib.dsmc_mlp_forward.argtypes = [P, P, C.c_int64, P, C.c_int32]
 _lib.dsmc_mlp_backward.argtypes = [P, P, P, C.c_int64, P, C.POINTER(C.c_double)]
 _lib.dsmc_mlp_adam_step.argtypes = [P, P, C.c_float, C.c_float, C.c_float, C.c_float]
@@ -162,7 +163,7 @@ for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_ge
            "dsmc_profile", "dsmc_philox", "dsmc_device_copy", "dig_couple", "dig_get", "dig_residual",
            "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
            "dsmc_mlp_get_weights", "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train",
-           "dig_set_closure", "dig_closure_data", "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
+           "dsmc_mlp_init_weights", "dig_set_closure", "dig_closure_data", "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
            "dsmc_get_tuning", "dsmc_set_tuning", "dsmc_autotune"]:
     getattr(_lib, _f).restype = C.c_int32
 
@@ -478,6 +479,9 @@ class Mlp:
         if a.size != MLP_PARAMS:
             raise ValueError("expected 35977 parameters")
         self._c(_lib.dsmc_mlp_set_weights(self.h, _p(a)))
+
+    def init_weights(self, seed=0):
+        self._c(_lib.dsmc_mlp_init_weights(self.h, seed))
 
     def get_weights(self):
         a = np.zeros(MLP_PARAMS, np.float32)
