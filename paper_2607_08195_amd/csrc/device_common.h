@@ -101,27 +101,32 @@ struct GroupDev {
 };
 
 // Slot of a particle in its cell's histogram bin.  Lanes of a wave that
-// land in the same cell take consecutive slots from one atomic add: the
-// first active lane's cell is served per round (at most kRankRounds rounds,
-// so a wave spread over many cells falls back to one atomic per lane).
-// Must be called by every lane of the wave (uniform control flow).
-constexpr int kRankRounds = 4;
+// land in the same cell are grouped (ballot rounds over the first pending
+// lane's cell, at most kRankRounds groups); one atomic add per group,
+// issued by its first lane together with the single adds of ungrouped
+// lanes, then each member takes base + its rank within the group.  Must be
+// called by every lane of the wave (uniform control flow).
+constexpr int kRankRounds = 8;
 __device__ __forceinline__ uint32_t bin_slot(int32_t* counts, int cell, bool active) {
     const int lane = threadIdx.x & 63;
     uint64_t pending = __ballot(active);
-    uint32_t slot = 0;
+    int leader_of_mine = lane;
+    uint64_t group = 0;
     for (int round = 0; round < kRankRounds && pending; ++round) {
         const int leader = __ffsll((unsigned long long)pending) - 1;
         const int c0 = __shfl(cell, leader, 64);
         const uint64_t same = __ballot(active && cell == c0) & pending;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&counts[c0], __popcll(same));
-        base = __shfl(base, leader, 64);
-        if ((same >> lane) & 1ull) slot = (uint32_t)(base + __popcll(same & ((1ull << lane) - 1ull)));
+        if ((same >> lane) & 1ull) {
+            leader_of_mine = leader;
+            group = same;
+        }
         pending &= ~same;
     }
-    if ((pending >> lane) & 1ull) slot = (uint32_t)atomicAdd(&counts[cell], 1);
-    return slot;
+    int base = 0;
+    if (active && (group == 0 || leader_of_mine == lane))
+        base = atomicAdd(&counts[cell], group ? __popcll(group) : 1);
+    const int gbase = __shfl(base, leader_of_mine, 64);
+    return group ? (uint32_t)(gbase + __popcll(group & ((1ull << lane) - 1ull))) : (uint32_t)base;
 }
 
 // Per-case parameters when several independent cases share one mesh (a

@@ -253,10 +253,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             }
         }
     }
-    {
-        const uint32_t slot = bin_slot(counts, dest, dest >= 0);
-        if (dest >= 0) rank[i] = slot;
-    }
     // wave-aggregated push of parked particles
     const uint64_t pm = __ballot(park);
     if (pm) {
@@ -271,6 +267,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             q.t[slot] = w.t;
             q.meta[slot] = (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22);
         }
+    }
+    {
+        const uint32_t slot = bin_slot(counts, dest, dest >= 0);
+        if (dest >= 0) rank[i] = slot;
     }
     block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
 }
