@@ -195,12 +195,126 @@ def bench_dig(args, dsmc, W, window=50):
     print(json.dumps(out))
 
 
+def _bins(sim, wl, nb=5):
+    """Cell -> coarse bin (nb^3 boxes over the unit cube) and cell volumes."""
+    import numpy as np
+    xyz, tets = wl.mesh.xyz, wl.mesh.tets
+    cen = xyz[tets].mean(axis=1)
+    a, b, c, d = (xyz[tets[:, k]] for k in range(4))
+    vol = np.abs(np.einsum("ij,ij->i", b - a, np.cross(c - a, d - a))) / 6.0
+    ijk = np.minimum((cen * nb).astype(int), nb - 1)
+    return ijk[:, 0] * nb * nb + ijk[:, 1] * nb + ijk[:, 2], vol, nb ** 3
+
+
+def _binned_u(u, rho, bins, vol, nbins):
+    """Mass-weighted bin averages of the velocity field."""
+    import numpy as np
+    w = np.where(np.isfinite(rho), rho, 0.0) * vol
+    out = np.zeros((nbins, 3))
+    for k in range(3):
+        out[:, k] = np.bincount(bins, weights=w * np.nan_to_num(u[:, k]), minlength=nbins) / np.maximum(
+            np.bincount(bins, weights=w, minlength=nbins), 1e-300)
+    return out
+
+
+def bench_race(args, dsmc, W, window=50, check=2000):
+    """Wall time for plain DSMC and for DSMC with the DIG coupling (learned
+    closure on) to reach the velocity field of a long plain reference run
+    within 1% L2 (mass-weighted averages over a 5^3 grid of boxes).  Plain
+    fields at step t: the average of the steps t/2..t; DIG fields: the FV
+    solution of the latest coupling.  Timed: GPU work of each method only."""
+    import numpy as np
+    import torch
+    kn, nh = args.race_kn, args.race_hex
+    mk = lambda seed, **kw: W.cavity(n_hex=nh, Kn=kn, ppc=30, jitter=0.1, vel_fp32=1, seed=seed, n_ss=0, **kw)
+    wl = mk(0)
+    bins, vol, nbins = _bins(None, wl)
+    res = {"config": {"workload": f"cavity_{nh}^3x6_Kn{kn:g}", "ppc": 30, "lid": 50.0}}
+    # reference: long plain run, average over its second half
+    ref = dsmc.Simulation(mk(1))
+    half = args.race_ref_steps // 2
+    ref.step(half)
+    s0, n0 = ref.sums(dsmc.SAMPLE_STEADY)
+    ref.step(args.race_ref_steps - half)
+    s1, n1 = ref.sums(dsmc.SAMPLE_STEADY)
+    ref.close()
+
+    def fields_of(sums, n, wl_):
+        sim_f = None
+        S = sums / n
+        rho = S[:, 0] * wl_.run.F_N / vol
+        u = S[:, 1:4] / np.maximum(S[:, :1], 1e-300)
+        return u, rho
+
+    u_ref, rho_ref = fields_of(s1 - s0, n1 - n0, wl)
+    U_ref = _binned_u(u_ref, rho_ref, bins, vol, nbins)
+    err = lambda U: float(np.linalg.norm(U - U_ref) / np.linalg.norm(U_ref))
+    res["reference_steps"] = args.race_ref_steps
+    # plain
+    sim = dsmc.Simulation(mk(2))
+    snaps = {0: (np.zeros_like(s0), 0)}
+    t_gpu, step, plain_hist, plain_t = 0.0, 0, [], None
+    while step < args.race_ref_steps:
+        a = time.perf_counter()
+        sim.step(check)
+        sim.sync()
+        t_gpu += time.perf_counter() - a
+        step += check
+        snaps[step] = sim.sums(dsmc.SAMPLE_STEADY)
+        h = (step // 2) // check * check
+        sa, na = snaps[h]
+        sb, nb_ = snaps[step]
+        u, rho = fields_of(sb - sa, nb_ - na, wl)
+        e = err(_binned_u(u, rho, bins, vol, nbins))
+        plain_hist.append((step, round(t_gpu, 3), round(e, 5)))
+        if e <= 0.01 and plain_t is None:
+            plain_t = (step, t_gpu)
+            break
+    sim.close()
+    res["plain"] = {"reached": plain_t, "history": plain_hist[-40:]}
+    # DIG with the learned closure (trained on this run's own early cells)
+    sim = dsmc.Simulation(mk(3, ewma_on=1, n_a=window))
+    net = dsmc.Mlp()
+    net.init_weights(seed=1)
+    prm = dict(kn_max=1.0, passes=3, n_m=200, eps_m=1e-6, cfl=0.8, feedback=1)
+    t_gpu, step, dig_hist, dig_t = 0.0, 0, [], None
+    trained = False
+    while step < args.race_ref_steps:
+        a = time.perf_counter()
+        sim.step(window)
+        r = sim.dig_couple(**prm)
+        if not trained and step >= 10 * window:
+            x, t, v = sim.closure_data()
+            net.train(x[v], t[v], steps=300, batch=2048, lr=1e-3, seed=2)
+            sim.set_closure(net, gate_tol=0.5)
+            trained = True
+        torch.cuda.synchronize()
+        t_gpu += time.perf_counter() - a
+        step += window
+        if step % check == 0 or step == window:
+            new = sim.dig_get("new")
+            e = err(_binned_u(new[:, 1:4], new[:, 0], bins, vol, nbins))
+            dig_hist.append((step, round(t_gpu, 3), round(e, 5), r["iters"], round(r["residual"], 4),
+                             r["n_closure"]))
+            if e <= 0.01 and dig_t is None:
+                dig_t = (step, t_gpu)
+                break
+    net.close()
+    sim.close()
+    res["dig"] = {"reached": dig_t, "history": dig_hist[-40:], "coupling": prm, "window": window}
+    res["metric"] = "wall seconds to 1% L2 of the reference velocity field"
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cavity_large", choices=["cavity_large", "cavity_small", "ensemble64", "dig_cavity40"])
+    ap.add_argument("--workload", default="cavity_large", choices=["cavity_large", "cavity_small", "ensemble64", "dig_cavity40", "fields_race"])
+    ap.add_argument("--race-hex", type=int, default=20)
+    ap.add_argument("--race-kn", type=float, default=0.01)
+    ap.add_argument("--race-ref-steps", type=int, default=200000)
     ap.add_argument("--graph", action="store_true", help="step through captured HIP graphs")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
@@ -222,6 +336,8 @@ def main():
         return bench_ensemble(args, dsmc, W)
     if args.workload == "dig_cavity40":
         return bench_dig(args, dsmc, W)
+    if args.workload == "fields_race":
+        return bench_race(args, dsmc, W)
     wl = W.cavity_large() if args.workload == "cavity_large" else W.cavity_small()
     sim = dsmc.Simulation(wl)
     np0 = sim.stats()["n_particles"]
