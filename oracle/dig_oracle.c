@@ -12,7 +12,8 @@
  * (section 3.2); the macroscopic equations (eq. macro, monatomic) are solved
  * towards steady state with the HoT frozen (eq. hot_used_in_macro_solver_ch3)
  * until the residual falls below eps_m or n_m iterations; the particles are
- * then adjusted to the new state M^{k+1}.
+ * then adjusted to the new state M^{k+1}; in a closed domain the density of
+ * M^{k+1} is first scaled so that its total mass equals the particles'.
  *
  * The finite-volume discretisation and the feedback map are not given in the
  * paper (they are delegated to its references); the readings implemented
@@ -569,6 +570,10 @@ int oracle_dig_solve(osim* s, double* prim, const double* hot, const odig_params
 /* ---------------------------------------------------------------------- */
 /* Particle feedback                                                        */
 /* ---------------------------------------------------------------------- */
+/* Per admissible or reconstructed cell with particles: velocities shifted
+ * and scaled from (u, T) of M^{k+1/2} to those of M^{k+1}; the particle
+ * count set from the new density, floor(rho_new V / (F_N m) + U), which
+ * leaves it unchanged when rho_new equals the cell's particle density. */
 void oracle_dig_feedback(osim* s, const double* po, const double* pn, const int* state) {
     int nt = s->nt;
     int64_t cap_new = s->np;
@@ -583,7 +588,7 @@ void oracle_dig_feedback(osim* s, const double* po, const double* pn, const int*
         const double* b = pn + NV * (size_t)c;
         if (!(a[0] > 0 && b[0] > 0 && a[4] > 0 && b[4] > 0)) continue;
         o_draw(s, (uint32_t)c, s->step, P_RECAL, 0, w);
-        target[c] = (int)floor((double)N * (b[0] / a[0]) + o_u01(w[0], w[1]));
+        target[c] = (int)floor(b[0] * s->vol[c] / (s->FN * s->m) + o_u01(w[0], w[1]));
         if (target[c] > N) cap_new += target[c] - N;
     }
     o_reserve(s, cap_new);
@@ -645,6 +650,13 @@ void oracle_dig_feedback(osim* s, const double* po, const double* pn, const int*
     o_sort(s);
 }
 
+/* No freestream or outflow boundary: the particle mass is fixed. */
+static int closed_domain(const osim* s) {
+    for (int g = 0; g < s->ng; ++g)
+        if (s->g_kind[g] == O_BC_INFLOW || s->g_kind[g] == O_BC_OUTFLOW) return 0;
+    return 1;
+}
+
 int oracle_dig_couple(osim* s, const odig_params* prm, odig_report* rep) {
     geometry(s);
     int nt = s->nt;
@@ -684,6 +696,13 @@ int oracle_dig_couple(osim* s, const odig_params* prm, odig_report* rep) {
     memcpy(half, prim, sizeof(double) * NV * (size_t)nt);
     if (r.n_rejected < nt) {
         oracle_dig_solve(s, prim, hot, prm, &r);
+        if (!r.failed && closed_domain(s)) {
+            /* a closed domain keeps the mass of its particles */
+            double mp = (double)s->np * s->FN * s->m, mfv = 0.0;
+            for (int c = 0; c < nt; ++c) mfv += prim[NV * (size_t)c] * s->vol[c];
+            double f = mp / mfv;
+            for (int c = 0; c < nt; ++c) prim[NV * (size_t)c] = prim[NV * (size_t)c] * f;
+        }
         if (!r.failed) {
             if (prm->feedback) oracle_dig_feedback(s, half, prim, state);
             memcpy(s->mprev, prim, sizeof(double) * NV * (size_t)nt);

@@ -186,7 +186,9 @@ def test_feedback_identity_and_shift_scale():
     o.set_particles(np.tile(xc, (n, 1)), v, np.zeros(n, np.int32), np.arange(n, dtype=np.uint32), 7, n)
     mean = v.mean(axis=0)
     T = wl.species.mass * ((v - mean) ** 2).sum(axis=1).mean() / (3 * KB)
-    old = np.tile([1.0, *mean, T], (o.nt, 1))
+    # the cell's particle density: n F_N m / V
+    rho = n * wl.run.F_N * wl.species.mass / o.volumes()[0]
+    old = np.tile([rho, *mean, T], (o.nt, 1))
     state = np.zeros(o.nt, np.int32)
     o.dig_feedback(old, old, state)
     p = o.particles()
@@ -195,7 +197,7 @@ def test_feedback_identity_and_shift_scale():
     new = old.copy()
     new[0, 1:4] = [-50.0, 20.0, 0.0]
     new[0, 4] = 4 * T
-    new[0, 0] = 2.0      # twice the density: exactly twice the particles
+    new[0, 0] = 2.0 * rho      # twice the density: exactly twice the particles
     o.dig_feedback(old, new, state)
     p = o.particles()
     assert len(p["pid"]) == 2 * n
@@ -209,8 +211,8 @@ def test_feedback_identity_and_shift_scale():
     T3 = np.stack([xyz[1] - xyz[0], xyz[2] - xyz[0], xyz[3] - xyz[0]], axis=1)
     lam = np.linalg.solve(T3, (p["x"][~orig] - xyz[0]).T).T
     assert (lam >= -1e-12).all() and (lam.sum(1) <= 1 + 1e-12).all()
-    # half the density: exactly half the particles
-    newer = new.copy(); newer[0, 0] = 1.0
+    # back to the first density: exactly the first count
+    newer = new.copy(); newer[0, 0] = rho
     o.dig_feedback(new, newer, state)
     assert o.np == n
 
@@ -225,3 +227,6 @@ def test_couple_runs_on_the_small_cavity():
     m = o.mprev()
     assert np.isfinite(m).all() and (m[:, 0] > 0).all() and (m[:, 4] > 0).all()
     assert abs(o.np / rep["np_before"] - 1) < 0.02
+    # closed cavity: the macroscopic solution carries exactly the particles' mass
+    mass = (m[:, 0] * o.volumes()).sum()
+    assert abs(mass / (rep["np_before"] * wl.run.F_N * wl.species.mass) - 1) < 1e-12
