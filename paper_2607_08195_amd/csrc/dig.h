@@ -35,6 +35,7 @@ struct DigGeom {
     const double* vol;     // [nt]
     const DigGroup* groups;
     double mass, R, mu_ref, omega, T_ref;
+    double FN;  // real molecules per particle
 };
 
 struct DigCtl {
@@ -42,6 +43,7 @@ struct DigCtl {
     int conv, failed, iters;
     int n_rejected, n_reconstructed, n_unreached;
     int n_closure, n_fallback;
+    double mass_scale;
 };
 
 struct DigWork {
@@ -85,6 +87,9 @@ void launch_dig_residual(hipStream_t s, const DigGeom& g, const double* prim, co
                          double* Rs, DigWork w, int first, double cfl);
 void launch_dig_iteration(hipStream_t s, const DigGeom& g, DigWork w, double cfl, double eps_m, int global_dt,
                           int it);
+// Closed domain: scale the density of w.prim so that its total mass equals
+// the particles' (n_particles F_N m).
+void launch_dig_mass_rescale(hipStream_t s, const DigGeom& g, DigWork w, const Scalars* sc);
 void launch_dig_set_local(hipStream_t s, const int32_t* state, uint8_t* local, int nt);
 void launch_dig_fb_count(hipStream_t s, const DigGeom& g, DigWork w, const int32_t* offsets, const int32_t* orig,
                          const Scalars* sc, RngKey key);

@@ -385,6 +385,7 @@ __global__ void k_dig_ctl_reset(DigCtl* ctl) {
     ctl->n_unreached = 0;
     ctl->n_closure = 0;
     ctl->n_fallback = 0;
+    ctl->mass_scale = 1.0;
 }
 
 __global__ void k_dig_copy(const double* src, double* dst, int64_t n) {
@@ -575,6 +576,29 @@ __global__ void k_dig_commit(DigGeom g, DigWork w) {
     if (c == 0) w.ctl->iters += 1;
 }
 
+__global__ __launch_bounds__(kDigThreads) void k_dig_mass_partial(DigGeom g, DigWork w) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const double m = c < g.nt ? w.prim[kDigNV * (size_t)c] * g.vol[c] : 0.0;
+    block_sum_min(m, 0.0, &w.partial[2 * blockIdx.x], &w.partial[2 * blockIdx.x + 1]);
+}
+
+__global__ __launch_bounds__(kDigThreads) void k_dig_mass_factor(DigGeom g, DigWork w, int nblk, const Scalars* sc) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kDigThreads) s += w.partial[2 * b];
+    __shared__ double tot, dummy;
+    block_sum_min(s, 0.0, &tot, &dummy);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double mp = (double)sc->np * g.FN * g.mass;
+        w.ctl->mass_scale = mp / tot;
+    }
+}
+
+__global__ void k_dig_mass_apply(DigGeom g, DigWork w) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < g.nt) w.prim[kDigNV * (size_t)c] = w.prim[kDigNV * (size_t)c] * w.ctl->mass_scale;
+}
+
 __global__ void k_dig_set_local(const int32_t* state, uint8_t* local, int nt) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c < nt) local[c] = state[c] != 0 ? 1 : 0;
@@ -587,8 +611,9 @@ __device__ __forceinline__ bool fb_valid(const double* a, const double* b) {
     return a[0] > 0 && b[0] > 0 && a[4] > 0 && b[4] > 0;
 }
 
-// Target count floor(N rho_new / rho_old + U) of each cell; clone counts
-// in the caller's cell order (new pids follow that order).
+// Target count floor(rho_new V / (F_N m) + U) of each cell (unchanged when
+// rho_new is the cell's particle density); clone counts in the caller's
+// cell order (new pids follow that order).
 __global__ void k_dig_fb_count(DigGeom g, DigWork w, const int32_t* offsets, const int32_t* orig, const Scalars* sc,
                                RngKey key) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -599,7 +624,7 @@ __global__ void k_dig_fb_count(DigGeom g, DigWork w, const int32_t* offsets, con
     const double* b = w.prim + kDigNV * (size_t)c;
     if (w.state[c] <= 1 && N > 0 && fb_valid(a, b)) {
         const Rand4 r = draw(key, (uint32_t)orig[c], sc->step, kPurposeRecalibrate, 0);
-        double t = floor((double)N * (b[0] / a[0]) + u01(r.w[0], r.w[1]));
+        double t = floor(b[0] * g.vol[c] / (g.FN * g.mass) + u01(r.w[0], r.w[1]));
         if (!(t < 1073741824.0)) t = 1073741824.0;
         T = (int)t;
     }
@@ -876,6 +901,13 @@ void launch_dig_iteration(hipStream_t s, const DigGeom& g, DigWork w, double cfl
         hipLaunchKernelGGL(k_dig_update, gr, bl, 0, s, g, w, alpha[k], global_dt);
     }
     hipLaunchKernelGGL(k_dig_commit, gr, bl, 0, s, g, w);
+}
+
+void launch_dig_mass_rescale(hipStream_t s, const DigGeom& g, DigWork w, const Scalars* sc) {
+    const dim3 gr = cells_grid(g.nt), bl(kDigThreads);
+    hipLaunchKernelGGL(k_dig_mass_partial, gr, bl, 0, s, g, w);
+    hipLaunchKernelGGL(k_dig_mass_factor, dim3(1), bl, 0, s, g, w, (int)gr.x, sc);
+    hipLaunchKernelGGL(k_dig_mass_apply, gr, bl, 0, s, g, w);
 }
 
 void launch_dig_set_local(hipStream_t s, const int32_t* state, uint8_t* local, int nt) {

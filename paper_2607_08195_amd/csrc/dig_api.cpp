@@ -214,6 +214,7 @@ dsmc_status ensure(dsmc_ctx c) {
     g.mu_ref = mu_ref_of(c);
     g.omega = c->omega;
     g.T_ref = c->Tref;
+    g.FN = c->FN;
     c->dig = d;
     return DSMC_OK;
 }
@@ -374,6 +375,9 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
     r.n_fallback = h.n_fallback;
     if (r.n_rejected < nt) {
         if ((st = run_solve(c, p, &r)) != DSMC_OK) return st;
+        bool closed = true;
+        for (const dsmc_boundary_desc& b : c->bcs) closed = closed && b.kind != DSMC_BC_INFLOW && b.kind != DSMC_BC_OUTFLOW;
+        if (!r.failed && closed) launch_dig_mass_rescale(s, d->g, d->w, c->d_sc);
         if (!r.failed) {
             if (p->feedback && (st = run_feedback(c)) != DSMC_OK) {
                 if (rep) *rep = r;
