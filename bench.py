@@ -233,14 +233,20 @@ def bench_race(args, dsmc, W, window=50, check=2000):
     # reference: long plain run, average over its second half
     ref = dsmc.Simulation(mk(1))
     half = args.race_ref_steps // 2
-    ref.step(half)
+    for done in range(0, half, 20000):
+        ref.step(min(20000, half - done))
+        ref.sync()
+        print(f"# reference step {done + min(20000, half - done)}", file=sys.stderr, flush=True)
     s0, n0 = ref.sums(dsmc.SAMPLE_STEADY)
-    ref.step(args.race_ref_steps - half)
+    for done in range(0, args.race_ref_steps - half, 20000):
+        ref.step(min(20000, args.race_ref_steps - half - done))
+        ref.sync()
+        print(f"# reference step {half + done + min(20000, args.race_ref_steps - half - done)}", file=sys.stderr,
+              flush=True)
     s1, n1 = ref.sums(dsmc.SAMPLE_STEADY)
     ref.close()
 
     def fields_of(sums, n, wl_):
-        sim_f = None
         S = sums / n
         rho = S[:, 0] * wl_.run.F_N / vol
         u = S[:, 1:4] / np.maximum(S[:, :1], 1e-300)
@@ -267,6 +273,7 @@ def bench_race(args, dsmc, W, window=50, check=2000):
         u, rho = fields_of(sb - sa, nb_ - na, wl)
         e = err(_binned_u(u, rho, bins, vol, nbins))
         plain_hist.append((step, round(t_gpu, 3), round(e, 5)))
+        print(f"# plain step {step} t {t_gpu:.2f} s err {e:.4f}", file=sys.stderr, flush=True)
         if e <= 0.01 and plain_t is None:
             plain_t = (step, t_gpu)
             break
@@ -296,6 +303,8 @@ def bench_race(args, dsmc, W, window=50, check=2000):
             e = err(_binned_u(new[:, 1:4], new[:, 0], bins, vol, nbins))
             dig_hist.append((step, round(t_gpu, 3), round(e, 5), r["iters"], round(r["residual"], 4),
                              r["n_closure"]))
+            print(f"# dig step {step} t {t_gpu:.2f} s err {e:.4f} resid {r['residual']:.3g} "
+                  f"closure {r['n_closure']} np {r['np_after']}", file=sys.stderr, flush=True)
             if e <= 0.01 and dig_t is None:
                 dig_t = (step, t_gpu)
                 break
