@@ -137,11 +137,11 @@ def bench_dig(args, dsmc, W, window=50):
     closure network is first trained on the run's own cell data.  --steps
     counts DSMC steps (rounded to whole windows)."""
     import torch
-    wl = W.cavity(n_hex=40, Kn=0.01, ppc=30, jitter=0.1, vel_fp32=1, ewma_on=1, n_a=window)
+    wl = W.cavity(n_hex=40, Kn=0.01, ppc=30, jitter=0.1, vel_fp32=1, ewma_on=1, n_a=1000)
     sim = dsmc.Simulation(wl)
     net = dsmc.Mlp()
     net.init_weights(seed=1)
-    prm = dict(kn_max=1.0, passes=3, n_m=100, eps_m=1e-4, cfl=0.5, feedback=1)
+    prm = dict(kn_max=1.0, passes=3, n_m=100, eps_m=1e-4, cfl=0.5, feedback=1, warm_start=1)
     sim.step(window)
     sim.dig_couple(**dict(prm, n_m=0, feedback=0))
     x, t, v = sim.closure_data()
@@ -226,10 +226,11 @@ def bench_race(args, dsmc, W, window=50, check=2000):
     import numpy as np
     import torch
     kn, nh = args.race_kn, args.race_hex
-    mk = lambda seed, **kw: W.cavity(n_hex=nh, Kn=kn, ppc=30, jitter=0.1, vel_fp32=1, seed=seed, n_ss=0, **kw)
+    mk = lambda seed, **kw: W.cavity(n_hex=nh, Kn=kn, ppc=30, jitter=0.1, vel_fp32=1, seed=seed, n_ss=0,
+                                     lid_speed=args.race_lid, **kw)
     wl = mk(0)
     bins, vol, nbins = _bins(None, wl)
-    res = {"config": {"workload": f"cavity_{nh}^3x6_Kn{kn:g}", "ppc": 30, "lid": 50.0}}
+    res = {"config": {"workload": f"cavity_{nh}^3x6_Kn{kn:g}", "ppc": 30, "lid": args.race_lid}}
     # reference: long plain run, average over its second half
     ref = dsmc.Simulation(mk(1))
     half = args.race_ref_steps // 2
@@ -280,10 +281,10 @@ def bench_race(args, dsmc, W, window=50, check=2000):
     sim.close()
     res["plain"] = {"reached": plain_t, "history": plain_hist[-40:]}
     # DIG with the learned closure (trained on this run's own early cells)
-    sim = dsmc.Simulation(mk(3, ewma_on=1, n_a=window))
+    sim = dsmc.Simulation(mk(3, ewma_on=1, n_a=1000))
     net = dsmc.Mlp()
     net.init_weights(seed=1)
-    prm = dict(kn_max=1.0, passes=3, n_m=200, eps_m=1e-6, cfl=0.8, feedback=1)
+    prm = dict(kn_max=1.0, passes=3, n_m=200, eps_m=1e-6, cfl=0.8, feedback=1, warm_start=1)
     t_gpu, step, dig_hist, dig_t = 0.0, 0, [], None
     trained = False
     while step < args.race_ref_steps:
@@ -324,6 +325,7 @@ def main():
     ap.add_argument("--race-hex", type=int, default=20)
     ap.add_argument("--race-kn", type=float, default=0.01)
     ap.add_argument("--race-ref-steps", type=int, default=200000)
+    ap.add_argument("--race-lid", type=float, default=200.0)
     ap.add_argument("--graph", action="store_true", help="step through captured HIP graphs")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")

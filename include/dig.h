@@ -57,6 +57,8 @@ typedef struct {
     double L0;          /* reference length of the Knudsen number, m */
     int32_t feedback;   /* 1: adjust the particles to M^{k+1} */
     int32_t global_dt;  /* 1: one pseudo-time step for all cells */
+    int32_t warm_start; /* 1: the solve starts from the previous macroscopic
+                           solution M^k (same steady target), 0: from M^{k+1/2} */
 } dig_params;
 
 typedef struct {

@@ -694,6 +694,8 @@ int oracle_dig_couple(osim* s, const odig_params* prm, odig_report* rep) {
         r.n_unreached += state[c] == 2;
     }
     memcpy(half, prim, sizeof(double) * NV * (size_t)nt);
+    /* the steady solve may start from the previous macroscopic solution */
+    if (prm->warm_start) memcpy(prim, s->mprev, sizeof(double) * NV * (size_t)nt);
     if (r.n_rejected < nt) {
         oracle_dig_solve(s, prim, hot, prm, &r);
         if (!r.failed && closed_domain(s)) {

@@ -96,6 +96,7 @@ typedef struct {
     double L0;      /* reference length of the Knudsen number */
     int feedback;   /* 1: adjust the particles to the macroscopic solution */
     int global_dt;  /* 1: one pseudo-time step for all cells (conservative) */
+    int warm_start; /* 1: the solve starts from M^k instead of M^{k+1/2} */
 } odig_params;
 
 typedef struct {

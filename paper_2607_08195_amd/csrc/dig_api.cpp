@@ -365,6 +365,7 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
     }
     launch_dig_gate(s, d->g, d->w, p->kn_max, p->passes);
     launch_dig_copy(s, d->w.prim, d->w.half, 5 * (int64_t)nt);
+    if (p->warm_start) launch_dig_copy(s, d->w.mprev, d->w.prim, 5 * (int64_t)nt);
     HIP_TRY(c, hipGetLastError());
     DigCtl h = read_ctl(c, &st);
     if (st != DSMC_OK) return st;
