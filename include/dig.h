@@ -112,8 +112,10 @@ dsmc_status dig_feedback(dsmc_ctx ctx, const double* prim_old, const double* pri
 
 /* Replace the sums of an accumulator (DSMC_SAMPLE_STEADY or
  * DSMC_SAMPLE_EWMA) by sums[n][13] (layout of dsmc_get_sums); restarts or
- * checkpoints the moving average. */
-dsmc_status dsmc_set_sums(dsmc_ctx ctx, int32_t which, const double* sums);
+ * checkpoints the moving average.  For the moving average, counts[n] (may be
+ * NULL to keep the current ones) are the per-cell numbers of samples taken,
+ * which set its weights. */
+dsmc_status dsmc_set_sums(dsmc_ctx ctx, int32_t which, const double* sums, const int32_t* counts);
 
 #ifdef __cplusplus
 }

@@ -51,6 +51,7 @@ def _load():
     lib.oracle_num_steady.argtypes = [P]
     lib.oracle_set_local_acc.argtypes = [P, P]
     lib.oracle_set_sums.argtypes = [P, i, P]
+    lib.oracle_get_ewma_counts.argtypes = [P, P]
     lib.oracle_fields.argtypes = [P, i, P]
     lib.oracle_get_volumes.argtypes = [P, P]
     lib.oracle_get_neighbours.argtypes = [P, P]
@@ -206,6 +207,11 @@ class Oracle:
     def sums(self, which=0):
         o = np.zeros((self.nt, 13))
         self.lib.oracle_get_sums(self.h, which, _p(o))
+        return o
+
+    def ewma_counts(self):
+        o = np.zeros(self.nt, np.int32)
+        self.lib.oracle_get_ewma_counts(self.h, _p(o))
         return o
 
     def set_sums(self, which, sums):

@@ -799,6 +799,8 @@ void oracle_get_sums(const osim* s, int which, double* out) {
 
 int64_t oracle_num_steady(const osim* s) { return s->n_steady; }
 
+void oracle_get_ewma_counts(const osim* s, int* out) { memcpy(out, s->ewma_m, sizeof(int) * (size_t)s->nt); }
+
 void oracle_set_sums(osim* s, int which, const double* in) {
     double* dst = which == 0 ? s->acc : s->ewma;
     memcpy(dst, in, sizeof(double) * NMOM * (size_t)s->nt);

@@ -70,6 +70,8 @@ void oracle_get_sums(const osim*, int which, double* out);
 int64_t oracle_num_steady(const osim*);
 /* Replace the steady (0) or moving-average (1) sums [nt][13]. */
 void oracle_set_sums(osim*, int which, const double* in);
+/* Per-cell numbers of moving-average samples taken. */
+void oracle_get_ewma_counts(const osim*, int* out);
 void oracle_set_local_acc(osim*, const unsigned char* flags);
 /* fields [nt][15]: n, rho, u(3), T, sigma(xx,yy,zz,xy,xz,yz), q(3) */
 void oracle_fields(const osim*, int which, double* out);

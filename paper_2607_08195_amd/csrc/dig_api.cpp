@@ -476,7 +476,7 @@ dsmc_status dig_closure_data(dsmc_ctx c, float* x, float* t, uint8_t* valid) {
     return DSMC_OK;
 }
 
-dsmc_status dsmc_set_sums(dsmc_ctx c, int32_t which, const double* sums) {
+dsmc_status dsmc_set_sums(dsmc_ctx c, int32_t which, const double* sums, const int32_t* counts) {
     if (!c || !sums || (which != DSMC_SAMPLE_STEADY && which != DSMC_SAMPLE_EWMA))
         return fail(c, DSMC_E_INVALID, "bad arguments");
     if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
@@ -487,6 +487,11 @@ dsmc_status dsmc_set_sums(dsmc_ctx c, int32_t which, const double* sums) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     HIP_TRY(c, hipMemcpy(which == DSMC_SAMPLE_STEADY ? c->d_acc : c->d_ewma, h.data(), sizeof(double) * h.size(),
                          hipMemcpyHostToDevice));
+    if (which == DSMC_SAMPLE_EWMA && counts) {
+        std::vector<int32_t> m(nt);
+        for (int t = 0; t < nt; ++t) m[t] = counts[c->hm.orig[t]];
+        HIP_TRY(c, hipMemcpy(c->d_ewma_m, m.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice));
+    }
     return DSMC_OK;
 }
 

@@ -138,7 +138,7 @@ _lib.dig_get.argtypes = [ctx_t, C.c_int32, P]
 _lib.dig_residual.argtypes = [ctx_t, P, P, P]
 _lib.dig_solve.argtypes = [ctx_t, P, P, C.POINTER(DigParams), C.POINTER(DigReport)]
 _lib.dig_feedback.argtypes = [ctx_t, P, P, P, C.POINTER(C.c_int64)]
-_lib.dsmc_set_sums.argtypes = [ctx_t, C.c_int32, P]
+_lib.dsmc_set_sums.argtypes = [ctx_t, C.c_int32, P, P]
 _lib.dsmc_batch_init.argtypes = [C.POINTER(ctx_t), C.c_int32, C.POINTER(MeshDesc), C.POINTER(SpeciesDesc),
                                  P, C.POINTER(BoundaryDesc), C.POINTER(RunDesc)]
 _lib.dsmc_batch_cases.argtypes = [ctx_t, C.POINTER(C.c_int32), P]
@@ -390,11 +390,12 @@ class Simulation:
     def device_copy(self, dst, src, nbytes):
         self._c(_lib.dsmc_device_copy(self.ctx, P(dst), P(src), nbytes))
 
-    def set_sums(self, which, sums):
+    def set_sums(self, which, sums, counts=None):
         a = np.ascontiguousarray(sums, np.float64)
         if a.shape != (self.nt, 13):
             raise ValueError("sums must be [n_tets, 13]")
-        self._c(_lib.dsmc_set_sums(self.ctx, which, _p(a)))
+        m = np.ascontiguousarray(counts, np.int32) if counts is not None else None
+        self._c(_lib.dsmc_set_sums(self.ctx, which, _p(a), _p(m)))
 
     # -- DIG coupling (include/dig.h) ------------------------------------
     def dig_couple(self, **kw):

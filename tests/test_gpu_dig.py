@@ -44,7 +44,7 @@ def _pair(D, wl, steps, n_a=None, capacity_factor=4):
     st = o.particles()
     g = D.Simulation(wl, fill=False, capacity=max(capacity_factor * o.np, 100000))
     g.set_state(st["x"], st["v"], st["cell"], st["pid"], o.step_index, o.next_pid, o.smax())
-    g.set_sums(D.SAMPLE_EWMA, o.sums(1))
+    g.set_sums(D.SAMPLE_EWMA, o.sums(1), o.ewma_counts())
     g.set_sums(D.SAMPLE_STEADY, o.sums(0))
     return o, g
 
