@@ -68,6 +68,7 @@ def _load():
     lib.oracle_dig_gate.argtypes = [P, P, P, P, d, i, P]
     lib.oracle_dig_solve.argtypes = [P, P, P, P, P]
     lib.oracle_dig_residual.argtypes = [P, P, P, P]
+    lib.oracle_dig_face_hot.argtypes = [P, P, P, i, P]
     lib.oracle_dig_feedback.argtypes = [P, P, P, P]
     lib.oracle_dig_couple.argtypes = [P, P, P]
     _lib = lib
@@ -297,6 +298,12 @@ class Oracle:
         rep = DigReport()
         self.lib.oracle_dig_solve(self.h, _p(prim), _p(hot), C.byref(prm), C.byref(rep))
         return prim, _report_dict(rep)
+
+    def dig_face_hot(self, prim, hot, consistent=1):
+        prim = np.ascontiguousarray(prim, np.float64); hot = np.ascontiguousarray(hot, np.float64)
+        o = np.zeros((self.nt, 4, 9))
+        self.lib.oracle_dig_face_hot(self.h, _p(prim), _p(hot), consistent, _p(o))
+        return o
 
     def dig_residual(self, prim, hot):
         prim = np.ascontiguousarray(prim, np.float64); hot = np.ascontiguousarray(hot, np.float64)

@@ -19,7 +19,8 @@
  * paper (they are delegated to its references); the readings implemented
  * here are stated in the design notes: cell-centred finite volumes with
  * least-squares gradients, linear face reconstruction, a central flux with
- * low-Mach-scaled scalar dissipation, NSF + frozen HoT viscous fluxes and
+ * low-Mach-scaled scalar dissipation, NSF + frozen HoT viscous fluxes (the
+ * HoT carried per face so that the sampled state is consistent) and
  * local pseudo-time stepping; feedback by velocity shift-and-scale and
  * clone/delete to the density ratio.
  */
@@ -351,9 +352,77 @@ static double wave_speed(const osim* s, const double* P, const double* n) {
     return un + th * c;
 }
 
+/* Face gradients of u and T: the base gradient (gb, [5][3]) plus the
+ * correction that makes its component along the connector dx equal the
+ * difference quotient of far - near. */
+static void face_grad(const double* gb, const double* far, const double* near, const double* dx, double dl,
+                      double* gu, double* gT) {
+    for (int v = 1; v < NV; ++v) {
+        double gf[3], ga = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            gf[j] = gb[3 * v + j];
+            ga += gf[j] * dx[j] / dl;
+        }
+        double jump = (far[v] - near[v]) / dl - ga;
+        for (int j = 0; j < 3; ++j) gf[j] += jump * dx[j] / dl;
+        if (v < 4)
+            for (int j = 0; j < 3; ++j) gu[3 * (v - 1) + j] = gf[j];
+        else
+            for (int j = 0; j < 3; ++j) gT[j] = gf[j];
+    }
+}
+
+/* HoT carried by each cell face [nt][4][9]: the cell HoT averaged to the
+ * face (the cell's own at a diffuse wall); with `consistent`, plus the
+ * difference between the cell NSF stresses (cell gradients, cell T)
+ * averaged to the face and the face NSF stress of the viscous flux (face
+ * gradients, face T), both at the state prim.  At prim the viscous stress of
+ * every face is then the average of the two cells' NSF + HoT, i.e. of their
+ * sampled stresses (the coupling step's HoT). */
+static void face_hot(osim* s, const double* prim, const double* g, const double* hot, int consistent, double* hotf) {
+    for (int c = 0; c < s->nt; ++c) {
+        const double* Pc = prim + NV * (size_t)c;
+        const double* gc = g + 15 * (size_t)c;
+        double nc[9];
+        nsf_local(s, Pc[4], gc + 3, gc + 12, nc);
+        for (int f = 0; f < 4; ++f) {
+            int nb;
+            double dx[3];
+            int kind = face_link(s, c, f, &nb, dx);
+            double* h = hotf + 36 * (size_t)c + 9 * f;
+            double dl = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+            double gu[9], gT[3], vf[9];
+            if (kind == L_INTERIOR || kind == L_PERIODIC) {
+                const double* Pn = prim + NV * (size_t)nb;
+                const double* gn = g + 15 * (size_t)nb;
+                double gavg[15], nn[9];
+                for (int k = 0; k < 15; ++k) gavg[k] = 0.5 * (gc[k] + gn[k]);
+                face_grad(gavg, Pn, Pc, dx, dl, gu, gT);
+                nsf_local(s, 0.5 * (Pc[4] + Pn[4]), gu, gT, vf);
+                nsf_local(s, Pn[4], gn + 3, gn + 12, nn);
+                for (int k = 0; k < 9; ++k) {
+                    h[k] = 0.5 * (hot[9 * (size_t)c + k] + hot[9 * (size_t)nb + k]);
+                    if (consistent) h[k] += 0.5 * (nc[k] + nn[k]) - vf[k];
+                }
+            } else if (kind == L_WALL) {
+                int grp = face_group(s, c, f);
+                double wallv[NV] = {Pc[0], s->g_u[3 * grp], s->g_u[3 * grp + 1], s->g_u[3 * grp + 2], s->g_T[grp]};
+                face_grad(gc, wallv, Pc, dx, dl, gu, gT);
+                nsf_local(s, s->g_T[grp], gu, gT, vf);
+                for (int k = 0; k < 9; ++k) {
+                    h[k] = hot[9 * (size_t)c + k];
+                    if (consistent) h[k] += nc[k] - vf[k];
+                }
+            } else {
+                for (int k = 0; k < 9; ++k) h[k] = 0.0;
+            }
+        }
+    }
+}
+
 /* residual R[nt][5] = sum over faces of (flux . n) A, and the sum over faces
  * of (spectral radius) A for the pseudo-time step: spec[nt] */
-static void residual_all(osim* s, const double* prim, const double* hot, const double* g, double* Rs, double* spec) {
+static void residual_all(osim* s, const double* prim, const double* hotf, const double* g, double* Rs, double* spec) {
     double R = KB / s->m;
     for (int c = 0; c < s->nt; ++c) {
         const double* Pc = prim + NV * (size_t)c;
@@ -402,25 +471,14 @@ static void residual_all(osim* s, const double* prim, const double* hot, const d
                 /* viscous: averaged gradients corrected along the centroid connector */
                 double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
                 double dl = sqrt(d2);
-                double gu[9], gT[3];
-                for (int v = 1; v < NV; ++v) {
-                    double gf[3], ga = 0.0;
-                    for (int j = 0; j < 3; ++j) {
-                        gf[j] = 0.5 * (gc[3 * v + j] + gn[3 * v + j]);
-                        ga += gf[j] * dx[j] / dl;
-                    }
-                    double jump = (Pn[v] - Pc[v]) / dl - ga;
-                    for (int j = 0; j < 3; ++j) gf[j] += jump * dx[j] / dl;
-                    if (v < 4)
-                        for (int j = 0; j < 3; ++j) gu[3 * (v - 1) + j] = gf[j];
-                    else
-                        for (int j = 0; j < 3; ++j) gT[j] = gf[j];
-                }
+                double gu[9], gT[3], gavg[15];
+                for (int k = 0; k < 15; ++k) gavg[k] = 0.5 * (gc[k] + gn[k]);
+                face_grad(gavg, Pn, Pc, dx, dl, gu, gT);
                 double Tf = 0.5 * (Pc[4] + Pn[4]);
                 double rf = 0.5 * (Pc[0] + Pn[0]);
                 double vis[9];
                 nsf_local(s, Tf, gu, gT, vis);
-                for (int k = 0; k < 9; ++k) vis[k] += 0.5 * (hot[9 * (size_t)c + k] + hot[9 * (size_t)nb + k]);
+                for (int k = 0; k < 9; ++k) vis[k] += hotf[36 * (size_t)c + 9 * f + k];
                 double uf[3] = {0.5 * (Pc[1] + Pn[1]), 0.5 * (Pc[2] + Pn[2]), 0.5 * (Pc[3] + Pn[3])};
                 double S[3][3] = {{vis[0], vis[3], vis[4]}, {vis[3], vis[1], vis[5]}, {vis[4], vis[5], vis[2]}};
                 double work = 0.0;
@@ -445,22 +503,10 @@ static void residual_all(osim* s, const double* prim, const double* hot, const d
                     double dl = sqrt(d2);
                     double wallv[NV] = {Pc[0], uw[0], uw[1], uw[2], Tw};
                     double gu[9], gT[3];
-                    for (int v = 1; v < NV; ++v) {
-                        double gf[3], ga = 0.0;
-                        for (int j = 0; j < 3; ++j) {
-                            gf[j] = gc[3 * v + j];
-                            ga += gf[j] * dx[j] / dl;
-                        }
-                        double jump = (wallv[v] - Pc[v]) / dl - ga;
-                        for (int j = 0; j < 3; ++j) gf[j] += jump * dx[j] / dl;
-                        if (v < 4)
-                            for (int j = 0; j < 3; ++j) gu[3 * (v - 1) + j] = gf[j];
-                        else
-                            for (int j = 0; j < 3; ++j) gT[j] = gf[j];
-                    }
+                    face_grad(gc, wallv, Pc, dx, dl, gu, gT);
                     double vis[9];
                     nsf_local(s, Tw, gu, gT, vis);
-                    for (int k = 0; k < 9; ++k) vis[k] += hot[9 * (size_t)c + k];
+                    for (int k = 0; k < 9; ++k) vis[k] += hotf[36 * (size_t)c + 9 * f + k];
                     double S[3][3] = {{vis[0], vis[3], vis[4]}, {vis[3], vis[1], vis[5]}, {vis[4], vis[5], vis[2]}};
                     double work = 0.0;
                     for (int i = 0; i < 3; ++i) {
@@ -498,13 +544,23 @@ static void residual_all(osim* s, const double* prim, const double* hot, const d
     }
 }
 
+void oracle_dig_face_hot(osim* s, const double* prim, const double* hot, int consistent, double* hotf) {
+    geometry(s);
+    double* g = (double*)malloc(sizeof(double) * 15 * (size_t)s->nt);
+    gradients5(s, prim, g);
+    face_hot(s, prim, g, hot, consistent, hotf);
+    free(g);
+}
+
 void oracle_dig_residual(osim* s, const double* prim, const double* hot, double* out) {
     geometry(s);
     double* g = (double*)malloc(sizeof(double) * 15 * (size_t)s->nt);
     double* spec = (double*)malloc(sizeof(double) * (size_t)s->nt);
+    double* hotf = (double*)malloc(sizeof(double) * 36 * (size_t)s->nt);
     gradients5(s, prim, g);
-    residual_all(s, prim, hot, g, out, spec);
-    free(g); free(spec);
+    face_hot(s, prim, g, hot, 0, hotf);
+    residual_all(s, prim, hotf, g, out, spec);
+    free(g); free(spec); free(hotf);
 }
 
 /* Pseudo-time marching to steady state: three-stage Runge-Kutta
@@ -512,8 +568,7 @@ void oracle_dig_residual(osim* s, const double* prim, const double* hot, double*
  * cfl V / sum_f A (|u.n| + c + viscous rate); stops when the density
  * residual norm falls below eps_m times its first value or after n_m
  * iterations. */
-int oracle_dig_solve(osim* s, double* prim, const double* hot, const odig_params* prm, odig_report* rep) {
-    geometry(s);
+static int solve_faces(osim* s, double* prim, const double* hotf, const odig_params* prm, odig_report* rep) {
     int nt = s->nt;
     const double alpha[3] = {1.0 / 3.0, 0.5, 1.0};
     double* g = (double*)malloc(sizeof(double) * 15 * (size_t)nt);
@@ -529,7 +584,7 @@ int oracle_dig_solve(osim* s, double* prim, const double* hot, const odig_params
         for (int c = 0; c < nt; ++c) cons_of(s, prim + NV * (size_t)c, U0 + NV * (size_t)c);
         for (int k = 0; k < 3 && !failed; ++k) {
             gradients5(s, stage, g);
-            residual_all(s, stage, hot, g, Rs, spec);
+            residual_all(s, stage, hotf, g, Rs, spec);
             if (k == 0) {
                 double acc = 0.0;
                 for (int c = 0; c < nt; ++c) acc += Rs[NV * (size_t)c] * Rs[NV * (size_t)c];
@@ -565,6 +620,18 @@ int oracle_dig_solve(osim* s, double* prim, const double* hot, const odig_params
     }
     free(g); free(Rs); free(spec); free(dt); free(U0); free(stage);
     return failed ? -1 : 0;
+}
+
+/* The solve with the cell HoT averaged to the faces. */
+int oracle_dig_solve(osim* s, double* prim, const double* hot, const odig_params* prm, odig_report* rep) {
+    geometry(s);
+    double* g = (double*)malloc(sizeof(double) * 15 * (size_t)s->nt);
+    double* hotf = (double*)malloc(sizeof(double) * 36 * (size_t)s->nt);
+    gradients5(s, prim, g);
+    face_hot(s, prim, g, hot, 0, hotf);
+    int rc = solve_faces(s, prim, hotf, prm, rep);
+    free(g); free(hotf);
+    return rc;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -694,10 +761,15 @@ int oracle_dig_couple(osim* s, const odig_params* prm, odig_report* rep) {
         r.n_unreached += state[c] == 2;
     }
     memcpy(half, prim, sizeof(double) * NV * (size_t)nt);
+    /* face HoT consistent with M^{k+1/2} */
+    double* g5 = (double*)malloc(sizeof(double) * 15 * (size_t)nt);
+    double* hotf = (double*)malloc(sizeof(double) * 36 * (size_t)nt);
+    gradients5(s, half, g5);
+    face_hot(s, half, g5, hot, 1, hotf);
     /* the steady solve may start from the previous macroscopic solution */
     if (prm->warm_start) memcpy(prim, s->mprev, sizeof(double) * NV * (size_t)nt);
     if (r.n_rejected < nt) {
-        oracle_dig_solve(s, prim, hot, prm, &r);
+        solve_faces(s, prim, hotf, prm, &r);
         if (!r.failed && closed_domain(s)) {
             /* a closed domain keeps the mass of its particles */
             double mp = (double)s->np * s->FN * s->m, mfv = 0.0;
@@ -713,7 +785,7 @@ int oracle_dig_couple(osim* s, const odig_params* prm, odig_report* rep) {
     for (int c = 0; c < nt; ++c) s->local_acc[c] = state[c] != 0;
     r.np_after = s->np;
     if (rep) *rep = r;
-    free(smp); free(prim); free(half); free(grad); free(nsf); free(hot); free(kn); free(state);
+    free(smp); free(prim); free(half); free(grad); free(nsf); free(hot); free(kn); free(state); free(g5); free(hotf);
     return r.failed ? -1 : 0;
 }
 

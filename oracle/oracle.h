@@ -132,6 +132,10 @@ void oracle_dig_kn_cell(osim*, const double* prim, double L0, double* out);
 void oracle_dig_gate(osim*, double* prim, double* hot, const double* kn, double kn_max, int passes, int* state);
 /* Macroscopic synthetic solve from prim (in/out) with frozen hot. */
 int oracle_dig_solve(osim*, double* prim, const double* hot, const odig_params*, odig_report*);
+/* HoT of every cell face hotf[nt][4][9] from cell HoT at prim: averaged to
+ * the faces, and with `consistent` corrected so that at prim each face's
+ * viscous stress is the average of the two cells' NSF + HoT. */
+void oracle_dig_face_hot(osim*, const double* prim, const double* hot, int consistent, double* hotf);
 /* Residual of the discrete macroscopic equations at prim: out[nt][5]. */
 void oracle_dig_residual(osim*, const double* prim, const double* hot, double* out);
 /* Particle feedback from (prim_old -> prim_new) on cells with state <= 1. */

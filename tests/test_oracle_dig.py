@@ -230,3 +230,49 @@ def test_couple_runs_on_the_small_cavity():
     # closed cavity: the macroscopic solution carries exactly the particles' mass
     mass = (m[:, 0] * o.volumes()).sum()
     assert abs(mass / (rep["np_before"] * wl.run.F_N * wl.species.mass) - 1) < 1e-12
+
+
+def test_face_hot_averages_and_is_conservative():
+    """Face HoT: the two cells' mean on interior faces, the cell's own on
+    diffuse walls, nothing elsewhere; the consistent correction is the same
+    seen from both cells of an interior face."""
+    wl = W.cavity(n_hex=3, Kn=0.1, ppc=2, jitter=0.15)
+    o = Oracle(wl, fill=False)
+    o.set_reference(wl.run.n0, wl.run.T0)
+    rng = np.random.default_rng(17)
+    nt = o.nt
+    prim = _uniform(wl, o)
+    prim[:, 0] *= 1 + 0.1 * rng.random(nt)
+    prim[:, 1:4] = 30 * rng.standard_normal((nt, 3))
+    prim[:, 4] *= 1 + 0.1 * rng.random(nt)
+    hot = rng.standard_normal((nt, 9))
+    avg = o.dig_face_hot(prim, hot, consistent=0)
+    cons = o.dig_face_hot(prim, hot, consistent=1)
+    nbr = o.neighbours()
+    for c in range(nt):
+        for f in range(4):
+            n = nbr[c, f]
+            if n >= 0:
+                assert np.allclose(avg[c, f], 0.5 * (hot[c] + hot[n]), rtol=1e-15, atol=0)
+                g = list(nbr[n]).index(c)
+                assert np.array_equal(cons[c, f], cons[n, g]), (c, f)
+            else:
+                assert np.array_equal(avg[c, f], hot[c])       # every cavity wall is diffuse
+    assert np.abs(cons - avg).max() > 0
+
+
+def test_face_hot_correction_vanishes_for_linear_fields():
+    """On a linear velocity field at uniform temperature the cell and face
+    gradients are exact, so the consistent face HoT equals the plain mean."""
+    U, Tw = 200.0, 273.0
+    wl = W.plates(n=(3, 6, 3), U=U, T1=Tw, T2=Tw, n0=1e21, periodic=True)
+    o = Oracle(wl, fill=False)
+    o.set_reference(wl.run.n0, Tw)
+    prim = _uniform(wl, o)
+    y = _centroids(wl, o)[:, 1]
+    prim[:, 1] = U * (y - 0.5)
+    hot = np.random.default_rng(3).standard_normal((o.nt, 9))
+    avg = o.dig_face_hot(prim, hot, consistent=0)
+    cons = o.dig_face_hot(prim, hot, consistent=1)
+    mu = wl.species.mu(Tw)
+    assert np.abs(cons - avg).max() <= 1e-9 * mu * U
