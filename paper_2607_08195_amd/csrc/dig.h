@@ -51,7 +51,8 @@ struct DigWork {
     uint8_t* ok;      // [nt] cell has samples
     double* prim;     // [nt][5] working state; M^{k+1} after the solve
     double* half;     // [nt][5] M^{k+1/2} after the gate
-    double* hot;      // [nt][9]
+    double* hot;      // [nt][9] cell HoT
+    double* hotf;     // [nt][4][9] HoT carried by each cell face (the solve's closure)
     double* grad;     // [nt][5][3] gradients of the primitives
     double* kn;       // [nt]
     uint8_t* avail;   // [nt]
@@ -80,10 +81,14 @@ void launch_dig_sampled(hipStream_t s, const DigGeom& g, const double* ewma, dou
 void launch_dig_kn(hipStream_t s, const DigGeom& g, DigWork w, double kn_ref, double T0, double rho0, double L0);
 void launch_dig_gradients(hipStream_t s, const DigGeom& g, const double* prim, double* grad, const DigCtl* ctl);
 void launch_dig_hot(hipStream_t s, const DigGeom& g, DigWork w);
+// Face HoT from cell HoT at prim (with `consistent`, corrected so that each
+// face's viscous stress at prim is the average of its cells' NSF + HoT).
+void launch_dig_face_hot(hipStream_t s, const DigGeom& g, const double* prim, const double* grad, const double* hot,
+                         double* hotf, int consistent);
 void launch_dig_gate(hipStream_t s, const DigGeom& g, DigWork w, double kn_max, int passes);
 void launch_dig_ctl_reset(hipStream_t s, DigCtl* ctl);
 void launch_dig_copy(hipStream_t s, const double* src, double* dst, int64_t n);
-void launch_dig_residual(hipStream_t s, const DigGeom& g, const double* prim, const double* hot, const double* grad,
+void launch_dig_residual(hipStream_t s, const DigGeom& g, const double* prim, const double* hotf, const double* grad,
                          double* Rs, DigWork w, int first, double cfl);
 void launch_dig_iteration(hipStream_t s, const DigGeom& g, DigWork w, double cfl, double eps_m, int global_dt,
                           int it);

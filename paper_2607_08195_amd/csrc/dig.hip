@@ -301,6 +301,57 @@ __global__ void k_dig_hot(DigGeom g, DigWork w) {
     for (int k = 0; k < 9; ++k) w.hot[9 * (size_t)c + k] = ok ? a[5 + k] - nsf[k] : 0.0;
 }
 
+// HoT carried by each cell face: the cell HoT averaged to the face (the
+// cell's own at a diffuse wall); with `consistent`, plus the cell NSF
+// stresses averaged to the face minus the face NSF stress of the viscous
+// flux, both at prim, so that at prim each face's viscous stress is the
+// average of its cells' NSF + HoT.
+__global__ void k_dig_face_hot(DigGeom g, const double* prim, const double* grad, const double* hot, double* hotf,
+                               int consistent) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt) return;
+    double Pc[kDigNV], gc[15], nc[9];
+    for (int v = 0; v < kDigNV; ++v) Pc[v] = prim[kDigNV * (size_t)c + v];
+    for (int k = 0; k < 15; ++k) gc[k] = grad[15 * (size_t)c + k];
+    nsf_local(g, Pc[4], gc + 3, gc + 12, nc);
+    for (int f = 0; f < 4; ++f) {
+        const int link = g.flink[4 * c + f];
+        const int kind = link & 7, idx = link >> 3;
+        const size_t fo = 12 * (size_t)c + 3 * f;
+        const double dx[3] = {g.fdx[fo], g.fdx[fo + 1], g.fdx[fo + 2]};
+        const double dl = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+        double* h = hotf + 36 * (size_t)c + 9 * f;
+        double gu[9], gT[3], vf[9];
+        if (kind == kLinkInterior || kind == kLinkPeriodic) {
+            const int nb = idx;
+            double Pn[kDigNV], gn[15], gavg[15], nn[9];
+            for (int v = 0; v < kDigNV; ++v) Pn[v] = prim[kDigNV * (size_t)nb + v];
+            for (int k = 0; k < 15; ++k) gn[k] = grad[15 * (size_t)nb + k];
+            for (int k = 0; k < 15; ++k) gavg[k] = 0.5 * (gc[k] + gn[k]);
+            face_gradients(gavg, Pn, Pc, dx, dl, gu, gT);
+            nsf_local(g, 0.5 * (Pc[4] + Pn[4]), gu, gT, vf);
+            nsf_local(g, Pn[4], gn + 3, gn + 12, nn);
+            for (int k = 0; k < 9; ++k) {
+                double v = 0.5 * (hot[9 * (size_t)c + k] + hot[9 * (size_t)nb + k]);
+                if (consistent) v += 0.5 * (nc[k] + nn[k]) - vf[k];
+                h[k] = v;
+            }
+        } else if (kind == kLinkWall) {
+            const DigGroup& gr = g.groups[idx];
+            const double wallv[kDigNV] = {Pc[0], gr.u[0], gr.u[1], gr.u[2], gr.T};
+            face_gradients(gc, wallv, Pc, dx, dl, gu, gT);
+            nsf_local(g, gr.T, gu, gT, vf);
+            for (int k = 0; k < 9; ++k) {
+                double v = hot[9 * (size_t)c + k];
+                if (consistent) v += nc[k] - vf[k];
+                h[k] = v;
+            }
+        } else {
+            for (int k = 0; k < 9; ++k) h[k] = 0.0;
+        }
+    }
+}
+
 // Admissibility (criterion on Kn_Delta) and availability of every cell.
 __global__ void k_dig_gate_init(DigGeom g, DigWork w, double kn_max) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -396,20 +447,18 @@ __global__ void k_dig_copy(const double* src, double* dst, int64_t n) {
 // ---------------------------------------------------------------------------
 // finite-volume residual: R_c = sum_f (F_inviscid + F_viscous).n A_f
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kDigThreads) void k_dig_residual(DigGeom g, const double* prim, const double* hot,
+__global__ __launch_bounds__(kDigThreads) void k_dig_residual(DigGeom g, const double* prim, const double* hotf,
                                                               const double* grad, double* Rs, DigWork w, int first,
                                                               double cfl) {
     if (stopped(w.ctl)) return;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     double r2 = 0.0, dtc = __builtin_inf();
     if (c < g.nt) {
-        double Pc[kDigNV], gc[15], hc[9];
+        double Pc[kDigNV], gc[15];
 #pragma unroll
         for (int v = 0; v < kDigNV; ++v) Pc[v] = prim[kDigNV * (size_t)c + v];
 #pragma unroll
         for (int k = 0; k < 15; ++k) gc[k] = grad[15 * (size_t)c + k];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) hc[k] = hot[9 * (size_t)c + k];
         const double xc[3] = {g.cen[3 * (size_t)c], g.cen[3 * (size_t)c + 1], g.cen[3 * (size_t)c + 2]};
         double Rc[kDigNV] = {0, 0, 0, 0, 0};
         double sp = 0.0;
@@ -461,9 +510,9 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_residual(DigGeom g, const d
                 const double rf = 0.5 * (Pc[0] + Pn[0]);
                 double vis[9];
                 nsf_local(g, Tf, gu, gT, vis);
-                const double* hn = hot + 9 * (size_t)nb;
+                const double* hf = hotf + 36 * (size_t)c + 9 * f;
 #pragma unroll
-                for (int k = 0; k < 9; ++k) vis[k] += 0.5 * (hc[k] + hn[k]);
+                for (int k = 0; k < 9; ++k) vis[k] += hf[k];
                 const double uf[3] = {0.5 * (Pc[1] + Pn[1]), 0.5 * (Pc[2] + Pn[2]), 0.5 * (Pc[3] + Pn[3])};
                 add_viscous(vis, n, uf, F);
                 lamv = viscous_rate(g, Tf, rf, dl);
@@ -481,8 +530,9 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_residual(DigGeom g, const d
                     face_gradients(gc, wallv, Pc, dx, dl, gu, gT);
                     double vis[9];
                     nsf_local(g, gr.T, gu, gT, vis);
+                    const double* hf = hotf + 36 * (size_t)c + 9 * f;
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) vis[k] += hc[k];
+                    for (int k = 0; k < 9; ++k) vis[k] += hf[k];
                     add_viscous(vis, n, gr.u, F);
                     lamv = viscous_rate(g, gr.T, Pc[0], dl);
                 }
@@ -879,10 +929,16 @@ void launch_dig_copy(hipStream_t s, const double* src, double* dst, int64_t n) {
     hipLaunchKernelGGL(k_dig_copy, cells_grid(n), dim3(kDigThreads), 0, s, src, dst, n);
 }
 
-void launch_dig_residual(hipStream_t s, const DigGeom& g, const double* prim, const double* hot, const double* grad,
+void launch_dig_residual(hipStream_t s, const DigGeom& g, const double* prim, const double* hotf, const double* grad,
                          double* Rs, DigWork w, int first, double cfl) {
-    hipLaunchKernelGGL(k_dig_residual, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, prim, hot, grad, Rs, w, first,
+    hipLaunchKernelGGL(k_dig_residual, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, prim, hotf, grad, Rs, w, first,
                        cfl);
+}
+
+void launch_dig_face_hot(hipStream_t s, const DigGeom& g, const double* prim, const double* grad, const double* hot,
+                         double* hotf, int consistent) {
+    hipLaunchKernelGGL(k_dig_face_hot, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, prim, grad, hot, hotf,
+                       consistent);
 }
 
 // One pseudo-time iteration: three stages with weights 1/3, 1/2, 1; the
@@ -895,7 +951,7 @@ void launch_dig_iteration(hipStream_t s, const DigGeom& g, DigWork w, double cfl
     hipLaunchKernelGGL(k_dig_save, gr, bl, 0, s, g, w);
     for (int k = 0; k < 3; ++k) {
         hipLaunchKernelGGL(k_dig_grad, gr, bl, 0, s, g, (const double*)w.stage, w.grad, (const DigCtl*)w.ctl);
-        hipLaunchKernelGGL(k_dig_residual, gr, bl, 0, s, g, (const double*)w.stage, (const double*)w.hot,
+        hipLaunchKernelGGL(k_dig_residual, gr, bl, 0, s, g, (const double*)w.stage, (const double*)w.hotf,
                            (const double*)w.grad, w.Rs, w, k == 0 ? 1 : 0, cfl);
         if (k == 0) hipLaunchKernelGGL(k_dig_check, dim3(1), bl, 0, s, w, nblk, it, eps_m);
         hipLaunchKernelGGL(k_dig_update, gr, bl, 0, s, g, w, alpha[k], global_dt);

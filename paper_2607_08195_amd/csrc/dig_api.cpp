@@ -157,7 +157,7 @@ dsmc_status ensure(dsmc_ctx c) {
               alloc_n(c, farea, G.farea.size()) && alloc_n(c, fdx, G.fdx.size()) && alloc_n(c, lsq, G.lsq.size()) &&
               alloc_n(c, flink, G.flink.size()) && alloc_n(c, groups, ng + 1);
     ok = ok && alloc_n(c, w.samp, 14 * (size_t)nt) && alloc_n(c, w.ok, nt) && alloc_n(c, w.prim, 5 * (size_t)nt) &&
-         alloc_n(c, w.half, 5 * (size_t)nt) && alloc_n(c, w.hot, 9 * (size_t)nt) &&
+         alloc_n(c, w.half, 5 * (size_t)nt) && alloc_n(c, w.hot, 9 * (size_t)nt) && alloc_n(c, w.hotf, 36 * (size_t)nt) &&
          alloc_n(c, w.grad, 15 * (size_t)nt) && alloc_n(c, w.kn, nt) && alloc_n(c, w.avail, nt) &&
          alloc_n(c, w.navail, nt) && alloc_n(c, w.nprim, 5 * (size_t)nt) && alloc_n(c, w.nhot, 9 * (size_t)nt) &&
          alloc_n(c, w.state, nt) && alloc_n(c, w.mprev, 5 * (size_t)nt) && alloc_n(c, w.Rs, 5 * (size_t)nt) &&
@@ -365,6 +365,9 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
     }
     launch_dig_gate(s, d->g, d->w, p->kn_max, p->passes);
     launch_dig_copy(s, d->w.prim, d->w.half, 5 * (int64_t)nt);
+    // the solve's face HoT, consistent with M^{k+1/2}
+    launch_dig_gradients(s, d->g, d->w.half, d->w.grad, nullptr);
+    launch_dig_face_hot(s, d->g, d->w.half, d->w.grad, d->w.hot, d->w.hotf, 1);
     if (p->warm_start) launch_dig_copy(s, d->w.mprev, d->w.prim, 5 * (int64_t)nt);
     HIP_TRY(c, hipGetLastError());
     DigCtl h = read_ctl(c, &st);
@@ -421,7 +424,8 @@ dsmc_status dig_residual(dsmc_ctx c, const double* prim, const double* hot, doub
     if ((st = to_device(c, d->w.nhot, hot, 9)) != DSMC_OK) return st;
     launch_dig_ctl_reset(c->stream, d->w.ctl);
     launch_dig_gradients(c->stream, d->g, d->w.stage, d->w.grad, d->w.ctl);
-    launch_dig_residual(c->stream, d->g, d->w.stage, d->w.nhot, d->w.grad, d->w.Rs, d->w, 0, 1.0);
+    launch_dig_face_hot(c->stream, d->g, d->w.stage, d->w.grad, d->w.nhot, d->w.hotf, 0);
+    launch_dig_residual(c->stream, d->g, d->w.stage, d->w.hotf, d->w.grad, d->w.Rs, d->w, 0, 1.0);
     HIP_TRY(c, hipGetLastError());
     return to_host(c, out, d->w.Rs, 5);
 }
@@ -434,6 +438,8 @@ dsmc_status dig_solve(dsmc_ctx c, double* prim, const double* hot, const dig_par
     DigState* d = c->dig;
     if ((st = to_device(c, d->w.prim, (const double*)prim, 5)) != DSMC_OK) return st;
     if ((st = to_device(c, d->w.hot, hot, 9)) != DSMC_OK) return st;
+    launch_dig_gradients(c->stream, d->g, d->w.prim, d->w.grad, nullptr);
+    launch_dig_face_hot(c->stream, d->g, d->w.prim, d->w.grad, d->w.hot, d->w.hotf, 0);
     dig_report r{};
     if ((st = run_solve(c, p, &r)) != DSMC_OK) return st;
     if ((st = to_host(c, prim, d->w.prim, 5)) != DSMC_OK) return st;
