@@ -69,6 +69,7 @@ def _load():
     lib.oracle_dig_solve.argtypes = [P, P, P, P, P]
     lib.oracle_dig_residual.argtypes = [P, P, P, P]
     lib.oracle_dig_face_hot.argtypes = [P, P, P, i, P]
+    lib.oracle_dig_residual_faces.argtypes = [P, P, P, P]
     lib.oracle_dig_feedback.argtypes = [P, P, P, P]
     lib.oracle_dig_couple.argtypes = [P, P, P]
     _lib = lib
@@ -303,6 +304,12 @@ class Oracle:
         prim = np.ascontiguousarray(prim, np.float64); hot = np.ascontiguousarray(hot, np.float64)
         o = np.zeros((self.nt, 4, 9))
         self.lib.oracle_dig_face_hot(self.h, _p(prim), _p(hot), consistent, _p(o))
+        return o
+
+    def dig_residual_faces(self, prim, hotf):
+        prim = np.ascontiguousarray(prim, np.float64); hotf = np.ascontiguousarray(hotf, np.float64)
+        o = np.zeros((self.nt, 5))
+        self.lib.oracle_dig_residual_faces(self.h, _p(prim), _p(hotf), _p(o))
         return o
 
     def dig_residual(self, prim, hot):

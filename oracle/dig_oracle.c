@@ -544,6 +544,15 @@ static void residual_all(osim* s, const double* prim, const double* hotf, const 
     }
 }
 
+void oracle_dig_residual_faces(osim* s, const double* prim, const double* hotf, double* out) {
+    geometry(s);
+    double* g = (double*)malloc(sizeof(double) * 15 * (size_t)s->nt);
+    double* spec = (double*)malloc(sizeof(double) * (size_t)s->nt);
+    gradients5(s, prim, g);
+    residual_all(s, prim, hotf, g, out, spec);
+    free(g); free(spec);
+}
+
 void oracle_dig_face_hot(osim* s, const double* prim, const double* hot, int consistent, double* hotf) {
     geometry(s);
     double* g = (double*)malloc(sizeof(double) * 15 * (size_t)s->nt);

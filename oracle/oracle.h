@@ -136,6 +136,8 @@ int oracle_dig_solve(osim*, double* prim, const double* hot, const odig_params*,
  * the faces, and with `consistent` corrected so that at prim each face's
  * viscous stress is the average of the two cells' NSF + HoT. */
 void oracle_dig_face_hot(osim*, const double* prim, const double* hot, int consistent, double* hotf);
+/* Residual at prim with given face HoT hotf[nt][4][9]: out[nt][5]. */
+void oracle_dig_residual_faces(osim*, const double* prim, const double* hotf, double* out);
 /* Residual of the discrete macroscopic equations at prim: out[nt][5]. */
 void oracle_dig_residual(osim*, const double* prim, const double* hot, double* out);
 /* Particle feedback from (prim_old -> prim_new) on cells with state <= 1. */
