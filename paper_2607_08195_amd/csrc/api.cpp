@@ -74,9 +74,8 @@ namespace {
 
 bool alloc_buf(dsmc_ctx c, Buf& b, int64_t cap, int vel64) {
     const size_t vs = vel64 ? sizeof(double) : sizeof(float);
-    return alloc_n(c, b.x, cap) && alloc_n(c, b.y, cap) && alloc_n(c, b.z, cap) &&
-           (b.vx = dev_alloc(c, vs * cap)) && (b.vy = dev_alloc(c, vs * cap)) &&
-           (b.vz = dev_alloc(c, vs * cap)) && alloc_n(c, b.cell, cap) && alloc_n(c, b.pid, cap);
+    return alloc_n(c, b.pos, 3 * (size_t)cap) && (b.vel = dev_alloc(c, vs * 3 * (size_t)cap)) &&
+           alloc_n(c, b.cell, cap) && alloc_n(c, b.pid, cap);
 }
 
 hipEvent_t get_event(dsmc_ctx c) {
@@ -127,7 +126,7 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
     PartDev<VT> a = as_dev<VT>(c->A), b = as_dev<VT>(c->B);
     {
         Timed t(c, kSlotBegin);
-        launch_begin(s, c->d_counts, c->nt, c->d_sc, smp ? 1 : 0, c->n_ss);
+        launch_begin(s, c->d_counts, c->nt, c->d_sc, smp ? 1 : 0, c->n_ss, c->wq.n);
     }
     if (mv) {
         Timed t(c, kSlotMove);
@@ -188,8 +187,16 @@ dsmc_status step_any(dsmc_ctx c, int mask) {
     return c->vel64 ? run_step<double>(c, mask) : run_step<float>(c, mask);
 }
 
+// Move schedules that read the per-case tables of a batch (lane, parked-wall
+// and capped parked-wall kernels).
+bool move_reads_cases(int v) {
+    return v == kMoveLane || v == kMoveLaneW6 || v == kMoveLaneW8 || v == kMoveDefer4 || v == kMoveDefer5 ||
+           v == kMoveDefer6 || v == kMoveDefer8 || v == kMoveCap4 || v == kMoveCap5 || v == kMoveCap6;
+}
+
 // Tuning overrides from the environment: DSMC_MOVE (lane, lane6, lane8,
-// batched), DSMC_MOVE_BATCH, DSMC_REORDER (0/1).
+// batched, defer4/5/6/8, cap4/5/6, refill5/6, pool128/256), DSMC_MOVE_BATCH,
+// DSMC_REORDER (0/1), DSMC_SORT, DSMC_COLLIDE.
 void read_tuning(dsmc_ctx c) {
     if (const char* v = std::getenv("DSMC_MOVE")) {
         std::string s(v);
@@ -205,8 +212,12 @@ void read_tuning(dsmc_ctx c) {
         else if (s == "refill6") c->move_variant = kMoveRefill6;
         else if (s == "pool128") c->move_variant = kMovePool128;
         else if (s == "pool256") c->move_variant = kMovePool256;
+        else if (s == "cap4") c->move_variant = kMoveCap4;
+        else if (s == "cap5") c->move_variant = kMoveCap5;
+        else if (s == "cap6") c->move_variant = kMoveCap6;
     }
-    if (const char* v = std::getenv("DSMC_MOVE_BATCH")) c->move_batch = std::max(64, std::atoi(v) / 64 * 64);
+    if (const char* v = std::getenv("DSMC_MOVE_BATCH"))
+        c->move_batch = std::min(kQueueMaxBatch, std::max(64, std::atoi(v) / 64 * 64));
     if (const char* v = std::getenv("DSMC_REORDER")) c->reorder = std::atoi(v) != 0;
     if (const char* v = std::getenv("DSMC_SORT")) c->sort_variant = std::string(v) == "scatter" ? kSortScatter : kSortGather;
     if (const char* v = std::getenv("DSMC_COLLIDE")) {
@@ -214,6 +225,8 @@ void read_tuning(dsmc_ctx c) {
         if (s == "lds") c->collide_variant = kCollideLds;
         else if (s == "global") c->collide_variant = kCollideGlobal;
         else if (s == "global8") c->collide_variant = kCollideGlobal8;
+        else if (s == "global3k") c->collide_variant = kCollideG3k;
+        else if (s == "global2k") c->collide_variant = kCollideG2k;
     }
 }
 
@@ -230,7 +243,7 @@ void drop_graph(dsmc_ctx_s::Graph& g) {
 // it found them) into a graph and instantiate it.
 dsmc_status capture_two_steps(dsmc_ctx c, dsmc_ctx_s::Graph& g) {
     drop_graph(g);
-    const void* a_x = c->A.x;
+    const void* a_x = c->A.pos;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     c->capturing = true;
     dsmc_status st = step_any(c, 31);
@@ -354,9 +367,7 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     c->vel64 = run->vel_fp64 ? 1 : 0;
     c->bcs.assign(bcs, bcs + n_bc);
     c->n_ss = run->n_ss; c->n_a = run->n_a; c->ewma_on = run->ewma_on ? 1 : 0;
-    if (bs && c->move_variant != kMoveLane && c->move_variant != kMoveLaneW6 && c->move_variant != kMoveLaneW8 &&
-        c->move_variant != kMoveDefer4 && c->move_variant != kMoveDefer5 && c->move_variant != kMoveDefer6 &&
-        c->move_variant != kMoveDefer8)
+    if (bs && !move_reads_cases(c->move_variant))
         c->move_variant = kMoveDefer6;  // the batch tables are read by the lane and deferring kernels
 
     // expected particle count at n0 sizes the default capacity
@@ -430,7 +441,11 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
          alloc_n(c, d_in_cst, (size_t)kInflowStride * nin + 1);
     ok = ok && alloc_buf(c, c->A, c->cap, c->vel64) && alloc_buf(c, c->B, c->cap, c->vel64) &&
          alloc_n(c, c->d_rank, c->cap) && alloc_n(c, c->d_perm, c->cap) && alloc_n(c, c->d_sortperm, c->cap) &&
-         alloc_n(c, c->wq.idx, c->cap) && alloc_n(c, c->wq.t, c->cap) && alloc_n(c, c->wq.meta, c->cap);
+         alloc_n(c, c->wq.idx, kQueueParts * queue_part_size(c->cap)) &&
+         alloc_n(c, c->wq.t, kQueueParts * queue_part_size(c->cap)) &&
+         alloc_n(c, c->wq.meta, kQueueParts * queue_part_size(c->cap)) &&
+         alloc_n(c, c->wq.n, (size_t)kQueueParts * kQueueStride);
+    c->wq.part = queue_part_size(c->cap);
     if (!ok) {
         dsmc_destroy(c);
         return fail(nullptr, DSMC_E_OOM, "device allocation failed");
@@ -635,9 +650,9 @@ dsmc_status dsmc_graph_step(dsmc_ctx c, int32_t n) {
     while (done + 2 <= n) {
         dsmc_ctx_s::Graph* g = nullptr;
         for (auto& cand : c->graphs)
-            if (cand.exec && cand.a_x == c->A.x && cand.sig == tuning_sig(c)) g = &cand;
+            if (cand.exec && cand.a_x == c->A.pos && cand.sig == tuning_sig(c)) g = &cand;
         if (!g) {
-            g = (c->graphs[0].a_x == c->A.x || !c->graphs[0].exec) ? &c->graphs[0] : &c->graphs[1];
+            g = (c->graphs[0].a_x == c->A.pos || !c->graphs[0].exec) ? &c->graphs[0] : &c->graphs[1];
             dsmc_status st = capture_two_steps(c, *g);
             if (st != DSMC_OK) return st;
         }
@@ -659,9 +674,8 @@ dsmc_status dsmc_get_tuning(dsmc_ctx c, dsmc_tuning* t) {
 
 dsmc_status dsmc_set_tuning(dsmc_ctx c, const dsmc_tuning* t) {
     if (!c || !t) return fail(c, DSMC_E_INVALID, "bad arguments");
-    const bool batch_ok = t->move == kMoveLane || t->move == kMoveLaneW6 || t->move == kMoveLaneW8 ||
-                          (t->move >= kMoveDefer6 && t->move <= kMoveDefer5);
-    if (t->move < 0 || t->move > kMovePool256 || t->collide < 0 || t->collide > kCollideGlobal8 || t->sort < 0 ||
+    const bool batch_ok = move_reads_cases(t->move);
+    if (t->move < 0 || t->move > kMoveCap6 || t->collide < 0 || t->collide > kCollideG2k || t->sort < 0 ||
         t->sort > kSortGather || (c->n_cases && !batch_ok))
         return fail(c, DSMC_E_INVALID, "unknown or unsupported kernel variant");
     c->move_variant = t->move;
@@ -675,7 +689,8 @@ dsmc_status dsmc_autotune(dsmc_ctx c, int32_t trial_steps, dsmc_tuning* out) {
     if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
     const bool was_profiling = c->profiling;
     dsmc_tuning best{c->move_variant, c->collide_variant, c->sort_variant, 1e300, 1e300, 1e300};
-    const int moves[] = {kMoveDefer4, kMoveDefer5, kMoveDefer6, kMoveDefer8, kMoveLaneW6, kMoveLaneW8};
+    const int moves[] = {kMoveDefer4, kMoveDefer5, kMoveDefer6, kMoveDefer8, kMoveCap4, kMoveCap5, kMoveCap6,
+                         kMoveLaneW6, kMoveLaneW8};
     for (int v : moves) {
         c->move_variant = v;
         double ms = 0;
@@ -684,7 +699,7 @@ dsmc_status dsmc_autotune(dsmc_ctx c, int32_t trial_steps, dsmc_tuning* out) {
         if (ms < best.move_ms) { best.move_ms = ms; best.move = v; }
     }
     c->move_variant = best.move;
-    const int collides[] = {kCollideGlobal, kCollideGlobal8, kCollideLds};
+    const int collides[] = {kCollideGlobal, kCollideGlobal8, kCollideG3k, kCollideG2k, kCollideLds};
     for (int v : collides) {
         c->collide_variant = v;
         double ms = 0;
@@ -782,24 +797,16 @@ dsmc_status dsmc_get_state(dsmc_ctx c, dsmc_state* st) {
         for (int t = 0; t < c->nt; ++t) st->smax[c->hm.orig[t]] = sm[t];
     }
     if (!st->x && !st->v && !st->cell && !st->pid) return DSMC_OK;
-    std::vector<double> x(n), y(n), z(n), vx(n), vy(n), vz(n);
+    std::vector<double> xs(3 * n), vs(3 * n);
     std::vector<int32_t> cell(n);
     std::vector<uint32_t> pid(n);
-    HIP_TRY(c, hipMemcpy(x.data(), c->A.x, 8 * n, hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(y.data(), c->A.y, 8 * n, hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(z.data(), c->A.z, 8 * n, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(xs.data(), c->A.pos, 24 * n, hipMemcpyDeviceToHost));
     if (c->vel64) {
-        HIP_TRY(c, hipMemcpy(vx.data(), c->A.vx, 8 * n, hipMemcpyDeviceToHost));
-        HIP_TRY(c, hipMemcpy(vy.data(), c->A.vy, 8 * n, hipMemcpyDeviceToHost));
-        HIP_TRY(c, hipMemcpy(vz.data(), c->A.vz, 8 * n, hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(vs.data(), c->A.vel, 24 * n, hipMemcpyDeviceToHost));
     } else {
-        std::vector<float> f(n);
-        HIP_TRY(c, hipMemcpy(f.data(), c->A.vx, 4 * n, hipMemcpyDeviceToHost));
-        for (int64_t i = 0; i < n; ++i) vx[i] = f[i];
-        HIP_TRY(c, hipMemcpy(f.data(), c->A.vy, 4 * n, hipMemcpyDeviceToHost));
-        for (int64_t i = 0; i < n; ++i) vy[i] = f[i];
-        HIP_TRY(c, hipMemcpy(f.data(), c->A.vz, 4 * n, hipMemcpyDeviceToHost));
-        for (int64_t i = 0; i < n; ++i) vz[i] = f[i];
+        std::vector<float> f(3 * n);
+        HIP_TRY(c, hipMemcpy(f.data(), c->A.vel, 12 * n, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < 3 * n; ++i) vs[i] = f[i];
     }
     HIP_TRY(c, hipMemcpy(cell.data(), c->A.cell, 4 * n, hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(pid.data(), c->A.pid, 4 * n, hipMemcpyDeviceToHost));
@@ -812,8 +819,8 @@ dsmc_status dsmc_get_state(dsmc_ctx c, dsmc_state* st) {
     });
     for (int64_t k = 0; k < n; ++k) {
         const int64_t i = idx[k];
-        if (st->x) { st->x[3 * k] = x[i]; st->x[3 * k + 1] = y[i]; st->x[3 * k + 2] = z[i]; }
-        if (st->v) { st->v[3 * k] = vx[i]; st->v[3 * k + 1] = vy[i]; st->v[3 * k + 2] = vz[i]; }
+        if (st->x) { st->x[3 * k] = xs[3 * i]; st->x[3 * k + 1] = xs[3 * i + 1]; st->x[3 * k + 2] = xs[3 * i + 2]; }
+        if (st->v) { st->v[3 * k] = vs[3 * i]; st->v[3 * k + 1] = vs[3 * i + 1]; st->v[3 * k + 2] = vs[3 * i + 2]; }
         if (st->cell) st->cell[k] = cell[i];
         if (st->pid) st->pid[k] = pid[i];
     }
@@ -836,32 +843,26 @@ dsmc_status dsmc_set_state(dsmc_ctx c, const dsmc_state* st) {
         if (ca != cb) return ca < cb;
         return st->pid[a] < st->pid[b];
     });
-    std::vector<double> x(n), y(n), z(n), vx(n), vy(n), vz(n);
+    std::vector<double> xs(3 * n), vs(3 * n);
     std::vector<int32_t> cell(n), counts(c->nt + 1, 0);
     std::vector<uint32_t> pid(n);
     for (int64_t k = 0; k < n; ++k) {
         const int64_t i = idx[k];
-        x[k] = st->x[3 * i]; y[k] = st->x[3 * i + 1]; z[k] = st->x[3 * i + 2];
-        vx[k] = st->v[3 * i]; vy[k] = st->v[3 * i + 1]; vz[k] = st->v[3 * i + 2];
+        for (int j = 0; j < 3; ++j) {
+            xs[3 * k + j] = st->x[3 * i + j];
+            vs[3 * k + j] = st->v[3 * i + j];
+        }
         cell[k] = inv[st->cell[i]]; pid[k] = st->pid[i];
         counts[cell[k] + 1]++;
     }
     for (int t = 0; t < c->nt; ++t) counts[t + 1] += counts[t];
-    HIP_TRY(c, hipMemcpy(c->A.x, x.data(), 8 * n, hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->A.y, y.data(), 8 * n, hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->A.z, z.data(), 8 * n, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->A.pos, xs.data(), 24 * n, hipMemcpyHostToDevice));
     if (c->vel64) {
-        HIP_TRY(c, hipMemcpy(c->A.vx, vx.data(), 8 * n, hipMemcpyHostToDevice));
-        HIP_TRY(c, hipMemcpy(c->A.vy, vy.data(), 8 * n, hipMemcpyHostToDevice));
-        HIP_TRY(c, hipMemcpy(c->A.vz, vz.data(), 8 * n, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->A.vel, vs.data(), 24 * n, hipMemcpyHostToDevice));
     } else {
-        std::vector<float> f(n);
-        for (int64_t i = 0; i < n; ++i) f[i] = (float)vx[i];
-        HIP_TRY(c, hipMemcpy(c->A.vx, f.data(), 4 * n, hipMemcpyHostToDevice));
-        for (int64_t i = 0; i < n; ++i) f[i] = (float)vy[i];
-        HIP_TRY(c, hipMemcpy(c->A.vy, f.data(), 4 * n, hipMemcpyHostToDevice));
-        for (int64_t i = 0; i < n; ++i) f[i] = (float)vz[i];
-        HIP_TRY(c, hipMemcpy(c->A.vz, f.data(), 4 * n, hipMemcpyHostToDevice));
+        std::vector<float> f(3 * n);
+        for (int64_t i = 0; i < 3 * n; ++i) f[i] = (float)vs[i];
+        HIP_TRY(c, hipMemcpy(c->A.vel, f.data(), 12 * n, hipMemcpyHostToDevice));
     }
     HIP_TRY(c, hipMemcpy(c->A.cell, cell.data(), 4 * n, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->A.pid, pid.data(), 4 * n, hipMemcpyHostToDevice));

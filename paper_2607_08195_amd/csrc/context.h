@@ -14,19 +14,15 @@
 namespace dsmcx {
 
 struct Buf {
-    double* x = nullptr;
-    double* y = nullptr;
-    double* z = nullptr;
-    void* vx = nullptr;
-    void* vy = nullptr;
-    void* vz = nullptr;
+    double* pos = nullptr;  // [cap][3]
+    void* vel = nullptr;    // [cap][3] float or double
     int32_t* cell = nullptr;
     uint32_t* pid = nullptr;
 };
 
 template <class VT>
 PartDev<VT> as_dev(const Buf& b) {
-    return PartDev<VT>{b.x, b.y, b.z, (VT*)b.vx, (VT*)b.vy, (VT*)b.vz, b.cell, b.pid};
+    return PartDev<VT>{b.pos, (VT*)b.vel, b.cell, b.pid};
 }
 
 struct DigState;  // coupling state, owned by the context
@@ -72,7 +68,7 @@ struct dsmc_ctx_s {
     dsmcx::Buf A, B;
     uint32_t* d_rank = nullptr;
     int32_t* d_perm = nullptr;
-    dsmcx::WallQueue wq{nullptr, nullptr, nullptr};
+    dsmcx::WallQueue wq{nullptr, nullptr, nullptr, nullptr, 0};
     // cells
     int32_t* d_counts = nullptr;
     int32_t* d_offsets = nullptr;
@@ -90,7 +86,7 @@ struct dsmc_ctx_s {
     // tuning choices
     int move_variant = dsmcx::kMoveDefer6;
     int move_batch = 0;
-    int collide_variant = dsmcx::kCollideGlobal;
+    int collide_variant = dsmcx::kCollideG3k;
     int sort_variant = dsmcx::kSortGather;
     int32_t* d_sortperm = nullptr;
     bool reorder = true;

@@ -699,9 +699,9 @@ __global__ __launch_bounds__(kFbLanes) void k_dig_fb_apply(DigWork w, PartDev<VT
     const double scale = sqrt(b[4] / a[4]);
     for (int i = lane; i < N; i += kFbLanes) {
         const int64_t k = a0 + i;
-        p.vx[k] = (VT)(b[1] + scale * ((double)p.vx[k] - a[1]));
-        p.vy[k] = (VT)(b[2] + scale * ((double)p.vy[k] - a[2]));
-        p.vz[k] = (VT)(b[3] + scale * ((double)p.vz[k] - a[3]));
+        p.vel[3 * k] = (VT)(b[1] + scale * ((double)p.vel[3 * k] - a[1]));
+        p.vel[3 * k + 1] = (VT)(b[2] + scale * ((double)p.vel[3 * k + 1] - a[2]));
+        p.vel[3 * k + 2] = (VT)(b[3] + scale * ((double)p.vel[3 * k + 2] - a[3]));
     }
     // logical (pid) order of the cell
     for (int i = lane; i < N; i += kFbLanes) {
@@ -784,12 +784,12 @@ __global__ __launch_bounds__(kFbLanes) void k_dig_fb_apply(DigWork w, PartDev<VT
             const double w0 = u1, w1 = u2 - u1, w2 = u3 - u2, w3 = 1.0 - u3;
             const int64_t d = base + k;
             if (d >= cap) continue;
-            p.x[d] = ((w0 * A[0] + w1 * B[0]) + w2 * C[0]) + w3 * D[0];
-            p.y[d] = ((w0 * A[1] + w1 * B[1]) + w2 * C[1]) + w3 * D[1];
-            p.z[d] = ((w0 * A[2] + w1 * B[2]) + w2 * C[2]) + w3 * D[2];
-            p.vx[d] = p.vx[si];
-            p.vy[d] = p.vy[si];
-            p.vz[d] = p.vz[si];
+            p.pos[3 * d] = ((w0 * A[0] + w1 * B[0]) + w2 * C[0]) + w3 * D[0];
+            p.pos[3 * d + 1] = ((w0 * A[1] + w1 * B[1]) + w2 * C[1]) + w3 * D[1];
+            p.pos[3 * d + 2] = ((w0 * A[2] + w1 * B[2]) + w2 * C[2]) + w3 * D[2];
+            p.vel[3 * d] = p.vel[3 * si];
+            p.vel[3 * d + 1] = p.vel[3 * si + 1];
+            p.vel[3 * d + 2] = p.vel[3 * si + 2];
             p.cell[d] = c;
             p.pid[d] = pid0 + (uint32_t)k;
         }

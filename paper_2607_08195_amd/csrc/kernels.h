@@ -22,19 +22,17 @@ enum { kFlagCapacity = 1 };
 // move kernel variants (tuning choice)
 enum { kMoveLane = 0, kMoveLaneW6 = 1, kMoveLaneW8 = 2, kMoveBatched = 3, kMoveDefer6 = 4, kMoveDefer8 = 5, kMoveDefer4 = 6,
        kMoveDefer5 = 7, kMoveRefill5 = 8, kMoveRefill6 = 9,
-       kMovePool128 = 10, kMovePool256 = 11 };
-enum { kCollideLds = 0, kCollideGlobal = 1, kCollideGlobal8 = 2 };
+       kMovePool128 = 10, kMovePool256 = 11, kMoveCap4 = 12, kMoveCap5 = 13, kMoveCap6 = 14 };
+enum { kCollideLds = 0, kCollideGlobal = 1, kCollideGlobal8 = 2, kCollideG3k = 3, kCollideG2k = 4 };
 enum { kSortScatter = 0, kSortGather = 1 };
 
-// Particle store, structure of arrays.
+// Particle store: positions and velocities interleaved per particle (a
+// scattered access then touches one cache line per quantity, not three),
+// cells and ids in arrays of their own.
 template <class VT>
 struct PartDev {
-    double* x;
-    double* y;
-    double* z;
-    VT* vx;
-    VT* vy;
-    VT* vz;
+    double* pos;      // [cap][3] positions, x y z of a particle adjacent
+    VT* vel;          // [cap][3] velocities, interleaved likewise
     int32_t* cell;
     uint32_t* pid;
 };
@@ -49,15 +47,29 @@ struct Scalars {
     uint32_t next_pid;
     int32_t ninj;       // particles injected this step
     int32_t flags;
-    int64_t n_wall;     // particles parked at a diffuse wall this step
 };
 
-// Particles parked at a diffuse wall by the deferring move kernel.
+// Particles parked by the deferring move kernels (at a diffuse wall, or in
+// flight after the capped number of exit tests).  The queue is split into
+// kQueueParts parts; workgroup b pushes into part b % kQueueParts, whose
+// counter lives on its own 256-byte line, so that the wave-aggregated
+// atomics of a launch spread over many addresses instead of queueing on one.
+constexpr int kQueueParts = 64;
+constexpr int kQueueStride = 32;     // counters kQueueStride x 8 bytes apart
+constexpr int kQueueMaxBatch = 4096; // largest particles-per-wave batch of any move kernel
 struct WallQueue {
-    int32_t* idx;    // particle index
-    double* t;       // remaining time
-    int32_t* meta;   // entry face | hits << 2 | hops << 12 | walls << 22
+    int32_t* idx;              // particle index
+    double* t;                 // remaining time (negative: parked in flight)
+    int32_t* meta;             // entry face | hits << 2 | hops << 12 | walls << 22
+    unsigned long long* n;     // [kQueueParts * kQueueStride] entries per part
+    int64_t part;              // entries per part
 };
+// Entries per part for a particle capacity: a part serves every
+// kQueueParts-th workgroup, each of which owns at most 4 * kQueueMaxBatch
+// particles, and the grids round up to 8 workgroups.
+inline int64_t queue_part_size(int64_t cap) {
+    return (cap + kQueueParts - 1) / kQueueParts + 2 * 4 * (int64_t)kQueueMaxBatch;
+}
 
 struct Counters {
     unsigned long long hops, walls, injected, removed, lost;
@@ -90,7 +102,8 @@ struct CollideParams {
     const CaseDev* cases;
 };
 
-void launch_begin(hipStream_t s, int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss);
+void launch_begin(hipStream_t s, int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss,
+                  unsigned long long* queue_n);
 void launch_init_count(hipStream_t s, const double* vol, const int32_t* orig, int nt, double n0, double FN,
                        RngKey key, int32_t* counts, int32_t* counts_orig, const int32_t* cell_case,
                        const CaseDev* cases);

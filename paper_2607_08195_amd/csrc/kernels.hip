@@ -51,17 +51,37 @@ __device__ __forceinline__ void block_counters(int a, int b, int c, int d, unsig
     }
 }
 
+// Wave-aggregated push of the lanes with `park` set into this workgroup's
+// part of the parked-particle queue (one atomic per wave).
+__device__ __forceinline__ void queue_push(const WallQueue& q, bool park, int64_t i, double t, int meta) {
+    const uint64_t pm = __ballot(park);
+    if (!pm) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)pm) - 1;
+    const int part = (int)(blockIdx.x % kQueueParts);
+    int64_t base = 0;
+    if (lane == leader)
+        base = (int64_t)atomicAdd(q.n + (size_t)part * kQueueStride, (unsigned long long)__popcll(pm));
+    base = __shfl(base, leader, 64);
+    if (park) {
+        const int64_t slot = part * q.part + base + __popcll(pm & ((1ull << lane) - 1ull));
+        q.idx[slot] = (int32_t)i;
+        q.t[slot] = t;
+        q.meta[slot] = meta;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // step bookkeeping
 // ---------------------------------------------------------------------------
-__global__ void k_begin(int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss) {
+__global__ void k_begin(int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss, unsigned long long* queue_n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i <= nt) counts[i] = 0;
+    if (i < kQueueParts) queue_n[i * kQueueStride] = 0ull;
     if (i == 0) {
         const uint32_t s = sc->step + 1;
         sc->step = s;
         sc->ninj = 0;
-        sc->n_wall = 0;
         if (do_sample && (int64_t)s > (int64_t)n_ss) sc->n_steady += 1;
     }
 }
@@ -131,15 +151,15 @@ __global__ void k_init_fill(const int4* tv, const double* xyz, int nt, const int
         if (s2 > s3) { tmp = s2; s2 = s3; s3 = tmp; }
         if (s1 > s2) { tmp = s1; s1 = s2; s2 = tmp; }
         const double w0 = s1, w1 = s2 - s1, w2 = s3 - s2, w3 = 1.0 - s3;
-        p.x[k] = ((w0 * A[0] + w1 * B[0]) + w2 * C[0]) + w3 * D[0];
-        p.y[k] = ((w0 * A[1] + w1 * B[1]) + w2 * C[1]) + w3 * D[1];
-        p.z[k] = ((w0 * A[2] + w1 * B[2]) + w2 * C[2]) + w3 * D[2];
+        p.pos[3 * k] = ((w0 * A[0] + w1 * B[0]) + w2 * C[0]) + w3 * D[0];
+        p.pos[3 * k + 1] = ((w0 * A[1] + w1 * B[1]) + w2 * C[1]) + w3 * D[1];
+        p.pos[3 * k + 2] = ((w0 * A[2] + w1 * B[2]) + w2 * C[2]) + w3 * D[2];
         double g1, g2, g3, g4;
         box_muller(u[3], u[4], g1, g2);
         box_muller(u[5], u[6], g3, g4);
-        p.vx[k] = (VT)(u0x + sig * g1);
-        p.vy[k] = (VT)(u0y + sig * g2);
-        p.vz[k] = (VT)(u0z + sig * g3);
+        p.vel[3 * k] = (VT)(u0x + sig * g1);
+        p.vel[3 * k + 1] = (VT)(u0y + sig * g2);
+        p.vel[3 * k + 2] = (VT)(u0z + sig * g3);
         p.cell[k] = t;
         p.pid[k] = id;
     }
@@ -173,8 +193,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     int hops = 0, walls = 0, rem = 0, lost = 0, dest = -1;
     if (i < n) {
         Walker w;
-        w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
-        w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
+        w.x0 = p.pos[3 * i]; w.x1 = p.pos[3 * i + 1]; w.x2 = p.pos[3 * i + 2];
+        w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
         w.c = p.cell[i]; w.pid = p.pid[i];
         RngKey kp = key;
         double dtp = dt;
@@ -188,9 +208,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         } while (st < 0);
         hops = w.nhop;
         walls = w.walls;
-        p.x[i] = w.x0; p.y[i] = w.x1; p.z[i] = w.x2;
+        p.pos[3 * i] = w.x0; p.pos[3 * i + 1] = w.x1; p.pos[3 * i + 2] = w.x2;
         if (w.walls) {
-            p.vx[i] = (VT)w.v0; p.vy[i] = (VT)w.v1; p.vz[i] = (VT)w.v2;
+            p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
         }
         if (st == 0) {
             p.cell[i] = w.c;
@@ -209,8 +229,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 // One particle per lane; a particle that reaches a diffuse wall is parked at
 // the wall (position, cell and remaining time) in a queue, so the costly
 // re-emission sampling does not diverge the hop loop.  k_move_walls then
-// re-emits the queued particles and finishes their step.
-template <class VT, int WPE>
+// re-emits the queued particles and finishes their step.  With CAP > 0 a
+// lane also stops after CAP exit tests and parks its particle in flight
+// (velocity written back, remaining time queued with a negative sign): a
+// wave then runs at most CAP iterations instead of the largest hop count of
+// its 64 particles, and the few long tracks finish in k_move_walls on
+// compacted waves.
+template <class VT, int WPE, int CAP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_move_defer(
     MeshDev m, PartDev<VT> p, Scalars* sc, int32_t* counts, uint32_t* rank, Counters* ctr, RngKey key,
     double dt, WallQueue q) {
@@ -218,10 +243,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const int64_t n = sc->np;
     int hops = 0, walls = 0, rem = 0, lost = 0, dest = -1;
     bool park = false;
-    Walker w;
+    Walker w{};
     if (i < n) {
-        w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
-        w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
+        w.x0 = p.pos[3 * i]; w.x1 = p.pos[3 * i + 1]; w.x2 = p.pos[3 * i + 2];
+        w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
         w.c = p.cell[i]; w.pid = p.pid[i];
         RngKey kp = key;
         double dtp = dt;
@@ -230,18 +255,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0;
         const uint32_t step = sc->step;
         int st;
+        int it = 0;
         do {
             st = hop_once<VT, true>(m, w, step, kp);
-        } while (st < 0);
-        p.x[i] = w.x0; p.y[i] = w.x1; p.z[i] = w.x2;
+        } while (st < 0 && (CAP == 0 || ++it < CAP));
+        p.pos[3 * i] = w.x0; p.pos[3 * i + 1] = w.x1; p.pos[3 * i + 2] = w.x2;
         if (st == kHopWallPending) {
             park = true;
             p.cell[i] = w.c;
+        } else if (CAP > 0 && st < 0) {
+            // in flight after CAP tests: the queued time carries a negative
+            // sign (a parked particle always has time left, t > 0)
+            park = true;
+            p.cell[i] = w.c;
+            p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
+            w.t = -w.t;
         } else {
             hops = w.nhop;
             walls = w.walls;
             if (w.walls) {
-                p.vx[i] = (VT)w.v0; p.vy[i] = (VT)w.v1; p.vz[i] = (VT)w.v2;
+                p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
             }
             if (st == 0) {
                 p.cell[i] = w.c;
@@ -253,21 +286,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             }
         }
     }
-    // wave-aggregated push of parked particles
-    const uint64_t pm = __ballot(park);
-    if (pm) {
-        const int lane = threadIdx.x & 63;
-        const int leader = __ffsll((unsigned long long)pm) - 1;
-        int64_t base = 0;
-        if (lane == leader) base = (int64_t)atomicAdd((unsigned long long*)&sc->n_wall, (unsigned long long)__popcll(pm));
-        base = __shfl(base, leader, 64);
-        if (park) {
-            const int64_t slot = base + __popcll(pm & ((1ull << lane) - 1ull));
-            q.idx[slot] = (int32_t)i;
-            q.t[slot] = w.t;
-            q.meta[slot] = (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22);
-        }
-    }
+    queue_push(q, park, i, w.t, (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22));
     {
         const uint32_t slot = bin_slot(counts, dest, dest >= 0);
         if (dest >= 0) rank[i] = slot;
@@ -297,8 +316,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     w.x0 = w.x1 = w.x2 = w.v0 = w.v1 = w.v2 = w.t = 0.0;
     w.c = 0; w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0; w.pid = 0;
     if (active) {
-        w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
-        w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
+        w.x0 = p.pos[3 * i]; w.x1 = p.pos[3 * i + 1]; w.x2 = p.pos[3 * i + 2];
+        w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
         w.c = p.cell[i]; w.pid = p.pid[i]; w.t = dt;
     }
     while (__ballot(active) != 0ull) {
@@ -307,12 +326,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         const bool done = active && st >= 0;
         const bool park = done && st == kHopWallPending;
         if (done) {
-            p.x[i] = w.x0; p.y[i] = w.x1; p.z[i] = w.x2;
+            p.pos[3 * i] = w.x0; p.pos[3 * i + 1] = w.x1; p.pos[3 * i + 2] = w.x2;
             if (park) {
                 p.cell[i] = w.c;
             } else {
                 if (w.walls) {
-                    p.vx[i] = (VT)w.v0; p.vy[i] = (VT)w.v1; p.vz[i] = (VT)w.v2;
+                    p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
                 }
                 if (st == 0) {
                     p.cell[i] = w.c;
@@ -326,28 +345,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 walls += w.walls;
             }
         }
-        const uint64_t pm = __ballot(park);
-        if (pm) {
-            const int leader = __ffsll((unsigned long long)pm) - 1;
-            int64_t base = 0;
-            if (lane == leader)
-                base = (int64_t)atomicAdd((unsigned long long*)&sc->n_wall, (unsigned long long)__popcll(pm));
-            base = __shfl(base, leader, 64);
-            if (park) {
-                const int64_t slot = base + __popcll(pm & below);
-                q.idx[slot] = (int32_t)i;
-                q.t[slot] = w.t;
-                q.meta[slot] = (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22);
-            }
-        }
+        queue_push(q, park, i, w.t, (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22));
         const uint64_t dm = __ballot(done);
         if (done) {
             const int64_t ni = next + __popcll(dm & below);
             active = ni < hi;
             if (active) {
                 i = ni;
-                w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
-                w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
+                w.x0 = p.pos[3 * i]; w.x1 = p.pos[3 * i + 1]; w.x2 = p.pos[3 * i + 2];
+                w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
                 w.c = p.cell[i]; w.pid = p.pid[i]; w.t = dt;
                 w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0;
             }
@@ -380,8 +386,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const int64_t lo = wv * (int64_t)POOL;
     const int cnt = (int)max((int64_t)0, min((int64_t)POOL, n - lo));
     for (int k = lane; k < cnt; k += 64) {
-        sx[wid][k] = p.x[lo + k]; sy[wid][k] = p.y[lo + k]; sz[wid][k] = p.z[lo + k];
-        svx[wid][k] = p.vx[lo + k]; svy[wid][k] = p.vy[lo + k]; svz[wid][k] = p.vz[lo + k];
+        sx[wid][k] = p.pos[3 * (lo + k)]; sy[wid][k] = p.pos[3 * (lo + k) + 1]; sz[wid][k] = p.pos[3 * (lo + k) + 2];
+        svx[wid][k] = p.vel[3 * (lo + k)]; svy[wid][k] = p.vel[3 * (lo + k) + 1]; svz[wid][k] = p.vel[3 * (lo + k) + 2];
         scell[wid][k] = p.cell[lo + k]; spid[wid][k] = p.pid[lo + k];
     }
     __syncthreads();
@@ -419,20 +425,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             scell[wid][j] = (st == 0 || park) ? w.c : -1;
             sstate[wid][j] = flags;
         }
-        const uint64_t pm = __ballot(park);
-        if (pm) {
-            const int leader = __ffsll((unsigned long long)pm) - 1;
-            int64_t base = 0;
-            if (lane == leader)
-                base = (int64_t)atomicAdd((unsigned long long*)&sc->n_wall, (unsigned long long)__popcll(pm));
-            base = __shfl(base, leader, 64);
-            if (park) {
-                const int64_t slot = base + __popcll(pm & below);
-                q.idx[slot] = (int32_t)(lo + j);
-                q.t[slot] = w.t;
-                q.meta[slot] = (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22);
-            }
-        }
+        queue_push(q, park, lo + j, w.t, (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22));
         const uint64_t dm = __ballot(done);
         if (done) {
             const int nj = next + __popcll(dm & below);
@@ -452,9 +445,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         const int64_t i = lo + k;
         const uint8_t f = sstate[wid][k];
         const int cc = scell[wid][k];
-        p.x[i] = sx[wid][k]; p.y[i] = sy[wid][k]; p.z[i] = sz[wid][k];
+        p.pos[3 * i] = sx[wid][k]; p.pos[3 * i + 1] = sy[wid][k]; p.pos[3 * i + 2] = sz[wid][k];
         if (f & 1) {
-            p.vx[i] = svx[wid][k]; p.vy[i] = svy[wid][k]; p.vz[i] = svz[wid][k];
+            p.vel[3 * i] = svx[wid][k]; p.vel[3 * i + 1] = svy[wid][k]; p.vel[3 * i + 2] = svz[wid][k];
         }
         p.cell[i] = cc;
         if (!(f & 2) && cc >= 0) rank[i] = (uint32_t)atomicAdd(&counts[cc], 1);
@@ -462,32 +455,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
 }
 
+// Takes queue entry e into the lane's walker: a particle parked at a diffuse
+// wall is re-emitted there, one parked in flight resumes with its velocity.
+template <class VT>
+__device__ __forceinline__ int64_t queue_take(const MeshDev& m, const PartDev<VT>& p, const WallQueue& q, int64_t e,
+                                              uint32_t step, RngKey key, Walker& w, RngKey& kp) {
+    const int64_t i = q.idx[e];
+    const int meta = q.meta[e];
+    const double tq = q.t[e];
+    w.x0 = p.pos[3 * i]; w.x1 = p.pos[3 * i + 1]; w.x2 = p.pos[3 * i + 2];
+    w.c = p.cell[i]; w.pid = p.pid[i]; w.t = tq < 0 ? -tq : tq;
+    w.entry = meta & 3; w.hits = (meta >> 2) & 1023; w.nhop = (meta >> 12) & 1023; w.walls = (meta >> 22) & 1023;
+    kp = key;
+    double dtp = 0.0;
+    case_params(m.cell_case, m.cases, w.c, kp, dtp);
+    if (tq < 0) {
+        w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
+    } else {
+        const int bf = -1 - m.nbr[4 * w.c + w.entry];
+        diffuse_reemit<VT>(m, w, bf, w.entry, step, kp);
+    }
+    return i;
+}
+
+// Finishes the step of the parked particles, one queue entry per lane at a
+// time.  Workgroups take the queue parts round-robin (gridDim.x is a
+// multiple of kQueueParts) and stride through their part.  (Refilling lanes
+// from the queue as their particles finish was measured slower: the refill
+// brings the scattered loads and the wall re-emission into every pass of
+// the hop loop.)
 template <class VT>
 __global__ __launch_bounds__(256) void k_move_walls(MeshDev m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
                                                    uint32_t* rank, Counters* ctr, RngKey key, WallQueue q) {
-    const int64_t nq = sc->n_wall;
+    const int part = (int)(blockIdx.x % kQueueParts);
+    const int64_t nq = (int64_t)q.n[(size_t)part * kQueueStride];
+    const int64_t stride = (int64_t)(gridDim.x / kQueueParts) * blockDim.x;
     const uint32_t step = sc->step;
     int hops = 0, walls = 0, rem = 0, lost = 0;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nq; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = q.idx[e];
-        const int meta = q.meta[e];
+    for (int64_t k = (int64_t)(blockIdx.x / kQueueParts) * blockDim.x + threadIdx.x; k < nq; k += stride) {
         Walker w;
-        w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
-        w.c = p.cell[i]; w.pid = p.pid[i]; w.t = q.t[e];
-        w.entry = meta & 3; w.hits = (meta >> 2) & 1023; w.nhop = (meta >> 12) & 1023; w.walls = (meta >> 22) & 1023;
-        RngKey kp = key;
-        double dtp = 0.0;
-        case_params(m.cell_case, m.cases, w.c, kp, dtp);
-        const int bf = -1 - m.nbr[4 * w.c + w.entry];
-        diffuse_reemit<VT>(m, w, bf, w.entry, step, kp);
+        RngKey kp;
+        const int64_t i = queue_take<VT>(m, p, q, part * q.part + k, step, key, w, kp);
         int st;
         do {
             st = hop_once<VT, false>(m, w, step, kp);
         } while (st < 0);
         hops += w.nhop;
         walls += w.walls;
-        p.x[i] = w.x0; p.y[i] = w.x1; p.z[i] = w.x2;
-        p.vx[i] = (VT)w.v0; p.vy[i] = (VT)w.v1; p.vz[i] = (VT)w.v2;
+        p.pos[3 * i] = w.x0; p.pos[3 * i + 1] = w.x1; p.pos[3 * i + 2] = w.x2;
+        p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
         if (st == 0) {
             p.cell[i] = w.c;
             rank[i] = (uint32_t)atomicAdd(&counts[w.c], 1);
@@ -523,8 +539,8 @@ __global__ __launch_bounds__(256) void k_move(MeshDev m, PartDev<VT> p, const Sc
     w.x0 = w.x1 = w.x2 = w.v0 = w.v1 = w.v2 = w.t = 0.0;
     w.c = 0; w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0; w.pid = 0;
     if (active) {
-        w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
-        w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
+        w.x0 = p.pos[3 * i]; w.x1 = p.pos[3 * i + 1]; w.x2 = p.pos[3 * i + 2];
+        w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
         w.c = p.cell[i]; w.pid = p.pid[i]; w.t = dt;
     }
     while (__ballot(active) != 0ull) {
@@ -532,9 +548,9 @@ __global__ __launch_bounds__(256) void k_move(MeshDev m, PartDev<VT> p, const Sc
         if (active) st = hop_once<VT>(m, w, step, key);
         const bool done = active && st >= 0;
         if (done) {
-            p.x[i] = w.x0; p.y[i] = w.x1; p.z[i] = w.x2;
+            p.pos[3 * i] = w.x0; p.pos[3 * i + 1] = w.x1; p.pos[3 * i + 2] = w.x2;
             if (w.walls) {
-                p.vx[i] = (VT)w.v0; p.vy[i] = (VT)w.v1; p.vz[i] = (VT)w.v2;
+                p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
             }
             if (st == 0) {
                 p.cell[i] = w.c;
@@ -553,8 +569,8 @@ __global__ __launch_bounds__(256) void k_move(MeshDev m, PartDev<VT> p, const Sc
             active = ni < hi;
             if (active) {
                 i = ni;
-                w.x0 = p.x[i]; w.x1 = p.y[i]; w.x2 = p.z[i];
-                w.v0 = (double)p.vx[i]; w.v1 = (double)p.vy[i]; w.v2 = (double)p.vz[i];
+                w.x0 = p.pos[3 * i]; w.x1 = p.pos[3 * i + 1]; w.x2 = p.pos[3 * i + 2];
+                w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
                 w.c = p.cell[i]; w.pid = p.pid[i]; w.t = dt;
                 w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0;
             }
@@ -672,8 +688,8 @@ __global__ __launch_bounds__(256) void k_inject_emit(MeshDev m, const InflowDev 
         if (slot >= cap) {
             atomicOr(&sc->flags, kFlagCapacity);
         } else {
-            p.x[slot] = x0; p.y[slot] = x1; p.z[slot] = x2;
-            p.vx[slot] = (VT)v0; p.vy[slot] = (VT)v1; p.vz[slot] = (VT)v2;
+            p.pos[3 * slot] = x0; p.pos[3 * slot + 1] = x1; p.pos[3 * slot + 2] = x2;
+            p.vel[3 * slot] = (VT)v0; p.vel[3 * slot + 1] = (VT)v1; p.vel[3 * slot + 2] = (VT)v2;
             p.pid[slot] = pid;
             if (o.status == 0) {
                 p.cell[slot] = c;
@@ -803,6 +819,26 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const int32_t* in, i
 // ---------------------------------------------------------------------------
 // counting-sort scatter
 // ---------------------------------------------------------------------------
+// Copies particle i of src to slot d of dst (cell given).  Every load is
+// issued before the first store: the two buffers never alias, but the
+// compiler cannot know it and would otherwise order each load after the
+// previous store.
+template <class VT>
+__device__ __forceinline__ void copy_particle(const PartDev<VT>& src, int64_t i, const PartDev<VT>& dst, int64_t d,
+                                              int32_t cell) {
+    const double x0 = src.pos[3 * i], x1 = src.pos[3 * i + 1], x2 = src.pos[3 * i + 2];
+    const VT v0 = src.vel[3 * i], v1 = src.vel[3 * i + 1], v2 = src.vel[3 * i + 2];
+    const uint32_t id = src.pid[i];
+    dst.pos[3 * d] = x0;
+    dst.pos[3 * d + 1] = x1;
+    dst.pos[3 * d + 2] = x2;
+    dst.vel[3 * d] = v0;
+    dst.vel[3 * d + 1] = v1;
+    dst.vel[3 * d + 2] = v2;
+    dst.cell[d] = cell;
+    dst.pid[d] = id;
+}
+
 template <class VT>
 __global__ __launch_bounds__(256) void k_scatter(PartDev<VT> src, PartDev<VT> dst, const Scalars* sc,
                                                 const int32_t* offsets, const uint32_t* rank, int64_t cap) {
@@ -811,14 +847,7 @@ __global__ __launch_bounds__(256) void k_scatter(PartDev<VT> src, PartDev<VT> ds
     const int c = src.cell[i];
     if (c < 0) return;
     const int64_t d = (int64_t)offsets[c] + rank[i];
-    dst.x[d] = src.x[i];
-    dst.y[d] = src.y[i];
-    dst.z[d] = src.z[i];
-    dst.vx[d] = src.vx[i];
-    dst.vy[d] = src.vy[i];
-    dst.vz[d] = src.vz[i];
-    dst.cell[d] = c;
-    dst.pid[d] = src.pid[i];
+    copy_particle(src, i, dst, d, c);
 }
 
 // Gather form of the counting sort: k_perm writes, for every destination
@@ -840,14 +869,7 @@ __global__ __launch_bounds__(256) void k_gather(PartDev<VT> src, PartDev<VT> dst
     const int64_t k = xcd_block() * 256 + threadIdx.x;
     if (k >= sc->np) return;
     const int64_t i = perm[k];
-    dst.x[k] = src.x[i];
-    dst.y[k] = src.y[i];
-    dst.z[k] = src.z[i];
-    dst.vx[k] = src.vx[i];
-    dst.vy[k] = src.vy[i];
-    dst.vz[k] = src.vz[i];
-    dst.cell[k] = src.cell[i];
-    dst.pid[k] = src.pid[i];
+    copy_particle(src, i, dst, k, src.cell[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -873,32 +895,32 @@ struct LdsCell {
 
 template <class VT>
 struct GlobalCell {
-    VT* v0; VT* v1; VT* v2;
+    VT* v;                 // interleaved velocities of the particle store
     const int32_t* perm;   // logical -> physical
     int64_t s0;
     __device__ __forceinline__ void get(int k, double& a, double& b, double& c) const {
         const int64_t l = perm[s0 + k];
-        a = (double)v0[l]; b = (double)v1[l]; c = (double)v2[l];
+        a = (double)v[3 * l]; b = (double)v[3 * l + 1]; c = (double)v[3 * l + 2];
     }
     __device__ __forceinline__ void put(int k, double a, double b, double c) const {
         const int64_t l = perm[s0 + k];
-        v0[l] = (VT)a; v1[l] = (VT)b; v2[l] = (VT)c;
+        v[3 * l] = (VT)a; v[3 * l + 1] = (VT)b; v[3 * l + 2] = (VT)c;
     }
 };
 
 template <class VT>
 struct LdsOrderCell {
-    VT* v0; VT* v1; VT* v2;
+    VT* v;                 // interleaved velocities of the particle store
     const uint16_t* ord;   // sorted position -> slot relative to the chunk start
     int s0;
     int64_t a;             // chunk start in the particle arrays
     __device__ __forceinline__ void get(int k, double& x, double& y, double& z) const {
         const int64_t l = a + ord[s0 + k];
-        x = (double)v0[l]; y = (double)v1[l]; z = (double)v2[l];
+        x = (double)v[3 * l]; y = (double)v[3 * l + 1]; z = (double)v[3 * l + 2];
     }
     __device__ __forceinline__ void put(int k, double x, double y, double z) const {
         const int64_t l = a + ord[s0 + k];
-        v0[l] = (VT)x; v1[l] = (VT)y; v2[l] = (VT)z;
+        v[3 * l] = (VT)x; v[3 * l + 1] = (VT)y; v[3 * l + 2] = (VT)z;
     }
 };
 
@@ -1015,9 +1037,9 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
     if (n <= kCollideCap) {
 #pragma unroll 4
         for (int64_t i = lane; i < n; i += kCollideLanes) {
-            sv0[i] = p.vx[a + i];
-            sv1[i] = p.vy[a + i];
-            sv2[i] = p.vz[a + i];
+            sv0[i] = p.vel[3 * (a + i)];
+            sv1[i] = p.vel[3 * (a + i) + 1];
+            sv2[i] = p.vel[3 * (a + i) + 2];
             spid[i] = p.pid[a + i];
             stouch[i] = 0;
         }
@@ -1045,9 +1067,9 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
         __syncthreads();
         for (int64_t i = lane; i < n; i += kCollideLanes) {
             if (stouch[i]) {
-                p.vx[a + i] = sv0[i];
-                p.vy[a + i] = sv1[i];
-                p.vz[a + i] = sv2[i];
+                p.vel[3 * (a + i)] = sv0[i];
+                p.vel[3 * (a + i) + 1] = sv1[i];
+                p.vel[3 * (a + i) + 2] = sv2[i];
             }
         }
     } else if (c < nt) {
@@ -1060,7 +1082,7 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
             for (int q = 0; q < N; ++q) r += p.pid[s0 + q] < pk;
             perm[s0 + r] = (int32_t)(s0 + k);
         }
-        GlobalCell<VT> cv{p.vx, p.vy, p.vz, perm, s0};
+        GlobalCell<VT> cv{p.vel, perm, s0};
         if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
         if (do_sample) sample_cell(cv, N, c, cp, step);
     }
@@ -1071,12 +1093,15 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
 // memory and are reached through the logical order, so several waves fit on
 // a CU.  Ranks are computed one particle per lane (independent LDS reads
 // that pipeline), the collisions and sums one cell per lane.
-template <class VT, int WPE>
+// CAP bounds the LDS of a workgroup (6 bytes per particle), hence how many
+// workgroups share a CU; a chunk of more than CAP particles takes the
+// global-memory path.
+template <class VT, int WPE, int CAP>
 __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(WPE))) void k_collide_sample_g(
     PartDev<VT> p, const int32_t* offsets, CollideParams cp, const Scalars* sc, int32_t* perm, int do_collide,
     int do_sample) {
-    __shared__ uint32_t spid[kCollideCapG];
-    __shared__ uint16_t sord[kCollideCapG];
+    __shared__ uint32_t spid[CAP];
+    __shared__ uint16_t sord[CAP];
     __shared__ int32_t soff[kCollideLanes + 1];
     const int nt = cp.nt;
     const int lane = threadIdx.x;
@@ -1087,7 +1112,7 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
     if (lane == 0) soff[kCollideLanes] = offsets[min(c0 + kCollideLanes, nt)] - (int32_t)a;
     const int64_t n = (int64_t)offsets[min(c0 + kCollideLanes, nt)] - a;
     const uint32_t step = sc->step;
-    if (n <= kCollideCapG) {
+    if (n <= CAP) {
 #pragma unroll 4
         for (int64_t i = lane; i < n; i += kCollideLanes) spid[i] = p.pid[a + i];
         __syncthreads();
@@ -1105,7 +1130,7 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
         if (c < nt) {
             const int s0 = soff[lane];
             const int N = soff[lane + 1] - s0;
-            LdsOrderCell<VT> cv{p.vx, p.vy, p.vz, sord, s0, a};
+            LdsOrderCell<VT> cv{p.vel, sord, s0, a};
             if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
             if (do_sample) sample_cell(cv, N, c, cp, step);
         }
@@ -1118,7 +1143,7 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
             for (int q = 0; q < N; ++q) r += p.pid[s0 + q] < pk;
             perm[s0 + r] = (int32_t)(s0 + k);
         }
-        GlobalCell<VT> cv{p.vx, p.vy, p.vz, perm, s0};
+        GlobalCell<VT> cv{p.vel, perm, s0};
         if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
         if (do_sample) sample_cell(cv, N, c, cp, step);
     }
@@ -1199,8 +1224,10 @@ static inline unsigned grid8(int64_t n, int b) {
     return (unsigned)(g > 0 ? g : 8);
 }
 
-void launch_begin(hipStream_t s, int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss) {
-    hipLaunchKernelGGL(k_begin, GRID(nt + 1, 256), dim3(256), 0, s, counts, nt, sc, do_sample, n_ss);
+void launch_begin(hipStream_t s, int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss,
+                  unsigned long long* queue_n) {
+    hipLaunchKernelGGL(k_begin, GRID(std::max(nt + 1, kQueueParts), 256), dim3(256), 0, s, counts, nt, sc,
+                       do_sample, n_ss, queue_n);
 }
 
 void launch_init_count(hipStream_t s, const double* vol, const int32_t* orig, int nt, double n0, double FN,
@@ -1252,17 +1279,32 @@ void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* 
     case kMoveDefer8: {
         const dim3 g(grid8(np_bound, 256));
         if (variant == kMoveDefer4)
-            hipLaunchKernelGGL((k_move_defer<VT, 4>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr, key,
-                               dt, wq);
+            hipLaunchKernelGGL((k_move_defer<VT, 4, 0>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
+                               key, dt, wq);
         else if (variant == kMoveDefer5)
-            hipLaunchKernelGGL((k_move_defer<VT, 5>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr, key,
-                               dt, wq);
+            hipLaunchKernelGGL((k_move_defer<VT, 5, 0>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
+                               key, dt, wq);
         else if (variant == kMoveDefer6)
-            hipLaunchKernelGGL((k_move_defer<VT, 6>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr, key,
-                               dt, wq);
+            hipLaunchKernelGGL((k_move_defer<VT, 6, 0>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
+                               key, dt, wq);
         else
-            hipLaunchKernelGGL((k_move_defer<VT, 8>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr, key,
-                               dt, wq);
+            hipLaunchKernelGGL((k_move_defer<VT, 8, 0>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
+                               key, dt, wq);
+        break;
+    }
+    case kMoveCap4:
+    case kMoveCap5:
+    case kMoveCap6: {
+        const dim3 g(grid8(np_bound, 256));
+        if (variant == kMoveCap4)
+            hipLaunchKernelGGL((k_move_defer<VT, 6, 4>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
+                               key, dt, wq);
+        else if (variant == kMoveCap5)
+            hipLaunchKernelGGL((k_move_defer<VT, 6, 5>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
+                               key, dt, wq);
+        else
+            hipLaunchKernelGGL((k_move_defer<VT, 6, 6>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
+                               key, dt, wq);
         break;
     }
     case kMovePool128:
@@ -1302,7 +1344,7 @@ void launch_move_walls(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Sca
 
 bool move_parks_walls(int variant) {
     return variant == kMoveDefer4 || variant == kMoveDefer5 || variant == kMoveDefer6 || variant == kMoveDefer8 ||
-           variant == kMovePool128 || variant == kMovePool256 || variant == kMoveRefill5 || variant == kMoveRefill6;
+           variant == kMoveCap4 || variant == kMoveCap5 || variant == kMoveCap6 || variant == kMovePool128 || variant == kMovePool256 || variant == kMoveRefill5 || variant == kMoveRefill6;
 }
 
 void launch_count(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
@@ -1353,11 +1395,17 @@ void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets,
                            const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant) {
     const int nchunk = (cp.nt + kCollideLanes - 1) / kCollideLanes;
     if (variant == kCollideGlobal)
-        hipLaunchKernelGGL((k_collide_sample_g<VT, 4>), dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc,
-                           perm, do_collide, do_sample);
+        hipLaunchKernelGGL((k_collide_sample_g<VT, 4, kCollideCapG>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
+                           offsets, cp, sc, perm, do_collide, do_sample);
     else if (variant == kCollideGlobal8)
-        hipLaunchKernelGGL((k_collide_sample_g<VT, 8>), dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc,
-                           perm, do_collide, do_sample);
+        hipLaunchKernelGGL((k_collide_sample_g<VT, 8, kCollideCapG>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
+                           offsets, cp, sc, perm, do_collide, do_sample);
+    else if (variant == kCollideG3k)
+        hipLaunchKernelGGL((k_collide_sample_g<VT, 4, 3072>), dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets,
+                           cp, sc, perm, do_collide, do_sample);
+    else if (variant == kCollideG2k)
+        hipLaunchKernelGGL((k_collide_sample_g<VT, 4, 2048>), dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets,
+                           cp, sc, perm, do_collide, do_sample);
     else
         hipLaunchKernelGGL(k_collide_sample<VT>, dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc, perm,
                            do_collide, do_sample);

@@ -43,7 +43,7 @@ def _cases():
 CASES = _cases()
 
 
-def _one_step_parity(D, wl, presteps, steps=1):
+def _one_step_parity(D, wl, presteps, steps=1, move=None, collide=None):
     wl.run.n_ss = presteps
     o = Oracle(wl)
     o.step(presteps)
@@ -51,6 +51,9 @@ def _one_step_parity(D, wl, presteps, steps=1):
     c0 = o.counters()
     g = D.Simulation(wl, fill=False, capacity=max(4 * o.np, 100000))
     g.set_state(st["x"], st["v"], st["cell"], st["pid"], o.step_index, o.next_pid, o.smax())
+    if move is not None or collide is not None:
+        t = g.tuning()
+        g.set_tuning(t["move"] if move is None else move, t["collide"] if collide is None else collide, t["sort"])
     for _ in range(steps):
         o.step(1)
         g.step(1)
@@ -80,6 +83,30 @@ def test_single_step_parity(dsmc, name):
     wl = make()
     info = _one_step_parity(dsmc, wl, pre)
     print(name, info)
+
+
+# every move schedule; the capped ones (12-14) park particles in flight
+# after 4-6 exit tests, which these cases (several hops per step, diffuse,
+# specular, periodic and open faces) exercise
+MOVES = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14]
+MOVE_CASES = ["cavity_6_fp64_kn1", "specular_box", "plates_periodic_couette", "open_box_inflow"]
+
+
+@pytest.mark.parametrize("case", MOVE_CASES)
+@pytest.mark.parametrize("move", MOVES)
+def test_move_schedules_parity(dsmc, move, case):
+    make, pre = CASES[case]
+    wl = make()
+    _one_step_parity(dsmc, wl, pre, steps=2, move=move)
+
+
+# every collide schedule; the dense case puts more particles in a 64-cell
+# chunk than the LDS of the smaller-chunk schedules holds (global fallback)
+@pytest.mark.parametrize("case", ["cavity_8_fp32_jitter_kn0.1", "dense_ppc45", "sparse_ppc1"])
+@pytest.mark.parametrize("collide", [0, 1, 2, 3, 4])
+def test_collide_schedules_parity(dsmc, collide, case):
+    make, pre = CASES[case]
+    _one_step_parity(dsmc, make(), pre, steps=2, collide=collide)
 
 
 def test_three_steps_parity_fp64(dsmc):
