@@ -238,13 +238,16 @@ dsmc_status dsmc_graph_step(dsmc_ctx ctx, int32_t n_steps);
 
 /* Kernel schedule: move 0 lane, 1 lane (6 waves/SIMD), 2 lane (8),
  * 3 batched, 4/5/6/7 parked-wall at 6/8/4/5 waves/SIMD, 8/9 refill,
- * 10/11 pooled, 12/13/14 parked-wall at 6 waves/SIMD that also parks
- * particles still in flight after 4/5/6 exit tests; collide 0 LDS-staged
+ * 10/11 pooled, 15 (default) / 16 parked-wall at 6 / 8 waves/SIMD testing
+ * only the three faces other than the entry face after the first test,
+ * 12/13/14 as 15 and also parking particles still in flight after 4/5/6
+ * exit tests;
+ * collide 0 LDS-staged
  * velocities, 1/2 LDS-ranked at 4/8 waves/SIMD (chunks up to 4096
  * particles in LDS), 3/4 LDS-ranked with chunks up to 3072/2048 particles
  * (more workgroups per CU); sort 0 scatter, 1 gather.
  * Every schedule gives the same results.  A batch accepts only move 0-2
- * and 4-7, 12-14. */
+ * and 4-7, 12-16. */
 typedef struct {
     int32_t move, collide, sort;
     double move_ms, collide_ms, sort_ms;  /* per step, filled by dsmc_autotune */

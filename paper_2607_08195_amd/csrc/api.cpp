@@ -191,11 +191,12 @@ dsmc_status step_any(dsmc_ctx c, int mask) {
 // and capped parked-wall kernels).
 bool move_reads_cases(int v) {
     return v == kMoveLane || v == kMoveLaneW6 || v == kMoveLaneW8 || v == kMoveDefer4 || v == kMoveDefer5 ||
-           v == kMoveDefer6 || v == kMoveDefer8 || v == kMoveCap4 || v == kMoveCap5 || v == kMoveCap6;
+           v == kMoveDefer6 || v == kMoveDefer8 || v == kMoveCap4 || v == kMoveCap5 || v == kMoveCap6 ||
+           v == kMoveFace3 || v == kMoveFace3W8;
 }
 
 // Tuning overrides from the environment: DSMC_MOVE (lane, lane6, lane8,
-// batched, defer4/5/6/8, cap4/5/6, refill5/6, pool128/256), DSMC_MOVE_BATCH,
+// batched, defer4/5/6/8, face3, face3w8, cap4/5/6, refill5/6, pool128/256), DSMC_MOVE_BATCH,
 // DSMC_REORDER (0/1), DSMC_SORT, DSMC_COLLIDE.
 void read_tuning(dsmc_ctx c) {
     if (const char* v = std::getenv("DSMC_MOVE")) {
@@ -215,6 +216,8 @@ void read_tuning(dsmc_ctx c) {
         else if (s == "cap4") c->move_variant = kMoveCap4;
         else if (s == "cap5") c->move_variant = kMoveCap5;
         else if (s == "cap6") c->move_variant = kMoveCap6;
+        else if (s == "face3") c->move_variant = kMoveFace3;
+        else if (s == "face3w8") c->move_variant = kMoveFace3W8;
     }
     if (const char* v = std::getenv("DSMC_MOVE_BATCH"))
         c->move_batch = std::min(kQueueMaxBatch, std::max(64, std::atoi(v) / 64 * 64));
@@ -368,7 +371,7 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     c->bcs.assign(bcs, bcs + n_bc);
     c->n_ss = run->n_ss; c->n_a = run->n_a; c->ewma_on = run->ewma_on ? 1 : 0;
     if (bs && !move_reads_cases(c->move_variant))
-        c->move_variant = kMoveDefer6;  // the batch tables are read by the lane and deferring kernels
+        c->move_variant = kMoveFace3;  // the batch tables are read by the lane and deferring kernels
 
     // expected particle count at n0 sizes the default capacity
     double fill_total = 0;
@@ -675,7 +678,7 @@ dsmc_status dsmc_get_tuning(dsmc_ctx c, dsmc_tuning* t) {
 dsmc_status dsmc_set_tuning(dsmc_ctx c, const dsmc_tuning* t) {
     if (!c || !t) return fail(c, DSMC_E_INVALID, "bad arguments");
     const bool batch_ok = move_reads_cases(t->move);
-    if (t->move < 0 || t->move > kMoveCap6 || t->collide < 0 || t->collide > kCollideG2k || t->sort < 0 ||
+    if (t->move < 0 || t->move > kMoveFace3W8 || t->collide < 0 || t->collide > kCollideG2k || t->sort < 0 ||
         t->sort > kSortGather || (c->n_cases && !batch_ok))
         return fail(c, DSMC_E_INVALID, "unknown or unsupported kernel variant");
     c->move_variant = t->move;
@@ -689,8 +692,8 @@ dsmc_status dsmc_autotune(dsmc_ctx c, int32_t trial_steps, dsmc_tuning* out) {
     if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
     const bool was_profiling = c->profiling;
     dsmc_tuning best{c->move_variant, c->collide_variant, c->sort_variant, 1e300, 1e300, 1e300};
-    const int moves[] = {kMoveDefer4, kMoveDefer5, kMoveDefer6, kMoveDefer8, kMoveCap4, kMoveCap5, kMoveCap6,
-                         kMoveLaneW6, kMoveLaneW8};
+    const int moves[] = {kMoveDefer4, kMoveDefer5, kMoveDefer6, kMoveDefer8, kMoveFace3, kMoveFace3W8, kMoveCap4,
+                         kMoveCap5, kMoveCap6, kMoveLaneW6, kMoveLaneW8};
     for (int v : moves) {
         c->move_variant = v;
         double ms = 0;

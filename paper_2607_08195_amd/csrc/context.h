@@ -84,7 +84,7 @@ struct dsmc_ctx_s {
     dsmcx::Counters* d_ctr = nullptr;
     int32_t* d_counts_orig = nullptr;  // [nt] scratch of the initial fill
     // tuning choices
-    int move_variant = dsmcx::kMoveDefer6;
+    int move_variant = dsmcx::kMoveFace3;
     int move_batch = 0;
     int collide_variant = dsmcx::kCollideG3k;
     int sort_variant = dsmcx::kSortGather;

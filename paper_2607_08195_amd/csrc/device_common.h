@@ -318,24 +318,52 @@ __device__ __forceinline__ void diffuse_reemit(const MeshDev& m, Walker& w, int 
 
 constexpr int kHopWallPending = 3;
 
+// Exit test over the three faces other than the entry face (entry >= 0),
+// visited from the entry face onwards; a tie keeps the lower face index, as
+// the ascending scan of exit_candidate does.
+__device__ __forceinline__ void exit_candidate3(const double4& pl, int f, const Walker& w, int& fb, double& lb) {
+    const double den = pl.x * w.v0 + pl.y * w.v1 + pl.z * w.v2;
+    double lam = (pl.w - (pl.x * w.x0 + pl.y * w.x1 + pl.z * w.x2)) / den;
+    lam = lam < 0 ? 0.0 : lam;
+    const bool take = (den > 0) && (fb < 0 || lam < lb || (lam == lb && f < fb));
+    fb = take ? f : fb;
+    lb = take ? lam : lb;
+}
+
 // With DEFER, reaching a diffuse wall stops the walker there and returns
 // kHopWallPending (the re-emission is left to a later pass); the walker's
-// entry holds the wall's local face.
-template <class VT, bool DEFER = false>
+// entry holds the wall's local face.  FACE3 is for a walker that has
+// entered its cell through a face (entry >= 0, as after any crossing or
+// boundary event): it tests (and loads the planes of) the other three faces
+// only, with the same result.
+template <class VT, bool DEFER = false, bool FACE3 = false>
 __device__ __forceinline__ int hop_once(const MeshDev& m, Walker& w, uint32_t step, RngKey key) {
     const int base = 4 * w.c;
-    // all four planes and neighbour codes of the cell in flight at once
-    const double4 p0 = m.plane[base + 0];
-    const double4 p1 = m.plane[base + 1];
-    const double4 p2 = m.plane[base + 2];
-    const double4 p3 = m.plane[base + 3];
     const int4 nb4 = *reinterpret_cast<const int4*>(m.nbr + base);
     int fb = -1;
     double lb = 0.0;
-    exit_candidate(p0, 0, w, fb, lb);
-    exit_candidate(p1, 1, w, fb, lb);
-    exit_candidate(p2, 2, w, fb, lb);
-    exit_candidate(p3, 3, w, fb, lb);
+    double4 p0, p1, p2, p3;
+    if (FACE3) {
+        const int f1 = (w.entry + 1) & 3, f2 = (w.entry + 2) & 3, f3 = (w.entry + 3) & 3;
+        p1 = m.plane[base + f1];
+        p2 = m.plane[base + f2];
+        p3 = m.plane[base + f3];
+        exit_candidate3(p1, f1, w, fb, lb);
+        exit_candidate3(p2, f2, w, fb, lb);
+        exit_candidate3(p3, f3, w, fb, lb);
+        // the exit face's plane in p0 (for a specular reflection)
+        p0 = fb == f1 ? p1 : fb == f2 ? p2 : p3;
+    } else {
+        // all four planes and neighbour codes of the cell in flight at once
+        p0 = m.plane[base + 0];
+        p1 = m.plane[base + 1];
+        p2 = m.plane[base + 2];
+        p3 = m.plane[base + 3];
+        exit_candidate(p0, 0, w, fb, lb);
+        exit_candidate(p1, 1, w, fb, lb);
+        exit_candidate(p2, 2, w, fb, lb);
+        exit_candidate(p3, 3, w, fb, lb);
+    }
     if (fb < 0 || lb >= w.t) {
         w.x0 = w.x0 + w.v0 * w.t;
         w.x1 = w.x1 + w.v1 * w.t;
@@ -363,7 +391,7 @@ __device__ __forceinline__ int hop_once(const MeshDev& m, Walker& w, uint32_t st
         }
         diffuse_reemit<VT>(m, w, bf, fb, step, key);
     } else if (g.kind == kBcSpecular) {
-        const double4 pl = fb == 0 ? p0 : fb == 1 ? p1 : fb == 2 ? p2 : p3;
+        const double4 pl = FACE3 ? p0 : fb == 0 ? p0 : fb == 1 ? p1 : fb == 2 ? p2 : p3;
         const double vn = pl.x * w.v0 + pl.y * w.v1 + pl.z * w.v2;
         const double nn = pl.x * pl.x + pl.y * pl.y + pl.z * pl.z;
         const double f2 = 2.0 * (vn / nn);

@@ -22,7 +22,8 @@ enum { kFlagCapacity = 1 };
 // move kernel variants (tuning choice)
 enum { kMoveLane = 0, kMoveLaneW6 = 1, kMoveLaneW8 = 2, kMoveBatched = 3, kMoveDefer6 = 4, kMoveDefer8 = 5, kMoveDefer4 = 6,
        kMoveDefer5 = 7, kMoveRefill5 = 8, kMoveRefill6 = 9,
-       kMovePool128 = 10, kMovePool256 = 11, kMoveCap4 = 12, kMoveCap5 = 13, kMoveCap6 = 14 };
+       kMovePool128 = 10, kMovePool256 = 11, kMoveCap4 = 12, kMoveCap5 = 13, kMoveCap6 = 14,
+       kMoveFace3 = 15, kMoveFace3W8 = 16 };
 enum { kCollideLds = 0, kCollideGlobal = 1, kCollideGlobal8 = 2, kCollideG3k = 3, kCollideG2k = 4 };
 enum { kSortScatter = 0, kSortGather = 1 };
 

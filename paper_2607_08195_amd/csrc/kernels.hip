@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 // wave then runs at most CAP iterations instead of the largest hop count of
 // its 64 particles, and the few long tracks finish in k_move_walls on
 // compacted waves.
-template <class VT, int WPE, int CAP>
+template <class VT, int WPE, int CAP, bool FACE3 = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_move_defer(
     MeshDev m, PartDev<VT> p, Scalars* sc, int32_t* counts, uint32_t* rank, Counters* ctr, RngKey key,
     double dt, WallQueue q) {
@@ -254,11 +254,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         w.t = dtp;
         w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0;
         const uint32_t step = sc->step;
-        int st;
-        int it = 0;
-        do {
-            st = hop_once<VT, true>(m, w, step, kp);
-        } while (st < 0 && (CAP == 0 || ++it < CAP));
+        // the first test (entry face unknown) over all four faces; with
+        // FACE3 the later ones over the three faces other than the entry
+        int st = hop_once<VT, true>(m, w, step, kp);
+        for (int it = 1; st < 0 && (CAP == 0 || it < CAP); ++it)
+            st = FACE3 ? hop_once<VT, true, true>(m, w, step, kp) : hop_once<VT, true>(m, w, step, kp);
         p.pos[3 * i] = w.x0; p.pos[3 * i + 1] = w.x1; p.pos[3 * i + 2] = w.x2;
         if (st == kHopWallPending) {
             park = true;
@@ -498,7 +498,7 @@ __global__ __launch_bounds__(256) void k_move_walls(MeshDev m, PartDev<VT> p, co
         const int64_t i = queue_take<VT>(m, p, q, part * q.part + k, step, key, w, kp);
         int st;
         do {
-            st = hop_once<VT, false>(m, w, step, kp);
+            st = hop_once<VT, false, true>(m, w, step, kp);  // parked walkers have an entry face
         } while (st < 0);
         hops += w.nhop;
         walls += w.walls;
@@ -1292,19 +1292,27 @@ void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* 
                                key, dt, wq);
         break;
     }
+    case kMoveFace3:
+        hipLaunchKernelGGL((k_move_defer<VT, 6, 0, true>), dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p,
+                           (Scalars*)sc, counts, rank, ctr, key, dt, wq);
+        break;
+    case kMoveFace3W8:
+        hipLaunchKernelGGL((k_move_defer<VT, 8, 0, true>), dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p,
+                           (Scalars*)sc, counts, rank, ctr, key, dt, wq);
+        break;
     case kMoveCap4:
     case kMoveCap5:
     case kMoveCap6: {
         const dim3 g(grid8(np_bound, 256));
         if (variant == kMoveCap4)
-            hipLaunchKernelGGL((k_move_defer<VT, 6, 4>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
-                               key, dt, wq);
+            hipLaunchKernelGGL((k_move_defer<VT, 6, 4, true>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank,
+                               ctr, key, dt, wq);
         else if (variant == kMoveCap5)
-            hipLaunchKernelGGL((k_move_defer<VT, 6, 5>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
-                               key, dt, wq);
+            hipLaunchKernelGGL((k_move_defer<VT, 6, 5, true>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank,
+                               ctr, key, dt, wq);
         else
-            hipLaunchKernelGGL((k_move_defer<VT, 6, 6>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
-                               key, dt, wq);
+            hipLaunchKernelGGL((k_move_defer<VT, 6, 6, true>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank,
+                               ctr, key, dt, wq);
         break;
     }
     case kMovePool128:
@@ -1344,7 +1352,8 @@ void launch_move_walls(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Sca
 
 bool move_parks_walls(int variant) {
     return variant == kMoveDefer4 || variant == kMoveDefer5 || variant == kMoveDefer6 || variant == kMoveDefer8 ||
-           variant == kMoveCap4 || variant == kMoveCap5 || variant == kMoveCap6 || variant == kMovePool128 || variant == kMovePool256 || variant == kMoveRefill5 || variant == kMoveRefill6;
+           variant == kMoveCap4 || variant == kMoveCap5 || variant == kMoveCap6 || variant == kMoveFace3 || variant == kMoveFace3W8 ||
+           variant == kMovePool128 || variant == kMovePool256 || variant == kMoveRefill5 || variant == kMoveRefill6;
 }
 
 void launch_count(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
