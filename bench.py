@@ -42,7 +42,7 @@ BYTES = {
 # rocprofv3 --pmc measurements of the move kernel (FETCH_SIZE + WRITE_SIZE per
 # dispatch, scaled by the copy-kernel calibration) and the source digest they
 # were taken on; the traffic figure is reported only while the digest matches.
-TRAFFIC = {"kernel": "move", "digest": "f3659b6935177c44", "bytes_per_launch": 579215407 + 684720066,
+TRAFFIC = {"kernel": "move", "digest": "d607e8a6d71a6f2f", "bytes_per_launch": 579781670 + 590511979,
            "source": "profiles/step_kernels_cavity40.md"}
 
 
