@@ -253,13 +253,27 @@ __global__ void k_dig_grad(DigGeom g, const double* prim, double* grad, const Di
     double b[kDigNV][3];
 #pragma unroll
     for (int v = 0; v < kDigNV; ++v) b[v][0] = b[v][1] = b[v][2] = 0.0;
+    // the four links at once, then the four neighbour states (a face without
+    // a neighbour cell loads the cell's own state, unused), so that the
+    // gathered loads are in flight together rather than one face at a time
+    const int4 lk = *reinterpret_cast<const int4*>(g.flink + 4 * (size_t)c);
+    const int links[4] = {lk.x, lk.y, lk.z, lk.w};
+    double nbv[4][kDigNV];
+#pragma unroll
     for (int f = 0; f < 4; ++f) {
-        const int link = g.flink[4 * c + f];
+        const int kind = links[f] & 7;
+        const int src = (kind == kLinkInterior || kind == kLinkPeriodic) ? (links[f] >> 3) : c;
+#pragma unroll
+        for (int v = 0; v < kDigNV; ++v) nbv[f][v] = prim[kDigNV * (size_t)src + v];
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const int link = links[f];
         const int kind = link & 7, idx = link >> 3;
         double far[kDigNV];
         if (kind == kLinkInterior || kind == kLinkPeriodic) {
 #pragma unroll
-            for (int v = 0; v < kDigNV; ++v) far[v] = prim[kDigNV * (size_t)idx + v];
+            for (int v = 0; v < kDigNV; ++v) far[v] = nbv[f][v];
         } else if (kind == kLinkWall) {
             const DigGroup& gr = g.groups[idx];
             far[0] = pc[0];
@@ -462,22 +476,27 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_residual(DigGeom g, const d
         const double xc[3] = {g.cen[3 * (size_t)c], g.cen[3 * (size_t)c + 1], g.cen[3 * (size_t)c + 2]};
         double Rc[kDigNV] = {0, 0, 0, 0, 0};
         double sp = 0.0;
+        const int4 lk = *reinterpret_cast<const int4*>(g.flink + 4 * (size_t)c);
         for (int f = 0; f < 4; ++f) {
-            const int link = g.flink[4 * c + f];
+            const int link = f == 0 ? lk.x : f == 1 ? lk.y : f == 2 ? lk.z : lk.w;
             const int kind = link & 7, idx = link >> 3;
+            const bool inner = kind == kLinkInterior || kind == kLinkPeriodic;
+            // the neighbour's state and gradients are requested with the
+            // face's geometry (a face without a neighbour cell reads its own
+            // cell's, unused)
+            const size_t nb = inner ? (size_t)idx : (size_t)c;
+            double Pn[kDigNV], gn[15];
+#pragma unroll
+            for (int v = 0; v < kDigNV; ++v) Pn[v] = prim[kDigNV * nb + v];
+#pragma unroll
+            for (int k = 0; k < 15; ++k) gn[k] = grad[15 * nb + k];
             const size_t fo = 12 * (size_t)c + 3 * f;
             const double n[3] = {g.fnu[fo], g.fnu[fo + 1], g.fnu[fo + 2]};
             const double dx[3] = {g.fdx[fo], g.fdx[fo + 1], g.fdx[fo + 2]};
             const double A = g.farea[4 * (size_t)c + f];
             double F[kDigNV] = {0, 0, 0, 0, 0};
             double lam = 0.0, lamv = 0.0;
-            if (kind == kLinkInterior || kind == kLinkPeriodic) {
-                const int nb = idx;
-                double Pn[kDigNV], gn[15];
-#pragma unroll
-                for (int v = 0; v < kDigNV; ++v) Pn[v] = prim[kDigNV * (size_t)nb + v];
-#pragma unroll
-                for (int k = 0; k < 15; ++k) gn[k] = grad[15 * (size_t)nb + k];
+            if (inner) {
                 const double xf[3] = {g.fcen[fo], g.fcen[fo + 1], g.fcen[fo + 2]};
                 double rc[3], rn[3];
 #pragma unroll
