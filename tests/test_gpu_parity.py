@@ -102,8 +102,9 @@ def test_move_schedules_parity(dsmc, move, case):
 
 
 # every collide schedule; the dense case puts more particles in a 64-cell
-# chunk than the LDS of the smaller-chunk schedules holds (global fallback)
-@pytest.mark.parametrize("case", ["cavity_8_fp32_jitter_kn0.1", "dense_ppc45", "sparse_ppc1"])
+# chunk than the LDS of the smaller-chunk schedules holds (global fallback);
+# the FP64 case stages double-precision velocities
+@pytest.mark.parametrize("case", ["cavity_8_fp32_jitter_kn0.1", "dense_ppc45", "sparse_ppc1", "cavity_6_fp64_kn1"])
 @pytest.mark.parametrize("collide", [0, 1, 2, 3, 4])
 def test_collide_schedules_parity(dsmc, collide, case):
     make, pre = CASES[case]
