@@ -113,9 +113,9 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
     const bool mv = mask & 1, inj = (mask & 2) && c->inflow.n > 0, srt = mask & 4, col = mask & 8,
                smp = mask & 16;
     if ((col || smp) && mv && !srt) return fail(c, DSMC_E_INVALID, "collide/sample after move needs sort");
-    // Under graph capture nothing may synchronise: grids cover the whole
-    // store and the kernels bound themselves by the device-side counts.
-    const int64_t need = c->capturing ? c->cap : c->np_bound + (inj ? c->max_inject : 0);
+    // Under graph capture nothing may synchronise: grids cover the capture
+    // bound and the kernels bound themselves by the device-side counts.
+    const int64_t need = c->capturing ? c->capture_bound : c->np_bound + (inj ? c->max_inject : 0);
     if (!c->capturing && need > c->cap) {
         dsmc_status st = sync_scalars(c, nullptr);
         if (st != DSMC_OK) return st;
@@ -131,7 +131,7 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
     if (mv) {
         Timed t(c, kSlotMove);
         launch_move<VT>(s, c->mesh, a, c->d_sc, c->d_counts, c->d_rank, c->d_ctr, c->key, c->dt,
-                        c->capturing ? c->cap : c->np_bound, c->move_variant, c->move_batch, c->wq);
+                        c->capturing ? c->capture_bound : c->np_bound, c->move_variant, c->move_batch, c->wq);
     }
     if (mv && move_parks_walls(c->move_variant)) {
         Timed t(c, kSlotWalls);
@@ -145,7 +145,8 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
                                c->key, c->dt, c->cap, c->max_inject);
     }
     if (srt) {
-        if (!mv && !inj) launch_count(s, a.cell, c->d_sc, c->d_counts, c->d_rank, c->capturing ? c->cap : c->np_bound);
+        if (!mv && !inj)
+            launch_count(s, a.cell, c->d_sc, c->d_counts, c->d_rank, c->capturing ? c->capture_bound : c->np_bound);
         {
             Timed t(c, kSlotScan);
             launch_scan(s, c->d_counts, c->nt, c->d_offsets, c->d_blocksums, c->d_sc, kScanCells);
@@ -243,9 +244,21 @@ void drop_graph(dsmc_ctx_s::Graph& g) {
 }
 
 // Record two full steps (the buffers swap twice, so a replay leaves them as
-// it found them) into a graph and instantiate it.
+// it found them) into a graph and instantiate it.  Without inflow the
+// particle count cannot grow inside a step, so the grids cover the exact
+// count at capture time (a replay with more particles captures again);
+// with inflow they cover the whole store.  (Grids over the whole store of
+// a closed cavity, twice its particles, cost about 1 ms per step of blocks
+// that exit at once.)
 dsmc_status capture_two_steps(dsmc_ctx c, dsmc_ctx_s::Graph& g) {
     drop_graph(g);
+    if (c->inflow.n > 0) {
+        c->capture_bound = c->cap;
+    } else {
+        dsmc_status st = sync_scalars(c, nullptr);
+        if (st != DSMC_OK) return st;
+        c->capture_bound = std::max<int64_t>(c->np_bound, 1);
+    }
     const void* a_x = c->A.pos;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     c->capturing = true;
@@ -266,6 +279,7 @@ dsmc_status capture_two_steps(dsmc_ctx c, dsmc_ctx_s::Graph& g) {
     HIP_TRY(c, hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
     g.a_x = a_x;
     g.sig = tuning_sig(c);
+    g.bound = c->capture_bound;
     return DSMC_OK;
 }
 
@@ -653,7 +667,7 @@ dsmc_status dsmc_graph_step(dsmc_ctx c, int32_t n) {
     while (done + 2 <= n) {
         dsmc_ctx_s::Graph* g = nullptr;
         for (auto& cand : c->graphs)
-            if (cand.exec && cand.a_x == c->A.pos && cand.sig == tuning_sig(c)) g = &cand;
+            if (cand.exec && cand.a_x == c->A.pos && cand.sig == tuning_sig(c) && c->np_bound <= cand.bound) g = &cand;
         if (!g) {
             g = (c->graphs[0].a_x == c->A.pos || !c->graphs[0].exec) ? &c->graphs[0] : &c->graphs[1];
             dsmc_status st = capture_two_steps(c, *g);
@@ -661,7 +675,9 @@ dsmc_status dsmc_graph_step(dsmc_ctx c, int32_t n) {
         }
         HIP_TRY(c, hipGraphLaunch(g->exec, c->stream));
         done += 2;
-        c->np_bound = c->cap;  // device-side count unknown until the next synchronising call
+        // without inflow the count cannot have grown; with it, unknown until
+        // the next synchronising call
+        if (c->inflow.n > 0) c->np_bound = c->cap;
     }
     if (done < n) return step_any(c, 31);
     return DSMC_OK;

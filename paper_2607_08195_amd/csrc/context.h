@@ -107,9 +107,12 @@ struct dsmc_ctx_s {
     int n_cases = 0;
     // captured two-step graphs, keyed by the particle buffer current at capture
     bool capturing = false;
+    // particle-grid bound of the steps being captured (see capture_two_steps)
+    int64_t capture_bound = 0;
     struct Graph {
         const void* a_x = nullptr;
         int sig = -1;
+        int64_t bound = 0;  // grids of the captured kernels cover this many particles
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
     } graphs[2];

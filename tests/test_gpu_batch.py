@@ -8,7 +8,9 @@
   counts bit-exactly with positions and velocities to the single-step
   criteria.
 * dsmc_graph_step gives the same particle state as dsmc_step, bit for bit,
-  for even and odd step counts, on a single case and on a batch.
+  for even and odd step counts, on a single case and on a batch, with
+  freestream inflow, and after the particle count has grown past the count
+  the graphs were captured with.
 * The autotuner's choice does not change results: a context stepped through
   the autotuner's trials matches one stepped the same number of steps with
   the default schedule, bit for bit.
@@ -107,6 +109,37 @@ def test_graph_step_equals_eager(D, batch, n):
     sa, sb = a.state(), b.state()
     assert np.array_equal(sa["x"], sb["x"]) and np.array_equal(sa["v"], sb["v"])
     assert np.array_equal(a.sums(D.SAMPLE_STEADY)[0], b.sums(D.SAMPLE_STEADY)[0])
+    a.close()
+    b.close()
+
+
+def test_graph_step_inflow_and_growth(D):
+    """Graph stepping with freestream inflow (grids over the whole store) and
+    after the particle count grows past the count the graphs were captured
+    with (they are captured again), bit-equal to ordinary stepping."""
+    wl = W.open_box(n=(6, 4, 4), ppc=8, vel_fp32=1)
+    a = D.Simulation(wl, stream=_stream(), capacity=60000)
+    b = D.Simulation(wl, stream=_stream(), capacity=60000)
+    a.step(4)
+    b.graph_step(4)
+    sa, sb = a.state(), b.state()
+    assert sa["n"] == sb["n"] and all(np.array_equal(sa[k], sb[k]) for k in ["cell", "pid", "x", "v"])
+    a.close()
+    b.close()
+    small = W.cavity(n_hex=5, Kn=0.1, ppc=10, vel_fp32=1, jitter=0.1)
+    big = D.Simulation(W.cavity(n_hex=5, Kn=0.1, ppc=30, vel_fp32=1, jitter=0.1)).state()
+    a = D.Simulation(small, stream=_stream(), capacity=100000)
+    b = D.Simulation(small, stream=_stream(), capacity=100000)
+    a.step(2)
+    b.graph_step(2)
+    for sim in (a, b):
+        sim.set_state(big["x"], big["v"], big["cell"], big["pid"], 2, int(big["pid"].max()) + 1)
+    a.step(4)
+    b.graph_step(4)
+    sa, sb = a.state(), b.state()
+    assert sa["n"] == sb["n"] == big["n"]
+    for k in ["cell", "pid", "x", "v"]:
+        assert np.array_equal(sa[k], sb[k]), k
     a.close()
     b.close()
 
