@@ -59,6 +59,10 @@ typedef struct {
     int32_t global_dt;  /* 1: one pseudo-time step for all cells */
     int32_t warm_start; /* 1: the solve starts from the previous macroscopic
                            solution M^k (same steady target), 0: from M^{k+1/2} */
+    int32_t accel;      /* 0: plain pseudo-time iterations; m > 0: Anderson
+                           mixing of the iterates over the last m (<= 64)
+                           differences (one host synchronisation per
+                           iteration; same steady solution) */
 } dig_params;
 
 typedef struct {

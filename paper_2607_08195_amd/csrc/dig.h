@@ -95,6 +95,35 @@ void launch_dig_iteration(hipStream_t s, const DigGeom& g, DigWork w, double cfl
 // Closed domain: scale the density of w.prim so that its total mass equals
 // the particles' (n_particles F_N m).
 void launch_dig_mass_rescale(hipStream_t s, const DigGeom& g, DigWork w, const Scalars* sc);
+// Anderson acceleration of the pseudo-time iteration (type II, Walker and
+// Ni): the iteration G is applied as a fixed-point map to the primitive
+// state x; with f = G(x) - x, the next state is G(x_k) - sum_i gamma_i dG_i,
+// gamma minimising |f_k - sum_i gamma_i dF_i| in the norm weighted by
+// 1/scale^2 per variable over the last m differences dF_i = f_{i+1} - f_i,
+// dG_i = G(x_{i+1}) - G(x_i).
+struct AaWork {
+    double* x;      // [nt][5] input of the current application of G
+    double* fprev;  // [nt][5] f of the previous application (then the current one)
+    double* gprev;  // [nt][5] G of the previous application (then the current one)
+    double* dF;     // [m][nt][5]
+    double* dG;     // [m][nt][5]
+    double* part;   // [blocks][2m + 1] block partials of the inner products
+    double* red;    // [2m + 2] reduced inner products, then two fallback counts
+                    // (used by alternate iterations)
+    double* gam;    // [m] coefficients
+    int m;
+};
+// f = gx - x into fprev (after dF_slot = f - fprev, dG_slot = gx - gprev
+// unless first), gx into gprev; clears the fallback count red[2m + parity].
+void launch_aa_diff(hipStream_t s, const DigGeom& g, const AaWork& a, const double* gx, int slot, int first,
+                    int parity);
+// red[i] = <dF_slot, dF_i> (i < cnt), red[m + i] = <f, dF_i>; weights w[5].
+void launch_aa_dots(hipStream_t s, const DigGeom& g, const AaWork& a, int slot, int cnt, const double* w5);
+// prim = gprev - sum_i gam_i dG_i cell by cell; a cell whose result is not
+// physical (density or temperature <= 0) keeps gprev; red[2m + parity]
+// counts them.
+void launch_aa_update(hipStream_t s, const DigGeom& g, const AaWork& a, int cnt, double* prim, int parity);
+
 void launch_dig_set_local(hipStream_t s, const int32_t* state, uint8_t* local, int nt);
 void launch_dig_fb_count(hipStream_t s, const DigGeom& g, DigWork w, const int32_t* offsets, const int32_t* orig,
                          const Scalars* sc, RngKey key);

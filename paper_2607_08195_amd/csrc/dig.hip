@@ -978,6 +978,114 @@ void launch_dig_iteration(hipStream_t s, const DigGeom& g, DigWork w, double cfl
     hipLaunchKernelGGL(k_dig_commit, gr, bl, 0, s, g, w);
 }
 
+// ---------------------------------------------------------------------------
+// Anderson acceleration of the pseudo-time iteration
+// ---------------------------------------------------------------------------
+__global__ void k_aa_diff(int n, const double* x, const double* gx, double* fprev, double* gprev, double* dF,
+                          double* dG, int first, double* flag_clear) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) *flag_clear = 0.0;
+    if (e >= n) return;
+    const double gv = gx[e];
+    const double f = gv - x[e];
+    if (!first) {
+        dF[e] = f - fprev[e];
+        dG[e] = gv - gprev[e];
+    }
+    fprev[e] = f;
+    gprev[e] = gv;
+}
+
+// Block (x, y): the weighted inner product of column y (y < cnt: the new
+// difference dF_slot with dF_y; otherwise f with dF_{y - cnt}) over the
+// block's cells; then a fixed-order reduction over the x blocks.
+constexpr int kAaMaxDepth = 64;
+__global__ __launch_bounds__(kDigThreads) void k_aa_dots(int nt, const double* f, const double* dF, int slot,
+                                                          int cnt, int m, double w0, double w1, double w2, double w3,
+                                                          double w4, double* part) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int col = y < cnt ? y : y - cnt;
+    const double wv[kDigNV] = {w0, w1, w2, w3, w4};
+    const size_t n = (size_t)nt * kDigNV;
+    const double* lhs = y < cnt ? dF + (size_t)slot * n : f;
+    double sum = 0.0;
+    if (c < nt) {
+        const double* d = dF + (size_t)col * n + kDigNV * (size_t)c;
+        const double* l = lhs + kDigNV * (size_t)c;
+#pragma unroll
+        for (int v = 0; v < kDigNV; ++v) sum += (l[v] * wv[v]) * d[v];
+    }
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    __shared__ double red[kDigThreads / 64];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kDigThreads / 64; ++k) t += red[k];
+        part[(size_t)blockIdx.x * (2 * m + 1) + (y < cnt ? y : m + col)] = t;
+    }
+}
+
+__global__ __launch_bounds__(kDigThreads) void k_aa_reduce(const double* part, int nblk, int m, int cnt,
+                                                            double* out) {
+    const int i = blockIdx.x;  // 0..2cnt-1
+    const int idx = i < cnt ? i : m + (i - cnt);
+    double sum = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kDigThreads) sum += part[(size_t)b * (2 * m + 1) + idx];
+    __shared__ double red[kDigThreads];
+    red[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = kDigThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[idx] = red[0];
+}
+
+__global__ void k_aa_update(int nt, const double* gprev, const double* dG, const double* gam, int cnt,
+                            double* prim, double* flag) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nt) return;
+    const size_t n = (size_t)nt * kDigNV;
+    double x[kDigNV];
+#pragma unroll
+    for (int v = 0; v < kDigNV; ++v) {
+        double t = gprev[kDigNV * (size_t)c + v];
+        for (int i = 0; i < cnt; ++i) t -= gam[i] * dG[(size_t)i * n + kDigNV * (size_t)c + v];
+        x[v] = t;
+    }
+    const bool ok = x[0] > 0 && x[4] > 0 && isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(x[3]) &&
+                    isfinite(x[4]);
+    if (!ok) {
+        atomicAdd(flag, 1.0);
+#pragma unroll
+        for (int v = 0; v < kDigNV; ++v) x[v] = gprev[kDigNV * (size_t)c + v];
+    }
+#pragma unroll
+    for (int v = 0; v < kDigNV; ++v) prim[kDigNV * (size_t)c + v] = x[v];
+}
+
+void launch_aa_diff(hipStream_t s, const DigGeom& g, const AaWork& a, const double* gx, int slot, int first,
+                    int parity) {
+    const int n = kDigNV * g.nt;
+    const size_t off = (size_t)slot * n;
+    hipLaunchKernelGGL(k_aa_diff, dim3((n + 255) / 256), dim3(256), 0, s, n, (const double*)a.x, gx, a.fprev,
+                       a.gprev, a.dF + off, a.dG + off, first, a.red + 2 * a.m + parity);
+}
+
+void launch_aa_dots(hipStream_t s, const DigGeom& g, const AaWork& a, int slot, int cnt, const double* w5) {
+    const dim3 gr = cells_grid(g.nt), bl(kDigThreads);
+    hipLaunchKernelGGL(k_aa_dots, dim3(gr.x, 2 * cnt), bl, 0, s, g.nt, (const double*)a.fprev, (const double*)a.dF,
+                       slot, cnt, a.m, w5[0], w5[1], w5[2], w5[3], w5[4], a.part);
+    hipLaunchKernelGGL(k_aa_reduce, dim3(2 * cnt), bl, 0, s, (const double*)a.part, (int)gr.x, a.m, cnt, a.red);
+}
+
+void launch_aa_update(hipStream_t s, const DigGeom& g, const AaWork& a, int cnt, double* prim, int parity) {
+    hipLaunchKernelGGL(k_aa_update, cells_grid(g.nt), dim3(kDigThreads), 0, s, g.nt, (const double*)a.gprev,
+                       (const double*)a.dG, (const double*)a.gam, cnt, prim, a.red + 2 * a.m + parity);
+}
+
 void launch_dig_mass_rescale(hipStream_t s, const DigGeom& g, DigWork w, const Scalars* sc) {
     const dim3 gr = cells_grid(g.nt), bl(kDigThreads);
     hipLaunchKernelGGL(k_dig_mass_partial, gr, bl, 0, s, g, w);

@@ -19,6 +19,7 @@ struct DigState {
     DigGeom g{};
     DigWork w{};
     int nblk = 0;
+    AaWork aa{};  // Anderson history, allocated at the first accelerated solve
 };
 
 void dig_release(dsmc_ctx c) {
@@ -232,14 +233,140 @@ DigCtl read_ctl(dsmc_ctx c, dsmc_status* st) {
 
 dsmc_status check_params(dsmc_ctx c, const dig_params* p) {
     if (!p) return fail(c, DSMC_E_INVALID, "params is NULL");
-    if (p->passes < 0 || p->n_m < 0 || !(p->cfl > 0) || !(p->L0 > 0) || !(p->eps_m >= 0))
+    if (p->passes < 0 || p->n_m < 0 || !(p->cfl > 0) || !(p->L0 > 0) || !(p->eps_m >= 0) || p->accel < 0)
         return fail(c, DSMC_E_INVALID, "bad coupling parameters");
     return DSMC_OK;
 }
 
 // Pseudo-time marching from w.prim with w.hot frozen; fills the solve part
 // of the report.
+constexpr int kAaDepthMax = 64;
+
+// History of depth m for the accelerated solve (kept for later solves).
+dsmc_status ensure_aa(dsmc_ctx c, int m) {
+    DigState* d = c->dig;
+    if (d->aa.m >= m) return DSMC_OK;
+    const size_t n = 5 * (size_t)c->nt;
+    AaWork& a = d->aa;
+    for (double* q : {a.x, a.fprev, a.gprev, a.dF, a.dG, a.part, a.red, a.gam}) dev_free(c, q);
+    a = AaWork{};
+    const bool ok = alloc_n(c, a.x, n) && alloc_n(c, a.fprev, n) && alloc_n(c, a.gprev, n) &&
+                    alloc_n(c, a.dF, n * m) && alloc_n(c, a.dG, n * m) &&
+                    alloc_n(c, a.part, (size_t)d->nblk * (2 * m + 1)) && alloc_n(c, a.red, 2 * (size_t)m + 2) &&
+                    alloc_n(c, a.gam, m);
+    if (!ok) return fail(c, DSMC_E_OOM, "device allocation of the acceleration history failed");
+    a.m = m;
+    return DSMC_OK;
+}
+
+// Solves the m x m system (H + lambda I) gam = b by Cholesky (lambda a
+// small multiple of the largest diagonal entry); false if H is not usable.
+bool solve_small(int n, int ld, const std::vector<double>& H, const std::vector<double>& b, std::vector<double>& x) {
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i) dmax = std::max(dmax, H[i * ld + i]);
+    if (!(dmax > 0) || !std::isfinite(dmax)) return false;
+    std::vector<double> L(n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double v = H[i * ld + j] + (i == j ? 1e-10 * dmax : 0.0);
+            for (int k = 0; k < j; ++k) v -= L[i * n + k] * L[j * n + k];
+            if (i == j) {
+                if (!(v > 0)) return false;
+                L[i * n + i] = std::sqrt(v);
+            } else {
+                L[i * n + j] = v / L[j * n + j];
+            }
+        }
+    std::vector<double> y(n);
+    for (int i = 0; i < n; ++i) {
+        double v = b[i];
+        for (int k = 0; k < i; ++k) v -= L[i * n + k] * y[k];
+        y[i] = v / L[i * n + i];
+    }
+    x.assign(n, 0.0);
+    for (int i = n - 1; i >= 0; --i) {
+        double v = y[i];
+        for (int k = i + 1; k < n; ++k) v -= L[k * n + i] * x[k];
+        x[i] = v / L[i * n + i];
+    }
+    for (double v : x)
+        if (!std::isfinite(v)) return false;
+    return true;
+}
+
+// Pseudo-time iteration accelerated by Anderson mixing of depth m: one
+// synchronisation per iteration, which brings back the inner products, the
+// control block and the fallback count of the previous mixing step.
+dsmc_status run_solve_aa(dsmc_ctx c, const dig_params* p, dig_report* r, int m) {
+    DigState* d = c->dig;
+    hipStream_t s = c->stream;
+    dsmc_status st = ensure_aa(c, m);
+    if (st != DSMC_OK) return st;
+    AaWork& a = d->aa;
+    const double R = kBoltzmann / c->mass;
+    const double rho = c->mass * c->n0, cs2 = R * c->T0, T2 = c->T0 * c->T0;
+    const double w5[5] = {1.0 / (rho * rho), 1.0 / cs2, 1.0 / cs2, 1.0 / cs2, 1.0 / T2};
+    const size_t n = 5 * (size_t)c->nt;
+    std::vector<double> H((size_t)m * m, 0.0), red(2 * (size_t)m + 2, 0.0), b(m), gam(m, 0.0), bs;
+    int cnt = 0, made = 0;  // stored differences, differences made since the last restart
+    bool fresh = true;      // the next application of G starts a new history
+    bool mixed = false;     // the previous iteration ended with a mixing step
+    DigCtl h{};
+    launch_dig_ctl_reset(s, d->w.ctl);
+    for (int it = 0; it < p->n_m; ++it) {
+        const int par = it & 1;
+        HIP_TRY(c, hipMemcpyAsync(a.x, d->w.prim, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        launch_dig_iteration(s, d->g, d->w, p->cfl, p->eps_m, p->global_dt ? 1 : 0, it);
+        const int slot = fresh ? 0 : made % m;
+        launch_aa_diff(s, d->g, a, d->w.prim, slot, fresh ? 1 : 0, par);
+        const int ncnt = fresh ? 0 : std::min(cnt + 1, m);
+        if (ncnt > 0) launch_aa_dots(s, d->g, a, slot, ncnt, w5);
+        HIP_TRY(c, hipMemcpyAsync(red.data(), a.red, sizeof(double) * (2 * m + 2), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipMemcpyAsync(&h, d->w.ctl, sizeof h, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        HIP_TRY(c, hipGetLastError());
+        if (h.conv || h.failed) break;
+        if (fresh) {
+            fresh = false;
+            cnt = made = 0;
+            mixed = false;
+            continue;  // G(x_0) is the next state
+        }
+        ++made;
+        cnt = ncnt;
+        if (mixed && red[2 * m + (par ^ 1)] > 0) {
+            // cells of the previous mixing step fell back to G(x): restart
+            fresh = true;
+            mixed = false;
+            continue;
+        }
+        for (int i = 0; i < cnt; ++i) {
+            H[(size_t)slot * m + i] = red[i];
+            H[(size_t)i * m + slot] = red[i];
+            b[i] = red[m + i];
+        }
+        bs.assign(b.begin(), b.begin() + cnt);
+        if (!solve_small(cnt, m, H, bs, gam)) {
+            fresh = true;  // the history is degenerate: plain step, new history
+            mixed = false;
+            continue;
+        }
+        HIP_TRY(c, hipMemcpyAsync(a.gam, gam.data(), sizeof(double) * cnt, hipMemcpyHostToDevice, s));
+        launch_aa_update(s, d->g, a, cnt, d->w.prim, par);
+        mixed = true;
+    }
+    HIP_TRY(c, hipGetLastError());
+    h = read_ctl(c, &st);
+    if (st != DSMC_OK) return st;
+    r->iters = h.iters;
+    r->residual = h.res0 > 0 ? h.res / h.res0 : 0.0;
+    r->converged = h.conv;
+    r->failed = h.failed;
+    return DSMC_OK;
+}
+
 dsmc_status run_solve(dsmc_ctx c, const dig_params* p, dig_report* r) {
+    if (p->accel > 0) return run_solve_aa(c, p, r, std::min(p->accel, kAaDepthMax));
     DigState* d = c->dig;
     launch_dig_ctl_reset(c->stream, d->w.ctl);
     dsmc_status st = DSMC_OK;

@@ -308,3 +308,37 @@ def test_cells_without_samples(dsmc):
     assert np.isinf(g.dig_get("kn")[::7]).all()
     _prim_close(g.dig_get("new"), o.mprev(), wl, 1e-10)
     g.close()
+
+
+def test_accelerated_solve_reaches_the_plain_steady_state(dsmc):
+    """Anderson mixing of the pseudo-time iterates (accel = 30) reaches the
+    steady state of the plain iterations from the same M^{k+1/2} and HoT
+    (dig_solve, both to a 1e-12 density residual ratio) in far fewer
+    iterations, and that state solves the oracle's discrete equations: the
+    oracle's residual there is at most 1e-9 of its value at M^{k+1/2} in
+    every equation.  The steady equations of a closed cavity leave the total
+    mass to the path (local pseudo-time steps do not conserve it while the
+    iteration has not converged; the coupling step rescales it to the
+    particles' mass afterwards): the two solutions are compared with their
+    densities normalised by their total mass, to 1e-4 of each column's
+    scale (observed: 2e-5)."""
+    wl = _cavity(Kn=0.1, n_hex=6, ppc=20, vel_fp32=0)
+    o, g = _pair(dsmc, wl, steps=40, n_a=50)
+    g.dig_couple(kn_max=1e9, passes=0, n_m=0, feedback=0)
+    prim, hot = g.dig_get("half"), g.dig_get("hot")
+    kw = dict(cfl=0.5, eps_m=1e-12, global_dt=0)
+    pp, rp = g.dig_solve(prim, hot, n_m=100000, accel=0, **kw)
+    pa, ra = g.dig_solve(prim, hot, n_m=20000, accel=30, **kw)
+    assert rp["converged"] and ra["converged"] and not ra["failed"], (rp, ra)
+    assert ra["iters"] < rp["iters"] / 5, (ra["iters"], rp["iters"])
+    R0 = np.abs(o.dig_residual(prim, hot)).max(axis=0)
+    for p in (pp, pa):
+        R = np.abs(o.dig_residual(p, hot)).max(axis=0)
+        assert np.all(R <= 1e-9 * R0), R / R0
+    vol = o.volumes()
+    a, b = pa.copy(), pp.copy()
+    a[:, 0] /= np.sum(a[:, 0] * vol)
+    b[:, 0] /= np.sum(b[:, 0] * vol)
+    d = np.abs(a - b).max(axis=0) / np.abs(b).max(axis=0)
+    assert np.all(d <= 1e-4), d
+    g.close()
