@@ -1,0 +1,96 @@
+"""Error behaviour of the C ABI as the headers state it: invalid meshes are
+DSMC_E_MESH at init (degenerate tet, a boundary triangle missing or matching
+no exterior face), invalid parameters DSMC_E_INVALID (non-positive time step,
+particle cells out of range in set_state, negative reconstruction passes or
+acceleration depth, unknown kernel schedule, empty or negative training
+sets), and a context stays usable after an argument error."""
+import numpy as np
+import pytest
+
+from paper_2607_08195_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+E_INVALID, E_MESH = -1, -2
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_08195_amd import dsmc
+    return dsmc
+
+
+def _wl():
+    return W.cavity(n_hex=2, Kn=1.0, ppc=4, vel_fp32=1)
+
+
+def _status(D, fn):
+    with pytest.raises(D.DsmcError) as e:
+        fn()
+    return e.value.status
+
+
+def test_degenerate_tet_is_a_mesh_error(D):
+    wl = _wl()
+    t = wl.mesh.tets.copy()
+    t[0, 1] = t[0, 0]
+    wl.mesh.tets = t
+    assert _status(D, lambda: D.Simulation(wl)) == E_MESH
+
+
+def test_boundary_faces_must_match_the_exterior(D):
+    wl = _wl()
+    m = wl.mesh
+    m.bfaces, m.bgroup = m.bfaces[1:].copy(), m.bgroup[1:].copy()
+    assert _status(D, lambda: D.Simulation(wl)) == E_MESH
+    wl = _wl()
+    m = wl.mesh
+    bf = m.bfaces.copy()
+    bf[0] = [bf[0][0], bf[0][1], int(np.max(m.tets))]  # a triangle no tet has
+    if len({tuple(sorted(r)) for r in bf.tolist()}) == len(bf):
+        m.bfaces = bf
+        assert _status(D, lambda: D.Simulation(wl)) == E_MESH
+
+
+def test_non_positive_time_step_is_invalid(D):
+    wl = _wl()
+    wl.run.dt = 0.0
+    assert _status(D, lambda: D.Simulation(wl)) == E_INVALID
+
+
+def test_argument_errors_leave_the_context_usable(D):
+    g = D.Simulation(_wl())
+    st = g.state()
+    bad = st["cell"].copy()
+    bad[0] = g.nt
+    assert _status(D, lambda: g.set_state(st["x"], st["v"], bad, st["pid"], 0, len(bad))) == E_INVALID
+    assert _status(D, lambda: g.set_tuning(99, 0, 0)) == E_INVALID
+    wl = _wl()
+    wl.run.ewma_on = 1
+    h = D.Simulation(wl)
+    h.step(3)
+    assert _status(D, lambda: h.dig_couple(passes=-1, n_m=0, feedback=0)) == E_INVALID
+    assert _status(D, lambda: h.dig_couple(n_m=0, feedback=0, accel=-1)) == E_INVALID
+    r = h.dig_couple(kn_max=1e9, passes=0, n_m=2, feedback=0)
+    assert r["iters"] == 2
+    h.close()
+    g.step(2)
+    assert g.state()["n"] == len(st["pid"])
+    g.close()
+
+
+def test_mlp_rejects_bad_training_sets(D):
+    net = D.Mlp()
+    net.init_weights(seed=1)
+    x = np.zeros((0, 13), np.float32)
+    t = np.zeros((0, 9), np.float32)
+    assert _status(D, lambda: net.train(x, t, steps=1)) == E_INVALID
+    x = np.random.default_rng(0).standard_normal((8, 13)).astype(np.float32)
+    t = np.zeros((8, 9), np.float32)
+    assert _status(D, lambda: net.train(x, t, steps=-1)) == E_INVALID
+    rep = net.train(x, t, steps=2, batch=0)
+    assert rep["steps"] == 2
+    net.close()
