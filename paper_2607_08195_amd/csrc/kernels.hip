@@ -851,16 +851,19 @@ __global__ __launch_bounds__(256) void k_scatter(PartDev<VT> src, PartDev<VT> ds
 }
 
 // Gather form of the counting sort: k_perm writes, for every destination
-// slot, the index of the particle that lands there (4-byte scattered
-// stores); k_gather then fills the sorted buffer slot by slot (coalesced
-// stores, gathered loads from the spatially local source buffer).
+// slot, the index of the particle that lands there and its cell (4-byte
+// scattered stores); k_gather then fills the rest of the sorted buffer slot
+// by slot (coalesced stores, gathered loads from the spatially local source
+// buffer).
 __global__ __launch_bounds__(256) void k_perm(const int32_t* cell, const Scalars* sc, const int32_t* offsets,
-                                             const uint32_t* rank, int32_t* perm, int64_t cap) {
+                                             const uint32_t* rank, int32_t* perm, int32_t* dst_cell, int64_t cap) {
     const int64_t i = xcd_block() * 256 + threadIdx.x;
     if (i >= sc->n_entries || i >= cap) return;
     const int c = cell[i];
     if (c < 0) return;
-    perm[(int64_t)offsets[c] + rank[i]] = (int32_t)i;
+    const int64_t d = (int64_t)offsets[c] + rank[i];
+    perm[d] = (int32_t)i;
+    dst_cell[d] = c;  // the slot's cell, so that the gather need not load it
 }
 
 template <class VT>
@@ -869,7 +872,16 @@ __global__ __launch_bounds__(256) void k_gather(PartDev<VT> src, PartDev<VT> dst
     const int64_t k = xcd_block() * 256 + threadIdx.x;
     if (k >= sc->np) return;
     const int64_t i = perm[k];
-    copy_particle(src, i, dst, k, src.cell[i]);
+    const double x0 = src.pos[3 * i], x1 = src.pos[3 * i + 1], x2 = src.pos[3 * i + 2];
+    const VT v0 = src.vel[3 * i], v1 = src.vel[3 * i + 1], v2 = src.vel[3 * i + 2];
+    const uint32_t id = src.pid[i];
+    dst.pos[3 * k] = x0;
+    dst.pos[3 * k + 1] = x1;
+    dst.pos[3 * k + 2] = x2;
+    dst.vel[3 * k] = v0;
+    dst.vel[3 * k + 1] = v1;
+    dst.vel[3 * k + 2] = v2;
+    dst.pid[k] = id;
 }
 
 // ---------------------------------------------------------------------------
@@ -946,6 +958,12 @@ __device__ __forceinline__ void ntc_cell(const Acc& cv, int N, int c, const Coll
         const double mean = ((((0.5 * Nd) * (Nd - 1.0)) * FN) * sm) * dt / cp.vol[c];
         M = (int)floor(mean + u01(r.w[0], r.w[1]));
         double seen = 0.0;
+        // (sigma c)/(sigma c)_max = K cr2^ex / sm is first estimated in FP32
+        // (hardware log2/exp2); when the estimate is below 1 and U lies
+        // outside a relative band of 1e-3 around it, both the acceptance and
+        // the (sigma c)_max update (only values above sm matter) are decided
+        // without the FP64 power, and decided as the FP64 expression would.
+        const float lk = log2f((float)cp.K) - log2f((float)sm), ex32 = (float)cp.ex;
         for (int k = 0; k < M; ++k) {
             const Rand4 w = draw(key, subj, step, kPurposePair, (uint64_t)k);
             const uint32_t i = pick(w.w[0], (uint32_t)N);
@@ -957,9 +975,17 @@ __device__ __forceinline__ void ntc_cell(const Acc& cv, int N, int c, const Coll
             cv.get((int)j, b0, b1, b2);
             const double gx = a0 - b0, gy = a1 - b1, gz = a2 - b2;
             const double cr2 = gx * gx + gy * gy + gz * gz;
-            const double sc = cp.K * pow(cr2, cp.ex);
-            if (sc > seen) seen = sc;
-            if (!(U < sc / sm)) continue;
+            const double est = (double)exp2f(fmaf(ex32, log2f((float)cr2), lk));
+            const double lo = est * (1.0 - 1e-3), hi = est * (1.0 + 1e-3);
+            bool take;
+            if (hi < 1.0 && (U < lo || U >= hi)) {
+                take = U < lo;
+            } else {
+                const double sc = cp.K * pow(cr2, cp.ex);
+                if (sc > seen) seen = sc;
+                take = U < sc / sm;
+            }
+            if (!take) continue;
             ++acc;
             const Rand4 q = draw(key, subj, step, kPurposeScatter, (uint64_t)k);
             const double cx = 2.0 * u01(q.w[0], q.w[1]) - 1.0;
@@ -1387,7 +1413,8 @@ template <class VT>
 void launch_scatter(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalars* sc, const int32_t* offsets,
                     const uint32_t* rank, int64_t bound, int64_t cap, int32_t* perm, int variant) {
     if (variant == kSortGather) {
-        hipLaunchKernelGGL(k_perm, dim3(grid8(bound, 256)), dim3(256), 0, s, src.cell, sc, offsets, rank, perm, cap);
+        hipLaunchKernelGGL(k_perm, dim3(grid8(bound, 256)), dim3(256), 0, s, src.cell, sc, offsets, rank, perm,
+                           dst.cell, cap);
     } else {
         hipLaunchKernelGGL(k_scatter<VT>, dim3(grid8(bound, 256)), dim3(256), 0, s, src, dst, sc, offsets, rank, cap);
     }
