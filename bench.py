@@ -24,8 +24,9 @@ sys.path.insert(0, ROOT)
 #                its rank
 #  move_walls:   per parked particle: queue (16) + x,cell,pid (32) read;
 #                x,v,cell,rank (44) written
-#  sort_perm:    read cell, rank (8) + the cell offset (4); write perm (4)
-#  sort_gather:  read perm (4) + a particle (44); write it (44)
+#  sort_perm:    read cell, rank (8) + the cell offset (4); write perm and the
+#                slot's cell (8)
+#  sort_gather:  read perm (4) + a particle but its cell (40); write them (40)
 #  collide:      read pid, cell, v (20); write v of collided particles (12 each);
 #                per cell: offset (4), smax r/w (16), pair counts (8), steady
 #                sums read+write (208)
@@ -33,8 +34,8 @@ sys.path.insert(0, ROOT)
 BYTES = {
     "move": lambda np_, nt, f: np_ * (76.0 + 12.0 * f["park"]),
     "move_walls": lambda np_, nt, f: np_ * f["park"] * 92.0,
-    "sort_perm": lambda np_, nt, f: np_ * 16.0,
-    "sort_gather": lambda np_, nt, f: np_ * 92.0,
+    "sort_perm": lambda np_, nt, f: np_ * 20.0,
+    "sort_gather": lambda np_, nt, f: np_ * 84.0,
     "collide_sample": lambda np_, nt, f: np_ * (20.0 + 12.0 * f["touched"]) + nt * 236.0,
     "scan": lambda np_, nt, f: nt * 12.0,
 }
@@ -42,7 +43,7 @@ BYTES = {
 # rocprofv3 --pmc measurements of the move kernel (FETCH_SIZE + WRITE_SIZE per
 # dispatch, scaled by the copy-kernel calibration) and the source digest they
 # were taken on; the traffic figure is reported only while the digest matches.
-TRAFFIC = {"kernel": "move", "digest": "d607e8a6d71a6f2f", "bytes_per_launch": 579781670 + 590511979,
+TRAFFIC = {"kernel": "move", "digest": "6fc719d32b049fe8", "bytes_per_launch": 579537860 + 590513087,
            "source": "profiles/step_kernels_cavity40.md"}
 
 
