@@ -85,6 +85,19 @@ typedef struct {
  * the feedback would overflow the particle store (state left unchanged). */
 dsmc_status dig_couple(dsmc_ctx ctx, const dig_params* params, dig_report* report);
 
+/* Batch contexts (dsmc_batch_init): one call couples every enabled case at
+ * once.  Each case uses its own reference state (n0, T0) for the Knudsen
+ * number, its own F_N, generator key and case-local cell subjects and
+ * particle ids (a case's next id starts at its largest id + 1 when the
+ * coupling state is first built), and its own closed-domain mass rescale,
+ * so an enabled case reproduces the single-case cycle of that case.  The
+ * pseudo-time solve runs over all cells together: its stopping test (eps_m)
+ * and, with global_dt or accel, its step and mixing coefficients are
+ * batch-wide, so only with eps_m = 0, local steps and accel = 0 is each
+ * case's solve the one its own context would make.  Report counts are
+ * batch totals.  All cases are enabled until dig_batch_enable says
+ * otherwise. */
+
 /* Per-cell arrays of the last dig_couple, in caller cell order:
  *  DIG_OUT_SAMPLED [n][14] rho, u(3), T, sigma(6), q(3) of the moving average (NaN: no samples)
  *  DIG_OUT_HALF    [n][5]  M^{k+1/2} after the gate and reconstruction
@@ -113,6 +126,12 @@ dsmc_status dig_solve(dsmc_ctx ctx, double* prim, const double* hot, const dig_p
  * with state[n] <= 1; re-sorts.  DSMC_E_CAPACITY as for dig_couple. */
 dsmc_status dig_feedback(dsmc_ctx ctx, const double* prim_old, const double* prim_new, const int32_t* state,
                          int64_t* np_after);
+
+/* Batch contexts: enabled[n_cases] (nonzero: coupled) selects the cases
+ * whose particles and local-accumulation flags dig_couple and dig_feedback
+ * change; the others keep stepping as plain DSMC.  DSMC_E_INVALID on a
+ * single-case context or a NULL array. */
+dsmc_status dig_batch_enable(dsmc_ctx ctx, const int32_t* enabled);
 
 /* Replace the sums of an accumulator (DSMC_SAMPLE_STEADY or
  * DSMC_SAMPLE_EWMA) by sums[n][13] (layout of dsmc_get_sums); restarts or

@@ -23,6 +23,20 @@ struct DigGroup {
     double rho;  // freestream mass density (inflow)
 };
 
+// Coupling parameters of one case of a batch (independent meshes joined in
+// one context): reference state, particle weight, generator key, cell
+// ranges (caller numbering and internal order) and the next particle id.
+struct DigCase {
+    double FN;
+    double mu0, p0, kfac;  // reference Knudsen number mu0 / (p0 L0) kfac, kfac = sqrt(pi R T0 / 2)
+    double T0, rho0, mass_scale;
+    uint32_t k0, k1;
+    int32_t cell0, cell_end;  // caller cells [cell0, cell_end)
+    int32_t first, end;       // internal cells [first, end)
+    int32_t enabled;          // 0: the case's particles are left as they are
+    uint32_t next_pid;
+};
+
 struct DigGeom {
     int nt;
     const double* cen;     // [nt][3] centroid
@@ -36,6 +50,9 @@ struct DigGeom {
     const DigGroup* groups;
     double mass, R, mu_ref, omega, T_ref;
     double FN;  // real molecules per particle
+    const int32_t* cell_case;  // batch: internal cell -> case (null for one case)
+    DigCase* cases;            // batch: per-case parameters
+    int n_cases;
 };
 
 struct DigCtl {
@@ -94,7 +111,13 @@ void launch_dig_iteration(hipStream_t s, const DigGeom& g, DigWork w, double cfl
                           int it);
 // Closed domain: scale the density of w.prim so that its total mass equals
 // the particles' (n_particles F_N m).
-void launch_dig_mass_rescale(hipStream_t s, const DigGeom& g, DigWork w, const Scalars* sc);
+void launch_dig_mass_rescale(hipStream_t s, const DigGeom& g, DigWork w, const Scalars* sc,
+                             const int32_t* offsets);
+// Batch: the next particle id of each case after its feedback clones.
+void launch_dig_case_pids(hipStream_t s, const DigGeom& g, const DigWork& w);
+// Batch: next particle id of each case = its largest id + 1.
+void launch_dig_case_pid_init(hipStream_t s, const DigGeom& g, const int32_t* cell, const uint32_t* pid,
+                              const Scalars* sc, int64_t bound);
 // Anderson acceleration of the pseudo-time iteration (type II, Walker and
 // Ni): the iteration G is applied as a fixed-point map to the primitive
 // state x; with f = G(x) - x, the next state is G(x_k) - sum_i gamma_i dG_i,
@@ -124,11 +147,13 @@ void launch_aa_dots(hipStream_t s, const DigGeom& g, const AaWork& a, int slot, 
 // counts them.
 void launch_aa_update(hipStream_t s, const DigGeom& g, const AaWork& a, int cnt, double* prim, int parity);
 
-void launch_dig_set_local(hipStream_t s, const int32_t* state, uint8_t* local, int nt);
+// Local-accumulation flags from the gate states (cases of a batch that are
+// not coupled keep theirs).
+void launch_dig_set_local(hipStream_t s, const DigGeom& g, const int32_t* state, uint8_t* local);
 void launch_dig_fb_count(hipStream_t s, const DigGeom& g, DigWork w, const int32_t* offsets, const int32_t* orig,
                          const Scalars* sc, RngKey key);
 template <class VT>
-void launch_dig_fb_apply(hipStream_t s, DigWork w, PartDev<VT> p, const int32_t* offsets, const int4* tv,
+void launch_dig_fb_apply(hipStream_t s, const DigGeom& g, DigWork w, PartDev<VT> p, const int32_t* offsets, const int4* tv,
                          const double* xyz, const int32_t* orig, const Scalars* sc, RngKey key, int32_t* scratch,
                          uint32_t* bits, int nt, int64_t cap);
 void launch_dig_count_all(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,

@@ -201,6 +201,7 @@ __global__ void k_dig_sampled(DigGeom g, const double* ewma, double FN, DigWork 
         w.ok[c] = 0;
         return;
     }
+    if (g.cases) FN = g.cases[g.cell_case[c]].FN;
     const double n = (FN * (S[0] / 1.0)) / g.vol[c];
     const double rho = g.mass * n;
     const double u0 = S[1] / S[0], u1 = S[2] / S[0], u2 = S[3] / S[0];
@@ -234,6 +235,12 @@ __global__ void k_dig_kn(DigGeom g, DigWork w, double kn_ref, double T0, double 
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nt) return;
     const double rho = w.prim[kDigNV * (size_t)c], T = w.prim[kDigNV * (size_t)c + 4];
+    if (g.cases) {
+        const DigCase& k = g.cases[g.cell_case[c]];
+        kn_ref = k.mu0 / (k.p0 * L0) * k.kfac;
+        T0 = k.T0;
+        rho0 = k.rho0;
+    }
     const double lam = kn_ref * pow(T / T0, g.omega - 0.5) / (rho / rho0);
     const double dc = 2.0 * cbrt(3.0 * g.vol[c] / (4.0 * M_PI)) / L0;
     const double k = lam / dc;
@@ -668,9 +675,10 @@ __global__ void k_dig_mass_apply(DigGeom g, DigWork w) {
     if (c < g.nt) w.prim[kDigNV * (size_t)c] = w.prim[kDigNV * (size_t)c] * w.ctl->mass_scale;
 }
 
-__global__ void k_dig_set_local(const int32_t* state, uint8_t* local, int nt) {
+__global__ void k_dig_set_local(DigGeom g, const int32_t* state, uint8_t* local) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < nt) local[c] = state[c] != 0 ? 1 : 0;
+    if (c >= g.nt || (g.cases && !g.cases[g.cell_case[c]].enabled)) return;
+    local[c] = state[c] != 0 ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -691,9 +699,20 @@ __global__ void k_dig_fb_count(DigGeom g, DigWork w, const int32_t* offsets, con
     int T = N;
     const double* a = w.half + kDigNV * (size_t)c;
     const double* b = w.prim + kDigNV * (size_t)c;
-    if (w.state[c] <= 1 && N > 0 && fb_valid(a, b)) {
-        const Rand4 r = draw(key, (uint32_t)orig[c], sc->step, kPurposeRecalibrate, 0);
-        double t = floor(b[0] * g.vol[c] / (g.FN * g.mass) + u01(r.w[0], r.w[1]));
+    double FN = g.FN;
+    uint32_t subject = (uint32_t)orig[c];
+    bool on = true;
+    if (g.cases) {
+        const DigCase& k = g.cases[g.cell_case[c]];
+        FN = k.FN;
+        key.k0 = k.k0;
+        key.k1 = k.k1;
+        subject -= (uint32_t)k.cell0;
+        on = k.enabled != 0;
+    }
+    if (on && w.state[c] <= 1 && N > 0 && fb_valid(a, b)) {
+        const Rand4 r = draw(key, subject, sc->step, kPurposeRecalibrate, 0);
+        double t = floor(b[0] * g.vol[c] / (FN * g.mass) + u01(r.w[0], r.w[1]));
         if (!(t < 1073741824.0)) t = 1073741824.0;
         T = (int)t;
     }
@@ -704,7 +723,7 @@ __global__ void k_dig_fb_count(DigGeom g, DigWork w, const int32_t* offsets, con
 // One wave per cell: shift-scale the velocities, rank the particles by pid,
 // then delete (one at a time among the remaining, in pid order) or clone.
 template <class VT>
-__global__ __launch_bounds__(kFbLanes) void k_dig_fb_apply(DigWork w, PartDev<VT> p, const int32_t* offsets,
+__global__ __launch_bounds__(kFbLanes) void k_dig_fb_apply(DigGeom g, DigWork w, PartDev<VT> p, const int32_t* offsets,
                                                            const int4* tv, const double* xyz, const int32_t* orig,
                                                            const Scalars* sc, RngKey key, int32_t* scratch,
                                                            uint32_t* bits, int64_t cap) {
@@ -714,6 +733,18 @@ __global__ __launch_bounds__(kFbLanes) void k_dig_fb_apply(DigWork w, PartDev<VT
     const int N = offsets[c + 1] - (int)a0;
     const double* a = w.half + kDigNV * (size_t)c;
     const double* b = w.prim + kDigNV * (size_t)c;
+    uint32_t subject = (uint32_t)orig[c];
+    uint32_t next_pid = sc->next_pid;
+    int64_t pid_off = 0;
+    if (g.cases) {
+        const DigCase& k = g.cases[g.cell_case[c]];
+        if (!k.enabled) return;
+        key.k0 = k.k0;
+        key.k1 = k.k1;
+        subject -= (uint32_t)k.cell0;
+        next_pid = k.next_pid;
+        pid_off = w.fb_off[k.cell0];
+    }
     if (w.state[c] > 1 || N == 0 || !fb_valid(a, b)) return;
     const double scale = sqrt(b[4] / a[4]);
     for (int i = lane; i < N; i += kFbLanes) {
@@ -731,7 +762,6 @@ __global__ __launch_bounds__(kFbLanes) void k_dig_fb_apply(DigWork w, PartDev<VT
     }
     __syncthreads();
     const int T = w.fb_tgt[c];
-    const uint32_t subject = (uint32_t)orig[c];
     const uint32_t step = sc->step;
     if (T < N) {
         // Live ranks as a bitmap (in the cell's slice of `bits`); each lane
@@ -789,8 +819,8 @@ __global__ __launch_bounds__(kFbLanes) void k_dig_fb_apply(DigWork w, PartDev<VT
         const double* B = xyz + 3 * (size_t)q.y;
         const double* C = xyz + 3 * (size_t)q.z;
         const double* D = xyz + 3 * (size_t)q.w;
-        const int64_t base = sc->np + w.fb_off[subject];
-        const uint32_t pid0 = sc->next_pid + (uint32_t)w.fb_off[subject];
+        const int64_t base = sc->np + w.fb_off[orig[c]];
+        const uint32_t pid0 = next_pid + (uint32_t)(w.fb_off[orig[c]] - pid_off);
         for (int k = lane; k < T - N; k += kFbLanes) {
             const Rand4 r1 = draw(key, subject, step, kPurposeRecalibrate, (uint64_t)(2 + 2 * k));
             const Rand4 r2 = draw(key, subject, step, kPurposeRecalibrate, (uint64_t)(3 + 2 * k));
@@ -1086,15 +1116,66 @@ void launch_aa_update(hipStream_t s, const DigGeom& g, const AaWork& a, int cnt,
                        (const double*)a.dG, (const double*)a.gam, cnt, prim, a.red + 2 * a.m + parity);
 }
 
-void launch_dig_mass_rescale(hipStream_t s, const DigGeom& g, DigWork w, const Scalars* sc) {
+// Batch: one workgroup per case sums its FV mass over its internal cells in
+// a fixed order; the factor matches the case's particle mass.
+__global__ __launch_bounds__(kDigThreads) void k_dig_mass_cases(DigGeom g, DigWork w, const int32_t* offsets) {
+    DigCase& k = g.cases[blockIdx.x];
+    double m = 0.0;
+    for (int c = k.first + (int)threadIdx.x; c < k.end; c += kDigThreads)
+        m += w.prim[kDigNV * (size_t)c] * g.vol[c];
+    __shared__ double tot, dummy;
+    block_sum_min(m, 0.0, &tot, &dummy);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double mp = (double)(offsets[k.end] - offsets[k.first]) * k.FN * g.mass;
+        k.mass_scale = tot > 0 ? mp / tot : 1.0;
+    }
+}
+
+__global__ void k_dig_mass_apply_cases(DigGeom g, DigWork w) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < g.nt) w.prim[kDigNV * (size_t)c] = w.prim[kDigNV * (size_t)c] * g.cases[g.cell_case[c]].mass_scale;
+}
+
+__global__ void k_dig_case_pids(DigGeom g, DigWork w) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= g.n_cases) return;
+    DigCase& d = g.cases[k];
+    if (d.enabled) d.next_pid += (uint32_t)(w.fb_off[d.cell_end] - w.fb_off[d.cell0]);
+}
+
+__global__ void k_dig_case_pid_init(DigGeom g, const int32_t* cell, const uint32_t* pid, const Scalars* sc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc->np) return;
+    const int c = cell[i];
+    if (c >= 0) atomicMax(&g.cases[g.cell_case[c]].next_pid, pid[i] + 1u);
+}
+
+void launch_dig_mass_rescale(hipStream_t s, const DigGeom& g, DigWork w, const Scalars* sc,
+                             const int32_t* offsets) {
     const dim3 gr = cells_grid(g.nt), bl(kDigThreads);
+    if (g.cases) {
+        hipLaunchKernelGGL(k_dig_mass_cases, dim3(g.n_cases), bl, 0, s, g, w, offsets);
+        hipLaunchKernelGGL(k_dig_mass_apply_cases, gr, bl, 0, s, g, w);
+        return;
+    }
     hipLaunchKernelGGL(k_dig_mass_partial, gr, bl, 0, s, g, w);
     hipLaunchKernelGGL(k_dig_mass_factor, dim3(1), bl, 0, s, g, w, (int)gr.x, sc);
     hipLaunchKernelGGL(k_dig_mass_apply, gr, bl, 0, s, g, w);
 }
 
-void launch_dig_set_local(hipStream_t s, const int32_t* state, uint8_t* local, int nt) {
-    hipLaunchKernelGGL(k_dig_set_local, cells_grid(nt), dim3(kDigThreads), 0, s, state, local, nt);
+void launch_dig_case_pids(hipStream_t s, const DigGeom& g, const DigWork& w) {
+    if (g.cases) hipLaunchKernelGGL(k_dig_case_pids, dim3((g.n_cases + 63) / 64), dim3(64), 0, s, g, w);
+}
+
+void launch_dig_case_pid_init(hipStream_t s, const DigGeom& g, const int32_t* cell, const uint32_t* pid,
+                              const Scalars* sc, int64_t bound) {
+    if (!g.cases || bound <= 0) return;
+    hipLaunchKernelGGL(k_dig_case_pid_init, dim3((unsigned)((bound + 255) / 256)), dim3(256), 0, s, g, cell, pid, sc);
+}
+
+void launch_dig_set_local(hipStream_t s, const DigGeom& g, const int32_t* state, uint8_t* local) {
+    hipLaunchKernelGGL(k_dig_set_local, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, state, local);
 }
 
 void launch_dig_fb_count(hipStream_t s, const DigGeom& g, DigWork w, const int32_t* offsets, const int32_t* orig,
@@ -1103,10 +1184,10 @@ void launch_dig_fb_count(hipStream_t s, const DigGeom& g, DigWork w, const int32
 }
 
 template <class VT>
-void launch_dig_fb_apply(hipStream_t s, DigWork w, PartDev<VT> p, const int32_t* offsets, const int4* tv,
-                         const double* xyz, const int32_t* orig, const Scalars* sc, RngKey key, int32_t* scratch,
-                         uint32_t* bits, int nt, int64_t cap) {
-    hipLaunchKernelGGL(k_dig_fb_apply<VT>, dim3((unsigned)nt), dim3(kFbLanes), 0, s, w, p, offsets, tv, xyz, orig,
+void launch_dig_fb_apply(hipStream_t s, const DigGeom& g, DigWork w, PartDev<VT> p, const int32_t* offsets,
+                         const int4* tv, const double* xyz, const int32_t* orig, const Scalars* sc, RngKey key,
+                         int32_t* scratch, uint32_t* bits, int nt, int64_t cap) {
+    hipLaunchKernelGGL(k_dig_fb_apply<VT>, dim3((unsigned)nt), dim3(kFbLanes), 0, s, g, w, p, offsets, tv, xyz, orig,
                        sc, key, scratch, bits, cap);
 }
 
@@ -1129,10 +1210,10 @@ void launch_fill_u8(hipStream_t s, uint8_t* p, uint8_t v, int64_t n) {
     hipLaunchKernelGGL(k_fill_u8, cells_grid(n), dim3(kDigThreads), 0, s, p, v, n);
 }
 
-template void launch_dig_fb_apply<float>(hipStream_t, DigWork, PartDev<float>, const int32_t*, const int4*,
+template void launch_dig_fb_apply<float>(hipStream_t, const DigGeom&, DigWork, PartDev<float>, const int32_t*, const int4*,
                                          const double*, const int32_t*, const Scalars*, RngKey, int32_t*, uint32_t*,
                                          int, int64_t);
-template void launch_dig_fb_apply<double>(hipStream_t, DigWork, PartDev<double>, const int32_t*, const int4*,
+template void launch_dig_fb_apply<double>(hipStream_t, const DigGeom&, DigWork, PartDev<double>, const int32_t*, const int4*,
                                           const double*, const int32_t*, const Scalars*, RngKey, int32_t*, uint32_t*,
                                           int, int64_t);
 

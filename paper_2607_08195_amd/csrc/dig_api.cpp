@@ -20,6 +20,7 @@ struct DigState {
     DigWork w{};
     int nblk = 0;
     AaWork aa{};  // Anderson history, allocated at the first accelerated solve
+    bool closed = true;  // no inflow or outflow boundary: the solve's mass is rescaled to the particles'
 };
 
 void dig_release(dsmc_ctx c) {
@@ -177,16 +178,67 @@ dsmc_status ensure(dsmc_ctx c) {
         for (int i = 0; i < 3; ++i) hg[g].u[i] = c->bcs[g].u[i];
         hg[g].rho = c->mass * c->bcs[g].n;
     }
+    // Batch: per-case reference state, particle weight, key and cell ranges
+    // (the cases are contiguous in both numberings).
+    const int ncase = c->n_cases;
+    std::vector<CaseDev> cd(std::max(1, ncase));
+    std::vector<DigCase> dc(ncase);
+    std::vector<int32_t> case_of(nt, 0);
+    if (ncase) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess ||
+            hipMemcpy(cd.data(), c->d_cases, sizeof(CaseDev) * ncase, hipMemcpyDeviceToHost) != hipSuccess) {
+            delete d;
+            return fail(c, DSMC_E_DEVICE, "reading the case table failed");
+        }
+        const double R = kBoltzmann / c->mass;
+        for (int k = 0; k < ncase; ++k) {
+            DigCase& q = dc[k];
+            const double T0 = cd[k].T0;
+            q.FN = cd[k].FN;
+            q.p0 = cd[k].n0 * kBoltzmann * T0;
+            q.mu0 = mu_ref_of(c) * std::pow(T0 / c->Tref, c->omega);
+            q.kfac = std::sqrt(M_PI * R * T0 / 2.0);
+            q.T0 = T0;
+            q.rho0 = c->mass * cd[k].n0;
+            q.mass_scale = 1.0;
+            q.k0 = cd[k].k0;
+            q.k1 = cd[k].k1;
+            q.cell0 = c->case_cell0[k];
+            q.cell_end = k + 1 < ncase ? c->case_cell0[k + 1] : nt;
+            q.first = nt;
+            q.end = 0;
+            q.enabled = 1;
+            q.next_pid = 0;
+        }
+        for (int t = 0; t < nt; ++t) {
+            const int o = c->hm.orig[t];
+            const int k = (int)(std::upper_bound(c->case_cell0.begin(), c->case_cell0.end(), o) - c->case_cell0.begin()) - 1;
+            case_of[t] = k;
+            dc[k].first = std::min(dc[k].first, t);
+            dc[k].end = std::max(dc[k].end, t + 1);
+        }
+        for (const DigCase& q : dc)
+            if (q.end - q.first != q.cell_end - q.cell0) {
+                delete d;
+                return fail(c, DSMC_E_INVALID, "batch cases are not contiguous in the internal cell order");
+            }
+        if (!alloc_n(c, d->g.cases, ncase)) {
+            delete d;
+            return fail(c, DSMC_E_OOM, "device allocation of the coupling state failed");
+        }
+    }
     std::vector<double> mprev(5 * (size_t)nt);
     for (int t = 0; t < nt; ++t) {
         double* p = &mprev[5 * (size_t)t];
-        p[0] = c->mass * c->n0;
-        p[1] = c->u0[0];
-        p[2] = c->u0[1];
-        p[3] = c->u0[2];
-        p[4] = c->T0;
+        const CaseDev& q = cd[case_of[t]];
+        p[0] = c->mass * (ncase ? q.n0 : c->n0);
+        p[1] = ncase ? q.u0[0] : c->u0[0];
+        p[2] = ncase ? q.u0[1] : c->u0[1];
+        p[3] = ncase ? q.u0[2] : c->u0[2];
+        p[4] = ncase ? q.T0 : c->T0;
     }
     dsmc_status st = DSMC_OK;
+    if (ncase) st = upload(c, d->g.cases, dc);
     if (st == DSMC_OK) st = upload(c, cen, G.cen);
     if (st == DSMC_OK) st = upload(c, fcen, G.fcen);
     if (st == DSMC_OK) st = upload(c, fnu, G.fnu);
@@ -216,6 +268,22 @@ dsmc_status ensure(dsmc_ctx c) {
     g.omega = c->omega;
     g.T_ref = c->Tref;
     g.FN = c->FN;
+    g.cell_case = ncase ? c->d_cell_case : nullptr;
+    g.n_cases = ncase;
+    for (const dsmc_boundary_desc& b : c->bcs) d->closed = d->closed && b.kind != DSMC_BC_INFLOW && b.kind != DSMC_BC_OUTFLOW;
+    if (ncase) {
+        // next particle id of each case: its largest id + 1
+        Scalars sc;
+        if ((st = sync_scalars(c, &sc)) != DSMC_OK) {
+            delete d;
+            return st;
+        }
+        launch_dig_case_pid_init(c->stream, g, c->A.cell, c->A.pid, c->d_sc, sc.np);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+            delete d;
+            return fail(c, DSMC_E_DEVICE, "case id scan failed");
+        }
+    }
     c->dig = d;
     return DSMC_OK;
 }
@@ -408,8 +476,9 @@ dsmc_status feedback_t(dsmc_ctx c) {
         return fail(c, DSMC_E_CAPACITY, "feedback clones would exceed the particle store");
     }
     PartDev<VT> a = as_dev<VT>(c->A), b = as_dev<VT>(c->B);
-    launch_dig_fb_apply<VT>(s, d->w, a, c->d_offsets, c->d_tv, c->d_xyz, c->d_orig, c->d_sc, c->key, c->d_perm,
+    launch_dig_fb_apply<VT>(s, d->g, d->w, a, c->d_offsets, c->d_tv, c->d_xyz, c->d_orig, c->d_sc, c->key, c->d_perm,
                             c->d_rank, nt, c->cap);
+    launch_dig_case_pids(s, d->g, d->w);
     // counting sort of the survivors and the clones
     launch_fill_i32(s, c->d_counts, 0, nt + 1);
     launch_dig_count_all(s, a.cell, c->d_sc, c->d_counts, c->d_rank, bound);
@@ -450,7 +519,6 @@ dsmc_status to_host(dsmc_ctx c, T* dst, const T* src, int k) {
 dsmc_status usable(dsmc_ctx c) {
     if (!c) return fail(c, DSMC_E_INVALID, "NULL context");
     if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
-    if (c->n_cases) return fail(c, DSMC_E_INVALID, "the coupling step is not available for a batch");
     return ensure(c);
 }
 
@@ -506,9 +574,7 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
     r.n_fallback = h.n_fallback;
     if (r.n_rejected < nt) {
         if ((st = run_solve(c, p, &r)) != DSMC_OK) return st;
-        bool closed = true;
-        for (const dsmc_boundary_desc& b : c->bcs) closed = closed && b.kind != DSMC_BC_INFLOW && b.kind != DSMC_BC_OUTFLOW;
-        if (!r.failed && closed) launch_dig_mass_rescale(s, d->g, d->w, c->d_sc);
+        if (!r.failed && d->closed) launch_dig_mass_rescale(s, d->g, d->w, c->d_sc, c->d_offsets);
         if (!r.failed) {
             if (p->feedback && (st = run_feedback(c)) != DSMC_OK) {
                 if (rep) *rep = r;
@@ -517,7 +583,7 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
             launch_dig_copy(s, d->w.prim, d->w.mprev, 5 * (int64_t)nt);
         }
     }
-    launch_dig_set_local(s, d->w.state, c->d_local, nt);
+    launch_dig_set_local(s, d->g, d->w.state, c->d_local);
     HIP_TRY(c, hipGetLastError());
     if ((st = sync_scalars(c, &sc)) != DSMC_OK) return st;
     r.np_after = sc.np;
@@ -589,6 +655,18 @@ dsmc_status dig_feedback(dsmc_ctx c, const double* prim_old, const double* prim_
         if ((st = sync_scalars(c, &sc)) != DSMC_OK) return st;
         *np_after = sc.np;
     }
+    return DSMC_OK;
+}
+
+dsmc_status dig_batch_enable(dsmc_ctx c, const int32_t* enabled) {
+    dsmc_status st = usable(c);
+    if (st != DSMC_OK) return st;
+    if (!c->n_cases || !enabled) return fail(c, DSMC_E_INVALID, "not a batch context or NULL array");
+    std::vector<DigCase> h(c->n_cases);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(h.data(), c->dig->g.cases, sizeof(DigCase) * h.size(), hipMemcpyDeviceToHost));
+    for (int k = 0; k < c->n_cases; ++k) h[k].enabled = enabled[k] != 0;
+    HIP_TRY(c, hipMemcpy(c->dig->g.cases, h.data(), sizeof(DigCase) * h.size(), hipMemcpyHostToDevice));
     return DSMC_OK;
 }
 

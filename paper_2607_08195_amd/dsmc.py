@@ -160,12 +160,13 @@ _lib.dsmc_mlp_last_error.restype = C.c_char_p
 _lib.dsmc_mlp_destroy.argtypes = [P]
 _lib.dig_set_closure.argtypes = [ctx_t, P, C.c_double]
 _lib.dig_closure_data.argtypes = [ctx_t, P, P, P]
+_lib.dig_batch_enable.argtypes = [ctx_t, P]
 for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_state",
            "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
            "dsmc_profile", "dsmc_philox", "dsmc_device_copy", "dig_couple", "dig_get", "dig_residual",
            "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
            "dsmc_mlp_get_weights", "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train",
-           "dsmc_mlp_init_weights", "dig_set_closure", "dig_closure_data", "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
+           "dsmc_mlp_init_weights", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
            "dsmc_get_tuning", "dsmc_set_tuning", "dsmc_autotune"]:
     getattr(_lib, _f).restype = C.c_int32
 
@@ -175,7 +176,7 @@ EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_g
             "dsmc_last_error", "dsmc_destroy", "dig_couple", "dig_get", "dig_residual", "dig_solve",
             "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights", "dsmc_mlp_get_weights",
             "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train", "dsmc_mlp_last_error",
-            "dsmc_mlp_destroy", "dig_set_closure", "dig_closure_data"]
+            "dsmc_mlp_destroy", "dig_set_closure", "dig_closure_data", "dig_batch_enable"]
 
 
 class DsmcError(RuntimeError):
@@ -433,6 +434,11 @@ class Simulation:
         n = C.c_int64()
         self._c(_lib.dig_feedback(self.ctx, _p(a), _p(b), _p(st), C.byref(n)))
         return int(n.value)
+
+    def dig_enable(self, enabled):
+        """Batch: couple only the cases whose flag is true (all by default)."""
+        e = np.ascontiguousarray(np.asarray(enabled, np.int32))
+        self._c(_lib.dig_batch_enable(self.ctx, _p(e)))
 
     def set_closure(self, mlp, gate_tol=0.05):
         """Attach a trained Mlp as the HoT closure of dig_couple (None detaches)."""

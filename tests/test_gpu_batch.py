@@ -161,13 +161,81 @@ def test_autotune_keeps_results(D):
     b.close()
 
 
-def test_batch_refuses_inflow_and_coupling(D):
+def test_batch_refuses_inflow(D):
     wl = W.open_box(n=(4, 3, 3), ppc=4, vel_fp32=1)
     with pytest.raises(D.DsmcError):
         D.Simulation([wl, wl])
-    g = D.Simulation(_cases(1)[:2])
+    g = D.Simulation(W.cavity(n_hex=2, Kn=1.0, ppc=4))
     with pytest.raises(D.DsmcError):
-        g.dig_couple(n_m=1)
+        g.dig_enable([1])
+    g.close()
+
+
+def _prim_close(a, b, wl, rel):
+    cs = np.sqrt(1.380649e-23 / wl.species.mass * wl.run.T0)
+    assert np.all(np.abs(a[:, 0] - b[:, 0]) <= rel * np.abs(b[:, 0])), "density"
+    du = np.abs(a[:, 1:4] - b[:, 1:4])
+    assert np.all(du <= rel * np.maximum(np.abs(b[:, 1:4]), cs)), f"velocity max {du.max():.3e}"
+    assert np.all(np.abs(a[:, 4] - b[:, 4]) <= rel * np.abs(b[:, 4])), "temperature"
+
+
+def test_batch_coupling_matches_oracle_per_case(D):
+    """DIG coupling on a batch with cases 0 and 2 coupled and 1 and 3 left
+    to plain DSMC: two cycles with DSMC steps between them, started from the
+    oracle's state after a window of steps.  Each case against the oracle
+    run of that case alone (coupled or not): cells, (cell, pid) order and
+    particle counts exact, clone positions to 1e-12, velocities to 1e-9 of
+    the largest, the kept macroscopic state M^k to 1e-10 (the criteria of
+    the single-case cycle; the solve runs a fixed n_m iterations, eps_m = 0,
+    so the batch-wide stopping test does not couple the cases)."""
+    cases = _cases(0)
+    for wl in cases:
+        wl.run.ewma_on = 1
+        wl.run.n_a = 50
+    oracles = [Oracle(wl) for wl in cases]
+    for o in oracles:
+        o.step(40)
+    nt = [o.nt for o in oracles]
+    begin = np.concatenate([[0], np.cumsum(nt)])
+    sts = [o.particles() for o in oracles]
+    g = D.Simulation(cases, fill=False, capacity=4 * sum(o.np for o in oracles) + 100000)
+    assert np.array_equal(g.case_cells(), begin)
+    cat = np.concatenate
+    g.set_state(cat([s_["x"] for s_ in sts]), cat([s_["v"] for s_ in sts]),
+                cat([s_["cell"] + begin[k] for k, s_ in enumerate(sts)]), cat([s_["pid"] for s_ in sts]),
+                oracles[0].step_index, 0, cat([o.smax() for o in oracles]))
+    g.set_sums(D.SAMPLE_EWMA, cat([o.sums(1) for o in oracles]), cat([o.ewma_counts() for o in oracles]))
+    g.set_sums(D.SAMPLE_STEADY, cat([o.sums(0) for o in oracles]))
+    on = [1, 0, 1, 0]
+    g.dig_enable(on)
+    kw = dict(kn_max=0.93, passes=3, n_m=40, eps_m=0.0, cfl=0.5, feedback=1)
+    changed = 0
+    for cycle in range(2):
+        rg = g.dig_couple(**kw)
+        assert rg["iters"] == 40 and not rg["failed"]
+        st = g.state()
+        mprev = g.dig_get("mprev")
+        for k, o in enumerate(oracles):
+            n0 = o.np
+            if on[k]:
+                ro = o.dig_couple(**kw)
+                assert ro["iters"] == 40 and not ro["failed"]
+                changed += o.np != n0
+            gk, ok = _split(st, begin, k), o.particles()
+            ctx = f"cycle {cycle} case {k}"
+            assert gk["n"] == o.np, ctx
+            assert np.array_equal(gk["cell"], ok["cell"]) and np.array_equal(gk["pid"], ok["pid"]), ctx
+            assert np.abs(gk["x"] - ok["x"]).max(initial=0.0) <= 1e-12, ctx
+            assert np.abs(gk["v"] - ok["v"]).max(initial=0.0) <= 1e-9 * np.abs(ok["v"]).max(), ctx
+            if on[k]:
+                _prim_close(mprev[begin[k]:begin[k + 1]], o.mprev(), cases[k], 1e-10)
+        g.step(3)
+        for o in oracles:
+            o.step(3)
+        st = g.state()
+        for k, o in enumerate(oracles):
+            compare_particles(_split(st, begin, k), o.particles(), 0, ctx=f"after cycle {cycle} case {k}")
+    assert changed > 0, "the feedback changed no particle count"
     g.close()
 
 
