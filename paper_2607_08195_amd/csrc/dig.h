@@ -53,6 +53,7 @@ struct DigGeom {
     const int32_t* cell_case;  // batch: internal cell -> case (null for one case)
     DigCase* cases;            // batch: per-case parameters
     int n_cases;
+    int skip_idle;             // batch: the solve leaves out the cells of cases not coupled
 };
 
 struct DigCtl {

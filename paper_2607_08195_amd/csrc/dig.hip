@@ -251,9 +251,15 @@ __global__ void k_dig_kn(DigGeom g, DigWork w, double kn_ref, double T0, double 
 // Weighted least squares over face neighbours: a diffuse wall contributes
 // its velocity and temperature (and the cell's own density) at the face
 // centroid; specular, inflow and outflow faces contribute nothing.
+// Batch, inside the coupling step's solve: cells of cases that are not
+// coupled are left out (cases share no faces, so no coupled cell reads them).
+__device__ __forceinline__ bool idle_cell(const DigGeom& g, int c) {
+    return g.skip_idle && !g.cases[g.cell_case[c]].enabled;
+}
+
 __global__ void k_dig_grad(DigGeom g, const double* prim, double* grad, const DigCtl* ctl) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.nt || stopped(ctl)) return;
+    if (c >= g.nt || stopped(ctl) || idle_cell(g, c)) return;
     double pc[kDigNV];
 #pragma unroll
     for (int v = 0; v < kDigNV; ++v) pc[v] = prim[kDigNV * (size_t)c + v];
@@ -474,7 +480,7 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_residual(DigGeom g, const d
     if (stopped(w.ctl)) return;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     double r2 = 0.0, dtc = __builtin_inf();
-    if (c < g.nt) {
+    if (c < g.nt && !idle_cell(g, c)) {
         double Pc[kDigNV], gc[15];
 #pragma unroll
         for (int v = 0; v < kDigNV; ++v) Pc[v] = prim[kDigNV * (size_t)c + v];
@@ -610,7 +616,7 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_check(DigWork w, int nblk, 
 
 __global__ void k_dig_save(DigGeom g, DigWork w) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.nt || stopped(w.ctl)) return;
+    if (c >= g.nt || stopped(w.ctl) || idle_cell(g, c)) return;
     double P[kDigNV], U[kDigNV];
 #pragma unroll
     for (int v = 0; v < kDigNV; ++v) {
@@ -625,7 +631,7 @@ __global__ void k_dig_save(DigGeom g, DigWork w) {
 // Stage update U = U0 - alpha dt / V R(stage).
 __global__ void k_dig_update(DigGeom g, DigWork w, double alpha, int global_dt) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.nt || stopped(w.ctl)) return;
+    if (c >= g.nt || stopped(w.ctl) || idle_cell(g, c)) return;
     const double dtc = global_dt ? w.ctl->dtmin : w.dt[c];
     double U[kDigNV];
 #pragma unroll
@@ -647,9 +653,10 @@ __global__ void k_dig_update(DigGeom g, DigWork w, double alpha, int global_dt) 
 __global__ void k_dig_commit(DigGeom g, DigWork w) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nt || stopped(w.ctl)) return;
+    if (c == 0) w.ctl->iters += 1;
+    if (idle_cell(g, c)) return;
 #pragma unroll
     for (int v = 0; v < kDigNV; ++v) w.prim[kDigNV * (size_t)c + v] = w.stage[kDigNV * (size_t)c + v];
-    if (c == 0) w.ctl->iters += 1;
 }
 
 __global__ __launch_bounds__(kDigThreads) void k_dig_mass_partial(DigGeom g, DigWork w) {
@@ -1128,7 +1135,7 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_mass_cases(DigGeom g, DigWo
     __syncthreads();
     if (threadIdx.x == 0) {
         const double mp = (double)(offsets[k.end] - offsets[k.first]) * k.FN * g.mass;
-        k.mass_scale = tot > 0 ? mp / tot : 1.0;
+        k.mass_scale = k.enabled && tot > 0 ? mp / tot : 1.0;
     }
 }
 

@@ -573,7 +573,10 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
     r.n_closure = h.n_closure;
     r.n_fallback = h.n_fallback;
     if (r.n_rejected < nt) {
-        if ((st = run_solve(c, p, &r)) != DSMC_OK) return st;
+        d->g.skip_idle = c->n_cases ? 1 : 0;
+        st = run_solve(c, p, &r);
+        d->g.skip_idle = 0;
+        if (st != DSMC_OK) return st;
         if (!r.failed && d->closed) launch_dig_mass_rescale(s, d->g, d->w, c->d_sc, c->d_offsets);
         if (!r.failed) {
             if (p->feedback && (st = run_feedback(c)) != DSMC_OK) {

@@ -266,3 +266,75 @@ def test_ensemble64_smallest_cases_match_oracle(D):
         assert np.array_equal(nc[begin[k]:begin[k + 1]], oc) and np.array_equal(na[begin[k]:begin[k + 1]], oa)
         compare_sums(sums[begin[k]:begin[k + 1]], o.sums(0))
     g.close()
+
+
+def _close(gk, ok, ctx, rel=1e-9):
+    """Criteria of the coupled cycle: cells, order and counts exact; positions
+    to 1e-11 m and velocities to `rel` of the largest speed (the solve's
+    ulp-level differences carried through the feedback)."""
+    assert gk["n"] == len(ok["pid"]), ctx
+    assert np.array_equal(gk["cell"], ok["cell"]) and np.array_equal(gk["pid"], ok["pid"]), ctx
+    assert np.abs(gk["x"] - ok["x"]).max(initial=0.0) <= 1e-11, ctx
+    assert np.abs(gk["v"] - ok["v"]).max(initial=0.0) <= rel * np.abs(ok["v"]).max(), ctx
+
+
+def test_ensemble64_half_coupled_smallest_cases_match_oracle(D):
+    """The 64-case ensemble with the coupling step on half of the cases (four
+    of the eight smallest among them) and a closure network attached: two
+    ordinary and two graph-replayed steps, one coupling cycle, then two
+    ordinary and two graph-replayed steps again.  The closure is evaluated on
+    every cell and its gate set to zero tolerance, so every cell keeps its
+    sampled HoT and the cycle is the oracle's.  Velocities are stored in
+    FP64 here: the solve's ulp-level differences would otherwise turn into
+    FP32 rounding flips.  The eight smallest cases against the oracle run of
+    each case alone (coupled or not): cells, order and pair counts exact,
+    positions to 1e-11 m, velocities and steady sums to 1e-9."""
+    cases = W.cavity_ensemble(64, vel_fp32=0)
+    for wl in cases:
+        wl.run.n_ss = 0
+        wl.run.ewma_on = 1
+        wl.run.n_a = 50
+    g = D.Simulation(cases, stream=_stream())
+    begin = g.case_cells()
+    small = np.argsort(np.diff(begin), kind="stable")[:8]
+    on = (np.arange(len(cases)) % 2 == 0).astype(np.int32)
+    for i, k in enumerate(small):
+        on[k] = 1 - i % 2
+    g.dig_enable(on)
+    net = D.Mlp()
+    net.init_weights(seed=3)
+    g.set_closure(net, gate_tol=0.0)
+    oracles = {int(k): Oracle(cases[k]) for k in small}
+    kw = dict(kn_max=0.93, passes=3, n_m=20, eps_m=0.0, cfl=0.5, feedback=1)
+    g.step(2)
+    g.graph_step(2)
+    for o in oracles.values():
+        o.step(4)
+    r = g.dig_couple(**kw)
+    assert r["iters"] == 20 and not r["failed"]
+    assert r["n_closure"] == 0 and r["n_fallback"] > 0
+    changed = 0
+    for k, o in oracles.items():
+        if on[k]:
+            n0 = o.np
+            o.dig_couple(**kw)
+            changed += o.np != n0
+    assert changed > 0
+    st = g.state()
+    for k, o in oracles.items():
+        _close(_split(st, begin, k), o.particles(), f"coupled case {k}")
+    g.step(2)
+    g.graph_step(2)
+    for o in oracles.values():
+        o.step(4)
+    st = g.state()
+    nc, na = g.pair_counts()
+    sums, ns = g.sums(D.SAMPLE_STEADY)
+    assert ns == 8
+    for k, o in oracles.items():
+        _close(_split(st, begin, k), o.particles(), f"case {k}")
+        oc, oa = o.pair_counts()
+        assert np.array_equal(nc[begin[k]:begin[k + 1]], oc) and np.array_equal(na[begin[k]:begin[k + 1]], oa)
+        compare_sums(sums[begin[k]:begin[k + 1]], o.sums(0), rel=1e-9)
+    net.close()
+    g.close()
