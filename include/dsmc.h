@@ -245,7 +245,9 @@ dsmc_status dsmc_graph_step(dsmc_ctx ctx, int32_t n_steps);
  * collide 0 LDS-staged
  * velocities, 1/2 LDS-ranked at 4/8 waves/SIMD (chunks up to 4096
  * particles in LDS), 3/4 LDS-ranked with chunks up to 3072/2048 particles
- * (more workgroups per CU); sort 0 scatter, 1 gather.
+ * (more workgroups per CU); sort 0 scatter, 1 gather, 2 gather done by
+ * the collide kernel chunk by chunk (collide 1-4; with collide 0 it acts as
+ * 1).  The autotuner's sort_ms includes the collide kernel.
  * Every schedule gives the same results.  A batch accepts only move 0-2
  * and 4-7, 12-16. */
 typedef struct {

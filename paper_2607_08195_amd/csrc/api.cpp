@@ -124,6 +124,7 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
     }
     hipStream_t s = c->stream;
     PartDev<VT> a = as_dev<VT>(c->A), b = as_dev<VT>(c->B);
+    bool fuse = false;  // the collide kernel gathers the sorted buffer
     {
         Timed t(c, kSlotBegin);
         launch_begin(s, c->d_counts, c->nt, c->d_sc, smp ? 1 : 0, c->n_ss, c->wq.n);
@@ -155,7 +156,8 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
             Timed t(c, kSlotScatter);
             launch_scatter<VT>(s, a, b, c->d_sc, c->d_offsets, c->d_rank, need, c->cap, c->d_sortperm, c->sort_variant);
         }
-        if (c->sort_variant == kSortGather) {
+        fuse = c->sort_variant == kSortFused && (col || smp) && collide_fuses_gather(c->collide_variant);
+        if (c->sort_variant == kSortGather || (c->sort_variant == kSortFused && !fuse)) {
             Timed t(c, kSlotGather);
             launch_gather<VT>(s, a, b, c->d_sc, c->d_sortperm, need);
         }
@@ -174,7 +176,7 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
         cp.cell_case = c->d_cell_case;
         cp.cases = c->d_cases;
         launch_collide_sample<VT>(s, a, c->d_offsets, cp, c->d_sc, c->d_perm, col ? 1 : 0, smp ? 1 : 0,
-                                  c->collide_variant);
+                                  c->collide_variant, fuse ? as_dev<VT>(c->B) : PartDev<VT>{}, c->d_sortperm);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -223,7 +225,10 @@ void read_tuning(dsmc_ctx c) {
     if (const char* v = std::getenv("DSMC_MOVE_BATCH"))
         c->move_batch = std::min(kQueueMaxBatch, std::max(64, std::atoi(v) / 64 * 64));
     if (const char* v = std::getenv("DSMC_REORDER")) c->reorder = std::atoi(v) != 0;
-    if (const char* v = std::getenv("DSMC_SORT")) c->sort_variant = std::string(v) == "scatter" ? kSortScatter : kSortGather;
+    if (const char* v = std::getenv("DSMC_SORT")) {
+        const std::string k(v);
+        c->sort_variant = k == "scatter" ? kSortScatter : k == "fused" ? kSortFused : kSortGather;
+    }
     if (const char* v = std::getenv("DSMC_COLLIDE")) {
         std::string s(v);
         if (s == "lds") c->collide_variant = kCollideLds;
@@ -695,7 +700,7 @@ dsmc_status dsmc_set_tuning(dsmc_ctx c, const dsmc_tuning* t) {
     if (!c || !t) return fail(c, DSMC_E_INVALID, "bad arguments");
     const bool batch_ok = move_reads_cases(t->move);
     if (t->move < 0 || t->move > kMoveFace3W8 || t->collide < 0 || t->collide > kCollideG2k || t->sort < 0 ||
-        t->sort > kSortGather || (c->n_cases && !batch_ok))
+        t->sort > kSortFused || (c->n_cases && !batch_ok))
         return fail(c, DSMC_E_INVALID, "unknown or unsupported kernel variant");
     c->move_variant = t->move;
     c->collide_variant = t->collide;
@@ -727,11 +732,12 @@ dsmc_status dsmc_autotune(dsmc_ctx c, int32_t trial_steps, dsmc_tuning* out) {
         if (ms < best.collide_ms) { best.collide_ms = ms; best.collide = v; }
     }
     c->collide_variant = best.collide;
-    const int sorts[] = {kSortGather, kSortScatter};
+    const int sorts[] = {kSortGather, kSortScatter, kSortFused};
     for (int v : sorts) {
         c->sort_variant = v;
         double ms = 0;
-        dsmc_status st = time_slots(c, trial_steps, {kSlotScan, kSlotScatter, kSlotGather}, &ms);
+        // the fused form gathers inside the collide kernel: compare sort + collide
+        dsmc_status st = time_slots(c, trial_steps, {kSlotScan, kSlotScatter, kSlotGather, kSlotCollide}, &ms);
         if (st != DSMC_OK) return st;
         if (ms < best.sort_ms) { best.sort_ms = ms; best.sort = v; }
     }

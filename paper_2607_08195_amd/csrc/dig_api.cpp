@@ -484,7 +484,7 @@ dsmc_status feedback_t(dsmc_ctx c) {
     launch_dig_count_all(s, a.cell, c->d_sc, c->d_counts, c->d_rank, bound);
     launch_scan(s, c->d_counts, nt, c->d_offsets, c->d_blocksums, c->d_sc, kScanCells);
     launch_scatter<VT>(s, a, b, c->d_sc, c->d_offsets, c->d_rank, bound, c->cap, c->d_sortperm, c->sort_variant);
-    if (c->sort_variant == kSortGather) launch_gather<VT>(s, a, b, c->d_sc, c->d_sortperm, bound);
+    if (c->sort_variant != kSortScatter) launch_gather<VT>(s, a, b, c->d_sc, c->d_sortperm, bound);
     std::swap(c->A, c->B);
     c->np_bound = bound;
     HIP_TRY(c, hipGetLastError());

@@ -25,7 +25,10 @@ enum { kMoveLane = 0, kMoveLaneW6 = 1, kMoveLaneW8 = 2, kMoveBatched = 3, kMoveD
        kMovePool128 = 10, kMovePool256 = 11, kMoveCap4 = 12, kMoveCap5 = 13, kMoveCap6 = 14,
        kMoveFace3 = 15, kMoveFace3W8 = 16 };
 enum { kCollideLds = 0, kCollideGlobal = 1, kCollideGlobal8 = 2, kCollideG3k = 3, kCollideG2k = 4 };
-enum { kSortScatter = 0, kSortGather = 1 };
+// sort: scatter by rank; gather (k_perm then k_gather); fused (k_perm, then
+// the collide kernel gathers each chunk before colliding it; G-type collide
+// schedules only, the others take the gather form)
+enum { kSortScatter = 0, kSortGather = 1, kSortFused = 2 };
 
 // Particle store: positions and velocities interleaved per particle (a
 // scattered access then touches one cache line per quantity, not three),
@@ -140,8 +143,12 @@ template <class VT>
 void launch_scatter(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalars* sc, const int32_t* offsets,
                     const uint32_t* rank, int64_t bound, int64_t cap, int32_t* perm, int variant);
 template <class VT>
+// With src.pos non-null (fused sort), p's slots are first gathered from src
+// through sortperm (G-type schedules only: collide_fuses_gather).
 void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
-                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant);
+                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant,
+                           PartDev<VT> src, const int32_t* sortperm);
+bool collide_fuses_gather(int variant);
 void launch_fields(hipStream_t s, const double* sums, int nt, double ns, double mass, double FN,
                    const double* vol, const int32_t* orig, double* out, const int32_t* cell_case,
                    const CaseDev* cases);

@@ -1122,10 +1122,16 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
 // CAP bounds the LDS of a workgroup (6 bytes per particle), hence how many
 // workgroups share a CU; a chunk of more than CAP particles takes the
 // global-memory path.
-template <class VT, int WPE, int CAP>
+// With FUSED, the chunk's slots of the sorted buffer p are first filled from
+// the unsorted buffer src through the gather permutation (slot -> source
+// index; k_perm has written the slots' cells): the sort's gather done by the
+// workgroup that then collides the chunk, so that gathering one chunk
+// overlaps the collisions of others and the velocities are read back from
+// cache.
+template <class VT, int WPE, int CAP, bool FUSED>
 __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(WPE))) void k_collide_sample_g(
     PartDev<VT> p, const int32_t* offsets, CollideParams cp, const Scalars* sc, int32_t* perm, int do_collide,
-    int do_sample) {
+    int do_sample, PartDev<VT> src, const int32_t* sortperm) {
     __shared__ uint32_t spid[CAP];
     __shared__ uint16_t sord[CAP];
     __shared__ int32_t soff[kCollideLanes + 1];
@@ -1138,10 +1144,57 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
     if (lane == 0) soff[kCollideLanes] = offsets[min(c0 + kCollideLanes, nt)] - (int32_t)a;
     const int64_t n = (int64_t)offsets[min(c0 + kCollideLanes, nt)] - a;
     const uint32_t step = sc->step;
-    if (n <= CAP) {
-#pragma unroll 4
-        for (int64_t i = lane; i < n; i += kCollideLanes) spid[i] = p.pid[a + i];
+    if (FUSED) {
+        // kFuseBatch particles per lane in flight: all loads of a batch are
+        // issued before its stores (the compiler cannot move a load of src
+        // above a store to p, which might alias it)
+        constexpr int kFuseBatch = 8;
+        for (int64_t i0 = lane; i0 < n; i0 += kFuseBatch * kCollideLanes) {
+            int64_t j[kFuseBatch];
+            double x[kFuseBatch][3];
+            VT v[kFuseBatch][3];
+            uint32_t id[kFuseBatch];
+#pragma unroll
+            for (int b = 0; b < kFuseBatch; ++b) {
+                const int64_t i = i0 + b * kCollideLanes;
+                j[b] = i < n ? sortperm[a + i] : 0;
+            }
+#pragma unroll
+            for (int b = 0; b < kFuseBatch; ++b) {
+                if (i0 + b * kCollideLanes < n) {
+                    x[b][0] = src.pos[3 * j[b]];
+                    x[b][1] = src.pos[3 * j[b] + 1];
+                    x[b][2] = src.pos[3 * j[b] + 2];
+                    v[b][0] = src.vel[3 * j[b]];
+                    v[b][1] = src.vel[3 * j[b] + 1];
+                    v[b][2] = src.vel[3 * j[b] + 2];
+                    id[b] = src.pid[j[b]];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < kFuseBatch; ++b) {
+                const int64_t i = i0 + b * kCollideLanes;
+                if (i < n) {
+                    const int64_t d = a + i;
+                    p.pos[3 * d] = x[b][0];
+                    p.pos[3 * d + 1] = x[b][1];
+                    p.pos[3 * d + 2] = x[b][2];
+                    p.vel[3 * d] = v[b][0];
+                    p.vel[3 * d + 1] = v[b][1];
+                    p.vel[3 * d + 2] = v[b][2];
+                    p.pid[d] = id[b];
+                    if (n <= CAP) spid[i] = id[b];
+                }
+            }
+        }
         __syncthreads();
+    }
+    if (n <= CAP) {
+        if (!FUSED) {
+#pragma unroll 4
+            for (int64_t i = lane; i < n; i += kCollideLanes) spid[i] = p.pid[a + i];
+            __syncthreads();
+        }
         for (int i = lane; i < (int)n; i += kCollideLanes) {
             const int k = p.cell[a + i] - c0;
             const int s0 = soff[k];
@@ -1412,7 +1465,7 @@ void launch_scan(hipStream_t s, const int32_t* in, int64_t n, int32_t* out, int3
 template <class VT>
 void launch_scatter(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalars* sc, const int32_t* offsets,
                     const uint32_t* rank, int64_t bound, int64_t cap, int32_t* perm, int variant) {
-    if (variant == kSortGather) {
+    if (variant == kSortGather || variant == kSortFused) {
         hipLaunchKernelGGL(k_perm, dim3(grid8(bound, 256)), dim3(256), 0, s, src.cell, sc, offsets, rank, perm,
                            dst.cell, cap);
     } else {
@@ -1426,22 +1479,35 @@ void launch_gather(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalar
     hipLaunchKernelGGL(k_gather<VT>, dim3(grid8(bound, 256)), dim3(256), 0, s, src, dst, sc, perm);
 }
 
+template <class VT, int WPE, int CAP>
+static void launch_collide_g(hipStream_t s, int nchunk, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
+                             const Scalars* sc, int32_t* perm, int do_collide, int do_sample, PartDev<VT> src,
+                             const int32_t* sortperm) {
+    if (src.pos)
+        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, true>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
+                           offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
+    else
+        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, false>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
+                           offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
+}
+
+bool collide_fuses_gather(int variant) {
+    return variant == kCollideGlobal || variant == kCollideGlobal8 || variant == kCollideG3k || variant == kCollideG2k;
+}
+
 template <class VT>
 void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
-                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant) {
+                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant,
+                           PartDev<VT> src, const int32_t* sortperm) {
     const int nchunk = (cp.nt + kCollideLanes - 1) / kCollideLanes;
     if (variant == kCollideGlobal)
-        hipLaunchKernelGGL((k_collide_sample_g<VT, 4, kCollideCapG>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
-                           offsets, cp, sc, perm, do_collide, do_sample);
+        launch_collide_g<VT, 4, kCollideCapG>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
     else if (variant == kCollideGlobal8)
-        hipLaunchKernelGGL((k_collide_sample_g<VT, 8, kCollideCapG>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
-                           offsets, cp, sc, perm, do_collide, do_sample);
+        launch_collide_g<VT, 8, kCollideCapG>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
     else if (variant == kCollideG3k)
-        hipLaunchKernelGGL((k_collide_sample_g<VT, 4, 3072>), dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets,
-                           cp, sc, perm, do_collide, do_sample);
+        launch_collide_g<VT, 4, 3072>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
     else if (variant == kCollideG2k)
-        hipLaunchKernelGGL((k_collide_sample_g<VT, 4, 2048>), dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets,
-                           cp, sc, perm, do_collide, do_sample);
+        launch_collide_g<VT, 4, 2048>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
     else
         hipLaunchKernelGGL(k_collide_sample<VT>, dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc, perm,
                            do_collide, do_sample);
@@ -1487,7 +1553,7 @@ void launch_fill_f64(hipStream_t s, double* p, double v, int64_t n) {
     template void launch_gather<VT>(hipStream_t, PartDev<VT>, PartDev<VT>, const Scalars*, const int32_t*,  \
                                     int64_t);                                                               \
     template void launch_collide_sample<VT>(hipStream_t, PartDev<VT>, const int32_t*, const CollideParams&, \
-                                            const Scalars*, int32_t*, int, int, int);
+                                            const Scalars*, int32_t*, int, int, int, PartDev<VT>, const int32_t*);
 
 INSTANTIATE(float)
 INSTANTIATE(double)

@@ -149,10 +149,10 @@ def test_autotune_keeps_results(D):
     a = D.Simulation(wl)
     b = D.Simulation(wl)
     t = a.autotune(trial_steps=2)
-    assert t["move"] in (1, 2, 4, 5, 6, 7, 12, 13, 14, 15, 16) and t["collide"] in (0, 1, 2, 3, 4) and t["sort"] in (0, 1)
+    assert t["move"] in (1, 2, 4, 5, 6, 7, 12, 13, 14, 15, 16) and t["collide"] in (0, 1, 2, 3, 4) and t["sort"] in (0, 1, 2)
     assert t["move_ms"] > 0 and t["collide_ms"] > 0 and t["sort_ms"] > 0
     steps = a.state(particles=False)["step"]
-    assert steps == 11 * 3 + 5 * 3 + 2 * 3
+    assert steps == 11 * 3 + 5 * 3 + 3 * 3
     b.step(steps)
     sa, sb = a.state(), b.state()
     for k in ["cell", "pid", "x", "v"]:

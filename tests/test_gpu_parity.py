@@ -43,7 +43,7 @@ def _cases():
 CASES = _cases()
 
 
-def _one_step_parity(D, wl, presteps, steps=1, move=None, collide=None):
+def _one_step_parity(D, wl, presteps, steps=1, move=None, collide=None, sort=None):
     wl.run.n_ss = presteps
     o = Oracle(wl)
     o.step(presteps)
@@ -51,9 +51,10 @@ def _one_step_parity(D, wl, presteps, steps=1, move=None, collide=None):
     c0 = o.counters()
     g = D.Simulation(wl, fill=False, capacity=max(4 * o.np, 100000))
     g.set_state(st["x"], st["v"], st["cell"], st["pid"], o.step_index, o.next_pid, o.smax())
-    if move is not None or collide is not None:
+    if move is not None or collide is not None or sort is not None:
         t = g.tuning()
-        g.set_tuning(t["move"] if move is None else move, t["collide"] if collide is None else collide, t["sort"])
+        g.set_tuning(t["move"] if move is None else move, t["collide"] if collide is None else collide,
+                     t["sort"] if sort is None else sort)
     for _ in range(steps):
         o.step(1)
         g.step(1)
@@ -109,6 +110,18 @@ def test_move_schedules_parity(dsmc, move, case):
 def test_collide_schedules_parity(dsmc, collide, case):
     make, pre = CASES[case]
     _one_step_parity(dsmc, make(), pre, steps=2, collide=collide)
+
+
+# every sort schedule with an LDS-staged and an LDS-ranked collide schedule:
+# the fused form gathers inside the collide kernel (the dense case takes its
+# global-memory path after the gather), with collide 0 it falls back to the
+# gather kernel; the inflow case sorts injected particles too
+@pytest.mark.parametrize("case", ["cavity_8_fp32_jitter_kn0.1", "dense_ppc45", "open_box_inflow", "cavity_6_fp64_kn1"])
+@pytest.mark.parametrize("collide", [0, 3])
+@pytest.mark.parametrize("sort", [0, 1, 2])
+def test_sort_schedules_parity(dsmc, sort, collide, case):
+    make, pre = CASES[case]
+    _one_step_parity(dsmc, make(), pre, steps=2, collide=collide, sort=sort)
 
 
 def test_three_steps_parity_fp64(dsmc):
