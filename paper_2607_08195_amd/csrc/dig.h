@@ -83,7 +83,7 @@ struct DigWork {
     double* dt;       // [nt] pseudo-time step
     double* U0;       // [nt][5] conserved state at the start of an iteration
     double* stage;    // [nt][5] stage state
-    double* partial;  // [2 * blocks] reduction partials
+    double* partial;  // [2 * blocks] reduction partials (blocks of the residual kernel: 4 lanes per cell)
     DigCtl* ctl;
     int32_t* fb_cnt;  // [nt] clones per cell, caller order
     int32_t* fb_off;  // [nt + 1]

@@ -257,61 +257,65 @@ __device__ __forceinline__ bool idle_cell(const DigGeom& g, int c) {
     return g.skip_idle && !g.cases[g.cell_case[c]].enabled;
 }
 
-__global__ void k_dig_grad(DigGeom g, const double* prim, double* grad, const DigCtl* ctl) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.nt || stopped(ctl) || idle_cell(g, c)) return;
-    double pc[kDigNV];
+// One lane per (cell, face), four consecutive lanes per cell: each lane
+// forms its face's weighted difference terms; the cell's sums are taken over
+// the four lanes in face order (a face without a value adds +0, which leaves
+// the sum unchanged), and each lane writes a quarter of the gradient.
+__global__ __launch_bounds__(kDigThreads) void k_dig_grad(DigGeom g, const double* prim, double* grad, const DigCtl* ctl) {
+    if (stopped(ctl)) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)(t >> 2), f = (int)(t & 3);
+    const bool live = c < g.nt && !idle_cell(g, c);
+    double tb[kDigNV][3];
 #pragma unroll
-    for (int v = 0; v < kDigNV; ++v) pc[v] = prim[kDigNV * (size_t)c + v];
+    for (int v = 0; v < kDigNV; ++v) tb[v][0] = tb[v][1] = tb[v][2] = 0.0;
+    if (live) {
+        const int link = g.flink[4 * (size_t)c + f];
+        const int kind = link & 7, idx = link >> 3;
+        const bool inner = kind == kLinkInterior || kind == kLinkPeriodic;
+        if (inner || kind == kLinkWall) {
+            double pc[kDigNV], far[kDigNV];
+#pragma unroll
+            for (int v = 0; v < kDigNV; ++v) pc[v] = prim[kDigNV * (size_t)c + v];
+            if (inner) {
+#pragma unroll
+                for (int v = 0; v < kDigNV; ++v) far[v] = prim[kDigNV * (size_t)idx + v];
+            } else {
+                const DigGroup& gr = g.groups[idx];
+                far[0] = pc[0];
+                far[1] = gr.u[0]; far[2] = gr.u[1]; far[3] = gr.u[2];
+                far[4] = gr.T;
+            }
+            const double* dx = g.fdx + 12 * (size_t)c + 3 * f;
+            const double d0 = dx[0], d1 = dx[1], d2 = dx[2];
+            const double wgt = 1.0 / (d0 * d0 + d1 * d1 + d2 * d2);
+#pragma unroll
+            for (int v = 0; v < kDigNV; ++v) {
+                const double dphi = far[v] - pc[v];
+                tb[v][0] = wgt * d0 * dphi;
+                tb[v][1] = wgt * d1 * dphi;
+                tb[v][2] = wgt * d2 * dphi;
+            }
+        }
+    }
+    const int q0 = (int)(threadIdx.x & 63) & ~3;
     double b[kDigNV][3];
 #pragma unroll
     for (int v = 0; v < kDigNV; ++v) b[v][0] = b[v][1] = b[v][2] = 0.0;
-    // the four links at once, then the four neighbour states (a face without
-    // a neighbour cell loads the cell's own state, unused), so that the
-    // gathered loads are in flight together rather than one face at a time
-    const int4 lk = *reinterpret_cast<const int4*>(g.flink + 4 * (size_t)c);
-    const int links[4] = {lk.x, lk.y, lk.z, lk.w};
-    double nbv[4][kDigNV];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        const int kind = links[f] & 7;
-        const int src = (kind == kLinkInterior || kind == kLinkPeriodic) ? (links[f] >> 3) : c;
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int v = 0; v < kDigNV; ++v) nbv[f][v] = prim[kDigNV * (size_t)src + v];
-    }
+        for (int v = 0; v < kDigNV; ++v)
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        const int link = links[f];
-        const int kind = link & 7, idx = link >> 3;
-        double far[kDigNV];
-        if (kind == kLinkInterior || kind == kLinkPeriodic) {
-#pragma unroll
-            for (int v = 0; v < kDigNV; ++v) far[v] = nbv[f][v];
-        } else if (kind == kLinkWall) {
-            const DigGroup& gr = g.groups[idx];
-            far[0] = pc[0];
-            far[1] = gr.u[0]; far[2] = gr.u[1]; far[3] = gr.u[2];
-            far[4] = gr.T;
-        } else {
-            continue;
-        }
-        const double* dx = g.fdx + 12 * (size_t)c + 3 * f;
-        const double d0 = dx[0], d1 = dx[1], d2 = dx[2];
-        const double wgt = 1.0 / (d0 * d0 + d1 * d1 + d2 * d2);
-#pragma unroll
-        for (int v = 0; v < kDigNV; ++v) {
-            const double dphi = far[v] - pc[v];
-            b[v][0] += wgt * d0 * dphi;
-            b[v][1] += wgt * d1 * dphi;
-            b[v][2] += wgt * d2 * dphi;
-        }
-    }
+            for (int i = 0; i < 3; ++i) b[v][i] += __shfl(tb[v][i], q0 + k, 64);
+    if (!live) return;
     const double* L = g.lsq + 9 * (size_t)c;
     double* o = grad + 15 * (size_t)c;
 #pragma unroll
     for (int v = 0; v < kDigNV; ++v)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) o[3 * v + i] = L[3 * i] * b[v][0] + L[3 * i + 1] * b[v][1] + L[3 * i + 2] * b[v][2];
+        for (int i = 0; i < 3; ++i)
+            if ((3 * v + i) % 4 == f) o[3 * v + i] = L[3 * i] * b[v][0] + L[3 * i + 1] * b[v][1] + L[3 * i + 2] * b[v][2];
 }
 
 // HoT = (sigma, q)_sampled - (sigma, q)_NSF at the sampled state
@@ -474,112 +478,127 @@ __global__ void k_dig_copy(const double* src, double* dst, int64_t n) {
 // ---------------------------------------------------------------------------
 // finite-volume residual: R_c = sum_f (F_inviscid + F_viscous).n A_f
 // ---------------------------------------------------------------------------
+// One lane per (cell, face), four consecutive lanes per cell: each lane
+// computes its face's flux; the cell's sums are then formed from the four
+// lanes' terms in face order (the order of a loop over the faces), so that
+// four times as many lanes keep the gathered neighbour loads in flight.
 __global__ __launch_bounds__(kDigThreads) void k_dig_residual(DigGeom g, const double* prim, const double* hotf,
                                                               const double* grad, double* Rs, DigWork w, int first,
                                                               double cfl) {
     if (stopped(w.ctl)) return;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    double r2 = 0.0, dtc = __builtin_inf();
-    if (c < g.nt && !idle_cell(g, c)) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)(t >> 2), f = (int)(t & 3);
+    const bool live = c < g.nt && !idle_cell(g, c);
+    double FA[kDigNV] = {0, 0, 0, 0, 0}, SA = 0.0;
+    if (live) {
         double Pc[kDigNV], gc[15];
 #pragma unroll
         for (int v = 0; v < kDigNV; ++v) Pc[v] = prim[kDigNV * (size_t)c + v];
 #pragma unroll
         for (int k = 0; k < 15; ++k) gc[k] = grad[15 * (size_t)c + k];
         const double xc[3] = {g.cen[3 * (size_t)c], g.cen[3 * (size_t)c + 1], g.cen[3 * (size_t)c + 2]};
-        double Rc[kDigNV] = {0, 0, 0, 0, 0};
-        double sp = 0.0;
-        const int4 lk = *reinterpret_cast<const int4*>(g.flink + 4 * (size_t)c);
-        for (int f = 0; f < 4; ++f) {
-            const int link = f == 0 ? lk.x : f == 1 ? lk.y : f == 2 ? lk.z : lk.w;
-            const int kind = link & 7, idx = link >> 3;
-            const bool inner = kind == kLinkInterior || kind == kLinkPeriodic;
-            // the neighbour's state and gradients are requested with the
-            // face's geometry (a face without a neighbour cell reads its own
-            // cell's, unused)
-            const size_t nb = inner ? (size_t)idx : (size_t)c;
-            double Pn[kDigNV], gn[15];
+        const int link = g.flink[4 * (size_t)c + f];
+        const int kind = link & 7, idx = link >> 3;
+        const bool inner = kind == kLinkInterior || kind == kLinkPeriodic;
+        // the neighbour's state and gradients are requested with the face's
+        // geometry (a face without a neighbour cell reads its own cell's,
+        // unused)
+        const size_t nb = inner ? (size_t)idx : (size_t)c;
+        double Pn[kDigNV], gn[15];
 #pragma unroll
-            for (int v = 0; v < kDigNV; ++v) Pn[v] = prim[kDigNV * nb + v];
+        for (int v = 0; v < kDigNV; ++v) Pn[v] = prim[kDigNV * nb + v];
 #pragma unroll
-            for (int k = 0; k < 15; ++k) gn[k] = grad[15 * nb + k];
-            const size_t fo = 12 * (size_t)c + 3 * f;
-            const double n[3] = {g.fnu[fo], g.fnu[fo + 1], g.fnu[fo + 2]};
-            const double dx[3] = {g.fdx[fo], g.fdx[fo + 1], g.fdx[fo + 2]};
-            const double A = g.farea[4 * (size_t)c + f];
-            double F[kDigNV] = {0, 0, 0, 0, 0};
-            double lam = 0.0, lamv = 0.0;
-            if (inner) {
-                const double xf[3] = {g.fcen[fo], g.fcen[fo + 1], g.fcen[fo + 2]};
-                double rc[3], rn[3];
+        for (int k = 0; k < 15; ++k) gn[k] = grad[15 * nb + k];
+        const size_t fo = 12 * (size_t)c + 3 * f;
+        const double n[3] = {g.fnu[fo], g.fnu[fo + 1], g.fnu[fo + 2]};
+        const double dx[3] = {g.fdx[fo], g.fdx[fo + 1], g.fdx[fo + 2]};
+        const double A = g.farea[4 * (size_t)c + f];
+        double F[kDigNV] = {0, 0, 0, 0, 0};
+        double lam = 0.0, lamv = 0.0;
+        if (inner) {
+            const double xf[3] = {g.fcen[fo], g.fcen[fo + 1], g.fcen[fo + 2]};
+            double rc[3], rn[3];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    rc[i] = xf[i] - xc[i];
-                    rn[i] = xf[i] - (xc[i] + dx[i]);
-                }
-                double PL[kDigNV], PR[kDigNV];
+            for (int i = 0; i < 3; ++i) {
+                rc[i] = xf[i] - xc[i];
+                rn[i] = xf[i] - (xc[i] + dx[i]);
+            }
+            double PL[kDigNV], PR[kDigNV];
+#pragma unroll
+            for (int v = 0; v < kDigNV; ++v) {
+                PL[v] = Pc[v] + (gc[3 * v] * rc[0] + gc[3 * v + 1] * rc[1] + gc[3 * v + 2] * rc[2]);
+                PR[v] = Pn[v] + (gn[3 * v] * rn[0] + gn[3 * v + 1] * rn[1] + gn[3 * v + 2] * rn[2]);
+            }
+            if (!(PL[0] > 0 && PL[4] > 0 && PR[0] > 0 && PR[4] > 0)) {
 #pragma unroll
                 for (int v = 0; v < kDigNV; ++v) {
-                    PL[v] = Pc[v] + (gc[3 * v] * rc[0] + gc[3 * v + 1] * rc[1] + gc[3 * v + 2] * rc[2]);
-                    PR[v] = Pn[v] + (gn[3 * v] * rn[0] + gn[3 * v + 1] * rn[1] + gn[3 * v + 2] * rn[2]);
+                    PL[v] = Pc[v];
+                    PR[v] = Pn[v];
                 }
-                if (!(PL[0] > 0 && PL[4] > 0 && PR[0] > 0 && PR[4] > 0)) {
+            }
+            central_flux(g, PL, PR, n, F, lam);
+            const double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
+            const double dl = sqrt(d2);
+            double gavg[15];
 #pragma unroll
-                    for (int v = 0; v < kDigNV; ++v) {
-                        PL[v] = Pc[v];
-                        PR[v] = Pn[v];
-                    }
-                }
-                central_flux(g, PL, PR, n, F, lam);
+            for (int k = 3; k < 15; ++k) gavg[k] = 0.5 * (gc[k] + gn[k]);
+            double gu[9], gT[3];
+            face_gradients(gavg, Pn, Pc, dx, dl, gu, gT);
+            const double Tf = 0.5 * (Pc[4] + Pn[4]);
+            const double rf = 0.5 * (Pc[0] + Pn[0]);
+            double vis[9];
+            nsf_local(g, Tf, gu, gT, vis);
+            const double* hf = hotf + 36 * (size_t)c + 9 * f;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) vis[k] += hf[k];
+            const double uf[3] = {0.5 * (Pc[1] + Pn[1]), 0.5 * (Pc[2] + Pn[2]), 0.5 * (Pc[3] + Pn[3])};
+            add_viscous(vis, n, uf, F);
+            lamv = viscous_rate(g, Tf, rf, dl);
+        } else if (kind == kLinkWall || kind == kLinkSpecular) {
+            const double p = Pc[0] * g.R * Pc[4];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) F[1 + i] = p * n[i];
+            lam = acoustic_speed(g, Pc, n);
+            if (kind == kLinkWall) {
+                const DigGroup& gr = g.groups[idx];
                 const double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
                 const double dl = sqrt(d2);
-                double gavg[15];
-#pragma unroll
-                for (int k = 3; k < 15; ++k) gavg[k] = 0.5 * (gc[k] + gn[k]);
+                const double wallv[kDigNV] = {Pc[0], gr.u[0], gr.u[1], gr.u[2], gr.T};
                 double gu[9], gT[3];
-                face_gradients(gavg, Pn, Pc, dx, dl, gu, gT);
-                const double Tf = 0.5 * (Pc[4] + Pn[4]);
-                const double rf = 0.5 * (Pc[0] + Pn[0]);
+                face_gradients(gc, wallv, Pc, dx, dl, gu, gT);
                 double vis[9];
-                nsf_local(g, Tf, gu, gT, vis);
+                nsf_local(g, gr.T, gu, gT, vis);
                 const double* hf = hotf + 36 * (size_t)c + 9 * f;
 #pragma unroll
                 for (int k = 0; k < 9; ++k) vis[k] += hf[k];
-                const double uf[3] = {0.5 * (Pc[1] + Pn[1]), 0.5 * (Pc[2] + Pn[2]), 0.5 * (Pc[3] + Pn[3])};
-                add_viscous(vis, n, uf, F);
-                lamv = viscous_rate(g, Tf, rf, dl);
-            } else if (kind == kLinkWall || kind == kLinkSpecular) {
-                const double p = Pc[0] * g.R * Pc[4];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) F[1 + i] = p * n[i];
-                lam = acoustic_speed(g, Pc, n);
-                if (kind == kLinkWall) {
-                    const DigGroup& gr = g.groups[idx];
-                    const double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
-                    const double dl = sqrt(d2);
-                    const double wallv[kDigNV] = {Pc[0], gr.u[0], gr.u[1], gr.u[2], gr.T};
-                    double gu[9], gT[3];
-                    face_gradients(gc, wallv, Pc, dx, dl, gu, gT);
-                    double vis[9];
-                    nsf_local(g, gr.T, gu, gT, vis);
-                    const double* hf = hotf + 36 * (size_t)c + 9 * f;
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) vis[k] += hf[k];
-                    add_viscous(vis, n, gr.u, F);
-                    lamv = viscous_rate(g, gr.T, Pc[0], dl);
-                }
-            } else if (kind == kLinkInflow) {
-                const DigGroup& gr = g.groups[idx];
-                const double PR[kDigNV] = {gr.rho, gr.u[0], gr.u[1], gr.u[2], gr.T};
-                central_flux(g, Pc, PR, n, F, lam);
-            } else {
-                flux_of(g, Pc, n, F);
-                lam = acoustic_speed(g, Pc, n);
+                add_viscous(vis, n, gr.u, F);
+                lamv = viscous_rate(g, gr.T, Pc[0], dl);
             }
-#pragma unroll
-            for (int v = 0; v < kDigNV; ++v) Rc[v] += F[v] * A;
-            sp += (lam + lamv) * A;
+        } else if (kind == kLinkInflow) {
+            const DigGroup& gr = g.groups[idx];
+            const double PR[kDigNV] = {gr.rho, gr.u[0], gr.u[1], gr.u[2], gr.T};
+            central_flux(g, Pc, PR, n, F, lam);
+        } else {
+            flux_of(g, Pc, n, F);
+            lam = acoustic_speed(g, Pc, n);
         }
+#pragma unroll
+        for (int v = 0; v < kDigNV; ++v) FA[v] = F[v] * A;
+        SA = (lam + lamv) * A;
+    }
+    // the cell's sums over its four lanes, in face order (every lane of the
+    // wave takes part in the exchange)
+    const int q0 = (int)(threadIdx.x & 63) & ~3;
+    double Rc[kDigNV] = {0, 0, 0, 0, 0};
+    double sp = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int v = 0; v < kDigNV; ++v) Rc[v] += __shfl(FA[v], q0 + k, 64);
+        sp += __shfl(SA, q0 + k, 64);
+    }
+    double r2 = 0.0, dtc = __builtin_inf();
+    if (live && f == 0) {
 #pragma unroll
         for (int v = 0; v < kDigNV; ++v) Rs[kDigNV * (size_t)c + v] = Rc[v];
         if (first) {
@@ -959,7 +978,7 @@ void launch_dig_kn(hipStream_t s, const DigGeom& g, DigWork w, double kn_ref, do
 }
 
 void launch_dig_gradients(hipStream_t s, const DigGeom& g, const double* prim, double* grad, const DigCtl* ctl) {
-    hipLaunchKernelGGL(k_dig_grad, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, prim, grad, ctl);
+    hipLaunchKernelGGL(k_dig_grad, cells_grid(4 * (int64_t)g.nt), dim3(kDigThreads), 0, s, g, prim, grad, ctl);
 }
 
 void launch_dig_hot(hipStream_t s, const DigGeom& g, DigWork w) {
@@ -987,7 +1006,7 @@ void launch_dig_copy(hipStream_t s, const double* src, double* dst, int64_t n) {
 
 void launch_dig_residual(hipStream_t s, const DigGeom& g, const double* prim, const double* hotf, const double* grad,
                          double* Rs, DigWork w, int first, double cfl) {
-    hipLaunchKernelGGL(k_dig_residual, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, prim, hotf, grad, Rs, w, first,
+    hipLaunchKernelGGL(k_dig_residual, cells_grid(4 * (int64_t)g.nt), dim3(kDigThreads), 0, s, g, prim, hotf, grad, Rs, w, first,
                        cfl);
 }
 
@@ -1001,13 +1020,13 @@ void launch_dig_face_hot(hipStream_t s, const DigGeom& g, const double* prim, co
 // convergence test and the step size come from the first stage.
 void launch_dig_iteration(hipStream_t s, const DigGeom& g, DigWork w, double cfl, double eps_m, int global_dt,
                           int it) {
-    const dim3 gr = cells_grid(g.nt), bl(kDigThreads);
-    const int nblk = (int)gr.x;
+    const dim3 gr = cells_grid(g.nt), grq = cells_grid(4 * (int64_t)g.nt), bl(kDigThreads);
+    const int nblk = (int)grq.x;  // partials of the residual kernel
     const double alpha[3] = {1.0 / 3.0, 0.5, 1.0};
     hipLaunchKernelGGL(k_dig_save, gr, bl, 0, s, g, w);
     for (int k = 0; k < 3; ++k) {
-        hipLaunchKernelGGL(k_dig_grad, gr, bl, 0, s, g, (const double*)w.stage, w.grad, (const DigCtl*)w.ctl);
-        hipLaunchKernelGGL(k_dig_residual, gr, bl, 0, s, g, (const double*)w.stage, (const double*)w.hotf,
+        hipLaunchKernelGGL(k_dig_grad, grq, bl, 0, s, g, (const double*)w.stage, w.grad, (const DigCtl*)w.ctl);
+        hipLaunchKernelGGL(k_dig_residual, grq, bl, 0, s, g, (const double*)w.stage, (const double*)w.hotf,
                            (const double*)w.grad, w.Rs, w, k == 0 ? 1 : 0, cfl);
         if (k == 0) hipLaunchKernelGGL(k_dig_check, dim3(1), bl, 0, s, w, nblk, it, eps_m);
         hipLaunchKernelGGL(k_dig_update, gr, bl, 0, s, g, w, alpha[k], global_dt);

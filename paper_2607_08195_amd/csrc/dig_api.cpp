@@ -164,7 +164,7 @@ dsmc_status ensure(dsmc_ctx c) {
          alloc_n(c, w.navail, nt) && alloc_n(c, w.nprim, 5 * (size_t)nt) && alloc_n(c, w.nhot, 9 * (size_t)nt) &&
          alloc_n(c, w.state, nt) && alloc_n(c, w.mprev, 5 * (size_t)nt) && alloc_n(c, w.Rs, 5 * (size_t)nt) &&
          alloc_n(c, w.dt, nt) && alloc_n(c, w.U0, 5 * (size_t)nt) && alloc_n(c, w.stage, 5 * (size_t)nt) &&
-         alloc_n(c, w.partial, 2 * (size_t)d->nblk) && alloc_n(c, w.ctl, 1) && alloc_n(c, w.fb_cnt, nt) &&
+         alloc_n(c, w.partial, 8 * (size_t)d->nblk) && alloc_n(c, w.ctl, 1) && alloc_n(c, w.fb_cnt, nt) &&
          alloc_n(c, w.fb_off, nt + 1) && alloc_n(c, w.fb_tgt, nt) && alloc_n(c, w.cx, 13 * (size_t)nt) &&
          alloc_n(c, w.ct, 9 * (size_t)nt) && alloc_n(c, w.cs, 9 * (size_t)nt) && alloc_n(c, w.cy, 9 * (size_t)nt) &&
          alloc_n(c, w.cvalid, nt);
