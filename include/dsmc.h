@@ -148,6 +148,27 @@ dsmc_status dsmc_sample(dsmc_ctx ctx, int32_t which, double* out, int32_t out_on
  * *n_samples.  Synchronises. */
 dsmc_status dsmc_get_sums(dsmc_ctx ctx, int32_t which, double* out, int64_t* n_samples);
 
+/* Surface sampling (the wall pressure, shear stress and heat flux the
+ * paper compares on the sphere, section 5): every interaction of a particle
+ * with a diffuse or specular boundary face on a step after n_ss adds, for
+ * that face, the velocity change v_in - v_out, the kinetic-energy change
+ * (|v_in|^2 - |v_out|^2) / 2 (per unit mass) and one hit.  on = 1 clears
+ * the sums and starts sampling, 0 stops it (sums kept); off by default.
+ * Synchronises.  The sums are added with device atomics, so their rounding
+ * depends on the order of the hits (the hit counts are exact). */
+dsmc_status dsmc_surface_sampling(dsmc_ctx ctx, int32_t on);
+
+/* Surface sums and fields of the boundary faces (input order) over the
+ * *n_steps sampled steps (steps after n_ss inside the on window):
+ * sums[n_bfaces][5] = sum of v_in - v_out (3), of the energy change, hits;
+ * fields[n_bfaces][6] = number flux F_N hits / (A t), pressure
+ * m F_N (S.n) / (A t), shear stress m F_N (S - (S.n) n) / (A t) (3),
+ * heat flux m F_N E / (A t), with S the velocity-change sum, E the energy
+ * sum, n the unit normal out of the gas, A the face area, t = n_steps dt
+ * (F_N and dt of the face's case in a batch; zeros without sampled steps).
+ * Either pointer may be NULL.  Synchronises. */
+dsmc_status dsmc_get_surface(dsmc_ctx ctx, double* sums, double* fields, int64_t* n_steps);
+
 /* Particle state.  dsmc_get_state fills n_particles, step and next_pid; the
  * arrays (host, may be NULL) receive the particles in (cell, pid) order:
  * x[n][3], v[n][3] (FP64), cell[n], pid[n], and smax[n_tets] the per-cell

@@ -39,6 +39,9 @@ def _load():
     lib.oracle_get_particles.argtypes = [P, P, P, P, P]
     lib.oracle_set_particles.argtypes = [P, i64, P, P, P, P, u32, u32]
     lib.oracle_get_smax.argtypes = [P, P]
+    lib.oracle_surface_sampling.argtypes = [P, C.c_int]
+    lib.oracle_get_surface.argtypes = [P, P]
+    lib.oracle_get_surface.restype = i64
     lib.oracle_set_smax.argtypes = [P, P]
     lib.oracle_step_index.restype = u32
     lib.oracle_step_index.argtypes = [P]
@@ -135,6 +138,7 @@ class Oracle:
         gn = arr([b.n for b in bcs], np.float64)
         gs = arr([b.shift for b in bcs], np.float64)
         self.nt = int(tets.shape[0])
+        self.nb = int(bf.shape[0])
         self.h = lib.oracle_create(
             int(xyz.shape[0]), _p(xyz), self.nt, _p(tets), int(bf.shape[0]), _p(bf), _p(bg), _p(bp),
             len(bcs), _p(gk), _p(gT), _p(gu), _p(gn), _p(gs),
@@ -178,6 +182,16 @@ class Oracle:
                                           step, next_pid)
         if r != 0:
             raise ValueError(self.lib.oracle_last_error().decode())
+
+    def surface_sampling(self, on=True):
+        self.lib.oracle_surface_sampling(self.h, 1 if on else 0)
+
+    def surface(self):
+        """Surface sums [n_bfaces][5] (sum of v_in - v_out, of
+        (|v_in|^2 - |v_out|^2)/2, hits) and the number of sampled steps."""
+        o = np.zeros((self.nb, 5))
+        n = self.lib.oracle_get_surface(self.h, _p(o))
+        return o, int(n)
 
     def smax(self):
         o = np.zeros(self.nt)

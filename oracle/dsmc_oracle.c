@@ -124,7 +124,7 @@ void oracle_destroy(osim* s) {
                     s->g_shift, s->in_mean, s->in_a, s->in_beta, s->in_sig, s->in_ut1, s->in_ut2,
                     s->x, s->v, s->cell, s->pid, s->smax, s->ncand, s->nacc, s->start, s->acc,
                     s->ewma, s->ewma_m, s->local_acc, s->inst, s->cen, s->fcen, s->fnu, s->farea,
-                    s->lsq, s->mprev};
+                    s->lsq, s->mprev, s->surf};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i) free(ptrs[i]);
     free(s);
 }
@@ -460,6 +460,22 @@ int oracle_init_fill(osim* s, double n0, double T0, const double* u0) {
 /* ------------------------------------------------------------------ */
 /* Move: face-to-face tracking with boundary interactions               */
 /* ------------------------------------------------------------------ */
+/* Surface sampling: one wall interaction at boundary face bf that turned
+ * velocity a into b adds the velocity change a - b (the momentum given to
+ * the wall per unit mass), the kinetic-energy change (|a|^2 - |b|^2)/2 and
+ * one hit to the face's sums, on the steps after n_ss while sampling is on
+ * (the stress and heat flux a surface receives: section 5, sphere surface
+ * pressure, shear stress and heat flux). */
+static void surface_hit(osim* s, int bf, uint32_t step, const double* a, const double* b) {
+    if (!s->surf_on || (int64_t)step <= (int64_t)s->n_ss) return;
+    double* q = s->surf + 5 * (size_t)bf;
+    q[0] += a[0] - b[0];
+    q[1] += a[1] - b[1];
+    q[2] += a[2] - b[2];
+    q[3] += 0.5 * ((a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) - (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]));
+    q[4] += 1.0;
+}
+
 /* returns 0 alive, 1 removed through an open boundary, 2 lost */
 static int trace(osim* s, double* x, double* v, int* cellp, int entry, uint32_t pid, uint32_t step,
                  double t) {
@@ -512,10 +528,12 @@ static int trace(osim* s, double* x, double* v, int* cellp, int entry, uint32_t 
             const double* t1 = s->bf_t1 + 3 * bf;
             const double* t2 = s->bf_t2 + 3 * bf;
             const double* uw = s->g_u + 3 * g;
+            const double vin[3] = {v[0], v[1], v[2]};
             for (int i = 0; i < 3; ++i) {
                 double tang = sw * (g1 * t1[i] + g2 * t2[i]);
                 v[i] = to_store(s, (vn * nin[i] + tang) + uw[i]);
             }
+            surface_hit(s, bf, step, vin, v);
             ++hits;
             s->walls++;
             entry = fb;
@@ -526,7 +544,9 @@ static int trace(osim* s, double* x, double* v, int* cellp, int entry, uint32_t 
             double vn = n[0] * v[0] + n[1] * v[1] + n[2] * v[2];
             double nn = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
             double f2 = 2.0 * (vn / nn);
+            const double vin[3] = {v[0], v[1], v[2]};
             for (int i = 0; i < 3; ++i) v[i] = to_store(s, v[i] - f2 * n[i]);
+            surface_hit(s, bf, step, vin, v);
             s->walls++;
             entry = fb;
             break;
@@ -781,6 +801,29 @@ int oracle_set_particles(osim* s, int64_t np, const double* x, const double* v, 
 void oracle_get_smax(const osim* s, double* out) { memcpy(out, s->smax, sizeof(double) * (size_t)s->nt); }
 void oracle_set_smax(osim* s, const double* in) { memcpy(s->smax, in, sizeof(double) * (size_t)s->nt); }
 uint32_t oracle_step_index(const osim* s) { return s->step; }
+
+int oracle_surface_sampling(osim* s, int on) {
+    if (on) {
+        if (!s->surf) s->surf = (double*)malloc(sizeof(double) * 5 * (size_t)(s->nb ? s->nb : 1));
+        if (!s->surf) { set_err("out of memory"); return -1; }
+        memset(s->surf, 0, sizeof(double) * 5 * (size_t)(s->nb ? s->nb : 1));
+        s->surf_on = 1;
+        s->surf_from = s->step;
+        s->surf_to = -1;
+    } else if (s->surf_on) {
+        s->surf_on = 0;
+        s->surf_to = s->step;
+    }
+    return 0;
+}
+
+int64_t oracle_get_surface(const osim* s, double* sums) {
+    if (!s->surf) return 0;
+    if (sums) memcpy(sums, s->surf, sizeof(double) * 5 * (size_t)s->nb);
+    int64_t end = s->surf_to < 0 ? (int64_t)s->step : s->surf_to;
+    int64_t from = s->surf_from > s->n_ss ? s->surf_from : s->n_ss;
+    return end > from ? end - from : 0;
+}
 uint32_t oracle_next_pid(const osim* s) { return s->next_pid; }
 
 void oracle_get_pair_counts(const osim* s, int* ncand, int* nacc) {

@@ -57,6 +57,14 @@ int oracle_set_particles(osim*, int64_t np, const double* x, const double* v,
 void oracle_get_smax(const osim*, double* out);
 void oracle_set_smax(osim*, const double* in);
 uint32_t oracle_step_index(const osim*);
+
+/* Surface sampling of the wall interactions (diffuse and specular faces):
+ * on = 1 clears the sums and starts, 0 stops.  oracle_get_surface copies
+ * the sums [nb][5] (boundary faces in input order: sum of v_in - v_out (3),
+ * of (|v_in|^2 - |v_out|^2)/2, hits) and returns the number of sampled
+ * steps (steps after n_ss inside the on window). */
+int oracle_surface_sampling(osim*, int on);
+int64_t oracle_get_surface(const osim*, double* sums);
 uint32_t oracle_next_pid(const osim*);
 
 /* Per-cell candidate / accepted pair counts of the last collide stage. */

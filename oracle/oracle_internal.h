@@ -52,6 +52,11 @@ struct osim {
     double* inst;
     /* counters */
     int64_t hops, walls, injected, removed, lost;
+    /* surface sampling: [nb][5] sums of (v_in - v_out), (|v_in|^2 - |v_out|^2)/2
+     * and hits over the sampled steps while on; window start and end steps */
+    double* surf;
+    int surf_on;
+    int64_t surf_from, surf_to;
     /* reference state of the run (initial fill) and DIG coupling state */
     double ref_n, ref_T, ref_u[3];
     double* cen;    /* [nt][3] cell centroids */

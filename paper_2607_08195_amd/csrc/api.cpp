@@ -240,7 +240,9 @@ void read_tuning(dsmc_ctx c) {
 }
 
 
-int tuning_sig(dsmc_ctx c) { return c->move_variant | (c->collide_variant << 8) | (c->sort_variant << 12); }
+int tuning_sig(dsmc_ctx c) {
+    return c->move_variant | (c->collide_variant << 8) | (c->sort_variant << 12) | (c->mesh.surf ? 1 << 16 : 0);
+}
 
 void drop_graph(dsmc_ctx_s::Graph& g) {
     if (g.exec) hipGraphExecDestroy(g.exec);
@@ -524,6 +526,9 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     c->mesh.bf_frame = c->d_bf_frame;
     c->mesh.groups = c->d_groups;
     c->mesh.mass = sp->mass;
+    c->mesh.nb = nb;
+    c->mesh.n_ss = run->n_ss;
+    c->mesh.surf = nullptr;
     c->inflow.n = nin;
     c->inflow.bface = d_in_bf;
     c->inflow.tcode = d_in_tc;
@@ -789,6 +794,78 @@ dsmc_status dsmc_sample(dsmc_ctx c, int32_t which, double* out, int32_t out_on_d
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     dev_free(c, tmp);
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_surface_sampling(dsmc_ctx c, int32_t on) {
+    if (!c) return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
+    Scalars sc;
+    dsmc_status st = sync_scalars(c, &sc);
+    if (st != DSMC_OK) return st;
+    if (on) {
+        if (!c->d_surf && !alloc_n(c, c->d_surf, 5 * (size_t)c->nb + 5))
+            return fail(c, DSMC_E_OOM, "device allocation failed");
+        launch_fill_f64(c->stream, c->d_surf, 0.0, 5 * (int64_t)c->nb + 5);
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        c->mesh.surf = c->d_surf;
+        c->surf_from = sc.step;
+        c->surf_to = -1;
+    } else if (c->mesh.surf) {
+        c->mesh.surf = nullptr;
+        c->surf_to = sc.step;
+    }
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_get_surface(dsmc_ctx c, double* sums, double* fields, int64_t* n_steps) {
+    if (!c) return fail(c, DSMC_E_INVALID, "bad arguments");
+    Scalars sc;
+    dsmc_status st = sync_scalars(c, &sc);
+    if (st != DSMC_OK) return st;
+    const int nb = c->nb;
+    std::vector<double> h(5 * (size_t)nb, 0.0);
+    if (c->d_surf) HIP_TRY(c, hipMemcpy(h.data(), c->d_surf, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+    const int64_t end = c->surf_to < 0 ? (int64_t)sc.step : c->surf_to;
+    const int64_t from = std::max<int64_t>(c->surf_from, c->n_ss);
+    const int64_t ns = c->d_surf && end > from ? end - from : 0;
+    if (n_steps) *n_steps = ns;
+    if (sums)
+        for (int b = 0; b < nb; ++b)
+            for (int k = 0; k < 5; ++k) sums[5 * (size_t)b + k] = h[(size_t)k * nb + b];
+    if (fields) {
+        // per face: F_N and dt of its case
+        std::vector<CaseDev> cases(std::max(1, c->n_cases));
+        if (c->n_cases)
+            HIP_TRY(c, hipMemcpy(cases.data(), c->d_cases, sizeof(CaseDev) * c->n_cases, hipMemcpyDeviceToHost));
+        for (int b = 0; b < nb; ++b) {
+            double FN = c->FN, dt = c->dt;
+            if (c->n_cases) {
+                const int o = c->hm.orig[c->hm.bf_tet[b]];
+                const int k = (int)(std::upper_bound(c->case_cell0.begin(), c->case_cell0.end(), o) -
+                                    c->case_cell0.begin()) - 1;
+                FN = cases[k].FN;
+                dt = cases[k].dt;
+            }
+            double* f = fields + 6 * (size_t)b;
+            const double ta = c->hm.bf_area[b] * ((double)ns * dt);
+            if (!(ta > 0)) {
+                for (int k = 0; k < 6; ++k) f[k] = 0.0;
+                continue;
+            }
+            // outward unit normal (into the wall) = minus the inward one of the face frame
+            const double* fr = &c->hm.bf_frame[9 * (size_t)b];
+            const double n[3] = {-fr[0], -fr[1], -fr[2]};
+            const double s = c->mass * FN / ta;
+            const double d[3] = {h[b], h[(size_t)nb + b], h[2 * (size_t)nb + b]};
+            const double dn = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
+            f[0] = FN * h[4 * (size_t)nb + b] / ta;
+            f[1] = s * dn;
+            for (int i = 0; i < 3; ++i) f[2 + i] = s * (d[i] - dn * n[i]);
+            f[5] = s * h[3 * (size_t)nb + b];
+        }
+    }
     return DSMC_OK;
 }
 

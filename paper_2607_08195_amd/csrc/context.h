@@ -55,6 +55,10 @@ struct dsmc_ctx_s {
     int32_t* d_bf_pcode = nullptr;
     double* d_bf_frame = nullptr;
     dsmcx::GroupDev* d_groups = nullptr;
+    // surface sampling: [5][nb] sums (mesh.surf points here while on) and the
+    // step window (to < 0: still running)
+    double* d_surf = nullptr;
+    int64_t surf_from = 0, surf_to = -1;
     int4* d_tv = nullptr;
     double* d_xyz = nullptr;
     int32_t* d_orig = nullptr;      // internal cell -> caller's cell id

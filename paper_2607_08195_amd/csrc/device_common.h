@@ -153,7 +153,26 @@ struct MeshDev {
     double mass;
     const int32_t* cell_case;  // [nt] case of each cell (batch), or null
     const CaseDev* cases;
+    int nb;                    // boundary faces
+    int n_ss;                  // surface sums are taken on steps after n_ss
+    double* surf;              // [5][nb] surface sums, or null (surface sampling off)
 };
+
+// Surface sampling at a wall interaction of boundary face bf that turned
+// velocity a into b: the velocity change a - b (momentum given to the wall
+// per unit mass), the energy change (|a|^2 - |b|^2) / 2 and the hit, added to
+// the face's sums on sampled steps.
+__device__ __forceinline__ void surface_hit(const MeshDev& m, int bf, uint32_t step, double a0, double a1,
+                                            double a2, double b0, double b1, double b2) {
+    if (!m.surf || (int64_t)step <= (int64_t)m.n_ss) return;
+    double* s = m.surf + bf;
+    const size_t nb = (size_t)m.nb;
+    unsafeAtomicAdd(s, a0 - b0);
+    unsafeAtomicAdd(s + nb, a1 - b1);
+    unsafeAtomicAdd(s + 2 * nb, a2 - b2);
+    unsafeAtomicAdd(s + 3 * nb, 0.5 * ((a0 * a0 + a1 * a1 + a2 * a2) - (b0 * b0 + b1 * b1 + b2 * b2)));
+    unsafeAtomicAdd(s + 4 * nb, 1.0);
+}
 
 // Generator key and time step of the case that owns `cell` (batch mode).
 __device__ __forceinline__ void case_params(const int32_t* cell_case, const CaseDev* cases, int cell, RngKey& key,
@@ -234,9 +253,11 @@ __device__ __forceinline__ TraceOut trace(const MeshDev& m, double& x0, double& 
             double g1, g2;
             box_muller(ub, uc, g1, g2);
             const double* fr = m.bf_frame + 9 * (size_t)bf;
+            const double a0 = v0, a1 = v1, a2 = v2;
             v0 = round_store<VT>((vn * fr[0] + g.sw * (g1 * fr[3] + g2 * fr[6])) + g.u[0]);
             v1 = round_store<VT>((vn * fr[1] + g.sw * (g1 * fr[4] + g2 * fr[7])) + g.u[1]);
             v2 = round_store<VT>((vn * fr[2] + g.sw * (g1 * fr[5] + g2 * fr[8])) + g.u[2]);
+            surface_hit(m, bf, step, a0, a1, a2, v0, v1, v2);
             ++hits;
             ++out.walls;
             entry = fb;
@@ -245,9 +266,11 @@ __device__ __forceinline__ TraceOut trace(const MeshDev& m, double& x0, double& 
             const double vn = pl.x * v0 + pl.y * v1 + pl.z * v2;
             const double nn = pl.x * pl.x + pl.y * pl.y + pl.z * pl.z;
             const double f2 = 2.0 * (vn / nn);
+            const double a0 = v0, a1 = v1, a2 = v2;
             v0 = round_store<VT>(v0 - f2 * pl.x);
             v1 = round_store<VT>(v1 - f2 * pl.y);
             v2 = round_store<VT>(v2 - f2 * pl.z);
+            surface_hit(m, bf, step, a0, a1, a2, v0, v1, v2);
             ++out.walls;
             entry = fb;
         } else if (g.kind == kBcPeriodic) {
@@ -308,9 +331,11 @@ __device__ __forceinline__ void diffuse_reemit(const MeshDev& m, Walker& w, int 
     double g1, g2;
     box_muller(ub, uc, g1, g2);
     const double* fr = m.bf_frame + 9 * (size_t)bf;
+    const double a0 = w.v0, a1 = w.v1, a2 = w.v2;
     w.v0 = round_store<VT>((vn * fr[0] + g.sw * (g1 * fr[3] + g2 * fr[6])) + g.u[0]);
     w.v1 = round_store<VT>((vn * fr[1] + g.sw * (g1 * fr[4] + g2 * fr[7])) + g.u[1]);
     w.v2 = round_store<VT>((vn * fr[2] + g.sw * (g1 * fr[5] + g2 * fr[8])) + g.u[2]);
+    surface_hit(m, bf, step, a0, a1, a2, w.v0, w.v1, w.v2);
     ++w.hits;
     ++w.walls;
     w.entry = fb;
@@ -336,7 +361,9 @@ __device__ __forceinline__ void exit_candidate3(const double4& pl, int f, const 
 // entered its cell through a face (entry >= 0, as after any crossing or
 // boundary event): it tests (and loads the planes of) the other three faces
 // only, with the same result.
-template <class VT, bool DEFER = false, bool FACE3 = false>
+// SURF = false leaves out the surface sampling of specular faces (for a
+// launch made while sampling is off: fewer live registers in the hop loop).
+template <class VT, bool DEFER = false, bool FACE3 = false, bool SURF = true>
 __device__ __forceinline__ int hop_once(const MeshDev& m, Walker& w, uint32_t step, RngKey key) {
     const int base = 4 * w.c;
     const int4 nb4 = *reinterpret_cast<const int4*>(m.nbr + base);
@@ -395,9 +422,11 @@ __device__ __forceinline__ int hop_once(const MeshDev& m, Walker& w, uint32_t st
         const double vn = pl.x * w.v0 + pl.y * w.v1 + pl.z * w.v2;
         const double nn = pl.x * pl.x + pl.y * pl.y + pl.z * pl.z;
         const double f2 = 2.0 * (vn / nn);
+        const double a0 = w.v0, a1 = w.v1, a2 = w.v2;
         w.v0 = round_store<VT>(w.v0 - f2 * pl.x);
         w.v1 = round_store<VT>(w.v1 - f2 * pl.y);
         w.v2 = round_store<VT>(w.v2 - f2 * pl.z);
+        if (SURF) surface_hit(m, bf, step, a0, a1, a2, w.v0, w.v1, w.v2);
         ++w.walls;
         w.entry = fb;
     } else if (g.kind == kBcPeriodic) {

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 // wave then runs at most CAP iterations instead of the largest hop count of
 // its 64 particles, and the few long tracks finish in k_move_walls on
 // compacted waves.
-template <class VT, int WPE, int CAP, bool FACE3 = false>
+template <class VT, int WPE, int CAP, bool FACE3 = false, bool SURF = true>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_move_defer(
     MeshDev m, PartDev<VT> p, Scalars* sc, int32_t* counts, uint32_t* rank, Counters* ctr, RngKey key,
     double dt, WallQueue q) {
@@ -256,13 +256,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         const uint32_t step = sc->step;
         // the first test (entry face unknown) over all four faces; with
         // FACE3 the later ones over the three faces other than the entry
-        int st = hop_once<VT, true>(m, w, step, kp);
+        int st = hop_once<VT, true, false, SURF>(m, w, step, kp);
         for (int it = 1; st < 0 && (CAP == 0 || it < CAP); ++it)
-            st = FACE3 ? hop_once<VT, true, true>(m, w, step, kp) : hop_once<VT, true>(m, w, step, kp);
+            st = FACE3 ? hop_once<VT, true, true, SURF>(m, w, step, kp) : hop_once<VT, true, false, SURF>(m, w, step, kp);
         p.pos[3 * i] = w.x0; p.pos[3 * i + 1] = w.x1; p.pos[3 * i + 2] = w.x2;
         if (st == kHopWallPending) {
             park = true;
             p.cell[i] = w.c;
+            // the velocity it reaches the wall with (surface sampling reads it)
+            if (w.walls) {
+                p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
+            }
         } else if (CAP > 0 && st < 0) {
             // in flight after CAP tests: the queued time carries a negative
             // sign (a parked particle always has time left, t > 0)
@@ -329,6 +333,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             p.pos[3 * i] = w.x0; p.pos[3 * i + 1] = w.x1; p.pos[3 * i + 2] = w.x2;
             if (park) {
                 p.cell[i] = w.c;
+                if (w.walls) {
+                    p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
+                }
             } else {
                 if (w.walls) {
                     p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
@@ -412,11 +419,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         if (done) {
             sx[wid][j] = w.x0; sy[wid][j] = w.x1; sz[wid][j] = w.x2;
             uint8_t flags = park ? 2 : 0;
+            if (w.walls) {
+                svx[wid][j] = (VT)w.v0; svy[wid][j] = (VT)w.v1; svz[wid][j] = (VT)w.v2;
+                flags |= 1;
+            }
             if (!park) {
-                if (w.walls) {
-                    svx[wid][j] = (VT)w.v0; svy[wid][j] = (VT)w.v1; svz[wid][j] = (VT)w.v2;
-                    flags |= 1;
-                }
                 rem += st == 1;
                 lost += st == 2;
                 hops += w.nhop;
@@ -472,6 +479,10 @@ __device__ __forceinline__ int64_t queue_take(const MeshDev& m, const PartDev<VT
     if (tq < 0) {
         w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
     } else {
+        // surface sampling needs the velocity the particle reached the wall with
+        if (m.surf) {
+            w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
+        }
         const int bf = -1 - m.nbr[4 * w.c + w.entry];
         diffuse_reemit<VT>(m, w, bf, w.entry, step, kp);
     }
@@ -1372,8 +1383,12 @@ void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* 
         break;
     }
     case kMoveFace3:
-        hipLaunchKernelGGL((k_move_defer<VT, 6, 0, true>), dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p,
-                           (Scalars*)sc, counts, rank, ctr, key, dt, wq);
+        if (m.surf)
+            hipLaunchKernelGGL((k_move_defer<VT, 6, 0, true>), dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p,
+                               (Scalars*)sc, counts, rank, ctr, key, dt, wq);
+        else
+            hipLaunchKernelGGL((k_move_defer<VT, 6, 0, true, false>), dim3(grid8(np_bound, 256)), dim3(256), 0, s,
+                               m, p, (Scalars*)sc, counts, rank, ctr, key, dt, wq);
         break;
     case kMoveFace3W8:
         hipLaunchKernelGGL((k_move_defer<VT, 8, 0, true>), dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p,

@@ -161,12 +161,15 @@ _lib.dsmc_mlp_destroy.argtypes = [P]
 _lib.dig_set_closure.argtypes = [ctx_t, P, C.c_double]
 _lib.dig_closure_data.argtypes = [ctx_t, P, P, P]
 _lib.dig_batch_enable.argtypes = [ctx_t, P]
+_lib.dsmc_surface_sampling.argtypes = [ctx_t, C.c_int32]
+_lib.dsmc_get_surface.argtypes = [ctx_t, P, P, C.POINTER(C.c_int64)]
 for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_state",
            "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
            "dsmc_profile", "dsmc_philox", "dsmc_device_copy", "dig_couple", "dig_get", "dig_residual",
            "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
            "dsmc_mlp_get_weights", "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train",
-           "dsmc_mlp_init_weights", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
+           "dsmc_mlp_init_weights", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_surface_sampling", "dsmc_get_surface",
+           "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
            "dsmc_get_tuning", "dsmc_set_tuning", "dsmc_autotune"]:
     getattr(_lib, _f).restype = C.c_int32
 
@@ -176,7 +179,8 @@ EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_g
             "dsmc_last_error", "dsmc_destroy", "dig_couple", "dig_get", "dig_residual", "dig_solve",
             "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights", "dsmc_mlp_get_weights",
             "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train", "dsmc_mlp_last_error",
-            "dsmc_mlp_destroy", "dig_set_closure", "dig_closure_data", "dig_batch_enable"]
+            "dsmc_mlp_destroy", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_surface_sampling",
+            "dsmc_get_surface"]
 
 
 class DsmcError(RuntimeError):
@@ -275,6 +279,7 @@ class Simulation:
         else:
             _check(_lib.dsmc_batch_init(C.byref(self.ctx), len(cases), meshes, C.byref(sd), _p(nbc), bcs, runs))
         self.nt = int(sum(int(w.mesh.tets.shape[0]) for w in cases))
+        self.nb = int(sum(int(w.mesh.bfaces.shape[0]) for w in cases))
         self.wl = wl
         self.cases = cases
 
@@ -364,6 +369,19 @@ class Simulation:
         sm = np.ascontiguousarray(smax, np.float64) if smax is not None else None
         st = State(len(cell), _p(x), _p(v), _p(cell), _p(pid), _p(sm), step, next_pid)
         self._c(_lib.dsmc_set_state(self.ctx, C.byref(st)))
+
+    def surface_sampling(self, on=True):
+        """Start (clearing the sums) or stop surface sampling (include/dsmc.h)."""
+        self._c(_lib.dsmc_surface_sampling(self.ctx, 1 if on else 0))
+
+    def surface(self):
+        """Surface sums [n_bfaces][5], fields [n_bfaces][6] (number flux,
+        pressure, shear stress (3), heat flux) and the sampled step count."""
+        sums = np.zeros((self.nb, 5))
+        fields = np.zeros((self.nb, 6))
+        n = C.c_int64()
+        self._c(_lib.dsmc_get_surface(self.ctx, _p(sums), _p(fields), C.byref(n)))
+        return sums, fields, int(n.value)
 
     def pair_counts(self):
         a = np.zeros(self.nt, np.int32); b = np.zeros(self.nt, np.int32)

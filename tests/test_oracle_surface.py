@@ -1,0 +1,171 @@
+"""Surface sampling of the oracle (the wall pressure, shear stress and heat
+flux compared on the sphere in section 5) pinned to:
+  * one wall interaction traced by hand: the face hit and the sums it gets
+    (velocity change and energy change of that particle, one hit), for a
+    diffuse and a specular wall, and nothing outside the sampled steps;
+  * the equilibrium closed box: every wall feels the pressure n k T and the
+    number flux n sqrt(kT / (2 pi m)), with no shear and no net heat flux;
+  * free-molecular Couette flow between diffuse plates moving at -U/2 and
+    +U/2: shear stress m Phi U on each plate (Phi = n sqrt(kT / (2 pi m))),
+    in the direction of the other plate's motion, pressure n k T;
+  * free-molecular heat transfer between plates at T1 and T2: number flux
+    Phi = n sqrt(2k / (pi m)) sqrt(T1 T2) / (sqrt T1 + sqrt T2) on both, heat
+    flux 2 k Phi (T2 - T1) into the colder plate; specular side walls take
+    only normal momentum and no energy.
+"""
+import math
+
+import numpy as np
+
+from paper_2607_08195_amd import workloads as W
+from oracle import Oracle
+from statutil import KB, batch_stat
+
+
+def _collisionless(wl):
+    wl.species = W.Species(d_ref=1e-25)
+    return wl
+
+
+def _face_geometry(wl):
+    """Area and unit normal out of the (convex box) domain of every boundary face."""
+    xyz, bf = wl.mesh.xyz, wl.mesh.bfaces
+    p, q, r = xyz[bf[:, 0]], xyz[bf[:, 1]], xyz[bf[:, 2]]
+    n = np.cross(q - p, r - p)
+    area = 0.5 * np.linalg.norm(n, axis=1)
+    n = n / (2.0 * area[:, None])
+    centre = 0.5 * (xyz.min(axis=0) + xyz.max(axis=0))
+    out = np.sign(((p + q + r) / 3.0 - centre) * n).sum(axis=1)
+    n *= np.where(out < 0, -1.0, 1.0)[:, None]
+    return area, n
+
+
+def _group_fields(wl, sums, nsteps, group):
+    """Number flux, pressure, shear vector and heat flux over the faces of a
+    boundary group (a plane): summed sums over the group's area and time."""
+    area, n = _face_geometry(wl)
+    sel = wl.mesh.bgroup == group
+    S = sums[sel].sum(axis=0)
+    A = area[sel].sum()
+    nrm = n[sel][0]
+    assert np.allclose(n[sel], nrm)
+    m, FN = wl.species.mass, wl.run.F_N
+    t = nsteps * wl.run.dt
+    dn = S[:3] @ nrm
+    return dict(flux=FN * S[4] / (A * t), p=m * FN * dn / (A * t),
+                tau=m * FN * (S[:3] - dn * nrm) / (A * t), q=m * FN * S[3] / (A * t))
+
+
+def _batches(o, wl, groups, nbatch, blen):
+    out = []
+    for _ in range(nbatch):
+        o.surface_sampling(True)
+        o.step(blen)
+        sums, ns = o.surface()
+        assert ns == blen
+        out.append({g: _group_fields(wl, sums, ns, g) for g in groups})
+    return out
+
+
+def test_single_hits_by_hand():
+    wl = W.cavity(n_hex=2, ppc=2, lid_speed=50.0, vel_fp32=0)
+    wl.run.n_ss = 0
+    o = Oracle(wl, fill=False)
+    xyz, tets = wl.mesh.xyz, o.tets()
+    cent = xyz[tets].mean(axis=1)
+    c = int(np.argmax(cent[:, 1]))          # a tet under the lid y = 1
+    x0 = cent[c].copy()
+    vin = np.array([10.0, 300.0, -20.0])
+    # just past the lid: the re-emitted particle cannot reach another wall
+    t = 1.1 * (1.0 - x0[1]) / vin[1]
+    o.surface_sampling(True)
+    cc, x, v = o.trace_one(x0, vin, c, 7, 1, t)
+    sums, _ = o.surface()
+    hit = np.nonzero(sums[:, 4])[0]
+    assert len(hit) == 1 and sums[hit[0], 4] == 1.0
+    b = hit[0]
+    assert wl.mesh.bgroup[b] == 3            # the lid group
+    assert np.array_equal(sums[b, :3], vin - v)
+    assert sums[b, 3] == 0.5 * ((vin @ vin) - (v @ v))
+    assert np.count_nonzero(sums) == np.count_nonzero(sums[b])
+    # step index 0 is not after n_ss = 0: nothing is added
+    o.surface_sampling(True)
+    o.trace_one(x0, vin, c, 7, 0, t)
+    assert not o.surface()[0].any()
+    # a specular wall: the velocity change is the reflection's, no energy
+    wl = W.closed_box(n_hex=2, kind=W.BC_SPECULAR, ppc=2, vel_fp32=0)
+    wl.run.n_ss = 0
+    o = Oracle(wl, fill=False)
+    cent = wl.mesh.xyz[o.tets()].mean(axis=1)
+    c = int(np.argmax(cent[:, 0]))
+    o.surface_sampling(True)
+    vin = np.array([400.0, 30.0, 5.0])
+    cc, x, v = o.trace_one(cent[c], vin, c, 3, 1, 1e-3)
+    sums, _ = o.surface()
+    b = np.nonzero(sums[:, 4])[0]
+    assert len(b) == 1
+    assert np.array_equal(sums[b[0], :3], vin - v)
+    assert abs(sums[b[0], 0] - 800.0) < 1e-9 and abs(sums[b[0], 1]) < 1e-9 and abs(sums[b[0], 2]) < 1e-9
+    assert abs(sums[b[0], 3]) < 1e-9 * (vin @ vin)
+
+
+def test_equilibrium_box_pressure_and_flux():
+    wl = W.closed_box(n_hex=4, kind=W.BC_DIFFUSE, Kn=1.0, ppc=20, vel_fp32=0)
+    o = Oracle(wl)
+    m, T = wl.species.mass, wl.run.T0
+    n = o.np * wl.run.F_N / 1.0
+    groups = list(range(6))
+    res = _batches(o, wl, groups, 20, 10)
+    p_exp = n * KB * T
+    flux_exp = n * math.sqrt(KB * T / (2 * math.pi * m))
+    cbar = math.sqrt(8 * KB * T / (math.pi * m))
+    for g in groups:
+        p, se = batch_stat([r[g]["p"] for r in res])
+        assert abs(p - p_exp) < 3.5 * se + 0.005 * p_exp, (g, p, p_exp, se)
+        f, sef = batch_stat([r[g]["flux"] for r in res])
+        assert abs(f - flux_exp) < 3.5 * sef + 0.005 * flux_exp, (g, f, flux_exp)
+        tau, set_ = batch_stat([r[g]["tau"] for r in res])
+        assert (np.abs(tau) < 3.5 * set_ + 1e-3 * p_exp).all(), (g, tau, set_)
+        q, seq = batch_stat([r[g]["q"] for r in res])
+        assert abs(q) < 3.5 * seq + 1e-3 * p_exp * cbar, (g, q, seq)
+
+
+def test_free_molecular_couette_shear():
+    U, Tw = 200.0, 273.0
+    wl = _collisionless(W.plates(n=(2, 8, 2), U=U, T1=Tw, T2=Tw, ppc=60, periodic=True))
+    o = Oracle(wl)
+    m = wl.species.mass
+    o.step(150)
+    n = o.np * wl.run.F_N / 1.0
+    res = _batches(o, wl, [2, 3], 24, 40)
+    phi = n * math.sqrt(KB * Tw / (2 * math.pi * m))
+    tau_exp = m * phi * U
+    # the lower plate (y = 0, moving -U/2) is dragged towards +x, the upper one towards -x
+    for g, sign in ((2, 1.0), (3, -1.0)):
+        tau, se = batch_stat([r[g]["tau"] for r in res])
+        assert abs(tau[0] - sign * tau_exp) < 3.5 * se[0] + 0.01 * tau_exp, (g, tau, tau_exp, se)
+        assert abs(tau[2]) < 3.5 * se[2] + 0.01 * tau_exp
+        p, sep = batch_stat([r[g]["p"] for r in res])
+        assert abs(p - n * KB * Tw) < 3.5 * sep + 0.01 * n * KB * Tw, (g, p)
+
+
+def test_free_molecular_heat_transfer_between_plates():
+    T1, T2 = 200.0, 400.0
+    wl = _collisionless(W.plates(n=(2, 8, 2), T1=T1, T2=T2, ppc=60, periodic=False, vel_fp32=0))
+    o = Oracle(wl)
+    m = wl.species.mass
+    o.step(150)
+    n = o.np * wl.run.F_N / 1.0
+    res = _batches(o, wl, [0, 1, 2, 3, 4, 5], 24, 40)
+    phi = n * math.sqrt(2 * KB / (math.pi * m)) * math.sqrt(T1 * T2) / (math.sqrt(T1) + math.sqrt(T2))
+    q_exp = 2 * KB * phi * (T2 - T1)
+    for g, sign in ((2, 1.0), (3, -1.0)):
+        f, sef = batch_stat([r[g]["flux"] for r in res])
+        assert abs(f - phi) < 3.5 * sef + 0.01 * phi, (g, f, phi)
+        q, seq = batch_stat([r[g]["q"] for r in res])
+        assert abs(q - sign * q_exp) < 3.5 * seq + 0.01 * abs(q_exp), (g, q, q_exp, seq)
+    # specular side walls (groups 0, 1, 4, 5): normal momentum only, no energy
+    for g in (0, 1, 4, 5):
+        for r in res:
+            assert np.all(np.abs(r[g]["tau"]) <= 1e-9 * abs(r[g]["p"]))
+            assert abs(r[g]["q"]) <= 1e-9 * abs(r[g]["p"]) * 1e3
