@@ -328,3 +328,162 @@ def open_box(n=(6, 4, 4), lo=(-2.0, -2.0, -2.0), hi=(4.0, 2.0, 2.0), T=200.0, u=
     bcs = [inflow, Boundary(BC_OUTFLOW, T), inflow, inflow, inflow, inflow]
     run = Run(n0=n_inf, T0=T, u0=(u, 0.0, 0.0), F_N=F_N, dt=dt, seed=seed, vel_fp32=vel_fp32)
     return Workload("open_box", mesh, sp, bcs, run, 1, dict(n_inf=n_inf, u=u, T=T))
+
+
+# ---------------------------------------------------------------------------
+# Sphere in a box
+# ---------------------------------------------------------------------------
+_HEX_QUADS = ((0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7))
+
+
+def _split_quads(q):
+    """Each quad (cyclic vertex ids) as two triangles along the diagonal
+    through its lowest-id vertex (the same diagonal from either side)."""
+    lo = np.argmin(q, axis=1)
+    ac = (lo == 0) | (lo == 2)
+    t1 = np.where(ac[:, None], q[:, [0, 1, 2]], q[:, [0, 1, 3]])
+    t2 = np.where(ac[:, None], q[:, [0, 2, 3]], q[:, [1, 2, 3]])
+    return t1, t2
+
+
+def sphere_box_mesh(N=4, K=3, a=1.0, R=0.5, lo=(-2.0, -2.0, -2.0), hi=(4.0, 2.0, 2.0), grade=5.0):
+    """Box [lo,hi] minus the sphere of radius R at the origin.  A cube
+    [-a,a]^3 around the sphere carries a cubed-sphere O-grid (N x N cells on
+    each cube face, K layers from the sphere to the cube, layer thickness
+    growing geometrically by `grade` from the wall outwards); the rest of
+    the box is Cartesian with the cube's spacing h = 2a/N (lo, hi on that
+    lattice).  Every hex is split into 12 tets around its centroid, each quad
+    face into two triangles along the diagonal through its lowest-id vertex
+    (conforming between neighbours).  Boundary groups: 0 x-, 1 x+, 2 y-,
+    3 y+, 4 z-, 5 z+, 6 sphere."""
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    h = 2.0 * a / N
+    n = np.rint((hi - lo) / h).astype(int)
+    assert np.allclose(lo + n * h, hi) and np.allclose(np.rint((-a - lo) / h), (-a - lo) / h)
+    c0 = np.rint((-a - lo) / h).astype(int)          # lattice index of the cube's low corner
+    c1 = c0 + N
+    # lattice vertices outside the open cube
+    I, J, Kk = np.meshgrid(np.arange(n[0] + 1), np.arange(n[1] + 1), np.arange(n[2] + 1), indexing="ij")
+    lat = np.stack([I.ravel(), J.ravel(), Kk.ravel()], axis=1)
+    inside = np.all((lat > c0) & (lat < c1), axis=1)
+    lid = np.full(len(lat), -1, dtype=np.int64)
+    keep = np.nonzero(~inside)[0]
+    lid[keep] = np.arange(len(keep))
+    xyz = [lo + lat[keep] * h]
+    nv = len(keep)
+
+    def lat_id(ijk):
+        ijk = np.asarray(ijk)
+        return lid[(ijk[..., 0] * (n[1] + 1) + ijk[..., 1]) * (n[2] + 1) + ijk[..., 2]]
+
+    # cube-surface lattice points and their O-grid layers 0..K-1 (layer K is the point itself)
+    on_cube = np.all((lat >= c0) & (lat <= c1), axis=1) & ~inside
+    cube_pts = lat[on_cube]
+    cube_index = np.full(len(lat), -1, dtype=np.int64)
+    cube_index[np.nonzero(on_cube)[0]] = np.arange(len(cube_pts))
+    P = lo + cube_pts * h
+    d = P / np.linalg.norm(P, axis=1, keepdims=True)
+    S = R * d
+    r = grade ** (1.0 / max(K - 1, 1))
+    dl = r ** np.arange(K)
+    g = np.concatenate([[0.0], np.cumsum(dl) / dl.sum()])
+    layers = np.stack([S + g[k] * (P - S) for k in range(K)], axis=1)   # [ncube, K, 3]
+    xyz.append(layers.reshape(-1, 3))
+    layer_base = nv
+    nv += len(cube_pts) * K
+
+    def oid(ijk, k):
+        ci = cube_index[(ijk[..., 0] * (n[1] + 1) + ijk[..., 1]) * (n[2] + 1) + ijk[..., 2]]
+        return np.where(k == K, lat_id(ijk), layer_base + ci * K + k)
+
+    hexes = []
+    # Cartesian cells outside the cube
+    ci, cj, ck = np.meshgrid(np.arange(n[0]), np.arange(n[1]), np.arange(n[2]), indexing="ij")
+    cells = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=1)
+    cells = cells[~np.all((cells >= c0) & (cells < c1), axis=1)]
+    corner = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0], [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]])
+    hexes.append(np.stack([lat_id(cells + corner[v]) for v in range(8)], axis=1))
+    # O-grid cells: on each cube face, N x N cells and K layers
+    u, v = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    u, v = u.ravel(), v.ravel()
+    for ax in range(3):
+        a1, a2 = (ax + 1) % 3, (ax + 2) % 3
+        for side in (c0[ax], c1[ax]):
+            base = np.zeros((len(u), 3), dtype=np.int64)
+            base[:, ax] = side
+            base[:, a1] = c0[a1] + u
+            base[:, a2] = c0[a2] + v
+            e1 = np.zeros(3, dtype=np.int64); e1[a1] = 1
+            e2 = np.zeros(3, dtype=np.int64); e2[a2] = 1
+            quad = [base, base + e1, base + e1 + e2, base + e2]
+            for k in range(K):
+                hexes.append(np.stack([oid(q, np.full(len(u), k)) for q in quad] +
+                                      [oid(q, np.full(len(u), k + 1)) for q in quad], axis=1))
+    H = np.concatenate(hexes).astype(np.int64)
+    assert (H >= 0).all()
+    xyz = np.concatenate(xyz)
+    cen = xyz[H].mean(axis=1)
+    cid = nv + np.arange(len(H))
+    xyz = np.concatenate([xyz, cen])
+    tets = []
+    for qd in _HEX_QUADS:
+        t1, t2 = _split_quads(H[:, qd])
+        tets.append(np.concatenate([cid[:, None], t1], axis=1))
+        tets.append(np.concatenate([cid[:, None], t2], axis=1))
+    tets = np.stack(tets, axis=1).reshape(-1, 4)
+    # boundary triangles: the box's outer quads and the sphere's quads
+    bq, bg = [], []
+    for ax in range(3):
+        a1, a2 = (ax + 1) % 3, (ax + 2) % 3
+        p, q = np.meshgrid(np.arange(n[a1]), np.arange(n[a2]), indexing="ij")
+        p, q = p.ravel(), q.ravel()
+        for s_, side in enumerate((0, n[ax])):
+            base = np.zeros((len(p), 3), dtype=np.int64)
+            base[:, ax] = side
+            base[:, a1] = p
+            base[:, a2] = q
+            e1 = np.zeros(3, dtype=np.int64); e1[a1] = 1
+            e2 = np.zeros(3, dtype=np.int64); e2[a2] = 1
+            bq.append(np.stack([lat_id(base), lat_id(base + e1), lat_id(base + e1 + e2), lat_id(base + e2)], axis=1))
+            bg.append(np.full(len(p), 2 * ax + s_))
+        for side in (c0[ax], c1[ax]):
+            base = np.zeros((len(u), 3), dtype=np.int64)
+            base[:, ax] = side
+            base[:, a1] = c0[a1] + u
+            base[:, a2] = c0[a2] + v
+            e1 = np.zeros(3, dtype=np.int64); e1[a1] = 1
+            e2 = np.zeros(3, dtype=np.int64); e2[a2] = 1
+            z = np.zeros(len(u), dtype=np.int64)
+            bq.append(np.stack([oid(base, z), oid(base + e1, z), oid(base + e1 + e2, z), oid(base + e2, z)], axis=1))
+            bg.append(np.full(len(u), 6))
+    BQ = np.concatenate(bq)
+    BG = np.concatenate(bg)
+    t1, t2 = _split_quads(BQ)
+    bfaces = np.concatenate([t1, t2]).astype(np.int32)
+    bgroup = np.concatenate([BG, BG]).astype(np.int32)
+    return Mesh(xyz=np.ascontiguousarray(xyz), tets=np.ascontiguousarray(tets.astype(np.int32)),
+                bfaces=np.ascontiguousarray(bfaces), bgroup=np.ascontiguousarray(bgroup), bpartner=None, h=h)
+
+
+def sphere_flow(N=4, K=3, grade=5.0, T=200.0, u=2634.66, Kn=0.05, Tw=500.0, ppc=10, n_particles=None,
+                seed=0, vel_fp32=1, dt=None, outflow=True, lo=(-2.0, -2.0, -2.0), hi=(4.0, 2.0, 2.0)):
+    """Hypersonic flow over a sphere of diameter 1 m (Kn referred to the
+    diameter) in the box [lo,hi]: freestream (T, u along +x) through the five
+    faces other than x+, vacuum outflow at x+ (with outflow=False, inflow
+    there too), diffuse sphere at Tw; filled with the freestream.  F_N gives
+    ppc particles per tet on average, or n_particles in all."""
+    sp = Species()
+    mesh = sphere_box_mesh(N=N, K=K, grade=grade, lo=lo, hi=hi)
+    n_inf = n0_from_kn(sp, Kn, T)
+    vol = float(np.prod(np.asarray(hi) - np.asarray(lo))) - math.pi / 6.0
+    total = n_particles if n_particles is not None else ppc * mesh.n_tets
+    F_N = n_inf * vol / total
+    if dt is None:
+        dt = 0.2 * mesh.h / u
+    inflow = Boundary(BC_INFLOW, T, (u, 0.0, 0.0), n=n_inf)
+    bcs = [inflow, Boundary(BC_OUTFLOW, T) if outflow else inflow, inflow, inflow, inflow, inflow,
+           Boundary(BC_DIFFUSE, Tw)]
+    run = Run(n0=n_inf, T0=T, u0=(u, 0.0, 0.0), F_N=F_N, dt=dt, seed=seed, vel_fp32=vel_fp32)
+    return Workload(f"sphere_N{N}K{K}", mesh, sp, bcs, run, 1,
+                    dict(n_inf=n_inf, u=u, T=T, Tw=Tw, R=0.5, Kn=Kn))

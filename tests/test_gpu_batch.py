@@ -297,7 +297,7 @@ def test_ensemble64_half_coupled_smallest_cases_match_oracle(D):
     g = D.Simulation(cases, stream=_stream())
     begin = g.case_cells()
     small = np.argsort(np.diff(begin), kind="stable")[:8]
-    on = (np.arange(len(cases)) % 2 == 0).astype(np.int32)
+    on = (np.arange(len(cases)) % 2 == 1).astype(np.int32)
     for i, k in enumerate(small):
         on[k] = 1 - i % 2
     g.dig_enable(on)

@@ -37,6 +37,7 @@ def _cases():
     c["open_box_inflow"] = (lambda: W.open_box(n=(6, 4, 4), ppc=12, vel_fp32=1), 6)
     c["sparse_ppc1"] = (lambda: W.cavity(n_hex=6, Kn=0.5, ppc=1, jitter=0.1, vel_fp32=1), 2)
     c["dense_ppc45"] = (lambda: W.cavity(n_hex=5, Kn=0.05, ppc=45, jitter=0.1, vel_fp32=1), 1)
+    c["sphere_hypersonic"] = (lambda: W.sphere_flow(N=4, K=3, ppc=8, vel_fp32=1), 4)
     return c
 
 
@@ -91,7 +92,7 @@ def test_single_step_parity(dsmc, name):
 # which these cases (several hops per step, diffuse, specular, periodic and
 # open faces) exercise
 MOVES = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16]
-MOVE_CASES = ["cavity_6_fp64_kn1", "specular_box", "plates_periodic_couette", "open_box_inflow"]
+MOVE_CASES = ["cavity_6_fp64_kn1", "specular_box", "plates_periodic_couette", "open_box_inflow", "sphere_hypersonic"]
 
 
 @pytest.mark.parametrize("case", MOVE_CASES)

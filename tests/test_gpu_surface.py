@@ -32,8 +32,14 @@ def _fields(wl, sums, ns):
     n = np.cross(q - p, r - p)
     area = 0.5 * np.linalg.norm(n, axis=1)
     n = n / (2.0 * area[:, None])
-    centre = 0.5 * (xyz.min(axis=0) + xyz.max(axis=0))
-    n *= np.where(np.sign(((p + q + r) / 3.0 - centre) * n).sum(axis=1) < 0, -1.0, 1.0)[:, None]
+    # out of the gas: away from the fourth vertex of the tet on the face
+    tets = wl.mesh.tets
+    opp = {}
+    for t in range(len(tets)):
+        for f in range(4):
+            opp[tuple(sorted(np.delete(tets[t], f)))] = tets[t][f]
+    far = xyz[[opp[tuple(sorted(b))] for b in bf]]
+    n *= np.where(((far - p) * n).sum(axis=1) > 0, -1.0, 1.0)[:, None]
     m, FN = wl.species.mass, wl.run.F_N
     ta = area * ns * wl.run.dt
     dn = (sums[:, :3] * n).sum(axis=1)
@@ -61,6 +67,7 @@ CASES = {
     "cavity_lid_fp32_jitter": lambda: W.cavity(n_hex=6, Kn=0.1, ppc=20, jitter=0.1, vel_fp32=1, lid_speed=100.0),
     "specular_box": lambda: W.closed_box(n_hex=5, kind=W.BC_SPECULAR, ppc=15, vel_fp32=1),
     "plates_couette": lambda: W.plates(n=(3, 6, 3), U=300.0, T1=250.0, T2=350.0, ppc=25, n0=3e19, vel_fp32=0),
+    "sphere_hypersonic": lambda: W.sphere_flow(N=4, K=3, ppc=8, vel_fp32=1),
 }
 
 

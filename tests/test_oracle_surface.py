@@ -169,3 +169,81 @@ def test_free_molecular_heat_transfer_between_plates():
         for r in res:
             assert np.all(np.abs(r[g]["tau"]) <= 1e-9 * abs(r[g]["p"]))
             assert abs(r[g]["q"]) <= 1e-9 * abs(r[g]["p"]) * 1e3
+
+
+# --------------------------------------------------------------------------
+# free-molecular flow over the sphere
+# --------------------------------------------------------------------------
+def _facet_force(xyz, tri, n, m, T, U, Tw):
+    """Expected force of a drifting Maxwellian (number density n, temperature
+    T, drift U) on flat facets, each with its own side facing the gas,
+    re-emitted diffusely at rest at Tw (free-molecular closed forms: incident
+    number, normal and tangential momentum fluxes of a drifting Maxwellian
+    through a plane, plus the normal momentum of the half-range Maxwellian
+    leaving the wall)."""
+    from scipy.special import erf
+    p, q, r = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
+    nv = np.cross(q - p, r - p)
+    A = 0.5 * np.linalg.norm(nv, axis=1)
+    nv /= (2.0 * A)[:, None]
+    c = (p + q + r) / 3.0
+    nv *= np.where((nv * c).sum(axis=1) < 0, -1.0, 1.0)[:, None]   # out of the body (sphere at the origin)
+    beta = math.sqrt(m / (2 * KB * T))
+    Un = nv @ U
+    sn = -beta * Un                                   # speed ratio towards the facet
+    e = np.exp(-sn * sn)
+    ef = 1.0 + erf(sn)
+    phi = n / (2 * math.sqrt(math.pi) * beta) * (e + math.sqrt(math.pi) * sn * ef)
+    pi_ = n * m / (2 * beta * beta) * (sn / math.sqrt(math.pi) * e + (0.5 + sn * sn) * ef)
+    pr = m * phi * math.sqrt(math.pi * KB * Tw / (2 * m))
+    Ut = U[None, :] - Un[:, None] * nv
+    F = A[:, None] * (-(pi_ + pr)[:, None] * nv + m * phi[:, None] * Ut)
+    return F.sum(axis=0)
+
+
+def _sphere_cd(s, Tw, T):
+    return ((2 * s * s + 1) / (math.sqrt(math.pi) * s ** 3) * math.exp(-s * s)
+            + (4 * s ** 4 + 4 * s * s - 1) / (2 * s ** 4) * math.erf(s)
+            + 2 * math.sqrt(math.pi) / (3 * s) * math.sqrt(Tw / T))
+
+
+def test_facet_force_reference_reproduces_the_sphere_drag():
+    """The facet closed forms, summed over a fine tessellation of the
+    sphere, give the free-molecular sphere drag coefficient."""
+    mesh = W.sphere_box_mesh(N=48, K=1, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0))
+    tri = mesh.bfaces[mesh.bgroup == 6]
+    m, T, Tw, n = W.Species().mass, 200.0, 300.0, 1e19
+    for u in (300.0, 866.0, 2634.66):
+        U = np.array([u, 0.0, 0.0])
+        F = _facet_force(mesh.xyz, tri, n, m, T, U, Tw)
+        s = u / math.sqrt(2 * KB * T / m)
+        D = _sphere_cd(s, Tw, T) * 0.5 * n * m * u * u * math.pi * 0.25
+        assert abs(F[0] / D - 1) < 2e-3, (u, F[0] / D)
+        assert abs(F[1]) < 1e-5 * D and abs(F[2]) < 1e-5 * D
+
+
+def test_free_molecular_sphere_drag():
+    """Collisionless freestream (speed ratio 3, inflow on all six box faces)
+    over the faceted sphere: the sampled drag and side forces against the
+    facet closed forms for the same polyhedron."""
+    u, T, Tw = 866.0, 200.0, 300.0
+    wl = _collisionless(W.sphere_flow(N=4, K=3, u=u, T=T, Tw=Tw, ppc=10, outflow=False, vel_fp32=0))
+    o = Oracle(wl)
+    m = wl.species.mass
+    n = wl.info["n_inf"]
+    sel = wl.mesh.bgroup == 6
+    ref = _facet_force(wl.mesh.xyz, wl.mesh.bfaces[sel], n, m, T, np.array([u, 0.0, 0.0]), Tw)
+    forces = []
+    for _ in range(10):
+        o.surface_sampling(True)
+        o.step(20)
+        sums, ns = o.surface()
+        forces.append(m * wl.run.F_N * sums[sel, :3].sum(axis=0) / (ns * wl.run.dt))
+    F, se = batch_stat(forces)
+    assert abs(F[0] - ref[0]) < 3.5 * se[0] + 0.003 * ref[0], (F, ref, se)
+    for k in (1, 2):
+        assert abs(F[k]) < 3.5 * se[k] + 0.003 * ref[0], (F, se)
+    # the drag of the polyhedron is within a few per cent of the sphere's
+    s = u / math.sqrt(2 * KB * T / m)
+    D = _sphere_cd(s, Tw, T) * 0.5 * n * m * u * u * math.pi * 0.25
+    assert abs(ref[0] / D - 1) < 0.05
