@@ -185,7 +185,8 @@ def bench_sphere(args, dsmc, W, develop=600):
     (cubed-sphere O-grid graded 5:1 towards the wall inside a Cartesian box),
     freestream inflow on five faces, vacuum outflow, 50M particles at the
     initial freestream fill.  `develop` untimed steps form the shock (about
-    two flow-through times), then surface sampling is switched on and
+    two flow-through times), the autotuner picks the schedules on the
+    developed flow, then surface sampling is switched on and
     --warmup and --steps ordinary steps follow; value = particle-steps/s over
     the timed steps.  The sphere's drag coefficient from the surface sums is
     reported beside it."""
@@ -193,8 +194,8 @@ def bench_sphere(args, dsmc, W, develop=600):
     import torch
     wl = W.sphere_flow(N=22, K=16, grade=5.0, n_particles=50_000_000, vel_fp32=1)
     sim = dsmc.Simulation(wl, capacity=80_000_000)
-    tune = sim.autotune(trial_steps=3)
     sim.step(develop)
+    tune = sim.autotune(trial_steps=3)  # on the developed flow (uneven cell occupancy)
     sim.surface_sampling(True)
     sim.step(args.warmup)
     sim.sync()

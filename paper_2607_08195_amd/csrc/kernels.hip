@@ -1155,6 +1155,7 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
     if (lane == 0) soff[kCollideLanes] = offsets[min(c0 + kCollideLanes, nt)] - (int32_t)a;
     const int64_t n = (int64_t)offsets[min(c0 + kCollideLanes, nt)] - a;
     const uint32_t step = sc->step;
+    __syncthreads();  // soff is read by every lane below
     if (FUSED) {
         // kFuseBatch particles per lane in flight: all loads of a batch are
         // issued before its stores (the compiler cannot move a load of src
@@ -1200,16 +1201,44 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
         }
         __syncthreads();
     }
-    if (n <= CAP) {
-        if (!FUSED) {
-#pragma unroll 4
-            for (int64_t i = lane; i < n; i += kCollideLanes) spid[i] = p.pid[a + i];
-            __syncthreads();
+    // The chunk's cells are taken in windows of consecutive cells whose
+    // particles fit in CAP (one window when the whole chunk fits): ranks in
+    // LDS, then the window's cells one per lane.  A single cell with more
+    // than CAP particles takes the global-memory path.
+    for (int k0 = 0; k0 < kCollideLanes;) {
+        int k1 = k0;
+        while (k1 < kCollideLanes && soff[k1 + 1] - soff[k0] <= CAP) ++k1;
+        const int w0 = soff[k0];
+        if (k1 == k0) {
+            // one cell beyond the LDS stage
+            if (lane == 0 && c0 + k0 < nt) {
+                const int cc = c0 + k0;
+                const int64_t s0 = offsets[cc];
+                const int N = offsets[cc + 1] - offsets[cc];
+                for (int k = 0; k < N; ++k) {
+                    const uint32_t pk = p.pid[s0 + k];
+                    int r = 0;
+                    for (int q = 0; q < N; ++q) r += p.pid[s0 + q] < pk;
+                    perm[s0 + r] = (int32_t)(s0 + k);
+                }
+                GlobalCell<VT> cv{p.vel, perm, s0};
+                if (do_collide) ntc_cell(cv, N, cc, cp, step, cp.smax, cp.ncand, cp.nacc);
+                if (do_sample) sample_cell(cv, N, cc, cp, step);
+            }
+            k0 = k0 + 1;
+            continue;
         }
-        for (int i = lane; i < (int)n; i += kCollideLanes) {
-            const int k = p.cell[a + i] - c0;
-            const int s0 = soff[k];
-            const int N = soff[k + 1] - s0;
+        const int wn = soff[k1] - w0;
+        if (!FUSED || n > CAP) {
+            if (k0 > 0) __syncthreads();  // the previous window's ranks are no longer read
+#pragma unroll 4
+            for (int i = lane; i < wn; i += kCollideLanes) spid[i] = p.pid[a + w0 + i];
+        }
+        __syncthreads();
+        for (int i = lane; i < wn; i += kCollideLanes) {
+            const int k = p.cell[a + w0 + i] - c0;
+            const int s0 = soff[k] - w0;
+            const int N = soff[k + 1] - soff[k];
             const uint32_t pk = spid[i];
             int r = 0;
 #pragma unroll 4
@@ -1217,25 +1246,14 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
             sord[s0 + r] = (uint16_t)i;
         }
         __syncthreads();
-        if (c < nt) {
-            const int s0 = soff[lane];
-            const int N = soff[lane + 1] - s0;
-            LdsOrderCell<VT> cv{p.vel, sord, s0, a};
+        if (lane >= k0 && lane < k1 && c < nt) {
+            const int s0 = soff[lane] - w0;
+            const int N = soff[lane + 1] - soff[lane];
+            LdsOrderCell<VT> cv{p.vel, sord, s0, a + w0};
             if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
             if (do_sample) sample_cell(cv, N, c, cp, step);
         }
-    } else if (c < nt) {
-        const int64_t s0 = offsets[c];
-        const int N = offsets[c + 1] - offsets[c];
-        for (int k = 0; k < N; ++k) {
-            const uint32_t pk = p.pid[s0 + k];
-            int r = 0;
-            for (int q = 0; q < N; ++q) r += p.pid[s0 + q] < pk;
-            perm[s0 + r] = (int32_t)(s0 + k);
-        }
-        GlobalCell<VT> cv{p.vel, perm, s0};
-        if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
-        if (do_sample) sample_cell(cv, N, c, cp, step);
+        k0 = k1;
     }
 }
 

@@ -4,7 +4,9 @@ Single-step parity from an identical state (set from the oracle's own
 state on both sides): bit-exact cell indices, (cell, pid) order and
 per-cell candidate/accepted pair counts; positions within 1e-12 relative;
 velocities within 1 float32 ulp (FP32 storage) or 1e-12 relative (FP64);
-moment sums within 1e-12 relative.  Cases cover diffuse walls with a moving
+moment sums within 1e-12 relative; (sigma c)_max within 1e-15 relative (a
+new maximum is an FP64 power, whose device and host results may differ in
+the last bit).  Cases cover diffuse walls with a moving
 lid, jittered irregular tets, specular walls, periodic plates, freestream
 inflow/outflow, sparse cells (0-1 particles), dense chunks beyond the LDS
 stage, and the full 384,000-tet cavity in the benchmark's configuration."""
@@ -44,6 +46,11 @@ def _cases():
 CASES = _cases()
 
 
+def _smax_close(a, b):
+    d = np.abs(a - b) / np.abs(b)
+    assert (d <= 1e-15).all(), f"(sigma c)_max: {int((d > 0).sum())} cells differ, max rel {d.max():.3e}"
+
+
 def _one_step_parity(D, wl, presteps, steps=1, move=None, collide=None, sort=None):
     wl.run.n_ss = presteps
     o = Oracle(wl)
@@ -66,7 +73,7 @@ def _one_step_parity(D, wl, presteps, steps=1, move=None, collide=None, sort=Non
     oc, oa = o.pair_counts()
     assert np.array_equal(gc, oc), "candidate pair counts differ"
     assert np.array_equal(ga, oa), "accepted pair counts differ"
-    assert np.array_equal(gs["smax"], o.smax())
+    _smax_close(gs["smax"], o.smax())
     gsum, ns = g.sums(D.SAMPLE_STEADY)
     assert ns == o.n_steady == steps
     compare_sums(gsum, o.sums(0))
@@ -140,7 +147,7 @@ def test_init_fill_parity(dsmc):
         compare_particles(gs, os_, wl.run.vel_fp32, ctx="init " + wl.name)
         # positions involve no libm: bitwise equal
         assert np.array_equal(gs["x"], os_["x"])
-        assert np.array_equal(gs["smax"], o.smax())
+        _smax_close(gs["smax"], o.smax())
         assert gs["next_pid"] == o.next_pid
         g.close()
 
