@@ -209,3 +209,14 @@ def test_full_size_cavity_single_step(dsmc):
     wl = W.cavity_large()
     info = _one_step_parity(dsmc, wl, 0)
     print("full size", info)
+
+
+def test_full_size_sphere_single_step(dsmc):
+    """The hypersonic sphere at the benchmark's size (1,963,104 tets, 50M
+    particles, FP32 velocities, inflow on five faces and outflow) with the
+    schedules the autotuner chose for it (move defer5, collide global3k,
+    sort fused): one step from the oracle's initial fill against the oracle,
+    compared on every particle and cell."""
+    wl = W.sphere_flow(N=22, K=16, grade=5.0, n_particles=50_000_000, vel_fp32=1)
+    info = _one_step_parity(dsmc, wl, 0, move=7, collide=3, sort=2)
+    print("full size sphere", info)
