@@ -34,6 +34,7 @@ struct DigCase {
     int32_t cell0, cell_end;  // caller cells [cell0, cell_end)
     int32_t first, end;       // internal cells [first, end)
     int32_t enabled;          // 0: the case's particles are left as they are
+    int32_t closed;           // no inflow or outflow face: the solve's mass is rescaled
     uint32_t next_pid;
 };
 

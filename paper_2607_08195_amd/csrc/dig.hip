@@ -1154,7 +1154,7 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_mass_cases(DigGeom g, DigWo
     __syncthreads();
     if (threadIdx.x == 0) {
         const double mp = (double)(offsets[k.end] - offsets[k.first]) * k.FN * g.mass;
-        k.mass_scale = k.enabled && tot > 0 ? mp / tot : 1.0;
+        k.mass_scale = k.enabled && k.closed && tot > 0 ? mp / tot : 1.0;
     }
 }
 

@@ -208,6 +208,7 @@ dsmc_status ensure(dsmc_ctx c) {
             q.first = nt;
             q.end = 0;
             q.enabled = 1;
+            q.closed = 1;
             q.next_pid = 0;
         }
         for (int t = 0; t < nt; ++t) {
@@ -216,6 +217,11 @@ dsmc_status ensure(dsmc_ctx c) {
             case_of[t] = k;
             dc[k].first = std::min(dc[k].first, t);
             dc[k].end = std::max(dc[k].end, t + 1);
+        }
+        // a case with an inflow or outflow face is open
+        for (int b = 0; b < c->nb; ++b) {
+            const int kind = c->bcs[c->hm.bf_group[b]].kind;
+            if (kind == DSMC_BC_INFLOW || kind == DSMC_BC_OUTFLOW) dc[case_of[c->hm.bf_tet[b]]].closed = 0;
         }
         for (const DigCase& q : dc)
             if (q.end - q.first != q.cell_end - q.cell0) {
@@ -271,6 +277,8 @@ dsmc_status ensure(dsmc_ctx c) {
     g.cell_case = ncase ? c->d_cell_case : nullptr;
     g.n_cases = ncase;
     for (const dsmc_boundary_desc& b : c->bcs) d->closed = d->closed && b.kind != DSMC_BC_INFLOW && b.kind != DSMC_BC_OUTFLOW;
+    // a batch rescales its closed cases (per case, in the kernel)
+    for (const DigCase& q : dc) d->closed = d->closed || q.closed;
     if (ncase) {
         // next particle id of each case: its largest id + 1
         Scalars sc;
