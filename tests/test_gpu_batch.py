@@ -188,7 +188,24 @@ def test_batch_coupling_matches_oracle_per_case(D):
     the largest, the kept macroscopic state M^k to 1e-10 (the criteria of
     the single-case cycle; the solve runs a fixed n_m iterations, eps_m = 0,
     so the batch-wide stopping test does not couple the cases)."""
-    cases = _cases(0)
+    _batch_coupling_check(D, _cases(0), [1, 0, 1, 0])
+
+
+def test_batch_coupling_open_case(D):
+    """A batch coupling a closed cavity and a diffuse box with a vacuum
+    outflow face: the closed case's solve is rescaled to its particles' mass,
+    the open one's is not, each as the oracle run of the case alone."""
+    cav = W.cavity(n_hex=3, Kn=0.05, ppc=12, lid_speed=150.0, seed=7, vel_fp32=0)
+    box = W.closed_box(n_hex=3, kind=W.BC_DIFFUSE, Kn=0.05, ppc=12, vel_fp32=0, seed=7)
+    box.boundaries = list(box.boundaries)
+    box.boundaries[1] = W.Boundary(W.BC_OUTFLOW, 273.0)
+    for k, wl in enumerate((cav, box)):
+        wl.run.case_id = 30 + k
+        wl.run.n_ss = 0
+    _batch_coupling_check(D, [cav, box], [1, 1])
+
+
+def _batch_coupling_check(D, cases, on):
     for wl in cases:
         wl.run.ewma_on = 1
         wl.run.n_a = 50
@@ -206,7 +223,6 @@ def test_batch_coupling_matches_oracle_per_case(D):
                 oracles[0].step_index, 0, cat([o.smax() for o in oracles]))
     g.set_sums(D.SAMPLE_EWMA, cat([o.sums(1) for o in oracles]), cat([o.ewma_counts() for o in oracles]))
     g.set_sums(D.SAMPLE_STEADY, cat([o.sums(0) for o in oracles]))
-    on = [1, 0, 1, 0]
     g.dig_enable(on)
     kw = dict(kn_max=0.93, passes=3, n_m=40, eps_m=0.0, cfl=0.5, feedback=1)
     changed = 0
