@@ -224,7 +224,7 @@ void read_tuning(dsmc_ctx c) {
     }
     if (const char* v = std::getenv("DSMC_MOVE_BATCH"))
         c->move_batch = std::min(kQueueMaxBatch, std::max(64, std::atoi(v) / 64 * 64));
-    if (const char* v = std::getenv("DSMC_REORDER")) c->reorder = std::atoi(v) != 0;
+    if (const char* v = std::getenv("DSMC_REORDER")) c->reorder = std::atoi(v);
     if (const char* v = std::getenv("DSMC_SORT")) {
         const std::string k(v);
         c->sort_variant = k == "scatter" ? kSortScatter : k == "fused" ? kSortFused : kSortGather;
@@ -366,7 +366,7 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     }
     HostMesh& hm = c->hm;
     read_tuning(c);
-    if (c->reorder) reorder_cells(hm, bs ? &bs->tet_case : nullptr);
+    if (c->reorder) reorder_cells(hm, bs ? &bs->tet_case : nullptr, c->reorder);
     else {
         hm.orig.resize(hm.nt);
         std::iota(hm.orig.begin(), hm.orig.end(), 0);

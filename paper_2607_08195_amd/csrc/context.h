@@ -93,7 +93,7 @@ struct dsmc_ctx_s {
     int collide_variant = dsmcx::kCollideG3k;
     int sort_variant = dsmcx::kSortGather;
     int32_t* d_sortperm = nullptr;
-    bool reorder = true;
+    int reorder = 2;  // cell order: 0 caller's, 1 Morton, 2 Hilbert
     // host view
     int64_t np_bound = 0;
     // profiling

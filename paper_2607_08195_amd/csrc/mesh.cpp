@@ -208,9 +208,36 @@ inline uint64_t spread3(uint64_t v) {
     v = (v | (v << 2)) & 0x1249249249249249ull;
     return v;
 }
+
+// Hilbert curve index of 21-bit coordinates (Skilling, "Programming the
+// Hilbert curve", 2004: the axes are turned into the curve's transposed
+// index by undoing the excess work of the Gray code level by level, then
+// Gray-encoded; interleaving the transposed words gives the index).
+inline uint64_t hilbert3(uint32_t x, uint32_t y, uint32_t z) {
+    uint32_t X[3] = {x, y, z};
+    const uint32_t M = 1u << 20;
+    for (uint32_t Q = M; Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    for (int i = 1; i < 3; ++i) X[i] ^= X[i - 1];
+    uint32_t t = 0;
+    for (uint32_t Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    return (spread3(X[0]) << 2) | (spread3(X[1]) << 1) | spread3(X[2]);
+}
 }  // namespace
 
-void reorder_cells(HostMesh& m, const std::vector<int32_t>* group) {
+void reorder_cells(HostMesh& m, const std::vector<int32_t>* group, int curve) {
     const int nt = m.nt;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     std::vector<double> cen(3 * (size_t)nt);
@@ -228,12 +255,14 @@ void reorder_cells(HostMesh& m, const std::vector<int32_t>* group) {
     std::vector<uint64_t> key(nt);
     for (int t = 0; t < nt; ++t) {
         uint64_t k = 0;
+        uint32_t qv[3];
         for (int i = 0; i < 3; ++i) {
             double q = (cen[3 * (size_t)t + i] - lo[i]) / ext * 2097151.0;
             uint64_t qi = (uint64_t)std::min(2097151.0, std::max(0.0, q));
+            qv[i] = (uint32_t)qi;
             k |= spread3(qi) << i;
         }
-        key[t] = k;
+        key[t] = curve == 2 ? hilbert3(qv[0], qv[1], qv[2]) : k;
     }
     m.orig.resize(nt);
     std::iota(m.orig.begin(), m.orig.end(), 0);

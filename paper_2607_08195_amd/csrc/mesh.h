@@ -42,6 +42,7 @@ std::string build_mesh(HostMesh& m, int nv, const double* xyz, int nt, const int
 // internal numbering changes: every interface keeps the caller's ids.
 // With `group` (one value per tet, caller numbering), tets are ordered by
 // group first, so each group stays contiguous.
-void reorder_cells(HostMesh& m, const std::vector<int32_t>* group = nullptr);
+// curve 1: Morton (Z-order) of the centroids, 2: Hilbert.
+void reorder_cells(HostMesh& m, const std::vector<int32_t>* group = nullptr, int curve = 1);
 
 }  // namespace dsmcx
