@@ -247,3 +247,34 @@ def test_free_molecular_sphere_drag():
     s = u / math.sqrt(2 * KB * T / m)
     D = _sphere_cd(s, Tw, T) * 0.5 * n * m * u * u * math.pi * 0.25
     assert abs(ref[0] / D - 1) < 0.05
+
+
+def test_cavity_surface_sums_conserve_energy_and_momentum():
+    """A closed lid-driven cavity at steady state: the gas's energy and
+    momentum do not change, so what all walls receive sums to zero (the lid
+    does work on the gas that the other walls take back as heat; the lid's
+    drag is balanced by the other walls), within the batch noise, while the
+    individual walls carry clearly nonzero shares."""
+    wl = W.cavity(n_hex=4, Kn=0.1, ppc=20, lid_speed=300.0, vel_fp32=0)
+    o = Oracle(wl)
+    o.step(300)
+    m, FN, dt = wl.species.mass, wl.run.F_N, wl.run.dt
+    tot_e, tot_p, lid_e, lid_px = [], [], [], []
+    for _ in range(12):
+        o.surface_sampling(True)
+        o.step(25)
+        sums, ns = o.surface()
+        t = ns * dt
+        tot_e.append(m * FN * sums[:, 3].sum() / t)
+        tot_p.append(m * FN * sums[:, :3].sum(axis=0) / t)
+        lid = wl.mesh.bgroup == 3
+        lid_e.append(m * FN * sums[lid, 3].sum() / t)
+        lid_px.append(m * FN * sums[lid, 0].sum() / t)
+    E, seE = batch_stat(tot_e)
+    P, seP = batch_stat(tot_p)
+    LE, seLE = batch_stat(lid_e)
+    LP, seLP = batch_stat(lid_px)
+    # the lid gives energy to the gas and is dragged back (-x) by it
+    assert LE < -5 * seLE and LP < -5 * seLP, (LE, seLE, LP, seLP)
+    assert abs(E) < 3.5 * seE + 0.02 * abs(LE), (E, seE, LE)
+    assert (np.abs(P) < 3.5 * seP + 0.02 * abs(LP)).all(), (P, seP, LP)
