@@ -158,3 +158,19 @@ def test_surface_batch_matches_oracle_per_case(D):
         b0 += nb
     assert b0 == len(gs)
     g.close()
+
+
+def test_surface_off_by_default(D):
+    """Without surface sampling switched on the sums stay empty: zero sums,
+    zero fields and no sampled steps, also after steps."""
+    wl = W.cavity(n_hex=3, Kn=0.5, ppc=10, vel_fp32=1)
+    wl.run.n_ss = 0
+    g = D.Simulation(wl)
+    g.step(3)
+    s, f, n = g.surface()
+    assert n == 0 and not s.any() and not f.any()
+    g.surface_sampling(False)          # stopping while off is allowed and changes nothing
+    g.step(1)
+    s, f, n = g.surface()
+    assert n == 0 and not s.any()
+    g.close()
