@@ -342,3 +342,24 @@ def test_accelerated_solve_reaches_the_plain_steady_state(dsmc):
     d = np.abs(a - b).max(axis=0) / np.abs(b).max(axis=0)
     assert np.all(d <= 1e-4), d
     g.close()
+
+
+def test_couple_on_hypersonic_sphere_fails_as_the_oracle(dsmc):
+    """The coupling step on the hypersonic sphere (inflow, outflow, diffuse
+    sphere, cells without samples in the wake): the gate's counts match the
+    oracle's, and the central-flux solve reaches a non-physical state in its
+    first iteration on both sides, so the feedback is skipped and the
+    particles are left as they were."""
+    wl = W.sphere_flow(N=4, K=3, ppc=10, vel_fp32=0)
+    o, g = _pair(dsmc, wl, steps=40, n_a=50)
+    n0 = g.state(particles=False)["n"]
+    kw = dict(kn_max=0.93, passes=3, n_m=40, eps_m=0.0, cfl=0.5, feedback=1)
+    rg = g.dig_couple(**kw)
+    ro = o.dig_couple(**kw)
+    for k in ["n_rejected", "n_reconstructed", "n_unreached", "iters", "converged", "failed", "np_before",
+              "np_after"]:
+        assert rg[k] == ro[k], (k, rg[k], ro[k])
+    assert rg["failed"] == 1 and rg["np_after"] == n0
+    gs, os_ = g.state(), o.particles()
+    assert np.array_equal(gs["cell"], os_["cell"]) and np.array_equal(gs["pid"], os_["pid"])
+    g.close()
