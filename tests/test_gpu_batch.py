@@ -354,3 +354,24 @@ def test_ensemble64_half_coupled_smallest_cases_match_oracle(D):
         compare_sums(sums[begin[k]:begin[k + 1]], o.sums(0), rel=1e-9)
     net.close()
     g.close()
+
+
+def test_batch_coupling_with_no_case_enabled_changes_nothing(D):
+    """All cases of a batch disabled: the coupling step runs its gate and
+    leaves every particle, the local-accumulation flags and the particle
+    count as they were."""
+    cases = _cases(1)
+    for wl in cases:
+        wl.run.ewma_on = 1
+        wl.run.n_a = 50
+    g = D.Simulation(cases)
+    g.step(20)
+    st0 = g.state()
+    g.dig_enable([0] * len(cases))
+    r = g.dig_couple(kn_max=0.93, passes=3, n_m=20, eps_m=0.0, cfl=0.5, feedback=1)
+    assert not r["failed"] and r["np_after"] == r["np_before"] == st0["n"]
+    st1 = g.state()
+    for k in ["x", "v", "cell", "pid"]:
+        assert np.array_equal(st0[k], st1[k]), k
+    g.step(2)
+    g.close()
