@@ -37,12 +37,12 @@ std::string build_mesh(HostMesh& m, int nv, const double* xyz, int nt, const int
                        int nb, const int32_t* bface, const int32_t* bgroup,
                        const int32_t* bpartner, int ngroups);
 
-// Renumber the tets along a Morton (Z-order) curve of their centroids so
-// that cells close in space are close in memory; fills orig/inv.  Only
-// internal numbering changes: every interface keeps the caller's ids.
-// With `group` (one value per tet, caller numbering), tets are ordered by
-// group first, so each group stays contiguous.
-// curve 1: Morton (Z-order) of the centroids, 2: Hilbert.
+// Renumber the tets along a space-filling curve of their centroids (curve
+// 1: Morton / Z-order, 2: Hilbert) so that cells close in space are close
+// in memory; fills orig/inv.  Only internal numbering changes: every
+// interface keeps the caller's ids.  With `group` (one value per tet,
+// caller numbering), tets are ordered by group first, so each group stays
+// contiguous.
 void reorder_cells(HostMesh& m, const std::vector<int32_t>* group = nullptr, int curve = 1);
 
 }  // namespace dsmcx
