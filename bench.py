@@ -47,7 +47,7 @@ BYTES = {
 # rocprofv3 --pmc measurements of the move kernel (FETCH_SIZE + WRITE_SIZE per
 # dispatch, scaled by the copy-kernel calibration) and the source digest they
 # were taken on; the traffic figure is reported only while the digest matches.
-TRAFFIC = {"kernel": "move", "digest": "6f015e485dfe4158", "bytes_per_launch": 576428231 + 580710282,
+TRAFFIC = {"kernel": "move", "digest": "a2255ca527a6ad13", "bytes_per_launch": 576308342 + 580642304,
            "source": "profiles/step_kernels_cavity40.md"}
 
 
@@ -70,6 +70,23 @@ def cpu_baseline(wl, steps):
     return dict(value=n * steps / dt, unit="particle-steps/s", cores=1, kind="oracle",
                 sample=f"{wl.name}: {steps} steps from the initial fill ({n * steps:.3g} particle-steps, "
                        f"{dt:.1f} s, 1 thread)")
+
+
+def copy_rate(sim, nbytes=1 << 30, reps=5):
+    """Read + write GB/s of the library's plain copy kernel on nbytes each
+    way: the bandwidth a streaming kernel achieves on this GPU."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    sim.device_copy(dst.data_ptr(), src.data_ptr(), nbytes)
+    sim.sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.device_copy(dst.data_ptr(), src.data_ptr(), nbytes)
+    sim.sync()
+    dt = (time.perf_counter() - t0) / reps
+    del src, dst
+    return 2 * nbytes / dt / 1e9
 
 
 def calibrate_copy(dsmc, W, nbytes=2 << 30, reps=10):
@@ -532,6 +549,7 @@ def main():
     roofline = dict(bound="hbm", kernel=dominant, achieved=round(gbs[dominant], 1), peak=peak, unit="GB/s",
                     frac=round(gbs[dominant] / peak, 4),
                     traffic=None if traffic is None else round(traffic, 1))
+    copy_gbs = copy_rate(sim)
 
     out = {
         "metric": "particle-steps/s",
@@ -554,6 +572,7 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in per_launch.items()},
         "kernel_GBps": {k: round(v, 1) for k, v in gbs.items()},
         "roofline": roofline,
+        "copy_kernel_GBps": round(copy_gbs, 1),
         "kernel_digest": digest,
     }
     sim.close()
