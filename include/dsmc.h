@@ -135,7 +135,15 @@ dsmc_status dsmc_step(dsmc_ctx ctx, int32_t n_steps);
  * 8 collide, 16 sample); for stage-level testing. */
 dsmc_status dsmc_step_stages(dsmc_ctx ctx, int32_t mask);
 
-enum { DSMC_SAMPLE_STEADY = 0, DSMC_SAMPLE_EWMA = 1 };
+/* Accumulators: STEADY sums every step after n_ss, EWMA is the moving
+ * average, INSTANT holds the sums of the last sampled step alone (kept only
+ * while switched on by dsmc_instant_sampling; zero before). */
+enum { DSMC_SAMPLE_STEADY = 0, DSMC_SAMPLE_EWMA = 1, DSMC_SAMPLE_INSTANT = 2 };
+
+/* on = 1: from the next step on, every sampled step also stores its own
+ * moment sums (DSMC_SAMPLE_INSTANT; 104 bytes per cell and step); 0 stops
+ * (the last sums are kept).  Synchronises. */
+dsmc_status dsmc_instant_sampling(dsmc_ctx ctx, int32_t on);
 
 /* Cell fields from an accumulator (eq. dsmc_temperatures over the sampled
  * steps): out[n_tets][15] = n, rho, u(3), T, sigma(xx,yy,zz,xy,xz,yz),
@@ -144,8 +152,8 @@ enum { DSMC_SAMPLE_STEADY = 0, DSMC_SAMPLE_EWMA = 1 };
 dsmc_status dsmc_sample(dsmc_ctx ctx, int32_t which, double* out, int32_t out_on_device);
 
 /* Raw moment sums out[n_tets][13] = S0, S1(3), S2(xx,yy,zz,xy,xz,yz), S3(3)
- * of an accumulator, and the number of steps summed (steady) into
- * *n_samples.  Synchronises. */
+ * of an accumulator, and the number of steps summed (steady; 1 for
+ * INSTANT) into *n_samples.  Synchronises. */
 dsmc_status dsmc_get_sums(dsmc_ctx ctx, int32_t which, double* out, int64_t* n_samples);
 
 /* Surface sampling (the wall pressure, shear stress and heat flux the

@@ -172,6 +172,7 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
         cp.key = c->key; cp.FN = c->FN; cp.dt = c->dt; cp.K = c->K; cp.ex = c->ex;
         cp.vol = c->d_vol; cp.smax = c->d_smax; cp.ncand = c->d_ncand; cp.nacc = c->d_nacc;
         cp.acc = c->d_acc; cp.ewma = c->d_ewma; cp.ewma_m = c->d_ewma_m; cp.local_acc = c->d_local;
+        cp.inst = c->inst_on ? c->d_inst : nullptr;
         cp.orig = c->d_orig;
         cp.cell_case = c->d_cell_case;
         cp.cases = c->d_cases;
@@ -241,7 +242,8 @@ void read_tuning(dsmc_ctx c) {
 
 
 int tuning_sig(dsmc_ctx c) {
-    return c->move_variant | (c->collide_variant << 8) | (c->sort_variant << 12) | (c->mesh.surf ? 1 << 16 : 0);
+    return c->move_variant | (c->collide_variant << 8) | (c->sort_variant << 12) | (c->mesh.surf ? 1 << 16 : 0) |
+           (c->inst_on ? 1 << 17 : 0);
 }
 
 void drop_graph(dsmc_ctx_s::Graph& g) {
@@ -773,14 +775,35 @@ dsmc_status dsmc_sync(dsmc_ctx c) {
     return sync_scalars(c, nullptr);
 }
 
+// The device array of an accumulator (INSTANT: allocated and cleared on
+// first use).
+static const double* accumulator(dsmc_ctx c, int32_t which) {
+    if (which == DSMC_SAMPLE_STEADY) return c->d_acc;
+    if (which == DSMC_SAMPLE_EWMA) return c->d_ewma;
+    if (!c->d_inst) {
+        if (!alloc_n(c, c->d_inst, (size_t)kNMom * c->nt)) return nullptr;
+        launch_fill_f64(c->stream, c->d_inst, 0.0, (int64_t)kNMom * c->nt);
+    }
+    return c->d_inst;
+}
+
+dsmc_status dsmc_instant_sampling(dsmc_ctx c, int32_t on) {
+    if (!c) return fail(c, DSMC_E_INVALID, "NULL context");
+    if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
+    if (on && !accumulator(c, DSMC_SAMPLE_INSTANT)) return fail(c, DSMC_E_OOM, "device allocation failed");
+    c->inst_on = on != 0;
+    return sync_scalars(c, nullptr);
+}
+
 dsmc_status dsmc_sample(dsmc_ctx c, int32_t which, double* out, int32_t out_on_device) {
-    if (!c || !out || (which != DSMC_SAMPLE_STEADY && which != DSMC_SAMPLE_EWMA))
+    if (!c || !out || (which != DSMC_SAMPLE_STEADY && which != DSMC_SAMPLE_EWMA && which != DSMC_SAMPLE_INSTANT))
         return fail(c, DSMC_E_INVALID, "bad arguments");
     Scalars sc;
     dsmc_status st = sync_scalars(c, &sc);
     if (st != DSMC_OK) return st;
     const double ns = which == DSMC_SAMPLE_STEADY ? (double)sc.n_steady : 1.0;
-    const double* src = which == DSMC_SAMPLE_STEADY ? c->d_acc : c->d_ewma;
+    const double* src = accumulator(c, which);
+    if (!src) return fail(c, DSMC_E_OOM, "device allocation failed");
     double* dout = out;
     double* tmp = nullptr;
     if (!out_on_device) {
@@ -870,17 +893,18 @@ dsmc_status dsmc_get_surface(dsmc_ctx c, double* sums, double* fields, int64_t* 
 }
 
 dsmc_status dsmc_get_sums(dsmc_ctx c, int32_t which, double* out, int64_t* n_samples) {
-    if (!c || !out || (which != DSMC_SAMPLE_STEADY && which != DSMC_SAMPLE_EWMA))
+    if (!c || !out || (which != DSMC_SAMPLE_STEADY && which != DSMC_SAMPLE_EWMA && which != DSMC_SAMPLE_INSTANT))
         return fail(c, DSMC_E_INVALID, "bad arguments");
+    const double* src = accumulator(c, which);
+    if (!src) return fail(c, DSMC_E_OOM, "device allocation failed");
     Scalars sc;
     dsmc_status st = sync_scalars(c, &sc);
     if (st != DSMC_OK) return st;
     std::vector<double> h((size_t)kNMom * c->nt);
-    HIP_TRY(c, hipMemcpy(h.data(), which == DSMC_SAMPLE_STEADY ? c->d_acc : c->d_ewma, sizeof(double) * h.size(),
-                         hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(h.data(), src, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
     for (int t = 0; t < c->nt; ++t)
         for (int k = 0; k < kNMom; ++k) out[(size_t)kNMom * c->hm.orig[t] + k] = h[(size_t)k * c->nt + t];
-    if (n_samples) *n_samples = sc.n_steady;
+    if (n_samples) *n_samples = which == DSMC_SAMPLE_INSTANT ? 1 : sc.n_steady;
     return DSMC_OK;
 }
 

@@ -58,6 +58,9 @@ struct dsmc_ctx_s {
     // surface sampling: [5][nb] sums (mesh.surf points here while on) and the
     // step window (to < 0: still running)
     double* d_surf = nullptr;
+    // instantaneous sums ([13][nt], the last sampled step) while on
+    double* d_inst = nullptr;
+    bool inst_on = false;
     int64_t surf_from = 0, surf_to = -1;
     int4* d_tv = nullptr;
     double* d_xyz = nullptr;

@@ -99,6 +99,7 @@ struct CollideParams {
     int32_t* nacc;
     double* acc;        // [13][nt] steady sums
     double* ewma;       // [13][nt] moving average
+    double* inst;       // [13][nt] sums of the step alone, or null
     int32_t* ewma_m;    // [nt] samples seen
     const uint8_t* local_acc;
     const int32_t* orig;  // [nt] caller's cell id (generator subject)

@@ -1034,6 +1034,10 @@ __device__ __forceinline__ void sample_cell(const Acc& cv, int N, int c, const C
         S[10] += vx * v2; S[11] += vy * v2; S[12] += vz * v2;
     }
     const int64_t nt = cp.nt;
+    if (cp.inst) {
+#pragma unroll
+        for (int k = 0; k < kNMom; ++k) cp.inst[k * nt + c] = S[k];
+    }
     if ((int64_t)step > (int64_t)cp.n_ss) {
 #pragma unroll
         for (int k = 0; k < kNMom; ++k) cp.acc[k * nt + c] += S[k];

@@ -20,7 +20,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 STAGE_MOVE, STAGE_INJECT, STAGE_SORT, STAGE_COLLIDE, STAGE_SAMPLE = 1, 2, 4, 8, 16
-SAMPLE_STEADY, SAMPLE_EWMA = 0, 1
+SAMPLE_STEADY, SAMPLE_EWMA, SAMPLE_INSTANT = 0, 1, 2
 STATUS = {0: "OK", -1: "INVALID", -2: "MESH", -3: "OOM", -4: "DEVICE", -5: "CAPACITY", -6: "LOST",
           -7: "NOT_CONVERGED"}
 
@@ -162,6 +162,7 @@ _lib.dig_set_closure.argtypes = [ctx_t, P, C.c_double]
 _lib.dig_closure_data.argtypes = [ctx_t, P, P, P]
 _lib.dig_batch_enable.argtypes = [ctx_t, P]
 _lib.dsmc_surface_sampling.argtypes = [ctx_t, C.c_int32]
+_lib.dsmc_instant_sampling.argtypes = [ctx_t, C.c_int32]
 _lib.dsmc_get_surface.argtypes = [ctx_t, P, P, C.POINTER(C.c_int64)]
 for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_state",
            "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
@@ -169,7 +170,7 @@ for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_ge
            "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
            "dsmc_mlp_get_weights", "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train",
            "dsmc_mlp_init_weights", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_surface_sampling", "dsmc_get_surface",
-           "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
+           "dsmc_instant_sampling", "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
            "dsmc_get_tuning", "dsmc_set_tuning", "dsmc_autotune"]:
     getattr(_lib, _f).restype = C.c_int32
 
@@ -180,7 +181,7 @@ EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_g
             "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights", "dsmc_mlp_get_weights",
             "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train", "dsmc_mlp_last_error",
             "dsmc_mlp_destroy", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_surface_sampling",
-            "dsmc_get_surface"]
+            "dsmc_get_surface", "dsmc_instant_sampling"]
 
 
 class DsmcError(RuntimeError):
@@ -369,6 +370,10 @@ class Simulation:
         sm = np.ascontiguousarray(smax, np.float64) if smax is not None else None
         st = State(len(cell), _p(x), _p(v), _p(cell), _p(pid), _p(sm), step, next_pid)
         self._c(_lib.dsmc_set_state(self.ctx, C.byref(st)))
+
+    def instant_sampling(self, on=True):
+        """Keep the moment sums of each sampled step (SAMPLE_INSTANT)."""
+        self._c(_lib.dsmc_instant_sampling(self.ctx, 1 if on else 0))
 
     def surface_sampling(self, on=True):
         """Start (clearing the sums) or stop surface sampling (include/dsmc.h)."""
