@@ -30,6 +30,9 @@ def _load():
     lib.oracle_create.argtypes = [i, P, i, P, i, P, P, P, i, P, P, P, P, P,
                                   d, d, d, d, d, d, u32, u32, i, i, i, i]
     lib.oracle_last_error.restype = C.c_char_p
+    lib.oracle_set_alpha.argtypes = [P, d]
+    lib.oracle_viscosity.restype = d
+    lib.oracle_viscosity.argtypes = [P, d]
     lib.oracle_destroy.argtypes = [P]
     lib.oracle_init_fill.argtypes = [P, d, d, P]
     lib.oracle_step.argtypes = [P, i]
@@ -146,6 +149,8 @@ class Oracle:
             run.seed & 0xFFFFFFFF, run.case_id, run.vel_fp32, run.n_ss, run.n_a, run.ewma_on)
         if not self.h:
             raise ValueError("oracle_create: " + lib.oracle_last_error().decode())
+        if lib.oracle_set_alpha(self.h, float(sp.alpha)) != 0:
+            raise ValueError("oracle_set_alpha: " + lib.oracle_last_error().decode())
         self.wl = wl
         if fill:
             u0 = np.asarray(run.u0, dtype=np.float64)
@@ -159,6 +164,9 @@ class Oracle:
     # -- stepping ---------------------------------------------------------
     def step(self, n=1):
         self.lib.oracle_step(self.h, n)
+
+    def viscosity(self, T):
+        return self.lib.oracle_viscosity(self.h, float(T))
 
     def step_stages(self, mask):
         self.lib.oracle_step_stages(self.h, mask)

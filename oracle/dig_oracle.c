@@ -37,11 +37,17 @@
 
 enum { L_INTERIOR = 0, L_PERIODIC = 1, L_WALL = 2, L_SPECULAR = 3, L_INFLOW = 4, L_OUTFLOW = 5 };
 
+/* Reference viscosity of the VHS/VSS molecule (Bird 1994, the model that
+ * section 2.1 cites): the hard-sphere-like Chapman-Enskog value times
+ * (alpha+1)(alpha+2)/(6 alpha), which is exactly 1 for VHS scattering. */
 static double mu_ref_of(const osim* s) {
-    double w = s->omega;
-    return 15.0 * sqrt(M_PI * s->m * KB * s->Tref) / (2.0 * M_PI * s->dref * s->dref * (5.0 - 2.0 * w) * (7.0 - 2.0 * w));
+    double w = s->omega, a = s->alpha;
+    double vss = ((a + 1.0) * (a + 2.0)) / (6.0 * a);
+    return 15.0 * sqrt(M_PI * s->m * KB * s->Tref) / (2.0 * M_PI * s->dref * s->dref * (5.0 - 2.0 * w) * (7.0 - 2.0 * w)) *
+           vss;
 }
 static double mu_of(const osim* s, double T) { return mu_ref_of(s) * pow(T / s->Tref, s->omega); }
+double oracle_viscosity(const osim* s, double T) { return mu_of(s, T); }
 static double kappa_of(const osim* s, double mu) { return 15.0 * KB * mu / (4.0 * s->m); }
 
 void oracle_set_reference(osim* s, double n0, double T0, const double* u0) {

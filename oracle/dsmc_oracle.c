@@ -138,6 +138,7 @@ osim* oracle_create(int nv, const double* xyz, int nt, const int* tet,
                     int vel_fp32, int n_ss, int n_a, int ewma_on) {
     osim* s = (osim*)calloc(1, sizeof(osim));
     s->m = mass; s->dref = d_ref; s->omega = omega; s->Tref = T_ref;
+    s->alpha = 1.0;
     s->FN = F_N; s->dt = dt; s->seed = seed; s->case_id = case_id;
     s->vel_fp32 = vel_fp32; s->n_ss = n_ss; s->n_a = n_a; s->ewma_on = ewma_on;
     s->nv = nv; s->nt = nt; s->nb = nb; s->ng = ng;
@@ -673,8 +674,48 @@ static void stage_inject(osim* s) {
 }
 
 /* ------------------------------------------------------------------ */
-/* NTC collisions, VHS                                                  */
+/* NTC collisions, VHS / VSS                                            */
 /* ------------------------------------------------------------------ */
+/* Post-collision relative velocity g' (|g'| = |g| = c_r) from the two
+ * uniform deviates R1 (deflection) and R2 (azimuth).
+ * VHS (alpha = 1): g' is isotropic, cos(theta) = 2 R1 - 1 about the x axis,
+ * independent of g.
+ * VSS (section 2.1 cites Bird 1994 for the model): the deflection chi from g
+ * obeys b/d = cos(chi/2)^(1/alpha) with (b/d)^2 uniform, so
+ * cos(chi) = 2 R1^(1/alpha) - 1; g' is g turned by chi at azimuth
+ * eps = 2 pi R2, in the frame (g/c_r, e1, e2) with
+ *   e1 = (0, g_z, -g_y) / g_yz,   e2 = (g_yz^2, -g_x g_y, -g_x g_z) / (c_r g_yz),
+ *   g_yz = sqrt(g_y^2 + g_z^2),
+ * that is g' = cos(chi) g + sin(chi) c_r (sin(eps) e2 + cos(eps) e1), Bird's
+ * rotation written as a frame.  When g_yz = 0 (g along x), e1 = y, e2 = z. */
+static void scatter(const osim* s, double gx, double gy, double gz, double cr2, double R1, double R2,
+                    double gp[3]) {
+    double cr = sqrt(cr2);
+    double eps = TWO_PI * R2;
+    if (s->alpha == 1.0) {
+        double cx = 2.0 * R1 - 1.0;
+        double sx = sqrt(1.0 - cx * cx);
+        gp[0] = cr * cx;
+        gp[1] = cr * (sx * cos(eps));
+        gp[2] = cr * (sx * sin(eps));
+        return;
+    }
+    double cc = 2.0 * pow(R1, 1.0 / s->alpha) - 1.0;
+    double sc = sqrt(1.0 - cc * cc);
+    double ce = cos(eps), se = sin(eps);
+    double gyz = sqrt(gy * gy + gz * gz);
+    double e1[3], e2[3];
+    if (gyz > 0.0) {
+        e1[0] = 0.0; e1[1] = gz / gyz; e1[2] = -gy / gyz;
+        e2[0] = gyz / cr; e2[1] = -(gx * gy) / (cr * gyz); e2[2] = -(gx * gz) / (cr * gyz);
+    } else {
+        e1[0] = 0.0; e1[1] = 1.0; e1[2] = 0.0;
+        e2[0] = 0.0; e2[1] = 0.0; e2[2] = 1.0;
+    }
+    double g[3] = {gx, gy, gz};
+    for (int d = 0; d < 3; ++d) gp[d] = cc * g[d] + (sc * cr) * (se * e2[d] + ce * e1[d]);
+}
+
 static void stage_collide(osim* s) {
     uint32_t w[4];
     for (int c = 0; c < s->nt; ++c) {
@@ -705,11 +746,8 @@ static void stage_collide(osim* s) {
             if (!(U < sc / smax)) continue;
             ++acc;
             draw(s, (uint32_t)c, s->step, P_SCATTER, (uint64_t)k, w);
-            double cx = 2.0 * u01(w[0], w[1]) - 1.0;
-            double sx = sqrt(1.0 - cx * cx);
-            double eps = TWO_PI * u01(w[2], w[3]);
-            double cr = sqrt(cr2);
-            double gp[3] = {cr * cx, cr * (sx * cos(eps)), cr * (sx * sin(eps))};
+            double gp[3];
+            scatter(s, gx, gy, gz, cr2, u01(w[0], w[1]), u01(w[2], w[3]), gp);
             for (int d = 0; d < 3; ++d) {
                 double cm = 0.5 * (vi[d] + vj[d]);
                 double hg = 0.5 * gp[d];
@@ -795,6 +833,15 @@ int oracle_set_particles(osim* s, int64_t np, const double* x, const double* v, 
     s->step = step;
     s->next_pid = next_pid;
     stage_sort(s);
+    return 0;
+}
+
+int oracle_set_alpha(osim* s, double alpha) {
+    if (!(alpha > 0.0)) {
+        set_err("alpha must be positive");
+        return -1;
+    }
+    s->alpha = alpha;
     return 0;
 }
 

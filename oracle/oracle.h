@@ -54,6 +54,11 @@ int64_t oracle_num_particles(const osim*);
 void oracle_get_particles(const osim*, double* x, double* v, int* cell, uint32_t* pid);
 int oracle_set_particles(osim*, int64_t np, const double* x, const double* v,
                          const int* cell, const uint32_t* pid, uint32_t step, uint32_t next_pid);
+/* VSS scattering exponent (section 2.1; 1, the default, is VHS).  Also
+ * scales the viscosity the continuum side uses.  -1 unless alpha > 0. */
+int oracle_set_alpha(osim*, double alpha);
+/* Viscosity of the species at temperature T (VHS/VSS power law). */
+double oracle_viscosity(const osim*, double T);
 void oracle_get_smax(const osim*, double* out);
 void oracle_set_smax(osim*, const double* in);
 uint32_t oracle_step_index(const osim*);

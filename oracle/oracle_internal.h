@@ -19,6 +19,7 @@ enum { P_INIT = 1, P_WALL = 2, P_INJCOUNT = 3, P_NTCCOUNT = 4, P_PAIR = 5, P_SCA
 struct osim {
     /* species */
     double m, dref, omega, Tref, K, ex;
+    double alpha;       /* VSS scattering exponent; 1 is VHS (isotropic) */
     /* run */
     double FN, dt;
     uint32_t seed, case_id;

@@ -33,11 +33,12 @@ class Species:
     alpha: float = 1.0          # 1 = VHS
 
     def mu(self, T):
-        """VHS viscosity at temperature T (power law in T with index omega,
-        coefficient from the hard-sphere-like reference diameter)."""
-        m, d, w = self.mass, self.d_ref, self.omega
+        """VHS/VSS viscosity at temperature T (power law in T with index
+        omega, coefficient from the reference diameter; VSS scattering scales
+        it by (alpha+1)(alpha+2)/(6 alpha), Bird 1994)."""
+        m, d, w, a = self.mass, self.d_ref, self.omega, self.alpha
         mu_ref = 15.0 * math.sqrt(math.pi * m * KB * self.T_ref) / (
-            2.0 * math.pi * d * d * (5.0 - 2.0 * w) * (7.0 - 2.0 * w))
+            2.0 * math.pi * d * d * (5.0 - 2.0 * w) * (7.0 - 2.0 * w)) * ((a + 1.0) * (a + 2.0) / (6.0 * a))
         return mu_ref * (T / self.T_ref) ** w
 
 
