@@ -69,14 +69,20 @@ typedef struct {
     const int32_t* bface_partner;
 } dsmc_mesh_desc;
 
-/* Variable hard sphere species (paper section 5: VHS collision model,
- * power-law viscosity index omega).  alpha must be 1 (VHS scattering). */
+/* Variable hard / soft sphere species (paper section 5: VHS collision
+ * model, power-law viscosity index omega; section 2.1: VSS).  The total
+ * cross-section is the VHS one of d_ref for every alpha.  alpha = 1 scatters
+ * isotropically (VHS); otherwise the deflection chi from the pre-collision
+ * relative velocity has cos(chi) = 2 R^(1/alpha) - 1 with R uniform and a
+ * uniform azimuth (VSS, Bird 1994), and the viscosity the continuum side
+ * uses is the VHS value times (alpha+1)(alpha+2)/(6 alpha).  alpha must be
+ * positive (DSMC_E_INVALID otherwise). */
 typedef struct {
     double mass;     /* kg */
     double d_ref;    /* reference diameter, m */
     double omega;    /* viscosity index */
     double T_ref;    /* reference temperature of d_ref, K */
-    double alpha;    /* scattering parameter; only 1 is supported */
+    double alpha;    /* VSS scattering exponent; 1 = VHS */
 } dsmc_species_desc;
 
 typedef enum {

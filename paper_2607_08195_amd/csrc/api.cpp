@@ -170,6 +170,7 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
         CollideParams cp;
         cp.nt = c->nt; cp.n_ss = c->n_ss; cp.n_a = c->n_a; cp.ewma_on = c->ewma_on;
         cp.key = c->key; cp.FN = c->FN; cp.dt = c->dt; cp.K = c->K; cp.ex = c->ex;
+        cp.vss = c->alpha != 1.0; cp.inv_alpha = 1.0 / c->alpha;
         cp.vol = c->d_vol; cp.smax = c->d_smax; cp.ncand = c->d_ncand; cp.nacc = c->d_nacc;
         cp.acc = c->d_acc; cp.ewma = c->d_ewma; cp.ewma_m = c->d_ewma_m; cp.local_acc = c->d_local;
         cp.inst = c->inst_on ? c->d_inst : nullptr;
@@ -343,8 +344,8 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     *out = nullptr;
     if (!mesh || !sp || !run || (n_bc > 0 && !bcs) || n_bc < 0)
         return fail(nullptr, DSMC_E_INVALID, "NULL descriptor");
-    if (sp->alpha != 1.0) return fail(nullptr, DSMC_E_INVALID, "only VHS scattering (alpha = 1) is supported");
-    if (!(sp->mass > 0) || !(sp->d_ref > 0) || !(sp->T_ref > 0) || !(run->F_N > 0) || !(run->dt > 0))
+    if (!(sp->mass > 0) || !(sp->d_ref > 0) || !(sp->T_ref > 0) || !(sp->alpha > 0) || !(run->F_N > 0) ||
+        !(run->dt > 0))
         return fail(nullptr, DSMC_E_INVALID, "non-positive physical parameter");
     if (run->n_a < 1) return fail(nullptr, DSMC_E_INVALID, "n_a must be >= 1");
     for (int g = 0; g < n_bc; ++g)
@@ -383,6 +384,7 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
         }
 
     c->mass = sp->mass; c->dref = sp->d_ref; c->omega = sp->omega; c->Tref = sp->T_ref;
+    c->alpha = sp->alpha;
     const double mr = sp->mass / 2.0;
     c->K = ((M_PI * sp->d_ref) * sp->d_ref) * std::pow(((2.0 * kBoltzmann) * sp->T_ref) / mr, sp->omega - 0.5) /
            std::tgamma(2.5 - sp->omega);

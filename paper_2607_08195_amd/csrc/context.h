@@ -42,6 +42,7 @@ struct dsmc_ctx_s {
     int nt = 0, nb = 0;
     // species / run
     double mass = 0, dref = 0, omega = 0, Tref = 0, K = 0, ex = 0;
+    double alpha = 1;   // VSS scattering exponent (1: VHS)
     double FN = 0, dt = 0, n0 = 0, T0 = 0, u0[3] = {0, 0, 0};
     dsmcx::RngKey key{0, 0};
     int vel64 = 0, n_ss = 0, n_a = 1000, ewma_on = 0;

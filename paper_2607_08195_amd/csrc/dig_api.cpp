@@ -130,11 +130,13 @@ void build_geometry(const HostMesh& m, const std::vector<dsmc_boundary_desc>& bc
     }
 }
 
-// Viscosity of the VHS gas at T_ref (Chapman-Enskog first approximation).
+// Viscosity of the VHS/VSS gas at T_ref (Chapman-Enskog first
+// approximation); VSS scattering multiplies the VHS value by
+// (alpha+1)(alpha+2)/(6 alpha), exactly 1 at alpha = 1 (Bird 1994).
 double mu_ref_of(dsmc_ctx c) {
-    const double w = c->omega;
+    const double w = c->omega, a = c->alpha;
     return 15.0 * std::sqrt(M_PI * c->mass * kBoltzmann * c->Tref) /
-           (2.0 * M_PI * c->dref * c->dref * (5.0 - 2.0 * w) * (7.0 - 2.0 * w));
+           (2.0 * M_PI * c->dref * c->dref * (5.0 - 2.0 * w) * (7.0 - 2.0 * w)) * (((a + 1.0) * (a + 2.0)) / (6.0 * a));
 }
 
 template <class T>

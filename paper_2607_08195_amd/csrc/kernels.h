@@ -93,6 +93,8 @@ struct CollideParams {
     int n_ss, n_a, ewma_on;
     RngKey key;
     double FN, dt, K, ex;
+    int vss;            // VSS scattering (alpha != 1); else isotropic VHS
+    double inv_alpha;   // 1 / alpha
     const double* vol;
     double* smax;
     int32_t* ncand;

@@ -947,7 +947,48 @@ struct LdsOrderCell {
     }
 };
 
-template <class Acc>
+// Post-collision relative velocity g' (|g'| = |g| = c_r) from two uniform
+// deviates R1 (deflection) and R2 (azimuth eps = 2 pi R2).  VHS: isotropic,
+// cos(theta) = 2 R1 - 1 measured from the x axis, independent of g.  VSS
+// (section 2.1, the model of Bird 1994): the deflection chi from g has
+// cos(chi) = 2 R1^(1/alpha) - 1 and g' = cos(chi) g + sin(chi) c_r
+// (cos(eps) e1 + sin(eps) e2) in the frame e1 = (0, g_z, -g_y) / g_yz,
+// e2 = (g_yz^2, -g_x g_y, -g_x g_z) / (c_r g_yz), g_yz = |(g_y, g_z)|; with
+// g along x (g_yz = 0) e1 and e2 are the y and z axes.  VSS is a template
+// parameter so that the isotropic kernels keep their register budget.
+template <bool VSS>
+__device__ __forceinline__ void scatter_vhs_vss(const CollideParams& cp, double gx, double gy, double gz,
+                                                double cr2, double R1, double R2, double& o0, double& o1,
+                                                double& o2) {
+    const double cr = sqrt(cr2);
+    const double eps = DSMC_TWO_PI * R2;
+    if (!VSS) {
+        const double cx = 2.0 * R1 - 1.0;
+        const double sx = sqrt(1.0 - cx * cx);
+        o0 = cr * cx;
+        o1 = cr * (sx * cos(eps));
+        o2 = cr * (sx * sin(eps));
+        return;
+    }
+    const double cc = 2.0 * pow(R1, cp.inv_alpha) - 1.0;
+    const double sc = sqrt(1.0 - cc * cc);
+    const double ce = cos(eps), se = sin(eps);
+    const double gyz = sqrt(gy * gy + gz * gz);
+    double e10 = 0.0, e11 = 1.0, e12 = 0.0, e20 = 0.0, e21 = 0.0, e22 = 1.0;
+    if (gyz > 0.0) {
+        e11 = gz / gyz;
+        e12 = -gy / gyz;
+        e20 = gyz / cr;
+        e21 = -(gx * gy) / (cr * gyz);
+        e22 = -(gx * gz) / (cr * gyz);
+    }
+    const double scr = sc * cr;
+    o0 = cc * gx + scr * (se * e20 + ce * e10);
+    o1 = cc * gy + scr * (se * e21 + ce * e11);
+    o2 = cc * gz + scr * (se * e22 + ce * e12);
+}
+
+template <bool VSS, class Acc>
 __device__ __forceinline__ void ntc_cell(const Acc& cv, int N, int c, const CollideParams& cp,
                                          uint32_t step, double* smax, int32_t* ncand, int32_t* nacc) {
     int M = 0, acc = 0;
@@ -999,13 +1040,8 @@ __device__ __forceinline__ void ntc_cell(const Acc& cv, int N, int c, const Coll
             if (!take) continue;
             ++acc;
             const Rand4 q = draw(key, subj, step, kPurposeScatter, (uint64_t)k);
-            const double cx = 2.0 * u01(q.w[0], q.w[1]) - 1.0;
-            const double sx = sqrt(1.0 - cx * cx);
-            const double eps = DSMC_TWO_PI * u01(q.w[2], q.w[3]);
-            const double cr = sqrt(cr2);
-            const double gp0 = cr * cx;
-            const double gp1 = cr * (sx * cos(eps));
-            const double gp2 = cr * (sx * sin(eps));
+            double gp0, gp1, gp2;
+            scatter_vhs_vss<VSS>(cp, gx, gy, gz, cr2, u01(q.w[0], q.w[1]), u01(q.w[2], q.w[3]), gp0, gp1, gp2);
             const double cm0 = 0.5 * (a0 + b0), cm1 = 0.5 * (a1 + b1), cm2 = 0.5 * (a2 + b2);
             const double h0 = 0.5 * gp0, h1 = 0.5 * gp1, h2 = 0.5 * gp2;
             cv.put((int)i, cm0 + h0, cm1 + h1, cm2 + h2);
@@ -1056,7 +1092,7 @@ __device__ __forceinline__ void sample_cell(const Acc& cv, int N, int c, const C
     }
 }
 
-template <class VT>
+template <class VT, bool VSS>
 __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p, const int32_t* offsets,
                                                                   CollideParams cp, const Scalars* sc,
                                                                   int32_t* perm, int do_collide,
@@ -1102,7 +1138,7 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
                 sord[s0 + j] = (uint16_t)(s0 + k);
             }
             LdsCell<VT> cv{sv0, sv1, sv2, sord, stouch, s0};
-            if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
+            if (do_collide) ntc_cell<VSS>(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
             if (do_sample) sample_cell(cv, N, c, cp, step);
         }
         __syncthreads();
@@ -1124,7 +1160,7 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
             perm[s0 + r] = (int32_t)(s0 + k);
         }
         GlobalCell<VT> cv{p.vel, perm, s0};
-        if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
+        if (do_collide) ntc_cell<VSS>(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
         if (do_sample) sample_cell(cv, N, c, cp, step);
     }
 }
@@ -1143,7 +1179,7 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
 // workgroup that then collides the chunk, so that gathering one chunk
 // overlaps the collisions of others and the velocities are read back from
 // cache.
-template <class VT, int WPE, int CAP, bool FUSED>
+template <class VT, int WPE, int CAP, bool FUSED, bool VSS>
 __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(WPE))) void k_collide_sample_g(
     PartDev<VT> p, const int32_t* offsets, CollideParams cp, const Scalars* sc, int32_t* perm, int do_collide,
     int do_sample, PartDev<VT> src, const int32_t* sortperm) {
@@ -1226,7 +1262,7 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
                     perm[s0 + r] = (int32_t)(s0 + k);
                 }
                 GlobalCell<VT> cv{p.vel, perm, s0};
-                if (do_collide) ntc_cell(cv, N, cc, cp, step, cp.smax, cp.ncand, cp.nacc);
+                if (do_collide) ntc_cell<VSS>(cv, N, cc, cp, step, cp.smax, cp.ncand, cp.nacc);
                 if (do_sample) sample_cell(cv, N, cc, cp, step);
             }
             k0 = k0 + 1;
@@ -1254,7 +1290,7 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
             const int s0 = soff[lane] - w0;
             const int N = soff[lane + 1] - soff[lane];
             LdsOrderCell<VT> cv{p.vel, sord, s0, a + w0};
-            if (do_collide) ntc_cell(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
+            if (do_collide) ntc_cell<VSS>(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
             if (do_sample) sample_cell(cv, N, c, cp, step);
         }
         k0 = k1;
@@ -1524,15 +1560,15 @@ void launch_gather(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalar
     hipLaunchKernelGGL(k_gather<VT>, dim3(grid8(bound, 256)), dim3(256), 0, s, src, dst, sc, perm);
 }
 
-template <class VT, int WPE, int CAP>
+template <class VT, int WPE, int CAP, bool VSS>
 static void launch_collide_g(hipStream_t s, int nchunk, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
                              const Scalars* sc, int32_t* perm, int do_collide, int do_sample, PartDev<VT> src,
                              const int32_t* sortperm) {
     if (src.pos)
-        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, true>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
+        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, true, VSS>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
                            offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
     else
-        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, false>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
+        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, false, VSS>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
                            offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
 }
 
@@ -1540,22 +1576,34 @@ bool collide_fuses_gather(int variant) {
     return variant == kCollideGlobal || variant == kCollideGlobal8 || variant == kCollideG3k || variant == kCollideG2k;
 }
 
+template <class VT, bool VSS>
+static void launch_collide_v(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
+                             const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant,
+                             PartDev<VT> src, const int32_t* sortperm) {
+    const int nchunk = (cp.nt + kCollideLanes - 1) / kCollideLanes;
+    if (variant == kCollideGlobal)
+        launch_collide_g<VT, 4, kCollideCapG, VSS>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src,
+                                                   sortperm);
+    else if (variant == kCollideGlobal8)
+        launch_collide_g<VT, 8, kCollideCapG, VSS>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src,
+                                                   sortperm);
+    else if (variant == kCollideG3k)
+        launch_collide_g<VT, 4, 3072, VSS>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
+    else if (variant == kCollideG2k)
+        launch_collide_g<VT, 4, 2048, VSS>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
+    else
+        hipLaunchKernelGGL((k_collide_sample<VT, VSS>), dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc,
+                           perm, do_collide, do_sample);
+}
+
 template <class VT>
 void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
                            const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant,
                            PartDev<VT> src, const int32_t* sortperm) {
-    const int nchunk = (cp.nt + kCollideLanes - 1) / kCollideLanes;
-    if (variant == kCollideGlobal)
-        launch_collide_g<VT, 4, kCollideCapG>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
-    else if (variant == kCollideGlobal8)
-        launch_collide_g<VT, 8, kCollideCapG>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
-    else if (variant == kCollideG3k)
-        launch_collide_g<VT, 4, 3072>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
-    else if (variant == kCollideG2k)
-        launch_collide_g<VT, 4, 2048>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
+    if (cp.vss)
+        launch_collide_v<VT, true>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, src, sortperm);
     else
-        hipLaunchKernelGGL(k_collide_sample<VT>, dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc, perm,
-                           do_collide, do_sample);
+        launch_collide_v<VT, false>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, src, sortperm);
 }
 
 void launch_fields(hipStream_t s, const double* sums, int nt, double ns, double mass, double FN,

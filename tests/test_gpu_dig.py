@@ -74,11 +74,13 @@ def _col_close(a, b, rel):
 
 
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("vel_fp32", [0, 1])
-def test_couple_stages_match_oracle(dsmc, vel_fp32):
+@pytest.mark.parametrize("vel_fp32,alpha", [(0, 1.0), (1, 1.0), (0, 1.4)])
+def test_couple_stages_match_oracle(dsmc, vel_fp32, alpha):
     """Sampled state, Kn_Delta, gate, HoT, solve and report of one coupling
-    cycle without feedback."""
+    cycle without feedback; alpha = 1.4 (VSS) changes the viscosity that
+    Kn_Delta and the constitutive relations use, and the scattering."""
     wl = _cavity(Kn=0.1, vel_fp32=vel_fp32)
+    wl.species.alpha = alpha
     o, g = _pair(dsmc, wl, steps=40, n_a=50)
     kw = dict(kn_max=0.93, passes=3, n_m=60, eps_m=1e-8, cfl=0.5, feedback=0)
     # oracle stage by stage (its couple runs the same sequence)

@@ -1,6 +1,6 @@
 """Error behaviour of the C ABI as the headers state it: invalid meshes are
 DSMC_E_MESH at init (degenerate tet, a boundary triangle missing or matching
-no exterior face), invalid parameters DSMC_E_INVALID (non-positive time step,
+no exterior face), invalid parameters DSMC_E_INVALID (non-positive time step or VSS exponent,
 particle cells out of range in set_state, negative reconstruction passes or
 acceleration depth, unknown kernel schedule, empty or negative training
 sets), and a context stays usable after an argument error."""
@@ -58,6 +58,13 @@ def test_boundary_faces_must_match_the_exterior(D):
 def test_non_positive_time_step_is_invalid(D):
     wl = _wl()
     wl.run.dt = 0.0
+    assert _status(D, lambda: D.Simulation(wl)) == E_INVALID
+
+
+@pytest.mark.parametrize("alpha", [0.0, -1.0, float("nan")])
+def test_non_positive_scattering_exponent_is_invalid(D, alpha):
+    wl = _wl()
+    wl.species.alpha = alpha
     assert _status(D, lambda: D.Simulation(wl)) == E_INVALID
 
 

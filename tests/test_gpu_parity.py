@@ -9,7 +9,8 @@ new maximum is an FP64 power, whose device and host results may differ in
 the last bit).  Cases cover diffuse walls with a moving
 lid, jittered irregular tets, specular walls, periodic plates, freestream
 inflow/outflow, sparse cells (0-1 particles), dense chunks beyond the LDS
-stage, and the full 384,000-tet cavity in the benchmark's configuration."""
+stage, VSS scattering (alpha = 1.4, 1.6) and the full 384,000-tet cavity in
+the benchmark's configuration."""
 import numpy as np
 import pytest
 
@@ -40,7 +41,16 @@ def _cases():
     c["sparse_ppc1"] = (lambda: W.cavity(n_hex=6, Kn=0.5, ppc=1, jitter=0.1, vel_fp32=1), 2)
     c["dense_ppc45"] = (lambda: W.cavity(n_hex=5, Kn=0.05, ppc=45, jitter=0.1, vel_fp32=1), 1)
     c["sphere_hypersonic"] = (lambda: W.sphere_flow(N=4, K=3, ppc=8, vel_fp32=1), 4)
+    # VSS scattering (alpha != 1): deflection about the relative velocity
+    c["vss_cavity_fp64_a1.4"] = (lambda: _vss(W.cavity(n_hex=6, Kn=0.5, ppc=20, vel_fp32=0), 1.4), 6)
+    c["vss_dense_fp32_a1.6"] = (lambda: _vss(W.cavity(n_hex=5, Kn=0.05, ppc=45, jitter=0.1, vel_fp32=1), 1.6), 1)
     return c
+
+
+def _vss(wl, alpha):
+    wl.species.alpha = alpha
+    wl.name += f"_vss{alpha}"
+    return wl
 
 
 CASES = _cases()
@@ -113,7 +123,8 @@ def test_move_schedules_parity(dsmc, move, case):
 # every collide schedule; the dense case puts more particles in a 64-cell
 # chunk than the LDS of the smaller-chunk schedules holds (global fallback);
 # the FP64 case stages double-precision velocities
-@pytest.mark.parametrize("case", ["cavity_8_fp32_jitter_kn0.1", "dense_ppc45", "sparse_ppc1", "cavity_6_fp64_kn1"])
+@pytest.mark.parametrize("case", ["cavity_8_fp32_jitter_kn0.1", "dense_ppc45", "sparse_ppc1", "cavity_6_fp64_kn1",
+                                  "vss_cavity_fp64_a1.4", "vss_dense_fp32_a1.6"])
 @pytest.mark.parametrize("collide", [0, 1, 2, 3, 4])
 def test_collide_schedules_parity(dsmc, collide, case):
     make, pre = CASES[case]
@@ -124,7 +135,8 @@ def test_collide_schedules_parity(dsmc, collide, case):
 # the fused form gathers inside the collide kernel (the dense case takes its
 # global-memory path after the gather), with collide 0 it falls back to the
 # gather kernel; the inflow case sorts injected particles too
-@pytest.mark.parametrize("case", ["cavity_8_fp32_jitter_kn0.1", "dense_ppc45", "open_box_inflow", "cavity_6_fp64_kn1"])
+@pytest.mark.parametrize("case", ["cavity_8_fp32_jitter_kn0.1", "dense_ppc45", "open_box_inflow", "cavity_6_fp64_kn1",
+                                  "vss_dense_fp32_a1.6"])
 @pytest.mark.parametrize("collide", [0, 3])
 @pytest.mark.parametrize("sort", [0, 1, 2])
 def test_sort_schedules_parity(dsmc, sort, collide, case):
