@@ -477,6 +477,12 @@ static void surface_hit(osim* s, int bf, uint32_t step, const double* a, const d
     q[4] += 1.0;
 }
 
+/* n . a with fused multiply-adds, n0 a0 first: the rounding the tracking
+ * below uses for its exit test (the paper fixes none). */
+static double dot_fused(const double* n, const double* a) {
+    return fma(n[2], a[2], fma(n[1], a[1], n[0] * a[0]));
+}
+
 /* returns 0 alive, 1 removed through an open boundary, 2 lost */
 static int trace(osim* s, double* x, double* v, int* cellp, int entry, uint32_t pid, uint32_t step,
                  double t) {
@@ -491,18 +497,18 @@ static int trace(osim* s, double* x, double* v, int* cellp, int entry, uint32_t 
             const double* n = s->fn + 3 * s->tf_face[k];
             double d = s->fd[s->tf_face[k]];
             double sg = s->tf_s[k];
-            double den = sg * (n[0] * v[0] + n[1] * v[1] + n[2] * v[2]);
+            double den = sg * dot_fused(n, v);
             if (den > 0) {
-                double lam = (sg * (d - (n[0] * x[0] + n[1] * x[1] + n[2] * x[2]))) / den;
+                double lam = (sg * (d - dot_fused(n, x))) / den;
                 if (lam < 0) lam = 0;
                 if (fb < 0 || lam < lb) { fb = f; lb = lam; }
             }
         }
         if (fb < 0 || lb >= t) {
-            for (int i = 0; i < 3; ++i) x[i] = x[i] + v[i] * t;
+            for (int i = 0; i < 3; ++i) x[i] = fma(v[i], t, x[i]);
             break;
         }
-        for (int i = 0; i < 3; ++i) x[i] = x[i] + v[i] * lb;
+        for (int i = 0; i < 3; ++i) x[i] = fma(v[i], lb, x[i]);
         t = t - lb;
         s->hops++;
         if (++nhop > MAX_HOPS) { s->lost++; *cellp = c; return 2; }

@@ -210,9 +210,9 @@ __device__ __forceinline__ TraceOut trace(const MeshDev& m, double& x0, double& 
         for (int f = 0; f < 4; ++f) {
             if (f == entry) continue;
             const double4 pl = m.plane[4 * c + f];
-            const double den = pl.x * v0 + pl.y * v1 + pl.z * v2;
+            const double den = fma(pl.z, v2, fma(pl.y, v1, pl.x * v0));
             if (den > 0) {
-                double lam = (pl.w - (pl.x * x0 + pl.y * x1 + pl.z * x2)) / den;
+                double lam = (pl.w - fma(pl.z, x2, fma(pl.y, x1, pl.x * x0))) / den;
                 if (lam < 0) lam = 0;
                 if (fb < 0 || lam < lb) {
                     fb = f;
@@ -221,14 +221,14 @@ __device__ __forceinline__ TraceOut trace(const MeshDev& m, double& x0, double& 
             }
         }
         if (fb < 0 || lb >= t) {
-            x0 = x0 + v0 * t;
-            x1 = x1 + v1 * t;
-            x2 = x2 + v2 * t;
+            x0 = fma(v0, t, x0);
+            x1 = fma(v1, t, x1);
+            x2 = fma(v2, t, x2);
             break;
         }
-        x0 = x0 + v0 * lb;
-        x1 = x1 + v1 * lb;
-        x2 = x2 + v2 * lb;
+        x0 = fma(v0, lb, x0);
+        x1 = fma(v1, lb, x1);
+        x2 = fma(v2, lb, x2);
         t = t - lb;
         ++nhop;
         if (nhop > DSMC_MAX_HOPS) {
@@ -307,8 +307,8 @@ struct Walker {
 // face with N.v > 0; clamped at 0; the running minimum keeps the lowest
 // face index on ties because faces are visited in ascending order.
 __device__ __forceinline__ void exit_candidate(const double4& pl, int f, const Walker& w, int& fb, double& lb) {
-    const double den = pl.x * w.v0 + pl.y * w.v1 + pl.z * w.v2;
-    double lam = (pl.w - (pl.x * w.x0 + pl.y * w.x1 + pl.z * w.x2)) / den;
+    const double den = fma(pl.z, w.v2, fma(pl.y, w.v1, pl.x * w.v0));
+    double lam = (pl.w - fma(pl.z, w.x2, fma(pl.y, w.x1, pl.x * w.x0))) / den;
     lam = lam < 0 ? 0.0 : lam;
     const bool ok = (f != w.entry) && (den > 0);
     const bool take = ok && (fb < 0 || lam < lb);
@@ -347,8 +347,8 @@ constexpr int kHopWallPending = 3;
 // visited from the entry face onwards; a tie keeps the lower face index, as
 // the ascending scan of exit_candidate does.
 __device__ __forceinline__ void exit_candidate3(const double4& pl, int f, const Walker& w, int& fb, double& lb) {
-    const double den = pl.x * w.v0 + pl.y * w.v1 + pl.z * w.v2;
-    double lam = (pl.w - (pl.x * w.x0 + pl.y * w.x1 + pl.z * w.x2)) / den;
+    const double den = fma(pl.z, w.v2, fma(pl.y, w.v1, pl.x * w.v0));
+    double lam = (pl.w - fma(pl.z, w.x2, fma(pl.y, w.x1, pl.x * w.x0))) / den;
     lam = lam < 0 ? 0.0 : lam;
     const bool take = (den > 0) && (fb < 0 || lam < lb || (lam == lb && f < fb));
     fb = take ? f : fb;
@@ -392,14 +392,14 @@ __device__ __forceinline__ int hop_once(const MeshDev& m, Walker& w, uint32_t st
         exit_candidate(p3, 3, w, fb, lb);
     }
     if (fb < 0 || lb >= w.t) {
-        w.x0 = w.x0 + w.v0 * w.t;
-        w.x1 = w.x1 + w.v1 * w.t;
-        w.x2 = w.x2 + w.v2 * w.t;
+        w.x0 = fma(w.v0, w.t, w.x0);
+        w.x1 = fma(w.v1, w.t, w.x1);
+        w.x2 = fma(w.v2, w.t, w.x2);
         return 0;
     }
-    w.x0 = w.x0 + w.v0 * lb;
-    w.x1 = w.x1 + w.v1 * lb;
-    w.x2 = w.x2 + w.v2 * lb;
+    w.x0 = fma(w.v0, lb, w.x0);
+    w.x1 = fma(w.v1, lb, w.x1);
+    w.x2 = fma(w.v2, lb, w.x2);
     w.t = w.t - lb;
     ++w.nhop;
     if (w.nhop > DSMC_MAX_HOPS) return 2;

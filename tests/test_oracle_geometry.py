@@ -3,6 +3,8 @@
 Independent checks: volumes against the box volume, face pairing against
 a counting argument, and a brute-force barycentric point location over all
 tets for the end point of traced trajectories."""
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -103,7 +105,9 @@ def test_ballistic_exact_within_cell_and_close_across():
         t = 1e-7
         c1, x, _ = o.trace_one(x0, v, c, k, 1, t)
         if c1 == c:
-            assert np.array_equal(x, x0 + v * t)   # same operation order, bitwise
+            # one rounding of the exact x0 + v t (a fused multiply-add), bitwise
+            exact = [float(Fraction(float(x0[i])) + Fraction(float(v[i])) * Fraction(t)) for i in range(3)]
+            assert np.array_equal(x, np.array(exact))
         t = 2e-4
         c1, x, v1 = o.trace_one(x0, v, c, k, 1, t)
         if np.array_equal(v1, v):  # no wall reflection on the way
