@@ -47,7 +47,7 @@ BYTES = {
 # rocprofv3 --pmc measurements of the move kernel (FETCH_SIZE + WRITE_SIZE per
 # dispatch, scaled by the copy-kernel calibration) and the source digest they
 # were taken on; the traffic figure is reported only while the digest matches.
-TRAFFIC = {"kernel": "move", "digest": "6783582172051d36", "bytes_per_launch": 576493082 + 580659456,
+TRAFFIC = {"kernel": "move", "digest": "ca2cda55d5f77610", "bytes_per_launch": 576332646 + 580667654,
            "source": "profiles/step_kernels_cavity40.md"}
 
 
