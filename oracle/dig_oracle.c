@@ -17,7 +17,7 @@
  *
  * The finite-volume discretisation and the feedback map are not given in the
  * paper (they are delegated to its references); the readings implemented
- * here are stated in the design notes: cell-centred finite volumes with
+ * here are: cell-centred finite volumes with
  * least-squares gradients, linear face reconstruction, a central flux with
  * low-Mach-scaled scalar dissipation, NSF + frozen HoT viscous fluxes (the
  * HoT carried per face so that the sampled state is consistent) and

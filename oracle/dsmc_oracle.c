@@ -11,14 +11,17 @@
  *  - Collisions: Bird's no-time-counter pair selection with the variable
  *    hard sphere model (section 2.1 and the gas model of section 5); the
  *    selection formula itself is not printed in the paper and is the
- *    standard NTC expression.
+ *    standard NTC expression.  Scattering is isotropic (VHS) or, with a
+ *    VSS exponent alpha != 1, Bird's variable soft sphere deflection law
+ *    (section 2.1 names the VSS model).
  *  - Cell sampling: eq. (dsmc_temperatures); the exponential moving average
  *    eq. (exponential_average_moments_ch3) and the steady average
  *    eq. (steady_average_moments_ch3) of section 3.1; cells in local
  *    accumulation (section 3.2) average cumulatively.
- *  - Geometry, random-number and operation-order contracts written down in
- *    the design notes, so that an independent implementation can agree
- *    bit-for-bit on integer outcomes.
+ *  - The geometry, random-number and operation-order conventions of this
+ *    file are fixed, so that an independent implementation can agree
+ *    bit-for-bit on integer outcomes (the exit test's dot products and the
+ *    free-flight advance use fused multiply-adds, the only contraction).
  */
 #include <math.h>
 #include <stdio.h>
