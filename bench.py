@@ -48,7 +48,7 @@ BYTES = {
 # dispatch, scaled by the copy-kernel calibration) and the source digest they
 # were taken on; the traffic figure is reported only while the digest matches.
 TRAFFIC = {"kernel": "move", "digest": "ca2cda55d5f77610", "bytes_per_launch": 576332646 + 580667654,
-           "source": "profiles/step_kernels_cavity40.md"}
+           "workload": "cavity_40^3x6_Kn0.1", "source": "profiles/step_kernels_cavity40.md"}
 
 
 def _kernel_digest():
@@ -455,7 +455,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cavity_large", choices=["cavity_large", "cavity_small", "ensemble64", "dig_cavity40", "fields_race", "sphere"])
+    ap.add_argument("--workload", default="cavity_large", choices=["cavity_large", "cavity_small", "cavity_vss", "ensemble64", "dig_cavity40", "fields_race",
+                                                              "sphere"])
     ap.add_argument("--race-hex", type=int, default=20)
     ap.add_argument("--race-kn", type=float, default=0.01)
     ap.add_argument("--race-ref-steps", type=int, default=200000)
@@ -488,7 +489,8 @@ def main():
         return bench_dig(args, dsmc, W)
     if args.workload == "fields_race":
         return bench_race(args, dsmc, W)
-    wl = W.cavity_large() if args.workload == "cavity_large" else W.cavity_small()
+    wl = {"cavity_large": W.cavity_large, "cavity_vss": W.cavity_large_vss,
+          "cavity_small": W.cavity_small}[args.workload]()
     sim = dsmc.Simulation(wl)
     np0 = sim.stats()["n_particles"]
     sim.step(args.warmup)
@@ -544,7 +546,8 @@ def main():
     peak = 8000.0
     digest = _kernel_digest()
     traffic = None
-    if TRAFFIC and TRAFFIC.get("digest") == digest and TRAFFIC.get("kernel") == dominant:
+    if (TRAFFIC and TRAFFIC.get("digest") == digest and TRAFFIC.get("kernel") == dominant
+            and TRAFFIC.get("workload") == wl.name):
         traffic = TRAFFIC["bytes_per_launch"] / 1e9 / (per_launch[dominant] * 1e-3)
     roofline = dict(bound="hbm", kernel=dominant, achieved=round(gbs[dominant], 1), peak=peak, unit="GB/s",
                     frac=round(gbs[dominant] / peak, 4),

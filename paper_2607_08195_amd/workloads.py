@@ -233,10 +233,11 @@ def tau_from_kn(sp: Species, Kn, T0, L0=1.0):
 # Named workloads
 # ---------------------------------------------------------------------------
 def cavity(n_hex=6, Kn=1.0, ppc=20, jitter=0.0, lid_speed=50.0, T0=273.0, seed=0,
-           vel_fp32=1, steps=500, n_ss=200, mesh_seed=0, ewma_on=0, n_a=1000):
+           vel_fp32=1, steps=500, n_ss=200, mesh_seed=0, ewma_on=0, n_a=1000, species=None):
     """3D lid-driven cavity on [0,1]^3: all walls diffuse at T0, the y=1 lid
-    moving at lid_speed in +x.  Initial equilibrium at rest (section 5.1)."""
-    sp = Species()
+    moving at lid_speed in +x.  Initial equilibrium at rest (section 5.1).
+    The gas is VHS argon unless `species` is given."""
+    sp = Species() if species is None else species
     mesh = kuhn_box(n_hex, n_hex, n_hex, jitter=jitter, seed=mesh_seed)
     n0 = n0_from_kn(sp, Kn, T0)
     dt = 0.2 * tau_from_kn(sp, Kn, T0)
@@ -246,8 +247,17 @@ def cavity(n_hex=6, Kn=1.0, ppc=20, jitter=0.0, lid_speed=50.0, T0=273.0, seed=0
     bcs[3] = Boundary(BC_DIFFUSE, T0, (lid_speed, 0.0, 0.0))
     run = Run(n0=n0, T0=T0, u0=(0.0, 0.0, 0.0), F_N=F_N, dt=dt, seed=seed, vel_fp32=vel_fp32,
               n_ss=n_ss, n_a=n_a, ewma_on=ewma_on)
-    return Workload(f"cavity_{n_hex}^3x6_Kn{Kn:g}", mesh, sp, bcs, run, steps,
+    name = f"cavity_{n_hex}^3x6_Kn{Kn:g}" + ("" if sp.alpha == 1.0 else f"_vss{sp.alpha:g}")
+    return Workload(name, mesh, sp, bcs, run, steps,
                     dict(Kn=Kn, n_hex=n_hex, ppc=ppc, lid_speed=lid_speed, jitter=jitter))
+
+
+def cavity_large_vss(steps=20000, n_ss=10000):
+    """The 40^3 x 6 cavity of cavity_large with argon as a variable soft
+    sphere (d_ref = 4.11e-10 m, alpha = 1.40 at T_ref = 273 K; the same
+    viscosity as the VHS argon, so the same n0 and dt within 0.1 %)."""
+    return cavity(n_hex=40, Kn=0.1, ppc=30, jitter=0.1, vel_fp32=1, steps=steps, n_ss=n_ss,
+                  species=Species(d_ref=4.11e-10, alpha=1.40))
 
 
 def cavity_small():
