@@ -223,6 +223,15 @@ def test_full_size_cavity_single_step(dsmc):
     print("full size", info)
 
 
+def test_full_size_vss_cavity_single_step(dsmc):
+    """The same cavity with argon as a variable soft sphere (alpha = 1.40, the
+    `cavity_vss` benchmark workload): one step of the VSS collide instance
+    against the oracle on every particle and cell."""
+    wl = W.cavity_large_vss()
+    info = _one_step_parity(dsmc, wl, 0)
+    print("full size vss", info)
+
+
 def test_full_size_sphere_single_step(dsmc):
     """The hypersonic sphere at the benchmark's size (1,963,104 tets, 50M
     particles, FP32 velocities, inflow on five faces and outflow) with the
