@@ -139,7 +139,7 @@ def bench_ensemble(args, dsmc, W, window=50):
     # coupling on the odd cases with a closure trained on their cells
     on = np.arange(len(cases)) % 2 == 1
     sim.dig_enable(on.astype(np.int32))
-    prm = dict(kn_max=1.0, passes=3, n_m=100, eps_m=1e-4, cfl=0.5, feedback=1, warm_start=1)
+    prm = dict(kn_max=1.0, passes=3, n_m=100, eps_m=1e-4, cfl=0.5, feedback=1, warm_start=1, unconverged=1)
     sim.dig_couple(**dict(prm, n_m=0, feedback=0))
     x, t, v = sim.closure_data()
     begin = sim.case_cells()
@@ -275,7 +275,7 @@ def bench_dig(args, dsmc, W, window=50):
     sim = dsmc.Simulation(wl)
     net = dsmc.Mlp()
     net.init_weights(seed=1)
-    prm = dict(kn_max=1.0, passes=3, n_m=100, eps_m=1e-4, cfl=0.5, feedback=1, warm_start=1)
+    prm = dict(kn_max=1.0, passes=3, n_m=100, eps_m=1e-4, cfl=0.5, feedback=1, warm_start=1, unconverged=1)
     sim.step(window)
     sim.dig_couple(**dict(prm, n_m=0, feedback=0))
     x, t, v = sim.closure_data()

@@ -63,6 +63,10 @@ typedef struct {
                            mixing of the iterates over the last m (<= 64)
                            differences (one host synchronisation per
                            iteration; same steady solution) */
+    int32_t unconverged; /* 0 (default): the closed-domain mass rescale and
+                           the particle feedback follow only a solve that
+                           reached eps_m; 1: also a solve that stopped at
+                           n_m iterations (never one that failed) */
 } dig_params;
 
 typedef struct {
@@ -76,11 +80,16 @@ typedef struct {
     int64_t np_before, np_after;
     int32_t n_closure;       /* cells whose HoT came from the learned closure (mlp.h) */
     int32_t n_fallback;      /* cells with samples that kept the sampled HoT */
+    int32_t fed_back;        /* 1: the particles were adjusted to M^{k+1} */
 } dig_report;
 
 /* One coupling cycle (Algorithm 1) on the context's current moving-average
  * sums and particles.  Skips the solve and the feedback when every cell is
- * rejected or the solve fails (report says which).  Sets the local
+ * rejected; skips the feedback when the solve fails or, unless
+ * params->unconverged, when it did not reach eps_m within n_m iterations
+ * (the report says which, and fed_back whether the particles changed).
+ * The solution of a solve that did not fail becomes M^k, the state kept for
+ * unreached cells and the warm start of the next cycle.  Sets the local
  * accumulation flags of rejected cells.  DSMC_E_CAPACITY if the clones of
  * the feedback would overflow the particle store (state left unchanged). */
 dsmc_status dig_couple(dsmc_ctx ctx, const dig_params* params, dig_report* report);

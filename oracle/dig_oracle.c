@@ -785,17 +785,22 @@ int oracle_dig_couple(osim* s, const odig_params* prm, odig_report* rep) {
     if (prm->warm_start) memcpy(prim, s->mprev, sizeof(double) * NV * (size_t)nt);
     if (r.n_rejected < nt) {
         solve_faces(s, prim, hotf, prm, &r);
-        if (!r.failed && closed_domain(s)) {
+        /* only the solution of the synthetic equations is fed back: a solve
+         * that stopped short of eps_m leaves the particles unchanged unless
+         * the caller asks otherwise */
+        int adjust = !r.failed && (r.converged || prm->unconverged);
+        if (adjust && closed_domain(s)) {
             /* a closed domain keeps the mass of its particles */
             double mp = (double)s->np * s->FN * s->m, mfv = 0.0;
             for (int c = 0; c < nt; ++c) mfv += prim[NV * (size_t)c] * s->vol[c];
             double f = mp / mfv;
             for (int c = 0; c < nt; ++c) prim[NV * (size_t)c] = prim[NV * (size_t)c] * f;
         }
-        if (!r.failed) {
-            if (prm->feedback) oracle_dig_feedback(s, half, prim, state);
-            memcpy(s->mprev, prim, sizeof(double) * NV * (size_t)nt);
+        if (adjust && prm->feedback) {
+            oracle_dig_feedback(s, half, prim, state);
+            r.fed_back = 1;
         }
+        if (!r.failed) memcpy(s->mprev, prim, sizeof(double) * NV * (size_t)nt);
     }
     for (int c = 0; c < nt; ++c) s->local_acc[c] = state[c] != 0;
     r.np_after = s->np;

@@ -112,6 +112,7 @@ typedef struct {
     int feedback;   /* 1: adjust the particles to the macroscopic solution */
     int global_dt;  /* 1: one pseudo-time step for all cells (conservative) */
     int warm_start; /* 1: the solve starts from M^k instead of M^{k+1/2} */
+    int unconverged; /* 1: feed back also a solve that stopped at n_m */
 } odig_params;
 
 typedef struct {
@@ -123,6 +124,7 @@ typedef struct {
     int n_reconstructed;
     int n_unreached;
     int64_t np_before, np_after;
+    int fed_back;      /* the particles were adjusted */
 } odig_report;
 
 /* Reference state (n0, T0, u0) used by the admissibility criterion and as the

@@ -587,14 +587,19 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
         st = run_solve(c, p, &r);
         d->g.skip_idle = 0;
         if (st != DSMC_OK) return st;
-        if (!r.failed && d->closed) launch_dig_mass_rescale(s, d->g, d->w, c->d_sc, c->d_offsets);
-        if (!r.failed) {
-            if (p->feedback && (st = run_feedback(c)) != DSMC_OK) {
+        // Algorithm 1 feeds back the solution of the synthetic equations: a
+        // solve that stopped short of eps_m leaves the particles as they are
+        // unless the caller asks otherwise
+        const bool adjust = !r.failed && (r.converged || p->unconverged);
+        if (adjust && d->closed) launch_dig_mass_rescale(s, d->g, d->w, c->d_sc, c->d_offsets);
+        if (adjust && p->feedback) {
+            if ((st = run_feedback(c)) != DSMC_OK) {
                 if (rep) *rep = r;
                 return st;
             }
-            launch_dig_copy(s, d->w.prim, d->w.mprev, 5 * (int64_t)nt);
+            r.fed_back = 1;
         }
+        if (!r.failed) launch_dig_copy(s, d->w.prim, d->w.mprev, 5 * (int64_t)nt);
     }
     launch_dig_set_local(s, d->g, d->w.state, c->d_local);
     HIP_TRY(c, hipGetLastError());

@@ -224,7 +224,7 @@ def _batch_coupling_check(D, cases, on):
     g.set_sums(D.SAMPLE_EWMA, cat([o.sums(1) for o in oracles]), cat([o.ewma_counts() for o in oracles]))
     g.set_sums(D.SAMPLE_STEADY, cat([o.sums(0) for o in oracles]))
     g.dig_enable(on)
-    kw = dict(kn_max=0.93, passes=3, n_m=40, eps_m=0.0, cfl=0.5, feedback=1)
+    kw = dict(kn_max=0.93, passes=3, n_m=40, eps_m=0.0, cfl=0.5, feedback=1, unconverged=1)
     changed = 0
     for cycle in range(2):
         rg = g.dig_couple(**kw)
@@ -321,7 +321,7 @@ def test_ensemble64_half_coupled_smallest_cases_match_oracle(D):
     net.init_weights(seed=3)
     g.set_closure(net, gate_tol=0.0)
     oracles = {int(k): Oracle(cases[k]) for k in small}
-    kw = dict(kn_max=0.93, passes=3, n_m=20, eps_m=0.0, cfl=0.5, feedback=1)
+    kw = dict(kn_max=0.93, passes=3, n_m=20, eps_m=0.0, cfl=0.5, feedback=1, unconverged=1)
     g.step(2)
     g.graph_step(2)
     for o in oracles.values():
@@ -368,7 +368,7 @@ def test_batch_coupling_with_no_case_enabled_changes_nothing(D):
     g.step(20)
     st0 = g.state()
     g.dig_enable([0] * len(cases))
-    r = g.dig_couple(kn_max=0.93, passes=3, n_m=20, eps_m=0.0, cfl=0.5, feedback=1)
+    r = g.dig_couple(kn_max=0.93, passes=3, n_m=20, eps_m=0.0, cfl=0.5, feedback=1, unconverged=1)
     assert not r["failed"] and r["np_after"] == r["np_before"] == st0["n"]
     st1 = g.state()
     for k in ["x", "v", "cell", "pid"]:

@@ -258,7 +258,7 @@ def test_couple_with_feedback_matches_oracle(dsmc, warm):
     DSMC steps between them."""
     wl = _cavity(Kn=0.1, n_hex=6, ppc=20, vel_fp32=0)
     o, g = _pair(dsmc, wl, steps=40, n_a=50)
-    kw = dict(kn_max=0.93, passes=3, n_m=40, eps_m=1e-8, cfl=0.5, feedback=1, warm_start=warm)
+    kw = dict(kn_max=0.93, passes=3, n_m=40, eps_m=1e-8, cfl=0.5, feedback=1, warm_start=warm, unconverged=1)
     g.dig_couple(**kw)
     o.dig_couple(**kw)
     g.step(3)
@@ -302,7 +302,7 @@ def test_cells_without_samples(dsmc):
     s[::7] = 0.0
     o.set_sums(1, s)
     g.set_sums(dsmc.SAMPLE_EWMA, s)
-    kw = dict(kn_max=1.0, passes=1, n_m=10, eps_m=0.0, feedback=1)
+    kw = dict(kn_max=1.0, passes=1, n_m=10, eps_m=0.0, feedback=1, unconverged=1)
     rg = g.dig_couple(**kw)
     ro = o.dig_couple(**kw)
     for k in ["n_rejected", "n_reconstructed", "n_unreached", "iters", "np_after"]:
@@ -364,4 +364,31 @@ def test_couple_on_hypersonic_sphere_fails_as_the_oracle(dsmc):
     assert rg["failed"] == 1 and rg["np_after"] == n0
     gs, os_ = g.state(), o.particles()
     assert np.array_equal(gs["cell"], os_["cell"]) and np.array_equal(gs["pid"], os_["pid"])
+    g.close()
+
+
+def test_unconverged_solve_leaves_the_particles(dsmc):
+    """A solve stopped by n_m short of eps_m: no rescale and no feedback on
+    either side (particles bit-identical to before), the iterate kept as
+    M^k to the solve criterion; with unconverged = 1 both sides feed back."""
+    wl = _cavity(Kn=0.1, n_hex=6, ppc=20, vel_fp32=0)
+    o, g = _pair(dsmc, wl, steps=30, n_a=50)
+    st0 = g.state()
+    kw = dict(kn_max=0.93, passes=3, n_m=6, eps_m=1e-12, cfl=0.5, feedback=1)
+    rg = g.dig_couple(**kw)
+    ro = o.dig_couple(**kw)
+    for k in ["iters", "converged", "failed", "fed_back", "np_before", "np_after"]:
+        assert rg[k] == ro[k], (k, rg[k], ro[k])
+    assert rg["fed_back"] == 0 and not rg["converged"]
+    st1 = g.state()
+    for k in ["x", "v", "cell", "pid"]:
+        assert np.array_equal(st0[k], st1[k]), k
+    _prim_close(g.dig_get("mprev"), o.mprev(), wl, 1e-10)
+    rg = g.dig_couple(**kw, unconverged=1)
+    ro = o.dig_couple(**kw, unconverged=1)
+    assert rg["fed_back"] == ro["fed_back"] == 1
+    assert rg["np_after"] == ro["np_after"]
+    gs, os_ = g.state(), o.particles()
+    assert np.array_equal(gs["cell"], os_["cell"]) and np.array_equal(gs["pid"], os_["pid"])
+    assert np.abs(gs["v"] - os_["v"]).max() <= 1e-9 * np.abs(os_["v"]).max()
     g.close()

@@ -221,7 +221,7 @@ def test_couple_runs_on_the_small_cavity():
     wl = W.cavity(n_hex=6, Kn=0.1, ppc=20, vel_fp32=0, ewma_on=1, n_a=50)
     o = Oracle(wl)
     o.step(50)
-    rep = o.dig_couple(kn_max=1.0, n_m=50)
+    rep = o.dig_couple(kn_max=1.0, n_m=50, unconverged=1)
     assert not rep["failed"] and rep["iters"] == 50
     assert rep["n_rejected"] < o.nt
     m = o.mprev()
@@ -276,3 +276,25 @@ def test_face_hot_correction_vanishes_for_linear_fields():
     cons = o.dig_face_hot(prim, hot, consistent=1)
     mu = wl.species.mu(Tw)
     assert np.abs(cons - avg).max() <= 1e-9 * mu * U
+
+
+def test_unconverged_solve_leaves_the_particles():
+    """Algorithm 1 feeds back the solution of the synthetic equations: a
+    solve stopped by n_m before eps_m leaves particles, count and mass as
+    they were (its iterate still becomes M^k); asked to, the same cycle
+    feeds back."""
+    wl = W.cavity(n_hex=4, Kn=0.1, ppc=20, vel_fp32=0, ewma_on=1, n_a=50)
+    o = Oracle(wl)
+    o.step(30)
+    before = o.particles()
+    rep = o.dig_couple(kn_max=1.0, n_m=5, eps_m=1e-12)
+    assert not rep["failed"] and not rep["converged"] and rep["iters"] == 5
+    assert rep["fed_back"] == 0 and rep["np_after"] == rep["np_before"]
+    after = o.particles()
+    for k in ["x", "v", "cell", "pid"]:
+        assert np.array_equal(before[k], after[k]), k
+    m = o.mprev()
+    assert not np.allclose(m[:, 4], wl.run.T0)        # the iterate is kept as M^k
+    rep = o.dig_couple(kn_max=1.0, n_m=5, eps_m=1e-12, unconverged=1)
+    assert rep["fed_back"] == 1
+    assert not np.array_equal(o.particles()["v"][:100], before["v"][:100])
