@@ -30,9 +30,12 @@
  *    with the local step cfl V / sum_f A (|u.n| + c + viscous rate);
  *  - feedback per admissible or reconstructed cell: velocities shifted and
  *    scaled, v' = u_new + sqrt(T_new / T_old) (v - u_old); particle count
- *    scaled to floor(N rho_new / rho_old + U) by deleting particles chosen
- *    one at a time among the remaining (pid order) or by cloning random
- *    particles to uniform positions in the cell with new pids; re-sorted.
+ *    set to floor(rho_new V / (F_N m) + U) (V the cell volume, m the
+ *    molecular mass: unchanged when rho_new equals the density the cell's
+ *    particles carry) by deleting particles chosen one at a time among the
+ *    remaining (pid order) or by cloning random particles to uniform
+ *    positions in the cell with new pids; re-sorted; only after a solve
+ *    that converged (dig_params.unconverged).
  *
  * Conventions are those of dsmc.h: status codes, SI units, host arrays in
  * the caller's cell numbering ([n_tets][k] row-major), calls synchronise

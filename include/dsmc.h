@@ -22,8 +22,8 @@
  *    allocator when one is given) and releases it in dsmc_destroy().
  *  - Work is enqueued asynchronously on the context's HIP stream.  Calls
  *    that return host data synchronise that stream.  Device-side faults
- *    (capacity overflow, lost particles) are latched and reported by the
- *    next synchronising call (dsmc_stats, dsmc_get_state, dsmc_sample,
+ *    (capacity overflow) are latched and reported by the next
+ *    synchronising call (dsmc_stats, dsmc_get_state, dsmc_sample,
  *    dsmc_sync).  After DSMC_E_CAPACITY or DSMC_E_DEVICE only
  *    dsmc_destroy() is valid.
  *  - One context per host thread; distinct contexts are independent.
@@ -46,9 +46,10 @@ typedef enum {
     DSMC_E_MESH = -2,          /* degenerate tet, unmatched boundary triangle, non-manifold face */
     DSMC_E_OOM = -3,           /* device allocation failed */
     DSMC_E_DEVICE = -4,        /* HIP runtime error */
-    DSMC_E_CAPACITY = -5,      /* particle store would overflow */
-    DSMC_E_LOST = -6,          /* (reported in counters; not returned by dsmc_step) */
-    DSMC_E_NOT_CONVERGED = -7  /* reserved for the coupling solve */
+    DSMC_E_CAPACITY = -5       /* particle store would overflow */
+    /* Particles lost to the hop limit are counted (dsmc_counters.lost), and
+     * a coupling solve that stops short of its tolerance is reported
+     * (dig_report.converged); neither is an error status. */
 } dsmc_status;
 
 /* Tetrahedral mesh (paper section 4.1: cells and faces of the local mesh).
@@ -253,8 +254,9 @@ dsmc_status dsmc_device_copy(dsmc_ctx ctx, void* dst, const void* src, size_t by
  * (the generator key (seed, case_id), cell subjects and particle ids are
  * case-local, so each case evolves as it would in a context of its own).
  * Batch-wide, from runs[0]: vel_fp64, n_ss, n_a, ewma_on, fill, capacity,
- * hip_stream, allocator.  Freestream inflow and the coupling step (dig.h)
- * are not available for a batch.  Every other call works on the joined
+ * hip_stream, allocator.  Freestream inflow is not available for a batch
+ * (DSMC_E_INVALID); the coupling step is (dig.h: dig_couple over the cases
+ * that dig_batch_enable selects).  Every other call works on the joined
  * mesh: cells are numbered case after case in the callers' order
  * (dsmc_batch_cases gives the first cell of each case). */
 dsmc_status dsmc_batch_init(dsmc_ctx* out, int32_t n_cases, const dsmc_mesh_desc* meshes,
@@ -266,9 +268,12 @@ dsmc_status dsmc_batch_cases(dsmc_ctx ctx, int32_t* n_cases, int32_t* cell_begin
 
 /* Advance n_steps full steps through a captured HIP graph: two steps are
  * recorded once (per particle-buffer parity and kernel schedule) and
- * replayed; an odd remainder runs as an ordinary step.  Kernel grids cover
- * the whole particle store; the kernels bound themselves by the device
- * counts.  Needs a non-null hip_stream.  Results equal dsmc_step's. */
+ * replayed; an odd remainder runs as an ordinary step.  With freestream
+ * inflow the kernel grids cover the whole particle store; without it they
+ * cover the particle count at capture time (a step cannot add particles),
+ * and a replay that finds more particles than that (after feedback clones)
+ * captures again.  The kernels bound themselves by the device counts.
+ * Needs a non-null hip_stream.  Results equal dsmc_step's. */
 dsmc_status dsmc_graph_step(dsmc_ctx ctx, int32_t n_steps);
 
 /* Kernel schedule: move 0 lane, 1 lane (6 waves/SIMD), 2 lane (8),

@@ -476,15 +476,19 @@ __device__ __forceinline__ int64_t queue_take(const MeshDev& m, const PartDev<VT
     kp = key;
     double dtp = 0.0;
     case_params(m.cell_case, m.cases, w.c, kp, dtp);
-    if (tq < 0) {
+    // a walker parked in flight carries a negative time; one parked at a
+    // diffuse wall entered through a boundary face.  Both tests are made:
+    // a non-finite time (a particle whose position lies in no cell) has no
+    // usable sign, and only a boundary face may be re-emitted from.
+    const int code = m.nbr[4 * w.c + w.entry];
+    if (tq < 0 || code >= 0) {
         w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
     } else {
         // surface sampling needs the velocity the particle reached the wall with
         if (m.surf) {
             w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
         }
-        const int bf = -1 - m.nbr[4 * w.c + w.entry];
-        diffuse_reemit<VT>(m, w, bf, w.entry, step, kp);
+        diffuse_reemit<VT>(m, w, -1 - code, w.entry, step, kp);
     }
     return i;
 }

@@ -22,7 +22,7 @@ _lib = C.CDLL(LIB_PATH)
 STAGE_MOVE, STAGE_INJECT, STAGE_SORT, STAGE_COLLIDE, STAGE_SAMPLE = 1, 2, 4, 8, 16
 SAMPLE_STEADY, SAMPLE_EWMA, SAMPLE_INSTANT = 0, 1, 2
 STATUS = {0: "OK", -1: "INVALID", -2: "MESH", -3: "OOM", -4: "DEVICE", -5: "CAPACITY", -6: "LOST",
-          -7: "NOT_CONVERGED"}
+}
 
 P = C.c_void_p
 

@@ -392,3 +392,48 @@ def test_unconverged_solve_leaves_the_particles(dsmc):
     assert np.array_equal(gs["cell"], os_["cell"]) and np.array_equal(gs["pid"], os_["pid"])
     assert np.abs(gs["v"] - os_["v"]).max() <= 1e-9 * np.abs(os_["v"]).max()
     g.close()
+
+
+def test_full_size_coupling_cycle(dsmc):
+    """The coupled benchmark's size: the 384,000-tet jittered cavity at
+    Kn = 0.01 with 30 particles per cell (11.52M particles, FP32
+    velocities).  The oracle fills and runs two sampled steps; both sides
+    then make one coupling cycle from that state (gate, HoT, 8 pseudo-time
+    iterations, closed-domain mass rescale and feedback), with the
+    reductions of the solve spread over thousands of workgroups on the
+    device.  Criteria as above: report counts and iterations exact,
+    residual ratio 1e-8, sampled state bit-exact, M^{k+1} 1e-10; particle
+    count, cells and (cell, pid) order exact; positions 1e-12 m (clones are
+    placed from the generator and the mesh); velocities within one FP32
+    ulp or 1e-9 of the largest speed (the solve's ulp-level differences
+    carried into the FP32 store)."""
+    from parity_util import f32_ulp
+    wl = W.cavity(n_hex=40, Kn=0.01, ppc=30, jitter=0.1, vel_fp32=1, ewma_on=1, n_a=2)
+    print("full-size coupling: oracle fill and 2 steps", flush=True)
+    o = Oracle(wl)
+    o.step(2)
+    st = o.particles()
+    print(f"  {len(st['pid'])} particles loaded", flush=True)
+    g = dsmc.Simulation(wl, fill=False, capacity=2 * len(st["pid"]))
+    g.set_state(st["x"], st["v"], st["cell"], st["pid"], o.step_index, o.next_pid, o.smax())
+    g.set_sums(dsmc.SAMPLE_EWMA, o.sums(1), o.ewma_counts())
+    kw = dict(kn_max=1.0, passes=3, n_m=8, eps_m=1e-12, cfl=0.5, feedback=1, unconverged=1)
+    rg = g.dig_couple(**kw)
+    print("  device cycle done", rg, flush=True)
+    ro = o.dig_couple(**kw)
+    print("  oracle cycle done", ro, flush=True)
+    for k in ["n_rejected", "n_reconstructed", "n_unreached", "iters", "converged", "failed", "fed_back",
+              "np_before", "np_after"]:
+        assert rg[k] == ro[k], (k, rg[k], ro[k])
+    assert rg["fed_back"] == 1 and rg["np_after"] != rg["np_before"]
+    assert abs(rg["residual"] - ro["residual"]) <= 1e-8 * ro["residual"]
+    assert _nan_equal(g.dig_get("sampled"), o.dig_sampled())
+    _prim_close(g.dig_get("mprev"), o.mprev(), wl, 1e-10)
+    gs, os_ = g.state(), o.particles()
+    assert np.array_equal(gs["cell"], os_["cell"]) and np.array_equal(gs["pid"], os_["pid"])
+    assert np.abs(gs["x"] - os_["x"]).max() <= 1e-12
+    dv = np.abs(gs["v"] - os_["v"])
+    lim = np.maximum(f32_ulp(os_["v"]), 1e-9 * np.abs(os_["v"]).max())
+    assert (dv <= lim).all(), (dv / lim).max()
+    print(f"  exact velocities {float((dv == 0).mean()):.6f}", flush=True)
+    g.close()
