@@ -21,33 +21,31 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic HBM bytes of each kernel, FP32-velocity layout: a particle is
-# x,y,z f64 (24) + v f32 (12) + cell i32 (4) + pid u32 (4) = 44 bytes.
-#  move:         read x,v,cell,pid (44); write x,cell (28) + rank (4); a particle
-#                parked at a diffuse wall writes a 16-byte queue entry instead of
-#                its rank
-#  move_walls:   per parked particle: queue (16) + x,cell,pid (32) read;
-#                x,v,cell,rank (44) written
-#  sort_perm:    read cell, rank (8) + the cell offset (4); write perm and the
-#                slot's cell (8)
-#  sort_gather:  read perm (4) + a particle but its cell (40); write them (40)
-#  collide:      read pid, cell, v (20); write v of collided particles (12 each);
-#                per cell: offset (4), smax r/w (16), pair counts (8), steady
-#                sums read+write (208)
-#  scan:         per cell: counts read twice (8), offsets written (4)
+# Algorithmic HBM bytes of each stage of the step: what the method has to
+# move, for the FP32-velocity layout of 44 bytes per particle (x,y,z f64 24,
+# v f32 12, cell i32 4, pid u32 4), independent of how the kernels do it:
+#  move:     read x, v, cell, pid (44); write x, cell (28); write v of a
+#            particle that met a wall (12 per wall interaction)
+#  scan:     the cell histogram and offsets (8 per cell)
+#  sort:     read and write every particle once (44 + 44)
+#  collide:  read v, pid (16); write v of collided particles (12 each); per
+#            cell the offset and (sigma c)_max (16) and the 13 FP64 moment
+#            sums read and written (208)
+# Stage -> kernels whose launch times it sums.
 BYTES = {
-    "move": lambda np_, nt, f: np_ * (76.0 + 12.0 * f["park"]),
-    "move_walls": lambda np_, nt, f: np_ * f["park"] * 92.0,
-    "sort_perm": lambda np_, nt, f: np_ * 20.0,
-    "sort_gather": lambda np_, nt, f: np_ * 84.0,
-    "collide_sample": lambda np_, nt, f: np_ * (20.0 + 12.0 * f["touched"]) + nt * 236.0,
-    "scan": lambda np_, nt, f: nt * 12.0,
+    "move": lambda np_, nt, f: np_ * (72.0 + 12.0 * f["walls"]),
+    "scan": lambda np_, nt, f: nt * 8.0,
+    "sort": lambda np_, nt, f: np_ * 88.0,
+    "collide_sample": lambda np_, nt, f: np_ * (16.0 + 12.0 * f["touched"]) + nt * 224.0,
 }
+STAGES = {"move": ["move", "move_walls"], "scan": ["scan"], "sort": ["sort_perm", "sort_gather"],
+          "collide_sample": ["collide_sample"]}
 
-# rocprofv3 --pmc measurements of the move kernel (FETCH_SIZE + WRITE_SIZE per
-# dispatch, scaled by the copy-kernel calibration) and the source digest they
-# were taken on; the traffic figure is reported only while the digest matches.
-TRAFFIC = {"kernel": "move", "digest": "ca2cda55d5f77610", "bytes_per_launch": 576332646 + 580667654,
+# rocprofv3 --pmc measurements of the dominant stage's kernels (FETCH_SIZE +
+# WRITE_SIZE per step, summed over the stage's kernels and scaled by the
+# copy-kernel calibration) and the source digest they were taken on; the
+# traffic figure is reported only while the digest matches.
+TRAFFIC = {"stage": "move", "digest": "", "bytes_per_launch": 0,
            "workload": "cavity_40^3x6_Kn0.1", "source": "profiles/step_kernels_cavity40.md"}
 
 
@@ -58,18 +56,64 @@ def _kernel_digest():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(wl, steps):
-    """The oracle as it stands, single-threaded, on a bounded sample of the
-    same workload: `steps` steps from its initial fill."""
+def _host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
+def _oracle_cavity_small(seed):
+    """One full run of the CPU-finishable cavity in a fresh process: returns
+    (particle-steps, seconds)."""
+    from paper_2607_08195_amd import workloads as W
+    from oracle import Oracle
+    wl = W.cavity_small()
+    wl.run.seed = seed
+    o = Oracle(wl)
+    n0 = o.np
+    t0 = time.perf_counter()
+    o.step(500)
+    return 0.5 * (n0 + o.np) * 500, time.perf_counter() - t0
+
+
+def cpu_baseline(wl, steps, procs):
+    """The oracle as it stands, on the host cores: (1) single-threaded on a
+    bounded sample of the benchmark workload, `steps` steps from its initial
+    fill (the reported value); (2) the full 500-step run of the
+    CPU-finishable cavity (6^3 x 6 tets, 25,920 particles) single-threaded;
+    (3) `procs` such runs at once in independent processes with disjoint
+    seeds (aggregate particle-steps/s over the group's wall time)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
     from oracle import Oracle
     o = Oracle(wl)
     n = o.np
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
+    del o
+    ps, ts = _oracle_cavity_small(0)
+    with ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn")) as ex:
+        ex.submit(time.sleep, 0).result()          # workers started before the clock
+        t1 = time.perf_counter()
+        runs = list(ex.map(_oracle_cavity_small, range(1, procs + 1)))
+        tw = time.perf_counter() - t1
+    agg = sum(r[0] for r in runs) / tw
     return dict(value=n * steps / dt, unit="particle-steps/s", cores=1, kind="oracle",
                 sample=f"{wl.name}: {steps} steps from the initial fill ({n * steps:.3g} particle-steps, "
-                       f"{dt:.1f} s, 1 thread)")
+                       f"{dt:.1f} s, 1 thread)",
+                cavity_small_full={"value": ps / ts, "steps": 500, "particle_steps": ps, "seconds": round(ts, 2),
+                                   "cores": 1},
+                aggregate={"value": agg, "processes": procs, "workload": "cavity_6^3x6_Kn1 x 500 steps each",
+                           "seconds": round(tw, 2), "per_process_mean": sum(r[0] / r[1] for r in runs) / procs},
+                host=_host_cpu())
 
 
 def copy_rate(sim, nbytes=1 << 30, reps=5):
@@ -464,7 +508,11 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="step through captured HIP graphs (the default for the cavity workloads)")
     ap.add_argument("--eager", action="store_true", help="step with ordinary launches instead of graphs")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=4,
+                    help="oracle steps of the benchmark workload timed single-threaded")
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="concurrent oracle processes of the aggregate (0: the host's cores, at most 16)")
+    ap.add_argument("--cpu-only", action="store_true", help="time the oracle alone (no GPU)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="time a plain device copy of 2 GiB (HBM calibration of the traffic counters)")
@@ -474,6 +522,13 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a "
               "design note, not part of this build", file=sys.stderr)
         sys.exit(2)
+
+    procs = args.cpu_procs or max(1, min(16, os.cpu_count() or 1))
+    if args.cpu_only:
+        from paper_2607_08195_amd import workloads as W
+        wl = W.cavity_large()
+        print(json.dumps({"workload": wl.name, "cpu_baseline": cpu_baseline(wl, args.cpu_steps, procs)}))
+        return
 
     import numpy as np
     import torch
@@ -538,20 +593,22 @@ def main():
     for name, (ms, cnt) in prof.items():
         if cnt:
             per_launch[name] = ms / cnt
-    frac = {"park": walls_pp, "touched": touched_pp}
+    stage_ms = {k: sum(per_launch.get(n, 0.0) for n in ks) for k, ks in STAGES.items()}
+    frac = {"walls": walls_pp, "touched": touched_pp}
     bytes_launch = {k: fn(npart, nt, frac) for k, fn in BYTES.items()}
-    gbs = {k: bytes_launch[k] / (per_launch[k] * 1e-3) / 1e9 for k in bytes_launch if k in per_launch}
-    dominant = max((k for k in bytes_launch if k in per_launch), key=lambda k: per_launch[k])
+    gbs = {k: bytes_launch[k] / (stage_ms[k] * 1e-3) / 1e9 for k in bytes_launch if stage_ms[k] > 0}
+    dominant = max(gbs, key=lambda k: stage_ms[k])
     step_bytes = sum(bytes_launch.values())
     peak = 8000.0
     digest = _kernel_digest()
     traffic = None
-    if (TRAFFIC and TRAFFIC.get("digest") == digest and TRAFFIC.get("kernel") == dominant
+    if (TRAFFIC and TRAFFIC.get("digest") == digest and TRAFFIC.get("stage") == dominant
             and TRAFFIC.get("workload") == wl.name):
-        traffic = TRAFFIC["bytes_per_launch"] / 1e9 / (per_launch[dominant] * 1e-3)
-    roofline = dict(bound="hbm", kernel=dominant, achieved=round(gbs[dominant], 1), peak=peak, unit="GB/s",
-                    frac=round(gbs[dominant] / peak, 4),
-                    traffic=None if traffic is None else round(traffic, 1))
+        traffic = TRAFFIC["bytes_per_launch"] / 1e9 / (stage_ms[dominant] * 1e-3)
+    roofline = dict(bound="hbm", kernel=dominant, kernels=STAGES[dominant], achieved=round(gbs[dominant], 1),
+                    peak=peak, unit="GB/s", frac=round(gbs[dominant] / peak, 4),
+                    traffic=None if traffic is None else round(traffic, 1),
+                    bytes_per_particle_step=round(bytes_launch[dominant] / npart, 2))
     copy_gbs = copy_rate(sim)
 
     out = {
@@ -573,14 +630,16 @@ def main():
         "step_algorithmic_GBps": round(step_bytes / (elapsed / args.steps) / 1e9, 1),
         "hops_per_particle_step": round(hops_pp, 3),
         "kernel_ms": {k: round(v, 4) for k, v in per_launch.items()},
-        "kernel_GBps": {k: round(v, 1) for k, v in gbs.items()},
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "stage_algorithmic_GBps": {k: round(v, 1) for k, v in gbs.items()},
+        "step_algorithmic_bytes_per_particle": round(step_bytes / npart, 1),
         "roofline": roofline,
         "copy_kernel_GBps": round(copy_gbs, 1),
         "kernel_digest": digest,
     }
     sim.close()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps, procs)
     print(json.dumps(out))
 
 
