@@ -40,7 +40,13 @@ def _load():
     lib.oracle_num_particles.restype = i64
     lib.oracle_num_particles.argtypes = [P]
     lib.oracle_get_particles.argtypes = [P, P, P, P, P]
-    lib.oracle_set_particles.argtypes = [P, i64, P, P, P, P, u32, u32]
+    lib.oracle_set_particles.argtypes = [P, i64, P, P, P, P, u32, u32, P]
+    lib.oracle_set_rotation.argtypes = [P, C.c_int, d]
+    lib.oracle_inelastic_probability.argtypes = [P]
+    lib.oracle_inelastic_probability.restype = d
+    lib.oracle_get_rotation.argtypes = [P, P]
+    lib.oracle_get_rot_sums.argtypes = [P, C.c_int, P]
+    lib.oracle_rot_fields.argtypes = [P, C.c_int, P]
     lib.oracle_get_smax.argtypes = [P, P]
     lib.oracle_surface_sampling.argtypes = [P, C.c_int]
     lib.oracle_get_surface.argtypes = [P, P]
@@ -152,6 +158,9 @@ class Oracle:
             raise ValueError("oracle_create: " + lib.oracle_last_error().decode())
         if lib.oracle_set_alpha(self.h, float(sp.alpha)) != 0:
             raise ValueError("oracle_set_alpha: " + lib.oracle_last_error().decode())
+        self.dr = int(getattr(sp, "dof_rot", 0))
+        if lib.oracle_set_rotation(self.h, self.dr, float(getattr(sp, "z_rot", 0.0))) != 0:
+            raise ValueError("oracle_set_rotation: " + lib.oracle_last_error().decode())
         self.wl = wl
         if fill:
             u0 = np.asarray(run.u0, dtype=np.float64)
@@ -182,15 +191,35 @@ class Oracle:
         x = np.zeros((n, 3)); v = np.zeros((n, 3))
         c = np.zeros(n, np.int32); p = np.zeros(n, np.uint32)
         self.lib.oracle_get_particles(self.h, _p(x), _p(v), _p(c), _p(p))
-        return dict(x=x, v=v, cell=c, pid=p)
+        out = dict(x=x, v=v, cell=c, pid=p)
+        if self.dr:
+            ir = np.zeros(n)
+            self.lib.oracle_get_rotation(self.h, _p(ir))
+            out["ir"] = ir
+        return out
 
-    def set_particles(self, x, v, cell, pid, step, next_pid):
+    def set_particles(self, x, v, cell, pid, step, next_pid, ir=None):
         x = np.ascontiguousarray(x, np.float64); v = np.ascontiguousarray(v, np.float64)
         cell = np.ascontiguousarray(cell, np.int32); pid = np.ascontiguousarray(pid, np.uint32)
+        ir = None if ir is None else np.ascontiguousarray(ir, np.float64)
         r = self.lib.oracle_set_particles(self.h, len(cell), _p(x), _p(v), _p(cell), _p(pid),
-                                          step, next_pid)
+                                          step, next_pid, _p(ir))
         if r != 0:
             raise ValueError(self.lib.oracle_last_error().decode())
+
+    @property
+    def inelastic_probability(self):
+        return self.lib.oracle_inelastic_probability(self.h)
+
+    def rot_sums(self, which=0):
+        o = np.zeros((self.nt, 4))
+        self.lib.oracle_get_rot_sums(self.h, which, _p(o))
+        return o
+
+    def rot_fields(self, which=0):
+        o = np.zeros((self.nt, 4))
+        self.lib.oracle_rot_fields(self.h, which, _p(o))
+        return o
 
     def surface_sampling(self, on=True):
         self.lib.oracle_surface_sampling(self.h, 1 if on else 0)

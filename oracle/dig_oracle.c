@@ -724,6 +724,7 @@ void oracle_dig_feedback(osim* s, const double* po, const double* pn, const int*
                 }
                 s->cell[d] = c;
                 s->pid[d] = s->next_pid++;
+                if (s->dr) s->ir[d] = s->ir[a0 + src];
             }
         }
     }

@@ -14,6 +14,15 @@
  *    standard NTC expression.  Scattering is isotropic (VHS) or, with a
  *    VSS exponent alpha != 1, Bird's variable soft sphere deflection law
  *    (section 2.1 names the VSS model).
+ *  - Rotational energy (paper section 2.1, eq. dsmc_particle_state and
+ *    eq. inelastic_probability) for a gas with two rotational degrees of
+ *    freedom: every particle carries I_r, drawn from the equilibrium
+ *    distribution at the local temperature when it is created (fill,
+ *    inflow) or re-emitted by a diffuse wall; after an accepted collision
+ *    each partner in turn exchanges energy with the pair's relative
+ *    translation with probability P_inelastic (Borgnakke-Larsen, applied
+ *    particle by particle); the cells also sum I_r and v I_r (rotational
+ *    temperature and heat flux of eq. dsmc_temperatures).
  *  - Cell sampling: eq. (dsmc_temperatures); the exponential moving average
  *    eq. (exponential_average_moments_ch3) and the steady average
  *    eq. (steady_average_moments_ch3) of section 3.1; cells in local
@@ -127,7 +136,7 @@ void oracle_destroy(osim* s) {
                     s->g_shift, s->in_mean, s->in_a, s->in_beta, s->in_sig, s->in_ut1, s->in_ut2,
                     s->x, s->v, s->cell, s->pid, s->smax, s->ncand, s->nacc, s->start, s->acc,
                     s->ewma, s->ewma_m, s->local_acc, s->inst, s->cen, s->fcen, s->fnu, s->farea,
-                    s->lsq, s->mprev, s->surf};
+                    s->lsq, s->mprev, s->surf, s->ir, s->racc, s->rewma, s->rinst};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i) free(ptrs[i]);
     free(s);
 }
@@ -359,6 +368,7 @@ static void reserve(osim* s, int64_t need) {
     s->v = (double*)realloc(s->v, sizeof(double) * 3 * (size_t)c);
     s->cell = (int*)realloc(s->cell, sizeof(int) * (size_t)c);
     s->pid = (uint32_t*)realloc(s->pid, sizeof(uint32_t) * (size_t)c);
+    if (s->dr) s->ir = (double*)realloc(s->ir, sizeof(double) * (size_t)c);
     s->cap = c;
 }
 
@@ -385,14 +395,17 @@ static void stage_sort(osim* s) {
     double* v = (double*)malloc(sizeof(double) * 3 * (size_t)(s->cap ? s->cap : 1));
     int* c = (int*)malloc(sizeof(int) * (size_t)(s->cap ? s->cap : 1));
     uint32_t* p = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(s->cap ? s->cap : 1));
+    double* ir = s->dr ? (double*)malloc(sizeof(double) * (size_t)(s->cap ? s->cap : 1)) : NULL;
     for (int64_t k = 0; k < n; ++k) {
         int64_t i = idx[k];
         memcpy(x + 3 * k, s->x + 3 * i, sizeof(double) * 3);
         memcpy(v + 3 * k, s->v + 3 * i, sizeof(double) * 3);
         c[k] = s->cell[i]; p[k] = s->pid[i];
+        if (ir) ir[k] = s->ir[i];
     }
     free(s->x); free(s->v); free(s->cell); free(s->pid); free(idx);
     s->x = x; s->v = v; s->cell = c; s->pid = p; s->np = n;
+    if (ir) { free(s->ir); s->ir = ir; }
     for (int t = 0; t <= s->nt; ++t) s->start[t] = 0;
     for (int64_t k = 0; k < n; ++k) s->start[s->cell[k] + 1]++;
     for (int t = 0; t < s->nt; ++t) s->start[t + 1] += s->start[t];
@@ -444,6 +457,11 @@ int oracle_init_fill(osim* s, double n0, double T0, const double* u0) {
             s->v[3 * k + 2] = to_store(s, u0[2] + sig * g3);
             s->cell[k] = t;
             s->pid[k] = id;
+            if (s->dr) {
+                /* two rotational degrees of freedom: exponential with mean k T0 */
+                draw(s, id, 0, P_INIT, 4, w);
+                s->ir[k] = -(KB * T0) * log(u01(w[0], w[1]));
+            }
         }
     }
     free(cnt);
@@ -487,7 +505,7 @@ static double dot_fused(const double* n, const double* a) {
 }
 
 /* returns 0 alive, 1 removed through an open boundary, 2 lost */
-static int trace(osim* s, double* x, double* v, int* cellp, int entry, uint32_t pid, uint32_t step,
+static int trace(osim* s, double* x, double* v, double* ir, int* cellp, int entry, uint32_t pid, uint32_t step,
                  double t) {
     int c = *cellp;
     int nhop = 0, hits = 0;
@@ -544,6 +562,8 @@ static int trace(osim* s, double* x, double* v, int* cellp, int entry, uint32_t 
                 v[i] = to_store(s, (vn * nin[i] + tang) + uw[i]);
             }
             surface_hit(s, bf, step, vin, v);
+            /* the re-emitted molecule's rotation is in equilibrium at the wall */
+            if (ir) *ir = -(KB * Tw) * log(u01(w[2], w[3]));
             ++hits;
             s->walls++;
             entry = fb;
@@ -581,7 +601,7 @@ static int trace(osim* s, double* x, double* v, int* cellp, int entry, uint32_t 
 
 int oracle_trace_one(osim* s, double* x, double* v, int cell, uint32_t pid, uint32_t step, double t) {
     int c = cell;
-    int st = trace(s, x, v, &c, -1, pid, step, t);
+    int st = trace(s, x, v, NULL, &c, -1, pid, step, t);
     return st == 0 ? c : -1;
 }
 
@@ -589,7 +609,7 @@ static void stage_move(osim* s) {
     for (int64_t i = 0; i < s->np; ++i) {
         if (s->cell[i] < 0) continue;
         int c = s->cell[i];
-        int st = trace(s, s->x + 3 * i, s->v + 3 * i, &c, -1, s->pid[i], s->step, s->dt);
+        int st = trace(s, s->x + 3 * i, s->v + 3 * i, s->dr ? s->ir + i : NULL, &c, -1, s->pid[i], s->step, s->dt);
         s->cell[i] = st == 0 ? c : -1;
     }
 }
@@ -670,13 +690,20 @@ static void stage_inject(osim* s) {
             uint32_t id = s->next_pid++;
             s->injected++;
             int c = s->bf_tet[b];
-            int st = trace(s, x, v, &c, s->bf_lf[b], id, s->step, ut * s->dt);
+            double irot = 0.0;
+            if (s->dr) {
+                /* freestream rotation in equilibrium at the freestream temperature */
+                draw(s, (uint32_t)b, s->step, P_INJECT, kb | 1u, w);
+                irot = -(KB * s->g_T[g]) * log(u01(w[2], w[3]));
+            }
+            int st = trace(s, x, v, s->dr ? &irot : NULL, &c, s->bf_lf[b], id, s->step, ut * s->dt);
             if (st != 0) continue;
             reserve(s, s->np + 1);
             memcpy(s->x + 3 * s->np, x, sizeof x);
             memcpy(s->v + 3 * s->np, v, sizeof v);
             s->cell[s->np] = c;
             s->pid[s->np] = id;
+            if (s->dr) s->ir[s->np] = irot;
             s->np++;
         }
     }
@@ -755,8 +782,48 @@ static void stage_collide(osim* s) {
             if (!(U < sc / smax)) continue;
             ++acc;
             draw(s, (uint32_t)c, s->step, P_SCATTER, (uint64_t)k, w);
+            double R1 = u01(w[0], w[1]), R2 = u01(w[2], w[3]);
             double gp[3];
-            scatter(s, gx, gy, gz, cr2, u01(w[0], w[1]), u01(w[2], w[3]), gp);
+            if (s->dr) {
+                /* Borgnakke-Larsen, particle by particle: with probability
+                 * P_inelastic a partner's rotational energy and the relative
+                 * translational energy E_t = m_r c_r^2 / 2 (m_r = m/2) are
+                 * pooled into E_c and split again; the translational share
+                 * E_t / E_c of a molecule with two rotational degrees of
+                 * freedom follows Beta(5/2 - omega, 1), whose inverse
+                 * distribution function gives E_t = E_c R^(1/(5/2 - omega)). */
+                double* Ii = s->ir + a + i;
+                double* Ij = s->ir + a + j;
+                double Et = (0.25 * s->m) * cr2;
+                double ex = 1.0 / (2.5 - s->omega);
+                int inel = 0;
+                uint32_t wi[4];
+                draw(s, (uint32_t)c, s->step, P_INELASTIC_I, (uint64_t)k, wi);
+                if (u01(wi[0], wi[1]) < s->pinel) {
+                    double Ec = Et + *Ii;
+                    Et = Ec * pow(u01(wi[2], wi[3]), ex);
+                    *Ii = Ec - Et;
+                    inel = 1;
+                }
+                draw(s, (uint32_t)c, s->step, P_INELASTIC_J, (uint64_t)k, wi);
+                if (u01(wi[0], wi[1]) < s->pinel) {
+                    double Ec = Et + *Ij;
+                    Et = Ec * pow(u01(wi[2], wi[3]), ex);
+                    *Ij = Ec - Et;
+                    inel = 1;
+                }
+                if (inel) {
+                    /* the relative velocity keeps its direction (the VSS
+                     * deflection is taken from it) and takes the new speed */
+                    double cr2n = (4.0 * Et) / s->m;
+                    double f = sqrt(cr2n / cr2);
+                    scatter(s, gx * f, gy * f, gz * f, cr2n, R1, R2, gp);
+                } else {
+                    scatter(s, gx, gy, gz, cr2, R1, R2, gp);
+                }
+            } else {
+                scatter(s, gx, gy, gz, cr2, R1, R2, gp);
+            }
             for (int d = 0; d < 3; ++d) {
                 double cm = 0.5 * (vi[d] + vj[d]);
                 double hg = 0.5 * gp[d];
@@ -776,8 +843,9 @@ static void stage_collide(osim* s) {
 static void stage_sample(osim* s) {
     int steady = (int64_t)s->step > (int64_t)s->n_ss;
     for (int c = 0; c < s->nt; ++c) {
-        double S[NMOM];
+        double S[NMOM], Rs[NROT];
         for (int k = 0; k < NMOM; ++k) S[k] = 0.0;
+        for (int k = 0; k < NROT; ++k) Rs[k] = 0.0;
         for (int64_t p = s->start[c]; p < s->start[c + 1]; ++p) {
             double vx = s->v[3 * p], vy = s->v[3 * p + 1], vz = s->v[3 * p + 2];
             double v2 = vx * vx + vy * vy + vz * vz;
@@ -786,10 +854,19 @@ static void stage_sample(osim* s) {
             S[4] += vx * vx; S[5] += vy * vy; S[6] += vz * vz;
             S[7] += vx * vy; S[8] += vx * vz; S[9] += vy * vz;
             S[10] += vx * v2; S[11] += vy * v2; S[12] += vz * v2;
+            if (s->dr) {
+                double I = s->ir[p];
+                Rs[0] += I;
+                Rs[1] += vx * I; Rs[2] += vy * I; Rs[3] += vz * I;
+            }
         }
         memcpy(s->inst + NMOM * (size_t)c, S, sizeof S);
-        if (steady)
+        if (s->dr) memcpy(s->rinst + NROT * (size_t)c, Rs, sizeof Rs);
+        if (steady) {
             for (int k = 0; k < NMOM; ++k) s->acc[NMOM * (size_t)c + k] += S[k];
+            if (s->dr)
+                for (int k = 0; k < NROT; ++k) s->racc[NROT * (size_t)c + k] += Rs[k];
+        }
         if (s->ewma_on) {
             int m = ++s->ewma_m[c];
             int n = (s->local_acc[c] || m < s->n_a) ? m : s->n_a;
@@ -799,6 +876,11 @@ static void stage_sample(osim* s) {
                 double* e = s->ewma + NMOM * (size_t)c + k;
                 *e = wo * *e + wn * S[k];
             }
+            if (s->dr)
+                for (int k = 0; k < NROT; ++k) {
+                    double* e = s->rewma + NROT * (size_t)c + k;
+                    *e = wo * *e + wn * Rs[k];
+                }
         }
     }
     if (steady) s->n_steady++;
@@ -830,10 +912,12 @@ void oracle_get_particles(const osim* s, double* x, double* v, int* cell, uint32
 }
 
 int oracle_set_particles(osim* s, int64_t np, const double* x, const double* v, const int* cell,
-                         const uint32_t* pid, uint32_t step, uint32_t next_pid) {
+                         const uint32_t* pid, uint32_t step, uint32_t next_pid, const double* ir) {
     reserve(s, np);
     for (int64_t i = 0; i < np; ++i)
         if (cell[i] < 0 || cell[i] >= s->nt) { set_err("particle cell out of range"); return -1; }
+    if (s->dr)
+        for (int64_t i = 0; i < np; ++i) s->ir[i] = ir ? ir[i] : 0.0;
     memcpy(s->x, x, sizeof(double) * 3 * (size_t)np);
     for (int64_t i = 0; i < 3 * np; ++i) s->v[i] = to_store(s, v[i]);
     memcpy(s->cell, cell, sizeof(int) * (size_t)np);
@@ -843,6 +927,65 @@ int oracle_set_particles(osim* s, int64_t np, const double* x, const double* v, 
     s->next_pid = next_pid;
     stage_sort(s);
     return 0;
+}
+
+/* Rotational degrees of freedom (0 or 2) and rotational collision number;
+ * the inelastic probability is eq. (inelastic_probability) with the
+ * species' VSS exponent and viscosity index (call after oracle_set_alpha
+ * and before the fill). */
+int oracle_set_rotation(osim* s, int dr, double zr) {
+    if (!(dr == 0 || dr == 2) || (dr && !(zr > 0.0))) {
+        set_err("rotational degrees of freedom must be 0 or 2, with a positive collision number");
+        return -1;
+    }
+    s->dr = dr;
+    s->zr = zr;
+    double a = s->alpha, w = s->omega;
+    s->pinel = dr ? ((a * (5.0 - 2.0 * w)) * (7.0 - 2.0 * w)) / ((((5.0 * (a + 1.0)) * (a + 2.0))) * zr) : 0.0;
+    if (dr) {
+        size_t ntz = (size_t)s->nt;
+        s->ir = (double*)realloc(s->ir, sizeof(double) * (size_t)(s->cap ? s->cap : 1));
+        for (int64_t i = 0; i < s->cap; ++i) s->ir[i] = 0.0;
+        free(s->racc); free(s->rewma); free(s->rinst);
+        s->racc = (double*)calloc(ntz * NROT, sizeof(double));
+        s->rewma = (double*)calloc(ntz * NROT, sizeof(double));
+        s->rinst = (double*)calloc(ntz * NROT, sizeof(double));
+    }
+    return 0;
+}
+
+double oracle_inelastic_probability(const osim* s) { return s->pinel; }
+
+void oracle_get_rotation(const osim* s, double* ir) {
+    if (s->dr && ir) memcpy(ir, s->ir, sizeof(double) * (size_t)s->np);
+}
+
+/* Rotational sums out[nt][4] = sum I_r, sum v_i I_r of an accumulator
+ * (0 steady, 1 moving average, 2 last step). */
+void oracle_get_rot_sums(const osim* s, int which, double* out) {
+    const double* src = which == 0 ? s->racc : which == 1 ? s->rewma : s->rinst;
+    if (s->dr) memcpy(out, src, sizeof(double) * NROT * (size_t)s->nt);
+}
+
+/* Rotational temperature and heat flux out[nt][4] (eq. dsmc_temperatures):
+ * T_r = 2 <I_r> / (d_r k), q_r,i = (N_eff / V) sum (v_i - u_i) I_r per
+ * sample; NaN where the cell has no samples. */
+void oracle_rot_fields(const osim* s, int which, double* out) {
+    const double* S = which == 0 ? s->acc : which == 1 ? s->ewma : s->inst;
+    const double* R = which == 0 ? s->racc : which == 1 ? s->rewma : s->rinst;
+    double ns = which == 0 ? (double)s->n_steady : 1.0;
+    for (int c = 0; c < s->nt; ++c) {
+        const double* a = S + NMOM * (size_t)c;
+        const double* r = R + NROT * (size_t)c;
+        double* o = out + 4 * (size_t)c;
+        if (!s->dr || !(a[0] > 0) || !(ns > 0)) {
+            for (int k = 0; k < 4; ++k) o[k] = NAN;
+            continue;
+        }
+        o[0] = (2.0 * (r[0] / a[0])) / ((double)s->dr * KB);
+        double f = s->FN / (s->vol[c] * ns);
+        for (int i = 0; i < 3; ++i) o[1 + i] = f * (r[1 + i] - (a[1 + i] / a[0]) * r[0]);
+    }
 }
 
 int oracle_set_alpha(osim* s, double alpha) {

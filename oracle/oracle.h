@@ -52,11 +52,24 @@ int oracle_step_stages(osim*, int mask);
 /* State in (cell, pid) order. */
 int64_t oracle_num_particles(const osim*);
 void oracle_get_particles(const osim*, double* x, double* v, int* cell, uint32_t* pid);
+/* ir[np]: rotational energies (J) when the gas rotates (NULL: zero). */
 int oracle_set_particles(osim*, int64_t np, const double* x, const double* v,
-                         const int* cell, const uint32_t* pid, uint32_t step, uint32_t next_pid);
+                         const int* cell, const uint32_t* pid, uint32_t step, uint32_t next_pid,
+                         const double* ir);
 /* VSS scattering exponent (section 2.1; 1, the default, is VHS).  Also
  * scales the viscosity the continuum side uses.  -1 unless alpha > 0. */
 int oracle_set_alpha(osim*, double alpha);
+/* Rotational degrees of freedom d_r (0 or 2) and rotational collision
+ * number Z_r (section 2.1, eq. inelastic_probability); call after
+ * oracle_set_alpha and before the fill.  -1 on other values. */
+int oracle_set_rotation(osim*, int dr, double zr);
+double oracle_inelastic_probability(const osim*);
+/* Rotational energies in (cell, pid) order (nothing for a monatomic gas). */
+void oracle_get_rotation(const osim*, double* ir);
+/* Rotational sums [nt][4] = sum I_r, sum v_i I_r (0 steady, 1 moving
+ * average, 2 last step) and fields [nt][4] = T_r, q_r (eq. dsmc_temperatures). */
+void oracle_get_rot_sums(const osim*, int which, double* out);
+void oracle_rot_fields(const osim*, int which, double* out);
 /* Viscosity of the species at temperature T (VHS/VSS power law). */
 double oracle_viscosity(const osim*, double T);
 void oracle_get_smax(const osim*, double* out);

@@ -14,12 +14,15 @@
 #define NMOM 13
 
 enum { P_INIT = 1, P_WALL = 2, P_INJCOUNT = 3, P_NTCCOUNT = 4, P_PAIR = 5, P_SCATTER = 6,
-       P_INITCOUNT = 9, P_INJECT = 10 };
+       P_INITCOUNT = 9, P_INJECT = 10, P_INELASTIC_I = 11, P_INELASTIC_J = 12 };
+#define NROT 4  /* rotational sums per cell: sum I_r, sum v_i I_r */
 
 struct osim {
     /* species */
     double m, dref, omega, Tref, K, ex;
     double alpha;       /* VSS scattering exponent; 1 is VHS (isotropic) */
+    int dr;             /* rotational degrees of freedom: 0 (monatomic) or 2 */
+    double zr, pinel;   /* rotational collision number; inelastic probability */
     /* run */
     double FN, dt;
     uint32_t seed, case_id;
@@ -45,12 +48,14 @@ struct osim {
     /* particles, kept in (cell, pid) order after the sort stage */
     int64_t np, cap;
     double* x; double* v; int* cell; uint32_t* pid;
+    double* ir;         /* rotational energy (J) of each particle when dr > 0 */
     uint32_t next_pid, step;
     /* per cell */
     double* smax; int* ncand; int* nacc; int64_t* start;
     double* acc; int64_t n_steady;
     double* ewma; int* ewma_m; unsigned char* local_acc;
     double* inst;
+    double* racc; double* rewma; double* rinst;  /* [nt][NROT] when dr > 0 */
     /* counters */
     int64_t hops, walls, injected, removed, lost;
     /* surface sampling: [nb][5] sums of (v_in - v_out), (|v_in|^2 - |v_out|^2)/2

@@ -31,6 +31,8 @@ class Species:
     omega: float = 0.81
     T_ref: float = 273.0
     alpha: float = 1.0          # 1 = VHS
+    dof_rot: int = 0            # rotational degrees of freedom (0 or 2)
+    z_rot: float = 0.0          # rotational collision number
 
     def mu(self, T):
         """VHS/VSS viscosity at temperature T (power law in T with index
