@@ -74,6 +74,24 @@ dsmc_status dsmc_mlp_forward(dsmc_mlp net, const float* x, int64_t n, float* y, 
  * grad[35977] (layout of the parameters) and *loss. */
 dsmc_status dsmc_mlp_backward(dsmc_mlp net, const float* x, const float* t, int64_t n, float* grad, double* loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * gradient of dsmc_mlp_backward with every array in device memory and no
+ * allocation, host synchronisation or host copy.  x[rows][13], t[rows][9]
+ * (inputs), grad[35977] and *loss (the mean squared error, outputs) are
+ * device pointers the caller owns; rows must be between 1 and
+ * DSMC_MLP_NOALLOC_MAX_ROWS (DSMC_E_INVALID otherwise).  The work is
+ * enqueued on the network's stream and the call returns at once.  Its
+ * per-block partials live in a fixed scratch array of the library
+ * (DSMC_MLP_NOALLOC_MAX_ROWS / 32 blocks of 35,977 floats, 18.4 MB, held on
+ * each device that creates a network until the process ends) shared by
+ * every call on that device: calls that overlap on one device race, so the
+ * caller orders them (one stream, or events).  Results equal
+ * dsmc_mlp_backward's on the same rows. */
+#define DSMC_MLP_NOALLOC_MAX_ROWS 4096
+dsmc_status dsmc_mlp_backward_noalloc(dsmc_mlp net, const float* x, const float* t, int64_t rows, float* grad,
+                                      double* loss);
+
 /* One Adam step with a caller-given gradient grad[35977]. */
 dsmc_status dsmc_mlp_adam_step(dsmc_mlp net, const float* grad, float lr, float beta1, float beta2, float eps);
 

@@ -48,8 +48,9 @@ void launch_mlp_forward(hipStream_t s, const MlpDev& m, const float* x, const in
 int64_t mlp_blocks(int64_t n);
 void launch_mlp_grad(hipStream_t s, const MlpDev& m, const float* x, const float* t, const int32_t* idx, int64_t n,
                      float* partial, float* loss_partial);
+// grad = sum of the block partials; *loss = (sum of the loss partials) / denom
 void launch_mlp_reduce(hipStream_t s, const float* partial, const float* loss_partial, int64_t nblk, float* grad,
-                       double* loss);
+                       double* loss, double denom = 1.0);
 void launch_mlp_adam(hipStream_t s, float* params, const float* grad, float* m, float* v, int step, float lr,
                      float b1, float b2, float eps);
 void launch_mlp_init(hipStream_t s, float* params, RngKey key);

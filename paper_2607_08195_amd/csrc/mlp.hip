@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_tile(MlpDev m, const float* x,
 
 // grad[p] = sum over blocks of the partials (fixed order); loss likewise.
 __global__ void k_mlp_reduce(const float* partial, const float* loss_partial, int64_t nblk, float* grad,
-                             double* loss) {
+                             double* loss, double denom) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p < kMlpParams) {
         float s = 0.f;
@@ -285,7 +285,7 @@ __global__ void k_mlp_reduce(const float* partial, const float* loss_partial, in
     if (p == 0) {
         double s = 0.0;
         for (int64_t b = 0; b < nblk; ++b) s += (double)loss_partial[b];
-        *loss = s;
+        *loss = s / denom;
     }
 }
 
@@ -391,9 +391,9 @@ void launch_mlp_grad(hipStream_t s, const MlpDev& m, const float* x, const float
 }
 
 void launch_mlp_reduce(hipStream_t s, const float* partial, const float* loss_partial, int64_t nblk, float* grad,
-                       double* loss) {
+                       double* loss, double denom) {
     hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, partial, loss_partial, nblk,
-                       grad, loss);
+                       grad, loss, denom);
 }
 
 void launch_mlp_adam(hipStream_t s, float* params, const float* grad, float* m, float* v, int step, float lr,

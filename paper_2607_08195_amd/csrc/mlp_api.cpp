@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -11,6 +12,7 @@
 
 struct dsmc_mlp_s {
     hipStream_t stream = nullptr;
+    int device = 0;             // the device current at create
     dsmc_allocator alloc{};
     bool has_alloc = false;
     std::vector<void*> owned;
@@ -117,6 +119,41 @@ dsmc_status ensure_blocks(dsmc_mlp n, int64_t blocks) {
 
 MlpDev view(dsmc_mlp n) { return mlp_dev_view(n->params, n->packed); }
 
+// Scratch of dsmc_mlp_backward_noalloc, one copy per device for the life of
+// the process: the per-block gradient partials of at most
+// DSMC_MLP_NOALLOC_MAX_ROWS rows ([blocks][kMlpParams] floats) followed by
+// the per-block loss partials.  Every block writes its whole partial, so
+// nothing has to start at zero.
+constexpr int64_t kNoAllocBlocks = DSMC_MLP_NOALLOC_MAX_ROWS / kMlpTile;
+constexpr size_t kNoAllocLossOffset = ((sizeof(float) * kMlpParams * kNoAllocBlocks + 255) / 256) * 256;
+constexpr size_t kNoAllocBytes = kNoAllocLossOffset + sizeof(float) * kNoAllocBlocks;
+static_assert(DSMC_MLP_NOALLOC_MAX_ROWS % kMlpTile == 0, "whole tiles");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+// The device address of this device's scratch (host code must not use the
+// array's own name: it is a host-side stand-in).  Called by dsmc_mlp_create
+// with the network's device current.
+dsmc_status bind_scratch(dsmc_mlp n) {
+    if (n->device < 0 || n->device >= kMaxDevices) return mfail(n, DSMC_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[n->device]) return DSMC_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return mfail(n, DSMC_E_DEVICE, std::string("hipGetSymbolAddress of the scratch failed: ") + hipGetErrorString(e));
+    g_scratch_ptr[n->device] = ptr;
+    return DSMC_OK;
+}
+
 }  // namespace
 
 namespace dsmcx {
@@ -132,6 +169,15 @@ dsmc_status dsmc_mlp_create(dsmc_mlp* out, void* hip_stream, const dsmc_allocato
     *out = nullptr;
     dsmc_mlp n = new dsmc_mlp_s();
     n->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&n->device) != hipSuccess) {
+        delete n;
+        return mfail(nullptr, DSMC_E_DEVICE, "no current device");
+    }
+    if (bind_scratch(n) != DSMC_OK) {
+        std::string m = n->err;
+        delete n;
+        return mfail(nullptr, DSMC_E_DEVICE, m);
+    }
     if (allocator) {
         if (!allocator->alloc || !allocator->free) {
             delete n;
@@ -230,6 +276,26 @@ dsmc_status dsmc_mlp_backward(dsmc_mlp n, const float* x, const float* t, int64_
     MLP_TRY(n, hipMemcpyAsync(&l, n->loss, sizeof(double), hipMemcpyDeviceToHost, n->stream));
     MLP_TRY(n, hipStreamSynchronize(n->stream));
     if (loss) *loss = l / ((double)rows * kMlpOut);
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_mlp_backward_noalloc(dsmc_mlp n, const float* x, const float* t, int64_t rows, float* grad,
+                                      double* loss) {
+    if (!n || !x || !t || !grad || !loss) return mfail(n, DSMC_E_INVALID, "bad arguments");
+    if (rows <= 0 || rows > DSMC_MLP_NOALLOC_MAX_ROWS)
+        return mfail(n, DSMC_E_INVALID, "rows must be between 1 and DSMC_MLP_NOALLOC_MAX_ROWS (" +
+                                            std::to_string(DSMC_MLP_NOALLOC_MAX_ROWS) + ")");
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        base = g_scratch_ptr[n->device];
+    }
+    if (!base) return mfail(n, DSMC_E_DEVICE, "the scratch of this device has no address");
+    float* partial = (float*)base;
+    float* loss_partial = (float*)((unsigned char*)base + kNoAllocLossOffset);
+    launch_mlp_grad(n->stream, view(n), x, t, nullptr, rows, partial, loss_partial);
+    launch_mlp_reduce(n->stream, partial, loss_partial, mlp_blocks(rows), grad, loss, (double)rows * kMlpOut);
+    MLP_TRY(n, hipGetLastError());
     return DSMC_OK;
 }
 

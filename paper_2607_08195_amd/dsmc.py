@@ -153,6 +153,7 @@ _lib.dsmc_mlp_get_weights.argtypes = [P, P]
 _lib.dsmc_mlp_init_weights.argtypes = [P, C.c_uint64]
 _lib.dsmc_mlp_forward.argtypes = [P, P, C.c_int64, P, C.c_int32]
 _lib.dsmc_mlp_backward.argtypes = [P, P, P, C.c_int64, P, C.POINTER(C.c_double)]
+_lib.dsmc_mlp_backward_noalloc.argtypes = [P, P, P, C.c_int64, P, P]
 _lib.dsmc_mlp_adam_step.argtypes = [P, P, C.c_float, C.c_float, C.c_float, C.c_float]
 _lib.dsmc_mlp_train.argtypes = [P, P, P, C.c_int64, C.POINTER(MlpTrainParams), C.POINTER(MlpTrainReport)]
 _lib.dsmc_mlp_last_error.argtypes = [P]
@@ -169,7 +170,7 @@ for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_ge
            "dsmc_profile", "dsmc_philox", "dsmc_device_copy", "dig_couple", "dig_get", "dig_residual",
            "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
            "dsmc_mlp_get_weights", "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train",
-           "dsmc_mlp_init_weights", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_surface_sampling", "dsmc_get_surface",
+           "dsmc_mlp_init_weights", "dsmc_mlp_backward_noalloc", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_surface_sampling", "dsmc_get_surface",
            "dsmc_instant_sampling", "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
            "dsmc_get_tuning", "dsmc_set_tuning", "dsmc_autotune"]:
     getattr(_lib, _f).restype = C.c_int32
@@ -179,7 +180,8 @@ EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_g
             "dsmc_profile", "dsmc_profile_read", "dsmc_profile_name", "dsmc_philox", "dsmc_device_copy",
             "dsmc_last_error", "dsmc_destroy", "dig_couple", "dig_get", "dig_residual", "dig_solve",
             "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights", "dsmc_mlp_get_weights",
-            "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train", "dsmc_mlp_last_error",
+            "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_backward_noalloc", "dsmc_mlp_adam_step",
+            "dsmc_mlp_train", "dsmc_mlp_last_error",
             "dsmc_mlp_destroy", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_surface_sampling",
             "dsmc_get_surface", "dsmc_instant_sampling"]
 
@@ -532,6 +534,16 @@ class Mlp:
         loss = C.c_double()
         self._c(_lib.dsmc_mlp_backward(self.h, _p(x), _p(t), x.shape[0], _p(g), C.byref(loss)))
         return float(loss.value), g
+
+    def backward_noalloc(self, x, t, grad, loss):
+        """dsmc_mlp_backward_noalloc on device tensors (x [n,13], t [n,9],
+        grad [35977] float32, loss [1] float64): enqueued on the network's
+        stream, no allocation and no synchronisation."""
+        for a, dt in ((x, torch.float32), (t, torch.float32), (grad, torch.float32), (loss, torch.float64)):
+            if not (a.is_cuda and a.is_contiguous() and a.dtype == dt):
+                raise ValueError("device tensors, contiguous, float32 (float64 for loss) expected")
+        self._c(_lib.dsmc_mlp_backward_noalloc(self.h, P(x.data_ptr()), P(t.data_ptr()), x.shape[0],
+                                               P(grad.data_ptr()), P(loss.data_ptr())))
 
     def adam_step(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         g = np.ascontiguousarray(grad, np.float32)
