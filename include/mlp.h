@@ -103,9 +103,13 @@ const char* dsmc_mlp_last_error(dsmc_mlp net);
 void dsmc_mlp_destroy(dsmc_mlp net);
 
 /* Closure of the coupling step (dig_couple): with a network, every cell with
- * samples gets the network's HoT when its distance to the sampled HoT,
- * relative to max(|(sigma/p, q/(p sqrt(RT)))| of the samples, 1e-3), is at
- * most gate_tol; otherwise (or with net NULL) the sampled HoT.  The network
+ * samples gets the network's HoT when its distance to the sampled HoT is at
+ * most gate_tol times max(sqrt(s^2 + 14.5 / n), 1e-3), with s =
+ * |(sigma/p, q/(p sqrt(RT)))| of the samples and n the particle samples of
+ * the moving average (mean particles per step x min(samples taken, n_a)):
+ * 14.5 / n is the expected squared sampling error of that vector in an
+ * equilibrium gas, so a network within a few noise widths of the window's
+ * own HoT is accepted; otherwise (or with net NULL) the sampled HoT.  The network
  * must stay alive while it is attached.  The report of dig_couple counts
  * the cells that took the network (n_closure) and fell back (n_fallback). */
 dsmc_status dig_set_closure(dsmc_ctx ctx, dsmc_mlp net, double gate_tol);

@@ -144,9 +144,21 @@ def closure_targets(hot, rho, T, R):
     return np.concatenate([hot[:, :6] / p[:, None], hot[:, 6:] / (p * cs)[:, None]], axis=1)
 
 
-def gate(mlp_out, sampled_hot_nd, sampled_stress_nd, tol):
-    """Per cell: use the MLP when its distance to the sampled HoT, relative
-    to max(|sampled stress and heat flux|, 1e-3), is at most tol and finite."""
-    e = np.linalg.norm(mlp_out - sampled_hot_nd, axis=1) / np.maximum(
-        np.linalg.norm(sampled_stress_nd, axis=1), 1e-3)
+# Expected squared norm of the nondimensional (sigma/p, q/(p sqrt(RT)))
+# estimated from one Maxwellian particle: 3 x 4/3 (normal stresses) + 3 x 1
+# (shear stresses) + 3 x 5/2 (heat fluxes), from the Gaussian moments.
+NOISE_PER_PARTICLE = 14.5
+
+
+def gate(mlp_out, sampled_hot_nd, sampled_stress_nd, tol, n_samples=None):
+    """Per cell: use the MLP when its distance to the sampled HoT is at most
+    tol times max(sqrt(|sampled stress and heat flux|^2 + noise^2), 1e-3)
+    and finite, the noise being the sampling error of that vector for
+    n_samples particle samples (14.5 / n_samples; none when n_samples is
+    None): a network within the sample's own noise of it is accepted."""
+    s2 = np.sum(np.asarray(sampled_stress_nd, dtype=np.float64) ** 2, axis=1)
+    if n_samples is not None:
+        n = np.asarray(n_samples, dtype=np.float64)
+        s2 = s2 + np.where(n > 0, NOISE_PER_PARTICLE / np.where(n > 0, n, 1.0), 0.0)
+    e = np.linalg.norm(mlp_out - sampled_hot_nd, axis=1) / np.maximum(np.sqrt(s2), 1e-3)
     return np.isfinite(e) & (e <= tol), e

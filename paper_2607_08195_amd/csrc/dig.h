@@ -162,6 +162,9 @@ void launch_dig_count_all(hipStream_t s, const int32_t* cell, const Scalars* sc,
                           int64_t bound);
 void launch_fill_u8(hipStream_t s, uint8_t* p, uint8_t v, int64_t n);
 void launch_dig_closure_prep(hipStream_t s, const DigGeom& g, DigWork w);
-void launch_dig_closure_gate(hipStream_t s, const DigGeom& g, DigWork w, double tol);
+// ewma [13][nt] moving-average sums (row 0: mean particles per step), ewma_m
+// [nt] samples taken, n_a the moving average's length
+void launch_dig_closure_gate(hipStream_t s, const DigGeom& g, DigWork w, double tol, const double* ewma,
+                             const int32_t* ewma_m, int n_a);
 
 }  // namespace dsmcx

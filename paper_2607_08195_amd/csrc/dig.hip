@@ -928,9 +928,14 @@ __global__ void k_dig_closure_prep(DigGeom g, DigWork w) {
     }
 }
 
-// Take the network's HoT where its distance to the sampled HoT, relative
-// to max(|sampled stress, heat flux|, 1e-3), is at most tol.
-__global__ void k_dig_closure_gate(DigGeom g, DigWork w, double tol) {
+// Take the network's HoT where its distance to the sampled HoT is at most
+// tol times max(sqrt(|sampled stress, heat flux|^2 + noise^2), 1e-3), the
+// noise being the sampling error of that nondimensional vector over the
+// moving average's particle samples: 14.5 / (mean particles per step x
+// min(samples taken, n_a)) (Gaussian moments: 3 x 4/3 + 3 x 1 + 3 x 5/2
+// per particle).
+__global__ void k_dig_closure_gate(DigGeom g, DigWork w, double tol, const double* ewma, const int32_t* ewma_m,
+                                   int n_a) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     int used = 0, fell = 0;
     if (c < g.nt && w.cvalid[c]) {
@@ -943,6 +948,9 @@ __global__ void k_dig_closure_gate(DigGeom g, DigWork w, double tol) {
             d2 += d * d;
             s2 += (double)sc[k] * (double)sc[k];
         }
+        const int mc = ewma_m[c] < n_a ? ewma_m[c] : n_a;
+        const double ns = ewma[c] * (double)mc;
+        if (ns > 0) s2 += 14.5 / ns;
         const double e = sqrt(d2) / fmax(sqrt(s2), 1e-3);
         if (isfinite(e) && e <= tol) {
             const double* P = w.prim + kDigNV * (size_t)c;
@@ -1227,8 +1235,9 @@ void launch_dig_closure_prep(hipStream_t s, const DigGeom& g, DigWork w) {
     hipLaunchKernelGGL(k_dig_closure_prep, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w);
 }
 
-void launch_dig_closure_gate(hipStream_t s, const DigGeom& g, DigWork w, double tol) {
-    hipLaunchKernelGGL(k_dig_closure_gate, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w, tol);
+void launch_dig_closure_gate(hipStream_t s, const DigGeom& g, DigWork w, double tol, const double* ewma,
+                             const int32_t* ewma_m, int n_a) {
+    hipLaunchKernelGGL(k_dig_closure_gate, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w, tol, ewma, ewma_m, n_a);
 }
 
 void launch_fill_u8(hipStream_t s, uint8_t* p, uint8_t v, int64_t n) {

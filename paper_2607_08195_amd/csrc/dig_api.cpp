@@ -566,7 +566,7 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
     launch_dig_closure_prep(s, d->g, d->w);
     if (c->closure) {
         launch_mlp_forward(s, mlp_handle_view(c->closure), d->w.cx, nullptr, nt, d->w.cy);
-        launch_dig_closure_gate(s, d->g, d->w, c->gate_tol);
+        launch_dig_closure_gate(s, d->g, d->w, c->gate_tol, c->d_ewma, c->d_ewma_m, c->n_a);
     }
     launch_dig_gate(s, d->g, d->w, p->kn_max, p->passes);
     launch_dig_copy(s, d->w.prim, d->w.half, 5 * (int64_t)nt);

@@ -11,7 +11,11 @@ with the same run's long-average HoT:
   * learned: the network evaluated on the short window's gradients and Kn.
 The test requires the learned closure to be closer to the long average than
 the short-window sample (in the nondimensional units of the closure, rms
-over cells), and prints both errors.
+over cells), and prints both errors.  With the network attached to the
+coupling step, its noise-aware gate (the network is taken where it lies
+within three sampling-noise widths of the window's own HoT) selects the
+network in a sizeable fraction of the cells, and the HoT the coupling step
+then uses is closer to the long average than the window's sampled HoT.
 """
 import numpy as np
 import pytest
@@ -37,7 +41,7 @@ def _closure_pair(D, sim, sums):
     return sim.closure_data()
 
 
-def _run(D, Kn, lid, seed, warm, long_steps, short_steps=100, n_hex=8, ppc=20):
+def _run(D, Kn, lid, seed, warm, long_steps, short_steps=100, n_hex=8, ppc=20, keep=False):
     wl = W.cavity(n_hex=n_hex, Kn=Kn, ppc=ppc, lid_speed=lid, seed=seed, vel_fp32=1, ewma_on=1,
                   n_a=short_steps, n_ss=warm)
     sim = D.Simulation(wl)
@@ -49,6 +53,8 @@ def _run(D, Kn, lid, seed, warm, long_steps, short_steps=100, n_hex=8, ppc=20):
     acc, ns = sim.sums(D.SAMPLE_STEADY)
     x_s, t_s, v_s = _closure_pair(D, sim, ewma)
     x_l, t_l, v_l = _closure_pair(D, sim, acc / ns)
+    if keep:
+        return x_s, t_s, v_s & v_l, x_l, t_l, (sim, wl, ewma)
     sim.close()
     return x_s, t_s, v_s & v_l, x_l, t_l
 
@@ -67,7 +73,7 @@ def test_learned_closure_beats_short_window_samples(D):
     rep = net.train(x, t, steps=3000, batch=1024, lr=2e-3, seed=5)
     assert rep["loss_last"] < rep["loss_first"]
     # held-out run
-    x_s, t_s, v, x_l, t_l = _run(D, 0.08, 140.0, seed=99, warm=3000, long_steps=20000)
+    x_s, t_s, v, x_l, t_l, (sim, wl, ewma) = _run(D, 0.08, 140.0, seed=99, warm=3000, long_steps=20000, keep=True)
     y = net.forward(x_s[v])
     err_learned = np.sqrt(np.mean(((y - t_l[v]) / scale) ** 2))
     err_sampled = np.sqrt(np.mean(((t_s[v] - t_l[v]) / scale) ** 2))
@@ -75,4 +81,20 @@ def test_learned_closure_beats_short_window_samples(D):
           f"short-window sampled {err_sampled:.4f}, gain {err_sampled / err_learned:.2f}x; "
           f"train {x.shape[0]} cells, loss {rep['loss_first']:.3e} -> {rep['loss_last']:.3e}")
     assert err_learned < err_sampled
+    # the gated closure inside the coupling step, on the short window
+    from oracle import mlp_oracle as M
+    sim.set_sums(D.SAMPLE_EWMA, ewma)
+    sim.set_closure(net, gate_tol=3.0)
+    r = sim.dig_couple(kn_max=1e9, passes=0, n_m=0, feedback=0)
+    half = sim.dig_get("half")
+    R = 1.380649e-23 / wl.species.mass
+    t_g = M.closure_targets(sim.dig_get("hot"), half[:, 0], half[:, 4], R)
+    err_gated = np.sqrt(np.mean(((t_g[v] - t_l[v]) / scale) ** 2))
+    frac = r["n_closure"] / max(1, r["n_closure"] + r["n_fallback"])
+    print(f"gated closure: network in {r['n_closure']} of {r['n_closure'] + r['n_fallback']} cells "
+          f"({frac:.1%}), rms error {err_gated:.4f} against sampled {err_sampled:.4f}")
+    assert frac > 0.2
+    assert err_gated < err_sampled
+    sim.set_closure(None)
+    sim.close()
     net.close()

@@ -153,7 +153,9 @@ def test_closure_in_couple_matches_oracle(D):
     st = o.particles()
     g = D.Simulation(wl, fill=False, capacity=4 * o.np)
     g.set_state(st["x"], st["v"], st["cell"], st["pid"], o.step_index, o.next_pid, o.smax())
-    g.set_sums(D.SAMPLE_EWMA, o.sums(1))
+    g.set_sums(D.SAMPLE_EWMA, o.sums(1), o.ewma_counts())
+    n_s = o.sums(1)[:, 0] * np.minimum(o.ewma_counts(), wl.run.n_a)
+    assert n_s.min() > 0
     p = _params(21, scale=0.5)
     net = D.Mlp()
     net.set_weights(p)
@@ -169,7 +171,7 @@ def test_closure_in_couple_matches_oracle(D):
     t_o = M.closure_targets(hot, prim[:, 0], prim[:, 4], R)
     s_o = M.closure_targets(smp[:, 5:], prim[:, 0], prim[:, 4], R)
     y_o, _ = M.forward(p, x_o.astype(np.float32).astype(np.float64), bf16=True)
-    use_o, e_o = M.gate(y_o, t_o, s_o, tol=1e30)
+    use_o, e_o = M.gate(y_o, t_o, s_o, tol=1e30, n_samples=n_s)
     assert use_o.all()
     # every cell takes the network: HoT = network output in physical units
     g.set_closure(net, gate_tol=1e30)
@@ -188,9 +190,9 @@ def test_closure_in_couple_matches_oracle(D):
     assert np.all(np.abs(hg - hot_exp) <= 1e-2 * np.abs(hot_exp) + 2e-3 * scale)
     # a threshold in the middle of the distance distribution: decisions agree
     # wherever the oracle's margin exceeds the bf16 resolution
-    _, e_o = M.gate(y_o, t_o, s_o, tol=0.0)
+    _, e_o = M.gate(y_o, t_o, s_o, tol=0.0, n_samples=n_s)
     tol = float(np.median(e_o))
-    use_o, _ = M.gate(y_o, t_o, s_o, tol=tol)
+    use_o, _ = M.gate(y_o, t_o, s_o, tol=tol, n_samples=n_s)
     g.set_closure(net, gate_tol=tol)
     r = g.dig_couple(**kw)
     assert r["n_closure"] + r["n_fallback"] == o.nt

@@ -164,3 +164,32 @@ def test_closure_scaling_and_gate_by_hand():
     assert use.tolist() == [True, True] and e[1] == pytest.approx(0.5 / 3.0)
     use, _ = M.gate(np.array([[np.nan] * 9]), np.zeros((1, 9)), np.ones((1, 9)), tol=0.2)
     assert not use[0]
+    # the sampling noise widens the denominator: 14.5 / n added to |s|^2
+    use, e = M.gate(np.array([[1.0] + [0.0] * 8]), np.zeros((1, 9)), np.array([[0.3, 0.4] + [0.0] * 7]), tol=1.0,
+                    n_samples=np.array([14.5 / 0.75]))
+    assert e[0] == pytest.approx(1.0) and use[0]
+
+
+def test_gate_noise_constant_is_the_sampling_variance_of_a_maxwellian():
+    """The gate's noise model: the nondimensional stress and heat flux
+    (eq. dsmc_temperatures, over p and p sqrt(RT)) estimated from n
+    particles of a Maxwellian at rest have zero mean and E|.|^2 = 14.5 / n
+    to leading order (Gaussian moments: normal stresses 4/3, shear
+    stresses 1, heat fluxes 5/2 each)."""
+    from statutil import fields_from_sums
+    rng = np.random.default_rng(12)
+    n, reps = 400, 3000
+    m, kT = 6.63e-26, 1.380649e-23 * 273.0
+    cs = math.sqrt(kT / m)
+    tot = 0.0
+    for _ in range(reps):
+        v = rng.standard_normal((n, 3)) * cs
+        S = np.concatenate([[n], v.sum(0), (v * v).sum(0), [(v[:, 0] * v[:, 1]).sum(), (v[:, 0] * v[:, 2]).sum(),
+                            (v[:, 1] * v[:, 2]).sum()], (v * (v * v).sum(1, keepdims=True)).sum(0)])
+        f = fields_from_sums(S, m, 1.0, 1.0, 1)
+        p = f["n"] * 1.380649e-23 * f["T"]
+        sig = f["sig"][[0, 1, 2, 0, 0, 1], [0, 1, 2, 1, 2, 2]] / p
+        q = f["q"] / (p * math.sqrt(1.380649e-23 * f["T"] / m))
+        tot += (sig ** 2).sum() + (q ** 2).sum()
+    est = tot / reps * n
+    assert abs(est / M.NOISE_PER_PARTICLE - 1) < 0.05, est
