@@ -94,7 +94,9 @@ typedef struct {
  * The solution of a solve that did not fail becomes M^k, the state kept for
  * unreached cells and the warm start of the next cycle.  Sets the local
  * accumulation flags of rejected cells.  DSMC_E_CAPACITY if the clones of
- * the feedback would overflow the particle store (state left unchanged). */
+ * the feedback would overflow the particle store (state left unchanged);
+ * DSMC_E_INVALID for a gas with rotational degrees of freedom (the synthetic
+ * equations and their closure are the monatomic ones). */
 dsmc_status dig_couple(dsmc_ctx ctx, const dig_params* params, dig_report* report);
 
 /* Batch contexts (dsmc_batch_init): one call couples every enabled case at
@@ -135,7 +137,9 @@ dsmc_status dig_solve(dsmc_ctx ctx, double* prim, const double* hot, const dig_p
                       dig_report* report);
 
 /* Particle feedback alone: from prim_old[n][5] to prim_new[n][5] on cells
- * with state[n] <= 1; re-sorts.  DSMC_E_CAPACITY as for dig_couple. */
+ * with state[n] <= 1; re-sorts.  It changes the translational velocities
+ * only; a clone takes the rotational energy of the particle it copies.
+ * DSMC_E_CAPACITY as for dig_couple. */
 dsmc_status dig_feedback(dsmc_ctx ctx, const double* prim_old, const double* prim_new, const int32_t* state,
                          int64_t* np_after);
 

@@ -77,13 +77,30 @@ typedef struct {
  * relative velocity has cos(chi) = 2 R^(1/alpha) - 1 with R uniform and a
  * uniform azimuth (VSS, Bird 1994), and the viscosity the continuum side
  * uses is the VHS value times (alpha+1)(alpha+2)/(6 alpha).  alpha must be
- * positive (DSMC_E_INVALID otherwise). */
+ * positive (DSMC_E_INVALID otherwise).
+ * Rotation (section 2.1, eq. dsmc_particle_state): with dof_rot = 2 every
+ * particle carries a rotational energy I_r, drawn from the equilibrium
+ * distribution (exponential, mean k T) at the fill (T0), at diffuse walls
+ * (T of the wall) and at inflow faces (T of the freestream); after an
+ * accepted collision each partner in turn, with probability
+ * alpha (5 - 2 omega)(7 - 2 omega) / (5 (alpha + 1)(alpha + 2) z_rot)
+ * (eq. inelastic_probability), pools its I_r with the relative
+ * translational energy E_t = m c_r^2 / 4 and keeps the share
+ * E_t = E_c R^(1 / (5/2 - omega)) for translation (Borgnakke-Larsen for two
+ * rotational degrees of freedom), the relative velocity keeping its
+ * direction.  dof_rot = 0 (monatomic) leaves all of this out.  Other values,
+ * or z_rot <= 0 with dof_rot = 2, are DSMC_E_INVALID.  A rotating gas runs
+ * the parked-wall move schedules (4-7, 12-17), the LDS-ranked collide
+ * schedules (1-4) and the scatter or gather sort (0, 1); the coupling step
+ * (dig.h) and surface sampling do not take its rotation into account. */
 typedef struct {
     double mass;     /* kg */
     double d_ref;    /* reference diameter, m */
     double omega;    /* viscosity index */
     double T_ref;    /* reference temperature of d_ref, K */
     double alpha;    /* VSS scattering exponent; 1 = VHS */
+    int32_t dof_rot; /* rotational degrees of freedom: 0 or 2 */
+    double z_rot;    /* rotational collision number (dof_rot = 2) */
 } dsmc_species_desc;
 
 typedef enum {
@@ -163,6 +180,15 @@ dsmc_status dsmc_sample(dsmc_ctx ctx, int32_t which, double* out, int32_t out_on
  * INSTANT) into *n_samples.  Synchronises. */
 dsmc_status dsmc_get_sums(dsmc_ctx ctx, int32_t which, double* out, int64_t* n_samples);
 
+/* Rotational sums of a rotating gas: out[n_tets][4] = sum of I_r and of
+ * v_i I_r (i = x, y, z) of an accumulator (layout and sample count of
+ * dsmc_get_sums); dsmc_rot_sample gives the rotational temperature and heat
+ * flux of eq. (dsmc_temperatures) out[n_tets][4] = T_r = 2 <I_r> / (d_r k),
+ * q_r,i = (N_eff / V) sum (v_i - u_i) I_r per sampled step (NaN without
+ * samples).  Host arrays; synchronise; DSMC_E_INVALID for a monatomic gas. */
+dsmc_status dsmc_get_rot_sums(dsmc_ctx ctx, int32_t which, double* out, int64_t* n_samples);
+dsmc_status dsmc_rot_sample(dsmc_ctx ctx, int32_t which, double* out);
+
 /* Surface sampling (the wall pressure, shear stress and heat flux the
  * paper compares on the sphere, section 5): every interaction of a particle
  * with a diffuse or specular boundary face on a step after n_ss adds, for
@@ -186,9 +212,11 @@ dsmc_status dsmc_get_surface(dsmc_ctx ctx, double* sums, double* fields, int64_t
 
 /* Particle state.  dsmc_get_state fills n_particles, step and next_pid; the
  * arrays (host, may be NULL) receive the particles in (cell, pid) order:
- * x[n][3], v[n][3] (FP64), cell[n], pid[n], and smax[n_tets] the per-cell
+ * x[n][3], v[n][3] (FP64), cell[n], pid[n], ir[n] the rotational energies
+ * (J; untouched for a monatomic gas), and smax[n_tets] the per-cell
  * (sigma_T c_r)_max.  dsmc_set_state replaces the state (particles in any
- * order); smax may be NULL to keep the current values. */
+ * order, ir in the same order or NULL for zero rotational energy); smax may
+ * be NULL to keep the current values. */
 typedef struct {
     int64_t n_particles;
     double* x;
@@ -198,6 +226,7 @@ typedef struct {
     double* smax;
     uint32_t step;
     uint32_t next_pid;
+    double* ir;
 } dsmc_state;
 
 dsmc_status dsmc_get_state(dsmc_ctx ctx, dsmc_state* state);
@@ -281,7 +310,10 @@ dsmc_status dsmc_graph_step(dsmc_ctx ctx, int32_t n_steps);
  * 10/11 pooled, 15 (default) / 16 parked-wall at 6 / 8 waves/SIMD testing
  * only the three faces other than the entry face after the first test,
  * 12/13/14 as 15 and also parking particles still in flight after 4/5/6
- * exit tests;
+ * exit tests, 17 persistent: the work of 15 done by a fixed grid (as many
+ * workgroups as the device holds at once) pulling tiles of 256 particles
+ * from a device work queue dealt out in one contiguous slice per XCD
+ * (a workgroup drains its XCD's slice, then takes tiles from the others);
  * collide 0 LDS-staged
  * velocities, 1/2 LDS-ranked at 4/8 waves/SIMD (chunks up to 4096
  * particles in LDS), 3/4 LDS-ranked with chunks up to 3072/2048 particles
@@ -289,7 +321,7 @@ dsmc_status dsmc_graph_step(dsmc_ctx ctx, int32_t n_steps);
  * the collide kernel chunk by chunk (collide 1-4; with collide 0 it acts as
  * 1).  The autotuner's sort_ms includes the collide kernel.
  * Every schedule gives the same results.  A batch accepts only move 0-2
- * and 4-7, 12-16. */
+ * and 4-7, 12-17. */
 typedef struct {
     int32_t move, collide, sort;
     double move_ms, collide_ms, sort_ms;  /* per step, filled by dsmc_autotune */

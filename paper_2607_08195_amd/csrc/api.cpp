@@ -177,6 +177,13 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
         cp.orig = c->d_orig;
         cp.cell_case = c->d_cell_case;
         cp.cases = c->d_cases;
+        cp.rot = c->dr ? 1 : 0;
+        cp.pinel = c->pinel;
+        cp.ex_bl = 1.0 / (2.5 - c->omega);
+        cp.mass = c->mass;
+        cp.racc = c->d_racc;
+        cp.rewma = c->d_rewma;
+        cp.rinst = c->dr && c->inst_on ? c->d_rinst : nullptr;
         launch_collide_sample<VT>(s, a, c->d_offsets, cp, c->d_sc, c->d_perm, col ? 1 : 0, smp ? 1 : 0,
                                   c->collide_variant, fuse ? as_dev<VT>(c->B) : PartDev<VT>{}, c->d_sortperm);
     }
@@ -192,12 +199,26 @@ dsmc_status step_any(dsmc_ctx c, int mask) {
     return c->vel64 ? run_step<double>(c, mask) : run_step<float>(c, mask);
 }
 
+// Schedules that carry the rotational energy of a rotating gas: the
+// parked-wall move kernels (their main pass stops at diffuse walls, whose
+// re-emission, rotation included, the walls pass makes), the LDS-ranked
+// collide kernels and the scatter or gather sort.
+bool rot_schedule_ok(int move, int collide, int sort) {
+    const bool mv = move == kMoveDefer4 || move == kMoveDefer5 || move == kMoveDefer6 || move == kMoveDefer8 ||
+                    move == kMoveCap4 || move == kMoveCap5 || move == kMoveCap6 || move == kMoveFace3 ||
+                    move == kMoveFace3W8 || move == kMovePersist;
+    const bool co = collide == kCollideGlobal || collide == kCollideGlobal8 || collide == kCollideG3k ||
+                    collide == kCollideG2k;
+    const bool so = sort == kSortScatter || sort == kSortGather;
+    return mv && co && so;
+}
+
 // Move schedules that read the per-case tables of a batch (lane, parked-wall
 // and capped parked-wall kernels).
 bool move_reads_cases(int v) {
     return v == kMoveLane || v == kMoveLaneW6 || v == kMoveLaneW8 || v == kMoveDefer4 || v == kMoveDefer5 ||
            v == kMoveDefer6 || v == kMoveDefer8 || v == kMoveCap4 || v == kMoveCap5 || v == kMoveCap6 ||
-           v == kMoveFace3 || v == kMoveFace3W8;
+           v == kMoveFace3 || v == kMoveFace3W8 || v == kMovePersist;
 }
 
 // Tuning overrides from the environment: DSMC_MOVE (lane, lane6, lane8,
@@ -223,6 +244,7 @@ void read_tuning(dsmc_ctx c) {
         else if (s == "cap6") c->move_variant = kMoveCap6;
         else if (s == "face3") c->move_variant = kMoveFace3;
         else if (s == "face3w8") c->move_variant = kMoveFace3W8;
+        else if (s == "persist") c->move_variant = kMovePersist;
     }
     if (const char* v = std::getenv("DSMC_MOVE_BATCH"))
         c->move_batch = std::min(kQueueMaxBatch, std::max(64, std::atoi(v) / 64 * 64));
@@ -321,7 +343,7 @@ template <class VT>
 void fill_dispatch(dsmc_ctx c, double sig) {
     const int32_t* pid_base = c->d_cell_case ? c->d_counts_orig : c->d_cell_tmp;
     launch_init_fill<VT>(c->stream, c->d_tv, c->d_xyz, c->nt, c->d_offsets, c->d_orig, pid_base, as_dev<VT>(c->A),
-                         c->key, sig, c->u0, c->cap, c->d_sc, c->d_cell_case, c->d_cases);
+                         c->key, sig, c->u0, c->cap, c->d_sc, c->d_cell_case, c->d_cases, c->T0);
 }
 
 // Cases of a batch: per-case run parameters, the case of every cell of the
@@ -347,6 +369,8 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     if (!(sp->mass > 0) || !(sp->d_ref > 0) || !(sp->T_ref > 0) || !(sp->alpha > 0) || !(run->F_N > 0) ||
         !(run->dt > 0))
         return fail(nullptr, DSMC_E_INVALID, "non-positive physical parameter");
+    if (!(sp->dof_rot == 0 || sp->dof_rot == 2) || (sp->dof_rot == 2 && !(sp->z_rot > 0)))
+        return fail(nullptr, DSMC_E_INVALID, "rotational degrees of freedom must be 0 or 2 (with z_rot > 0)");
     if (run->n_a < 1) return fail(nullptr, DSMC_E_INVALID, "n_a must be >= 1");
     for (int g = 0; g < n_bc; ++g)
         if (bcs[g].kind < 0 || bcs[g].kind > 4) return fail(nullptr, DSMC_E_INVALID, "bad boundary kind");
@@ -385,6 +409,21 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
 
     c->mass = sp->mass; c->dref = sp->d_ref; c->omega = sp->omega; c->Tref = sp->T_ref;
     c->alpha = sp->alpha;
+    c->dr = sp->dof_rot;
+    c->zr = sp->z_rot;
+    {
+        const double a = sp->alpha, w = sp->omega;
+        c->pinel = c->dr ? ((a * (5.0 - 2.0 * w)) * (7.0 - 2.0 * w)) / ((((5.0 * (a + 1.0)) * (a + 2.0))) * c->zr)
+                         : 0.0;
+    }
+    if (c->dr) {
+        // the rotating gas runs the kernels that carry the rotational energy
+        if (!rot_schedule_ok(c->move_variant, c->collide_variant, c->sort_variant)) {
+            c->move_variant = kMoveFace3;
+            c->collide_variant = kCollideG3k;
+            c->sort_variant = kSortGather;
+        }
+    }
     const double mr = sp->mass / 2.0;
     c->K = ((M_PI * sp->d_ref) * sp->d_ref) * std::pow(((2.0 * kBoltzmann) * sp->T_ref) / mr, sp->omega - 0.5) /
            std::tgamma(2.5 - sp->omega);
@@ -440,6 +479,7 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
         for (int i = 0; i < 9; ++i) cst[6 + i] = fr[i];
         for (int v = 0; v < 3; ++v)
             for (int i = 0; i < 3; ++i) cst[15 + 3 * v + i] = hm.xyz[3 * (size_t)hm.bf_vtx[3 * (size_t)b + v] + i];
+        cst[24] = kBoltzmann * T;
         in_cst.insert(in_cst.end(), cst, cst + kInflowStride);
         in_bf.push_back(b);
         in_tc.push_back((hm.bf_tet[b] << 2) | hm.bf_lf[b]);
@@ -467,12 +507,16 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     double* d_in_cst = nullptr;
     ok = ok && alloc_n(c, d_in_bf, nin + 1) && alloc_n(c, d_in_tc, nin + 1) &&
          alloc_n(c, d_in_cst, (size_t)kInflowStride * nin + 1);
+    if (c->dr)
+        ok = ok && alloc_n(c, c->A.ir, c->cap) && alloc_n(c, c->B.ir, c->cap) &&
+             alloc_n(c, c->d_racc, (size_t)4 * nt) && alloc_n(c, c->d_rewma, (size_t)4 * nt) &&
+             alloc_n(c, c->d_rinst, (size_t)4 * nt);
     ok = ok && alloc_buf(c, c->A, c->cap, c->vel64) && alloc_buf(c, c->B, c->cap, c->vel64) &&
          alloc_n(c, c->d_rank, c->cap) && alloc_n(c, c->d_perm, c->cap) && alloc_n(c, c->d_sortperm, c->cap) &&
          alloc_n(c, c->wq.idx, kQueueParts * queue_part_size(c->cap)) &&
          alloc_n(c, c->wq.t, kQueueParts * queue_part_size(c->cap)) &&
          alloc_n(c, c->wq.meta, kQueueParts * queue_part_size(c->cap)) &&
-         alloc_n(c, c->wq.n, (size_t)kQueueParts * kQueueStride);
+         alloc_n(c, c->wq.n, (size_t)(kQueueParts + kTileSlices) * kQueueStride);
     c->wq.part = queue_part_size(c->cap);
     if (!ok) {
         dsmc_destroy(c);
@@ -492,6 +536,7 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
         d.pad = 0;
         d.beta = std::sqrt(((2.0 * kBoltzmann) * bcs[g].T) / sp->mass);
         d.sw = std::sqrt((kBoltzmann * bcs[g].T) / sp->mass);
+        d.kT = kBoltzmann * bcs[g].T;
         for (int i = 0; i < 3; ++i) {
             d.u[i] = bcs[g].u[i];
             d.shift[i] = bcs[g].shift[i];
@@ -533,6 +578,7 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     c->mesh.nb = nb;
     c->mesh.n_ss = run->n_ss;
     c->mesh.surf = nullptr;
+    c->mesh.rot = c->dr ? 1 : 0;
     c->inflow.n = nin;
     c->inflow.bface = d_in_bf;
     c->inflow.tcode = d_in_tc;
@@ -584,6 +630,11 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     launch_fill_i32(s, c->d_nacc, 0, nt);
     launch_fill_f64(s, c->d_acc, 0.0, (int64_t)kNMom * nt);
     launch_fill_f64(s, c->d_ewma, 0.0, (int64_t)kNMom * nt);
+    if (c->dr) {
+        launch_fill_f64(s, c->d_racc, 0.0, (int64_t)4 * nt);
+        launch_fill_f64(s, c->d_rewma, 0.0, (int64_t)4 * nt);
+        launch_fill_f64(s, c->d_rinst, 0.0, (int64_t)4 * nt);
+    }
     launch_fill_i32(s, c->d_ewma_m, 0, nt);
     HIP_TRY(c, hipMemsetAsync(c->d_local, 0, nt, s));
     launch_fill_i32(s, c->d_offsets, 0, nt + 1);
@@ -708,9 +759,12 @@ dsmc_status dsmc_get_tuning(dsmc_ctx c, dsmc_tuning* t) {
 dsmc_status dsmc_set_tuning(dsmc_ctx c, const dsmc_tuning* t) {
     if (!c || !t) return fail(c, DSMC_E_INVALID, "bad arguments");
     const bool batch_ok = move_reads_cases(t->move);
-    if (t->move < 0 || t->move > kMoveFace3W8 || t->collide < 0 || t->collide > kCollideG2k || t->sort < 0 ||
+    if (t->move < 0 || t->move > kMovePersist || t->collide < 0 || t->collide > kCollideG2k || t->sort < 0 ||
         t->sort > kSortFused || (c->n_cases && !batch_ok))
         return fail(c, DSMC_E_INVALID, "unknown or unsupported kernel variant");
+    if (c->dr && !rot_schedule_ok(t->move, t->collide, t->sort))
+        return fail(c, DSMC_E_INVALID, "a rotating gas needs a parked-wall move, LDS-ranked collide and scatter or "
+                                       "gather sort schedule");
     c->move_variant = t->move;
     c->collide_variant = t->collide;
     c->sort_variant = t->sort;
@@ -723,8 +777,9 @@ dsmc_status dsmc_autotune(dsmc_ctx c, int32_t trial_steps, dsmc_tuning* out) {
     const bool was_profiling = c->profiling;
     dsmc_tuning best{c->move_variant, c->collide_variant, c->sort_variant, 1e300, 1e300, 1e300};
     const int moves[] = {kMoveDefer4, kMoveDefer5, kMoveDefer6, kMoveDefer8, kMoveFace3, kMoveFace3W8, kMoveCap4,
-                         kMoveCap5, kMoveCap6, kMoveLaneW6, kMoveLaneW8};
+                         kMoveCap5, kMoveCap6, kMoveLaneW6, kMoveLaneW8, kMovePersist};
     for (int v : moves) {
+        if (c->dr && !rot_schedule_ok(v, c->collide_variant, c->sort_variant)) continue;
         c->move_variant = v;
         double ms = 0;
         dsmc_status st = time_slots(c, trial_steps, {kSlotMove, kSlotWalls}, &ms);
@@ -734,6 +789,7 @@ dsmc_status dsmc_autotune(dsmc_ctx c, int32_t trial_steps, dsmc_tuning* out) {
     c->move_variant = best.move;
     const int collides[] = {kCollideGlobal, kCollideGlobal8, kCollideG3k, kCollideG2k, kCollideLds};
     for (int v : collides) {
+        if (c->dr && !rot_schedule_ok(c->move_variant, v, c->sort_variant)) continue;
         c->collide_variant = v;
         double ms = 0;
         dsmc_status st = time_slots(c, trial_steps, {kSlotCollide}, &ms);
@@ -743,6 +799,7 @@ dsmc_status dsmc_autotune(dsmc_ctx c, int32_t trial_steps, dsmc_tuning* out) {
     c->collide_variant = best.collide;
     const int sorts[] = {kSortGather, kSortScatter, kSortFused};
     for (int v : sorts) {
+        if (c->dr && !rot_schedule_ok(c->move_variant, c->collide_variant, v)) continue;
         c->sort_variant = v;
         double ms = 0;
         // the fused form gathers inside the collide kernel: compare sort + collide
@@ -910,6 +967,56 @@ dsmc_status dsmc_get_sums(dsmc_ctx c, int32_t which, double* out, int64_t* n_sam
     return DSMC_OK;
 }
 
+dsmc_status dsmc_get_rot_sums(dsmc_ctx c, int32_t which, double* out, int64_t* n_samples) {
+    if (!c || !out || (which != DSMC_SAMPLE_STEADY && which != DSMC_SAMPLE_EWMA && which != DSMC_SAMPLE_INSTANT))
+        return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (!c->dr) return fail(c, DSMC_E_INVALID, "the gas has no rotational degrees of freedom");
+    const double* src = which == DSMC_SAMPLE_STEADY ? c->d_racc : which == DSMC_SAMPLE_EWMA ? c->d_rewma : c->d_rinst;
+    Scalars sc;
+    dsmc_status st = sync_scalars(c, &sc);
+    if (st != DSMC_OK) return st;
+    std::vector<double> h((size_t)4 * c->nt);
+    HIP_TRY(c, hipMemcpy(h.data(), src, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+    for (int t = 0; t < c->nt; ++t)
+        for (int k = 0; k < 4; ++k) out[(size_t)4 * c->hm.orig[t] + k] = h[(size_t)k * c->nt + t];
+    if (n_samples) *n_samples = which == DSMC_SAMPLE_INSTANT ? 1 : sc.n_steady;
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_rot_sample(dsmc_ctx c, int32_t which, double* out) {
+    if (!c || !out) return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (!c->dr) return fail(c, DSMC_E_INVALID, "the gas has no rotational degrees of freedom");
+    std::vector<double> S((size_t)kNMom * c->nt), R((size_t)4 * c->nt);
+    int64_t n_steady = 0;
+    dsmc_status st = dsmc_get_sums(c, which, S.data(), &n_steady);
+    if (st == DSMC_OK) st = dsmc_get_rot_sums(c, which, R.data(), nullptr);
+    if (st != DSMC_OK) return st;
+    const double ns = which == DSMC_SAMPLE_STEADY ? (double)n_steady : 1.0;
+    std::vector<int32_t> cs;
+    std::vector<double> fn(c->nt, c->FN);
+    if (c->d_cell_case) {
+        // per-case particle weights of a batch, in the caller's cell order
+        cs.resize(c->nt);
+        HIP_TRY(c, hipMemcpy(cs.data(), c->d_cell_case, sizeof(int32_t) * c->nt, hipMemcpyDeviceToHost));
+        std::vector<CaseDev> cases(c->n_cases);
+        HIP_TRY(c, hipMemcpy(cases.data(), c->d_cases, sizeof(CaseDev) * c->n_cases, hipMemcpyDeviceToHost));
+        for (int t = 0; t < c->nt; ++t) fn[c->hm.orig[t]] = cases[cs[t]].FN;
+    }
+    for (int o = 0; o < c->nt; ++o) {
+        const double* a = &S[(size_t)kNMom * o];
+        const double* r = &R[(size_t)4 * o];
+        double* q = out + 4 * (size_t)o;
+        if (!(a[0] > 0) || !(ns > 0)) {
+            for (int k = 0; k < 4; ++k) q[k] = std::nan("");
+            continue;
+        }
+        q[0] = (2.0 * (r[0] / a[0])) / ((double)c->dr * kBoltzmann);
+        const double f = fn[o] / (c->hm.vol[c->hm.inv[o]] * ns);
+        for (int i = 0; i < 3; ++i) q[1 + i] = f * (r[1 + i] - (a[1 + i] / a[0]) * r[0]);
+    }
+    return DSMC_OK;
+}
+
 dsmc_status dsmc_get_state(dsmc_ctx c, dsmc_state* st) {
     if (!c || !st) return fail(c, DSMC_E_INVALID, "bad arguments");
     Scalars sc;
@@ -924,11 +1031,13 @@ dsmc_status dsmc_get_state(dsmc_ctx c, dsmc_state* st) {
         HIP_TRY(c, hipMemcpy(sm.data(), c->d_smax, sizeof(double) * c->nt, hipMemcpyDeviceToHost));
         for (int t = 0; t < c->nt; ++t) st->smax[c->hm.orig[t]] = sm[t];
     }
-    if (!st->x && !st->v && !st->cell && !st->pid) return DSMC_OK;
-    std::vector<double> xs(3 * n), vs(3 * n);
+    double* ir_out = c->dr ? st->ir : nullptr;
+    if (!st->x && !st->v && !st->cell && !st->pid && !ir_out) return DSMC_OK;
+    std::vector<double> xs(3 * n), vs(3 * n), irs(ir_out ? n : 0);
     std::vector<int32_t> cell(n);
     std::vector<uint32_t> pid(n);
     HIP_TRY(c, hipMemcpy(xs.data(), c->A.pos, 24 * n, hipMemcpyDeviceToHost));
+    if (ir_out) HIP_TRY(c, hipMemcpy(irs.data(), c->A.ir, 8 * n, hipMemcpyDeviceToHost));
     if (c->vel64) {
         HIP_TRY(c, hipMemcpy(vs.data(), c->A.vel, 24 * n, hipMemcpyDeviceToHost));
     } else {
@@ -951,6 +1060,7 @@ dsmc_status dsmc_get_state(dsmc_ctx c, dsmc_state* st) {
         if (st->v) { st->v[3 * k] = vs[3 * i]; st->v[3 * k + 1] = vs[3 * i + 1]; st->v[3 * k + 2] = vs[3 * i + 2]; }
         if (st->cell) st->cell[k] = cell[i];
         if (st->pid) st->pid[k] = pid[i];
+        if (ir_out) ir_out[k] = irs[i];
     }
     return DSMC_OK;
 }
@@ -994,6 +1104,13 @@ dsmc_status dsmc_set_state(dsmc_ctx c, const dsmc_state* st) {
     }
     HIP_TRY(c, hipMemcpy(c->A.cell, cell.data(), 4 * n, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->A.pid, pid.data(), 4 * n, hipMemcpyHostToDevice));
+    if (c->dr) {
+        // rotational energies in the same order (zero when the caller gives none)
+        std::vector<double> irs(n, 0.0);
+        if (st->ir)
+            for (int64_t k = 0; k < n; ++k) irs[k] = st->ir[idx[k]];
+        HIP_TRY(c, hipMemcpy(c->A.ir, irs.data(), 8 * n, hipMemcpyHostToDevice));
+    }
     HIP_TRY(c, hipMemcpy(c->d_offsets, counts.data(), 4 * (c->nt + 1), hipMemcpyHostToDevice));
     if (st->smax) {
         std::vector<double> sm(c->nt);

@@ -18,11 +18,12 @@ struct Buf {
     void* vel = nullptr;    // [cap][3] float or double
     int32_t* cell = nullptr;
     uint32_t* pid = nullptr;
+    double* ir = nullptr;   // [cap] rotational energies, or null (monatomic gas)
 };
 
 template <class VT>
 PartDev<VT> as_dev(const Buf& b) {
-    return PartDev<VT>{b.pos, (VT*)b.vel, b.cell, b.pid};
+    return PartDev<VT>{b.pos, (VT*)b.vel, b.cell, b.pid, b.ir};
 }
 
 struct DigState;  // coupling state, owned by the context
@@ -43,6 +44,11 @@ struct dsmc_ctx_s {
     // species / run
     double mass = 0, dref = 0, omega = 0, Tref = 0, K = 0, ex = 0;
     double alpha = 1;   // VSS scattering exponent (1: VHS)
+    int dr = 0;         // rotational degrees of freedom (0 or 2)
+    double zr = 0, pinel = 0;  // rotational collision number, inelastic probability
+    double* d_racc = nullptr;   // [4][nt] rotational sums (steady), when dr > 0
+    double* d_rewma = nullptr;  // [4][nt] moving average of the rotational sums
+    double* d_rinst = nullptr;  // [4][nt] rotational sums of the last step
     double FN = 0, dt = 0, n0 = 0, T0 = 0, u0[3] = {0, 0, 0};
     dsmcx::RngKey key{0, 0};
     int vel64 = 0, n_ss = 0, n_a = 1000, ewma_on = 0;

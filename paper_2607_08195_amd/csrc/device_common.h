@@ -23,6 +23,8 @@ enum : uint32_t {
     kPurposeMlp = 8,
     kPurposeInitCount = 9,
     kPurposeInject = 10,
+    kPurposeInelasticI = 11,  // rotational exchange of the first partner of a pair (block = candidate)
+    kPurposeInelasticJ = 12,  // and of the second
 };
 
 enum : int { kBcDiffuse = 0, kBcSpecular = 1, kBcInflow = 2, kBcOutflow = 3, kBcPeriodic = 4 };
@@ -101,6 +103,7 @@ struct GroupDev {
     double sw;       // sqrt(k T / m)
     double u[3];
     double shift[3];
+    double kT;       // k T (mean rotational energy of two degrees of freedom)
 };
 
 // Slot of a particle in its cell's histogram bin.  Lanes of a wave that
@@ -156,6 +159,7 @@ struct MeshDev {
     int nb;                    // boundary faces
     int n_ss;                  // surface sums are taken on steps after n_ss
     double* surf;              // [5][nb] surface sums, or null (surface sampling off)
+    int rot;                   // 1: particles carry rotational energy (two degrees of freedom)
 };
 
 // Surface sampling at a wall interaction of boundary face bf that turned
@@ -198,7 +202,8 @@ struct TraceOut {
 template <class VT>
 __device__ __forceinline__ TraceOut trace(const MeshDev& m, double& x0, double& x1, double& x2,
                                           double& v0, double& v1, double& v2, int& cell, int entry,
-                                          uint32_t pid, uint32_t step, RngKey key, double t) {
+                                          uint32_t pid, uint32_t step, RngKey key, double t,
+                                          double* ir = nullptr) {
     TraceOut out{0, 0, 0};
     int c = cell;
     int nhop = 0;
@@ -258,6 +263,7 @@ __device__ __forceinline__ TraceOut trace(const MeshDev& m, double& x0, double& 
             v1 = round_store<VT>((vn * fr[1] + g.sw * (g1 * fr[4] + g2 * fr[7])) + g.u[1]);
             v2 = round_store<VT>((vn * fr[2] + g.sw * (g1 * fr[5] + g2 * fr[8])) + g.u[2]);
             surface_hit(m, bf, step, a0, a1, a2, v0, v1, v2);
+            if (ir) *ir = -g.kT * log(u01(r1.w[2], r1.w[3]));
             ++hits;
             ++out.walls;
             entry = fb;
@@ -295,6 +301,7 @@ struct Walker {
     double x0, x1, x2, v0, v1, v2, t;
     int c, entry, nhop, hits, walls;
     uint32_t pid;
+    double ir;   // rotational energy (read and written only when the gas rotates)
 };
 
 // One exit test of a walker (and the crossing or boundary interaction it
@@ -336,6 +343,8 @@ __device__ __forceinline__ void diffuse_reemit(const MeshDev& m, Walker& w, int 
     w.v1 = round_store<VT>((vn * fr[1] + g.sw * (g1 * fr[4] + g2 * fr[7])) + g.u[1]);
     w.v2 = round_store<VT>((vn * fr[2] + g.sw * (g1 * fr[5] + g2 * fr[8])) + g.u[2]);
     surface_hit(m, bf, step, a0, a1, a2, w.v0, w.v1, w.v2);
+    // the re-emitted molecule's rotation is in equilibrium at the wall
+    if (m.rot) w.ir = -g.kT * log(u01(r1.w[2], r1.w[3]));
     ++w.hits;
     ++w.walls;
     w.entry = fb;

@@ -867,6 +867,7 @@ __global__ __launch_bounds__(kFbLanes) void k_dig_fb_apply(DigGeom g, DigWork w,
             p.vel[3 * d + 2] = p.vel[3 * si + 2];
             p.cell[d] = c;
             p.pid[d] = pid0 + (uint32_t)k;
+            if (p.ir) p.ir[d] = p.ir[si];
         }
     }
 }

@@ -542,6 +542,7 @@ extern "C" {
 dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
     dsmc_status st = usable(c);
     if (st != DSMC_OK) return st;
+    if (c->dr) return fail(c, DSMC_E_INVALID, "the synthetic equations are those of a monatomic gas");
     if ((st = check_params(c, p)) != DSMC_OK) return st;
     DigState* d = c->dig;
     hipStream_t s = c->stream;

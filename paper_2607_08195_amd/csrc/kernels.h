@@ -16,14 +16,14 @@ constexpr int kMoveBatch = 512;        // particles per wave in the move kernel
 constexpr int kCollideLanes = 64;       // one wave, one lane per cell
 constexpr int kCollideCap = 2048;       // particles of one 64-cell chunk staged in LDS
 constexpr int kCollideCapG = 4096;      // particles of one chunk ranked in LDS (order-only variant)
-constexpr int kInflowStride = 24;       // doubles per inflow face
+constexpr int kInflowStride = 25;       // doubles per inflow face
 enum { kScanPlain = 0, kScanCells = 1, kScanInject = 2, kScanInit = 3 };
 enum { kFlagCapacity = 1 };
 // move kernel variants (tuning choice)
 enum { kMoveLane = 0, kMoveLaneW6 = 1, kMoveLaneW8 = 2, kMoveBatched = 3, kMoveDefer6 = 4, kMoveDefer8 = 5, kMoveDefer4 = 6,
        kMoveDefer5 = 7, kMoveRefill5 = 8, kMoveRefill6 = 9,
        kMovePool128 = 10, kMovePool256 = 11, kMoveCap4 = 12, kMoveCap5 = 13, kMoveCap6 = 14,
-       kMoveFace3 = 15, kMoveFace3W8 = 16 };
+       kMoveFace3 = 15, kMoveFace3W8 = 16, kMovePersist = 17 };
 enum { kCollideLds = 0, kCollideGlobal = 1, kCollideGlobal8 = 2, kCollideG3k = 3, kCollideG2k = 4 };
 // sort: scatter by rank; gather (k_perm then k_gather); fused (k_perm, then
 // the collide kernel gathers each chunk before colliding it; G-type collide
@@ -39,6 +39,7 @@ struct PartDev {
     VT* vel;          // [cap][3] velocities, interleaved likewise
     int32_t* cell;
     uint32_t* pid;
+    double* ir;       // [cap] rotational energies (J), or null for a monatomic gas
 };
 
 // Device-resident scalars of the step (read by kernels, never by the host
@@ -61,6 +62,9 @@ struct Scalars {
 constexpr int kQueueParts = 64;
 constexpr int kQueueStride = 32;     // counters kQueueStride x 8 bytes apart
 constexpr int kQueueMaxBatch = 4096; // largest particles-per-wave batch of any move kernel
+// The persistent move's tile counters follow the queue counters in the same
+// array, one per XCD slice, kQueueStride apart.
+constexpr int kTileSlices = 8;
 struct WallQueue {
     int32_t* idx;              // particle index
     double* t;                 // remaining time (negative: parked in flight)
@@ -79,8 +83,9 @@ struct Counters {
     unsigned long long hops, walls, injected, removed, lost;
 };
 
-// Inflow faces: consts[j][24] = mean count, speed ratio a, beta, sigma,
-// tangential mean (2), inward normal (3), t1 (3), t2 (3), vertices A,B,C (9).
+// Inflow faces: consts[j][25] = mean count, speed ratio a, beta, sigma,
+// tangential mean (2), inward normal (3), t1 (3), t2 (3), vertices A,B,C (9),
+// k T of the freestream.
 struct InflowDev {
     int n;
     const int32_t* bface;   // boundary face index (generator subject)
@@ -95,6 +100,13 @@ struct CollideParams {
     double FN, dt, K, ex;
     int vss;            // VSS scattering (alpha != 1); else isotropic VHS
     double inv_alpha;   // 1 / alpha
+    int rot;            // rotational energy exchange (Borgnakke-Larsen) and sums
+    double pinel;       // inelastic probability per partner (eq. inelastic_probability)
+    double ex_bl;       // 1 / (5/2 - omega): the translational share's exponent
+    double mass;        // molecular mass
+    double* racc;       // [4][nt] steady rotational sums (sum I_r, sum v_i I_r), or null
+    double* rewma;      // [4][nt] moving average of the rotational sums, or null
+    double* rinst;      // [4][nt] rotational sums of the step alone, or null
     const double* vol;
     double* smax;
     int32_t* ncand;
@@ -117,7 +129,8 @@ void launch_init_count(hipStream_t s, const double* vol, const int32_t* orig, in
 template <class VT>
 void launch_init_fill(hipStream_t s, const int4* tv, const double* xyz, int nt, const int32_t* offsets,
                       const int32_t* orig, const int32_t* pid_base, PartDev<VT> p, RngKey key, double sig,
-                      const double* u0, int64_t cap, Scalars* sc, const int32_t* cell_case, const CaseDev* cases);
+                      const double* u0, int64_t cap, Scalars* sc, const int32_t* cell_case, const CaseDev* cases,
+                      double T0);
 // batch: case-local particle ids (prefix minus the case's first prefix) and per-case (sigma c)_max
 void launch_batch_pid_base(hipStream_t s, const int32_t* prefix, const int32_t* case_first, const int32_t* case_of_orig,
                            int nt, int32_t* out);

@@ -51,14 +51,16 @@ __device__ __forceinline__ void block_counters(int a, int b, int c, int d, unsig
     }
 }
 
-// Wave-aggregated push of the lanes with `park` set into this workgroup's
-// part of the parked-particle queue (one atomic per wave).
-__device__ __forceinline__ void queue_push(const WallQueue& q, bool park, int64_t i, double t, int meta) {
+// Wave-aggregated push of the lanes with `park` set into a part of the
+// parked-particle queue (one atomic per wave); by default the part of this
+// workgroup.
+__device__ __forceinline__ void queue_push(const WallQueue& q, bool park, int64_t i, double t, int meta,
+                                           int part = -1) {
     const uint64_t pm = __ballot(park);
     if (!pm) return;
     const int lane = threadIdx.x & 63;
     const int leader = __ffsll((unsigned long long)pm) - 1;
-    const int part = (int)(blockIdx.x % kQueueParts);
+    if (part < 0) part = (int)(blockIdx.x % kQueueParts);
     int64_t base = 0;
     if (lane == leader)
         base = (int64_t)atomicAdd(q.n + (size_t)part * kQueueStride, (unsigned long long)__popcll(pm));
@@ -77,7 +79,7 @@ __device__ __forceinline__ void queue_push(const WallQueue& q, bool park, int64_
 __global__ void k_begin(int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss, unsigned long long* queue_n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i <= nt) counts[i] = 0;
-    if (i < kQueueParts) queue_n[i * kQueueStride] = 0ull;
+    if (i < kQueueParts + kTileSlices) queue_n[i * kQueueStride] = 0ull;
     if (i == 0) {
         const uint32_t s = sc->step + 1;
         sc->step = s;
@@ -114,13 +116,14 @@ template <class VT>
 __global__ void k_init_fill(const int4* tv, const double* xyz, int nt, const int32_t* offsets,
                             const int32_t* orig, const int32_t* pid_base, PartDev<VT> p, RngKey key, double sig,
                             double u0x, double u0y, double u0z, int64_t cap, Scalars* sc, const int32_t* cell_case,
-                            const CaseDev* cases) {
+                            const CaseDev* cases, double T0) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
     if (cell_case) {
         const CaseDev& cs = cases[cell_case[t]];
         key.k0 = cs.k0;
         key.k1 = cs.k1;
+        T0 = cs.T0;
         sig = cs.sig;
         u0x = cs.u0[0];
         u0y = cs.u0[1];
@@ -162,6 +165,11 @@ __global__ void k_init_fill(const int4* tv, const double* xyz, int nt, const int
         p.vel[3 * k + 2] = (VT)(u0z + sig * g3);
         p.cell[k] = t;
         p.pid[k] = id;
+        if (p.ir) {
+            // two rotational degrees of freedom: exponential with mean k T0
+            const Rand4 r = draw(key, id, 0u, kPurposeInit, 4);
+            p.ir[k] = -(kBoltzmannDev * T0) * log(u01(r.w[0], r.w[1]));
+        }
     }
 }
 
@@ -294,6 +302,89 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     {
         const uint32_t slot = bin_slot(counts, dest, dest >= 0);
         if (dest >= 0) rank[i] = slot;
+    }
+    block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
+}
+
+// Persistent move with a device work queue of tiles.  A fixed grid (a whole
+// number of workgroups per XCD, as many as the CUs hold at once) pulls
+// tiles of 256 consecutive particles.  The tiles are dealt out in
+// kTileSlices contiguous slices, one per XCD, each with its own counter on
+// its own line; a workgroup takes tiles from its XCD's slice and, once that
+// slice is empty, from the others in turn, so that each XCD's L2 keeps the
+// mesh neighbourhood of its slice while the last tiles balance the load.
+// Per particle the work is that of k_move_defer with FACE3; a tile's parked
+// particles go to the queue part of its tile index, as those of a
+// non-persistent workgroup of that index would.  The grid does not depend
+// on the particle count (the tile count is read from the device), so a
+// captured graph stays valid as the count changes.  Every workgroup leaves
+// once all slice counters have passed their slice's end.
+template <class VT, bool SURF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_move_persist(
+    MeshDev m, PartDev<VT> p, Scalars* sc, int32_t* counts, uint32_t* rank, Counters* ctr, RngKey key,
+    double dt, WallQueue q) {
+    __shared__ int64_t s_tile;
+    const int64_t n = sc->np;
+    const int64_t ntiles = (n + 255) / 256;
+    const uint32_t step = sc->step;
+    unsigned long long* tile_ctr = q.n + (size_t)kQueueParts * kQueueStride;
+    const int home = (int)(blockIdx.x % kTileSlices);
+    int hops = 0, walls = 0, rem = 0, lost = 0;
+    for (int k = 0; k < kTileSlices; ++k) {
+        const int sl = (home + k) % kTileSlices;
+        const int64_t lo = ntiles * sl / kTileSlices, hi = ntiles * (sl + 1) / kTileSlices;
+        for (;;) {
+            if (threadIdx.x == 0) {
+                const int64_t t = lo + (int64_t)atomicAdd(tile_ctr + (size_t)sl * kQueueStride, 1ull);
+                s_tile = t < hi ? t : -1;
+            }
+            __syncthreads();
+            const int64_t tile = s_tile;
+            __syncthreads();
+            if (tile < 0) break;
+            const int64_t i = tile * 256 + threadIdx.x;
+            int dest = -1;
+            bool park = false;
+            Walker w{};
+            if (i < n) {
+                w.x0 = p.pos[3 * i]; w.x1 = p.pos[3 * i + 1]; w.x2 = p.pos[3 * i + 2];
+                w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
+                w.c = p.cell[i]; w.pid = p.pid[i];
+                RngKey kp = key;
+                double dtp = dt;
+                case_params(m.cell_case, m.cases, w.c, kp, dtp);
+                w.t = dtp;
+                w.entry = -1; w.nhop = 0; w.hits = 0; w.walls = 0;
+                int st = hop_once<VT, true, false, SURF>(m, w, step, kp);
+                while (st < 0) st = hop_once<VT, true, true, SURF>(m, w, step, kp);
+                p.pos[3 * i] = w.x0; p.pos[3 * i + 1] = w.x1; p.pos[3 * i + 2] = w.x2;
+                if (st == kHopWallPending) {
+                    park = true;
+                    p.cell[i] = w.c;
+                    if (w.walls) {
+                        p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
+                    }
+                } else {
+                    hops += w.nhop;
+                    walls += w.walls;
+                    if (w.walls) {
+                        p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
+                    }
+                    if (st == 0) {
+                        p.cell[i] = w.c;
+                        dest = w.c;
+                    } else {
+                        p.cell[i] = -1;
+                        rem += st == 1;
+                        lost += st == 2;
+                    }
+                }
+            }
+            queue_push(q, park, i, w.t, (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22),
+                       (int)(tile % kQueueParts));
+            const uint32_t slot = bin_slot(counts, dest, dest >= 0);
+            if (dest >= 0) rank[i] = slot;
+        }
     }
     block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
 }
@@ -473,6 +564,7 @@ __device__ __forceinline__ int64_t queue_take(const MeshDev& m, const PartDev<VT
     w.x0 = p.pos[3 * i]; w.x1 = p.pos[3 * i + 1]; w.x2 = p.pos[3 * i + 2];
     w.c = p.cell[i]; w.pid = p.pid[i]; w.t = tq < 0 ? -tq : tq;
     w.entry = meta & 3; w.hits = (meta >> 2) & 1023; w.nhop = (meta >> 12) & 1023; w.walls = (meta >> 22) & 1023;
+    if (m.rot) w.ir = p.ir[i];
     kp = key;
     double dtp = 0.0;
     case_params(m.cell_case, m.cases, w.c, kp, dtp);
@@ -519,6 +611,7 @@ __global__ __launch_bounds__(256) void k_move_walls(MeshDev m, PartDev<VT> p, co
         walls += w.walls;
         p.pos[3 * i] = w.x0; p.pos[3 * i + 1] = w.x1; p.pos[3 * i + 2] = w.x2;
         p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
+        if (m.rot) p.ir[i] = w.ir;
         if (st == 0) {
             p.cell[i] = w.c;
             rank[i] = (uint32_t)atomicAdd(&counts[w.c], 1);
@@ -673,6 +766,8 @@ __global__ __launch_bounds__(256) void k_inject_emit(MeshDev m, const InflowDev 
         if (r1 + r2 > 1.0) { r1 = 1.0 - r1; r2 = 1.0 - r2; }
         r = draw(key, bf, step, kPurposeInject, kb | 1u);
         const double ut = u01(r.w[0], r.w[1]);
+        // freestream rotation in equilibrium at the freestream temperature
+        double irot = p.ir ? -cst[24] * log(u01(r.w[2], r.w[3])) : 0.0;
         r = draw(key, bf, step, kPurposeInject, kb | 2u);
         double g1, g2;
         box_muller(u01(r.w[0], r.w[1]), u01(r.w[2], r.w[3]), g1, g2);
@@ -696,7 +791,8 @@ __global__ __launch_bounds__(256) void k_inject_emit(MeshDev m, const InflowDev 
         const int code = in.tcode[j];
         int c = code >> 2;
         made = 1;
-        const TraceOut o = trace<VT>(m, x0, x1, x2, v0, v1, v2, c, code & 3, pid, step, key, ut * dt);
+        const TraceOut o = trace<VT>(m, x0, x1, x2, v0, v1, v2, c, code & 3, pid, step, key, ut * dt,
+                                     p.ir ? &irot : nullptr);
         hops = o.hops;
         walls = o.walls;
         const int64_t slot = sc->np + idx;
@@ -706,6 +802,7 @@ __global__ __launch_bounds__(256) void k_inject_emit(MeshDev m, const InflowDev 
             p.pos[3 * slot] = x0; p.pos[3 * slot + 1] = x1; p.pos[3 * slot + 2] = x2;
             p.vel[3 * slot] = (VT)v0; p.vel[3 * slot + 1] = (VT)v1; p.vel[3 * slot + 2] = (VT)v2;
             p.pid[slot] = pid;
+            if (p.ir) p.ir[slot] = irot;
             if (o.status == 0) {
                 p.cell[slot] = c;
                 rank[slot] = (uint32_t)atomicAdd(&counts[c], 1);
@@ -852,6 +949,7 @@ __device__ __forceinline__ void copy_particle(const PartDev<VT>& src, int64_t i,
     dst.vel[3 * d + 2] = v2;
     dst.cell[d] = cell;
     dst.pid[d] = id;
+    if (src.ir) dst.ir[d] = src.ir[i];
 }
 
 template <class VT>
@@ -897,6 +995,7 @@ __global__ __launch_bounds__(256) void k_gather(PartDev<VT> src, PartDev<VT> dst
     dst.vel[3 * k + 1] = v1;
     dst.vel[3 * k + 2] = v2;
     dst.pid[k] = id;
+    if (src.ir) dst.ir[k] = src.ir[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -925,6 +1024,7 @@ struct GlobalCell {
     VT* v;                 // interleaved velocities of the particle store
     const int32_t* perm;   // logical -> physical
     int64_t s0;
+    double* ir;            // rotational energies of the particle store (rotating gas)
     __device__ __forceinline__ void get(int k, double& a, double& b, double& c) const {
         const int64_t l = perm[s0 + k];
         a = (double)v[3 * l]; b = (double)v[3 * l + 1]; c = (double)v[3 * l + 2];
@@ -933,6 +1033,8 @@ struct GlobalCell {
         const int64_t l = perm[s0 + k];
         v[3 * l] = (VT)a; v[3 * l + 1] = (VT)b; v[3 * l + 2] = (VT)c;
     }
+    __device__ __forceinline__ double getI(int k) const { return ir[perm[s0 + k]]; }
+    __device__ __forceinline__ void putI(int k, double e) const { ir[perm[s0 + k]] = e; }
 };
 
 template <class VT>
@@ -949,6 +1051,9 @@ struct LdsOrderCell {
         const int64_t l = a + ord[s0 + k];
         v[3 * l] = (VT)x; v[3 * l + 1] = (VT)y; v[3 * l + 2] = (VT)z;
     }
+    double* ir;            // rotational energies of the particle store (rotating gas)
+    __device__ __forceinline__ double getI(int k) const { return ir[a + ord[s0 + k]]; }
+    __device__ __forceinline__ void putI(int k, double e) const { ir[a + ord[s0 + k]] = e; }
 };
 
 // Post-collision relative velocity g' (|g'| = |g| = c_r) from two uniform
@@ -992,7 +1097,7 @@ __device__ __forceinline__ void scatter_vhs_vss(const CollideParams& cp, double 
     o2 = cc * gz + scr * (se * e22 + ce * e12);
 }
 
-template <bool VSS, class Acc>
+template <bool VSS, bool ROT = false, class Acc>
 __device__ __forceinline__ void ntc_cell(const Acc& cv, int N, int c, const CollideParams& cp,
                                          uint32_t step, double* smax, int32_t* ncand, int32_t* nacc) {
     int M = 0, acc = 0;
@@ -1045,7 +1150,44 @@ __device__ __forceinline__ void ntc_cell(const Acc& cv, int N, int c, const Coll
             ++acc;
             const Rand4 q = draw(key, subj, step, kPurposeScatter, (uint64_t)k);
             double gp0, gp1, gp2;
-            scatter_vhs_vss<VSS>(cp, gx, gy, gz, cr2, u01(q.w[0], q.w[1]), u01(q.w[2], q.w[3]), gp0, gp1, gp2);
+            if constexpr (ROT) {
+                // Borgnakke-Larsen, partner by partner: with probability
+                // pinel the partner's rotational energy and the relative
+                // translational energy E_t = m c_r^2 / 4 are pooled and the
+                // translation keeps E_c R^(1/(5/2 - omega)) (two rotational
+                // degrees of freedom); the relative velocity keeps its
+                // direction and takes the new speed
+                const double R1 = u01(q.w[0], q.w[1]), R2 = u01(q.w[2], q.w[3]);
+                double Ii = cv.getI((int)i), Ij = cv.getI((int)j);
+                double Et = (0.25 * cp.mass) * cr2;
+                bool inel = false;
+                const Rand4 ri = draw(key, subj, step, kPurposeInelasticI, (uint64_t)k);
+                if (u01(ri.w[0], ri.w[1]) < cp.pinel) {
+                    const double Ec = Et + Ii;
+                    Et = Ec * pow(u01(ri.w[2], ri.w[3]), cp.ex_bl);
+                    Ii = Ec - Et;
+                    inel = true;
+                }
+                const Rand4 rj = draw(key, subj, step, kPurposeInelasticJ, (uint64_t)k);
+                if (u01(rj.w[0], rj.w[1]) < cp.pinel) {
+                    const double Ec = Et + Ij;
+                    Et = Ec * pow(u01(rj.w[2], rj.w[3]), cp.ex_bl);
+                    Ij = Ec - Et;
+                    inel = true;
+                }
+                if (inel) {
+                    cv.putI((int)i, Ii);
+                    cv.putI((int)j, Ij);
+                    const double cr2n = (4.0 * Et) / cp.mass;
+                    const double f = sqrt(cr2n / cr2);
+                    scatter_vhs_vss<VSS>(cp, gx * f, gy * f, gz * f, cr2n, R1, R2, gp0, gp1, gp2);
+                } else {
+                    scatter_vhs_vss<VSS>(cp, gx, gy, gz, cr2, R1, R2, gp0, gp1, gp2);
+                }
+            } else {
+                scatter_vhs_vss<VSS>(cp, gx, gy, gz, cr2, u01(q.w[0], q.w[1]), u01(q.w[2], q.w[3]), gp0, gp1,
+                                     gp2);
+            }
             const double cm0 = 0.5 * (a0 + b0), cm1 = 0.5 * (a1 + b1), cm2 = 0.5 * (a2 + b2);
             const double h0 = 0.5 * gp0, h1 = 0.5 * gp1, h2 = 0.5 * gp2;
             cv.put((int)i, cm0 + h0, cm1 + h1, cm2 + h2);
@@ -1057,7 +1199,7 @@ __device__ __forceinline__ void ntc_cell(const Acc& cv, int N, int c, const Coll
     nacc[c] = acc;
 }
 
-template <class Acc>
+template <bool ROT = false, class Acc>
 __device__ __forceinline__ void sample_cell(const Acc& cv, int N, int c, const CollideParams& cp,
                                             uint32_t step) {
     double S[kNMom];
@@ -1092,6 +1234,37 @@ __device__ __forceinline__ void sample_cell(const Acc& cv, int N, int c, const C
         for (int k = 0; k < kNMom; ++k) {
             double* e = cp.ewma + k * nt + c;
             *e = wo * *e + wn * S[k];
+        }
+    }
+    if constexpr (ROT) {
+        // rotational sums: sum I_r, sum v_i I_r (rotational temperature and
+        // heat flux of eq. dsmc_temperatures), in the same particle order
+        double Rr[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < N; ++k) {
+            double vx, vy, vz;
+            cv.get(k, vx, vy, vz);
+            const double I = cv.getI(k);
+            Rr[0] += I;
+            Rr[1] += vx * I; Rr[2] += vy * I; Rr[3] += vz * I;
+        }
+        if (cp.rinst) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cp.rinst[k * nt + c] = Rr[k];
+        }
+        if ((int64_t)step > (int64_t)cp.n_ss) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cp.racc[k * nt + c] += Rr[k];
+        }
+        if (cp.ewma_on) {
+            const int m = cp.ewma_m[c];
+            const int n = (cp.local_acc[c] || m < cp.n_a) ? m : cp.n_a;
+            const double wo = (double)(n - 1) / (double)n;
+            const double wn = 1.0 / (double)n;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double* e = cp.rewma + k * nt + c;
+                *e = wo * *e + wn * Rr[k];
+            }
         }
     }
 }
@@ -1163,7 +1336,7 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
             for (int q = 0; q < N; ++q) r += p.pid[s0 + q] < pk;
             perm[s0 + r] = (int32_t)(s0 + k);
         }
-        GlobalCell<VT> cv{p.vel, perm, s0};
+        GlobalCell<VT> cv{p.vel, perm, s0, nullptr};
         if (do_collide) ntc_cell<VSS>(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
         if (do_sample) sample_cell(cv, N, c, cp, step);
     }
@@ -1183,7 +1356,7 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
 // workgroup that then collides the chunk, so that gathering one chunk
 // overlaps the collisions of others and the velocities are read back from
 // cache.
-template <class VT, int WPE, int CAP, bool FUSED, bool VSS>
+template <class VT, int WPE, int CAP, bool FUSED, bool VSS, bool ROT = false>
 __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(WPE))) void k_collide_sample_g(
     PartDev<VT> p, const int32_t* offsets, CollideParams cp, const Scalars* sc, int32_t* perm, int do_collide,
     int do_sample, PartDev<VT> src, const int32_t* sortperm) {
@@ -1265,9 +1438,9 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
                     for (int q = 0; q < N; ++q) r += p.pid[s0 + q] < pk;
                     perm[s0 + r] = (int32_t)(s0 + k);
                 }
-                GlobalCell<VT> cv{p.vel, perm, s0};
-                if (do_collide) ntc_cell<VSS>(cv, N, cc, cp, step, cp.smax, cp.ncand, cp.nacc);
-                if (do_sample) sample_cell(cv, N, cc, cp, step);
+                GlobalCell<VT> cv{p.vel, perm, s0, p.ir};
+                if (do_collide) ntc_cell<VSS, ROT>(cv, N, cc, cp, step, cp.smax, cp.ncand, cp.nacc);
+                if (do_sample) sample_cell<ROT>(cv, N, cc, cp, step);
             }
             k0 = k0 + 1;
             continue;
@@ -1293,9 +1466,9 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
         if (lane >= k0 && lane < k1 && c < nt) {
             const int s0 = soff[lane] - w0;
             const int N = soff[lane + 1] - soff[lane];
-            LdsOrderCell<VT> cv{p.vel, sord, s0, a + w0};
-            if (do_collide) ntc_cell<VSS>(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
-            if (do_sample) sample_cell(cv, N, c, cp, step);
+            LdsOrderCell<VT> cv{p.vel, sord, s0, a + w0, p.ir};
+            if (do_collide) ntc_cell<VSS, ROT>(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
+            if (do_sample) sample_cell<ROT>(cv, N, c, cp, step);
         }
         k0 = k1;
     }
@@ -1386,7 +1559,7 @@ static inline unsigned grid8(int64_t n, int b) {
 
 void launch_begin(hipStream_t s, int32_t* counts, int nt, Scalars* sc, int do_sample, int n_ss,
                   unsigned long long* queue_n) {
-    hipLaunchKernelGGL(k_begin, GRID(std::max(nt + 1, kQueueParts), 256), dim3(256), 0, s, counts, nt, sc,
+    hipLaunchKernelGGL(k_begin, GRID(std::max(nt + 1, kQueueParts + kTileSlices), 256), dim3(256), 0, s, counts, nt, sc,
                        do_sample, n_ss, queue_n);
 }
 
@@ -1409,9 +1582,27 @@ void launch_batch_smax(hipStream_t s, const int32_t* cell_case, const CaseDev* c
 template <class VT>
 void launch_init_fill(hipStream_t s, const int4* tv, const double* xyz, int nt, const int32_t* offsets,
                       const int32_t* orig, const int32_t* pid_base, PartDev<VT> p, RngKey key, double sig,
-                      const double* u0, int64_t cap, Scalars* sc, const int32_t* cell_case, const CaseDev* cases) {
+                      const double* u0, int64_t cap, Scalars* sc, const int32_t* cell_case, const CaseDev* cases,
+                      double T0) {
     hipLaunchKernelGGL(k_init_fill<VT>, GRID(nt, 128), dim3(128), 0, s, tv, xyz, nt, offsets, orig, pid_base, p,
-                       key, sig, u0[0], u0[1], u0[2], cap, sc, cell_case, cases);
+                       key, sig, u0[0], u0[1], u0[2], cap, sc, cell_case, cases, T0);
+}
+
+// Workgroups of the persistent move: as many as the device holds at once
+// (its occupancy on every CU), rounded down to a multiple of kTileSlices.
+static int persist_grid() {
+    static int cached = 0;
+    if (cached) return cached;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_move_persist<float, false>, 256, 0) != hipSuccess ||
+        per_cu <= 0)
+        per_cu = 4;
+    const int g = cus * per_cu / kTileSlices * kTileSlices;
+    cached = g > 0 ? g : kTileSlices;
+    return cached;
 }
 
 template <class VT>
@@ -1464,6 +1655,16 @@ void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* 
         hipLaunchKernelGGL((k_move_defer<VT, 8, 0, true>), dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p,
                            (Scalars*)sc, counts, rank, ctr, key, dt, wq);
         break;
+    case kMovePersist: {
+        const dim3 g((unsigned)persist_grid());
+        if (m.surf)
+            hipLaunchKernelGGL((k_move_persist<VT, true>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
+                               key, dt, wq);
+        else
+            hipLaunchKernelGGL((k_move_persist<VT, false>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank,
+                               ctr, key, dt, wq);
+        break;
+    }
     case kMoveCap4:
     case kMoveCap5:
     case kMoveCap6: {
@@ -1517,7 +1718,8 @@ void launch_move_walls(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Sca
 bool move_parks_walls(int variant) {
     return variant == kMoveDefer4 || variant == kMoveDefer5 || variant == kMoveDefer6 || variant == kMoveDefer8 ||
            variant == kMoveCap4 || variant == kMoveCap5 || variant == kMoveCap6 || variant == kMoveFace3 || variant == kMoveFace3W8 ||
-           variant == kMovePool128 || variant == kMovePool256 || variant == kMoveRefill5 || variant == kMoveRefill6;
+           variant == kMovePool128 || variant == kMovePool256 || variant == kMoveRefill5 || variant == kMoveRefill6 ||
+           variant == kMovePersist;
 }
 
 void launch_count(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
@@ -1564,38 +1766,45 @@ void launch_gather(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalar
     hipLaunchKernelGGL(k_gather<VT>, dim3(grid8(bound, 256)), dim3(256), 0, s, src, dst, sc, perm);
 }
 
-template <class VT, int WPE, int CAP, bool VSS>
+template <class VT, int WPE, int CAP, bool VSS, bool ROT>
 static void launch_collide_g(hipStream_t s, int nchunk, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
                              const Scalars* sc, int32_t* perm, int do_collide, int do_sample, PartDev<VT> src,
                              const int32_t* sortperm) {
-    if (src.pos)
+    if constexpr (ROT) {
+        // a rotating gas never takes the fused gather (the host refuses that schedule)
+        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, false, VSS, true>), dim3(nchunk), dim3(kCollideLanes), 0,
+                           s, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
+    } else if (src.pos) {
         hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, true, VSS>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
                            offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
-    else
+    } else {
         hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, false, VSS>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
                            offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
+    }
 }
 
 bool collide_fuses_gather(int variant) {
     return variant == kCollideGlobal || variant == kCollideGlobal8 || variant == kCollideG3k || variant == kCollideG2k;
 }
 
-template <class VT, bool VSS>
+template <class VT, bool VSS, bool ROT>
 static void launch_collide_v(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
                              const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant,
                              PartDev<VT> src, const int32_t* sortperm) {
     const int nchunk = (cp.nt + kCollideLanes - 1) / kCollideLanes;
     if (variant == kCollideGlobal)
-        launch_collide_g<VT, 4, kCollideCapG, VSS>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src,
-                                                   sortperm);
+        launch_collide_g<VT, 4, kCollideCapG, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample,
+                                                        src, sortperm);
     else if (variant == kCollideGlobal8)
-        launch_collide_g<VT, 8, kCollideCapG, VSS>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src,
-                                                   sortperm);
+        launch_collide_g<VT, 8, kCollideCapG, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample,
+                                                        src, sortperm);
     else if (variant == kCollideG3k)
-        launch_collide_g<VT, 4, 3072, VSS>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
+        launch_collide_g<VT, 4, 3072, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src,
+                                                sortperm);
     else if (variant == kCollideG2k)
-        launch_collide_g<VT, 4, 2048, VSS>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
-    else
+        launch_collide_g<VT, 4, 2048, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src,
+                                                sortperm);
+    else if constexpr (!ROT)
         hipLaunchKernelGGL((k_collide_sample<VT, VSS>), dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc,
                            perm, do_collide, do_sample);
 }
@@ -1604,10 +1813,19 @@ template <class VT>
 void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
                            const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant,
                            PartDev<VT> src, const int32_t* sortperm) {
-    if (cp.vss)
-        launch_collide_v<VT, true>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, src, sortperm);
-    else
-        launch_collide_v<VT, false>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, src, sortperm);
+    if (cp.rot) {
+        if (cp.vss)
+            launch_collide_v<VT, true, true>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, src,
+                                             sortperm);
+        else
+            launch_collide_v<VT, false, true>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, src,
+                                              sortperm);
+    } else if (cp.vss) {
+        launch_collide_v<VT, true, false>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, src, sortperm);
+    } else {
+        launch_collide_v<VT, false, false>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, src,
+                                           sortperm);
+    }
 }
 
 void launch_fields(hipStream_t s, const double* sums, int nt, double ns, double mass, double FN,
@@ -1639,7 +1857,8 @@ void launch_fill_f64(hipStream_t s, double* p, double v, int64_t n) {
 #define INSTANTIATE(VT)                                                                                      \
     template void launch_init_fill<VT>(hipStream_t, const int4*, const double*, int, const int32_t*,       \
                                        const int32_t*, const int32_t*, PartDev<VT>, RngKey, double,         \
-                                       const double*, int64_t, Scalars*, const int32_t*, const CaseDev*);   \
+                                       const double*, int64_t, Scalars*, const int32_t*, const CaseDev*,    \
+                                       double);                                                             \
     template void launch_move<VT>(hipStream_t, const MeshDev&, PartDev<VT>, const Scalars*, int32_t*,       \
                                   uint32_t*, Counters*, RngKey, double, int64_t, int, int, WallQueue);      \
     template void launch_inject_emit<VT>(hipStream_t, const MeshDev&, const InflowDev&, PartDev<VT>,        \

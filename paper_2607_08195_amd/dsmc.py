@@ -34,7 +34,7 @@ class MeshDesc(C.Structure):
 
 class SpeciesDesc(C.Structure):
     _fields_ = [("mass", C.c_double), ("d_ref", C.c_double), ("omega", C.c_double), ("T_ref", C.c_double),
-                ("alpha", C.c_double)]
+                ("alpha", C.c_double), ("dof_rot", C.c_int32), ("z_rot", C.c_double)]
 
 
 class BoundaryDesc(C.Structure):
@@ -59,7 +59,7 @@ class RunDesc(C.Structure):
 
 class State(C.Structure):
     _fields_ = [("n_particles", C.c_int64), ("x", P), ("v", P), ("cell", P), ("pid", P), ("smax", P),
-                ("step", C.c_uint32), ("next_pid", C.c_uint32)]
+                ("step", C.c_uint32), ("next_pid", C.c_uint32), ("ir", P)]
 
 
 class Counters(C.Structure):
@@ -118,6 +118,8 @@ _lib.dsmc_step.argtypes = [ctx_t, C.c_int32]
 _lib.dsmc_step_stages.argtypes = [ctx_t, C.c_int32]
 _lib.dsmc_sample.argtypes = [ctx_t, C.c_int32, P, C.c_int32]
 _lib.dsmc_get_sums.argtypes = [ctx_t, C.c_int32, P, C.POINTER(C.c_int64)]
+_lib.dsmc_get_rot_sums.argtypes = [ctx_t, C.c_int32, P, C.POINTER(C.c_int64)]
+_lib.dsmc_rot_sample.argtypes = [ctx_t, C.c_int32, P]
 _lib.dsmc_get_state.argtypes = [ctx_t, C.POINTER(State)]
 _lib.dsmc_set_state.argtypes = [ctx_t, C.POINTER(State)]
 _lib.dsmc_get_pair_counts.argtypes = [ctx_t, P, P]
@@ -165,7 +167,8 @@ _lib.dig_batch_enable.argtypes = [ctx_t, P]
 _lib.dsmc_surface_sampling.argtypes = [ctx_t, C.c_int32]
 _lib.dsmc_instant_sampling.argtypes = [ctx_t, C.c_int32]
 _lib.dsmc_get_surface.argtypes = [ctx_t, P, P, C.POINTER(C.c_int64)]
-for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_state",
+for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_rot_sums",
+           "dsmc_rot_sample", "dsmc_get_state",
            "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
            "dsmc_profile", "dsmc_philox", "dsmc_device_copy", "dig_couple", "dig_get", "dig_residual",
            "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
@@ -175,7 +178,8 @@ for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_ge
            "dsmc_get_tuning", "dsmc_set_tuning", "dsmc_autotune"]:
     getattr(_lib, _f).restype = C.c_int32
 
-EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_state",
+EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_rot_sums",
+            "dsmc_rot_sample", "dsmc_get_state",
             "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
             "dsmc_profile", "dsmc_profile_read", "dsmc_profile_name", "dsmc_philox", "dsmc_device_copy",
             "dsmc_last_error", "dsmc_destroy", "dig_couple", "dig_get", "dig_residual", "dig_solve",
@@ -274,7 +278,9 @@ class Simulation:
         for i, b in enumerate(allb):
             bcs[i] = BoundaryDesc(b.kind, b.T, (C.c_double * 3)(*b.u), b.n, (C.c_double * 3)(*b.shift))
         sp = cases[0].species
-        sd = SpeciesDesc(sp.mass, sp.d_ref, sp.omega, sp.T_ref, sp.alpha)
+        sd = SpeciesDesc(sp.mass, sp.d_ref, sp.omega, sp.T_ref, sp.alpha, int(getattr(sp, "dof_rot", 0)),
+                         float(getattr(sp, "z_rot", 0.0)))
+        self.dof_rot = int(getattr(sp, "dof_rot", 0))
         self.ctx = ctx_t()
         if len(cases) == 1 and not isinstance(wl, (list, tuple)):
             _check(_lib.dsmc_init(C.byref(self.ctx), C.byref(meshes[0]), C.byref(sd), int(nbc[0]), bcs,
@@ -351,6 +357,19 @@ class Simulation:
         self._c(_lib.dsmc_get_sums(self.ctx, which, _p(out), C.byref(ns)))
         return out, int(ns.value)
 
+    def rot_sums(self, which=SAMPLE_STEADY):
+        """Rotational sums [n_tets][4] (sum I_r, sum v_i I_r) and the sample count."""
+        out = np.zeros((self.nt, 4))
+        ns = C.c_int64()
+        self._c(_lib.dsmc_get_rot_sums(self.ctx, which, _p(out), C.byref(ns)))
+        return out, int(ns.value)
+
+    def rot_fields(self, which=SAMPLE_STEADY):
+        """Rotational temperature and heat flux [n_tets][4] (T_r, q_r)."""
+        out = np.zeros((self.nt, 4))
+        self._c(_lib.dsmc_rot_sample(self.ctx, which, _p(out)))
+        return out
+
     def state(self, particles=True):
         st = State()
         smax = np.zeros(self.nt)
@@ -361,16 +380,20 @@ class Simulation:
         if particles:
             x = np.zeros((n, 3)); v = np.zeros((n, 3))
             c = np.zeros(n, np.int32); p = np.zeros(n, np.uint32)
-            st.x, st.v, st.cell, st.pid = _p(x), _p(v), _p(c), _p(p)
+            ir = np.zeros(n) if self.dof_rot else None
+            st.x, st.v, st.cell, st.pid, st.ir = _p(x), _p(v), _p(c), _p(p), _p(ir)
             self._c(_lib.dsmc_get_state(self.ctx, C.byref(st)))
             res.update(x=x, v=v, cell=c, pid=p)
+            if ir is not None:
+                res["ir"] = ir
         return res
 
-    def set_state(self, x, v, cell, pid, step, next_pid, smax=None):
+    def set_state(self, x, v, cell, pid, step, next_pid, smax=None, ir=None):
         x = np.ascontiguousarray(x, np.float64); v = np.ascontiguousarray(v, np.float64)
         cell = np.ascontiguousarray(cell, np.int32); pid = np.ascontiguousarray(pid, np.uint32)
         sm = np.ascontiguousarray(smax, np.float64) if smax is not None else None
-        st = State(len(cell), _p(x), _p(v), _p(cell), _p(pid), _p(sm), step, next_pid)
+        irs = np.ascontiguousarray(ir, np.float64) if ir is not None else None
+        st = State(len(cell), _p(x), _p(v), _p(cell), _p(pid), _p(sm), step, next_pid, _p(irs))
         self._c(_lib.dsmc_set_state(self.ctx, C.byref(st)))
 
     def instant_sampling(self, on=True):

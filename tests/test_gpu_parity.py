@@ -108,7 +108,7 @@ def test_single_step_parity(dsmc, name):
 # after 4-6 exit tests and 15/16 test three faces after the first crossing,
 # which these cases (several hops per step, diffuse, specular, periodic and
 # open faces) exercise
-MOVES = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16]
+MOVES = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17]
 MOVE_CASES = ["cavity_6_fp64_kn1", "specular_box", "plates_periodic_couette", "open_box_inflow", "sphere_hypersonic"]
 
 

@@ -1,0 +1,230 @@
+"""GPU path of a gas with two rotational degrees of freedom (section 2.1:
+eq. dsmc_particle_state, the Borgnakke-Larsen exchange at the probability of
+eq. inelastic_probability; rotational temperature and heat flux of
+eq. dsmc_temperatures) against the CPU oracle through the C ABI.
+
+The paper's nitrogen (m = 4.65e-26 kg, d = 4.17e-10 m, omega = 0.74,
+Z_r = 2.59; z_rot = 1 where more inelastic events are wanted) on the
+workloads of the monatomic parity tests: diffuse walls with a moving lid
+(wall re-emission draws I_r at the wall temperature), specular walls with
+VSS scattering, freestream inflow (injected molecules carry equilibrium
+I_r), periodic plates and dense chunks beyond the LDS stage.  From an
+identical state: bit-exact cell indices, (cell, pid) order and pair counts;
+positions within 1e-12 relative; velocities within 1 float32 ulp (FP32
+storage) or 1e-12 relative (FP64); rotational energies within 1e-12 of
+max(|I_r|, k T0); moment and rotational sums within 1e-12 relative;
+rotational fields within 1e-10 relative.  Every schedule that carries the
+rotational energy is run; the others are refused for a rotating gas.
+"""
+import numpy as np
+import pytest
+
+from paper_2607_08195_amd import workloads as W
+from oracle import Oracle
+from parity_util import compare_particles, compare_sums
+
+pytestmark = pytest.mark.gpu
+
+KB = 1.380649e-23
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_08195_amd import dsmc
+    return dsmc
+
+
+def _n2(wl, alpha=1.0, z_rot=2.59):
+    wl.species = W.Species(mass=4.65e-26, d_ref=4.17e-10, omega=0.74, T_ref=273.0, alpha=alpha, dof_rot=2,
+                           z_rot=z_rot)
+    wl.name += "_n2"
+    return wl
+
+
+CASES = {
+    "n2_cavity_fp64": (lambda: _n2(W.cavity(n_hex=6, Kn=0.5, ppc=20, vel_fp32=0)), 6),
+    "n2_cavity_fp32_jitter": (lambda: _n2(W.cavity(n_hex=7, Kn=0.1, ppc=25, jitter=0.1, vel_fp32=1), z_rot=1.0), 4),
+    "n2_vss_specular_fp32": (lambda: _n2(W.closed_box(n_hex=5, kind=W.BC_SPECULAR, Kn=0.1, ppc=15, vel_fp32=1),
+                                         alpha=1.4, z_rot=1.0), 3),
+    "n2_open_box_inflow": (lambda: _n2(W.open_box(n=(6, 4, 4), ppc=12, vel_fp32=1)), 6),
+    "n2_plates_periodic": (lambda: _n2(W.plates(n=(3, 6, 3), U=300.0, T1=250.0, T2=350.0, ppc=25, n0=3e19,
+                                                vel_fp32=0)), 4),
+    "n2_dense_ppc45": (lambda: _n2(W.cavity(n_hex=5, Kn=0.05, ppc=45, jitter=0.1, vel_fp32=1), z_rot=1.0), 1),
+}
+
+# schedules that carry the rotational energy
+ROT_MOVES = [4, 5, 6, 7, 12, 13, 14, 15, 16, 17]
+ROT_COLLIDES = [1, 2, 3, 4]
+ROT_SORTS = [0, 1]
+
+
+def _compare_ir(g, o, T0, ctx):
+    d = np.abs(g["ir"] - o["ir"])
+    lim = 1e-12 * np.maximum(np.abs(o["ir"]), KB * T0)
+    bad = d > lim
+    assert not bad.any(), f"{ctx}: {bad.sum()} rotational energies off, max {d.max():.3e}"
+
+
+def _compare_rot_fields(gf, of):
+    assert np.array_equal(np.isnan(gf), np.isnan(of))
+    scale = np.nanmax(np.abs(of), axis=0, keepdims=True)
+    assert np.all(np.nan_to_num(np.abs(gf - of)) <= 1e-10 * scale), "rotational fields"
+
+
+def _parity(D, wl, presteps, steps=2, move=None, collide=None, sort=None):
+    wl.run.n_ss = presteps
+    o = Oracle(wl)
+    o.step(presteps)
+    st = o.particles()
+    assert "ir" in st
+    g = D.Simulation(wl, fill=False, capacity=max(4 * o.np, 100000))
+    g.set_state(st["x"], st["v"], st["cell"], st["pid"], o.step_index, o.next_pid, o.smax(), ir=st["ir"])
+    t = g.tuning()
+    g.set_tuning(t["move"] if move is None else move, t["collide"] if collide is None else collide,
+                 t["sort"] if sort is None else sort)
+    for k in range(steps):
+        o.step(1)
+        g.step(1)
+        gs, os_ = g.state(), o.particles()
+        ctx = f"{wl.name} step {k + 1} move {move} collide {collide} sort {sort}"
+        compare_particles(gs, os_, wl.run.vel_fp32, ctx=ctx)
+        _compare_ir(gs, os_, wl.run.T0, ctx)
+        gc, ga = g.pair_counts()
+        oc, oa = o.pair_counts()
+        assert np.array_equal(gc, oc) and np.array_equal(ga, oa), f"{ctx}: pair counts"
+    gsum, ns = g.sums(D.SAMPLE_STEADY)
+    assert ns == o.n_steady == steps
+    compare_sums(gsum, o.sums(0))
+    grs, nrs = g.rot_sums(D.SAMPLE_STEADY)
+    assert nrs == steps
+    compare_sums(grs, o.rot_sums(0))
+    _compare_rot_fields(g.rot_fields(D.SAMPLE_STEADY), o.rot_fields(0))
+    g.close()
+    return o
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_rotation_parity(D, name):
+    make, pre = CASES[name]
+    o = _parity(D, make(), pre)
+    # the cases exercise the exchange: inelastic collisions change I_r
+    assert o.inelastic_probability > 0.2
+
+
+@pytest.mark.parametrize("case", ["n2_cavity_fp64", "n2_open_box_inflow", "n2_plates_periodic"])
+@pytest.mark.parametrize("move", ROT_MOVES)
+def test_rotation_move_schedules(D, move, case):
+    make, pre = CASES[case]
+    _parity(D, make(), pre, move=move)
+
+
+@pytest.mark.parametrize("case", ["n2_cavity_fp32_jitter", "n2_dense_ppc45", "n2_vss_specular_fp32"])
+@pytest.mark.parametrize("collide", ROT_COLLIDES)
+def test_rotation_collide_schedules(D, collide, case):
+    make, pre = CASES[case]
+    _parity(D, make(), pre, collide=collide)
+
+
+@pytest.mark.parametrize("case", ["n2_cavity_fp32_jitter", "n2_open_box_inflow"])
+@pytest.mark.parametrize("sort", ROT_SORTS)
+def test_rotation_sort_schedules(D, sort, case):
+    make, pre = CASES[case]
+    _parity(D, make(), pre, sort=sort)
+
+
+def test_rotation_fill_and_instant_sums(D):
+    """Initial fill (I_r from the equilibrium at T0 through one log call) and
+    the sums of single steps."""
+    wl = _n2(W.cavity(n_hex=6, Kn=0.5, ppc=20, vel_fp32=0))
+    o = Oracle(wl)
+    g = D.Simulation(wl)
+    gs, os_ = g.state(), o.particles()
+    compare_particles(gs, os_, 0, ctx="fill")
+    _compare_ir(gs, os_, wl.run.T0, "fill")
+    g.instant_sampling(True)
+    for _ in range(3):
+        g.step(1)
+        o.step(1)
+        gr, n = g.rot_sums(D.SAMPLE_INSTANT)
+        assert n == 1
+        compare_sums(gr, o.rot_sums(2))
+        _compare_rot_fields(g.rot_fields(D.SAMPLE_INSTANT), o.rot_fields(2))
+    g.close()
+
+
+def test_rotation_refuses_other_schedules_and_coupling(D):
+    wl = _n2(W.cavity(n_hex=4, Kn=0.5, ppc=10, vel_fp32=1))
+    g = D.Simulation(wl)
+    t = g.tuning()
+    assert t["move"] in ROT_MOVES and t["collide"] in ROT_COLLIDES and t["sort"] in ROT_SORTS
+    for move, collide, sort in [(0, t["collide"], t["sort"]), (t["move"], 0, t["sort"]),
+                                (t["move"], t["collide"], 2)]:
+        with pytest.raises(D.DsmcError):
+            g.set_tuning(move, collide, sort)
+    assert g.tuning() == t
+    with pytest.raises(D.DsmcError):
+        g.dig_couple()
+    # the autotuner tries rotation-carrying schedules only
+    best = g.autotune(1)
+    assert best["move"] in ROT_MOVES and best["collide"] in ROT_COLLIDES and best["sort"] in ROT_SORTS
+    g.close()
+    # a monatomic context has no rotational sums
+    a = D.Simulation(W.cavity(n_hex=3, Kn=0.5, ppc=5, vel_fp32=1))
+    with pytest.raises(D.DsmcError):
+        a.rot_sums()
+    a.close()
+
+
+def test_rotation_graph_step_equals_eager(D):
+    import torch
+    wl = _n2(W.open_box(n=(6, 4, 4), ppc=8, vel_fp32=1))
+    a = D.Simulation(wl, stream=torch.cuda.Stream(), capacity=60000)
+    b = D.Simulation(wl, stream=torch.cuda.Stream(), capacity=60000)
+    a.step(5)
+    b.graph_step(5)
+    sa, sb = a.state(), b.state()
+    assert sa["n"] == sb["n"]
+    for k in ["cell", "pid", "x", "v", "ir"]:
+        assert np.array_equal(sa[k], sb[k]), k
+    assert np.array_equal(a.rot_sums(D.SAMPLE_STEADY)[0], b.rot_sums(D.SAMPLE_STEADY)[0])
+    a.close()
+    b.close()
+
+
+def test_rotation_batch_matches_oracle(D):
+    specs = [(3, 0.05, 150.0), (5, 0.5, 30.0), (4, 0.1, 200.0)]
+    cases = []
+    for k, (n, Kn, lid) in enumerate(specs):
+        wl = _n2(W.cavity(n_hex=n, Kn=Kn, ppc=12, lid_speed=lid, seed=7, vel_fp32=1), z_rot=1.0)
+        wl.run.case_id = 20 + k
+        wl.run.n_ss = 0
+        cases.append(wl)
+    g = D.Simulation(cases)
+    begin = g.case_cells()
+    oracles = [Oracle(wl) for wl in cases]
+
+    def split(st, k):
+        m = (st["cell"] >= begin[k]) & (st["cell"] < begin[k + 1])
+        return dict(n=int(m.sum()), x=st["x"][m], v=st["v"][m], cell=st["cell"][m] - begin[k], pid=st["pid"][m],
+                    ir=st["ir"][m])
+
+    for step in range(4):
+        if step:
+            g.step(1)
+            for o in oracles:
+                o.step(1)
+        st = g.state()
+        for k, o in enumerate(oracles):
+            gk, ok = split(st, k), o.particles()
+            compare_particles(gk, ok, 1, ctx=f"case {k} step {step}")
+            _compare_ir(gk, ok, cases[k].run.T0, f"case {k} step {step}")
+    rs, ns = g.rot_sums(D.SAMPLE_STEADY)
+    rf = g.rot_fields(D.SAMPLE_STEADY)
+    for k, o in enumerate(oracles):
+        assert ns == o.n_steady == 3
+        compare_sums(rs[begin[k]:begin[k + 1]], o.rot_sums(0))
+        _compare_rot_fields(rf[begin[k]:begin[k + 1]], o.rot_fields(0))
+    g.close()
