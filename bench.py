@@ -180,6 +180,34 @@ def bench_ensemble(args, dsmc, W, window=50):
         timings[mode] = time.perf_counter() - t0
     n1 = sim.stats()["n_particles"]
     plain = 0.5 * (np0 + n1) * args.steps
+    # the persistent move (tiles pulled from an XCD-sliced device work queue)
+    # in the same graph-replayed batched step
+    sim.set_tuning(17, tune["collide"], tune["sort"])
+    sim.graph_step(args.warmup)
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.graph_step(args.steps)
+    sim.sync()
+    timings["graph_persistent"] = time.perf_counter() - t0
+    sim.set_tuning(tune["move"], tune["collide"], tune["sort"])
+    # the same cases one after another, each in a context of its own, with
+    # the same kernels and schedule (graph-replayed): the batched launch
+    # against sequential per-case launches
+    seq_t, seq_ps = 0.0, 0.0
+    for wl in cases:
+        one = dsmc.Simulation(wl, stream=stream)
+        one.set_tuning(tune["move"], tune["collide"], tune["sort"])
+        na = one.stats()["n_particles"]
+        one.graph_step(args.warmup)
+        one.sync()
+        a = time.perf_counter()
+        one.graph_step(args.steps)
+        one.sync()
+        seq_t += time.perf_counter() - a
+        seq_ps += 0.5 * (na + one.stats()["n_particles"]) * args.steps
+        one.close()
+    print(f"# ensemble: batched graph {1e3 * timings['graph'] / args.steps:.2f} ms/step, sequential per-case "
+          f"{1e3 * seq_t / args.steps:.2f} ms/step", file=sys.stderr, flush=True)
     # coupling on the odd cases with a closure trained on their cells
     on = np.arange(len(cases)) % 2 == 1
     sim.dig_enable(on.astype(np.int32))
@@ -233,6 +261,10 @@ def bench_ensemble(args, dsmc, W, window=50):
         "plain_eager_ms_per_step": 1e3 * timings["eager"] / args.steps,
         "plain_graph_ms_per_step": 1e3 * timings["graph"] / args.steps,
         "plain_value_graph": plain / timings["graph"],
+        "plain_graph_persistent_ms_per_step": 1e3 * timings["graph_persistent"] / args.steps,
+        "sequential_per_case": {"ms_per_step": 1e3 * seq_t / args.steps, "value": seq_ps / seq_t,
+                                "launches": "each case in a context of its own, graph-replayed, same schedule"},
+        "batched_over_sequential": (plain / timings["graph"]) / (seq_ps / seq_t),
         "closure_training": {"steps": 200, "batch": 4096, "seconds": round(train_s, 3),
                              "loss_first": train["loss_first"], "loss_last": train["loss_last"]},
         "last_report": rep,
@@ -373,124 +405,201 @@ def bench_dig(args, dsmc, W, window=50):
     print(json.dumps(out))
 
 
-def _bins(sim, wl, nb=5):
-    """Cell -> coarse bin (nb^3 boxes over the unit cube) and cell volumes."""
+def _ttf_geometry(wl, nb=10, nline=40):
+    """Bins of the time-to-fields comparison: cell -> one of nb^3 boxes over
+    the unit cube, cell volumes, and the cells of the two centreline slabs
+    (2h wide, h the hex spacing) with their index along the line: the
+    vertical line x = z = 1/2 (binned in y) and the horizontal line
+    y = z = 1/2 (binned in x)."""
     import numpy as np
     xyz, tets = wl.mesh.xyz, wl.mesh.tets
     cen = xyz[tets].mean(axis=1)
     a, b, c, d = (xyz[tets[:, k]] for k in range(4))
     vol = np.abs(np.einsum("ij,ij->i", b - a, np.cross(c - a, d - a))) / 6.0
     ijk = np.minimum((cen * nb).astype(int), nb - 1)
-    return ijk[:, 0] * nb * nb + ijk[:, 1] * nb + ijk[:, 2], vol, nb ** 3
+    h = 1.0 / wl.info["n_hex"]
+    near = lambda i, j: (np.abs(cen[:, i] - 0.5) < h) & (np.abs(cen[:, j] - 0.5) < h)
+    line = lambda ax: np.minimum((cen[:, ax] * nline).astype(int), nline - 1)
+    return dict(bin=ijk[:, 0] * nb * nb + ijk[:, 1] * nb + ijk[:, 2], nbins=nb ** 3, vol=vol, nline=nline,
+                vsel=near(0, 2), vidx=line(1), hsel=near(1, 2), hidx=line(0))
 
 
-def _binned_u(u, rho, bins, vol, nbins):
-    """Mass-weighted bin averages of the velocity field."""
+def _ttf_reduce(S, G):
+    """Cell moment sums [nt, 13] -> sums over the boxes and the line bins."""
     import numpy as np
-    w = np.where(np.isfinite(rho), rho, 0.0) * vol
-    out = np.zeros((nbins, 3))
-    for k in range(3):
-        out[:, k] = np.bincount(bins, weights=w * np.nan_to_num(u[:, k]), minlength=nbins) / np.maximum(
-            np.bincount(bins, weights=w, minlength=nbins), 1e-300)
+    box = np.stack([np.bincount(G["bin"], weights=S[:, k], minlength=G["nbins"]) for k in range(7)], axis=1)
+    lv = np.stack([np.bincount(G["vidx"][G["vsel"]], weights=S[G["vsel"], k], minlength=G["nline"])
+                   for k in range(4)], axis=1)
+    lh = np.stack([np.bincount(G["hidx"][G["hsel"]], weights=S[G["hsel"], k], minlength=G["nline"])
+                   for k in range(4)], axis=1)
+    return box, lv, lh
+
+
+def _ttf_fields(red, n, G, wl):
+    """Fields of binned sums over n steps (eq. dsmc_temperatures pooled over
+    each bin): density, velocity, temperature per box; u_x / U_lid along the
+    vertical line and u_y / U_lid along the horizontal line."""
+    import numpy as np
+    box, lv, lh = red
+    m, FN = wl.species.mass, wl.run.F_N
+    V = np.bincount(G["bin"], weights=G["vol"], minlength=G["nbins"])
+    S0 = np.maximum(box[:, 0], 1e-300)
+    u = box[:, 1:4] / S0[:, None]
+    T = m / (3 * KB_) * ((box[:, 4] + box[:, 5] + box[:, 6]) / S0 - (u * u).sum(axis=1))
+    rho = m * FN * box[:, 0] / n / np.maximum(V, 1e-300)
+    U = wl.info["lid_speed"]
+    return dict(u=u, rho=rho, T=T, vline=lv[:, 1] / np.maximum(lv[:, 0], 1e-300) / U,
+                hline=lh[:, 2] / np.maximum(lh[:, 0], 1e-300) / U)
+
+
+def _ttf_err(F, R):
+    import numpy as np
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    out = dict(u=rel(F["u"], R["u"]), rho=rel(F["rho"], R["rho"]), T=rel(F["T"], R["T"]),
+               vline=rel(F["vline"], R["vline"]), hline=rel(F["hline"], R["hline"]))
+    out["e"] = max(out["u"], out["rho"], out["T"])
     return out
 
 
-def bench_race(args, dsmc, W, window=50, check=2000):
-    """Wall time for plain DSMC and for DSMC with the DIG coupling (learned
-    closure on) to reach the velocity field of a long plain reference run
-    within 1% L2 (mass-weighted averages over a 5^3 grid of boxes).  Plain
-    fields at step t: the average of the steps t/2..t; DIG fields: the FV
-    solution of the latest coupling.  Timed: GPU work of each method only."""
+KB_ = 1.380649e-23
+
+
+def bench_time_to_fields(args, dsmc, W, window=50, block=500):
+    """Time to fields on the coupled-cavity configuration (384,000 jittered
+    tets, Kn = 0.01, 30 particles per cell, lid 50 m/s): wall seconds of GPU
+    work until a method's fields are within 1% of a long plain reference.
+
+    Reference: plain DSMC, `ttf_transient` steps, then `ttf_sampled` steps
+    averaged; its noise is the difference between its two sampled halves.
+    Fields: 10^3 boxes (density, velocity, temperature pooled per box) and
+    the two centreline velocity profiles (reported beside the error).
+    Error e = max of the relative L2 differences of velocity, density and
+    temperature over the boxes.  Each method adds its moment sums every
+    `block` steps; at step t its fields are those of the steps since the
+    block boundary nearest below t/2 (the last-half window), and its time to
+    fields is the first GPU time with e <= 1%.  Methods: plain DSMC; the
+    coupled method with the sampled HoT (one coupling cycle every `window`
+    steps, moving average over 1000 steps, 100 pseudo-time iterations
+    warm-started, the particles adjusted to M^{k+1} after the iterations as
+    in Algorithm 1); and the same with the learned closure, trained first on
+    three runs at Kn 0.02, 0.04 and 0.08 (Kn 0.01 held out)."""
     import numpy as np
     import torch
-    kn, nh = args.race_kn, args.race_hex
-    mk = lambda seed, **kw: W.cavity(n_hex=nh, Kn=kn, ppc=30, jitter=0.1, vel_fp32=1, seed=seed, n_ss=0,
-                                     lid_speed=args.race_lid, **kw)
+    nh, kn, lid = args.ttf_hex, args.ttf_kn, args.ttf_lid
+    mk = lambda seed, kn_=kn, **kw: W.cavity(n_hex=nh, Kn=kn_, ppc=30, jitter=0.1, vel_fp32=1, seed=seed, n_ss=0,
+                                             lid_speed=lid, **kw)
     wl = mk(0)
-    bins, vol, nbins = _bins(None, wl)
-    res = {"config": {"workload": f"cavity_{nh}^3x6_Kn{kn:g}", "ppc": 30, "lid": args.race_lid}}
-    # reference: long plain run, average over its second half
-    ref = dsmc.Simulation(mk(1))
-    half = args.race_ref_steps // 2
-    for done in range(0, half, 20000):
-        ref.step(min(20000, half - done))
+    G = _ttf_geometry(wl)
+    res = {"metric": "GPU seconds to fields within 1% L2 of a long plain reference",
+           "config": {"workload": f"cavity_{nh}^3x6_Kn{kn:g}_lid{lid:g}", "ppc": 30, "bins": "10^3 boxes",
+                      "block_steps": block, "coupling_window": window}}
+    log = lambda msg: print("# " + msg, file=sys.stderr, flush=True)
+
+    def stepper(sim, n):
+        sim.graph_step(n)
+
+    # reference
+    ref = dsmc.Simulation(mk(101), stream=torch.cuda.Stream())
+    t0 = time.perf_counter()
+    for done in range(0, args.ttf_transient, 10000):
+        stepper(ref, min(10000, args.ttf_transient - done))
         ref.sync()
-        print(f"# reference step {done + min(20000, half - done)}", file=sys.stderr, flush=True)
-    s0, n0 = ref.sums(dsmc.SAMPLE_STEADY)
-    for done in range(0, args.race_ref_steps - half, 20000):
-        ref.step(min(20000, args.race_ref_steps - half - done))
-        ref.sync()
-        print(f"# reference step {half + done + min(20000, args.race_ref_steps - half - done)}", file=sys.stderr,
-              flush=True)
-    s1, n1 = ref.sums(dsmc.SAMPLE_STEADY)
+        log(f"reference transient step {done + min(10000, args.ttf_transient - done)}")
+    s_a, n_a = ref.sums(dsmc.SAMPLE_STEADY)
+    half = args.ttf_sampled // 2
+    marks = []
+    for target in (half, args.ttf_sampled):
+        done = 0
+        while done < target - (0 if not marks else half):
+            k = min(10000, target - (0 if not marks else half) - done)
+            stepper(ref, k)
+            ref.sync()
+            done += k
+            log(f"reference sampled step {done + (half if marks else 0)}")
+        marks.append(ref.sums(dsmc.SAMPLE_STEADY))
+    ref_s = time.perf_counter() - t0
     ref.close()
+    (s_b, n_b), (s_c, n_c) = marks
+    R = _ttf_fields(_ttf_reduce(s_c - s_a, G), n_c - n_a, G, wl)
+    R1 = _ttf_fields(_ttf_reduce(s_b - s_a, G), n_b - n_a, G, wl)
+    R2 = _ttf_fields(_ttf_reduce(s_c - s_b, G), n_c - n_b, G, wl)
+    res["reference"] = {"transient_steps": args.ttf_transient, "sampled_steps": args.ttf_sampled,
+                        "seconds": round(ref_s, 1), "halves_difference": _ttf_err(R1, R2)}
+    log(f"reference halves differ by {res['reference']['halves_difference']}")
 
-    def fields_of(sums, n, wl_):
-        S = sums / n
-        rho = S[:, 0] * wl_.run.F_N / vol
-        u = S[:, 1:4] / np.maximum(S[:, :1], 1e-300)
-        return u, rho
+    def race(name, sim, cap, couple=None):
+        snaps = {0: tuple(np.zeros_like(a) for a in _ttf_reduce(np.zeros((sim.nt, 13)), G))}
+        t_gpu, step, hist, reached = 0.0, 0, [], None
+        reps = []
+        while step < cap:
+            a = time.perf_counter()
+            if couple is None:
+                stepper(sim, block)
+            else:
+                for _ in range(block // window):
+                    stepper(sim, window)
+                    reps.append(couple(sim))
+            sim.sync()
+            t_gpu += time.perf_counter() - a
+            step += block
+            S, n = sim.sums(dsmc.SAMPLE_STEADY)
+            snaps[step] = _ttf_reduce(S, G)
+            h = (step // 2) // block * block
+            F = _ttf_fields(tuple(x - y for x, y in zip(snaps[step], snaps[h])), step - h, G, wl)
+            err = _ttf_err(F, R)
+            hist.append((step, round(t_gpu, 3), {k: round(v, 5) for k, v in err.items()}))
+            if step % 5000 == 0 or err["e"] <= 0.01:
+                extra = "" if not reps else (f" couple iters {reps[-1]['iters']} resid {reps[-1]['residual']:.3g} "
+                                             f"closure {reps[-1]['n_closure']} np {reps[-1]['np_after']}")
+                log(f"{name} step {step} t {t_gpu:.2f} s e {err['e']:.4f} (u {err['u']:.4f}){extra}")
+            if err["e"] <= 0.01:
+                reached = {"step": step, "seconds": round(t_gpu, 2)}
+                break
+        out = {"reached": reached, "steps_run": step, "seconds_run": round(t_gpu, 2),
+               "final_error": hist[-1][2], "history": hist[::max(1, len(hist) // 40)]}
+        if reps:
+            out["couplings"] = len(reps)
+            out["last_coupling"] = {k: reps[-1][k] for k in ("iters", "residual", "converged", "fed_back",
+                                                             "n_rejected", "n_closure", "n_fallback")}
+            out["closure_cells_mean"] = float(np.mean([r["n_closure"] for r in reps]))
+        return out
 
-    u_ref, rho_ref = fields_of(s1 - s0, n1 - n0, wl)
-    U_ref = _binned_u(u_ref, rho_ref, bins, vol, nbins)
-    err = lambda U: float(np.linalg.norm(U - U_ref) / np.linalg.norm(U_ref))
-    res["reference_steps"] = args.race_ref_steps
     # plain
-    sim = dsmc.Simulation(mk(2))
-    snaps = {0: (np.zeros_like(s0), 0)}
-    t_gpu, step, plain_hist, plain_t = 0.0, 0, [], None
-    while step < args.race_ref_steps:
-        a = time.perf_counter()
-        sim.step(check)
-        sim.sync()
-        t_gpu += time.perf_counter() - a
-        step += check
-        snaps[step] = sim.sums(dsmc.SAMPLE_STEADY)
-        h = (step // 2) // check * check
-        sa, na = snaps[h]
-        sb, nb_ = snaps[step]
-        u, rho = fields_of(sb - sa, nb_ - na, wl)
-        e = err(_binned_u(u, rho, bins, vol, nbins))
-        plain_hist.append((step, round(t_gpu, 3), round(e, 5)))
-        print(f"# plain step {step} t {t_gpu:.2f} s err {e:.4f}", file=sys.stderr, flush=True)
-        if e <= 0.01 and plain_t is None:
-            plain_t = (step, t_gpu)
-            break
+    sim = dsmc.Simulation(mk(102), stream=torch.cuda.Stream())
+    res["plain"] = race("plain", sim, args.ttf_cap)
     sim.close()
-    res["plain"] = {"reached": plain_t, "history": plain_hist[-40:]}
-    # DIG with the learned closure (trained on this run's own early cells)
-    sim = dsmc.Simulation(mk(3, ewma_on=1, n_a=1000))
+    prm = dict(kn_max=1.0, passes=3, n_m=args.ttf_nm, eps_m=1e-6, cfl=0.5, feedback=1, warm_start=1,
+               unconverged=1)
+    res["coupling"] = prm
+    # coupled, sampled HoT
+    sim = dsmc.Simulation(mk(103, ewma_on=1, n_a=1000), stream=torch.cuda.Stream())
+    res["dig"] = race("dig", sim, args.ttf_dig_cap, couple=lambda s: s.dig_couple(**prm))
+    sim.close()
+    # learned closure: training pairs from three other Knudsen numbers
+    xs, ts = [], []
+    t0 = time.perf_counter()
+    for k, kn_t in enumerate((0.02, 0.04, 0.08)):
+        tr = dsmc.Simulation(mk(200 + k, kn_=kn_t, ewma_on=1, n_a=1000), stream=torch.cuda.Stream())
+        stepper(tr, args.ttf_train_steps)
+        tr.dig_couple(**dict(prm, n_m=0, feedback=0))
+        x, t, v = tr.closure_data()
+        xs.append(x[v]); ts.append(t[v])
+        tr.close()
+        log(f"closure training data from Kn {kn_t}: {int(v.sum())} cells")
     net = dsmc.Mlp()
     net.init_weights(seed=1)
-    prm = dict(kn_max=1.0, passes=3, n_m=200, eps_m=1e-6, cfl=0.8, feedback=1, warm_start=1)
-    t_gpu, step, dig_hist, dig_t = 0.0, 0, [], None
-    trained = False
-    while step < args.race_ref_steps:
-        a = time.perf_counter()
-        sim.step(window)
-        r = sim.dig_couple(**prm)
-        if not trained and step >= 10 * window:
-            x, t, v = sim.closure_data()
-            net.train(x[v], t[v], steps=300, batch=2048, lr=1e-3, seed=2)
-            sim.set_closure(net, gate_tol=0.5)
-            trained = True
-        torch.cuda.synchronize()
-        t_gpu += time.perf_counter() - a
-        step += window
-        if step % check == 0 or step == window:
-            new = sim.dig_get("new")
-            e = err(_binned_u(new[:, 1:4], new[:, 0], bins, vol, nbins))
-            dig_hist.append((step, round(t_gpu, 3), round(e, 5), r["iters"], round(r["residual"], 4),
-                             r["n_closure"]))
-            print(f"# dig step {step} t {t_gpu:.2f} s err {e:.4f} resid {r['residual']:.3g} "
-                  f"closure {r['n_closure']} np {r['np_after']}", file=sys.stderr, flush=True)
-            if e <= 0.01 and dig_t is None:
-                dig_t = (step, t_gpu)
-                break
-    net.close()
+    X, T = np.concatenate(xs), np.concatenate(ts)
+    tr_rep = net.train(X, T, steps=args.ttf_train_iters, batch=4096, lr=1e-3, seed=2)
+    torch.cuda.synchronize()
+    res["closure_training"] = {"samples": int(len(X)), "knudsen": [0.02, 0.04, 0.08],
+                               "steps_per_run": args.ttf_train_steps, "adam_steps": args.ttf_train_iters,
+                               "loss_first": tr_rep["loss_first"], "loss_last": tr_rep["loss_last"],
+                               "seconds": round(time.perf_counter() - t0, 1), "gate_tol": args.ttf_gate}
+    sim = dsmc.Simulation(mk(104, ewma_on=1, n_a=1000), stream=torch.cuda.Stream())
+    sim.set_closure(net, gate_tol=args.ttf_gate)
+    res["dig_mlp"] = race("dig+mlp", sim, args.ttf_dig_cap, couple=lambda s: s.dig_couple(**prm))
     sim.close()
-    res["dig"] = {"reached": dig_t, "history": dig_hist[-40:], "coupling": prm, "window": window}
-    res["metric"] = "wall seconds to 1% L2 of the reference velocity field"
+    net.close()
     print(json.dumps(res))
 
 
@@ -499,12 +608,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cavity_large", choices=["cavity_large", "cavity_small", "cavity_vss", "ensemble64", "dig_cavity40", "fields_race",
-                                                              "sphere"])
-    ap.add_argument("--race-hex", type=int, default=20)
-    ap.add_argument("--race-kn", type=float, default=0.01)
-    ap.add_argument("--race-ref-steps", type=int, default=200000)
-    ap.add_argument("--race-lid", type=float, default=200.0)
+    ap.add_argument("--workload", default="cavity_large",
+                    choices=["cavity_large", "cavity_small", "cavity_vss", "ensemble64", "dig_cavity40",
+                             "time_to_fields", "sphere"])
+    ap.add_argument("--ttf-hex", type=int, default=40)
+    ap.add_argument("--ttf-kn", type=float, default=0.01)
+    ap.add_argument("--ttf-lid", type=float, default=50.0)
+    ap.add_argument("--ttf-transient", type=int, default=50000)
+    ap.add_argument("--ttf-sampled", type=int, default=100000)
+    ap.add_argument("--ttf-cap", type=int, default=120000, help="plain DSMC steps at most")
+    ap.add_argument("--ttf-dig-cap", type=int, default=40000, help="coupled-method steps at most")
+    ap.add_argument("--ttf-nm", type=int, default=100)
+    ap.add_argument("--ttf-gate", type=float, default=0.5)
+    ap.add_argument("--ttf-train-steps", type=int, default=3000)
+    ap.add_argument("--ttf-train-iters", type=int, default=2000)
     ap.add_argument("--graph", action="store_true",
                     help="step through captured HIP graphs (the default for the cavity workloads)")
     ap.add_argument("--eager", action="store_true", help="step with ordinary launches instead of graphs")
@@ -542,8 +659,8 @@ def main():
         return bench_sphere(args, dsmc, W)
     if args.workload == "dig_cavity40":
         return bench_dig(args, dsmc, W)
-    if args.workload == "fields_race":
-        return bench_race(args, dsmc, W)
+    if args.workload == "time_to_fields":
+        return bench_time_to_fields(args, dsmc, W)
     wl = {"cavity_large": W.cavity_large, "cavity_vss": W.cavity_large_vss,
           "cavity_small": W.cavity_small}[args.workload]()
     sim = dsmc.Simulation(wl)
