@@ -526,6 +526,7 @@ def bench_time_to_fields(args, dsmc, W, window=50, block=500):
     res["reference"] = {"transient_steps": args.ttf_transient, "sampled_steps": args.ttf_sampled,
                         "seconds": round(ref_s, 1), "halves_difference": _ttf_err(R1, R2)}
     log(f"reference halves differ by {res['reference']['halves_difference']}")
+    log("reference result " + json.dumps(res["reference"]))
 
     def race(name, sim, cap, couple=None):
         snaps = {0: tuple(np.zeros_like(a) for a in _ttf_reduce(np.zeros((sim.nt, 13)), G))}
@@ -562,6 +563,7 @@ def bench_time_to_fields(args, dsmc, W, window=50, block=500):
             out["last_coupling"] = {k: reps[-1][k] for k in ("iters", "residual", "converged", "fed_back",
                                                              "n_rejected", "n_closure", "n_fallback")}
             out["closure_cells_mean"] = float(np.mean([r["n_closure"] for r in reps]))
+        log(f"{name} result " + json.dumps(out))
         return out
 
     # plain
