@@ -108,11 +108,130 @@ struct Timed {
     }
 };
 
+CollideParams collide_params(dsmc_ctx c) {
+    CollideParams cp;
+    cp.nt = c->nt; cp.n_ss = c->n_ss; cp.n_a = c->n_a; cp.ewma_on = c->ewma_on;
+    cp.key = c->key; cp.FN = c->FN; cp.dt = c->dt; cp.K = c->K; cp.ex = c->ex;
+    cp.vss = c->alpha != 1.0; cp.inv_alpha = 1.0 / c->alpha;
+    cp.vol = c->d_vol; cp.smax = c->d_smax; cp.ncand = c->d_ncand; cp.nacc = c->d_nacc;
+    cp.acc = c->d_acc; cp.ewma = c->d_ewma; cp.ewma_m = c->d_ewma_m; cp.local_acc = c->d_local;
+    cp.inst = c->inst_on ? c->d_inst : nullptr;
+    cp.orig = c->d_orig;
+    cp.cell_case = c->d_cell_case;
+    cp.cases = c->d_cases;
+    cp.rot = c->dr ? 1 : 0;
+    cp.pinel = c->pinel;
+    cp.ex_bl = 1.0 / (2.5 - c->omega);
+    cp.mass = c->mass;
+    cp.racc = c->d_racc;
+    cp.rewma = c->d_rewma;
+    cp.rinst = c->dr && c->inst_on ? c->d_rinst : nullptr;
+    return cp;
+}
+
+// The deferred sort needs the three-face move and an LDS-ranked collide.
+bool deferred_ok(int move, int collide) { return move == kMoveFace3 && collide_fuses_gather(collide); }
+
+}  // namespace
+
+namespace dsmcx {
+
+// Writes the pending sorted order of a deferred sort out to B and swaps, so
+// that A is sorted by cell again (for calls that read or rebuild the store).
+dsmc_status materialize(dsmc_ctx c) {
+    if (!c->pending) return DSMC_OK;
+    if (c->vel64)
+        launch_gather<double>(c->stream, as_dev<double>(c->A), as_dev<double>(c->B), c->d_sc, c->d_sortperm,
+                              c->np_bound);
+    else
+        launch_gather<float>(c->stream, as_dev<float>(c->A), as_dev<float>(c->B), c->d_sc, c->d_sortperm,
+                             c->np_bound);
+    std::swap(c->A, c->B);
+    c->pending = false;
+    HIP_TRY(c, hipGetLastError());
+    return DSMC_OK;
+}
+
+}  // namespace dsmcx
+
+namespace {
+
+// Gives a sorted store the identity order, so that a deferred step can
+// start from it.
+void ensure_pending(dsmc_ctx c) {
+    if (c->pending) return;
+    launch_perm_identity(c->stream, c->A.cell, c->d_sc, c->d_sortperm, c->B.cell, c->np_bound);
+    c->pending = true;
+}
+
+// One step with the deferred sort: the move reads the particles in the
+// previous step's sorted order and writes them in it (k_move_defer's gather
+// form, into B, which then becomes A); the sort only computes the new order;
+// the collide kernel reaches the particles through it.
+template <class VT>
+dsmc_status run_step_deferred(dsmc_ctx c, bool inj, bool col, bool smp, int64_t need) {
+    hipStream_t s = c->stream;
+    if (!c->capturing) ensure_pending(c);
+    PartDev<VT> a = as_dev<VT>(c->A), b = as_dev<VT>(c->B);
+    {
+        Timed t(c, kSlotBegin);
+        launch_begin(s, c->d_counts, c->nt, c->d_sc, smp ? 1 : 0, c->n_ss, c->wq.n);
+    }
+    {
+        Timed t(c, kSlotMove);
+        launch_move<VT>(s, c->mesh, b, c->d_sc, c->d_counts, c->d_rank, c->d_ctr, c->key, c->dt,
+                        c->capturing ? c->capture_bound : c->np_bound, c->move_variant, c->move_batch, c->wq, a,
+                        c->d_sortperm);
+    }
+    std::swap(c->A, c->B);
+    std::swap(a, b);
+    {
+        Timed t(c, kSlotWalls);
+        launch_move_walls<VT>(s, c->mesh, a, c->d_sc, c->d_counts, c->d_rank, c->d_ctr, c->key, c->wq);
+    }
+    if (inj) {
+        Timed t(c, kSlotInject);
+        launch_inject_count(s, c->inflow, c->d_sc, c->key, c->d_fcount);
+        launch_scan(s, c->d_fcount, c->inflow.n, c->d_foff, c->d_blocksums, c->d_sc, kScanInject);
+        launch_inject_emit<VT>(s, c->mesh, c->inflow, a, c->d_sc, c->d_foff, c->d_counts, c->d_rank, c->d_ctr,
+                               c->key, c->dt, c->cap, c->max_inject);
+    }
+    {
+        Timed t(c, kSlotScan);
+        launch_scan(s, c->d_counts, c->nt, c->d_offsets, c->d_blocksums, c->d_sc, kScanCells);
+    }
+    {
+        Timed t(c, kSlotScatter);
+        launch_scatter<VT>(s, a, b, c->d_sc, c->d_offsets, c->d_rank, need, c->cap, c->d_sortperm, kSortDeferred);
+    }
+    c->np_bound = need;
+    {
+        Timed t(c, kSlotCollide);
+        const CollideParams cp = collide_params(c);
+        launch_collide_sample<VT>(s, a, c->d_offsets, cp, c->d_sc, c->d_perm, col ? 1 : 0, smp ? 1 : 0,
+                                  c->collide_variant, kGatherIndirect, b, c->d_sortperm);
+    }
+    c->pending = true;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        c->broken = true;
+        return fail(c, DSMC_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    return DSMC_OK;
+}
+
 template <class VT>
 dsmc_status run_step(dsmc_ctx c, int mask) {
     const bool mv = mask & 1, inj = (mask & 2) && c->inflow.n > 0, srt = mask & 4, col = mask & 8,
                smp = mask & 16;
     if ((col || smp) && mv && !srt) return fail(c, DSMC_E_INVALID, "collide/sample after move needs sort");
+    const bool defer = c->sort_variant == kSortDeferred && deferred_ok(c->move_variant, c->collide_variant) && mv &&
+                       srt && (col || smp);
+    if (!defer && c->pending) {
+        // a partial step works on the sorted store
+        dsmc_status st = materialize(c);
+        if (st != DSMC_OK) return st;
+    }
     // Under graph capture nothing may synchronise: grids cover the capture
     // bound and the kernels bound themselves by the device-side counts.
     const int64_t need = c->capturing ? c->capture_bound : c->np_bound + (inj ? c->max_inject : 0);
@@ -122,6 +241,7 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
         if (c->np_bound + (inj ? c->max_inject : 0) > c->cap)
             return fail(c, DSMC_E_CAPACITY, "particle store capacity would be exceeded");
     }
+    if (defer) return run_step_deferred<VT>(c, inj, col, smp, need);
     hipStream_t s = c->stream;
     PartDev<VT> a = as_dev<VT>(c->A), b = as_dev<VT>(c->B);
     bool fuse = false;  // the collide kernel gathers the sorted buffer
@@ -157,7 +277,7 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
             launch_scatter<VT>(s, a, b, c->d_sc, c->d_offsets, c->d_rank, need, c->cap, c->d_sortperm, c->sort_variant);
         }
         fuse = c->sort_variant == kSortFused && (col || smp) && collide_fuses_gather(c->collide_variant);
-        if (c->sort_variant == kSortGather || (c->sort_variant == kSortFused && !fuse)) {
+        if (c->sort_variant != kSortScatter && !fuse) {
             Timed t(c, kSlotGather);
             launch_gather<VT>(s, a, b, c->d_sc, c->d_sortperm, need);
         }
@@ -167,25 +287,10 @@ dsmc_status run_step(dsmc_ctx c, int mask) {
     }
     if (col || smp) {
         Timed t(c, kSlotCollide);
-        CollideParams cp;
-        cp.nt = c->nt; cp.n_ss = c->n_ss; cp.n_a = c->n_a; cp.ewma_on = c->ewma_on;
-        cp.key = c->key; cp.FN = c->FN; cp.dt = c->dt; cp.K = c->K; cp.ex = c->ex;
-        cp.vss = c->alpha != 1.0; cp.inv_alpha = 1.0 / c->alpha;
-        cp.vol = c->d_vol; cp.smax = c->d_smax; cp.ncand = c->d_ncand; cp.nacc = c->d_nacc;
-        cp.acc = c->d_acc; cp.ewma = c->d_ewma; cp.ewma_m = c->d_ewma_m; cp.local_acc = c->d_local;
-        cp.inst = c->inst_on ? c->d_inst : nullptr;
-        cp.orig = c->d_orig;
-        cp.cell_case = c->d_cell_case;
-        cp.cases = c->d_cases;
-        cp.rot = c->dr ? 1 : 0;
-        cp.pinel = c->pinel;
-        cp.ex_bl = 1.0 / (2.5 - c->omega);
-        cp.mass = c->mass;
-        cp.racc = c->d_racc;
-        cp.rewma = c->d_rewma;
-        cp.rinst = c->dr && c->inst_on ? c->d_rinst : nullptr;
+        const CollideParams cp = collide_params(c);
         launch_collide_sample<VT>(s, a, c->d_offsets, cp, c->d_sc, c->d_perm, col ? 1 : 0, smp ? 1 : 0,
-                                  c->collide_variant, fuse ? as_dev<VT>(c->B) : PartDev<VT>{}, c->d_sortperm);
+                                  c->collide_variant, fuse ? kGatherFused : kGatherNone,
+                                  fuse ? as_dev<VT>(c->B) : PartDev<VT>{}, c->d_sortperm);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -209,7 +314,7 @@ bool rot_schedule_ok(int move, int collide, int sort) {
                     move == kMoveFace3W8 || move == kMovePersist;
     const bool co = collide == kCollideGlobal || collide == kCollideGlobal8 || collide == kCollideG3k ||
                     collide == kCollideG2k;
-    const bool so = sort == kSortScatter || sort == kSortGather;
+    const bool so = sort == kSortScatter || sort == kSortGather || (sort == kSortDeferred && deferred_ok(move, collide));
     return mv && co && so;
 }
 
@@ -251,7 +356,10 @@ void read_tuning(dsmc_ctx c) {
     if (const char* v = std::getenv("DSMC_REORDER")) c->reorder = std::atoi(v);
     if (const char* v = std::getenv("DSMC_SORT")) {
         const std::string k(v);
-        c->sort_variant = k == "scatter" ? kSortScatter : k == "fused" ? kSortFused : kSortGather;
+        c->sort_variant = k == "scatter"  ? kSortScatter
+                          : k == "fused"    ? kSortFused
+                          : k == "deferred" ? kSortDeferred
+                                            : kSortGather;
     }
     if (const char* v = std::getenv("DSMC_COLLIDE")) {
         std::string s(v);
@@ -291,6 +399,7 @@ dsmc_status capture_two_steps(dsmc_ctx c, dsmc_ctx_s::Graph& g) {
         if (st != DSMC_OK) return st;
         c->capture_bound = std::max<int64_t>(c->np_bound, 1);
     }
+    if (c->sort_variant == kSortDeferred && deferred_ok(c->move_variant, c->collide_variant)) ensure_pending(c);
     const void* a_x = c->A.pos;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     c->capturing = true;
@@ -728,6 +837,10 @@ dsmc_status dsmc_graph_step(dsmc_ctx c, int32_t n) {
     if (!c || n < 0) return fail(c, DSMC_E_INVALID, "bad arguments");
     if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
     if (!c->stream) return fail(c, DSMC_E_INVALID, "graph stepping needs a non-null HIP stream");
+    // a captured deferred step starts from a pending order (a state read may
+    // have written it out since the last replay)
+    if (n >= 2 && c->sort_variant == kSortDeferred && deferred_ok(c->move_variant, c->collide_variant))
+        ensure_pending(c);
     int done = 0;
     while (done + 2 <= n) {
         dsmc_ctx_s::Graph* g = nullptr;
@@ -760,11 +873,17 @@ dsmc_status dsmc_set_tuning(dsmc_ctx c, const dsmc_tuning* t) {
     if (!c || !t) return fail(c, DSMC_E_INVALID, "bad arguments");
     const bool batch_ok = move_reads_cases(t->move);
     if (t->move < 0 || t->move > kMovePersist || t->collide < 0 || t->collide > kCollideG2k || t->sort < 0 ||
-        t->sort > kSortFused || (c->n_cases && !batch_ok))
+        t->sort > kSortDeferred || (c->n_cases && !batch_ok))
         return fail(c, DSMC_E_INVALID, "unknown or unsupported kernel variant");
+    if (t->sort == kSortDeferred && !deferred_ok(t->move, t->collide))
+        return fail(c, DSMC_E_INVALID, "the deferred sort needs the three-face move and an LDS-ranked collide");
     if (c->dr && !rot_schedule_ok(t->move, t->collide, t->sort))
-        return fail(c, DSMC_E_INVALID, "a rotating gas needs a parked-wall move, LDS-ranked collide and scatter or "
-                                       "gather sort schedule");
+        return fail(c, DSMC_E_INVALID, "a rotating gas needs a parked-wall move, LDS-ranked collide and scatter, "
+                                       "gather or deferred sort schedule");
+    if (t->sort != kSortDeferred) {
+        dsmc_status st = materialize(c);
+        if (st != DSMC_OK) return st;
+    }
     c->move_variant = t->move;
     c->collide_variant = t->collide;
     c->sort_variant = t->sort;
@@ -776,6 +895,12 @@ dsmc_status dsmc_autotune(dsmc_ctx c, int32_t trial_steps, dsmc_tuning* out) {
     if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
     const bool was_profiling = c->profiling;
     dsmc_tuning best{c->move_variant, c->collide_variant, c->sort_variant, 1e300, 1e300, 1e300};
+    // moves and collides are timed with the plain gather sort
+    if (c->sort_variant == kSortDeferred) {
+        dsmc_status st = materialize(c);
+        if (st != DSMC_OK) return st;
+        c->sort_variant = kSortGather;
+    }
     const int moves[] = {kMoveDefer4, kMoveDefer5, kMoveDefer6, kMoveDefer8, kMoveFace3, kMoveFace3W8, kMoveCap4,
                          kMoveCap5, kMoveCap6, kMoveLaneW6, kMoveLaneW8, kMovePersist};
     for (int v : moves) {
@@ -797,15 +922,22 @@ dsmc_status dsmc_autotune(dsmc_ctx c, int32_t trial_steps, dsmc_tuning* out) {
         if (ms < best.collide_ms) { best.collide_ms = ms; best.collide = v; }
     }
     c->collide_variant = best.collide;
-    const int sorts[] = {kSortGather, kSortScatter, kSortFused};
+    const int sorts[] = {kSortGather, kSortScatter, kSortFused, kSortDeferred};
     for (int v : sorts) {
         if (c->dr && !rot_schedule_ok(c->move_variant, c->collide_variant, v)) continue;
+        if (v == kSortDeferred && !deferred_ok(c->move_variant, c->collide_variant)) continue;
         c->sort_variant = v;
         double ms = 0;
-        // the fused form gathers inside the collide kernel: compare sort + collide
-        dsmc_status st = time_slots(c, trial_steps, {kSlotScan, kSlotScatter, kSlotGather, kSlotCollide}, &ms);
+        // the fused form gathers inside the collide kernel and the deferred
+        // one inside the move: compare the whole step
+        dsmc_status st = time_slots(c, trial_steps,
+                                    {kSlotMove, kSlotWalls, kSlotScan, kSlotScatter, kSlotGather, kSlotCollide}, &ms);
         if (st != DSMC_OK) return st;
         if (ms < best.sort_ms) { best.sort_ms = ms; best.sort = v; }
+    }
+    if (best.sort != kSortDeferred) {
+        dsmc_status st = materialize(c);
+        if (st != DSMC_OK) return st;
     }
     c->sort_variant = best.sort;
     c->profiling = was_profiling;
@@ -825,6 +957,8 @@ dsmc_status dsmc_step(dsmc_ctx c, int32_t n) {
 
 dsmc_status dsmc_step_stages(dsmc_ctx c, int32_t mask) {
     if (!c || mask < 0 || mask > 31) return fail(c, DSMC_E_INVALID, "bad arguments");
+    if ((mask & 3) && !(mask & 4))
+        return fail(c, DSMC_E_INVALID, "move or injection without the sort would leave the store unsorted");
     if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
     return step_any(c, mask);
 }
@@ -1017,8 +1151,51 @@ dsmc_status dsmc_rot_sample(dsmc_ctx c, int32_t which, double* out) {
     return DSMC_OK;
 }
 
+dsmc_status dsmc_sample_cells(dsmc_ctx c, int32_t which, int32_t n_cells, const int32_t* tet_cell, double* out) {
+    if (!c || !tet_cell || !out || n_cells < 0) return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (c->n_cases) return fail(c, DSMC_E_INVALID, "cell fields of a batch: use dsmc_sample per case");
+    for (int t = 0; t < c->nt; ++t)
+        if (tet_cell[t] < 0 || tet_cell[t] >= n_cells) return fail(c, DSMC_E_INVALID, "tet_cell out of range");
+    std::vector<double> S((size_t)kNMom * c->nt);
+    int64_t n_steady = 0;
+    dsmc_status st = dsmc_get_sums(c, which, S.data(), &n_steady);
+    if (st != DSMC_OK) return st;
+    // per cell: sums and volumes of its tetrahedra in ascending order, laid
+    // out as the device accumulators are ([13][n_cells]) for the field kernel
+    const int ne = std::max(n_cells, 1);
+    std::vector<double> agg((size_t)kNMom * ne, 0.0), vol(ne, 0.0);
+    std::vector<int32_t> ident(ne);
+    std::iota(ident.begin(), ident.end(), 0);
+    for (int t = 0; t < c->nt; ++t) {
+        const int e = tet_cell[t];
+        for (int k = 0; k < kNMom; ++k) agg[(size_t)k * ne + e] += S[(size_t)kNMom * t + k];
+        vol[e] += c->hm.vol[c->hm.inv[t]];
+    }
+    double *d_agg = nullptr, *d_vol = nullptr, *d_out = nullptr;
+    int32_t* d_id = nullptr;
+    if (!alloc_n(c, d_agg, agg.size()) || !alloc_n(c, d_vol, (size_t)ne) || !alloc_n(c, d_out, 15 * (size_t)ne) ||
+        !alloc_n(c, d_id, (size_t)ne)) {
+        dev_free(c, d_agg); dev_free(c, d_vol); dev_free(c, d_out); dev_free(c, d_id);
+        return fail(c, DSMC_E_OOM, "device allocation failed");
+    }
+    HIP_TRY(c, hipMemcpyAsync(d_agg, agg.data(), sizeof(double) * agg.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d_vol, vol.data(), sizeof(double) * ne, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d_id, ident.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice, c->stream));
+    const double ns = which == DSMC_SAMPLE_STEADY ? (double)n_steady : 1.0;
+    launch_fields(c->stream, d_agg, n_cells, ns, c->mass, c->FN, d_vol, d_id, d_out, nullptr, nullptr);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipMemcpyAsync(out, d_out, sizeof(double) * 15 * (size_t)n_cells, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dev_free(c, d_agg); dev_free(c, d_vol); dev_free(c, d_out); dev_free(c, d_id);
+    return DSMC_OK;
+}
+
 dsmc_status dsmc_get_state(dsmc_ctx c, dsmc_state* st) {
     if (!c || !st) return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (st->x || st->v || st->cell || st->pid || st->ir) {
+        dsmc_status s = materialize(c);
+        if (s != DSMC_OK) return s;
+    }
     Scalars sc;
     dsmc_status s = sync_scalars(c, &sc);
     if (s != DSMC_OK) return s;
@@ -1071,6 +1248,7 @@ dsmc_status dsmc_set_state(dsmc_ctx c, const dsmc_state* st) {
     const int64_t n = st->n_particles;
     if (n > c->cap) return fail(c, DSMC_E_CAPACITY, "state larger than the particle store");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->pending = false;  // the store is rewritten sorted
     std::vector<int64_t> idx(n);
     std::iota(idx.begin(), idx.end(), 0);
     for (int64_t i = 0; i < n; ++i)

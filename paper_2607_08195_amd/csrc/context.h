@@ -121,6 +121,9 @@ struct dsmc_ctx_s {
     int n_cases = 0;
     // captured two-step graphs, keyed by the particle buffer current at capture
     bool capturing = false;
+    // deferred sort: A holds the particles where the last move left them and
+    // d_sortperm / B.cell their sorted order (slot -> particle, slot -> cell)
+    bool pending = false;
     // particle-grid bound of the steps being captured (see capture_two_steps)
     int64_t capture_bound = 0;
     struct Graph {
@@ -149,6 +152,8 @@ bool alloc_n(dsmc_ctx c, T*& p, size_t n) {
 
 // Exact particle count and latched device flags (synchronises).
 dsmc_status sync_scalars(dsmc_ctx c, Scalars* out);
+// Physically sorts the store when a deferred sort left its order pending.
+dsmc_status materialize(dsmc_ctx c);
 
 }  // namespace dsmcx
 

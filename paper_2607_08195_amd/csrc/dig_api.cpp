@@ -529,6 +529,9 @@ dsmc_status to_host(dsmc_ctx c, T* dst, const T* src, int k) {
 dsmc_status usable(dsmc_ctx c) {
     if (!c) return fail(c, DSMC_E_INVALID, "NULL context");
     if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
+    // the feedback and the batch tables read the store sorted by cell
+    dsmc_status st = materialize(c);
+    if (st != DSMC_OK) return st;
     return ensure(c);
 }
 

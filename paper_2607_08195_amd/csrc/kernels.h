@@ -27,8 +27,15 @@ enum { kMoveLane = 0, kMoveLaneW6 = 1, kMoveLaneW8 = 2, kMoveBatched = 3, kMoveD
 enum { kCollideLds = 0, kCollideGlobal = 1, kCollideGlobal8 = 2, kCollideG3k = 3, kCollideG2k = 4 };
 // sort: scatter by rank; gather (k_perm then k_gather); fused (k_perm, then
 // the collide kernel gathers each chunk before colliding it; G-type collide
-// schedules only, the others take the gather form)
-enum { kSortScatter = 0, kSortGather = 1, kSortFused = 2 };
+// schedules only, the others take the gather form); deferred (k_perm only:
+// the collide kernel reaches the particles through the sorted order, and the
+// next step's move reads them in that order and writes them sorted, so no
+// pass of its own moves the particle store; three-face move and G-type
+// collide schedules)
+enum { kSortScatter = 0, kSortGather = 1, kSortFused = 2, kSortDeferred = 3 };
+// how the collide kernel reaches the sorted particles: in place, gathered
+// into the sorted buffer first (fused sort), or through the sorted order
+enum { kGatherNone = 0, kGatherFused = 1, kGatherIndirect = 2 };
 
 // Particle store: positions and velocities interleaved per particle (a
 // scattered access then touches one cache line per quantity, not three),
@@ -136,9 +143,11 @@ void launch_batch_pid_base(hipStream_t s, const int32_t* prefix, const int32_t* 
                            int nt, int32_t* out);
 void launch_batch_smax(hipStream_t s, const int32_t* cell_case, const CaseDev* cases, int nt, double* smax);
 template <class VT>
+// With gperm (deferred sort, three-face schedule): slot k of p receives the
+// moved particle gperm[k] of src; p.cell already holds the slots' cells.
 void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
                  uint32_t* rank, Counters* ctr, RngKey key, double dt, int64_t np_bound, int variant, int batch,
-                 WallQueue wq);
+                 WallQueue wq, PartDev<VT> src = PartDev<VT>{}, const int32_t* gperm = nullptr);
 template <class VT>
 void launch_move_walls(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
                        uint32_t* rank, Counters* ctr, RngKey key, WallQueue wq);
@@ -146,6 +155,8 @@ bool move_parks_walls(int variant);
 template <class VT>
 void launch_gather(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalars* sc, const int32_t* perm,
                    int64_t bound);
+void launch_perm_identity(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* perm, int32_t* dst_cell,
+                          int64_t bound);
 void launch_count(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* counts, uint32_t* rank,
                   int64_t np_bound);
 void launch_inject_count(hipStream_t s, const InflowDev& in, const Scalars* sc, RngKey key, int32_t* fcount);
@@ -158,11 +169,13 @@ void launch_scan(hipStream_t s, const int32_t* in, int64_t n, int32_t* out, int3
 template <class VT>
 void launch_scatter(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalars* sc, const int32_t* offsets,
                     const uint32_t* rank, int64_t bound, int64_t cap, int32_t* perm, int variant);
+// gmode kGatherFused: p's slots are first gathered from src through
+// sortperm; kGatherIndirect: slot d of the sorted order is particle
+// sortperm[d] of p, with its cell in src.cell[d] (both G-type schedules only:
+// collide_fuses_gather).
 template <class VT>
-// With src.pos non-null (fused sort), p's slots are first gathered from src
-// through sortperm (G-type schedules only: collide_fuses_gather).
 void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
-                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant,
+                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant, int gmode,
                            PartDev<VT> src, const int32_t* sortperm);
 bool collide_fuses_gather(int variant);
 void launch_fields(hipStream_t s, const double* sums, int nt, double ns, double mass, double FN,

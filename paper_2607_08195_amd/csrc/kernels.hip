@@ -243,19 +243,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 // wave then runs at most CAP iterations instead of the largest hop count of
 // its 64 particles, and the few long tracks finish in k_move_walls on
 // compacted waves.
-template <class VT, int WPE, int CAP, bool FACE3 = false, bool SURF = true>
+// With GATHER the kernel also does the previous step's sort: lane i takes
+// slot i of that sorted order, i.e. particle gperm[i] of src (its cell
+// already in p.cell[i], written by the sort), and writes the moved particle
+// to slot i of p, so the sorted buffer is never written separately.
+template <class VT, int WPE, int CAP, bool FACE3 = false, bool SURF = true, bool GATHER = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_move_defer(
     MeshDev m, PartDev<VT> p, Scalars* sc, int32_t* counts, uint32_t* rank, Counters* ctr, RngKey key,
-    double dt, WallQueue q) {
+    double dt, WallQueue q, PartDev<VT> src, const int32_t* gperm) {
     const int64_t i = xcd_block() * 256 + threadIdx.x;
     const int64_t n = sc->np;
     int hops = 0, walls = 0, rem = 0, lost = 0, dest = -1;
     bool park = false;
     Walker w{};
     if (i < n) {
-        w.x0 = p.pos[3 * i]; w.x1 = p.pos[3 * i + 1]; w.x2 = p.pos[3 * i + 2];
-        w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
-        w.c = p.cell[i]; w.pid = p.pid[i];
+        if (GATHER) {
+            const int64_t j = gperm[i];
+            w.x0 = src.pos[3 * j]; w.x1 = src.pos[3 * j + 1]; w.x2 = src.pos[3 * j + 2];
+            w.v0 = (double)src.vel[3 * j]; w.v1 = (double)src.vel[3 * j + 1]; w.v2 = (double)src.vel[3 * j + 2];
+            w.c = p.cell[i]; w.pid = src.pid[j];
+            if (src.ir) p.ir[i] = src.ir[j];
+            p.pid[i] = w.pid;
+        } else {
+            w.x0 = p.pos[3 * i]; w.x1 = p.pos[3 * i + 1]; w.x2 = p.pos[3 * i + 2];
+            w.v0 = (double)p.vel[3 * i]; w.v1 = (double)p.vel[3 * i + 1]; w.v2 = (double)p.vel[3 * i + 2];
+            w.c = p.cell[i]; w.pid = p.pid[i];
+        }
         RngKey kp = key;
         double dtp = dt;
         case_params(m.cell_case, m.cases, w.c, kp, dtp);
@@ -272,7 +285,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             park = true;
             p.cell[i] = w.c;
             // the velocity it reaches the wall with (surface sampling reads it)
-            if (w.walls) {
+            if (GATHER || w.walls) {
                 p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
             }
         } else if (CAP > 0 && st < 0) {
@@ -285,7 +298,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         } else {
             hops = w.nhop;
             walls = w.walls;
-            if (w.walls) {
+            if (GATHER || w.walls) {
                 p.vel[3 * i] = (VT)w.v0; p.vel[3 * i + 1] = (VT)w.v1; p.vel[3 * i + 2] = (VT)w.v2;
             }
             if (st == 0) {
@@ -979,6 +992,16 @@ __global__ __launch_bounds__(256) void k_perm(const int32_t* cell, const Scalars
     dst_cell[d] = c;  // the slot's cell, so that the gather need not load it
 }
 
+// The sorted order of a buffer that is already sorted: slot k holds
+// particle k (deferred sort after a physical sort).
+__global__ __launch_bounds__(256) void k_perm_identity(const int32_t* cell, const Scalars* sc, int32_t* perm,
+                                                      int32_t* dst_cell) {
+    const int64_t k = xcd_block() * 256 + threadIdx.x;
+    if (k >= sc->np) return;
+    perm[k] = (int32_t)k;
+    dst_cell[k] = cell[k];
+}
+
 template <class VT>
 __global__ __launch_bounds__(256) void k_gather(PartDev<VT> src, PartDev<VT> dst, const Scalars* sc,
                                                const int32_t* perm) {
@@ -1054,6 +1077,27 @@ struct LdsOrderCell {
     double* ir;            // rotational energies of the particle store (rotating gas)
     __device__ __forceinline__ double getI(int k) const { return ir[a + ord[s0 + k]]; }
     __device__ __forceinline__ void putI(int k, double e) const { ir[a + ord[s0 + k]] = e; }
+};
+
+// As LdsOrderCell for particles left where the move put them: the window's
+// slot -> particle index table in LDS.
+template <class VT>
+struct LdsIndCell {
+    VT* v;                 // interleaved velocities of the particle store
+    const uint16_t* ord;   // sorted position -> slot relative to the window start
+    const uint32_t* src;   // window slot -> particle index
+    int s0;
+    __device__ __forceinline__ void get(int k, double& x, double& y, double& z) const {
+        const int64_t l = src[ord[s0 + k]];
+        x = (double)v[3 * l]; y = (double)v[3 * l + 1]; z = (double)v[3 * l + 2];
+    }
+    __device__ __forceinline__ void put(int k, double x, double y, double z) const {
+        const int64_t l = src[ord[s0 + k]];
+        v[3 * l] = (VT)x; v[3 * l + 1] = (VT)y; v[3 * l + 2] = (VT)z;
+    }
+    double* ir;            // rotational energies of the particle store (rotating gas)
+    __device__ __forceinline__ double getI(int k) const { return ir[src[ord[s0 + k]]]; }
+    __device__ __forceinline__ void putI(int k, double e) const { ir[src[ord[s0 + k]]] = e; }
 };
 
 // Post-collision relative velocity g' (|g'| = |g| = c_r) from two uniform
@@ -1355,11 +1399,15 @@ __global__ __launch_bounds__(kCollideLanes) void k_collide_sample(PartDev<VT> p,
 // index; k_perm has written the slots' cells): the sort's gather done by the
 // workgroup that then collides the chunk, so that gathering one chunk
 // overlaps the collisions of others and the velocities are read back from
-// cache.
-template <class VT, int WPE, int CAP, bool FUSED, bool VSS, bool ROT = false>
+// cache.  With IND (deferred sort) nothing is moved: slot d of the sorted
+// order is particle sortperm[d] of p, its cell src.cell[d]; after the
+// ranking the window's pid table is overwritten with those particle indices.
+template <class VT, int WPE, int CAP, int GM, bool VSS, bool ROT = false>
 __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(WPE))) void k_collide_sample_g(
     PartDev<VT> p, const int32_t* offsets, CollideParams cp, const Scalars* sc, int32_t* perm, int do_collide,
     int do_sample, PartDev<VT> src, const int32_t* sortperm) {
+    constexpr bool FUSED = GM == kGatherFused;
+    constexpr bool IND = GM == kGatherIndirect;
     __shared__ uint32_t spid[CAP];
     __shared__ uint16_t sord[CAP];
     __shared__ int32_t soff[kCollideLanes + 1];
@@ -1433,10 +1481,10 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
                 const int64_t s0 = offsets[cc];
                 const int N = offsets[cc + 1] - offsets[cc];
                 for (int k = 0; k < N; ++k) {
-                    const uint32_t pk = p.pid[s0 + k];
+                    const uint32_t pk = IND ? p.pid[sortperm[s0 + k]] : p.pid[s0 + k];
                     int r = 0;
-                    for (int q = 0; q < N; ++q) r += p.pid[s0 + q] < pk;
-                    perm[s0 + r] = (int32_t)(s0 + k);
+                    for (int q = 0; q < N; ++q) r += (IND ? p.pid[sortperm[s0 + q]] : p.pid[s0 + q]) < pk;
+                    perm[s0 + r] = IND ? sortperm[s0 + k] : (int32_t)(s0 + k);
                 }
                 GlobalCell<VT> cv{p.vel, perm, s0, p.ir};
                 if (do_collide) ntc_cell<VSS, ROT>(cv, N, cc, cp, step, cp.smax, cp.ncand, cp.nacc);
@@ -1449,11 +1497,12 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
         if (!FUSED || n > CAP) {
             if (k0 > 0) __syncthreads();  // the previous window's ranks are no longer read
 #pragma unroll 4
-            for (int i = lane; i < wn; i += kCollideLanes) spid[i] = p.pid[a + w0 + i];
+            for (int i = lane; i < wn; i += kCollideLanes)
+                spid[i] = IND ? p.pid[sortperm[a + w0 + i]] : p.pid[a + w0 + i];
         }
         __syncthreads();
         for (int i = lane; i < wn; i += kCollideLanes) {
-            const int k = p.cell[a + w0 + i] - c0;
+            const int k = (IND ? src.cell[a + w0 + i] : p.cell[a + w0 + i]) - c0;
             const int s0 = soff[k] - w0;
             const int N = soff[k + 1] - soff[k];
             const uint32_t pk = spid[i];
@@ -1463,7 +1512,19 @@ __global__ __launch_bounds__(kCollideLanes) __attribute__((amdgpu_waves_per_eu(W
             sord[s0 + r] = (uint16_t)i;
         }
         __syncthreads();
-        if (lane >= k0 && lane < k1 && c < nt) {
+        if constexpr (IND) {
+            // the pids are ranked: the table now maps window slots to particles
+#pragma unroll 4
+            for (int i = lane; i < wn; i += kCollideLanes) spid[i] = (uint32_t)sortperm[a + w0 + i];
+            __syncthreads();
+            if (lane >= k0 && lane < k1 && c < nt) {
+                const int s0 = soff[lane] - w0;
+                const int N = soff[lane + 1] - soff[lane];
+                LdsIndCell<VT> cv{p.vel, sord, spid, s0, p.ir};
+                if (do_collide) ntc_cell<VSS, ROT>(cv, N, c, cp, step, cp.smax, cp.ncand, cp.nacc);
+                if (do_sample) sample_cell<ROT>(cv, N, c, cp, step);
+            }
+        } else if (lane >= k0 && lane < k1 && c < nt) {
             const int s0 = soff[lane] - w0;
             const int N = soff[lane + 1] - soff[lane];
             LdsOrderCell<VT> cv{p.vel, sord, s0, a + w0, p.ir};
@@ -1608,7 +1669,18 @@ static int persist_grid() {
 template <class VT>
 void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* sc, int32_t* counts,
                  uint32_t* rank, Counters* ctr, RngKey key, double dt, int64_t np_bound, int variant, int batch,
-                 WallQueue wq) {
+                 WallQueue wq, PartDev<VT> src, const int32_t* gperm) {
+    if (gperm) {
+        // the sort's gather folded into the move (three-face schedule)
+        const dim3 g(grid8(np_bound, 256));
+        if (m.surf)
+            hipLaunchKernelGGL((k_move_defer<VT, 6, 0, true, true, true>), g, dim3(256), 0, s, m, p, (Scalars*)sc,
+                               counts, rank, ctr, key, dt, wq, src, gperm);
+        else
+            hipLaunchKernelGGL((k_move_defer<VT, 7, 0, true, false, true>), g, dim3(256), 0, s, m, p, (Scalars*)sc,
+                               counts, rank, ctr, key, dt, wq, src, gperm);
+        return;
+    }
     switch (variant) {
     case kMoveBatched: {
         const int b = batch > 0 ? batch : kMoveBatch;
@@ -1631,29 +1703,29 @@ void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* 
         const dim3 g(grid8(np_bound, 256));
         if (variant == kMoveDefer4)
             hipLaunchKernelGGL((k_move_defer<VT, 4, 0>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
-                               key, dt, wq);
+                               key, dt, wq, PartDev<VT>{}, nullptr);
         else if (variant == kMoveDefer5)
             hipLaunchKernelGGL((k_move_defer<VT, 5, 0>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
-                               key, dt, wq);
+                               key, dt, wq, PartDev<VT>{}, nullptr);
         else if (variant == kMoveDefer6)
             hipLaunchKernelGGL((k_move_defer<VT, 6, 0>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
-                               key, dt, wq);
+                               key, dt, wq, PartDev<VT>{}, nullptr);
         else
             hipLaunchKernelGGL((k_move_defer<VT, 8, 0>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank, ctr,
-                               key, dt, wq);
+                               key, dt, wq, PartDev<VT>{}, nullptr);
         break;
     }
     case kMoveFace3:
         if (m.surf)
             hipLaunchKernelGGL((k_move_defer<VT, 6, 0, true>), dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p,
-                               (Scalars*)sc, counts, rank, ctr, key, dt, wq);
+                               (Scalars*)sc, counts, rank, ctr, key, dt, wq, PartDev<VT>{}, nullptr);
         else
             hipLaunchKernelGGL((k_move_defer<VT, 6, 0, true, false>), dim3(grid8(np_bound, 256)), dim3(256), 0, s,
-                               m, p, (Scalars*)sc, counts, rank, ctr, key, dt, wq);
+                               m, p, (Scalars*)sc, counts, rank, ctr, key, dt, wq, PartDev<VT>{}, nullptr);
         break;
     case kMoveFace3W8:
         hipLaunchKernelGGL((k_move_defer<VT, 8, 0, true>), dim3(grid8(np_bound, 256)), dim3(256), 0, s, m, p,
-                           (Scalars*)sc, counts, rank, ctr, key, dt, wq);
+                           (Scalars*)sc, counts, rank, ctr, key, dt, wq, PartDev<VT>{}, nullptr);
         break;
     case kMovePersist: {
         const dim3 g((unsigned)persist_grid());
@@ -1671,13 +1743,13 @@ void launch_move(hipStream_t s, const MeshDev& m, PartDev<VT> p, const Scalars* 
         const dim3 g(grid8(np_bound, 256));
         if (variant == kMoveCap4)
             hipLaunchKernelGGL((k_move_defer<VT, 6, 4, true>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank,
-                               ctr, key, dt, wq);
+                               ctr, key, dt, wq, PartDev<VT>{}, nullptr);
         else if (variant == kMoveCap5)
             hipLaunchKernelGGL((k_move_defer<VT, 6, 5, true>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank,
-                               ctr, key, dt, wq);
+                               ctr, key, dt, wq, PartDev<VT>{}, nullptr);
         else
             hipLaunchKernelGGL((k_move_defer<VT, 6, 6, true>), g, dim3(256), 0, s, m, p, (Scalars*)sc, counts, rank,
-                               ctr, key, dt, wq);
+                               ctr, key, dt, wq, PartDev<VT>{}, nullptr);
         break;
     }
     case kMovePool128:
@@ -1752,7 +1824,7 @@ void launch_scan(hipStream_t s, const int32_t* in, int64_t n, int32_t* out, int3
 template <class VT>
 void launch_scatter(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalars* sc, const int32_t* offsets,
                     const uint32_t* rank, int64_t bound, int64_t cap, int32_t* perm, int variant) {
-    if (variant == kSortGather || variant == kSortFused) {
+    if (variant != kSortScatter) {
         hipLaunchKernelGGL(k_perm, dim3(grid8(bound, 256)), dim3(256), 0, s, src.cell, sc, offsets, rank, perm,
                            dst.cell, cap);
     } else {
@@ -1766,20 +1838,28 @@ void launch_gather(hipStream_t s, PartDev<VT> src, PartDev<VT> dst, const Scalar
     hipLaunchKernelGGL(k_gather<VT>, dim3(grid8(bound, 256)), dim3(256), 0, s, src, dst, sc, perm);
 }
 
+void launch_perm_identity(hipStream_t s, const int32_t* cell, const Scalars* sc, int32_t* perm, int32_t* dst_cell,
+                          int64_t bound) {
+    hipLaunchKernelGGL(k_perm_identity, dim3(grid8(bound, 256)), dim3(256), 0, s, cell, sc, perm, dst_cell);
+}
+
 template <class VT, int WPE, int CAP, bool VSS, bool ROT>
 static void launch_collide_g(hipStream_t s, int nchunk, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
-                             const Scalars* sc, int32_t* perm, int do_collide, int do_sample, PartDev<VT> src,
-                             const int32_t* sortperm) {
-    if constexpr (ROT) {
+                             const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int gmode,
+                             PartDev<VT> src, const int32_t* sortperm) {
+    if (gmode == kGatherIndirect) {
+        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, kGatherIndirect, VSS, ROT>), dim3(nchunk),
+                           dim3(kCollideLanes), 0, s, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
+    } else if constexpr (ROT) {
         // a rotating gas never takes the fused gather (the host refuses that schedule)
-        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, false, VSS, true>), dim3(nchunk), dim3(kCollideLanes), 0,
+        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, kGatherNone, VSS, true>), dim3(nchunk),
+                           dim3(kCollideLanes), 0, s, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
+    } else if (gmode == kGatherFused) {
+        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, kGatherFused, VSS>), dim3(nchunk), dim3(kCollideLanes), 0,
                            s, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
-    } else if (src.pos) {
-        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, true, VSS>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
-                           offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
     } else {
-        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, false, VSS>), dim3(nchunk), dim3(kCollideLanes), 0, s, p,
-                           offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
+        hipLaunchKernelGGL((k_collide_sample_g<VT, WPE, CAP, kGatherNone, VSS>), dim3(nchunk), dim3(kCollideLanes), 0,
+                           s, p, offsets, cp, sc, perm, do_collide, do_sample, src, sortperm);
     }
 }
 
@@ -1789,20 +1869,20 @@ bool collide_fuses_gather(int variant) {
 
 template <class VT, bool VSS, bool ROT>
 static void launch_collide_v(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
-                             const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant,
+                             const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant, int gmode,
                              PartDev<VT> src, const int32_t* sortperm) {
     const int nchunk = (cp.nt + kCollideLanes - 1) / kCollideLanes;
     if (variant == kCollideGlobal)
         launch_collide_g<VT, 4, kCollideCapG, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample,
-                                                        src, sortperm);
+                                                        gmode, src, sortperm);
     else if (variant == kCollideGlobal8)
         launch_collide_g<VT, 8, kCollideCapG, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample,
-                                                        src, sortperm);
+                                                        gmode, src, sortperm);
     else if (variant == kCollideG3k)
-        launch_collide_g<VT, 4, 3072, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src,
+        launch_collide_g<VT, 4, 3072, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, gmode, src,
                                                 sortperm);
     else if (variant == kCollideG2k)
-        launch_collide_g<VT, 4, 2048, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, src,
+        launch_collide_g<VT, 4, 2048, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, gmode, src,
                                                 sortperm);
     else if constexpr (!ROT)
         hipLaunchKernelGGL((k_collide_sample<VT, VSS>), dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc,
@@ -1811,19 +1891,19 @@ static void launch_collide_v(hipStream_t s, PartDev<VT> p, const int32_t* offset
 
 template <class VT>
 void launch_collide_sample(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
-                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant,
+                           const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant, int gmode,
                            PartDev<VT> src, const int32_t* sortperm) {
     if (cp.rot) {
         if (cp.vss)
-            launch_collide_v<VT, true, true>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, src,
+            launch_collide_v<VT, true, true>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, gmode, src,
                                              sortperm);
         else
-            launch_collide_v<VT, false, true>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, src,
+            launch_collide_v<VT, false, true>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, gmode, src,
                                               sortperm);
     } else if (cp.vss) {
-        launch_collide_v<VT, true, false>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, src, sortperm);
+        launch_collide_v<VT, true, false>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, gmode, src, sortperm);
     } else {
-        launch_collide_v<VT, false, false>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, src,
+        launch_collide_v<VT, false, false>(s, p, offsets, cp, sc, perm, do_collide, do_sample, variant, gmode, src,
                                            sortperm);
     }
 }
@@ -1860,7 +1940,8 @@ void launch_fill_f64(hipStream_t s, double* p, double v, int64_t n) {
                                        const double*, int64_t, Scalars*, const int32_t*, const CaseDev*,    \
                                        double);                                                             \
     template void launch_move<VT>(hipStream_t, const MeshDev&, PartDev<VT>, const Scalars*, int32_t*,       \
-                                  uint32_t*, Counters*, RngKey, double, int64_t, int, int, WallQueue);      \
+                                  uint32_t*, Counters*, RngKey, double, int64_t, int, int, WallQueue,       \
+                                  PartDev<VT>, const int32_t*);                                             \
     template void launch_inject_emit<VT>(hipStream_t, const MeshDev&, const InflowDev&, PartDev<VT>,        \
                                          Scalars*, const int32_t*, int32_t*, uint32_t*, Counters*, RngKey,  \
                                          double, int64_t, int64_t);                                         \
@@ -1871,7 +1952,8 @@ void launch_fill_f64(hipStream_t s, double* p, double v, int64_t n) {
     template void launch_gather<VT>(hipStream_t, PartDev<VT>, PartDev<VT>, const Scalars*, const int32_t*,  \
                                     int64_t);                                                               \
     template void launch_collide_sample<VT>(hipStream_t, PartDev<VT>, const int32_t*, const CollideParams&, \
-                                            const Scalars*, int32_t*, int, int, int, PartDev<VT>, const int32_t*);
+                                            const Scalars*, int32_t*, int, int, int, int, PartDev<VT>,        \
+                                            const int32_t*);
 
 INSTANTIATE(float)
 INSTANTIATE(double)

@@ -144,6 +144,53 @@ def test_sort_schedules_parity(dsmc, sort, collide, case):
     _one_step_parity(dsmc, make(), pre, steps=2, collide=collide, sort=sort)
 
 
+# deferred sort: the move reads the particles in the previous step's sorted
+# order and writes them sorted, the collide kernel reaches them through the
+# order; three steps, so that the second and third moves start from an order
+# the sort computed (the first starts from the identity order)
+@pytest.mark.parametrize("case", ["cavity_8_fp32_jitter_kn0.1", "dense_ppc45", "open_box_inflow", "cavity_6_fp64_kn1",
+                                  "vss_dense_fp32_a1.6", "sphere_hypersonic", "plates_periodic_couette",
+                                  "specular_box", "sparse_ppc1"])
+@pytest.mark.parametrize("collide", [1, 2, 3, 4])
+def test_deferred_sort_parity(dsmc, collide, case):
+    make, pre = CASES[case]
+    _one_step_parity(dsmc, make(), pre, steps=3, move=15, collide=collide, sort=3)
+
+
+def test_deferred_sort_refuses_other_schedules(dsmc):
+    g = dsmc.Simulation(W.cavity(n_hex=3, Kn=0.5, ppc=5, vel_fp32=1))
+    for move, collide in [(12, 3), (15, 0), (17, 3)]:
+        with pytest.raises(dsmc.DsmcError):
+            g.set_tuning(move, collide, 3)
+    # a move without the sort is refused (it would leave the store unsorted)
+    with pytest.raises(dsmc.DsmcError):
+        g.step_stages(1)
+    g.close()
+
+
+def test_deferred_sort_matches_gather_across_reads(dsmc):
+    """Deferred stepping interleaved with state reads (which write the
+    pending order out) and with surface sampling gives the states of the
+    gather sort, bit for bit."""
+    wl = W.cavity(n_hex=7, Kn=0.1, ppc=25, jitter=0.1, vel_fp32=1)
+    a = dsmc.Simulation(wl)
+    b = dsmc.Simulation(wl)
+    a.set_tuning(15, 3, 1)
+    b.set_tuning(15, 3, 3)
+    a.surface_sampling(True)
+    b.surface_sampling(True)
+    for n in [1, 3, 2, 5]:
+        a.step(n)
+        b.step(n)
+        sa, sb = a.state(), b.state()
+        for k in ["cell", "pid", "x", "v"]:
+            assert np.array_equal(sa[k], sb[k]), (n, k)
+    assert np.array_equal(a.sums(dsmc.SAMPLE_STEADY)[0], b.sums(dsmc.SAMPLE_STEADY)[0])
+    assert np.array_equal(a.surface()[0], b.surface()[0])
+    a.close()
+    b.close()
+
+
 def test_three_steps_parity_fp64(dsmc):
     wl = W.cavity(n_hex=6, Kn=1.0, ppc=20, vel_fp32=0)
     _one_step_parity(dsmc, wl, 0, steps=3)

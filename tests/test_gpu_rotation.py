@@ -58,7 +58,7 @@ CASES = {
 # schedules that carry the rotational energy
 ROT_MOVES = [4, 5, 6, 7, 12, 13, 14, 15, 16, 17]
 ROT_COLLIDES = [1, 2, 3, 4]
-ROT_SORTS = [0, 1]
+ROT_SORTS = [0, 1, 3]
 
 
 def _compare_ir(g, o, T0, ctx):
