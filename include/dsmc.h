@@ -156,7 +156,8 @@ dsmc_status dsmc_init(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
 dsmc_status dsmc_step(dsmc_ctx ctx, int32_t n_steps);
 
 /* One step restricted to the stages in mask (1 move, 2 inject, 4 sort,
- * 8 collide, 16 sample); for stage-level testing. */
+ * 8 collide, 16 sample); for stage-level testing.  A mask with move or
+ * injection must include the sort (DSMC_E_INVALID otherwise). */
 dsmc_status dsmc_step_stages(dsmc_ctx ctx, int32_t mask);
 
 /* Accumulators: STEADY sums every step after n_ss, EWMA is the moving
@@ -188,6 +189,74 @@ dsmc_status dsmc_get_sums(dsmc_ctx ctx, int32_t which, double* out, int64_t* n_s
  * samples).  Host arrays; synchronise; DSMC_E_INVALID for a monatomic gas. */
 dsmc_status dsmc_get_rot_sums(dsmc_ctx ctx, int32_t which, double* out, int64_t* n_samples);
 dsmc_status dsmc_rot_sample(dsmc_ctx ctx, int32_t which, double* out);
+
+/* Mixed-element meshes (section 5.4: tetrahedral, pyramid ("pentahedral"),
+ * triangular-prism and hexahedral cells).  The step works on tetrahedra:
+ * dsmc_mesh_decompose turns a mixed mesh into a conforming tetrahedral one
+ * for dsmc_init, and dsmc_sample_cells gives the fields of the original
+ * cells from the sums of their tetrahedra.
+ *
+ * cell_nv[c] = 4, 5, 6 or 8 vertices, listed in cell_vtx one cell after the
+ * other in these local orders: tetrahedron v0..v3; pyramid base v0 v1 v2 v3
+ * (cyclic) and apex v4; prism triangles v0 v1 v2 and v3 v4 v5 with v3 over
+ * v0, v4 over v1, v5 over v2; hexahedron v0 v1 v2 v3 (cyclic) and v4..v7
+ * over them.  Boundary faces: bface_nv[b] = 3 or 4 vertices (cyclic) in
+ * bface_vtx, a group each, periodic partners (bface_partner, may be NULL)
+ * only between triangles.
+ *
+ * Decomposition: a quadrilateral face (a, b, c, d) is split into (a, b, c),
+ * (a, c, d) when a or c has the smallest vertex index of the four, else
+ * into (a, b, d), (b, c, d), so neighbours split a shared face alike; a
+ * pyramid becomes its apex over its two base triangles; a prism or a
+ * hexahedron gets a new vertex at the mean of its vertices (coordinate-wise
+ * sum in local order, divided by the vertex count; new vertices numbered
+ * after the input ones in cell order) and one tetrahedron per face
+ * triangle with it: the two triangles first, then the quadrilaterals
+ * (v0 v1 v4 v3), (v1 v2 v5 v4), (v2 v0 v3 v5) of a prism, and (v0 v1 v2
+ * v3), (v4 v5 v6 v7), (v0 v1 v5 v4), (v1 v2 v6 v5), (v2 v3 v7 v6), (v3 v0
+ * v4 v7) of a hexahedron.  Tetrahedra come in cell order (tet_cell: the
+ * cell of each), boundary triangles in face order (bface_parent: the face
+ * of each).  Cells must be convex (star-shaped from their vertex mean);
+ * dsmc_init checks the result as any tetrahedral mesh.
+ *
+ * Call with every output array NULL to get the counts, then with arrays of
+ * at least those sizes (n_vertices, n_tets, n_bfaces set to their
+ * capacities).  DSMC_E_MESH on a bad cell or face (dsmc_mesh_error says
+ * which); DSMC_E_INVALID for NULL arguments or short arrays.  Host only. */
+typedef struct {
+    int32_t n_vertices;
+    const double* xyz;           /* [n_vertices][3] */
+    int32_t n_cells;
+    const int32_t* cell_nv;      /* [n_cells] */
+    const int32_t* cell_vtx;     /* sum of cell_nv entries */
+    int32_t n_bfaces;
+    const int32_t* bface_nv;     /* [n_bfaces] */
+    const int32_t* bface_vtx;    /* sum of bface_nv entries */
+    const int32_t* bface_group;  /* [n_bfaces] */
+    const int32_t* bface_partner; /* [n_bfaces] or NULL */
+} dsmc_mixed_mesh_desc;
+
+typedef struct {
+    int32_t n_vertices, n_tets, n_bfaces; /* capacities in, counts out */
+    double* xyz;            /* [n_vertices][3]: the input vertices, then the new ones */
+    int32_t* tet_vtx;       /* [n_tets][4] */
+    int32_t* tet_cell;      /* [n_tets] */
+    int32_t* bface_vtx;     /* [n_bfaces][3] */
+    int32_t* bface_group;   /* [n_bfaces] */
+    int32_t* bface_partner; /* [n_bfaces], -1 where none */
+    int32_t* bface_parent;  /* [n_bfaces] */
+} dsmc_tet_mesh_out;
+
+dsmc_status dsmc_mesh_decompose(const dsmc_mixed_mesh_desc* in, dsmc_tet_mesh_out* out);
+const char* dsmc_mesh_error(void);
+
+/* Fields of the cells of a mixed mesh: the moment sums of each cell's
+ * tetrahedra (tet_cell[n_tets] from dsmc_mesh_decompose, caller's tet
+ * numbering) added in ascending tetrahedron order, over the sum of their
+ * volumes, through the formulas of dsmc_sample: out[n_cells][15] (NaN for
+ * a cell without samples).  Host arrays; synchronises.  DSMC_E_INVALID for
+ * a cell index out of range or a batch context. */
+dsmc_status dsmc_sample_cells(dsmc_ctx ctx, int32_t which, int32_t n_cells, const int32_t* tet_cell, double* out);
 
 /* Surface sampling (the wall pressure, shear stress and heat flux the
  * paper compares on the sphere, section 5): every interaction of a particle

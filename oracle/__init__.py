@@ -65,6 +65,7 @@ def _load():
     lib.oracle_set_sums.argtypes = [P, i, P]
     lib.oracle_get_ewma_counts.argtypes = [P, P]
     lib.oracle_fields.argtypes = [P, i, P]
+    lib.oracle_fields_of_sums.argtypes = [P, P, P, i, d, P]
     lib.oracle_get_volumes.argtypes = [P, P]
     lib.oracle_get_neighbours.argtypes = [P, P]
     lib.oracle_get_tets.argtypes = [P, P]
@@ -284,6 +285,14 @@ class Oracle:
     def fields(self, which=0):
         o = np.zeros((self.nt, 15))
         self.lib.oracle_fields(self.h, which, _p(o))
+        return o
+
+    def fields_of_sums(self, sums, vol, ns):
+        """Fields [n][15] of given sums [n][13] over volumes [n], ns samples."""
+        sums = np.ascontiguousarray(sums, np.float64)
+        vol = np.ascontiguousarray(vol, np.float64)
+        o = np.zeros((len(vol), 15))
+        self.lib.oracle_fields_of_sums(self.h, _p(sums), _p(vol), len(vol), float(ns), _p(o))
         return o
 
     def volumes(self):

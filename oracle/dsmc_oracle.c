@@ -1054,38 +1054,47 @@ void oracle_set_local_acc(osim* s, const unsigned char* flags) {
 
 /* Fields from a sum set over ns samples (eq. dsmc_temperatures, with the
  * cell mean taken over all sampled particles). */
+/* Fields of one set of moment sums S (eq. dsmc_temperatures): number
+ * density, density, velocity, temperature, stress, heat flux; NaN without
+ * samples. */
+static void fields_of(const double* S, double ns, double FN, double m, double vol, double* o) {
+    if (!(S[0] > 0) || !(ns > 0)) {
+        for (int k = 0; k < 15; ++k) o[k] = NAN;
+        return;
+    }
+    double nbar = S[0] / ns;
+    double n = (FN * nbar) / vol;
+    double rho = m * n;
+    double u[3] = {S[1] / S[0], S[2] / S[0], S[3] / S[0]};
+    /* C_ij = S2_ij/S0 - u_i u_j, order xx, yy, zz, xy, xz, yz */
+    const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+    double C[6];
+    for (int k = 0; k < 6; ++k) C[k] = S[4 + k] / S[0] - u[ii[k]] * u[jj[k]];
+    double Ckk = C[0] + C[1] + C[2];
+    double T = (m * Ckk) / (3.0 * KB);
+    o[0] = n; o[1] = rho; o[2] = u[0]; o[3] = u[1]; o[4] = u[2]; o[5] = T;
+    for (int k = 0; k < 6; ++k) o[6 + k] = rho * (C[k] - (k < 3 ? Ckk / 3.0 : 0.0));
+    /* full second-moment matrix entries S2_ij */
+    double M2[3][3] = {{S[4], S[7], S[8]}, {S[7], S[5], S[9]}, {S[8], S[9], S[6]}};
+    double S2kk = S[4] + S[5] + S[6];
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < 3; ++i) {
+        double uS = u[0] * M2[i][0] + u[1] * M2[i][1] + u[2] * M2[i][2];
+        double br = ((S[10 + i] - 2.0 * uS) - u[i] * S2kk) + 2.0 * S[0] * u[i] * uu;
+        o[12 + i] = (rho / 2.0) * br / S[0];
+    }
+}
+
 void oracle_fields(const osim* s, int which, double* out) {
     const double* src = which == 0 ? s->acc : which == 1 ? s->ewma : s->inst;
     double ns = which == 0 ? (double)s->n_steady : 1.0;
-    for (int c = 0; c < s->nt; ++c) {
-        const double* S = src + NMOM * (size_t)c;
-        double* o = out + 15 * (size_t)c;
-        if (!(S[0] > 0) || !(ns > 0)) {
-            for (int k = 0; k < 15; ++k) o[k] = NAN;
-            continue;
-        }
-        double nbar = S[0] / ns;
-        double n = (s->FN * nbar) / s->vol[c];
-        double rho = s->m * n;
-        double u[3] = {S[1] / S[0], S[2] / S[0], S[3] / S[0]};
-        /* C_ij = S2_ij/S0 - u_i u_j, order xx, yy, zz, xy, xz, yz */
-        const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
-        double C[6];
-        for (int k = 0; k < 6; ++k) C[k] = S[4 + k] / S[0] - u[ii[k]] * u[jj[k]];
-        double Ckk = C[0] + C[1] + C[2];
-        double T = (s->m * Ckk) / (3.0 * KB);
-        o[0] = n; o[1] = rho; o[2] = u[0]; o[3] = u[1]; o[4] = u[2]; o[5] = T;
-        for (int k = 0; k < 6; ++k) o[6 + k] = rho * (C[k] - (k < 3 ? Ckk / 3.0 : 0.0));
-        /* full second-moment matrix entries S2_ij */
-        double M2[3][3] = {{S[4], S[7], S[8]}, {S[7], S[5], S[9]}, {S[8], S[9], S[6]}};
-        double S2kk = S[4] + S[5] + S[6];
-        double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-        for (int i = 0; i < 3; ++i) {
-            double uS = u[0] * M2[i][0] + u[1] * M2[i][1] + u[2] * M2[i][2];
-            double br = ((S[10 + i] - 2.0 * uS) - u[i] * S2kk) + 2.0 * S[0] * u[i] * uu;
-            o[12 + i] = (rho / 2.0) * br / S[0];
-        }
-    }
+    for (int c = 0; c < s->nt; ++c) fields_of(src + NMOM * (size_t)c, ns, s->FN, s->m, s->vol[c], out + 15 * (size_t)c);
+}
+
+/* The same fields of n given sets of sums [n][13] over the given volumes
+ * (cells made of several tetrahedra). */
+void oracle_fields_of_sums(const osim* s, const double* sums, const double* vol, int n, double ns, double* out) {
+    for (int c = 0; c < n; ++c) fields_of(sums + NMOM * (size_t)c, ns, s->FN, s->m, vol[c], out + 15 * (size_t)c);
 }
 
 void oracle_get_volumes(const osim* s, double* vol) { memcpy(vol, s->vol, sizeof(double) * (size_t)s->nt); }

@@ -101,6 +101,7 @@ void oracle_get_ewma_counts(const osim*, int* out);
 void oracle_set_local_acc(osim*, const unsigned char* flags);
 /* fields [nt][15]: n, rho, u(3), T, sigma(xx,yy,zz,xy,xz,yz), q(3) */
 void oracle_fields(const osim*, int which, double* out);
+void oracle_fields_of_sums(const osim*, const double* sums, const double* vol, int n, double ns, double* out);
 
 /* Geometry accessors for the tests. */
 void oracle_get_volumes(const osim*, double* vol);

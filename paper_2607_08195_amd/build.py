@@ -13,7 +13,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdsmc.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "dig.hip", "mlp.hip", "api.cpp", "dig_api.cpp", "mlp_api.cpp", "mesh.cpp"]
+SOURCES = ["kernels.hip", "dig.hip", "mlp.hip", "api.cpp", "dig_api.cpp", "mlp_api.cpp", "mesh.cpp", "mixed.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result",
          "-I", INCLUDE, "-I", CSRC]

@@ -62,6 +62,18 @@ class State(C.Structure):
                 ("step", C.c_uint32), ("next_pid", C.c_uint32), ("ir", P)]
 
 
+class MixedMeshDesc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("xyz", P), ("n_cells", C.c_int32), ("cell_nv", P), ("cell_vtx", P),
+                ("n_bfaces", C.c_int32), ("bface_nv", P), ("bface_vtx", P), ("bface_group", P),
+                ("bface_partner", P)]
+
+
+class TetMeshOut(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_tets", C.c_int32), ("n_bfaces", C.c_int32), ("xyz", P),
+                ("tet_vtx", P), ("tet_cell", P), ("bface_vtx", P), ("bface_group", P), ("bface_partner", P),
+                ("bface_parent", P)]
+
+
 class Counters(C.Structure):
     _fields_ = [("n_particles", C.c_int64), ("hops", C.c_int64), ("wall_hits", C.c_int64),
                 ("injected", C.c_int64), ("removed", C.c_int64), ("lost", C.c_int64), ("step", C.c_uint32)]
@@ -119,6 +131,10 @@ _lib.dsmc_step_stages.argtypes = [ctx_t, C.c_int32]
 _lib.dsmc_sample.argtypes = [ctx_t, C.c_int32, P, C.c_int32]
 _lib.dsmc_get_sums.argtypes = [ctx_t, C.c_int32, P, C.POINTER(C.c_int64)]
 _lib.dsmc_get_rot_sums.argtypes = [ctx_t, C.c_int32, P, C.POINTER(C.c_int64)]
+_lib.dsmc_mesh_decompose.argtypes = [C.POINTER(MixedMeshDesc), C.POINTER(TetMeshOut)]
+_lib.dsmc_mesh_error.restype = C.c_char_p
+_lib.dsmc_mesh_error.argtypes = []
+_lib.dsmc_sample_cells.argtypes = [ctx_t, C.c_int32, C.c_int32, P, P]
 _lib.dsmc_rot_sample.argtypes = [ctx_t, C.c_int32, P]
 _lib.dsmc_get_state.argtypes = [ctx_t, C.POINTER(State)]
 _lib.dsmc_set_state.argtypes = [ctx_t, C.POINTER(State)]
@@ -168,7 +184,7 @@ _lib.dsmc_surface_sampling.argtypes = [ctx_t, C.c_int32]
 _lib.dsmc_instant_sampling.argtypes = [ctx_t, C.c_int32]
 _lib.dsmc_get_surface.argtypes = [ctx_t, P, P, C.POINTER(C.c_int64)]
 for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_rot_sums",
-           "dsmc_rot_sample", "dsmc_get_state",
+           "dsmc_rot_sample", "dsmc_mesh_decompose", "dsmc_sample_cells", "dsmc_get_state",
            "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
            "dsmc_profile", "dsmc_philox", "dsmc_device_copy", "dig_couple", "dig_get", "dig_residual",
            "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
@@ -179,7 +195,7 @@ for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_ge
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_rot_sums",
-            "dsmc_rot_sample", "dsmc_get_state",
+            "dsmc_rot_sample", "dsmc_mesh_decompose", "dsmc_mesh_error", "dsmc_sample_cells", "dsmc_get_state",
             "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
             "dsmc_profile", "dsmc_profile_read", "dsmc_profile_name", "dsmc_philox", "dsmc_device_copy",
             "dsmc_last_error", "dsmc_destroy", "dig_couple", "dig_get", "dig_residual", "dig_solve",
@@ -203,6 +219,38 @@ def _p(a):
 def _check(status, ctx=None):
     if status != 0:
         raise DsmcError(status, _lib.dsmc_last_error(ctx).decode())
+
+
+def decompose(xyz, cells, bfaces, bgroup, bpartner=None):
+    """Tetrahedral mesh of a mixed-element mesh (dsmc_mesh_decompose):
+    cells and bfaces are vertex-index lists (4/5/6/8 and 3/4 entries).
+    Returns a dict of xyz, tets, tet_cell, bfaces, bgroup, bpartner,
+    bparent."""
+    xyz = np.ascontiguousarray(xyz, np.float64)
+    cnv = np.array([len(c) for c in cells], np.int32)
+    cv = np.ascontiguousarray(np.concatenate([np.asarray(c, np.int32) for c in cells]) if cells else
+                              np.zeros(0, np.int32))
+    bnv = np.array([len(f) for f in bfaces], np.int32)
+    bv = np.ascontiguousarray(np.concatenate([np.asarray(f, np.int32) for f in bfaces]) if bfaces else
+                              np.zeros(0, np.int32))
+    bg = np.ascontiguousarray(bgroup, np.int32)
+    bp = None if bpartner is None else np.ascontiguousarray(bpartner, np.int32)
+    d = MixedMeshDesc(len(xyz), _p(xyz), len(cells), _p(cnv), _p(cv), len(bfaces), _p(bnv), _p(bv), _p(bg), _p(bp))
+    o = TetMeshOut()
+    st = _lib.dsmc_mesh_decompose(C.byref(d), C.byref(o))
+    if st != 0:
+        raise DsmcError(st, _lib.dsmc_mesh_error().decode())
+    out = dict(xyz=np.zeros((o.n_vertices, 3)), tets=np.zeros((o.n_tets, 4), np.int32),
+               tet_cell=np.zeros(o.n_tets, np.int32), bfaces=np.zeros((o.n_bfaces, 3), np.int32),
+               bgroup=np.zeros(o.n_bfaces, np.int32), bpartner=np.zeros(o.n_bfaces, np.int32),
+               bparent=np.zeros(o.n_bfaces, np.int32))
+    o.xyz, o.tet_vtx, o.tet_cell = _p(out["xyz"]), _p(out["tets"]), _p(out["tet_cell"])
+    o.bface_vtx, o.bface_group = _p(out["bfaces"]), _p(out["bgroup"])
+    o.bface_partner, o.bface_parent = _p(out["bpartner"]), _p(out["bparent"])
+    st = _lib.dsmc_mesh_decompose(C.byref(d), C.byref(o))
+    if st != 0:
+        raise DsmcError(st, _lib.dsmc_mesh_error().decode())
+    return out
 
 
 def philox(ctr, key):
@@ -368,6 +416,13 @@ class Simulation:
         """Rotational temperature and heat flux [n_tets][4] (T_r, q_r)."""
         out = np.zeros((self.nt, 4))
         self._c(_lib.dsmc_rot_sample(self.ctx, which, _p(out)))
+        return out
+
+    def sample_cells(self, tet_cell, n_cells, which=SAMPLE_STEADY):
+        """Fields [n_cells][15] of the cells of a mixed mesh (dsmc_sample_cells)."""
+        tc = np.ascontiguousarray(tet_cell, np.int32)
+        out = np.zeros((n_cells, 15))
+        self._c(_lib.dsmc_sample_cells(self.ctx, which, int(n_cells), _p(tc), _p(out)))
         return out
 
     def state(self, particles=True):

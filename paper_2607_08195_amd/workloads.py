@@ -215,6 +215,124 @@ def _grid_keys(ijk, ax, n, to_lo=False):
 
 
 # ---------------------------------------------------------------------------
+# Mixed-element box
+# ---------------------------------------------------------------------------
+@dataclass
+class MixedMesh:
+    """Mesh of tetrahedra, pyramids, prisms and hexahedra (vertex lists in
+    the local orders of include/dsmc.h) with boundary triangles and
+    quadrilaterals."""
+    xyz: np.ndarray             # [nv,3]
+    cells: list                 # vertex-index lists of 4, 5, 6 or 8
+    bfaces: list                # vertex-index lists of 3 or 4 (cyclic)
+    bgroup: np.ndarray          # [nb]
+    kind: np.ndarray            # [n_cells] 4, 5, 6, 8
+    h: float = 0.0
+
+
+def _default_kinds(i, j, k, n):
+    """Layer of prisms at the bottom (z), then hexahedra, pyramids and
+    tetrahedra side by side in x."""
+    nx, ny, nz = n
+    if k < max(1, nz // 4):
+        return "prism"
+    if i < nx // 3:
+        return "hex"
+    if i < (2 * nx) // 3:
+        return "pyr"
+    return "tet"
+
+
+def mixed_box(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), jitter=0.0, seed=0, kinds=None):
+    """Box [lo,hi] on an nx*ny*nz grid of hexahedral blocks, each block one
+    hexahedron, two prisms (split by the vertical plane through its
+    (i,j)-(i+1,j+1) diagonal), six pyramids around a vertex at its centre,
+    or the six Kuhn tetrahedra, chosen by kinds(i, j, k, (nx, ny, nz)).
+    Boundary faces are the cells' faces on the box sides, grouped 0 x-,
+    1 x+, 2 y-, 3 y+, 4 z-, 5 z+.  ``jitter`` moves interior grid vertices
+    by uniform +-jitter*h per coordinate (box-face vertices tangentially)."""
+    kinds = kinds or _default_kinds
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    n = np.array([nx, ny, nz])
+    hv = (hi - lo) / n
+    vid = lambda i, j, k: (i * (ny + 1) + j) * (nz + 1) + k
+    gi = [np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1)]
+    I, J, K = np.meshgrid(*gi, indexing="ij")
+    idx = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1)
+    xyz = lo + idx * hv
+    for ax in range(3):
+        xyz[idx[:, ax] == n[ax], ax] = hi[ax]
+    if jitter > 0:
+        rng = np.random.default_rng(seed)
+        on_face = (idx == 0) | (idx == n)
+        movable = on_face.sum(axis=1) <= 1
+        disp = rng.uniform(-jitter, jitter, size=xyz.shape) * hv
+        disp[on_face] = 0.0
+        disp[~movable] = 0.0
+        xyz = xyz + disp
+    pts = [p for p in xyz]
+    cells, kind = [], []
+    tri_faces = []   # candidate boundary faces of every cell (vertex lists)
+
+    def add(v, faces):
+        cells.append(v)
+        kind.append(len(v))
+        tri_faces.extend(faces)
+
+    for i in range(nx):
+        for j in range(ny):
+            for k in range(nz):
+                c = [vid(i, j, k), vid(i + 1, j, k), vid(i + 1, j + 1, k), vid(i, j + 1, k),
+                     vid(i, j, k + 1), vid(i + 1, j, k + 1), vid(i + 1, j + 1, k + 1), vid(i, j + 1, k + 1)]
+                quads = [[c[0], c[1], c[2], c[3]], [c[4], c[5], c[6], c[7]], [c[0], c[1], c[5], c[4]],
+                         [c[1], c[2], c[6], c[5]], [c[2], c[3], c[7], c[6]], [c[3], c[0], c[4], c[7]]]
+                t = kinds(i, j, k, (nx, ny, nz))
+                if t == "hex":
+                    add(c, quads)
+                elif t == "prism":
+                    a = [c[0], c[1], c[2], c[4], c[5], c[6]]
+                    b = [c[0], c[2], c[3], c[4], c[6], c[7]]
+                    add(a, [[a[0], a[1], a[2]], [a[3], a[4], a[5]], [a[0], a[1], a[4], a[3]],
+                            [a[1], a[2], a[5], a[4]]])
+                    add(b, [[b[0], b[1], b[2]], [b[3], b[4], b[5]], [b[1], b[2], b[5], b[4]],
+                            [b[2], b[0], b[3], b[5]]])
+                elif t == "pyr":
+                    ctr = len(pts)
+                    pts.append(np.mean(xyz[c], axis=0))
+                    for q in quads:
+                        add(q + [ctr], [q])
+                elif t == "tet":
+                    base = np.array([i, j, k])
+                    for perm in itertools.permutations(range(3)):
+                        p = base.copy()
+                        v = [vid(*p)]
+                        for ax in perm:
+                            p = p.copy()
+                            p[ax] += 1
+                            v.append(vid(*p))
+                        add(v, [[v[1], v[2], v[3]], [v[0], v[2], v[3]], [v[0], v[1], v[3]], [v[0], v[1], v[2]]])
+                else:
+                    raise ValueError(t)
+    P = np.array(pts)
+    tol = 1e-9 * float((hi - lo).max())
+    bfaces, bgroup, seen = [], [], set()
+    for f in tri_faces:
+        q = P[f]
+        for ax in range(3):
+            for side, val in ((0, lo[ax]), (1, hi[ax])):
+                if np.all(np.abs(q[:, ax] - val) < tol):
+                    key = tuple(sorted(f))
+                    if key not in seen:
+                        seen.add(key)
+                        bfaces.append(list(f))
+                        bgroup.append(2 * ax + side)
+    return MixedMesh(xyz=np.ascontiguousarray(P), cells=cells, bfaces=bfaces,
+                     bgroup=np.array(bgroup, dtype=np.int32), kind=np.array(kind, dtype=np.int32),
+                     h=float(hv.min()))
+
+
+# ---------------------------------------------------------------------------
 # Reference scales
 # ---------------------------------------------------------------------------
 def n0_from_kn(sp: Species, Kn, T0, L0=1.0):
@@ -241,17 +359,29 @@ def cavity(n_hex=6, Kn=1.0, ppc=20, jitter=0.0, lid_speed=50.0, T0=273.0, seed=0
     The gas is VHS argon unless `species` is given."""
     sp = Species() if species is None else species
     mesh = kuhn_box(n_hex, n_hex, n_hex, jitter=jitter, seed=mesh_seed)
+    name = f"cavity_{n_hex}^3x6_Kn{Kn:g}" + ("" if sp.alpha == 1.0 else f"_vss{sp.alpha:g}")
+    wl = cavity_on_mesh(mesh, Kn=Kn, ppc=ppc, lid_speed=lid_speed, T0=T0, seed=seed, vel_fp32=vel_fp32,
+                        steps=steps, n_ss=n_ss, ewma_on=ewma_on, n_a=n_a, species=sp, name=name)
+    wl.info.update(n_hex=n_hex, jitter=jitter)
+    return wl
+
+
+def cavity_on_mesh(mesh, Kn=1.0, ppc=20, lid_speed=50.0, T0=273.0, seed=0, vel_fp32=1, steps=500, n_ss=200,
+                   ewma_on=0, n_a=1000, species=None, n_cells=None, name="cavity"):
+    """The lid-driven cavity of `cavity` on a given tetrahedral mesh of the
+    unit cube (boundary groups 0 x-, 1 x+, 2 y-, 3 y+ (the lid), 4 z-,
+    5 z+), ppc particles per cell on average over n_cells cells (default:
+    the tetrahedra)."""
+    sp = Species() if species is None else species
     n0 = n0_from_kn(sp, Kn, T0)
     dt = 0.2 * tau_from_kn(sp, Kn, T0)
-    F_N = n0 * 1.0 / (ppc * mesh.n_tets)
+    F_N = n0 * 1.0 / (ppc * (mesh.n_tets if n_cells is None else n_cells))
     bcs = [Boundary(BC_DIFFUSE, T0)] * 6
     bcs = list(bcs)
     bcs[3] = Boundary(BC_DIFFUSE, T0, (lid_speed, 0.0, 0.0))
     run = Run(n0=n0, T0=T0, u0=(0.0, 0.0, 0.0), F_N=F_N, dt=dt, seed=seed, vel_fp32=vel_fp32,
               n_ss=n_ss, n_a=n_a, ewma_on=ewma_on)
-    name = f"cavity_{n_hex}^3x6_Kn{Kn:g}" + ("" if sp.alpha == 1.0 else f"_vss{sp.alpha:g}")
-    return Workload(name, mesh, sp, bcs, run, steps,
-                    dict(Kn=Kn, n_hex=n_hex, ppc=ppc, lid_speed=lid_speed, jitter=jitter))
+    return Workload(name, mesh, sp, bcs, run, steps, dict(Kn=Kn, ppc=ppc, lid_speed=lid_speed))
 
 
 def cavity_large_vss(steps=20000, n_ss=10000):

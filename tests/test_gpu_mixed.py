@@ -1,0 +1,95 @@
+"""Mixed-element meshes on the GPU (section 5.4: tetrahedral, pyramid, prism
+and hexahedral cells): the library decomposes the mesh
+(dsmc_mesh_decompose), the oracle decomposes it on its own, and both run
+the lid-driven cavity on the result.
+
+From the oracle's state after a few steps, three steps on both sides:
+bit-exact cells, (cell, pid) order and pair counts, positions within 1e-12,
+velocities within 1 float32 ulp (FP32) or 1e-12 relative (FP64), sums
+within 1e-12 of the column scale (the single-step criteria of the
+tetrahedral parity tests); the fields of the original cells from
+dsmc_sample_cells within 1e-10 of the oracle's, from the same sums.
+"""
+import numpy as np
+import pytest
+
+from paper_2607_08195_amd import workloads as W
+from oracle import Oracle
+import oracle.mixed as OM
+from parity_util import compare_particles, compare_sums
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_08195_amd import dsmc
+    return dsmc
+
+
+def _workloads(D, n=(6, 5, 6), jitter=0.1, vel_fp32=0, Kn=0.5, ppc=20, seed=4):
+    m = W.mixed_box(*n, jitter=jitter, seed=seed)
+    g = D.decompose(m.xyz, m.cells, m.bfaces, m.bgroup)
+    xyz, tets, tc, bf, bg, bp, bpar = OM.decompose(m.xyz, m.cells, m.bfaces, m.bgroup)
+    mk = lambda mesh: W.cavity_on_mesh(mesh, Kn=Kn, ppc=ppc, vel_fp32=vel_fp32, n_ss=0, n_cells=len(m.cells),
+                                       lid_speed=120.0, name="mixed_cavity")
+    wg = mk(W.Mesh(xyz=g["xyz"], tets=g["tets"], bfaces=g["bfaces"], bgroup=g["bgroup"], bpartner=None, h=m.h))
+    wo = mk(W.Mesh(xyz=xyz, tets=tets, bfaces=bf, bgroup=bg, bpartner=None, h=m.h))
+    return m, g, wg, wo, tc
+
+
+@pytest.mark.parametrize("vel_fp32", [0, 1])
+def test_mixed_cavity_parity(D, vel_fp32):
+    m, g, wg, wo, tc = _workloads(D, vel_fp32=vel_fp32)
+    assert np.array_equal(g["tet_cell"], tc)
+    pre = 5
+    wo.run.n_ss = pre
+    wg.run.n_ss = pre
+    o = Oracle(wo)
+    o.step(pre)
+    st = o.particles()
+    sim = D.Simulation(wg, fill=False, capacity=max(4 * o.np, 100000))
+    sim.set_state(st["x"], st["v"], st["cell"], st["pid"], o.step_index, o.next_pid, o.smax())
+    for k in range(3):
+        o.step(1)
+        sim.step(1)
+    gs, os_ = sim.state(), o.particles()
+    compare_particles(gs, os_, vel_fp32, ctx=f"mixed fp32={vel_fp32}")
+    gc, ga = sim.pair_counts()
+    oc, oa = o.pair_counts()
+    assert np.array_equal(gc, oc) and np.array_equal(ga, oa)
+    gsum, ns = sim.sums(D.SAMPLE_STEADY)
+    assert ns == o.n_steady == 3
+    compare_sums(gsum, o.sums(0))
+    gf = sim.sample_cells(g["tet_cell"], len(m.cells), D.SAMPLE_STEADY)
+    of = OM.cell_fields(o, tc, len(m.cells), which=0)
+    assert np.array_equal(np.isnan(gf), np.isnan(of))
+    scale = np.nanmax(np.abs(of), axis=0, keepdims=True)
+    assert np.all(np.nan_to_num(np.abs(gf - of)) <= 1e-10 * scale)
+    c0 = o.counters()
+    assert c0["lost"] == 0
+    sim.close()
+
+
+def test_mixed_cavity_fill_and_long_run(D):
+    """The library's own fill and 200 graph-replayed steps on the mixed
+    mesh: no particle lost, the cell fields at the fill density and
+    temperature on average, and the original cells' tetrahedra all sampled."""
+    import torch
+    m, g, wg, wo, tc = _workloads(D, n=(8, 8, 8), vel_fp32=1, ppc=30)
+    sim = D.Simulation(wg, stream=torch.cuda.Stream())
+    sim.graph_step(200)
+    st = sim.stats()
+    assert st["lost"] == 0
+    f = sim.sample_cells(g["tet_cell"], len(m.cells), D.SAMPLE_STEADY)
+    assert not np.isnan(f).any()
+    cv = np.bincount(g["tet_cell"], weights=Oracle(wo, fill=False).volumes(), minlength=len(m.cells))
+    assert abs(np.average(f[:, 0], weights=cv) / wg.run.n0 - 1) < 0.01
+    assert abs(np.average(f[:, 5], weights=cv) / wg.run.T0 - 1) < 0.02
+    # the lid drags the gas along +x near y = 1
+    top = np.array([np.mean(m.xyz[c][:, 1]) > 0.85 for c in m.cells])
+    assert np.average(f[top, 2], weights=cv[top]) > 0.1 * 120.0
+    sim.close()
