@@ -94,9 +94,20 @@ typedef struct {
  * The solution of a solve that did not fail becomes M^k, the state kept for
  * unreached cells and the warm start of the next cycle.  Sets the local
  * accumulation flags of rejected cells.  DSMC_E_CAPACITY if the clones of
- * the feedback would overflow the particle store (state left unchanged);
- * DSMC_E_INVALID for a gas with rotational degrees of freedom (the synthetic
- * equations and their closure are the monatomic ones). */
+ * the feedback would overflow the particle store (state left unchanged).
+ *
+ * A gas with two rotational degrees of freedom (dsmc_species_desc.dof_rot)
+ * couples through the polyatomic equations of section 2.2: the primitives
+ * are rho, u(3), T_t, T_r; the total energy includes e_r = (d_r/2) R T_r
+ * and a sixth equation carries rho e_r with the rotational heat flux and
+ * the relaxation source (d_r/2) rho R (T - T_r) / (Z_r tau), T = (3 T_t +
+ * d_r T_r)/(3 + d_r), tau = mu(T_t)/p_t (eq. macro); the NSF heat fluxes are
+ * -kappa_t grad T_t and -kappa_r grad T_r with (kappa_t, kappa_r) = (mu R /
+ * 2) A^{-1} (5, d_r) (eq. thermal_conductivity_matrix, A from the species);
+ * the HoT include q_r; the solve's convergence norm adds the
+ * rotational-energy residual divided by R T0 to the density residual; the
+ * feedback scales each particle's I_r by T_r^{k+1}/T_r^{k+1/2}.  The
+ * learned closure and params->accel are refused for it (DSMC_E_INVALID). */
 dsmc_status dig_couple(dsmc_ctx ctx, const dig_params* params, dig_report* report);
 
 /* Batch contexts (dsmc_batch_init): one call couples every enabled case at
@@ -112,14 +123,17 @@ dsmc_status dig_couple(dsmc_ctx ctx, const dig_params* params, dig_report* repor
  * batch totals.  All cases are enabled until dig_batch_enable says
  * otherwise. */
 
-/* Per-cell arrays of the last dig_couple, in caller cell order:
- *  DIG_OUT_SAMPLED [n][14] rho, u(3), T, sigma(6), q(3) of the moving average (NaN: no samples)
- *  DIG_OUT_HALF    [n][5]  M^{k+1/2} after the gate and reconstruction
- *  DIG_OUT_NEW     [n][5]  M^{k+1} from the macroscopic solve
+/* Per-cell arrays of the last dig_couple, in caller cell order (widths of a
+ * rotating gas in brackets):
+ *  DIG_OUT_SAMPLED [n][14] rho, u(3), T, sigma(6), q(3) of the moving average
+ *                          ([n][18]: then T_r, q_r(3)); NaN: no samples
+ *  DIG_OUT_HALF    [n][5]  M^{k+1/2} after the gate and reconstruction ([n][6]: rho, u, T_t, T_r)
+ *  DIG_OUT_NEW     [n][5]  M^{k+1} from the macroscopic solve ([n][6])
  *  DIG_OUT_HOT     [n][9]  frozen HoT (sigma xx,yy,zz,xy,xz,yz; q) after reconstruction
+ *                          ([n][12]: sigma, q_t, q_r)
  *  DIG_OUT_KN      [n]     Kn_Delta of the sampled state (inf: no samples)
  *  DIG_OUT_STATE   [n]     int32: 0 admissible, 1 reconstructed, 2 unreached
- *  DIG_OUT_MPREV   [n][5]  the state M^k kept for unreached cells */
+ *  DIG_OUT_MPREV   [n][5]  the state M^k kept for unreached cells ([n][6]) */
 enum {
     DIG_OUT_SAMPLED = 0, DIG_OUT_HALF = 1, DIG_OUT_NEW = 2, DIG_OUT_HOT = 3,
     DIG_OUT_KN = 4, DIG_OUT_STATE = 5, DIG_OUT_MPREV = 6
@@ -128,18 +142,21 @@ dsmc_status dig_get(dsmc_ctx ctx, int32_t which, void* out);
 
 /* Residual of the discrete macroscopic equations (eq. macro with frozen
  * HoT) at prim[n][5] = rho, u(3), T: out[n][5] = sum over the cell's faces
- * of the numerical flux times the face area (mass, momentum, energy). */
+ * of the numerical flux times the face area (mass, momentum, energy); a
+ * rotating gas: prim[n][6] = rho, u(3), T_t, T_r, hot[n][12], out[n][6]
+ * with rho e_r last, less the cell volume times its relaxation source. */
 dsmc_status dig_residual(dsmc_ctx ctx, const double* prim, const double* hot, double* out);
 
-/* Macroscopic solve alone from prim[n][5] (in/out) with frozen hot[n][9];
- * uses n_m, eps_m, cfl and global_dt of params. */
+/* Macroscopic solve alone from prim[n][5] (in/out) with frozen hot[n][9]
+ * (rotating gas: [n][6] and [n][12]); uses n_m, eps_m, cfl, global_dt and
+ * accel of params. */
 dsmc_status dig_solve(dsmc_ctx ctx, double* prim, const double* hot, const dig_params* params,
                       dig_report* report);
 
 /* Particle feedback alone: from prim_old[n][5] to prim_new[n][5] on cells
- * with state[n] <= 1; re-sorts.  It changes the translational velocities
- * only; a clone takes the rotational energy of the particle it copies.
- * DSMC_E_CAPACITY as for dig_couple. */
+ * with state[n] <= 1; re-sorts.  A rotating gas takes [n][6] and scales
+ * the rotational energies by the ratio of T_r; a clone takes the rotational
+ * energy of the particle it copies.  DSMC_E_CAPACITY as for dig_couple. */
 dsmc_status dig_feedback(dsmc_ctx ctx, const double* prim_old, const double* prim_new, const int32_t* state,
                          int64_t* np_after);
 
@@ -155,6 +172,10 @@ dsmc_status dig_batch_enable(dsmc_ctx ctx, const int32_t* enabled);
  * NULL to keep the current ones) are the per-cell numbers of samples taken,
  * which set its weights. */
 dsmc_status dsmc_set_sums(dsmc_ctx ctx, int32_t which, const double* sums, const int32_t* counts);
+
+/* The same for the rotational sums of a rotating gas: sums[n][4] (layout
+ * of dsmc_get_rot_sums).  DSMC_E_INVALID for a monatomic gas. */
+dsmc_status dsmc_set_rot_sums(dsmc_ctx ctx, int32_t which, const double* sums);
 
 #ifdef __cplusplus
 }

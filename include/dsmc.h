@@ -91,8 +91,13 @@ typedef struct {
  * direction.  dof_rot = 0 (monatomic) leaves all of this out.  Other values,
  * or z_rot <= 0 with dof_rot = 2, are DSMC_E_INVALID.  A rotating gas runs
  * the parked-wall move schedules (4-7, 12-17), the LDS-ranked collide
- * schedules (1-4) and the scatter or gather sort (0, 1); the coupling step
- * (dig.h) and surface sampling do not take its rotation into account. */
+ * schedules (1-4) and the scatter, gather or deferred sort (0, 1, 3); the
+ * coupling step (dig.h) solves the polyatomic synthetic equations for it,
+ * with the heat conductivities from heat_relax = (A_tt, A_tr, A_rt, A_rr),
+ * the relaxation matrix of eq. thermal_conductivity_matrix (all zero:
+ * nitrogen's 0.786, -0.201, -0.059, 0.842; a singular matrix is
+ * DSMC_E_INVALID); surface sampling does not take the rotation into
+ * account. */
 typedef struct {
     double mass;     /* kg */
     double d_ref;    /* reference diameter, m */
@@ -101,6 +106,7 @@ typedef struct {
     double alpha;    /* VSS scattering exponent; 1 = VHS */
     int32_t dof_rot; /* rotational degrees of freedom: 0 or 2 */
     double z_rot;    /* rotational collision number (dof_rot = 2) */
+    double heat_relax[4]; /* heat-flux relaxation matrix A (dof_rot = 2), row-major */
 } dsmc_species_desc;
 
 typedef enum {

@@ -76,6 +76,7 @@ def _load():
     for name in ["oracle_dig_sampled", "oracle_get_mprev"]:
         getattr(lib, name).argtypes = [P, P]
     lib.oracle_dig_gradients.argtypes = [P, P, P]
+    lib.oracle_set_heat_relaxation.argtypes = [P, P]
     lib.oracle_dig_nsf.argtypes = [P, P, P, P]
     lib.oracle_dig_kn_cell.argtypes = [P, P, d, P]
     lib.oracle_dig_gate.argtypes = [P, P, P, P, d, i, P]
@@ -162,6 +163,13 @@ class Oracle:
         self.dr = int(getattr(sp, "dof_rot", 0))
         if lib.oracle_set_rotation(self.h, self.dr, float(getattr(sp, "z_rot", 0.0))) != 0:
             raise ValueError("oracle_set_rotation: " + lib.oracle_last_error().decode())
+        if self.dr and getattr(sp, "a_heat", None) is not None:
+            a = np.ascontiguousarray(sp.a_heat, np.float64)
+            if lib.oracle_set_heat_relaxation(self.h, _p(a)) != 0:
+                raise ValueError("oracle_set_heat_relaxation: singular matrix")
+        # widths of the coupling arrays: primitives, HoT, sampled state, gradients
+        self.nv, self.nh = (6, 12) if self.dr else (5, 9)
+        self.nsw, self.ngw = (18, 15) if self.dr else (14, 12)
         self.wl = wl
         if fill:
             u0 = np.asarray(run.u0, dtype=np.float64)
@@ -325,19 +333,19 @@ class Oracle:
         self.lib.oracle_set_reference(self.h, n0, T0, _p(u))
 
     def dig_sampled(self):
-        o = np.zeros((self.nt, 14))
+        o = np.zeros((self.nt, self.nsw))
         self.lib.oracle_dig_sampled(self.h, _p(o))
         return o
 
     def dig_gradients(self, prim):
         prim = np.ascontiguousarray(prim, np.float64)
-        o = np.zeros((self.nt, 12))
+        o = np.zeros((self.nt, self.ngw))
         self.lib.oracle_dig_gradients(self.h, _p(prim), _p(o))
         return o
 
     def dig_nsf(self, prim, grad):
         prim = np.ascontiguousarray(prim, np.float64); grad = np.ascontiguousarray(grad, np.float64)
-        o = np.zeros((self.nt, 9))
+        o = np.zeros((self.nt, self.nh))
         self.lib.oracle_dig_nsf(self.h, _p(prim), _p(grad), _p(o))
         return o
 
@@ -363,19 +371,19 @@ class Oracle:
 
     def dig_face_hot(self, prim, hot, consistent=1):
         prim = np.ascontiguousarray(prim, np.float64); hot = np.ascontiguousarray(hot, np.float64)
-        o = np.zeros((self.nt, 4, 9))
+        o = np.zeros((self.nt, 4, self.nh))
         self.lib.oracle_dig_face_hot(self.h, _p(prim), _p(hot), consistent, _p(o))
         return o
 
     def dig_residual_faces(self, prim, hotf):
         prim = np.ascontiguousarray(prim, np.float64); hotf = np.ascontiguousarray(hotf, np.float64)
-        o = np.zeros((self.nt, 5))
+        o = np.zeros((self.nt, self.nv))
         self.lib.oracle_dig_residual_faces(self.h, _p(prim), _p(hotf), _p(o))
         return o
 
     def dig_residual(self, prim, hot):
         prim = np.ascontiguousarray(prim, np.float64); hot = np.ascontiguousarray(hot, np.float64)
-        o = np.zeros((self.nt, 5))
+        o = np.zeros((self.nt, self.nv))
         self.lib.oracle_dig_residual(self.h, _p(prim), _p(hot), _p(o))
         return o
 
@@ -391,6 +399,6 @@ class Oracle:
         return _report_dict(rep)
 
     def mprev(self):
-        o = np.zeros((self.nt, 5))
+        o = np.zeros((self.nt, self.nv))
         self.lib.oracle_get_mprev(self.h, _p(o))
         return o

@@ -942,6 +942,8 @@ int oracle_set_rotation(osim* s, int dr, double zr) {
     s->zr = zr;
     double a = s->alpha, w = s->omega;
     s->pinel = dr ? ((a * (5.0 - 2.0 * w)) * (7.0 - 2.0 * w)) / ((((5.0 * (a + 1.0)) * (a + 2.0))) * zr) : 0.0;
+    /* nitrogen's heat-flux relaxation matrix until set otherwise */
+    s->a_heat[0] = 0.786; s->a_heat[1] = -0.201; s->a_heat[2] = -0.059; s->a_heat[3] = 0.842;
     if (dr) {
         size_t ntz = (size_t)s->nt;
         s->ir = (double*)realloc(s->ir, sizeof(double) * (size_t)(s->cap ? s->cap : 1));

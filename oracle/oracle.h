@@ -145,13 +145,23 @@ typedef struct {
  * initial macroscopic state; set by oracle_init_fill or explicitly. */
 void oracle_set_reference(osim*, double n0, double T0, const double* u0);
 
+/* A rotating gas (d_r = 2) couples through the polyatomic equations of
+ * section 2.2: primitives [nt][6] = rho, u(3), T_t, T_r; HoT [nt][12] =
+ * sigma(6), q_t(3), q_r(3); the heat conductivities from the relaxation
+ * matrix A (eq. thermal_conductivity_matrix), set here (A_tt, A_tr, A_rt,
+ * A_rr; the default is the nitrogen matrix 0.786, -0.201, -0.059, 0.842).
+ * The arrays below are [nt][5] and [nt][9] for a monatomic gas. */
+int oracle_set_heat_relaxation(osim*, const double* a);
+
 /* Sampled macroscopic state of every cell from the moving-average sums:
- * out[nt][14] = rho, u(3), T, sigma(6), q(3); NaN for cells without samples. */
+ * out[nt][14] = rho, u(3), T, sigma(6), q(3) (rotating gas: [nt][18], then
+ * T_r, q_r(3)); NaN for cells without samples. */
 void oracle_dig_sampled(osim*, double* out);
-/* Least-squares gradients of u and T: grad[nt][12] = du_i/dx_j (row-major), dT/dx_j,
- * from prim[nt][5] = rho, u(3), T. */
+/* Least-squares gradients of u and T: grad[nt][12] = du_i/dx_j (row-major),
+ * dT/dx_j (rotating gas: [nt][15], then dT_r/dx_j), from the primitives. */
 void oracle_dig_gradients(osim*, const double* prim, double* grad);
-/* NSF stress and heat flux from prim and its gradients: out[nt][9]. */
+/* NSF stress and heat flux from prim and its gradients: out[nt][9] (rotating
+ * gas: [nt][12], sigma, q_t, q_r). */
 void oracle_dig_nsf(osim*, const double* prim, const double* grad, double* out);
 /* Cell Knudsen number Kn_Delta for prim: out[nt]. */
 void oracle_dig_kn_cell(osim*, const double* prim, double L0, double* out);

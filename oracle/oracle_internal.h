@@ -70,7 +70,9 @@ struct osim {
     double* fnu;    /* [nt][4][3] outward unit normals */
     double* farea;  /* [nt][4] face areas */
     double* lsq;    /* [nt][9] inverse least-squares matrix (zero when singular) */
-    double* mprev;  /* [nt][5] rho, u(3), T of the last macroscopic solution */
+    double* mprev;  /* [nt][5] rho, u(3), T (monatomic) or [nt][6] rho, u(3), T_t, T_r
+                       of the last macroscopic solution */
+    double a_heat[4]; /* heat-flux relaxation coefficients A_tt, A_tr, A_rt, A_rr */
     int dig_ready;
 };
 

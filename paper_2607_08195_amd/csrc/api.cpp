@@ -520,6 +520,17 @@ dsmc_status init_impl(dsmc_ctx* out, const dsmc_mesh_desc* mesh, const dsmc_spec
     c->alpha = sp->alpha;
     c->dr = sp->dof_rot;
     c->zr = sp->z_rot;
+    if (c->dr) {
+        const double* a = sp->heat_relax;
+        const bool zero = a[0] == 0.0 && a[1] == 0.0 && a[2] == 0.0 && a[3] == 0.0;
+        const double dflt[4] = {0.786, -0.201, -0.059, 0.842};
+        for (int k = 0; k < 4; ++k) c->a_heat[k] = zero ? dflt[k] : a[k];
+        const double det = c->a_heat[0] * c->a_heat[3] - c->a_heat[1] * c->a_heat[2];
+        if (!(std::isfinite(det) && det != 0.0)) {
+            delete c;
+            return fail(nullptr, DSMC_E_INVALID, "singular heat-flux relaxation matrix");
+        }
+    }
     {
         const double a = sp->alpha, w = sp->omega;
         c->pinel = c->dr ? ((a * (5.0 - 2.0 * w)) * (7.0 - 2.0 * w)) / ((((5.0 * (a + 1.0)) * (a + 2.0))) * c->zr)

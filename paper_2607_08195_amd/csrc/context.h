@@ -46,6 +46,7 @@ struct dsmc_ctx_s {
     double alpha = 1;   // VSS scattering exponent (1: VHS)
     int dr = 0;         // rotational degrees of freedom (0 or 2)
     double zr = 0, pinel = 0;  // rotational collision number, inelastic probability
+    double a_heat[4] = {0, 0, 0, 0};  // heat-flux relaxation matrix of a rotating gas
     double* d_racc = nullptr;   // [4][nt] rotational sums (steady), when dr > 0
     double* d_rewma = nullptr;  // [4][nt] moving average of the rotational sums
     double* d_rinst = nullptr;  // [4][nt] rotational sums of the last step

@@ -10,7 +10,10 @@
 
 namespace dsmcx {
 
-constexpr int kDigNV = 5;        // primitive variables: rho, u(3), T
+constexpr int kDigNV = 5;        // primitive variables of a monatomic gas: rho, u(3), T
+// A gas with rotational degrees of freedom carries rho, u(3), T_t, T_r (6
+// primitives), sigma(6), q_t(3), q_r(3) (12 HoT) and 18 sampled values.
+constexpr int kDigNVR = 6;
 constexpr int kDigThreads = 256;
 constexpr int kFbLanes = 64;     // one wave per cell in the feedback kernel
 
@@ -55,6 +58,13 @@ struct DigGeom {
     DigCase* cases;            // batch: per-case parameters
     int n_cases;
     int skip_idle;             // batch: the solve leaves out the cells of cases not coupled
+    // rotating gas (dr = 2): rotational collision number, heat-flux
+    // relaxation matrix (A_tt, A_tr, A_rt, A_rr) and R T0, the scale of the
+    // rotational-energy residual in the convergence norm (per case in a batch)
+    int dr;
+    double zr;
+    double a_heat[4];
+    double ert;
 };
 
 struct DigCtl {
@@ -65,25 +75,28 @@ struct DigCtl {
     double mass_scale;
 };
 
+// Arrays below are per cell with NV = 5 primitives and NH = 9 HoT for a
+// monatomic gas, NV = 6 and NH = 12 for a rotating one.
 struct DigWork {
-    double* samp;     // [nt][14] rho, u(3), T, sigma(6), q(3) of the moving average; NaN without samples
+    double* samp;     // [nt][14] rho, u(3), T, sigma(6), q(3) of the moving average (rotating: [nt][18],
+                      // then T_r, q_r(3)); NaN without samples
     uint8_t* ok;      // [nt] cell has samples
-    double* prim;     // [nt][5] working state; M^{k+1} after the solve
-    double* half;     // [nt][5] M^{k+1/2} after the gate
-    double* hot;      // [nt][9] cell HoT
-    double* hotf;     // [nt][4][9] HoT carried by each cell face (the solve's closure)
-    double* grad;     // [nt][5][3] gradients of the primitives
+    double* prim;     // [nt][NV] working state; M^{k+1} after the solve
+    double* half;     // [nt][NV] M^{k+1/2} after the gate
+    double* hot;      // [nt][NH] cell HoT
+    double* hotf;     // [nt][4][NH] HoT carried by each cell face (the solve's closure)
+    double* grad;     // [nt][NV][3] gradients of the primitives
     double* kn;       // [nt]
     uint8_t* avail;   // [nt]
     uint8_t* navail;  // [nt]
-    double* nprim;    // [nt][5] reconstruction candidates of one pass
-    double* nhot;     // [nt][9]
+    double* nprim;    // [nt][NV] reconstruction candidates of one pass
+    double* nhot;     // [nt][NH]
     int32_t* state;   // [nt] 0 admissible, 1 reconstructed, 2 unreached
-    double* mprev;    // [nt][5] M^k
-    double* Rs;       // [nt][5] residual
+    double* mprev;    // [nt][NV] M^k
+    double* Rs;       // [nt][NV] residual
     double* dt;       // [nt] pseudo-time step
-    double* U0;       // [nt][5] conserved state at the start of an iteration
-    double* stage;    // [nt][5] stage state
+    double* U0;       // [nt][NV] conserved state at the start of an iteration
+    double* stage;    // [nt][NV] stage state
     double* partial;  // [2 * blocks] reduction partials (blocks of the residual kernel: 4 lanes per cell)
     DigCtl* ctl;
     int32_t* fb_cnt;  // [nt] clones per cell, caller order
@@ -96,7 +109,8 @@ struct DigWork {
     uint8_t* cvalid;  // [nt]
 };
 
-void launch_dig_sampled(hipStream_t s, const DigGeom& g, const double* ewma, double FN, DigWork w);
+// rewma [4][nt]: the rotational moving-average sums of a rotating gas (else null)
+void launch_dig_sampled(hipStream_t s, const DigGeom& g, const double* ewma, const double* rewma, double FN, DigWork w);
 void launch_dig_kn(hipStream_t s, const DigGeom& g, DigWork w, double kn_ref, double T0, double rho0, double L0);
 void launch_dig_gradients(hipStream_t s, const DigGeom& g, const double* prim, double* grad, const DigCtl* ctl);
 void launch_dig_hot(hipStream_t s, const DigGeom& g, DigWork w);

@@ -23,18 +23,42 @@ namespace {
 constexpr double kGamma = 5.0 / 3.0;
 constexpr double kMachCut = 0.05;
 
+// Per-cell widths: NV primitives (5, or 6 with rotation), NH HoT (9 or 12),
+// NS sampled values (14 or 18).
+template <int NV> struct Widths {
+    static constexpr int NH = NV == 6 ? 12 : 9;
+    static constexpr int NS = NV == 6 ? 18 : 14;
+    static constexpr int NG = 3 * NV;
+};
+
 __device__ __forceinline__ bool stopped(const DigCtl* ctl) { return ctl != nullptr && (ctl->conv | ctl->failed); }
 
 __device__ __forceinline__ double mu_of(const DigGeom& g, double T) { return g.mu_ref * pow(T / g.T_ref, g.omega); }
 __device__ __forceinline__ double kappa_of(const DigGeom& g, double mu) {
     return 15.0 * kBoltzmannDev * mu / (4.0 * g.mass);
 }
+// Translational and rotational conductivities of a rotating gas
+// (eq. thermal_conductivity_matrix): (mu R / 2) A^{-1} (5, d_r).
+__device__ __forceinline__ void kappas_of(const DigGeom& g, double mu, double& kt, double& kr) {
+    const double det = g.a_heat[0] * g.a_heat[3] - g.a_heat[1] * g.a_heat[2];
+    const double f = (mu * g.R) / 2.0;
+    kt = f * ((g.a_heat[3] * 5.0 - g.a_heat[1] * (double)g.dr) / det);
+    kr = f * ((g.a_heat[0] * (double)g.dr - g.a_heat[2] * 5.0) / det);
+}
+// ratio of specific heats of the frozen gas
+template <int NV>
+__device__ __forceinline__ double gamma_of(const DigGeom& g) {
+    if constexpr (NV == 6) return (5.0 + g.dr) / (3.0 + g.dr);
+    return kGamma;
+}
 
 // NSF stress (xx,yy,zz,xy,xz,yz) and Fourier heat flux (eq. nsf_heat_flux)
-// from gu[i][j] = du_i/dx_j and gT at temperature T.
-__device__ void nsf_local(const DigGeom& g, double T, const double* gu, const double* gT, double* out) {
+// from gu[i][j] = du_i/dx_j and gT at temperature T; with rotation the
+// translational and rotational heat fluxes from gT and gTr.
+template <int NV>
+__device__ void nsf_local(const DigGeom& g, double T, const double* gu, const double* gT, const double* gTr,
+                          double* out) {
     const double mu = mu_of(g, T);
-    const double kap = kappa_of(g, mu);
     const double div = gu[0] + gu[4] + gu[8];
     const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
@@ -43,19 +67,38 @@ __device__ void nsf_local(const DigGeom& g, double T, const double* gu, const do
         if (k < 3) e -= (2.0 / 3.0) * div;
         out[k] = -mu * e;
     }
+    if constexpr (NV == 6) {
+        double kt, kr;
+        kappas_of(g, mu, kt, kr);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) out[6 + j] = -kap * gT[j];
+        for (int j = 0; j < 3; ++j) out[6 + j] = -kt * gT[j];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) out[9 + j] = -kr * gTr[j];
+    } else {
+        const double kap = kappa_of(g, mu);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) out[6 + j] = -kap * gT[j];
+    }
 }
 
+template <int NV>
 __device__ __forceinline__ void cons_of(const DigGeom& g, const double* P, double* U) {
     const double uu = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
     U[0] = P[0];
     U[1] = P[0] * P[1];
     U[2] = P[0] * P[2];
     U[3] = P[0] * P[3];
-    U[4] = P[0] * (1.5 * g.R * P[4] + 0.5 * uu);
+    if constexpr (NV == 6) {
+        // total energy with e_r = (d_r/2) R T_r, and rho e_r (eq. energy_definitions)
+        const double er = (0.5 * g.dr) * g.R * P[5];
+        U[4] = P[0] * ((1.5 * g.R * P[4] + 0.5 * uu) + er);
+        U[5] = P[0] * er;
+    } else {
+        U[4] = P[0] * (1.5 * g.R * P[4] + 0.5 * uu);
+    }
 }
 
+template <int NV>
 __device__ __forceinline__ bool prim_of(const DigGeom& g, const double* U, double* P) {
     if (!(U[0] > 0)) return false;
     P[0] = U[0];
@@ -63,29 +106,45 @@ __device__ __forceinline__ bool prim_of(const DigGeom& g, const double* U, doubl
     P[2] = U[2] / U[0];
     P[3] = U[3] / U[0];
     const double uu = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
+    if constexpr (NV == 6) {
+        const double er = U[5] / U[0];
+        P[4] = ((U[4] / U[0] - 0.5 * uu) - er) / (1.5 * g.R);
+        P[5] = er / ((0.5 * g.dr) * g.R);
+        return P[4] > 0 && isfinite(P[4]) && P[5] > 0 && isfinite(P[5]);
+    }
     P[4] = (U[4] / U[0] - 0.5 * uu) / (1.5 * g.R);
     return P[4] > 0 && isfinite(P[4]);
 }
 
-// Inviscid flux F(P).n of the monatomic Euler part of eq. macro.
+// Inviscid flux F(P).n of eq. macro (pressure rho R T_t).
+template <int NV>
 __device__ __forceinline__ void flux_of(const DigGeom& g, const double* P, const double* n, double* F) {
     const double un = P[1] * n[0] + P[2] * n[1] + P[3] * n[2];
     const double p = P[0] * g.R * P[4];
     const double uu = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
-    const double E = 1.5 * g.R * P[4] + 0.5 * uu;
     F[0] = P[0] * un;
 #pragma unroll
     for (int i = 0; i < 3; ++i) F[1 + i] = P[0] * P[1 + i] * un + p * n[i];
-    F[4] = (P[0] * E + p) * un;
+    if constexpr (NV == 6) {
+        const double er = (0.5 * g.dr) * g.R * P[5];
+        const double E = (1.5 * g.R * P[4] + 0.5 * uu) + er;
+        F[4] = (P[0] * E + p) * un;
+        F[5] = P[0] * er * un;
+    } else {
+        const double E = 1.5 * g.R * P[4] + 0.5 * uu;
+        F[4] = (P[0] * E + p) * un;
+    }
 }
 
+template <int NV>
 __device__ __forceinline__ double acoustic_speed(const DigGeom& g, const double* P, const double* n) {
-    return fabs(P[1] * n[0] + P[2] * n[1] + P[3] * n[2]) + sqrt(kGamma * g.R * P[4]);
+    return fabs(P[1] * n[0] + P[2] * n[1] + P[3] * n[2]) + sqrt(gamma_of<NV>(g) * g.R * P[4]);
 }
 
 // Dissipation speed |u.n| + theta c, theta = min(1, max(Mach, 0.05)).
+template <int NV>
 __device__ __forceinline__ double wave_speed(const DigGeom& g, const double* P, const double* n) {
-    const double c = sqrt(kGamma * g.R * P[4]);
+    const double c = sqrt(gamma_of<NV>(g) * g.R * P[4]);
     const double un = fabs(P[1] * n[0] + P[2] * n[1] + P[3] * n[2]);
     const double u = sqrt(P[1] * P[1] + P[2] * P[2] + P[3] * P[3]);
     double th = u / c;
@@ -95,27 +154,30 @@ __device__ __forceinline__ double wave_speed(const DigGeom& g, const double* P, 
 }
 
 // Central flux with scalar dissipation between states L and R.
+template <int NV>
 __device__ __forceinline__ void central_flux(const DigGeom& g, const double* PL, const double* PR, const double* n,
                                              double* F, double& lam) {
-    double FL[kDigNV], FR[kDigNV], UL[kDigNV], UR[kDigNV];
-    flux_of(g, PL, n, FL);
-    flux_of(g, PR, n, FR);
-    cons_of(g, PL, UL);
-    cons_of(g, PR, UR);
-    const double aL = wave_speed(g, PL, n), aR = wave_speed(g, PR, n);
+    double FL[NV], FR[NV], UL[NV], UR[NV];
+    flux_of<NV>(g, PL, n, FL);
+    flux_of<NV>(g, PR, n, FR);
+    cons_of<NV>(g, PL, UL);
+    cons_of<NV>(g, PR, UR);
+    const double aL = wave_speed<NV>(g, PL, n), aR = wave_speed<NV>(g, PR, n);
     const double lam_d = aL > aR ? aL : aR;
 #pragma unroll
-    for (int v = 0; v < kDigNV; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam_d * (UR[v] - UL[v]);
-    const double sL = acoustic_speed(g, PL, n), sR = acoustic_speed(g, PR, n);
+    for (int v = 0; v < NV; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam_d * (UR[v] - UL[v]);
+    const double sL = acoustic_speed<NV>(g, PL, n), sR = acoustic_speed<NV>(g, PR, n);
     lam = sL > sR ? sL : sR;
 }
 
-// Face gradients of u and T: base gradients plus the correction that makes
-// their component along the connector dx equal the difference quotient.
+// Face gradients of u and T (and T_r): base gradients plus the correction
+// that makes their component along the connector dx equal the difference
+// quotient.
+template <int NV>
 __device__ __forceinline__ void face_gradients(const double* gbase, const double* far, const double* near,
-                                               const double* dx, double dl, double* gu, double* gT) {
+                                               const double* dx, double dl, double* gu, double* gT, double* gTr) {
 #pragma unroll
-    for (int v = 1; v < kDigNV; ++v) {
+    for (int v = 1; v < NV; ++v) {
         double gf[3], ga = 0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -128,15 +190,19 @@ __device__ __forceinline__ void face_gradients(const double* gbase, const double
         if (v < 4) {
 #pragma unroll
             for (int j = 0; j < 3; ++j) gu[3 * (v - 1) + j] = gf[j];
-        } else {
+        } else if (v == 4) {
 #pragma unroll
             for (int j = 0; j < 3; ++j) gT[j] = gf[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) gTr[j] = gf[j];
         }
     }
 }
 
 // Momentum and energy parts of the viscous flux: (sigma + q).n with the
-// face velocity uf doing work.
+// face velocity uf doing work; a rotating gas's q_r also enters rho e_r.
+template <int NV>
 __device__ __forceinline__ void add_viscous(const double* vis, const double* n, const double* uf, double* F) {
     const double S[3][3] = {{vis[0], vis[3], vis[4]}, {vis[3], vis[1], vis[5]}, {vis[4], vis[5], vis[2]}};
     double work = 0.0;
@@ -147,12 +213,37 @@ __device__ __forceinline__ void add_viscous(const double* vis, const double* n, 
         work += sn * uf[i];
     }
     F[4] += work + (vis[6] * n[0] + vis[7] * n[1] + vis[8] * n[2]);
+    if constexpr (NV == 6) {
+        const double qr = vis[9] * n[0] + vis[10] * n[1] + vis[11] * n[2];
+        F[4] += qr;
+        F[5] += qr;
+    }
 }
 
+template <int NV>
 __device__ __forceinline__ double viscous_rate(const DigGeom& g, double T, double rho, double dl) {
     const double mu = mu_of(g, T);
+    if constexpr (NV == 6) {
+        double kt, kr;
+        kappas_of(g, mu, kt, kr);
+        double d = 4.0 * mu / (3.0 * rho);
+        const double dt_ = kt / (1.5 * rho * g.R), dr_ = kr / ((0.5 * g.dr) * rho * g.R);
+        if (dt_ > d) d = dt_;
+        if (dr_ > d) d = dr_;
+        return 2.0 * d / dl;
+    }
     const double dmom = 4.0 * mu / (3.0 * rho), dth = kappa_of(g, mu) / (1.5 * rho * g.R);
     return 2.0 * (dmom > dth ? dmom : dth) / dl;
+}
+
+// Rotational relaxation source of rho e_r (eq. macro):
+// (d_r/2) rho R (T - T_r) / (Z_r tau), T = (3 T_t + d_r T_r)/(3 + d_r),
+// tau = mu(T_t)/p_t; rate = 1/(Z_r tau).
+__device__ __forceinline__ double relax_source(const DigGeom& g, const double* P, double& rate) {
+    const double T = (3.0 * P[4] + g.dr * P[5]) / (3.0 + g.dr);
+    const double tau = mu_of(g, P[4]) / (P[0] * g.R * P[4]);
+    rate = 1.0 / (g.zr * tau);
+    return (((0.5 * g.dr) * P[0]) * g.R) * (T - P[5]) * rate;
 }
 
 __device__ __forceinline__ int wave_sum_i(int v) {
@@ -186,18 +277,20 @@ __device__ void block_sum_min(double s, double m, double* out_s, double* out_m) 
 // sampled state (eq. sampled_macro_state_ch3 with the cell formulas of
 // eq. dsmc_temperatures applied to the moving-average sums)
 // ---------------------------------------------------------------------------
-__global__ void k_dig_sampled(DigGeom g, const double* ewma, double FN, DigWork w) {
+template <int NV>
+__global__ void k_dig_sampled(DigGeom g, const double* ewma, const double* rewma, double FN, DigWork w) {
+    constexpr int NS = Widths<NV>::NS;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nt) return;
     const int nt = g.nt;
     double S[kNMom];
 #pragma unroll
     for (int k = 0; k < kNMom; ++k) S[k] = ewma[(int64_t)k * nt + c];
-    double* o = w.samp + 14 * (size_t)c;
-    double* P = w.prim + kDigNV * (size_t)c;
+    double* o = w.samp + NS * (size_t)c;
+    double* P = w.prim + NV * (size_t)c;
     if (!(S[0] > 0)) {
-        for (int k = 0; k < 14; ++k) o[k] = __builtin_nan("");
-        for (int v = 0; v < kDigNV; ++v) P[v] = w.mprev[kDigNV * (size_t)c + v];
+        for (int k = 0; k < NS; ++k) o[k] = __builtin_nan("");
+        for (int v = 0; v < NV; ++v) P[v] = w.mprev[NV * (size_t)c + v];
         w.ok[c] = 0;
         return;
     }
@@ -224,17 +317,29 @@ __global__ void k_dig_sampled(DigGeom g, const double* ewma, double FN, DigWork 
     o[11] = (rho / 2.0) * (((S[10] - 2.0 * uS0) - u0 * S2kk) + 2.0 * S[0] * u0 * uu) / S[0];
     o[12] = (rho / 2.0) * (((S[11] - 2.0 * uS1) - u1 * S2kk) + 2.0 * S[0] * u1 * uu) / S[0];
     o[13] = (rho / 2.0) * (((S[12] - 2.0 * uS2) - u2 * S2kk) + 2.0 * S[0] * u2 * uu) / S[0];
+    if constexpr (NV == 6) {
+        // rotational temperature and heat flux of the same sums
+        const double r0 = rewma[c], r1 = rewma[(int64_t)nt + c], r2 = rewma[2 * (int64_t)nt + c],
+                     r3 = rewma[3 * (int64_t)nt + c];
+        o[14] = (2.0 * (r0 / S[0])) / ((double)g.dr * kBoltzmannDev);
+        const double f = FN / (g.vol[c] * 1.0);
+        o[15] = f * (r1 - (S[1] / S[0]) * r0);
+        o[16] = f * (r2 - (S[2] / S[0]) * r0);
+        o[17] = f * (r3 - (S[3] / S[0]) * r0);
+    }
     const bool ok = isfinite(rho) && rho > 0;
-    for (int v = 0; v < kDigNV; ++v) P[v] = ok ? o[v] : w.mprev[kDigNV * (size_t)c + v];
+    for (int v = 0; v < 5; ++v) P[v] = ok ? o[v] : w.mprev[NV * (size_t)c + v];
+    if constexpr (NV == 6) P[5] = ok ? o[14] : w.mprev[NV * (size_t)c + 5];
     w.ok[c] = ok ? 1 : 0;
 }
 
 // Kn_Delta = (Kn (T/T0)^(omega-1/2) / (rho/rho0)) / (d_c / L0), d_c = 2 (3V/4pi)^(1/3)
 // (eq. cell_kn_stability); infinite for cells without samples.
+template <int NV>
 __global__ void k_dig_kn(DigGeom g, DigWork w, double kn_ref, double T0, double rho0, double L0) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nt) return;
-    const double rho = w.prim[kDigNV * (size_t)c], T = w.prim[kDigNV * (size_t)c + 4];
+    const double rho = w.prim[NV * (size_t)c], T = w.prim[NV * (size_t)c + 4];
     if (g.cases) {
         const DigCase& k = g.cases[g.cell_case[c]];
         kn_ref = k.mu0 / (k.p0 * L0) * k.kfac;
@@ -249,10 +354,11 @@ __global__ void k_dig_kn(DigGeom g, DigWork w, double kn_ref, double T0, double 
 }
 
 // Weighted least squares over face neighbours: a diffuse wall contributes
-// its velocity and temperature (and the cell's own density) at the face
-// centroid; specular, inflow and outflow faces contribute nothing.
-// Batch, inside the coupling step's solve: cells of cases that are not
-// coupled are left out (cases share no faces, so no coupled cell reads them).
+// its velocity and temperature (both temperatures of a rotating gas) and the
+// cell's own density at the face centroid; specular, inflow and outflow
+// faces contribute nothing.  Batch, inside the coupling step's solve: cells
+// of cases that are not coupled are left out (cases share no faces, so no
+// coupled cell reads them).
 __device__ __forceinline__ bool idle_cell(const DigGeom& g, int c) {
     return g.skip_idle && !g.cases[g.cell_case[c]].enabled;
 }
@@ -261,36 +367,38 @@ __device__ __forceinline__ bool idle_cell(const DigGeom& g, int c) {
 // forms its face's weighted difference terms; the cell's sums are taken over
 // the four lanes in face order (a face without a value adds +0, which leaves
 // the sum unchanged), and each lane writes a quarter of the gradient.
+template <int NV>
 __global__ __launch_bounds__(kDigThreads) void k_dig_grad(DigGeom g, const double* prim, double* grad, const DigCtl* ctl) {
     if (stopped(ctl)) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = (int)(t >> 2), f = (int)(t & 3);
     const bool live = c < g.nt && !idle_cell(g, c);
-    double tb[kDigNV][3];
+    double tb[NV][3];
 #pragma unroll
-    for (int v = 0; v < kDigNV; ++v) tb[v][0] = tb[v][1] = tb[v][2] = 0.0;
+    for (int v = 0; v < NV; ++v) tb[v][0] = tb[v][1] = tb[v][2] = 0.0;
     if (live) {
         const int link = g.flink[4 * (size_t)c + f];
         const int kind = link & 7, idx = link >> 3;
         const bool inner = kind == kLinkInterior || kind == kLinkPeriodic;
         if (inner || kind == kLinkWall) {
-            double pc[kDigNV], far[kDigNV];
+            double pc[NV], far[NV];
 #pragma unroll
-            for (int v = 0; v < kDigNV; ++v) pc[v] = prim[kDigNV * (size_t)c + v];
+            for (int v = 0; v < NV; ++v) pc[v] = prim[NV * (size_t)c + v];
             if (inner) {
 #pragma unroll
-                for (int v = 0; v < kDigNV; ++v) far[v] = prim[kDigNV * (size_t)idx + v];
+                for (int v = 0; v < NV; ++v) far[v] = prim[NV * (size_t)idx + v];
             } else {
                 const DigGroup& gr = g.groups[idx];
                 far[0] = pc[0];
                 far[1] = gr.u[0]; far[2] = gr.u[1]; far[3] = gr.u[2];
                 far[4] = gr.T;
+                if constexpr (NV == 6) far[5] = gr.T;
             }
             const double* dx = g.fdx + 12 * (size_t)c + 3 * f;
             const double d0 = dx[0], d1 = dx[1], d2 = dx[2];
             const double wgt = 1.0 / (d0 * d0 + d1 * d1 + d2 * d2);
 #pragma unroll
-            for (int v = 0; v < kDigNV; ++v) {
+            for (int v = 0; v < NV; ++v) {
                 const double dphi = far[v] - pc[v];
                 tb[v][0] = wgt * d0 * dphi;
                 tb[v][1] = wgt * d1 * dphi;
@@ -299,20 +407,20 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_grad(DigGeom g, const doubl
         }
     }
     const int q0 = (int)(threadIdx.x & 63) & ~3;
-    double b[kDigNV][3];
+    double b[NV][3];
 #pragma unroll
-    for (int v = 0; v < kDigNV; ++v) b[v][0] = b[v][1] = b[v][2] = 0.0;
+    for (int v = 0; v < NV; ++v) b[v][0] = b[v][1] = b[v][2] = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int v = 0; v < kDigNV; ++v)
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int i = 0; i < 3; ++i) b[v][i] += __shfl(tb[v][i], q0 + k, 64);
     if (!live) return;
     const double* L = g.lsq + 9 * (size_t)c;
-    double* o = grad + 15 * (size_t)c;
+    double* o = grad + 3 * NV * (size_t)c;
 #pragma unroll
-    for (int v = 0; v < kDigNV; ++v)
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int i = 0; i < 3; ++i)
             if ((3 * v + i) % 4 == f) o[3 * v + i] = L[3 * i] * b[v][0] + L[3 * i + 1] * b[v][1] + L[3 * i + 2] * b[v][2];
@@ -320,16 +428,32 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_grad(DigGeom g, const doubl
 
 // HoT = (sigma, q)_sampled - (sigma, q)_NSF at the sampled state
 // (eq. hot_extraction_ch3); zero for cells without samples.
+template <int NV>
 __global__ void k_dig_hot(DigGeom g, DigWork w) {
+    constexpr int NH = Widths<NV>::NH, NS = Widths<NV>::NS;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nt) return;
-    const double* gr = w.grad + 15 * (size_t)c;
-    double nsf[9];
-    nsf_local(g, w.prim[kDigNV * (size_t)c + 4], gr + 3, gr + 12, nsf);
+    const double* gr = w.grad + 3 * NV * (size_t)c;
+    double nsf[NH];
+    nsf_local<NV>(g, w.prim[NV * (size_t)c + 4], gr + 3, gr + 12, gr + 15, nsf);
     const bool ok = w.ok[c];
-    const double* a = w.samp + 14 * (size_t)c;
+    const double* a = w.samp + NS * (size_t)c;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) w.hot[9 * (size_t)c + k] = ok ? a[5 + k] - nsf[k] : 0.0;
+    for (int k = 0; k < 9; ++k) w.hot[NH * (size_t)c + k] = ok ? a[5 + k] - nsf[k] : 0.0;
+    if constexpr (NV == 6) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) w.hot[NH * (size_t)c + 9 + k] = ok ? a[15 + k] - nsf[9 + k] : 0.0;
+    }
+}
+
+// The state a diffuse wall imposes: the cell's density, the wall's velocity
+// and temperature (both temperatures).
+template <int NV>
+__device__ __forceinline__ void wall_state(const DigGroup& gr, const double* Pc, double* wv) {
+    wv[0] = Pc[0];
+    wv[1] = gr.u[0]; wv[2] = gr.u[1]; wv[3] = gr.u[2];
+    wv[4] = gr.T;
+    if constexpr (NV == 6) wv[5] = gr.T;
 }
 
 // HoT carried by each cell face: the cell HoT averaged to the face (the
@@ -337,58 +461,62 @@ __global__ void k_dig_hot(DigGeom g, DigWork w) {
 // stresses averaged to the face minus the face NSF stress of the viscous
 // flux, both at prim, so that at prim each face's viscous stress is the
 // average of its cells' NSF + HoT.
+template <int NV>
 __global__ void k_dig_face_hot(DigGeom g, const double* prim, const double* grad, const double* hot, double* hotf,
                                int consistent) {
+    constexpr int NH = Widths<NV>::NH, NG = Widths<NV>::NG;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nt) return;
-    double Pc[kDigNV], gc[15], nc[9];
-    for (int v = 0; v < kDigNV; ++v) Pc[v] = prim[kDigNV * (size_t)c + v];
-    for (int k = 0; k < 15; ++k) gc[k] = grad[15 * (size_t)c + k];
-    nsf_local(g, Pc[4], gc + 3, gc + 12, nc);
+    double Pc[NV], gc[NG], nc[NH];
+    for (int v = 0; v < NV; ++v) Pc[v] = prim[NV * (size_t)c + v];
+    for (int k = 0; k < NG; ++k) gc[k] = grad[NG * (size_t)c + k];
+    nsf_local<NV>(g, Pc[4], gc + 3, gc + 12, gc + 15, nc);
     for (int f = 0; f < 4; ++f) {
         const int link = g.flink[4 * c + f];
         const int kind = link & 7, idx = link >> 3;
         const size_t fo = 12 * (size_t)c + 3 * f;
         const double dx[3] = {g.fdx[fo], g.fdx[fo + 1], g.fdx[fo + 2]};
         const double dl = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
-        double* h = hotf + 36 * (size_t)c + 9 * f;
-        double gu[9], gT[3], vf[9];
+        double* h = hotf + 4 * NH * (size_t)c + NH * f;
+        double gu[9], gT[3], gTr[3], vf[NH];
         if (kind == kLinkInterior || kind == kLinkPeriodic) {
             const int nb = idx;
-            double Pn[kDigNV], gn[15], gavg[15], nn[9];
-            for (int v = 0; v < kDigNV; ++v) Pn[v] = prim[kDigNV * (size_t)nb + v];
-            for (int k = 0; k < 15; ++k) gn[k] = grad[15 * (size_t)nb + k];
-            for (int k = 0; k < 15; ++k) gavg[k] = 0.5 * (gc[k] + gn[k]);
-            face_gradients(gavg, Pn, Pc, dx, dl, gu, gT);
-            nsf_local(g, 0.5 * (Pc[4] + Pn[4]), gu, gT, vf);
-            nsf_local(g, Pn[4], gn + 3, gn + 12, nn);
-            for (int k = 0; k < 9; ++k) {
-                double v = 0.5 * (hot[9 * (size_t)c + k] + hot[9 * (size_t)nb + k]);
+            double Pn[NV], gn[NG], gavg[NG], nn[NH];
+            for (int v = 0; v < NV; ++v) Pn[v] = prim[NV * (size_t)nb + v];
+            for (int k = 0; k < NG; ++k) gn[k] = grad[NG * (size_t)nb + k];
+            for (int k = 0; k < NG; ++k) gavg[k] = 0.5 * (gc[k] + gn[k]);
+            face_gradients<NV>(gavg, Pn, Pc, dx, dl, gu, gT, gTr);
+            nsf_local<NV>(g, 0.5 * (Pc[4] + Pn[4]), gu, gT, gTr, vf);
+            nsf_local<NV>(g, Pn[4], gn + 3, gn + 12, gn + 15, nn);
+            for (int k = 0; k < NH; ++k) {
+                double v = 0.5 * (hot[NH * (size_t)c + k] + hot[NH * (size_t)nb + k]);
                 if (consistent) v += 0.5 * (nc[k] + nn[k]) - vf[k];
                 h[k] = v;
             }
         } else if (kind == kLinkWall) {
             const DigGroup& gr = g.groups[idx];
-            const double wallv[kDigNV] = {Pc[0], gr.u[0], gr.u[1], gr.u[2], gr.T};
-            face_gradients(gc, wallv, Pc, dx, dl, gu, gT);
-            nsf_local(g, gr.T, gu, gT, vf);
-            for (int k = 0; k < 9; ++k) {
-                double v = hot[9 * (size_t)c + k];
+            double wallv[NV];
+            wall_state<NV>(gr, Pc, wallv);
+            face_gradients<NV>(gc, wallv, Pc, dx, dl, gu, gT, gTr);
+            nsf_local<NV>(g, gr.T, gu, gT, gTr, vf);
+            for (int k = 0; k < NH; ++k) {
+                double v = hot[NH * (size_t)c + k];
                 if (consistent) v += nc[k] - vf[k];
                 h[k] = v;
             }
         } else {
-            for (int k = 0; k < 9; ++k) h[k] = 0.0;
+            for (int k = 0; k < NH; ++k) h[k] = 0.0;
         }
     }
 }
 
 // Admissibility (criterion on Kn_Delta) and availability of every cell.
+template <int NV>
 __global__ void k_dig_gate_init(DigGeom g, DigWork w, double kn_max) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nt) return;
     bool ok = w.kn[c] <= kn_max;
-    for (int v = 0; v < kDigNV && ok; ++v) ok = isfinite(w.prim[kDigNV * (size_t)c + v]);
+    for (int v = 0; v < NV && ok; ++v) ok = isfinite(w.prim[NV * (size_t)c + v]);
     w.avail[c] = ok ? 1 : 0;
     w.navail[c] = ok ? 1 : 0;
     w.state[c] = ok ? 0 : 2;
@@ -397,42 +525,52 @@ __global__ void k_dig_gate_init(DigGeom g, DigWork w, double kn_max) {
 // One reconstruction pass: every unavailable cell with available face
 // neighbours takes their equal-weight mean of M and HoT.  Results become
 // visible to neighbours only in the next pass (k_dig_gate_commit).
+template <int NV>
 __global__ void k_dig_gate_pass(DigGeom g, DigWork w) {
+    constexpr int NH = Widths<NV>::NH;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nt || w.avail[c]) return;
     int cnt = 0;
-    double sp[kDigNV] = {0, 0, 0, 0, 0}, sh[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double sp[NV], sh[NH];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sp[v] = 0.0;
+#pragma unroll
+    for (int v = 0; v < NH; ++v) sh[v] = 0.0;
     for (int f = 0; f < 4; ++f) {
         const int link = g.flink[4 * c + f];
         const int kind = link & 7, nb = link >> 3;
         if ((kind != kLinkInterior && kind != kLinkPeriodic) || !w.avail[nb]) continue;
         ++cnt;
 #pragma unroll
-        for (int v = 0; v < kDigNV; ++v) sp[v] += w.prim[kDigNV * (size_t)nb + v];
+        for (int v = 0; v < NV; ++v) sp[v] += w.prim[NV * (size_t)nb + v];
 #pragma unroll
-        for (int v = 0; v < 9; ++v) sh[v] += w.hot[9 * (size_t)nb + v];
+        for (int v = 0; v < NH; ++v) sh[v] += w.hot[NH * (size_t)nb + v];
     }
     if (!cnt) return;
 #pragma unroll
-    for (int v = 0; v < kDigNV; ++v) w.nprim[kDigNV * (size_t)c + v] = sp[v] / cnt;
+    for (int v = 0; v < NV; ++v) w.nprim[NV * (size_t)c + v] = sp[v] / cnt;
 #pragma unroll
-    for (int v = 0; v < 9; ++v) w.nhot[9 * (size_t)c + v] = sh[v] / cnt;
+    for (int v = 0; v < NH; ++v) w.nhot[NH * (size_t)c + v] = sh[v] / cnt;
     w.navail[c] = 1;
     w.state[c] = 1;
 }
 
+template <int NV>
 __global__ void k_dig_gate_commit(DigGeom g, DigWork w) {
+    constexpr int NH = Widths<NV>::NH;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nt) return;
     if (w.navail[c] && !w.avail[c]) {
-        for (int v = 0; v < kDigNV; ++v) w.prim[kDigNV * (size_t)c + v] = w.nprim[kDigNV * (size_t)c + v];
-        for (int v = 0; v < 9; ++v) w.hot[9 * (size_t)c + v] = w.nhot[9 * (size_t)c + v];
+        for (int v = 0; v < NV; ++v) w.prim[NV * (size_t)c + v] = w.nprim[NV * (size_t)c + v];
+        for (int v = 0; v < NH; ++v) w.hot[NH * (size_t)c + v] = w.nhot[NH * (size_t)c + v];
         w.avail[c] = 1;
     }
 }
 
 // Unreached cells keep M^k with zero HoT; counts of the report.
+template <int NV>
 __global__ void k_dig_gate_final(DigGeom g, DigWork w) {
+    constexpr int NH = Widths<NV>::NH;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     int rej = 0, rec = 0, unr = 0;
     if (c < g.nt) {
@@ -441,8 +579,8 @@ __global__ void k_dig_gate_final(DigGeom g, DigWork w) {
         rec = st == 1;
         unr = st == 2;
         if (st == 2) {
-            for (int v = 0; v < kDigNV; ++v) w.prim[kDigNV * (size_t)c + v] = w.mprev[kDigNV * (size_t)c + v];
-            for (int v = 0; v < 9; ++v) w.hot[9 * (size_t)c + v] = 0.0;
+            for (int v = 0; v < NV; ++v) w.prim[NV * (size_t)c + v] = w.mprev[NV * (size_t)c + v];
+            for (int v = 0; v < NH; ++v) w.hot[NH * (size_t)c + v] = 0.0;
         }
     }
     rej = wave_sum_i(rej);
@@ -477,25 +615,31 @@ __global__ void k_dig_copy(const double* src, double* dst, int64_t n) {
 
 // ---------------------------------------------------------------------------
 // finite-volume residual: R_c = sum_f (F_inviscid + F_viscous).n A_f
+// (minus V times the relaxation source in the rho e_r equation)
 // ---------------------------------------------------------------------------
 // One lane per (cell, face), four consecutive lanes per cell: each lane
 // computes its face's flux; the cell's sums are then formed from the four
 // lanes' terms in face order (the order of a loop over the faces), so that
 // four times as many lanes keep the gathered neighbour loads in flight.
+template <int NV>
 __global__ __launch_bounds__(kDigThreads) void k_dig_residual(DigGeom g, const double* prim, const double* hotf,
                                                               const double* grad, double* Rs, DigWork w, int first,
                                                               double cfl) {
+    constexpr int NH = Widths<NV>::NH, NG = Widths<NV>::NG;
     if (stopped(w.ctl)) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = (int)(t >> 2), f = (int)(t & 3);
     const bool live = c < g.nt && !idle_cell(g, c);
-    double FA[kDigNV] = {0, 0, 0, 0, 0}, SA = 0.0;
+    double FA[NV], SA = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) FA[v] = 0.0;
+    double Pc[NV];
     if (live) {
-        double Pc[kDigNV], gc[15];
+        double gc[NG];
 #pragma unroll
-        for (int v = 0; v < kDigNV; ++v) Pc[v] = prim[kDigNV * (size_t)c + v];
+        for (int v = 0; v < NV; ++v) Pc[v] = prim[NV * (size_t)c + v];
 #pragma unroll
-        for (int k = 0; k < 15; ++k) gc[k] = grad[15 * (size_t)c + k];
+        for (int k = 0; k < NG; ++k) gc[k] = grad[NG * (size_t)c + k];
         const double xc[3] = {g.cen[3 * (size_t)c], g.cen[3 * (size_t)c + 1], g.cen[3 * (size_t)c + 2]};
         const int link = g.flink[4 * (size_t)c + f];
         const int kind = link & 7, idx = link >> 3;
@@ -504,16 +648,18 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_residual(DigGeom g, const d
         // geometry (a face without a neighbour cell reads its own cell's,
         // unused)
         const size_t nb = inner ? (size_t)idx : (size_t)c;
-        double Pn[kDigNV], gn[15];
+        double Pn[NV], gn[NG];
 #pragma unroll
-        for (int v = 0; v < kDigNV; ++v) Pn[v] = prim[kDigNV * nb + v];
+        for (int v = 0; v < NV; ++v) Pn[v] = prim[NV * nb + v];
 #pragma unroll
-        for (int k = 0; k < 15; ++k) gn[k] = grad[15 * nb + k];
+        for (int k = 0; k < NG; ++k) gn[k] = grad[NG * nb + k];
         const size_t fo = 12 * (size_t)c + 3 * f;
         const double n[3] = {g.fnu[fo], g.fnu[fo + 1], g.fnu[fo + 2]};
         const double dx[3] = {g.fdx[fo], g.fdx[fo + 1], g.fdx[fo + 2]};
         const double A = g.farea[4 * (size_t)c + f];
-        double F[kDigNV] = {0, 0, 0, 0, 0};
+        double F[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v] = 0.0;
         double lam = 0.0, lamv = 0.0;
         if (inner) {
             const double xf[3] = {g.fcen[fo], g.fcen[fo + 1], g.fcen[fo + 2]};
@@ -523,95 +669,115 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_residual(DigGeom g, const d
                 rc[i] = xf[i] - xc[i];
                 rn[i] = xf[i] - (xc[i] + dx[i]);
             }
-            double PL[kDigNV], PR[kDigNV];
+            double PL[NV], PR[NV];
 #pragma unroll
-            for (int v = 0; v < kDigNV; ++v) {
+            for (int v = 0; v < NV; ++v) {
                 PL[v] = Pc[v] + (gc[3 * v] * rc[0] + gc[3 * v + 1] * rc[1] + gc[3 * v + 2] * rc[2]);
                 PR[v] = Pn[v] + (gn[3 * v] * rn[0] + gn[3 * v + 1] * rn[1] + gn[3 * v + 2] * rn[2]);
             }
-            if (!(PL[0] > 0 && PL[4] > 0 && PR[0] > 0 && PR[4] > 0)) {
+            bool pos = PL[0] > 0 && PL[4] > 0 && PR[0] > 0 && PR[4] > 0;
+            if constexpr (NV == 6) pos = pos && PL[5] > 0 && PR[5] > 0;
+            if (!pos) {
 #pragma unroll
-                for (int v = 0; v < kDigNV; ++v) {
+                for (int v = 0; v < NV; ++v) {
                     PL[v] = Pc[v];
                     PR[v] = Pn[v];
                 }
             }
-            central_flux(g, PL, PR, n, F, lam);
+            central_flux<NV>(g, PL, PR, n, F, lam);
             const double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
             const double dl = sqrt(d2);
-            double gavg[15];
+            double gavg[NG];
 #pragma unroll
-            for (int k = 3; k < 15; ++k) gavg[k] = 0.5 * (gc[k] + gn[k]);
-            double gu[9], gT[3];
-            face_gradients(gavg, Pn, Pc, dx, dl, gu, gT);
+            for (int k = 3; k < NG; ++k) gavg[k] = 0.5 * (gc[k] + gn[k]);
+            double gu[9], gT[3], gTr[3];
+            face_gradients<NV>(gavg, Pn, Pc, dx, dl, gu, gT, gTr);
             const double Tf = 0.5 * (Pc[4] + Pn[4]);
             const double rf = 0.5 * (Pc[0] + Pn[0]);
-            double vis[9];
-            nsf_local(g, Tf, gu, gT, vis);
-            const double* hf = hotf + 36 * (size_t)c + 9 * f;
+            double vis[NH];
+            nsf_local<NV>(g, Tf, gu, gT, gTr, vis);
+            const double* hf = hotf + 4 * NH * (size_t)c + NH * f;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) vis[k] += hf[k];
+            for (int k = 0; k < NH; ++k) vis[k] += hf[k];
             const double uf[3] = {0.5 * (Pc[1] + Pn[1]), 0.5 * (Pc[2] + Pn[2]), 0.5 * (Pc[3] + Pn[3])};
-            add_viscous(vis, n, uf, F);
-            lamv = viscous_rate(g, Tf, rf, dl);
+            add_viscous<NV>(vis, n, uf, F);
+            lamv = viscous_rate<NV>(g, Tf, rf, dl);
         } else if (kind == kLinkWall || kind == kLinkSpecular) {
             const double p = Pc[0] * g.R * Pc[4];
 #pragma unroll
             for (int i = 0; i < 3; ++i) F[1 + i] = p * n[i];
-            lam = acoustic_speed(g, Pc, n);
+            lam = acoustic_speed<NV>(g, Pc, n);
             if (kind == kLinkWall) {
                 const DigGroup& gr = g.groups[idx];
                 const double d2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
                 const double dl = sqrt(d2);
-                const double wallv[kDigNV] = {Pc[0], gr.u[0], gr.u[1], gr.u[2], gr.T};
-                double gu[9], gT[3];
-                face_gradients(gc, wallv, Pc, dx, dl, gu, gT);
-                double vis[9];
-                nsf_local(g, gr.T, gu, gT, vis);
-                const double* hf = hotf + 36 * (size_t)c + 9 * f;
+                double wallv[NV];
+                wall_state<NV>(gr, Pc, wallv);
+                double gu[9], gT[3], gTr[3];
+                face_gradients<NV>(gc, wallv, Pc, dx, dl, gu, gT, gTr);
+                double vis[NH];
+                nsf_local<NV>(g, gr.T, gu, gT, gTr, vis);
+                const double* hf = hotf + 4 * NH * (size_t)c + NH * f;
 #pragma unroll
-                for (int k = 0; k < 9; ++k) vis[k] += hf[k];
-                add_viscous(vis, n, gr.u, F);
-                lamv = viscous_rate(g, gr.T, Pc[0], dl);
+                for (int k = 0; k < NH; ++k) vis[k] += hf[k];
+                add_viscous<NV>(vis, n, gr.u, F);
+                lamv = viscous_rate<NV>(g, gr.T, Pc[0], dl);
             }
         } else if (kind == kLinkInflow) {
             const DigGroup& gr = g.groups[idx];
-            const double PR[kDigNV] = {gr.rho, gr.u[0], gr.u[1], gr.u[2], gr.T};
-            central_flux(g, Pc, PR, n, F, lam);
+            double PR[NV];
+            PR[0] = gr.rho; PR[1] = gr.u[0]; PR[2] = gr.u[1]; PR[3] = gr.u[2]; PR[4] = gr.T;
+            if constexpr (NV == 6) PR[5] = gr.T;
+            central_flux<NV>(g, Pc, PR, n, F, lam);
         } else {
-            flux_of(g, Pc, n, F);
-            lam = acoustic_speed(g, Pc, n);
+            flux_of<NV>(g, Pc, n, F);
+            lam = acoustic_speed<NV>(g, Pc, n);
         }
 #pragma unroll
-        for (int v = 0; v < kDigNV; ++v) FA[v] = F[v] * A;
+        for (int v = 0; v < NV; ++v) FA[v] = F[v] * A;
         SA = (lam + lamv) * A;
     }
     // the cell's sums over its four lanes, in face order (every lane of the
     // wave takes part in the exchange)
     const int q0 = (int)(threadIdx.x & 63) & ~3;
-    double Rc[kDigNV] = {0, 0, 0, 0, 0};
+    double Rc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Rc[v] = 0.0;
     double sp = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
 #pragma unroll
-        for (int v = 0; v < kDigNV; ++v) Rc[v] += __shfl(FA[v], q0 + k, 64);
+        for (int v = 0; v < NV; ++v) Rc[v] += __shfl(FA[v], q0 + k, 64);
         sp += __shfl(SA, q0 + k, 64);
     }
     double r2 = 0.0, dtc = __builtin_inf();
     if (live && f == 0) {
+        if constexpr (NV == 6) {
+            double rate;
+            const double src = relax_source(g, Pc, rate);
+            Rc[5] -= g.vol[c] * src;
+            sp += g.vol[c] * rate;
+        }
 #pragma unroll
-        for (int v = 0; v < kDigNV; ++v) Rs[kDigNV * (size_t)c + v] = Rc[v];
+        for (int v = 0; v < NV; ++v) Rs[NV * (size_t)c + v] = Rc[v];
         if (first) {
             dtc = cfl * g.vol[c] / sp;
             w.dt[c] = dtc;
             r2 = Rc[0] * Rc[0];
+            if constexpr (NV == 6) {
+                // the rotational-energy residual in mass units, R_er / (R T0)
+                const double ert = g.cases ? g.R * g.cases[g.cell_case[c]].T0 : g.ert;
+                const double r5 = Rc[5] / ert;
+                r2 = r2 + r5 * r5;
+            }
         }
     }
     if (first) block_sum_min(r2, dtc, &w.partial[2 * blockIdx.x], &w.partial[2 * blockIdx.x + 1]);
 }
 
-// Density residual norm, first-iteration reference, convergence test and
-// the smallest local step (single workgroup).
+// Density residual norm (with rotation: and the rotational-energy residual),
+// first-iteration reference, convergence test and the smallest local step
+// (single workgroup).
 __global__ __launch_bounds__(kDigThreads) void k_dig_check(DigWork w, int nblk, int it, double eps_m) {
     if (stopped(w.ctl)) return;
     double s = 0.0, m = __builtin_inf();
@@ -633,54 +799,58 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_check(DigWork w, int nblk, 
     }
 }
 
+template <int NV>
 __global__ void k_dig_save(DigGeom g, DigWork w) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nt || stopped(w.ctl) || idle_cell(g, c)) return;
-    double P[kDigNV], U[kDigNV];
+    double P[NV], U[NV];
 #pragma unroll
-    for (int v = 0; v < kDigNV; ++v) {
-        P[v] = w.prim[kDigNV * (size_t)c + v];
-        w.stage[kDigNV * (size_t)c + v] = P[v];
+    for (int v = 0; v < NV; ++v) {
+        P[v] = w.prim[NV * (size_t)c + v];
+        w.stage[NV * (size_t)c + v] = P[v];
     }
-    cons_of(g, P, U);
+    cons_of<NV>(g, P, U);
 #pragma unroll
-    for (int v = 0; v < kDigNV; ++v) w.U0[kDigNV * (size_t)c + v] = U[v];
+    for (int v = 0; v < NV; ++v) w.U0[NV * (size_t)c + v] = U[v];
 }
 
 // Stage update U = U0 - alpha dt / V R(stage).
+template <int NV>
 __global__ void k_dig_update(DigGeom g, DigWork w, double alpha, int global_dt) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nt || stopped(w.ctl) || idle_cell(g, c)) return;
     const double dtc = global_dt ? w.ctl->dtmin : w.dt[c];
-    double U[kDigNV];
+    double U[NV];
 #pragma unroll
-    for (int v = 0; v < kDigNV; ++v)
-        U[v] = w.U0[kDigNV * (size_t)c + v] - alpha * dtc / g.vol[c] * w.Rs[kDigNV * (size_t)c + v];
-    double P[kDigNV];
-    if (prim_of(g, U, P)) {
+    for (int v = 0; v < NV; ++v)
+        U[v] = w.U0[NV * (size_t)c + v] - alpha * dtc / g.vol[c] * w.Rs[NV * (size_t)c + v];
+    double P[NV];
+    if (prim_of<NV>(g, U, P)) {
 #pragma unroll
-        for (int v = 0; v < kDigNV; ++v) w.stage[kDigNV * (size_t)c + v] = P[v];
+        for (int v = 0; v < NV; ++v) w.stage[NV * (size_t)c + v] = P[v];
     } else {
         if (U[0] > 0) {
 #pragma unroll
-            for (int v = 0; v < kDigNV; ++v) w.stage[kDigNV * (size_t)c + v] = P[v];
+            for (int v = 0; v < NV; ++v) w.stage[NV * (size_t)c + v] = P[v];
         }
         atomicOr(&w.ctl->failed, 1);
     }
 }
 
+template <int NV>
 __global__ void k_dig_commit(DigGeom g, DigWork w) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nt || stopped(w.ctl)) return;
     if (c == 0) w.ctl->iters += 1;
     if (idle_cell(g, c)) return;
 #pragma unroll
-    for (int v = 0; v < kDigNV; ++v) w.prim[kDigNV * (size_t)c + v] = w.stage[kDigNV * (size_t)c + v];
+    for (int v = 0; v < NV; ++v) w.prim[NV * (size_t)c + v] = w.stage[NV * (size_t)c + v];
 }
 
+template <int NV>
 __global__ __launch_bounds__(kDigThreads) void k_dig_mass_partial(DigGeom g, DigWork w) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const double m = c < g.nt ? w.prim[kDigNV * (size_t)c] * g.vol[c] : 0.0;
+    const double m = c < g.nt ? w.prim[NV * (size_t)c] * g.vol[c] : 0.0;
     block_sum_min(m, 0.0, &w.partial[2 * blockIdx.x], &w.partial[2 * blockIdx.x + 1]);
 }
 
@@ -696,9 +866,10 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_mass_factor(DigGeom g, DigW
     }
 }
 
+template <int NV>
 __global__ void k_dig_mass_apply(DigGeom g, DigWork w) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < g.nt) w.prim[kDigNV * (size_t)c] = w.prim[kDigNV * (size_t)c] * w.ctl->mass_scale;
+    if (c < g.nt) w.prim[NV * (size_t)c] = w.prim[NV * (size_t)c] * w.ctl->mass_scale;
 }
 
 __global__ void k_dig_set_local(DigGeom g, const int32_t* state, uint8_t* local) {
@@ -710,8 +881,10 @@ __global__ void k_dig_set_local(DigGeom g, const int32_t* state, uint8_t* local)
 // ---------------------------------------------------------------------------
 // particle feedback (Algorithm 1: particles adjusted to M^{k+1})
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool fb_valid(const double* a, const double* b) {
-    return a[0] > 0 && b[0] > 0 && a[4] > 0 && b[4] > 0;
+__device__ __forceinline__ bool fb_valid(const DigGeom& g, const double* a, const double* b) {
+    bool ok = a[0] > 0 && b[0] > 0 && a[4] > 0 && b[4] > 0;
+    if (g.dr) ok = ok && a[5] > 0 && b[5] > 0;
+    return ok;
 }
 
 // Target count floor(rho_new V / (F_N m) + U) of each cell (unchanged when
@@ -723,8 +896,9 @@ __global__ void k_dig_fb_count(DigGeom g, DigWork w, const int32_t* offsets, con
     if (c >= g.nt) return;
     const int N = offsets[c + 1] - offsets[c];
     int T = N;
-    const double* a = w.half + kDigNV * (size_t)c;
-    const double* b = w.prim + kDigNV * (size_t)c;
+    const int nv = g.dr ? kDigNVR : kDigNV;
+    const double* a = w.half + nv * (size_t)c;
+    const double* b = w.prim + nv * (size_t)c;
     double FN = g.FN;
     uint32_t subject = (uint32_t)orig[c];
     bool on = true;
@@ -736,7 +910,7 @@ __global__ void k_dig_fb_count(DigGeom g, DigWork w, const int32_t* offsets, con
         subject -= (uint32_t)k.cell0;
         on = k.enabled != 0;
     }
-    if (on && w.state[c] <= 1 && N > 0 && fb_valid(a, b)) {
+    if (on && w.state[c] <= 1 && N > 0 && fb_valid(g, a, b)) {
         const Rand4 r = draw(key, subject, sc->step, kPurposeRecalibrate, 0);
         double t = floor(b[0] * g.vol[c] / (FN * g.mass) + u01(r.w[0], r.w[1]));
         if (!(t < 1073741824.0)) t = 1073741824.0;
@@ -757,8 +931,9 @@ __global__ __launch_bounds__(kFbLanes) void k_dig_fb_apply(DigGeom g, DigWork w,
     const int lane = threadIdx.x;
     const int64_t a0 = offsets[c];
     const int N = offsets[c + 1] - (int)a0;
-    const double* a = w.half + kDigNV * (size_t)c;
-    const double* b = w.prim + kDigNV * (size_t)c;
+    const int nv = g.dr ? kDigNVR : kDigNV;
+    const double* a = w.half + nv * (size_t)c;
+    const double* b = w.prim + nv * (size_t)c;
     uint32_t subject = (uint32_t)orig[c];
     uint32_t next_pid = sc->next_pid;
     int64_t pid_off = 0;
@@ -771,13 +946,18 @@ __global__ __launch_bounds__(kFbLanes) void k_dig_fb_apply(DigGeom g, DigWork w,
         next_pid = k.next_pid;
         pid_off = w.fb_off[k.cell0];
     }
-    if (w.state[c] > 1 || N == 0 || !fb_valid(a, b)) return;
+    if (w.state[c] > 1 || N == 0 || !fb_valid(g, a, b)) return;
     const double scale = sqrt(b[4] / a[4]);
     for (int i = lane; i < N; i += kFbLanes) {
         const int64_t k = a0 + i;
         p.vel[3 * k] = (VT)(b[1] + scale * ((double)p.vel[3 * k] - a[1]));
         p.vel[3 * k + 1] = (VT)(b[2] + scale * ((double)p.vel[3 * k + 1] - a[2]));
         p.vel[3 * k + 2] = (VT)(b[3] + scale * ((double)p.vel[3 * k + 2] - a[3]));
+    }
+    if (g.dr && p.ir) {
+        // rotational energies scaled by the ratio of the rotational temperatures
+        const double rs = b[5] / a[5];
+        for (int i = lane; i < N; i += kFbLanes) p.ir[a0 + i] = rs * p.ir[a0 + i];
     }
     // logical (pid) order of the cell
     for (int i = lane; i < N; i += kFbLanes) {
@@ -978,30 +1158,36 @@ __global__ void k_dig_closure_gate(DigGeom g, DigWork w, double tol, const doubl
 // ---------------------------------------------------------------------------
 static inline dim3 cells_grid(int64_t n) { return dim3((unsigned)((n + kDigThreads - 1) / kDigThreads)); }
 
-void launch_dig_sampled(hipStream_t s, const DigGeom& g, const double* ewma, double FN, DigWork w) {
-    hipLaunchKernelGGL(k_dig_sampled, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, ewma, FN, w);
+// Kernels of the coupling step come in a monatomic (5 primitives) and a
+// rotating (6) instance; the launchers pick by the gas.
+#define DIG_NV(g, kernel) ((g).dr ? (kernel<kDigNVR>) : (kernel<kDigNV>))
+
+void launch_dig_sampled(hipStream_t s, const DigGeom& g, const double* ewma, const double* rewma, double FN,
+                        DigWork w) {
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_sampled), cells_grid(g.nt), dim3(kDigThreads), 0, s, g, ewma, rewma, FN, w);
 }
 
 void launch_dig_kn(hipStream_t s, const DigGeom& g, DigWork w, double kn_ref, double T0, double rho0, double L0) {
-    hipLaunchKernelGGL(k_dig_kn, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w, kn_ref, T0, rho0, L0);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_kn), cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w, kn_ref, T0, rho0, L0);
 }
 
 void launch_dig_gradients(hipStream_t s, const DigGeom& g, const double* prim, double* grad, const DigCtl* ctl) {
-    hipLaunchKernelGGL(k_dig_grad, cells_grid(4 * (int64_t)g.nt), dim3(kDigThreads), 0, s, g, prim, grad, ctl);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_grad), cells_grid(4 * (int64_t)g.nt), dim3(kDigThreads), 0, s, g, prim, grad,
+                       ctl);
 }
 
 void launch_dig_hot(hipStream_t s, const DigGeom& g, DigWork w) {
-    hipLaunchKernelGGL(k_dig_hot, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_hot), cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w);
 }
 
 void launch_dig_gate(hipStream_t s, const DigGeom& g, DigWork w, double kn_max, int passes) {
     const dim3 gr = cells_grid(g.nt), bl(kDigThreads);
-    hipLaunchKernelGGL(k_dig_gate_init, gr, bl, 0, s, g, w, kn_max);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_gate_init), gr, bl, 0, s, g, w, kn_max);
     for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_dig_gate_pass, gr, bl, 0, s, g, w);
-        hipLaunchKernelGGL(k_dig_gate_commit, gr, bl, 0, s, g, w);
+        hipLaunchKernelGGL(DIG_NV(g, k_dig_gate_pass), gr, bl, 0, s, g, w);
+        hipLaunchKernelGGL(DIG_NV(g, k_dig_gate_commit), gr, bl, 0, s, g, w);
     }
-    hipLaunchKernelGGL(k_dig_gate_final, gr, bl, 0, s, g, w);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_gate_final), gr, bl, 0, s, g, w);
 }
 
 void launch_dig_ctl_reset(hipStream_t s, DigCtl* ctl) {
@@ -1015,13 +1201,13 @@ void launch_dig_copy(hipStream_t s, const double* src, double* dst, int64_t n) {
 
 void launch_dig_residual(hipStream_t s, const DigGeom& g, const double* prim, const double* hotf, const double* grad,
                          double* Rs, DigWork w, int first, double cfl) {
-    hipLaunchKernelGGL(k_dig_residual, cells_grid(4 * (int64_t)g.nt), dim3(kDigThreads), 0, s, g, prim, hotf, grad, Rs, w, first,
-                       cfl);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_residual), cells_grid(4 * (int64_t)g.nt), dim3(kDigThreads), 0, s, g, prim,
+                       hotf, grad, Rs, w, first, cfl);
 }
 
 void launch_dig_face_hot(hipStream_t s, const DigGeom& g, const double* prim, const double* grad, const double* hot,
                          double* hotf, int consistent) {
-    hipLaunchKernelGGL(k_dig_face_hot, cells_grid(g.nt), dim3(kDigThreads), 0, s, g, prim, grad, hot, hotf,
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_face_hot), cells_grid(g.nt), dim3(kDigThreads), 0, s, g, prim, grad, hot, hotf,
                        consistent);
 }
 
@@ -1032,15 +1218,16 @@ void launch_dig_iteration(hipStream_t s, const DigGeom& g, DigWork w, double cfl
     const dim3 gr = cells_grid(g.nt), grq = cells_grid(4 * (int64_t)g.nt), bl(kDigThreads);
     const int nblk = (int)grq.x;  // partials of the residual kernel
     const double alpha[3] = {1.0 / 3.0, 0.5, 1.0};
-    hipLaunchKernelGGL(k_dig_save, gr, bl, 0, s, g, w);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_save), gr, bl, 0, s, g, w);
     for (int k = 0; k < 3; ++k) {
-        hipLaunchKernelGGL(k_dig_grad, grq, bl, 0, s, g, (const double*)w.stage, w.grad, (const DigCtl*)w.ctl);
-        hipLaunchKernelGGL(k_dig_residual, grq, bl, 0, s, g, (const double*)w.stage, (const double*)w.hotf,
-                           (const double*)w.grad, w.Rs, w, k == 0 ? 1 : 0, cfl);
+        hipLaunchKernelGGL(DIG_NV(g, k_dig_grad), grq, bl, 0, s, g, (const double*)w.stage, w.grad,
+                           (const DigCtl*)w.ctl);
+        hipLaunchKernelGGL(DIG_NV(g, k_dig_residual), grq, bl, 0, s, g, (const double*)w.stage,
+                           (const double*)w.hotf, (const double*)w.grad, w.Rs, w, k == 0 ? 1 : 0, cfl);
         if (k == 0) hipLaunchKernelGGL(k_dig_check, dim3(1), bl, 0, s, w, nblk, it, eps_m);
-        hipLaunchKernelGGL(k_dig_update, gr, bl, 0, s, g, w, alpha[k], global_dt);
+        hipLaunchKernelGGL(DIG_NV(g, k_dig_update), gr, bl, 0, s, g, w, alpha[k], global_dt);
     }
-    hipLaunchKernelGGL(k_dig_commit, gr, bl, 0, s, g, w);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_commit), gr, bl, 0, s, g, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -1157,7 +1344,7 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_mass_cases(DigGeom g, DigWo
     DigCase& k = g.cases[blockIdx.x];
     double m = 0.0;
     for (int c = k.first + (int)threadIdx.x; c < k.end; c += kDigThreads)
-        m += w.prim[kDigNV * (size_t)c] * g.vol[c];
+        m += w.prim[(g.dr ? kDigNVR : kDigNV) * (size_t)c] * g.vol[c];
     __shared__ double tot, dummy;
     block_sum_min(m, 0.0, &tot, &dummy);
     __syncthreads();
@@ -1169,7 +1356,8 @@ __global__ __launch_bounds__(kDigThreads) void k_dig_mass_cases(DigGeom g, DigWo
 
 __global__ void k_dig_mass_apply_cases(DigGeom g, DigWork w) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < g.nt) w.prim[kDigNV * (size_t)c] = w.prim[kDigNV * (size_t)c] * g.cases[g.cell_case[c]].mass_scale;
+    const size_t nv = g.dr ? kDigNVR : kDigNV;
+    if (c < g.nt) w.prim[nv * (size_t)c] = w.prim[nv * (size_t)c] * g.cases[g.cell_case[c]].mass_scale;
 }
 
 __global__ void k_dig_case_pids(DigGeom g, DigWork w) {
@@ -1194,9 +1382,9 @@ void launch_dig_mass_rescale(hipStream_t s, const DigGeom& g, DigWork w, const S
         hipLaunchKernelGGL(k_dig_mass_apply_cases, gr, bl, 0, s, g, w);
         return;
     }
-    hipLaunchKernelGGL(k_dig_mass_partial, gr, bl, 0, s, g, w);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_mass_partial), gr, bl, 0, s, g, w);
     hipLaunchKernelGGL(k_dig_mass_factor, dim3(1), bl, 0, s, g, w, (int)gr.x, sc);
-    hipLaunchKernelGGL(k_dig_mass_apply, gr, bl, 0, s, g, w);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_mass_apply), gr, bl, 0, s, g, w);
 }
 
 void launch_dig_case_pids(hipStream_t s, const DigGeom& g, const DigWork& w) {

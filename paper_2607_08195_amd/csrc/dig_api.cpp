@@ -145,6 +145,10 @@ dsmc_status upload(dsmc_ctx c, T* dst, const std::vector<T>& src) {
     return DSMC_OK;
 }
 
+int dig_nv(dsmc_ctx c) { return c->dr ? kDigNVR : kDigNV; }
+int dig_nh(dsmc_ctx c) { return c->dr ? 12 : 9; }
+int dig_ns(dsmc_ctx c) { return c->dr ? 18 : 14; }
+
 dsmc_status ensure(dsmc_ctx c) {
     if (c->dig) return DSMC_OK;
     HostGeom G;
@@ -157,15 +161,17 @@ dsmc_status ensure(dsmc_ctx c) {
     int32_t* flink;
     DigGroup* groups;
     DigWork& w = d->w;
+    // widths per cell: primitives, HoT, sampled values (rotating gas: 6, 12, 18)
+    const size_t nv = dig_nv(c), nh = dig_nh(c), ns = dig_ns(c);
     bool ok = alloc_n(c, cen, G.cen.size()) && alloc_n(c, fcen, G.fcen.size()) && alloc_n(c, fnu, G.fnu.size()) &&
               alloc_n(c, farea, G.farea.size()) && alloc_n(c, fdx, G.fdx.size()) && alloc_n(c, lsq, G.lsq.size()) &&
               alloc_n(c, flink, G.flink.size()) && alloc_n(c, groups, ng + 1);
-    ok = ok && alloc_n(c, w.samp, 14 * (size_t)nt) && alloc_n(c, w.ok, nt) && alloc_n(c, w.prim, 5 * (size_t)nt) &&
-         alloc_n(c, w.half, 5 * (size_t)nt) && alloc_n(c, w.hot, 9 * (size_t)nt) && alloc_n(c, w.hotf, 36 * (size_t)nt) &&
-         alloc_n(c, w.grad, 15 * (size_t)nt) && alloc_n(c, w.kn, nt) && alloc_n(c, w.avail, nt) &&
-         alloc_n(c, w.navail, nt) && alloc_n(c, w.nprim, 5 * (size_t)nt) && alloc_n(c, w.nhot, 9 * (size_t)nt) &&
-         alloc_n(c, w.state, nt) && alloc_n(c, w.mprev, 5 * (size_t)nt) && alloc_n(c, w.Rs, 5 * (size_t)nt) &&
-         alloc_n(c, w.dt, nt) && alloc_n(c, w.U0, 5 * (size_t)nt) && alloc_n(c, w.stage, 5 * (size_t)nt) &&
+    ok = ok && alloc_n(c, w.samp, ns * nt) && alloc_n(c, w.ok, nt) && alloc_n(c, w.prim, nv * nt) &&
+         alloc_n(c, w.half, nv * nt) && alloc_n(c, w.hot, nh * nt) && alloc_n(c, w.hotf, 4 * nh * nt) &&
+         alloc_n(c, w.grad, 3 * nv * nt) && alloc_n(c, w.kn, nt) && alloc_n(c, w.avail, nt) &&
+         alloc_n(c, w.navail, nt) && alloc_n(c, w.nprim, nv * nt) && alloc_n(c, w.nhot, nh * nt) &&
+         alloc_n(c, w.state, nt) && alloc_n(c, w.mprev, nv * nt) && alloc_n(c, w.Rs, nv * nt) &&
+         alloc_n(c, w.dt, nt) && alloc_n(c, w.U0, nv * nt) && alloc_n(c, w.stage, nv * nt) &&
          alloc_n(c, w.partial, 8 * (size_t)d->nblk) && alloc_n(c, w.ctl, 1) && alloc_n(c, w.fb_cnt, nt) &&
          alloc_n(c, w.fb_off, nt + 1) && alloc_n(c, w.fb_tgt, nt) && alloc_n(c, w.cx, 13 * (size_t)nt) &&
          alloc_n(c, w.ct, 9 * (size_t)nt) && alloc_n(c, w.cs, 9 * (size_t)nt) && alloc_n(c, w.cy, 9 * (size_t)nt) &&
@@ -235,15 +241,16 @@ dsmc_status ensure(dsmc_ctx c) {
             return fail(c, DSMC_E_OOM, "device allocation of the coupling state failed");
         }
     }
-    std::vector<double> mprev(5 * (size_t)nt);
+    std::vector<double> mprev(nv * nt);
     for (int t = 0; t < nt; ++t) {
-        double* p = &mprev[5 * (size_t)t];
+        double* p = &mprev[nv * t];
         const CaseDev& q = cd[case_of[t]];
         p[0] = c->mass * (ncase ? q.n0 : c->n0);
         p[1] = ncase ? q.u0[0] : c->u0[0];
         p[2] = ncase ? q.u0[1] : c->u0[1];
         p[3] = ncase ? q.u0[2] : c->u0[2];
         p[4] = ncase ? q.T0 : c->T0;
+        if (nv == 6) p[5] = p[4];
     }
     dsmc_status st = DSMC_OK;
     if (ncase) st = upload(c, d->g.cases, dc);
@@ -278,6 +285,10 @@ dsmc_status ensure(dsmc_ctx c) {
     g.FN = c->FN;
     g.cell_case = ncase ? c->d_cell_case : nullptr;
     g.n_cases = ncase;
+    g.dr = c->dr;
+    g.zr = c->zr;
+    for (int k = 0; k < 4; ++k) g.a_heat[k] = c->a_heat[k];
+    g.ert = g.R * c->T0;
     for (const dsmc_boundary_desc& b : c->bcs) d->closed = d->closed && b.kind != DSMC_BC_INFLOW && b.kind != DSMC_BC_OUTFLOW;
     // a batch rescales its closed cases (per case, in the kernel)
     for (const DigCase& q : dc) d->closed = d->closed || q.closed;
@@ -545,9 +556,11 @@ extern "C" {
 dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
     dsmc_status st = usable(c);
     if (st != DSMC_OK) return st;
-    if (c->dr) return fail(c, DSMC_E_INVALID, "the synthetic equations are those of a monatomic gas");
     if ((st = check_params(c, p)) != DSMC_OK) return st;
+    if (c->dr && (c->closure || p->accel > 0))
+        return fail(c, DSMC_E_INVALID, "the learned closure and the accelerated solve are monatomic");
     DigState* d = c->dig;
+    const int nv = dig_nv(c);
     hipStream_t s = c->stream;
     const int nt = c->nt;
     Scalars sc;
@@ -563,7 +576,7 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
     const double rho0 = c->mass * c->n0;
 
     launch_dig_ctl_reset(s, d->w.ctl);
-    launch_dig_sampled(s, d->g, c->d_ewma, c->FN, d->w);
+    launch_dig_sampled(s, d->g, c->d_ewma, c->dr ? c->d_rewma : nullptr, c->FN, d->w);
     launch_dig_kn(s, d->g, d->w, kn_ref, T0, rho0, p->L0);
     launch_dig_gradients(s, d->g, d->w.prim, d->w.grad, nullptr);
     launch_dig_hot(s, d->g, d->w);
@@ -573,11 +586,11 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
         launch_dig_closure_gate(s, d->g, d->w, c->gate_tol, c->d_ewma, c->d_ewma_m, c->n_a);
     }
     launch_dig_gate(s, d->g, d->w, p->kn_max, p->passes);
-    launch_dig_copy(s, d->w.prim, d->w.half, 5 * (int64_t)nt);
+    launch_dig_copy(s, d->w.prim, d->w.half, nv * (int64_t)nt);
     // the solve's face HoT, consistent with M^{k+1/2}
     launch_dig_gradients(s, d->g, d->w.half, d->w.grad, nullptr);
     launch_dig_face_hot(s, d->g, d->w.half, d->w.grad, d->w.hot, d->w.hotf, 1);
-    if (p->warm_start) launch_dig_copy(s, d->w.mprev, d->w.prim, 5 * (int64_t)nt);
+    if (p->warm_start) launch_dig_copy(s, d->w.mprev, d->w.prim, nv * (int64_t)nt);
     HIP_TRY(c, hipGetLastError());
     DigCtl h = read_ctl(c, &st);
     if (st != DSMC_OK) return st;
@@ -603,7 +616,7 @@ dsmc_status dig_couple(dsmc_ctx c, const dig_params* p, dig_report* rep) {
             }
             r.fed_back = 1;
         }
-        if (!r.failed) launch_dig_copy(s, d->w.prim, d->w.mprev, 5 * (int64_t)nt);
+        if (!r.failed) launch_dig_copy(s, d->w.prim, d->w.mprev, nv * (int64_t)nt);
     }
     launch_dig_set_local(s, d->g, d->w.state, c->d_local);
     HIP_TRY(c, hipGetLastError());
@@ -619,13 +632,13 @@ dsmc_status dig_get(dsmc_ctx c, int32_t which, void* out) {
     if (!out) return fail(c, DSMC_E_INVALID, "out is NULL");
     const DigWork& w = c->dig->w;
     switch (which) {
-    case DIG_OUT_SAMPLED: return to_host(c, (double*)out, w.samp, 14);
-    case DIG_OUT_HALF: return to_host(c, (double*)out, w.half, 5);
-    case DIG_OUT_NEW: return to_host(c, (double*)out, w.prim, 5);
-    case DIG_OUT_HOT: return to_host(c, (double*)out, w.hot, 9);
+    case DIG_OUT_SAMPLED: return to_host(c, (double*)out, w.samp, dig_ns(c));
+    case DIG_OUT_HALF: return to_host(c, (double*)out, w.half, dig_nv(c));
+    case DIG_OUT_NEW: return to_host(c, (double*)out, w.prim, dig_nv(c));
+    case DIG_OUT_HOT: return to_host(c, (double*)out, w.hot, dig_nh(c));
     case DIG_OUT_KN: return to_host(c, (double*)out, w.kn, 1);
     case DIG_OUT_STATE: return to_host(c, (int32_t*)out, w.state, 1);
-    case DIG_OUT_MPREV: return to_host(c, (double*)out, w.mprev, 5);
+    case DIG_OUT_MPREV: return to_host(c, (double*)out, w.mprev, dig_nv(c));
     default: return fail(c, DSMC_E_INVALID, "unknown coupling output");
     }
 }
@@ -635,14 +648,14 @@ dsmc_status dig_residual(dsmc_ctx c, const double* prim, const double* hot, doub
     if (st != DSMC_OK) return st;
     if (!prim || !hot || !out) return fail(c, DSMC_E_INVALID, "NULL array");
     DigState* d = c->dig;
-    if ((st = to_device(c, d->w.stage, prim, 5)) != DSMC_OK) return st;
-    if ((st = to_device(c, d->w.nhot, hot, 9)) != DSMC_OK) return st;
+    if ((st = to_device(c, d->w.stage, prim, dig_nv(c))) != DSMC_OK) return st;
+    if ((st = to_device(c, d->w.nhot, hot, dig_nh(c))) != DSMC_OK) return st;
     launch_dig_ctl_reset(c->stream, d->w.ctl);
     launch_dig_gradients(c->stream, d->g, d->w.stage, d->w.grad, d->w.ctl);
     launch_dig_face_hot(c->stream, d->g, d->w.stage, d->w.grad, d->w.nhot, d->w.hotf, 0);
     launch_dig_residual(c->stream, d->g, d->w.stage, d->w.hotf, d->w.grad, d->w.Rs, d->w, 0, 1.0);
     HIP_TRY(c, hipGetLastError());
-    return to_host(c, out, d->w.Rs, 5);
+    return to_host(c, out, d->w.Rs, dig_nv(c));
 }
 
 dsmc_status dig_solve(dsmc_ctx c, double* prim, const double* hot, const dig_params* p, dig_report* rep) {
@@ -650,14 +663,15 @@ dsmc_status dig_solve(dsmc_ctx c, double* prim, const double* hot, const dig_par
     if (st != DSMC_OK) return st;
     if ((st = check_params(c, p)) != DSMC_OK) return st;
     if (!prim || !hot) return fail(c, DSMC_E_INVALID, "NULL array");
+    if (c->dr && p->accel > 0) return fail(c, DSMC_E_INVALID, "the accelerated solve is monatomic");
     DigState* d = c->dig;
-    if ((st = to_device(c, d->w.prim, (const double*)prim, 5)) != DSMC_OK) return st;
-    if ((st = to_device(c, d->w.hot, hot, 9)) != DSMC_OK) return st;
+    if ((st = to_device(c, d->w.prim, (const double*)prim, dig_nv(c))) != DSMC_OK) return st;
+    if ((st = to_device(c, d->w.hot, hot, dig_nh(c))) != DSMC_OK) return st;
     launch_dig_gradients(c->stream, d->g, d->w.prim, d->w.grad, nullptr);
     launch_dig_face_hot(c->stream, d->g, d->w.prim, d->w.grad, d->w.hot, d->w.hotf, 0);
     dig_report r{};
     if ((st = run_solve(c, p, &r)) != DSMC_OK) return st;
-    if ((st = to_host(c, prim, d->w.prim, 5)) != DSMC_OK) return st;
+    if ((st = to_host(c, prim, d->w.prim, dig_nv(c))) != DSMC_OK) return st;
     if (rep) *rep = r;
     return DSMC_OK;
 }
@@ -668,8 +682,8 @@ dsmc_status dig_feedback(dsmc_ctx c, const double* prim_old, const double* prim_
     if (st != DSMC_OK) return st;
     if (!prim_old || !prim_new || !state) return fail(c, DSMC_E_INVALID, "NULL array");
     DigState* d = c->dig;
-    if ((st = to_device(c, d->w.half, prim_old, 5)) != DSMC_OK) return st;
-    if ((st = to_device(c, d->w.prim, prim_new, 5)) != DSMC_OK) return st;
+    if ((st = to_device(c, d->w.half, prim_old, dig_nv(c))) != DSMC_OK) return st;
+    if ((st = to_device(c, d->w.prim, prim_new, dig_nv(c))) != DSMC_OK) return st;
     if ((st = to_device(c, d->w.state, state, 1)) != DSMC_OK) return st;
     if ((st = run_feedback(c)) != DSMC_OK) return st;
     if (np_after) {
@@ -694,6 +708,7 @@ dsmc_status dig_batch_enable(dsmc_ctx c, const int32_t* enabled) {
 
 dsmc_status dig_set_closure(dsmc_ctx c, dsmc_mlp net, double gate_tol) {
     if (!c || !(gate_tol >= 0)) return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (c->dr && net) return fail(c, DSMC_E_INVALID, "the learned closure predicts monatomic HoT");
     c->closure = net;
     c->gate_tol = gate_tol;
     return DSMC_OK;
@@ -706,6 +721,21 @@ dsmc_status dig_closure_data(dsmc_ctx c, float* x, float* t, uint8_t* valid) {
     if (x && (st = to_host(c, x, w.cx, 13)) != DSMC_OK) return st;
     if (t && (st = to_host(c, t, w.ct, 9)) != DSMC_OK) return st;
     if (valid && (st = to_host(c, valid, w.cvalid, 1)) != DSMC_OK) return st;
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_set_rot_sums(dsmc_ctx c, int32_t which, const double* sums) {
+    if (!c || !sums || (which != DSMC_SAMPLE_STEADY && which != DSMC_SAMPLE_EWMA))
+        return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (c->broken) return fail(c, DSMC_E_INVALID, "context is in an error state");
+    if (!c->dr) return fail(c, DSMC_E_INVALID, "the gas has no rotational degrees of freedom");
+    const int nt = c->nt;
+    std::vector<double> h((size_t)4 * nt);
+    for (int t = 0; t < nt; ++t)
+        for (int k = 0; k < 4; ++k) h[(size_t)k * nt + t] = sums[(size_t)4 * c->hm.orig[t] + k];
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(which == DSMC_SAMPLE_STEADY ? c->d_racc : c->d_rewma, h.data(), sizeof(double) * h.size(),
+                         hipMemcpyHostToDevice));
     return DSMC_OK;
 }
 

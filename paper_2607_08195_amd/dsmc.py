@@ -34,7 +34,8 @@ class MeshDesc(C.Structure):
 
 class SpeciesDesc(C.Structure):
     _fields_ = [("mass", C.c_double), ("d_ref", C.c_double), ("omega", C.c_double), ("T_ref", C.c_double),
-                ("alpha", C.c_double), ("dof_rot", C.c_int32), ("z_rot", C.c_double)]
+                ("alpha", C.c_double), ("dof_rot", C.c_int32), ("z_rot", C.c_double),
+                ("heat_relax", C.c_double * 4)]
 
 
 class BoundaryDesc(C.Structure):
@@ -158,6 +159,7 @@ _lib.dig_residual.argtypes = [ctx_t, P, P, P]
 _lib.dig_solve.argtypes = [ctx_t, P, P, C.POINTER(DigParams), C.POINTER(DigReport)]
 _lib.dig_feedback.argtypes = [ctx_t, P, P, P, C.POINTER(C.c_int64)]
 _lib.dsmc_set_sums.argtypes = [ctx_t, C.c_int32, P, P]
+_lib.dsmc_set_rot_sums.argtypes = [ctx_t, C.c_int32, P]
 _lib.dsmc_batch_init.argtypes = [C.POINTER(ctx_t), C.c_int32, C.POINTER(MeshDesc), C.POINTER(SpeciesDesc),
                                  P, C.POINTER(BoundaryDesc), C.POINTER(RunDesc)]
 _lib.dsmc_batch_cases.argtypes = [ctx_t, C.POINTER(C.c_int32), P]
@@ -187,7 +189,7 @@ for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_ge
            "dsmc_rot_sample", "dsmc_mesh_decompose", "dsmc_sample_cells", "dsmc_get_state",
            "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
            "dsmc_profile", "dsmc_philox", "dsmc_device_copy", "dig_couple", "dig_get", "dig_residual",
-           "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
+           "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_set_rot_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
            "dsmc_mlp_get_weights", "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train",
            "dsmc_mlp_init_weights", "dsmc_mlp_backward_noalloc", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_surface_sampling", "dsmc_get_surface",
            "dsmc_instant_sampling", "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
@@ -199,7 +201,8 @@ EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_g
             "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
             "dsmc_profile", "dsmc_profile_read", "dsmc_profile_name", "dsmc_philox", "dsmc_device_copy",
             "dsmc_last_error", "dsmc_destroy", "dig_couple", "dig_get", "dig_residual", "dig_solve",
-            "dig_feedback", "dsmc_set_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights", "dsmc_mlp_get_weights",
+            "dig_feedback", "dsmc_set_sums", "dsmc_set_rot_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
+            "dsmc_mlp_get_weights",
             "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_backward_noalloc", "dsmc_mlp_adam_step",
             "dsmc_mlp_train", "dsmc_mlp_last_error",
             "dsmc_mlp_destroy", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_surface_sampling",
@@ -327,8 +330,11 @@ class Simulation:
             bcs[i] = BoundaryDesc(b.kind, b.T, (C.c_double * 3)(*b.u), b.n, (C.c_double * 3)(*b.shift))
         sp = cases[0].species
         sd = SpeciesDesc(sp.mass, sp.d_ref, sp.omega, sp.T_ref, sp.alpha, int(getattr(sp, "dof_rot", 0)),
-                         float(getattr(sp, "z_rot", 0.0)))
+                         float(getattr(sp, "z_rot", 0.0)),
+                         (C.c_double * 4)(*getattr(sp, "a_heat", (0.0, 0.0, 0.0, 0.0))))
         self.dof_rot = int(getattr(sp, "dof_rot", 0))
+        # widths of the coupling arrays: primitives, HoT, sampled values
+        self.nv, self.nh, self.nsw = (6, 12, 18) if self.dof_rot else (5, 9, 14)
         self.ctx = ctx_t()
         if len(cases) == 1 and not isinstance(wl, (list, tuple)):
             _check(_lib.dsmc_init(C.byref(self.ctx), C.byref(meshes[0]), C.byref(sd), int(nbc[0]), bcs,
@@ -503,6 +509,11 @@ class Simulation:
         self._c(_lib.dsmc_set_sums(self.ctx, which, _p(a), _p(m)))
 
     # -- DIG coupling (include/dig.h) ------------------------------------
+    def set_rot_sums(self, which, sums):
+        """Replace the rotational sums of an accumulator (dsmc_set_rot_sums)."""
+        sums = np.ascontiguousarray(sums, np.float64)
+        self._c(_lib.dsmc_set_rot_sums(self.ctx, which, _p(sums)))
+
     def dig_couple(self, **kw):
         prm = dig_params(**kw)
         rep = DigReport()
@@ -511,6 +522,7 @@ class Simulation:
 
     def dig_get(self, which):
         code, k = DIG_OUT[which]
+        k = {5: self.nv, 9: self.nh, 14: self.nsw}.get(k, k)
         if which == "state":
             out = np.zeros(self.nt, np.int32)
         else:
@@ -520,7 +532,7 @@ class Simulation:
 
     def dig_residual(self, prim, hot):
         prim = np.ascontiguousarray(prim, np.float64); hot = np.ascontiguousarray(hot, np.float64)
-        out = np.zeros((self.nt, 5))
+        out = np.zeros((self.nt, self.nv))
         self._c(_lib.dig_residual(self.ctx, _p(prim), _p(hot), _p(out)))
         return out
 

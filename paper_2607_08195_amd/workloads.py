@@ -33,6 +33,9 @@ class Species:
     alpha: float = 1.0          # 1 = VHS
     dof_rot: int = 0            # rotational degrees of freedom (0 or 2)
     z_rot: float = 0.0          # rotational collision number
+    # heat-flux relaxation coefficients A_tt, A_tr, A_rt, A_rr of a rotating
+    # gas (the conductivity matrix of section 2.2); nitrogen's
+    a_heat: tuple = (0.786, -0.201, -0.059, 0.842)
 
     def mu(self, T):
         """VHS/VSS viscosity at temperature T (power law in T with index
