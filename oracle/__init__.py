@@ -93,7 +93,7 @@ def _load():
 class DigParams(C.Structure):
     _fields_ = [("kn_max", C.c_double), ("passes", C.c_int), ("n_m", C.c_int), ("eps_m", C.c_double),
                 ("cfl", C.c_double), ("L0", C.c_double), ("feedback", C.c_int), ("global_dt", C.c_int),
-                ("warm_start", C.c_int), ("unconverged", C.c_int)]
+                ("warm_start", C.c_int), ("unconverged", C.c_int), ("solver", C.c_int), ("krylov", C.c_int)]
 
 
 class DigReport(C.Structure):
@@ -103,8 +103,9 @@ class DigReport(C.Structure):
 
 
 def dig_params(kn_max=1.0, passes=3, n_m=200, eps_m=1e-6, cfl=0.5, L0=1.0, feedback=1, global_dt=0, warm_start=0,
-               unconverged=0):
-    return DigParams(kn_max, passes, n_m, eps_m, cfl, L0, feedback, global_dt, warm_start, unconverged)
+               unconverged=0, solver=0, krylov=0):
+    return DigParams(kn_max, passes, n_m, eps_m, cfl, L0, feedback, global_dt, warm_start, unconverged, solver,
+                     krylov)
 
 
 def _report_dict(r):

@@ -786,6 +786,234 @@ static int solve_faces(osim* s, double* prim, const double* hotf, const odig_par
     return failed ? -1 : 0;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Newton-Krylov solve of the same steady equations                         */
+/* ---------------------------------------------------------------------- */
+/* The steady discrete equations R(U) = 0 of the marching above, solved by
+ * Newton's method with pseudo-transient continuation (Kelley and Keyes,
+ * SIAM J. Numer. Anal. 35, 1998): step k solves
+ *     (diag(S_c) / c_k + J(U_k)) dU = -R(U_k)
+ * approximately, S_c being the sum that sets the local pseudo-time step of
+ * the marching (V_c / dtau_c = S_c / cfl), and c_k the pseudo-time CFL
+ * number, grown by the ratio of successive residual norms (switched
+ * evolution relaxation, Mulder and van Leer, J. Comput. Phys. 59, 1985)
+ * from the caller's cfl, within [cfl, NK_CFL_MAX].  The linear system is
+ * solved by one cycle of at most m steps of GMRES (Saad and Schultz, SIAM J.
+ * Sci. Stat. Comput. 7, 1986) from zero, with classical Gram-Schmidt applied
+ * twice, Givens rotations, and a stop at NK_ETA of the initial linear
+ * residual; products with the Jacobian are forward differences of the
+ * residual (Knoll and Keyes, J. Comput. Phys. 193, 2004).  Unknowns and
+ * equations are scaled by the reference state (density rho0, momentum
+ * rho0 a0, energies rho0 a0^2, a0^2 = R T0), and the preconditioner on the
+ * right divides cell c's unknowns by S_c (1 + 1/c_k) (the pseudo-time
+ * operator's diagonal).  An update that leaves a cell non-physical is
+ * halved, at most NK_HALVINGS times; then the solve fails.  The stopping test is
+ * that of the marching (density residual, with rotation the rotational
+ * energy residual too, against eps_m times its first value), taken at the
+ * start of each Newton step; iters counts the updates made. */
+#define NK_ETA 0.05
+#define NK_CFL_MAX 1e8
+#define NK_FD 1e-7
+#define NK_HALVINGS 10
+
+static double conv_norm(const osim* s, const double* Rs) {
+    int nv = nv_of(s);
+    double acc = 0.0, ert = (KB / s->m) * s->ref_T;
+    for (int c = 0; c < s->nt; ++c) {
+        double r0 = Rs[nv * (size_t)c];
+        acc += r0 * r0;
+        if (s->dr) {
+            double r5 = Rs[nv * (size_t)c + 5] / ert;
+            acc += r5 * r5;
+        }
+    }
+    return sqrt(acc);
+}
+
+static int solve_nk(osim* s, double* prim, const double* hotf, const odig_params* prm, odig_report* rep) {
+    const int nt = s->nt, nv = nv_of(s);
+    const size_t n = (size_t)nv * nt;
+    const int m = prm->krylov > 0 ? prm->krylov : 40;
+    const double R = KB / s->m;
+    const double rho0 = s->m * s->ref_n, a2 = R * s->ref_T, a0 = sqrt(a2);
+    double sc[NVX];
+    sc[0] = rho0;
+    sc[1] = sc[2] = sc[3] = rho0 * a0;
+    sc[4] = sc[5] = rho0 * a2;
+    double* g = (double*)malloc(sizeof(double) * GS * (size_t)nt);
+    double* R0 = (double*)malloc(sizeof(double) * n);
+    double* Rp = (double*)malloc(sizeof(double) * n);
+    double* spec = (double*)malloc(sizeof(double) * (size_t)nt);
+    double* specp = (double*)malloc(sizeof(double) * (size_t)nt);
+    double* pc = (double*)malloc(sizeof(double) * (size_t)nt);
+    double* U = (double*)malloc(sizeof(double) * n);
+    double* Ut = (double*)malloc(sizeof(double) * n);
+    double* Pt = (double*)malloc(sizeof(double) * n);
+    double* V = (double*)malloc(sizeof(double) * n * (size_t)(m + 1));
+    double* w = (double*)malloc(sizeof(double) * n);
+    double* z = (double*)malloc(sizeof(double) * n);
+    double* H = (double*)calloc((size_t)(m + 1) * m, sizeof(double));
+    double* cs = (double*)malloc(sizeof(double) * m);
+    double* sn = (double*)malloc(sizeof(double) * m);
+    double* gv = (double*)malloc(sizeof(double) * (m + 1));
+    double* y = (double*)malloc(sizeof(double) * m);
+    double* h = (double*)malloc(sizeof(double) * (m + 1));
+    for (int c = 0; c < nt; ++c) cons_of(s, prim + nv * (size_t)c, U + nv * (size_t)c);
+    double res0 = 0.0, res = 0.0, cfl = prm->cfl, bprev = 0.0;
+    int k = 0, conv = 0, failed = 0;
+    for (k = 0; k < prm->n_m; ++k) {
+        gradients(s, prim, g);
+        residual_all(s, prim, hotf, g, R0, spec);
+        res = conv_norm(s, R0);
+        if (k == 0) res0 = res;
+        if (!(res0 > 0) || res <= prm->eps_m * res0) {
+            conv = 1;
+            break;
+        }
+        /* right-hand side -R in scaled units, its norm, the CFL number */
+        double beta = 0.0;
+        for (size_t e = 0; e < n; ++e) {
+            V[e] = -R0[e] / sc[e % nv];
+            beta += V[e] * V[e];
+        }
+        beta = sqrt(beta);
+        if (k > 0) {
+            cfl = cfl * (bprev / beta);
+            if (cfl < prm->cfl) cfl = prm->cfl;
+            if (cfl > NK_CFL_MAX) cfl = NK_CFL_MAX;
+        }
+        bprev = beta;
+        for (int c = 0; c < nt; ++c) pc[c] = spec[c] * (1.0 + 1.0 / cfl);
+        double xr = 0.0;
+        for (size_t e = 0; e < n; ++e) {
+            double x = U[e] / sc[e % nv];
+            xr += x * x;
+        }
+        xr = sqrt(xr / (double)n);
+        for (size_t e = 0; e < n; ++e) V[e] = V[e] / beta;
+        memset(H, 0, sizeof(double) * (size_t)(m + 1) * m);
+        gv[0] = beta;
+        int jn = 0;
+        for (int j = 0; j < m; ++j) {
+            const double* vj = V + n * (size_t)j;
+            /* w = B v_j: the preconditioned direction in U, a forward
+             * difference of the residual along it, the pseudo-time diagonal */
+            double vn = 0.0;
+            for (int c = 0; c < nt; ++c)
+                for (int v = 0; v < nv; ++v) {
+                    double q = vj[nv * (size_t)c + v] / pc[c];
+                    vn += q * q;
+                }
+            vn = sqrt(vn / (double)n);
+            double eps = NK_FD * (1.0 + xr) / vn;
+            int ok = 1;
+            for (int c = 0; c < nt && ok; ++c) {
+                for (int v = 0; v < nv; ++v) {
+                    size_t e = nv * (size_t)c + v;
+                    Ut[e] = U[e] + eps * (sc[v] * vj[e] / pc[c]);
+                }
+                ok = prim_of(s, Ut + nv * (size_t)c, Pt + nv * (size_t)c);
+            }
+            if (!ok) {
+                failed = 1;
+                break;
+            }
+            gradients(s, Pt, g);
+            residual_all(s, Pt, hotf, g, Rp, specp);
+            for (int c = 0; c < nt; ++c)
+                for (int v = 0; v < nv; ++v) {
+                    size_t e = nv * (size_t)c + v;
+                    double du = sc[v] * vj[e] / pc[c];
+                    w[e] = ((Rp[e] - R0[e]) / eps + spec[c] / cfl * du) / sc[v];
+                }
+            /* classical Gram-Schmidt, twice */
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int i = 0; i <= j; ++i) {
+                    const double* vi = V + n * (size_t)i;
+                    double d = 0.0;
+                    for (size_t e = 0; e < n; ++e) d += vi[e] * w[e];
+                    h[i] = d;
+                }
+                for (size_t e = 0; e < n; ++e) {
+                    double t = w[e];
+                    for (int i = 0; i <= j; ++i) t -= h[i] * V[n * (size_t)i + e];
+                    w[e] = t;
+                }
+                for (int i = 0; i <= j; ++i) H[i * m + j] += h[i];
+            }
+            double hn = 0.0;
+            for (size_t e = 0; e < n; ++e) hn += w[e] * w[e];
+            hn = sqrt(hn);
+            H[(j + 1) * m + j] = hn;
+            if (hn > 0)
+                for (size_t e = 0; e < n; ++e) V[n * (size_t)(j + 1) + e] = w[e] / hn;
+            /* the earlier rotations, then a new one that zeroes H[j+1][j] */
+            for (int i = 0; i < j; ++i) {
+                double a = H[i * m + j], b = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * b;
+                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            double a = H[j * m + j], b = H[(j + 1) * m + j];
+            double r = sqrt(a * a + b * b);
+            cs[j] = r > 0 ? a / r : 1.0;
+            sn[j] = r > 0 ? b / r : 0.0;
+            H[j * m + j] = r;
+            H[(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            jn = j + 1;
+            if (fabs(gv[j + 1]) <= NK_ETA * beta || !(hn > 0)) break;
+        }
+        if (failed) break;
+        /* y from the triangular system, z = V y, dU = preconditioned z */
+        for (int i = jn - 1; i >= 0; --i) {
+            double t = gv[i];
+            for (int l = i + 1; l < jn; ++l) t -= H[i * m + l] * y[l];
+            y[i] = t / H[i * m + i];
+        }
+        for (size_t e = 0; e < n; ++e) {
+            double t = 0.0;
+            for (int i = 0; i < jn; ++i) t += y[i] * V[n * (size_t)i + e];
+            z[e] = t;
+        }
+        double alpha = 1.0;
+        int accepted = 0;
+        for (int tries = 0; tries <= NK_HALVINGS && !accepted; ++tries) {
+            int ok = 1;
+            for (int c = 0; c < nt && ok; ++c) {
+                for (int v = 0; v < nv; ++v) {
+                    size_t e = nv * (size_t)c + v;
+                    Ut[e] = U[e] + alpha * (sc[v] * z[e] / pc[c]);
+                }
+                ok = prim_of(s, Ut + nv * (size_t)c, Pt + nv * (size_t)c);
+            }
+            if (ok)
+                accepted = 1;
+            else
+                alpha = 0.5 * alpha;
+        }
+        if (!accepted) {
+            failed = 1;
+            break;
+        }
+        memcpy(U, Ut, sizeof(double) * n);
+        memcpy(prim, Pt, sizeof(double) * n);
+    }
+    if (rep) {
+        rep->iters = k;
+        rep->residual = res0 > 0 ? res / res0 : 0.0;
+        rep->converged = conv;
+        rep->failed = failed;
+    }
+    free(g); free(R0); free(Rp); free(spec); free(specp); free(pc); free(U); free(Ut); free(Pt); free(V);
+    free(w); free(z); free(H); free(cs); free(sn); free(gv); free(y); free(h);
+    return failed ? -1 : 0;
+}
+
+static int solve_any(osim* s, double* prim, const double* hotf, const odig_params* prm, odig_report* rep) {
+    return prm->solver == 1 ? solve_nk(s, prim, hotf, prm, rep) : solve_faces(s, prim, hotf, prm, rep);
+}
+
 /* The solve with the cell HoT averaged to the faces. */
 int oracle_dig_solve(osim* s, double* prim, const double* hot, const odig_params* prm, odig_report* rep) {
     geometry(s);
@@ -793,7 +1021,7 @@ int oracle_dig_solve(osim* s, double* prim, const double* hot, const odig_params
     double* hotf = (double*)malloc(sizeof(double) * 4 * NHX * (size_t)s->nt);
     gradients(s, prim, g);
     face_hot(s, prim, g, hot, 0, hotf);
-    int rc = solve_faces(s, prim, hotf, prm, rep);
+    int rc = solve_any(s, prim, hotf, prm, rep);
     free(g); free(hotf);
     return rc;
 }
@@ -952,7 +1180,7 @@ int oracle_dig_couple(osim* s, const odig_params* prm, odig_report* rep) {
     /* the steady solve may start from the previous macroscopic solution */
     if (prm->warm_start) memcpy(prim, s->mprev, sizeof(double) * nv * (size_t)nt);
     if (r.n_rejected < nt) {
-        solve_faces(s, prim, hotf, prm, &r);
+        solve_any(s, prim, hotf, prm, &r);
         /* only the solution of the synthetic equations is fed back: a solve
          * that stopped short of eps_m leaves the particles unchanged unless
          * the caller asks otherwise */

@@ -127,6 +127,10 @@ typedef struct {
     int global_dt;  /* 1: one pseudo-time step for all cells (conservative) */
     int warm_start; /* 1: the solve starts from M^k instead of M^{k+1/2} */
     int unconverged; /* 1: feed back also a solve that stopped at n_m */
+    int solver;     /* 0: three-stage pseudo-time marching; 1: Newton-Krylov
+                       (n_m counts Newton steps, cfl is the initial
+                       pseudo-time CFL number of the continuation) */
+    int krylov;     /* GMRES steps per Newton step (0: 40) */
 } odig_params;
 
 typedef struct {
