@@ -70,6 +70,13 @@ typedef struct {
                            the particle feedback follow only a solve that
                            reached eps_m; 1: also a solve that stopped at
                            n_m iterations (never one that failed) */
+    int32_t solver;     /* 0: three-stage pseudo-time marching (n_m
+                           iterations); 1: Newton-Krylov solve of the same
+                           steady equations (n_m Newton steps; cfl is the
+                           initial CFL number of its pseudo-transient
+                           continuation; not with accel, global_dt or a
+                           batch) */
+    int32_t krylov;     /* GMRES steps per Newton step, 0 (default 40) to 100 */
 } dig_params;
 
 typedef struct {

@@ -163,6 +163,55 @@ void launch_aa_dots(hipStream_t s, const DigGeom& g, const AaWork& a, int slot, 
 // counts them.
 void launch_aa_update(hipStream_t s, const DigGeom& g, const AaWork& a, int cnt, double* prim, int parity);
 
+// Newton-Krylov solve of the steady equations: pseudo-transient
+// continuation (Kelley and Keyes 1998) with one GMRES(m) cycle per Newton
+// step (Saad and Schultz 1986), Jacobian products by forward differences of
+// the residual (Knoll and Keyes 2004), unknowns and equations scaled by
+// NkScale, right preconditioning by the pseudo-time diagonal.
+constexpr int kNkMaxKrylov = 100;
+struct NkScale {
+    double s[kDigNVR];  // rho0, rho0 a0 (3), rho0 a0^2 (energy, and rho e_r)
+};
+struct NkWork {
+    double* V;     // [m + 1][nt][NV] Krylov basis
+    double* w;     // [nt][NV] new direction
+    double* U;     // [nt][NV] conserved state of the Newton iterate
+    double* Ut;    // [nt][NV] trial state
+    double* R0;    // [nt][NV] residual at U
+    double* Rp;    // [nt][NV] residual at the perturbed state
+    double* part;  // [m + 1][blocks] block partials
+    double* red;   // reduced values, slots below
+    double* y;     // [m] coefficients of the update
+    int32_t* flag; // a trial or perturbed cell was not physical
+    int m;
+};
+// Slots of NkWork::red: first and second Gram-Schmidt coefficients, |w|^2,
+// |V/p|^2 and the finite-difference step of the next product, |b|^2 and
+// |U/scale|^2 of the Newton step.
+__host__ __device__ constexpr int kNkH1(int m) { return 0; }
+__host__ __device__ constexpr int kNkH2(int m) { return m + 1; }
+__host__ __device__ constexpr int kNkHn2(int m) { return 2 * m + 2; }
+__host__ __device__ constexpr int kNkVs2(int m) { return 2 * m + 3; }
+__host__ __device__ constexpr int kNkEps(int m) { return 2 * m + 4; }
+__host__ __device__ constexpr int kNkBeta2(int m) { return 2 * m + 5; }
+__host__ __device__ constexpr int kNkXr2(int m) { return 2 * m + 6; }
+__host__ __device__ constexpr int kNkRedSize(int m) { return 2 * m + 7; }
+// Residual and spectral sums at w.prim (w.Rs, w.dt = V / S), the stopping
+// test of Newton step `it` (w.ctl), R0, U (from w.prim when it == 0), V_0 =
+// -R0 / scale; |V_0|^2 and |U/scale|^2 into red.
+void launch_nk_begin(hipStream_t s, const DigGeom& g, DigWork w, NkWork nk, NkScale sc, int it, double eps_m);
+// V_0 /= sqrt(red[beta2]) and the finite-difference step of its product.
+void launch_nk_scale(hipStream_t s, const DigGeom& g, DigWork w, NkWork nk, double cfl, double fd);
+// Arnoldi step j: the product with V_j, two Gram-Schmidt passes (H column j
+// = red[H1] + red[H2], |w|^2 in red[Hn2]), V_{j+1} and the next step.
+void launch_nk_arnoldi(hipStream_t s, const DigGeom& g, DigWork w, NkWork nk, NkScale sc, int j, double cfl,
+                       double fd);
+// Trial state U + alpha P^-1 V y (y in nk.y, jn terms) into nk.Ut, w.stage.
+void launch_nk_try(hipStream_t s, const DigGeom& g, DigWork w, NkWork nk, NkScale sc, int jn, double alpha,
+                   double cfl);
+// U = Ut, w.prim = w.stage.
+void launch_nk_commit(hipStream_t s, const DigGeom& g, DigWork w, NkWork nk);
+
 // Local-accumulation flags from the gate states (cases of a batch that are
 // not coupled keep theirs).
 void launch_dig_set_local(hipStream_t s, const DigGeom& g, const int32_t* state, uint8_t* local);

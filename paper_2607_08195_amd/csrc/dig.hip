@@ -1338,6 +1338,327 @@ void launch_aa_update(hipStream_t s, const DigGeom& g, const AaWork& a, int cnt,
                        (const double*)a.dG, (const double*)a.gam, cnt, prim, a.red + 2 * a.m + parity);
 }
 
+// ---------------------------------------------------------------------------
+// Newton-Krylov solve (pseudo-transient continuation, one GMRES cycle per
+// Newton step, Jacobian products by forward differences of the residual)
+// ---------------------------------------------------------------------------
+// One lane per cell.  Unknowns and equations are scaled per variable by
+// NkScale; the right preconditioner divides cell c's unknowns by
+// p_c = S_c (1 + 1/cfl), S_c = V_c / dt_c the sum that sets the marching's
+// local step (the residual kernel's dt at CFL number 1).  Inner products are
+// reduced in a fixed order: wave, then the block's four waves, then
+// k_nk_reduce over the blocks.
+
+// Per-column block partials: column i's value of this lane is added over the
+// block and written to part[i * nblk + block].
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void nk_block_column(double (*red)[kDigThreads / 64], int i, double v) {
+    v = wave_sum_d(v);
+    if ((threadIdx.x & 63) == 0) red[i][threadIdx.x >> 6] = v;
+}
+
+__device__ __forceinline__ void nk_block_store(double (*red)[kDigThreads / 64], int ncol, double* part) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < ncol; i += blockDim.x)
+        part[(size_t)i * gridDim.x + blockIdx.x] = ((red[i][0] + red[i][1]) + red[i][2]) + red[i][3];
+}
+
+// Fixed-order sum over the blocks of column blockIdx.x into out[blockIdx.x].
+__global__ __launch_bounds__(kDigThreads) void k_nk_reduce(const double* part, int nblk, double* out) {
+    const double* p = part + (size_t)blockIdx.x * nblk;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kDigThreads) s += p[b];
+    __shared__ double tot, dummy;
+    block_sum_min(s, 0.0, &tot, &dummy);
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
+// The finite-difference step of the next product from the reduced
+// sum of squares of the preconditioned direction and that of the state.
+__global__ __launch_bounds__(kDigThreads) void k_nk_reduce_eps(const double* part, int nblk, double* red, int m,
+                                                                double n, double fd) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kDigThreads) s += part[b];
+    __shared__ double tot, dummy;
+    block_sum_min(s, 0.0, &tot, &dummy);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        red[kNkVs2(m)] = tot;
+        const double vn = sqrt(tot / n), xr = sqrt(red[kNkXr2(m)] / n);
+        red[kNkEps(m)] = fd * (1.0 + xr) / vn;
+    }
+}
+
+// Start of a Newton step: R0 = the residual just computed; U from the
+// primitives on the first step; V_0 = -R0 / scale; partials of |V_0|^2 and
+// |U / scale|^2.
+template <int NV>
+__global__ __launch_bounds__(kDigThreads) void k_nk_start(DigGeom g, DigWork w, NkWork nk, NkScale sc, int first) {
+    __shared__ double red[2][kDigThreads / 64];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double b2 = 0.0, x2 = 0.0;
+    if (c < g.nt) {
+        double U[NV];
+        if (first) {
+            double P[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) P[v] = w.prim[NV * (size_t)c + v];
+            cons_of<NV>(g, P, U);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) nk.U[NV * (size_t)c + v] = U[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) U[v] = nk.U[NV * (size_t)c + v];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const size_t e = NV * (size_t)c + v;
+            const double r = w.Rs[e];
+            nk.R0[e] = r;
+            const double b = -r / sc.s[v];
+            nk.V[e] = b;
+            b2 += b * b;
+            const double x = U[v] / sc.s[v];
+            x2 += x * x;
+        }
+    }
+    nk_block_column(red, 0, b2);
+    nk_block_column(red, 1, x2);
+    nk_block_store(red, 2, nk.part);
+}
+
+// V_0 /= beta; partial of |V_0 / p|^2 (the next finite-difference step).
+template <int NV>
+__global__ __launch_bounds__(kDigThreads) void k_nk_scale(DigGeom g, DigWork w, NkWork nk, double cfl) {
+    __shared__ double red[1][kDigThreads / 64];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double q2 = 0.0;
+    if (c < g.nt) {
+        const double beta = sqrt(nk.red[kNkBeta2(nk.m)]);
+        const double pc = g.vol[c] / w.dt[c] * (1.0 + 1.0 / cfl);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const size_t e = NV * (size_t)c + v;
+            const double x = nk.V[e] / beta;
+            nk.V[e] = x;
+            const double q = x / pc;
+            q2 += q * q;
+        }
+    }
+    nk_block_column(red, 0, q2);
+    nk_block_store(red, 1, nk.part);
+}
+
+// The state perturbed along the preconditioned direction V_j, as
+// primitives in w.stage; a cell that is not physical sets the flag.
+template <int NV>
+__global__ __launch_bounds__(kDigThreads) void k_nk_perturb(DigGeom g, DigWork w, NkWork nk, NkScale sc, int j,
+                                                            double cfl) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt) return;
+    const double eps = nk.red[kNkEps(nk.m)];
+    const double pc = g.vol[c] / w.dt[c] * (1.0 + 1.0 / cfl);
+    const double* vj = nk.V + (size_t)j * NV * g.nt;
+    double U[NV], P[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const size_t e = NV * (size_t)c + v;
+        U[v] = nk.U[e] + eps * (sc.s[v] * vj[e] / pc);
+    }
+    if (!prim_of<NV>(g, U, P)) atomicOr(nk.flag, 1);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w.stage[NV * (size_t)c + v] = P[v];
+}
+
+// w = scaled ((R(U + eps d) - R(U)) / eps + S / cfl d), d the preconditioned
+// V_j; partials of <V_i, w>, i <= j (the first Gram-Schmidt pass).
+template <int NV>
+__global__ __launch_bounds__(kDigThreads) void k_nk_matvec(DigGeom g, DigWork w, NkWork nk, NkScale sc, int j,
+                                                           double cfl) {
+    __shared__ double red[kNkMaxKrylov + 1][kDigThreads / 64];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = c < g.nt;
+    const size_t n = (size_t)NV * g.nt;
+    double wv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) wv[v] = 0.0;
+    if (live) {
+        const double eps = nk.red[kNkEps(nk.m)];
+        const double sp = g.vol[c] / w.dt[c];
+        const double pc = sp * (1.0 + 1.0 / cfl);
+        const double* vj = nk.V + (size_t)j * n;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const size_t e = NV * (size_t)c + v;
+            const double du = sc.s[v] * vj[e] / pc;
+            wv[v] = ((nk.Rp[e] - nk.R0[e]) / eps + sp / cfl * du) / sc.s[v];
+            nk.w[e] = wv[v];
+        }
+    }
+    for (int i = 0; i <= j; ++i) {
+        double d = 0.0;
+        if (live) {
+            const double* vi = nk.V + (size_t)i * n + NV * (size_t)c;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) d += vi[v] * wv[v];
+        }
+        nk_block_column(red, i, d);
+    }
+    nk_block_store(red, j + 1, nk.part);
+}
+
+// w -= sum_{i <= j} h_i V_i with h = red[off ...]; then partials of the next
+// pass's <V_i, w> (norm = 0) or of |w|^2 (norm = 1).
+template <int NV>
+__global__ __launch_bounds__(kDigThreads) void k_nk_orth(DigGeom g, NkWork nk, int j, int off, int norm) {
+    __shared__ double red[kNkMaxKrylov + 1][kDigThreads / 64];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = c < g.nt;
+    const size_t n = (size_t)NV * g.nt;
+    double wv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) wv[v] = 0.0;
+    if (live) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const size_t e = NV * (size_t)c + v;
+            double t = nk.w[e];
+            for (int i = 0; i <= j; ++i) t -= nk.red[off + i] * nk.V[(size_t)i * n + e];
+            wv[v] = t;
+            nk.w[e] = t;
+        }
+    }
+    if (norm) {
+        double d = 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) d += wv[v] * wv[v];
+        nk_block_column(red, 0, d);
+        nk_block_store(red, 1, nk.part);
+        return;
+    }
+    for (int i = 0; i <= j; ++i) {
+        double d = 0.0;
+        if (live) {
+            const double* vi = nk.V + (size_t)i * n + NV * (size_t)c;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) d += vi[v] * wv[v];
+        }
+        nk_block_column(red, i, d);
+    }
+    nk_block_store(red, j + 1, nk.part);
+}
+
+// V_{j+1} = w / |w| (when |w| > 0); partial of |V_{j+1} / p|^2.
+template <int NV>
+__global__ __launch_bounds__(kDigThreads) void k_nk_normalize(DigGeom g, DigWork w, NkWork nk, int j, double cfl) {
+    __shared__ double red[1][kDigThreads / 64];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double q2 = 0.0;
+    const double hn = sqrt(nk.red[kNkHn2(nk.m)]);
+    if (c < g.nt && hn > 0) {
+        const size_t n = (size_t)NV * g.nt;
+        const double pc = g.vol[c] / w.dt[c] * (1.0 + 1.0 / cfl);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const size_t e = NV * (size_t)c + v;
+            const double x = nk.w[e] / hn;
+            nk.V[(size_t)(j + 1) * n + e] = x;
+            const double q = x / pc;
+            q2 += q * q;
+        }
+    }
+    nk_block_column(red, 0, q2);
+    nk_block_store(red, 1, nk.part);
+}
+
+// Trial state U + alpha dU, dU the preconditioned sum_{i < jn} y_i V_i, into
+// nk.Ut and (as primitives) w.stage; a cell that is not physical sets the
+// flag.
+template <int NV>
+__global__ __launch_bounds__(kDigThreads) void k_nk_try(DigGeom g, DigWork w, NkWork nk, NkScale sc, int jn,
+                                                        double alpha, double cfl) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt) return;
+    const size_t n = (size_t)NV * g.nt;
+    const double pc = g.vol[c] / w.dt[c] * (1.0 + 1.0 / cfl);
+    double U[NV], P[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const size_t e = NV * (size_t)c + v;
+        double z = 0.0;
+        for (int i = 0; i < jn; ++i) z += nk.y[i] * nk.V[(size_t)i * n + e];
+        U[v] = nk.U[e] + alpha * (sc.s[v] * z / pc);
+        nk.Ut[e] = U[v];
+    }
+    if (!prim_of<NV>(g, U, P)) atomicOr(nk.flag, 1);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w.stage[NV * (size_t)c + v] = P[v];
+}
+
+template <int NV>
+__global__ void k_nk_commit(DigGeom g, DigWork w, NkWork nk) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nt) return;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const size_t e = NV * (size_t)c + v;
+        nk.U[e] = nk.Ut[e];
+        w.prim[e] = w.stage[e];
+    }
+}
+
+void launch_nk_begin(hipStream_t s, const DigGeom& g, DigWork w, NkWork nk, NkScale sc, int it, double eps_m) {
+    const dim3 gr = cells_grid(g.nt), grq = cells_grid(4 * (int64_t)g.nt), bl(kDigThreads);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_grad), grq, bl, 0, s, g, (const double*)w.prim, w.grad, (const DigCtl*)nullptr);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_residual), grq, bl, 0, s, g, (const double*)w.prim, (const double*)w.hotf,
+                       (const double*)w.grad, w.Rs, w, 1, 1.0);
+    hipLaunchKernelGGL(k_dig_check, dim3(1), bl, 0, s, w, (int)grq.x, it, eps_m);
+    hipLaunchKernelGGL(DIG_NV(g, k_nk_start), gr, bl, 0, s, g, w, nk, sc, it == 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_nk_reduce, dim3(2), bl, 0, s, (const double*)nk.part, (int)gr.x, nk.red + kNkBeta2(nk.m));
+}
+
+void launch_nk_scale(hipStream_t s, const DigGeom& g, DigWork w, NkWork nk, double cfl, double fd) {
+    const dim3 gr = cells_grid(g.nt), bl(kDigThreads);
+    hipLaunchKernelGGL(DIG_NV(g, k_nk_scale), gr, bl, 0, s, g, w, nk, cfl);
+    hipLaunchKernelGGL(k_nk_reduce_eps, dim3(1), bl, 0, s, (const double*)nk.part, (int)gr.x, nk.red, nk.m,
+                       (double)(g.dr ? kDigNVR : kDigNV) * g.nt, fd);
+}
+
+void launch_nk_arnoldi(hipStream_t s, const DigGeom& g, DigWork w, NkWork nk, NkScale sc, int j, double cfl,
+                       double fd) {
+    const dim3 gr = cells_grid(g.nt), grq = cells_grid(4 * (int64_t)g.nt), bl(kDigThreads);
+    const int nblk = (int)gr.x, m = nk.m;
+    hipLaunchKernelGGL(DIG_NV(g, k_nk_perturb), gr, bl, 0, s, g, w, nk, sc, j, cfl);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_grad), grq, bl, 0, s, g, (const double*)w.stage, w.grad,
+                       (const DigCtl*)nullptr);
+    hipLaunchKernelGGL(DIG_NV(g, k_dig_residual), grq, bl, 0, s, g, (const double*)w.stage, (const double*)w.hotf,
+                       (const double*)w.grad, nk.Rp, w, 0, 1.0);
+    hipLaunchKernelGGL(DIG_NV(g, k_nk_matvec), gr, bl, 0, s, g, w, nk, sc, j, cfl);
+    hipLaunchKernelGGL(k_nk_reduce, dim3(j + 1), bl, 0, s, (const double*)nk.part, nblk, nk.red + kNkH1(m));
+    hipLaunchKernelGGL(DIG_NV(g, k_nk_orth), gr, bl, 0, s, g, nk, j, kNkH1(m), 0);
+    hipLaunchKernelGGL(k_nk_reduce, dim3(j + 1), bl, 0, s, (const double*)nk.part, nblk, nk.red + kNkH2(m));
+    hipLaunchKernelGGL(DIG_NV(g, k_nk_orth), gr, bl, 0, s, g, nk, j, kNkH2(m), 1);
+    hipLaunchKernelGGL(k_nk_reduce, dim3(1), bl, 0, s, (const double*)nk.part, nblk, nk.red + kNkHn2(m));
+    hipLaunchKernelGGL(DIG_NV(g, k_nk_normalize), gr, bl, 0, s, g, w, nk, j, cfl);
+    hipLaunchKernelGGL(k_nk_reduce_eps, dim3(1), bl, 0, s, (const double*)nk.part, nblk, nk.red, m,
+                       (double)(g.dr ? kDigNVR : kDigNV) * g.nt, fd);
+}
+
+void launch_nk_try(hipStream_t s, const DigGeom& g, DigWork w, NkWork nk, NkScale sc, int jn, double alpha,
+                   double cfl) {
+    hipLaunchKernelGGL(DIG_NV(g, k_nk_try), cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w, nk, sc, jn, alpha, cfl);
+}
+
+void launch_nk_commit(hipStream_t s, const DigGeom& g, DigWork w, NkWork nk) {
+    hipLaunchKernelGGL(DIG_NV(g, k_nk_commit), cells_grid(g.nt), dim3(kDigThreads), 0, s, g, w, nk);
+}
+
 // Batch: one workgroup per case sums its FV mass over its internal cells in
 // a fixed order; the factor matches the case's particle mass.
 __global__ __launch_bounds__(kDigThreads) void k_dig_mass_cases(DigGeom g, DigWork w, const int32_t* offsets) {

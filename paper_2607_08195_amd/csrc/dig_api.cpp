@@ -20,6 +20,7 @@ struct DigState {
     DigWork w{};
     int nblk = 0;
     AaWork aa{};  // Anderson history, allocated at the first accelerated solve
+    NkWork nk{};  // Krylov basis and work of the Newton-Krylov solve, allocated at its first use
     bool closed = true;  // no inflow or outflow boundary: the solve's mass is rescaled to the particles'
 };
 
@@ -324,6 +325,12 @@ dsmc_status check_params(dsmc_ctx c, const dig_params* p) {
     if (!p) return fail(c, DSMC_E_INVALID, "params is NULL");
     if (p->passes < 0 || p->n_m < 0 || !(p->cfl > 0) || !(p->L0 > 0) || !(p->eps_m >= 0) || p->accel < 0)
         return fail(c, DSMC_E_INVALID, "bad coupling parameters");
+    if (p->solver != 0 && p->solver != 1) return fail(c, DSMC_E_INVALID, "solver must be 0 or 1");
+    if (p->krylov < 0 || p->krylov > kNkMaxKrylov) return fail(c, DSMC_E_INVALID, "krylov must be in [0, 100]");
+    if (p->solver == 1 && (p->accel > 0 || p->global_dt))
+        return fail(c, DSMC_E_INVALID, "the Newton-Krylov solve takes neither accel nor global_dt");
+    if (p->solver == 1 && c->dig && c->dig->g.n_cases > 0)
+        return fail(c, DSMC_E_INVALID, "the Newton-Krylov solve is not available for a batch");
     return DSMC_OK;
 }
 
@@ -454,7 +461,147 @@ dsmc_status run_solve_aa(dsmc_ctx c, const dig_params* p, dig_report* r, int m) 
     return DSMC_OK;
 }
 
+constexpr int kNkDefaultKrylov = 40;
+constexpr double kNkEta = 0.05;      // GMRES stops at this fraction of its initial residual
+constexpr double kNkCflMax = 1e8;    // largest pseudo-time CFL number of the continuation
+constexpr double kNkFd = 1e-7;       // relative size of the finite-difference step
+constexpr int kNkHalvings = 10;      // halvings of an update that leaves a cell non-physical
+
+dsmc_status ensure_nk(dsmc_ctx c, int m) {
+    DigState* d = c->dig;
+    if (d->nk.m >= m) return DSMC_OK;
+    NkWork& k = d->nk;
+    for (double* q : {k.V, k.w, k.U, k.Ut, k.R0, k.Rp, k.part, k.red, k.y}) dev_free(c, q);
+    dev_free(c, k.flag);
+    k = NkWork{};
+    const size_t n = (size_t)dig_nv(c) * c->nt;
+    const size_t nblk = ((size_t)c->nt + kDigThreads - 1) / kDigThreads;
+    const bool ok = alloc_n(c, k.V, n * (m + 1)) && alloc_n(c, k.w, n) && alloc_n(c, k.U, n) && alloc_n(c, k.Ut, n) &&
+                    alloc_n(c, k.R0, n) && alloc_n(c, k.Rp, n) && alloc_n(c, k.part, nblk * (m + 1)) &&
+                    alloc_n(c, k.red, (size_t)kNkRedSize(m)) && alloc_n(c, k.y, (size_t)m) && alloc_n(c, k.flag, 1);
+    if (!ok) return fail(c, DSMC_E_OOM, "device allocation of the Krylov basis failed");
+    k.m = m;
+    return DSMC_OK;
+}
+
+// Newton-Krylov solve from w.prim with w.hotf frozen (the steady equations
+// of the marching): pseudo-transient continuation with the CFL number
+// grown by the ratio of successive residual norms from p->cfl (within
+// [p->cfl, kNkCflMax]); each Newton step runs one cycle of at most m GMRES
+// steps from zero on the scaled, right-preconditioned system
+// (S/cfl + J) dU = -R, stopping at kNkEta of its initial residual; an
+// update that leaves a cell non-physical is halved up to kNkHalvings
+// times, then the solve fails.  The stopping test is the marching's (the
+// density residual norm, with rotation the rotational-energy residual too,
+// against eps_m times its first value), taken at the start of each Newton
+// step; iters counts the updates.  Host round trips: one per Newton step,
+// one per GMRES step and one per trial update.
+dsmc_status run_solve_nk(dsmc_ctx c, const dig_params* p, dig_report* r) {
+    DigState* d = c->dig;
+    hipStream_t s = c->stream;
+    const int m = p->krylov > 0 ? p->krylov : kNkDefaultKrylov;
+    dsmc_status st = ensure_nk(c, m);
+    if (st != DSMC_OK) return st;
+    NkWork& nk = d->nk;
+    const int nv = dig_nv(c);
+    const double n = (double)nv * c->nt;
+    const double R = kBoltzmann / c->mass;
+    const double rho0 = c->mass * c->n0, a2 = R * c->T0, a0 = std::sqrt(a2);
+    NkScale sc{};
+    sc.s[0] = rho0;
+    sc.s[1] = sc.s[2] = sc.s[3] = rho0 * a0;
+    sc.s[4] = sc.s[5] = rho0 * a2;
+    std::vector<double> red((size_t)kNkRedSize(m)), H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+    launch_dig_ctl_reset(s, d->w.ctl);
+    double cfl = p->cfl, bprev = 0.0;
+    bool failed = false;
+    DigCtl h{};
+    int k = 0;
+    auto fetch = [&](int32_t* flag) -> dsmc_status {
+        HIP_TRY(c, hipMemcpyAsync(red.data(), nk.red, sizeof(double) * red.size(), hipMemcpyDeviceToHost, s));
+        if (flag) HIP_TRY(c, hipMemcpyAsync(flag, nk.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        HIP_TRY(c, hipGetLastError());
+        return DSMC_OK;
+    };
+    for (k = 0; k < p->n_m; ++k) {
+        launch_nk_begin(s, d->g, d->w, nk, sc, k, p->eps_m);
+        HIP_TRY(c, hipMemcpyAsync(&h, d->w.ctl, sizeof h, hipMemcpyDeviceToHost, s));
+        if ((st = fetch(nullptr)) != DSMC_OK) return st;
+        if (h.conv) break;
+        const double beta = std::sqrt(red[kNkBeta2(m)]);
+        if (k > 0) cfl = std::min(kNkCflMax, std::max(p->cfl, cfl * (bprev / beta)));
+        bprev = beta;
+        HIP_TRY(c, hipMemsetAsync(nk.flag, 0, sizeof(int32_t), s));
+        launch_nk_scale(s, d->g, d->w, nk, cfl, kNkFd);
+        std::fill(H.begin(), H.end(), 0.0);
+        gv[0] = beta;
+        int jn = 0;
+        for (int j = 0; j < m; ++j) {
+            launch_nk_arnoldi(s, d->g, d->w, nk, sc, j, cfl, kNkFd);
+            int32_t flag = 0;
+            if ((st = fetch(&flag)) != DSMC_OK) return st;
+            if (flag) {
+                failed = true;
+                break;
+            }
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = (0.0 + red[kNkH1(m) + i]) + red[kNkH2(m) + i];
+            const double hn = std::sqrt(red[kNkHn2(m)]);
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+            const double rr = std::sqrt(a * a + b * b);
+            cs[j] = rr > 0 ? a / rr : 1.0;
+            sn[j] = rr > 0 ? b / rr : 0.0;
+            H[(size_t)j * m + j] = rr;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            jn = j + 1;
+            if (std::fabs(gv[j + 1]) <= kNkEta * beta || !(hn > 0)) break;
+        }
+        if (failed) break;
+        for (int i = jn - 1; i >= 0; --i) {
+            double t = gv[i];
+            for (int l = i + 1; l < jn; ++l) t -= H[(size_t)i * m + l] * y[l];
+            y[i] = t / H[(size_t)i * m + i];
+        }
+        HIP_TRY(c, hipMemcpyAsync(nk.y, y.data(), sizeof(double) * jn, hipMemcpyHostToDevice, s));
+        double alpha = 1.0;
+        bool accepted = false;
+        for (int tries = 0; tries <= kNkHalvings && !accepted; ++tries) {
+            HIP_TRY(c, hipMemsetAsync(nk.flag, 0, sizeof(int32_t), s));
+            launch_nk_try(s, d->g, d->w, nk, sc, jn, alpha, cfl);
+            int32_t flag = 0;
+            HIP_TRY(c, hipMemcpyAsync(&flag, nk.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(c, hipStreamSynchronize(s));
+            if (!flag)
+                accepted = true;
+            else
+                alpha = 0.5 * alpha;
+        }
+        if (!accepted) {
+            failed = true;
+            break;
+        }
+        launch_nk_commit(s, d->g, d->w, nk);
+    }
+    HIP_TRY(c, hipGetLastError());
+    h = read_ctl(c, &st);
+    if (st != DSMC_OK) return st;
+    r->iters = k;
+    r->residual = h.res0 > 0 ? h.res / h.res0 : 0.0;
+    r->converged = h.conv;
+    r->failed = failed ? 1 : 0;
+    return DSMC_OK;
+}
+
 dsmc_status run_solve(dsmc_ctx c, const dig_params* p, dig_report* r) {
+    if (p->solver == 1) return run_solve_nk(c, p, r);
     if (p->accel > 0) return run_solve_aa(c, p, r, std::min(p->accel, kAaDepthMax));
     DigState* d = c->dig;
     launch_dig_ctl_reset(c->stream, d->w.ctl);

@@ -88,7 +88,8 @@ class Tuning(C.Structure):
 class DigParams(C.Structure):
     _fields_ = [("kn_max", C.c_double), ("passes", C.c_int32), ("n_m", C.c_int32), ("eps_m", C.c_double),
                 ("cfl", C.c_double), ("L0", C.c_double), ("feedback", C.c_int32), ("global_dt", C.c_int32),
-                ("warm_start", C.c_int32), ("accel", C.c_int32), ("unconverged", C.c_int32)]
+                ("warm_start", C.c_int32), ("accel", C.c_int32), ("unconverged", C.c_int32),
+                ("solver", C.c_int32), ("krylov", C.c_int32)]
 
 
 class DigReport(C.Structure):
@@ -116,8 +117,9 @@ DIG_OUT = {"sampled": (0, 14), "half": (1, 5), "new": (2, 5), "hot": (3, 9), "kn
 
 
 def dig_params(kn_max=1.0, passes=3, n_m=200, eps_m=1e-6, cfl=0.5, L0=1.0, feedback=1, global_dt=0, warm_start=0,
-               accel=0, unconverged=0):
-    return DigParams(kn_max, passes, n_m, eps_m, cfl, L0, feedback, global_dt, warm_start, accel, unconverged)
+               accel=0, unconverged=0, solver=0, krylov=0):
+    return DigParams(kn_max, passes, n_m, eps_m, cfl, L0, feedback, global_dt, warm_start, accel, unconverged,
+                     solver, krylov)
 
 
 def _report(r):
