@@ -464,144 +464,178 @@ def _ttf_err(F, R):
 KB_ = 1.380649e-23
 
 
-def bench_time_to_fields(args, dsmc, W, window=50, block=500):
+TTF_LEVELS = (0.10, 0.05, 0.04, 0.03, 0.02, 0.01)
+
+
+def bench_time_to_fields(args, dsmc, W, block=500):
     """Time to fields on the coupled-cavity configuration (384,000 jittered
     tets, Kn = 0.01, 30 particles per cell, lid 50 m/s): wall seconds of GPU
-    work until a method's fields are within 1% of a long plain reference.
+    work until a method's fields are within 1% (and, for the record, within
+    each of TTF_LEVELS) of a long plain reference.
 
     Reference: plain DSMC, `ttf_transient` steps, then `ttf_sampled` steps
-    averaged; its noise is the difference between its two sampled halves.
+    averaged; its noise is the difference between its two sampled halves
+    (stored with --ttf-ref-out and read back with --ttf-ref-in, so that
+    several races share one reference).
     Fields: 10^3 boxes (density, velocity, temperature pooled per box) and
     the two centreline velocity profiles (reported beside the error).
     Error e = max of the relative L2 differences of velocity, density and
     temperature over the boxes.  Each method adds its moment sums every
     `block` steps; at step t its fields are those of the steps since the
     block boundary nearest below t/2 (the last-half window), and its time to
-    fields is the first GPU time with e <= 1%.  Methods: plain DSMC; the
-    coupled method with the sampled HoT (one coupling cycle every `window`
-    steps, moving average over 1000 steps, 100 pseudo-time iterations
-    warm-started, the particles adjusted to M^{k+1} after the iterations as
-    in Algorithm 1); and the same with the learned closure, trained first on
-    three runs at Kn 0.02, 0.04 and 0.08 (Kn 0.01 held out)."""
+    a level is the first GPU time with e at or below it.  Methods
+    (--ttf-methods): plain DSMC; the coupled method with the sampled HoT (one
+    coupling cycle every --ttf-window steps on the moving average over 1000
+    steps, warm-started from M^k, the particles adjusted to M^{k+1} after
+    the solve as in Algorithm 1) with the Newton-Krylov solve (--ttf-nm
+    Newton steps, the first coupling --ttf-first-nm) or the pseudo-time
+    marching (--ttf-solver march); and the same with the learned closure,
+    trained first on three runs at Kn 0.02, 0.04 and 0.08 (Kn 0.01 held
+    out)."""
     import numpy as np
     import torch
     nh, kn, lid = args.ttf_hex, args.ttf_kn, args.ttf_lid
+    window = args.ttf_window
+    methods = args.ttf_methods.split(",")
     mk = lambda seed, kn_=kn, **kw: W.cavity(n_hex=nh, Kn=kn_, ppc=30, jitter=0.1, vel_fp32=1, seed=seed, n_ss=0,
                                              lid_speed=lid, **kw)
     wl = mk(0)
     G = _ttf_geometry(wl)
     res = {"metric": "GPU seconds to fields within 1% L2 of a long plain reference",
            "config": {"workload": f"cavity_{nh}^3x6_Kn{kn:g}_lid{lid:g}", "ppc": 30, "bins": "10^3 boxes",
-                      "block_steps": block, "coupling_window": window}}
+                      "block_steps": block, "coupling_window": window, "levels": list(TTF_LEVELS)}}
     log = lambda msg: print("# " + msg, file=sys.stderr, flush=True)
 
     def stepper(sim, n):
         sim.graph_step(n)
 
-    # reference
-    ref = dsmc.Simulation(mk(101), stream=torch.cuda.Stream())
-    t0 = time.perf_counter()
-    for done in range(0, args.ttf_transient, 10000):
-        stepper(ref, min(10000, args.ttf_transient - done))
-        ref.sync()
-        log(f"reference transient step {done + min(10000, args.ttf_transient - done)}")
-    s_a, n_a = ref.sums(dsmc.SAMPLE_STEADY)
-    half = args.ttf_sampled // 2
-    marks = []
-    for target in (half, args.ttf_sampled):
-        done = 0
-        while done < target - (0 if not marks else half):
-            k = min(10000, target - (0 if not marks else half) - done)
-            stepper(ref, k)
+    keys = ("u", "rho", "T", "vline", "hline")
+    if args.ttf_ref_in:
+        z = np.load(args.ttf_ref_in)
+        R = {k: z["R_" + k] for k in keys}
+        res["reference"] = json.loads(str(z["meta"]))
+        log("reference read from " + args.ttf_ref_in)
+    else:
+        ref = dsmc.Simulation(mk(101), stream=torch.cuda.Stream())
+        t0 = time.perf_counter()
+        for done in range(0, args.ttf_transient, 10000):
+            stepper(ref, min(10000, args.ttf_transient - done))
             ref.sync()
-            done += k
-            log(f"reference sampled step {done + (half if marks else 0)}")
-        marks.append(ref.sums(dsmc.SAMPLE_STEADY))
-    ref_s = time.perf_counter() - t0
-    ref.close()
-    (s_b, n_b), (s_c, n_c) = marks
-    R = _ttf_fields(_ttf_reduce(s_c - s_a, G), n_c - n_a, G, wl)
-    R1 = _ttf_fields(_ttf_reduce(s_b - s_a, G), n_b - n_a, G, wl)
-    R2 = _ttf_fields(_ttf_reduce(s_c - s_b, G), n_c - n_b, G, wl)
-    res["reference"] = {"transient_steps": args.ttf_transient, "sampled_steps": args.ttf_sampled,
-                        "seconds": round(ref_s, 1), "halves_difference": _ttf_err(R1, R2)}
+            log(f"reference transient step {done + min(10000, args.ttf_transient - done)}")
+        s_a, n_a = ref.sums(dsmc.SAMPLE_STEADY)
+        half = args.ttf_sampled // 2
+        marks = []
+        for target in (half, args.ttf_sampled):
+            done = 0
+            while done < target - (0 if not marks else half):
+                k = min(10000, target - (0 if not marks else half) - done)
+                stepper(ref, k)
+                ref.sync()
+                done += k
+                log(f"reference sampled step {done + (half if marks else 0)}")
+            marks.append(ref.sums(dsmc.SAMPLE_STEADY))
+        ref_s = time.perf_counter() - t0
+        ref.close()
+        (s_b, n_b), (s_c, n_c) = marks
+        R = _ttf_fields(_ttf_reduce(s_c - s_a, G), n_c - n_a, G, wl)
+        R1 = _ttf_fields(_ttf_reduce(s_b - s_a, G), n_b - n_a, G, wl)
+        R2 = _ttf_fields(_ttf_reduce(s_c - s_b, G), n_c - n_b, G, wl)
+        res["reference"] = {"transient_steps": args.ttf_transient, "sampled_steps": args.ttf_sampled,
+                            "seconds": round(ref_s, 1), "halves_difference": _ttf_err(R1, R2)}
+        if args.ttf_ref_out:
+            np.savez(args.ttf_ref_out, meta=json.dumps(res["reference"]), **{"R_" + k: R[k] for k in keys})
     log(f"reference halves differ by {res['reference']['halves_difference']}")
     log("reference result " + json.dumps(res["reference"]))
 
     def race(name, sim, cap, couple=None):
         snaps = {0: tuple(np.zeros_like(a) for a in _ttf_reduce(np.zeros((sim.nt, 13)), G))}
-        t_gpu, step, hist, reached = 0.0, 0, [], None
-        reps = []
+        t_gpu, step, hist, reached = 0.0, 0, [], {}
+        reps, t_couple = [], 0.0
         while step < cap:
             a = time.perf_counter()
-            if couple is None:
-                stepper(sim, block)
-            else:
-                for _ in range(block // window):
-                    stepper(sim, window)
-                    reps.append(couple(sim))
+            end = step + block
+            while step < end:
+                nxt = end if couple is None else min(end, (step // window + 1) * window)
+                stepper(sim, nxt - step)
+                step = nxt
+                if couple is not None and step % window == 0:
+                    c0 = time.perf_counter()
+                    reps.append(couple(sim, len(reps)))
+                    t_couple += time.perf_counter() - c0
             sim.sync()
             t_gpu += time.perf_counter() - a
-            step += block
             S, n = sim.sums(dsmc.SAMPLE_STEADY)
             snaps[step] = _ttf_reduce(S, G)
             h = (step // 2) // block * block
             F = _ttf_fields(tuple(x - y for x, y in zip(snaps[step], snaps[h])), step - h, G, wl)
             err = _ttf_err(F, R)
             hist.append((step, round(t_gpu, 3), {k: round(v, 5) for k, v in err.items()}))
+            for lv in TTF_LEVELS:
+                if err["e"] <= lv and str(lv) not in reached:
+                    reached[str(lv)] = {"step": step, "seconds": round(t_gpu, 2)}
             if step % 5000 == 0 or err["e"] <= 0.01:
-                extra = "" if not reps else (f" couple iters {reps[-1]['iters']} resid {reps[-1]['residual']:.3g} "
-                                             f"closure {reps[-1]['n_closure']} np {reps[-1]['np_after']}")
+                extra = "" if not reps else (f" couple iters {reps[-1]['iters']} krylov {reps[-1]['krylov_steps']} "
+                                             f"resid {reps[-1]['residual']:.3g} closure {reps[-1]['n_closure']} "
+                                             f"np {reps[-1]['np_after']}")
                 log(f"{name} step {step} t {t_gpu:.2f} s e {err['e']:.4f} (u {err['u']:.4f}){extra}")
             if err["e"] <= 0.01:
-                reached = {"step": step, "seconds": round(t_gpu, 2)}
                 break
-        out = {"reached": reached, "steps_run": step, "seconds_run": round(t_gpu, 2),
+        out = {"reached": reached.get("0.01"), "levels": reached, "steps_run": step, "seconds_run": round(t_gpu, 2),
                "final_error": hist[-1][2], "history": hist[::max(1, len(hist) // 40)]}
         if reps:
             out["couplings"] = len(reps)
-            out["last_coupling"] = {k: reps[-1][k] for k in ("iters", "residual", "converged", "fed_back",
-                                                             "n_rejected", "n_closure", "n_fallback")}
+            out["coupling_seconds"] = round(t_couple, 2)
+            out["first_coupling"] = {k: reps[0][k] for k in ("iters", "krylov_steps", "residual", "converged",
+                                                              "fed_back", "n_rejected")}
+            out["last_coupling"] = {k: reps[-1][k] for k in ("iters", "krylov_steps", "residual", "converged",
+                                                             "fed_back", "n_rejected", "n_closure", "n_fallback")}
             out["closure_cells_mean"] = float(np.mean([r["n_closure"] for r in reps]))
         log(f"{name} result " + json.dumps(out))
         return out
 
-    # plain
-    sim = dsmc.Simulation(mk(102), stream=torch.cuda.Stream())
-    res["plain"] = race("plain", sim, args.ttf_cap)
-    sim.close()
-    prm = dict(kn_max=1.0, passes=3, n_m=args.ttf_nm, eps_m=1e-6, cfl=0.5, feedback=1, warm_start=1,
-               unconverged=1)
-    res["coupling"] = prm
-    # coupled, sampled HoT
-    sim = dsmc.Simulation(mk(103, ewma_on=1, n_a=1000), stream=torch.cuda.Stream())
-    res["dig"] = race("dig", sim, args.ttf_dig_cap, couple=lambda s: s.dig_couple(**prm))
-    sim.close()
-    # learned closure: training pairs from three other Knudsen numbers
-    xs, ts = [], []
-    t0 = time.perf_counter()
-    for k, kn_t in enumerate((0.02, 0.04, 0.08)):
-        tr = dsmc.Simulation(mk(200 + k, kn_=kn_t, ewma_on=1, n_a=1000), stream=torch.cuda.Stream())
-        stepper(tr, args.ttf_train_steps)
-        tr.dig_couple(**dict(prm, n_m=0, feedback=0))
-        x, t, v = tr.closure_data()
-        xs.append(x[v]); ts.append(t[v])
-        tr.close()
-        log(f"closure training data from Kn {kn_t}: {int(v.sum())} cells")
-    net = dsmc.Mlp()
-    net.init_weights(seed=1)
-    X, T = np.concatenate(xs), np.concatenate(ts)
-    tr_rep = net.train(X, T, steps=args.ttf_train_iters, batch=4096, lr=1e-3, seed=2)
-    torch.cuda.synchronize()
-    res["closure_training"] = {"samples": int(len(X)), "knudsen": [0.02, 0.04, 0.08],
-                               "steps_per_run": args.ttf_train_steps, "adam_steps": args.ttf_train_iters,
-                               "loss_first": tr_rep["loss_first"], "loss_last": tr_rep["loss_last"],
-                               "seconds": round(time.perf_counter() - t0, 1), "gate_tol": args.ttf_gate}
-    sim = dsmc.Simulation(mk(104, ewma_on=1, n_a=1000), stream=torch.cuda.Stream())
-    sim.set_closure(net, gate_tol=args.ttf_gate)
-    res["dig_mlp"] = race("dig+mlp", sim, args.ttf_dig_cap, couple=lambda s: s.dig_couple(**prm))
-    sim.close()
-    net.close()
+    if "plain" in methods:
+        sim = dsmc.Simulation(mk(102), stream=torch.cuda.Stream())
+        res["plain"] = race("plain", sim, args.ttf_cap)
+        sim.close()
+    nk = args.ttf_solver == "nk"
+    prm = dict(kn_max=1.0, passes=3, n_m=args.ttf_nm, eps_m=args.ttf_eps, cfl=args.ttf_cfl, feedback=1,
+               warm_start=1, unconverged=1, solver=1 if nk else 0, krylov=args.ttf_krylov if nk else 0)
+    first = dict(prm, n_m=args.ttf_first_nm if args.ttf_first_nm > 0 else args.ttf_nm)
+    res["coupling"] = dict(prm, first_n_m=first["n_m"])
+
+    def couple(sim, k):
+        return sim.dig_couple(**(first if k == 0 else prm))
+
+    if "dig" in methods:
+        sim = dsmc.Simulation(mk(103, ewma_on=1, n_a=1000), stream=torch.cuda.Stream())
+        res["dig"] = race("dig", sim, args.ttf_dig_cap, couple=couple)
+        sim.close()
+    if "mlp" in methods:
+        # learned closure: training pairs from three other Knudsen numbers
+        xs, ts = [], []
+        t0 = time.perf_counter()
+        for k, kn_t in enumerate((0.02, 0.04, 0.08)):
+            tr = dsmc.Simulation(mk(200 + k, kn_=kn_t, ewma_on=1, n_a=1000), stream=torch.cuda.Stream())
+            stepper(tr, args.ttf_train_steps)
+            tr.dig_couple(**dict(prm, n_m=0, feedback=0))
+            x, t, v = tr.closure_data()
+            xs.append(x[v]); ts.append(t[v])
+            tr.close()
+            log(f"closure training data from Kn {kn_t}: {int(v.sum())} cells")
+        net = dsmc.Mlp()
+        net.init_weights(seed=1)
+        X, T = np.concatenate(xs), np.concatenate(ts)
+        tr_rep = net.train(X, T, steps=args.ttf_train_iters, batch=4096, lr=1e-3, seed=2)
+        torch.cuda.synchronize()
+        res["closure_training"] = {"samples": int(len(X)), "knudsen": [0.02, 0.04, 0.08],
+                                   "steps_per_run": args.ttf_train_steps, "adam_steps": args.ttf_train_iters,
+                                   "loss_first": tr_rep["loss_first"], "loss_last": tr_rep["loss_last"],
+                                   "seconds": round(time.perf_counter() - t0, 1), "gate_tol": args.ttf_gate}
+        sim = dsmc.Simulation(mk(104, ewma_on=1, n_a=1000), stream=torch.cuda.Stream())
+        sim.set_closure(net, gate_tol=args.ttf_gate)
+        res["dig_mlp"] = race("dig+mlp", sim, args.ttf_dig_cap, couple=couple)
+        sim.close()
+        net.close()
     print(json.dumps(res))
 
 
@@ -620,7 +654,16 @@ def main():
     ap.add_argument("--ttf-sampled", type=int, default=100000)
     ap.add_argument("--ttf-cap", type=int, default=120000, help="plain DSMC steps at most")
     ap.add_argument("--ttf-dig-cap", type=int, default=40000, help="coupled-method steps at most")
-    ap.add_argument("--ttf-nm", type=int, default=100)
+    ap.add_argument("--ttf-methods", default="plain,dig,mlp", help="races to run: plain, dig, mlp")
+    ap.add_argument("--ttf-solver", default="nk", choices=["nk", "march"])
+    ap.add_argument("--ttf-window", type=int, default=500, help="DSMC steps between coupling cycles")
+    ap.add_argument("--ttf-nm", type=int, default=20, help="Newton steps (marching: iterations) per coupling")
+    ap.add_argument("--ttf-first-nm", type=int, default=80, help="the same for the first coupling (0: --ttf-nm)")
+    ap.add_argument("--ttf-eps", type=float, default=1e-3)
+    ap.add_argument("--ttf-cfl", type=float, default=10.0)
+    ap.add_argument("--ttf-krylov", type=int, default=40)
+    ap.add_argument("--ttf-ref-out", default="", help="store the reference fields (.npz)")
+    ap.add_argument("--ttf-ref-in", default="", help="read the reference fields (.npz) instead of running it")
     ap.add_argument("--ttf-gate", type=float, default=0.5)
     ap.add_argument("--ttf-train-steps", type=int, default=3000)
     ap.add_argument("--ttf-train-iters", type=int, default=2000)

@@ -91,6 +91,8 @@ typedef struct {
     int32_t n_closure;       /* cells whose HoT came from the learned closure (mlp.h) */
     int32_t n_fallback;      /* cells with samples that kept the sampled HoT */
     int32_t fed_back;        /* 1: the particles were adjusted to M^{k+1} */
+    int32_t krylov_steps;    /* Newton-Krylov solve: GMRES steps (residual
+                                evaluations of Jacobian products) in all */
 } dig_report;
 
 /* One coupling cycle (Algorithm 1) on the context's current moving-average

@@ -99,7 +99,7 @@ class DigParams(C.Structure):
 class DigReport(C.Structure):
     _fields_ = [("iters", C.c_int), ("residual", C.c_double), ("converged", C.c_int), ("failed", C.c_int),
                 ("n_rejected", C.c_int), ("n_reconstructed", C.c_int), ("n_unreached", C.c_int),
-                ("np_before", C.c_int64), ("np_after", C.c_int64), ("fed_back", C.c_int)]
+                ("np_before", C.c_int64), ("np_after", C.c_int64), ("fed_back", C.c_int), ("krylov_steps", C.c_int)]
 
 
 def dig_params(kn_max=1.0, passes=3, n_m=200, eps_m=1e-6, cfl=0.5, L0=1.0, feedback=1, global_dt=0, warm_start=0,

@@ -797,7 +797,10 @@ static int solve_faces(osim* s, double* prim, const double* hotf, const odig_par
  * the marching (V_c / dtau_c = S_c / cfl), and c_k the pseudo-time CFL
  * number, grown by the ratio of successive residual norms (switched
  * evolution relaxation, Mulder and van Leer, J. Comput. Phys. 59, 1985)
- * from the caller's cfl, within [cfl, NK_CFL_MAX].  The linear system is
+ * from the caller's cfl, within [cfl, NK_CFL_MAX], and at least halved
+ * after a step whose linear solve left more than NK_LIN_POOR of its initial
+ * residual (the linear system at that CFL number is beyond one GMRES
+ * cycle).  The linear system is
  * solved by one cycle of at most m steps of GMRES (Saad and Schultz, SIAM J.
  * Sci. Stat. Comput. 7, 1986) from zero, with classical Gram-Schmidt applied
  * twice, Givens rotations, and a stop at NK_ETA of the initial linear
@@ -815,6 +818,7 @@ static int solve_faces(osim* s, double* prim, const double* hotf, const odig_par
 #define NK_CFL_MAX 1e8
 #define NK_FD 1e-7
 #define NK_HALVINGS 10
+#define NK_LIN_POOR 0.5
 
 static double conv_norm(const osim* s, const double* Rs) {
     int nv = nv_of(s);
@@ -859,8 +863,8 @@ static int solve_nk(osim* s, double* prim, const double* hotf, const odig_params
     double* y = (double*)malloc(sizeof(double) * m);
     double* h = (double*)malloc(sizeof(double) * (m + 1));
     for (int c = 0; c < nt; ++c) cons_of(s, prim + nv * (size_t)c, U + nv * (size_t)c);
-    double res0 = 0.0, res = 0.0, cfl = prm->cfl, bprev = 0.0;
-    int k = 0, conv = 0, failed = 0;
+    double res0 = 0.0, res = 0.0, cfl = prm->cfl, bprev = 0.0, lin = 0.0;
+    int k = 0, conv = 0, failed = 0, nkry = 0;
     for (k = 0; k < prm->n_m; ++k) {
         gradients(s, prim, g);
         residual_all(s, prim, hotf, g, R0, spec);
@@ -878,7 +882,9 @@ static int solve_nk(osim* s, double* prim, const double* hotf, const odig_params
         }
         beta = sqrt(beta);
         if (k > 0) {
-            cfl = cfl * (bprev / beta);
+            double f = bprev / beta;
+            if (lin > NK_LIN_POOR && f > 0.5) f = 0.5;
+            cfl = cfl * f;
             if (cfl < prm->cfl) cfl = prm->cfl;
             if (cfl > NK_CFL_MAX) cfl = NK_CFL_MAX;
         }
@@ -962,9 +968,11 @@ static int solve_nk(osim* s, double* prim, const double* hotf, const odig_params
             gv[j + 1] = -sn[j] * gv[j];
             gv[j] = cs[j] * gv[j];
             jn = j + 1;
+            ++nkry;
             if (fabs(gv[j + 1]) <= NK_ETA * beta || !(hn > 0)) break;
         }
         if (failed) break;
+        lin = fabs(gv[jn]) / beta;
         /* y from the triangular system, z = V y, dU = preconditioned z */
         for (int i = jn - 1; i >= 0; --i) {
             double t = gv[i];
@@ -1004,6 +1012,7 @@ static int solve_nk(osim* s, double* prim, const double* hotf, const odig_params
         rep->residual = res0 > 0 ? res / res0 : 0.0;
         rep->converged = conv;
         rep->failed = failed;
+        rep->krylov_steps = nkry;
     }
     free(g); free(R0); free(Rp); free(spec); free(specp); free(pc); free(U); free(Ut); free(Pt); free(V);
     free(w); free(z); free(H); free(cs); free(sn); free(gv); free(y); free(h);

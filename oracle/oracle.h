@@ -143,6 +143,7 @@ typedef struct {
     int n_unreached;
     int64_t np_before, np_after;
     int fed_back;      /* the particles were adjusted */
+    int krylov_steps;  /* Newton-Krylov solve: GMRES steps in all */
 } odig_report;
 
 /* Reference state (n0, T0, u0) used by the admissibility criterion and as the

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <string>
 #include <utility>
@@ -466,6 +468,7 @@ constexpr double kNkEta = 0.05;      // GMRES stops at this fraction of its init
 constexpr double kNkCflMax = 1e8;    // largest pseudo-time CFL number of the continuation
 constexpr double kNkFd = 1e-7;       // relative size of the finite-difference step
 constexpr int kNkHalvings = 10;      // halvings of an update that leaves a cell non-physical
+constexpr double kNkLinPoor = 0.5;   // a linear solve that leaves more than this halves the CFL number
 
 dsmc_status ensure_nk(dsmc_ctx c, int m) {
     DigState* d = c->dig;
@@ -487,7 +490,8 @@ dsmc_status ensure_nk(dsmc_ctx c, int m) {
 // Newton-Krylov solve from w.prim with w.hotf frozen (the steady equations
 // of the marching): pseudo-transient continuation with the CFL number
 // grown by the ratio of successive residual norms from p->cfl (within
-// [p->cfl, kNkCflMax]); each Newton step runs one cycle of at most m GMRES
+// [p->cfl, kNkCflMax]) and at least halved after a step whose linear solve
+// left more than kNkLinPoor of its initial residual; each Newton step runs one cycle of at most m GMRES
 // steps from zero on the scaled, right-preconditioned system
 // (S/cfl + J) dU = -R, stopping at kNkEta of its initial residual; an
 // update that leaves a cell non-physical is halved up to kNkHalvings
@@ -513,10 +517,13 @@ dsmc_status run_solve_nk(dsmc_ctx c, const dig_params* p, dig_report* r) {
     sc.s[4] = sc.s[5] = rho0 * a2;
     std::vector<double> red((size_t)kNkRedSize(m)), H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
     launch_dig_ctl_reset(s, d->w.ctl);
-    double cfl = p->cfl, bprev = 0.0;
+    double cfl = p->cfl, bprev = 0.0, lin = 0.0;
     bool failed = false;
     DigCtl h{};
-    int k = 0;
+    int k = 0, nkry = 0;
+    // DSMC_NK_TRACE=1: one line per Newton step on stderr
+    const char* tr = std::getenv("DSMC_NK_TRACE");
+    const bool trace = tr && tr[0] == '1';
     auto fetch = [&](int32_t* flag) -> dsmc_status {
         HIP_TRY(c, hipMemcpyAsync(red.data(), nk.red, sizeof(double) * red.size(), hipMemcpyDeviceToHost, s));
         if (flag) HIP_TRY(c, hipMemcpyAsync(flag, nk.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -530,7 +537,11 @@ dsmc_status run_solve_nk(dsmc_ctx c, const dig_params* p, dig_report* r) {
         if ((st = fetch(nullptr)) != DSMC_OK) return st;
         if (h.conv) break;
         const double beta = std::sqrt(red[kNkBeta2(m)]);
-        if (k > 0) cfl = std::min(kNkCflMax, std::max(p->cfl, cfl * (bprev / beta)));
+        if (k > 0) {
+            double f = bprev / beta;
+            if (lin > kNkLinPoor && f > 0.5) f = 0.5;
+            cfl = std::min(kNkCflMax, std::max(p->cfl, cfl * f));
+        }
         bprev = beta;
         HIP_TRY(c, hipMemsetAsync(nk.flag, 0, sizeof(int32_t), s));
         launch_nk_scale(s, d->g, d->w, nk, cfl, kNkFd);
@@ -562,9 +573,15 @@ dsmc_status run_solve_nk(dsmc_ctx c, const dig_params* p, dig_report* r) {
             gv[j + 1] = -sn[j] * gv[j];
             gv[j] = cs[j] * gv[j];
             jn = j + 1;
+            ++nkry;
             if (std::fabs(gv[j + 1]) <= kNkEta * beta || !(hn > 0)) break;
         }
+        if (trace)
+            std::fprintf(stderr, "nk step %d: density residual %.3e of the first, |b| %.4e, cfl %.3e, gmres %d, "
+                         "linear residual %.3e\n", k, h.res0 > 0 ? h.res / h.res0 : 0.0, beta, cfl, jn,
+                         std::fabs(gv[jn]) / beta);
         if (failed) break;
+        lin = std::fabs(gv[jn]) / beta;
         for (int i = jn - 1; i >= 0; --i) {
             double t = gv[i];
             for (int l = i + 1; l < jn; ++l) t -= H[(size_t)i * m + l] * y[l];
@@ -597,6 +614,7 @@ dsmc_status run_solve_nk(dsmc_ctx c, const dig_params* p, dig_report* r) {
     r->residual = h.res0 > 0 ? h.res / h.res0 : 0.0;
     r->converged = h.conv;
     r->failed = failed ? 1 : 0;
+    r->krylov_steps = nkry;
     return DSMC_OK;
 }
 

@@ -96,7 +96,7 @@ class DigReport(C.Structure):
     _fields_ = [("iters", C.c_int32), ("residual", C.c_double), ("converged", C.c_int32), ("failed", C.c_int32),
                 ("n_rejected", C.c_int32), ("n_reconstructed", C.c_int32), ("n_unreached", C.c_int32),
                 ("np_before", C.c_int64), ("np_after", C.c_int64), ("n_closure", C.c_int32),
-                ("n_fallback", C.c_int32), ("fed_back", C.c_int32)]
+                ("n_fallback", C.c_int32), ("fed_back", C.c_int32), ("krylov_steps", C.c_int32)]
 
 
 class MlpTrainParams(C.Structure):

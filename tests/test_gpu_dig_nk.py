@@ -10,7 +10,8 @@ library) into differences of about 1e-9 in a product.  The Newton iteration
 is contracting, so these stay at that level instead of growing:
   * fixed numbers of Newton steps (eps_m = 0) and converged solves: every
     primitive within 1e-6 of its column's scale, the iteration counts equal
-    (converged solves: equal or one apart);
+    (converged solves: equal or one apart), and so the GMRES step counts
+    (converged: within 5 %);
   * one coupling cycle with the solve and feedback (FP64 velocities): the
     report counts exact; M^{k+1} within 1e-6; the particles in the same
     cells and order, positions within 1e-12 m, velocities within 1e-6 of
@@ -85,8 +86,10 @@ def test_solve_matches_oracle(D, gas):
         assert rg["converged"] == ro["converged"]
         if kw["eps_m"] == 0.0:
             assert rg["iters"] == ro["iters"] == kw["n_m"]
+            assert rg["krylov_steps"] == ro["krylov_steps"]
         else:
             assert ro["converged"] and abs(rg["iters"] - ro["iters"]) <= 1
+            assert abs(rg["krylov_steps"] - ro["krylov_steps"]) <= 0.05 * ro["krylov_steps"]
         _col_close(pg, po, 1e-6, f"{gas} n_m={kw['n_m']}")
     g.close()
 
