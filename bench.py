@@ -639,6 +639,61 @@ def bench_time_to_fields(args, dsmc, W, block=500):
     print(json.dumps(res))
 
 
+def bench_dig_bias(args, dsmc, W):
+    """Fixed point of the coupling step against the DSMC steady state: the
+    lid-driven cavity at Kn 0.01 (lid 50 m/s, 30 particles per cell) on
+    n^3 x 6 tets for each n of --bias-hex, plain DSMC for --bias-transient
+    steps, then the moving average restarted and run for --bias-avg steps;
+    one coupling cycle without feedback solves the synthetic equations to a
+    1e-7 density residual ratio (Newton-Krylov) from that state with its
+    HoT.  Reported: the relative L2 difference of the solved and the sampled
+    velocity pooled over 10^3 boxes (the time-to-fields metric) and the
+    ratio of their norms.  A consistent fixed point would give the sampled
+    state's noise only (which shrinks with the averaging length)."""
+    import numpy as np
+    import torch
+    out = {"metric": "relative L2 difference of solved and sampled box velocities",
+           "config": {"workload": "cavity_Kn0.01_lid50", "ppc": 30, "jitter": args.bias_jitter,
+                      "transient_steps": args.bias_transient, "averaged_steps": args.bias_avg},
+           "meshes": []}
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    for nh in [int(x) for x in args.bias_hex.split(",")]:
+        wl = W.cavity(n_hex=nh, Kn=0.01, ppc=30, jitter=args.bias_jitter, vel_fp32=1, seed=7, n_ss=0,
+                      lid_speed=50.0, ewma_on=1, n_a=args.bias_avg)
+        G = _ttf_geometry(wl)
+        vol = G["vol"]
+
+        def boxed(P):
+            w = P[:, 0] * vol
+            num = np.stack([np.bincount(G["bin"], weights=w * P[:, 1 + k], minlength=G["nbins"]) for k in range(3)],
+                           axis=1)
+            return num / np.bincount(G["bin"], weights=w, minlength=G["nbins"])[:, None]
+
+        sim = dsmc.Simulation(wl, stream=torch.cuda.Stream())
+        t0 = time.perf_counter()
+        for done in range(0, args.bias_transient, 10000):
+            sim.graph_step(min(10000, args.bias_transient - done))
+            sim.sync()
+        sim.set_sums(dsmc.SAMPLE_EWMA, np.zeros((sim.nt, 13)), np.zeros(sim.nt, np.int32))
+        for done in range(0, args.bias_avg, 10000):
+            sim.graph_step(min(10000, args.bias_avg - done))
+            sim.sync()
+            print(f"# n_hex {nh}: averaged {done + min(10000, args.bias_avg - done)} steps", file=sys.stderr, flush=True)
+        t1 = time.perf_counter()
+        rep = sim.dig_couple(kn_max=1.0, passes=3, feedback=0, warm_start=0, n_m=200, eps_m=1e-7, cfl=10.0,
+                             solver=1, krylov=40)
+        t2 = time.perf_counter()
+        half, new = boxed(sim.dig_get("half")), boxed(sim.dig_get("new"))
+        m = {"n_hex": nh, "tets": sim.nt, "solved_vs_sampled": round(rel(new, half), 5),
+             "norm_ratio": round(float(np.linalg.norm(new) / np.linalg.norm(half)), 5),
+             "newton_steps": rep["iters"], "krylov_steps": rep["krylov_steps"], "converged": rep["converged"],
+             "dsmc_seconds": round(t1 - t0, 1), "solve_seconds": round(t2 - t1, 2)}
+        print("# " + json.dumps(m), file=sys.stderr, flush=True)
+        out["meshes"].append(m)
+        sim.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -646,7 +701,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="cavity_large",
                     choices=["cavity_large", "cavity_small", "cavity_vss", "ensemble64", "dig_cavity40",
-                             "time_to_fields", "sphere"])
+                             "time_to_fields", "dig_bias", "sphere"])
+    ap.add_argument("--bias-hex", default="20,30,40", help="mesh sizes of the dig_bias workload")
+    ap.add_argument("--bias-jitter", type=float, default=0.1)
+    ap.add_argument("--bias-transient", type=int, default=10000)
+    ap.add_argument("--bias-avg", type=int, default=80000)
     ap.add_argument("--ttf-hex", type=int, default=40)
     ap.add_argument("--ttf-kn", type=float, default=0.01)
     ap.add_argument("--ttf-lid", type=float, default=50.0)
@@ -706,6 +765,8 @@ def main():
         return bench_dig(args, dsmc, W)
     if args.workload == "time_to_fields":
         return bench_time_to_fields(args, dsmc, W)
+    if args.workload == "dig_bias":
+        return bench_dig_bias(args, dsmc, W)
     wl = {"cavity_large": W.cavity_large, "cavity_vss": W.cavity_large_vss,
           "cavity_small": W.cavity_small}[args.workload]()
     sim = dsmc.Simulation(wl)
