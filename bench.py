@@ -498,11 +498,13 @@ def bench_time_to_fields(args, dsmc, W, block=500):
     window = args.ttf_window
     methods = args.ttf_methods.split(",")
     mk = lambda seed, kn_=kn, **kw: W.cavity(n_hex=nh, Kn=kn_, ppc=30, jitter=0.1, vel_fp32=1, seed=seed, n_ss=0,
-                                             lid_speed=lid, **kw)
+                                             lid_speed=lid, grade=args.ttf_grade, **kw)
     wl = mk(0)
     G = _ttf_geometry(wl)
     res = {"metric": "GPU seconds to fields within 1% L2 of a long plain reference",
-           "config": {"workload": f"cavity_{nh}^3x6_Kn{kn:g}_lid{lid:g}", "ppc": 30, "bins": "10^3 boxes",
+           "config": {"workload": f"cavity_{nh}^3x6_Kn{kn:g}_lid{lid:g}" + (f"_grade{args.ttf_grade:g}"
+                                                                              if args.ttf_grade else ""),
+                      "ppc": 30, "bins": "10^3 boxes",
                       "block_steps": block, "coupling_window": window, "levels": list(TTF_LEVELS)}}
     log = lambda msg: print("# " + msg, file=sys.stderr, flush=True)
 
@@ -653,13 +655,14 @@ def bench_dig_bias(args, dsmc, W):
     import numpy as np
     import torch
     out = {"metric": "relative L2 difference of solved and sampled box velocities",
-           "config": {"workload": "cavity_Kn0.01_lid50", "ppc": 30, "jitter": args.bias_jitter,
+           "config": {"workload": f"cavity_Kn{args.bias_kn:g}_lid50", "ppc": 30, "jitter": args.bias_jitter,
+                      "grade": args.bias_grade,
                       "transient_steps": args.bias_transient, "averaged_steps": args.bias_avg},
            "meshes": []}
     rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
     for nh in [int(x) for x in args.bias_hex.split(",")]:
-        wl = W.cavity(n_hex=nh, Kn=0.01, ppc=30, jitter=args.bias_jitter, vel_fp32=1, seed=7, n_ss=0,
-                      lid_speed=50.0, ewma_on=1, n_a=args.bias_avg)
+        wl = W.cavity(n_hex=nh, Kn=args.bias_kn, ppc=30, jitter=args.bias_jitter, vel_fp32=1, seed=7, n_ss=0,
+                      lid_speed=50.0, ewma_on=1, n_a=args.bias_avg, grade=args.bias_grade)
         G = _ttf_geometry(wl)
         vol = G["vol"]
 
@@ -704,11 +707,14 @@ def main():
                              "time_to_fields", "dig_bias", "sphere"])
     ap.add_argument("--bias-hex", default="20,30,40", help="mesh sizes of the dig_bias workload")
     ap.add_argument("--bias-jitter", type=float, default=0.1)
+    ap.add_argument("--bias-grade", type=float, default=0.0, help="wall refinement of the dig_bias meshes")
+    ap.add_argument("--bias-kn", type=float, default=0.01)
     ap.add_argument("--bias-transient", type=int, default=10000)
     ap.add_argument("--bias-avg", type=int, default=80000)
     ap.add_argument("--ttf-hex", type=int, default=40)
     ap.add_argument("--ttf-kn", type=float, default=0.01)
     ap.add_argument("--ttf-lid", type=float, default=50.0)
+    ap.add_argument("--ttf-grade", type=float, default=0.0, help="wall refinement of the time-to-fields mesh")
     ap.add_argument("--ttf-transient", type=int, default=50000)
     ap.add_argument("--ttf-sampled", type=int, default=100000)
     ap.add_argument("--ttf-cap", type=int, default=120000, help="plain DSMC steps at most")

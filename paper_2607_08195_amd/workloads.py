@@ -136,13 +136,17 @@ def _box_boundary(tets, xyz, lo, hi, tol):
 
 
 def kuhn_box(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), jitter=0.0, seed=0,
-             periodic_axes=()):
+             periodic_axes=(), grade=0.0):
     """Box [lo,hi] meshed as nx*ny*nz hexes x 6 Kuhn tets.  ``jitter`` moves
     interior vertices by uniform +-jitter*h per coordinate, vertices on one
     box face only tangentially, and leaves edge and corner vertices fixed; a
     vertex is redrawn while any of its tets falls below 5% of the nominal
     volume.  ``periodic_axes`` pairs the faces on opposite sides of the
-    listed axes (translation partners); jitter must then be 0."""
+    listed axes (translation partners); jitter must then be 0.  ``grade`` =
+    b > 0 clusters the vertices towards both faces of every axis, after the
+    jitter: s -> (1 + tanh(b (2s - 1)) / tanh(b)) / 2 for the fraction s of
+    the box (the spacing at a face shrinks by b (1 - tanh(b)^2) / tanh(b),
+    0.29 for b = 1.5); ``h`` is then the smallest spacing."""
     lo = np.asarray(lo, float)
     hi = np.asarray(hi, float)
     n = np.array([nx, ny, nz])
@@ -184,6 +188,15 @@ def kuhn_box(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), jitter=0.0, see
             xyz[bad_v] = base[bad_v] + d
         else:
             raise RuntimeError("jitter could not reach the minimum tet volume")
+    if grade > 0:
+        assert not periodic_axes
+        frac = (xyz - lo) / (hi - lo)
+        mapped = 0.5 * (1.0 + np.tanh(grade * (2.0 * frac - 1.0)) / np.tanh(grade))
+        on_end = (idx == 0) | (idx == n)
+        mapped[on_end] = frac[on_end]  # box faces stay where they are
+        xyz = lo + mapped * (hi - lo)
+        first = 0.5 * (1.0 + np.tanh(grade * (2.0 / n - 1.0)) / np.tanh(grade))
+        h = float((first * (hi - lo)).min())
     bfaces, bgroup = _box_boundary(tets, xyz, lo, hi, 1e-9 * float((hi - lo).max()))
     partner = None
     if periodic_axes:
@@ -356,16 +369,18 @@ def tau_from_kn(sp: Species, Kn, T0, L0=1.0):
 # Named workloads
 # ---------------------------------------------------------------------------
 def cavity(n_hex=6, Kn=1.0, ppc=20, jitter=0.0, lid_speed=50.0, T0=273.0, seed=0,
-           vel_fp32=1, steps=500, n_ss=200, mesh_seed=0, ewma_on=0, n_a=1000, species=None):
+           vel_fp32=1, steps=500, n_ss=200, mesh_seed=0, ewma_on=0, n_a=1000, species=None, grade=0.0):
     """3D lid-driven cavity on [0,1]^3: all walls diffuse at T0, the y=1 lid
     moving at lid_speed in +x.  Initial equilibrium at rest (section 5.1).
-    The gas is VHS argon unless `species` is given."""
+    The gas is VHS argon unless `species` is given; ``grade`` refines the
+    mesh towards the walls (kuhn_box)."""
     sp = Species() if species is None else species
-    mesh = kuhn_box(n_hex, n_hex, n_hex, jitter=jitter, seed=mesh_seed)
-    name = f"cavity_{n_hex}^3x6_Kn{Kn:g}" + ("" if sp.alpha == 1.0 else f"_vss{sp.alpha:g}")
+    mesh = kuhn_box(n_hex, n_hex, n_hex, jitter=jitter, seed=mesh_seed, grade=grade)
+    name = (f"cavity_{n_hex}^3x6_Kn{Kn:g}" + ("" if sp.alpha == 1.0 else f"_vss{sp.alpha:g}") +
+            ("" if grade == 0 else f"_grade{grade:g}"))
     wl = cavity_on_mesh(mesh, Kn=Kn, ppc=ppc, lid_speed=lid_speed, T0=T0, seed=seed, vel_fp32=vel_fp32,
                         steps=steps, n_ss=n_ss, ewma_on=ewma_on, n_a=n_a, species=sp, name=name)
-    wl.info.update(n_hex=n_hex, jitter=jitter)
+    wl.info.update(n_hex=n_hex, jitter=jitter, grade=grade)
     return wl
 
 

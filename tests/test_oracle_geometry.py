@@ -47,6 +47,30 @@ def test_volumes_and_faces(jitter):
     assert sorted(b.tolist()) == list(range(nb))
 
 
+@pytest.mark.parametrize("jitter", [0.0, 0.1])
+def test_wall_graded_box(jitter):
+    """Grading towards the walls keeps a valid mesh of the same box: the
+    oracle's volumes are positive and fill it, the faces pair as on the
+    uniform mesh, the first spacing at a wall is the closed form
+    (1 + tanh(b (2/n - 1)) / tanh(b)) / 2 and cells shrink towards the walls."""
+    n, b = 6, 1.5
+    wl = W.cavity(n_hex=n, jitter=jitter, ppc=2, grade=b)
+    o = Oracle(wl, fill=False)
+    vol = o.volumes()
+    assert (vol > 0).all() and abs(vol.sum() - 1.0) < 1e-13
+    assert len(wl.mesh.bfaces) == 6 * 2 * n * n
+    assert (o.neighbours() < 0).sum() == len(wl.mesh.bfaces)
+    first = 0.5 * (1.0 + np.tanh(b * (2.0 / n - 1.0)) / np.tanh(b))
+    assert abs(wl.mesh.h - first) < 1e-15
+    if jitter == 0.0:
+        xs = np.unique(np.round(wl.mesh.xyz[:, 0], 12))
+        assert len(xs) == n + 1 and abs(xs[1] - first) < 1e-12
+        assert np.all(np.diff(xs)[: n // 2 - 1] < np.diff(xs)[1: n // 2])
+    cen = wl.mesh.xyz[wl.mesh.tets].mean(axis=1)
+    dist = np.min(np.minimum(cen, 1.0 - cen), axis=1)
+    assert vol[dist < 0.1].mean() < vol[dist > 0.3].mean() / 4
+
+
 def test_invalid_mesh_rejected():
     wl = W.cavity(n_hex=2, ppc=2)
     wl.mesh.bfaces = wl.mesh.bfaces[:-1].copy()
