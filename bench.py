@@ -33,10 +33,11 @@ sys.path.insert(0, ROOT)
 #            sums read and written (208)
 # Stage -> kernels whose launch times it sums.
 BYTES = {
-    "move": lambda np_, nt, f: np_ * (72.0 + 12.0 * f["walls"]),
+    "move": lambda np_, nt, f: np_ * (72.0 + (12.0 + 8.0 * f["rot"]) * f["walls"]),
     "scan": lambda np_, nt, f: nt * 8.0,
-    "sort": lambda np_, nt, f: np_ * 88.0,
-    "collide_sample": lambda np_, nt, f: np_ * (16.0 + 12.0 * f["touched"]) + nt * 224.0,
+    "sort": lambda np_, nt, f: np_ * (88.0 + 16.0 * f["rot"]),
+    "collide_sample": lambda np_, nt, f: (np_ * (16.0 + 12.0 * f["touched"] + f["rot"] * (8.0 + 8.0 * f["touched"]))
+                                          + nt * (224.0 + 64.0 * f["rot"])),
 }
 STAGES = {"move": ["move", "move_walls"], "scan": ["scan"], "sort": ["sort_perm", "sort_gather"],
           "collide_sample": ["collide_sample"]}
@@ -641,6 +642,24 @@ def bench_time_to_fields(args, dsmc, W, block=500):
     print(json.dumps(res))
 
 
+def mixed_cavity(dsmc, W, n=32):
+    """The lid-driven cavity of cavity_large on a mixed-element mesh: n^3
+    hexahedral blocks (10 % vertex jitter) split into tetrahedra, pyramids,
+    prisms and hexahedra, decomposed by the library into tetrahedra (about
+    377,000 for n = 32); Kn 0.1, 30 particles per tetrahedron, FP32
+    velocities."""
+    import numpy as np
+    m = W.mixed_box(n, n, n, jitter=0.1, seed=1)
+    d = dsmc.decompose(m.xyz, m.cells, m.bfaces, m.bgroup)
+    mesh = W.Mesh(xyz=d["xyz"], tets=d["tets"], bfaces=d["bfaces"], bgroup=d["bgroup"], bpartner=None, h=m.h)
+    wl = W.cavity_on_mesh(mesh, Kn=0.1, ppc=30, vel_fp32=1, n_ss=10000, steps=20000,
+                          name=f"mixed_cavity_{n}^3_Kn0.1")
+    kinds, counts = np.unique(m.kind, return_counts=True)
+    names = {4: "tetrahedra", 5: "pyramids", 6: "prisms", 8: "hexahedra"}
+    wl.info["cells"] = {names[int(k)]: int(c) for k, c in zip(kinds, counts)}
+    return wl
+
+
 def bench_dig_bias(args, dsmc, W):
     """Fixed point of the coupling step against the DSMC steady state: the
     lid-driven cavity at Kn 0.01 (lid 50 m/s, 30 particles per cell) on
@@ -703,8 +722,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="cavity_large",
-                    choices=["cavity_large", "cavity_small", "cavity_vss", "ensemble64", "dig_cavity40",
-                             "time_to_fields", "dig_bias", "sphere"])
+                    choices=["cavity_large", "cavity_small", "cavity_vss", "cavity_n2", "cavity_mixed",
+                             "ensemble64", "dig_cavity40", "time_to_fields", "dig_bias", "sphere"])
     ap.add_argument("--bias-hex", default="20,30,40", help="mesh sizes of the dig_bias workload")
     ap.add_argument("--bias-jitter", type=float, default=0.1)
     ap.add_argument("--bias-grade", type=float, default=0.0, help="wall refinement of the dig_bias meshes")
@@ -773,8 +792,8 @@ def main():
         return bench_time_to_fields(args, dsmc, W)
     if args.workload == "dig_bias":
         return bench_dig_bias(args, dsmc, W)
-    wl = {"cavity_large": W.cavity_large, "cavity_vss": W.cavity_large_vss,
-          "cavity_small": W.cavity_small}[args.workload]()
+    wl = {"cavity_large": W.cavity_large, "cavity_vss": W.cavity_large_vss, "cavity_small": W.cavity_small,
+          "cavity_n2": W.cavity_large_n2, "cavity_mixed": lambda: mixed_cavity(dsmc, W)}[args.workload]()
     sim = dsmc.Simulation(wl)
     np0 = sim.stats()["n_particles"]
     sim.step(args.warmup)
@@ -823,7 +842,7 @@ def main():
         if cnt:
             per_launch[name] = ms / cnt
     stage_ms = {k: sum(per_launch.get(n, 0.0) for n in ks) for k, ks in STAGES.items()}
-    frac = {"walls": walls_pp, "touched": touched_pp}
+    frac = {"walls": walls_pp, "touched": touched_pp, "rot": 1.0 if wl.species.dof_rot else 0.0}
     bytes_launch = {k: fn(npart, nt, frac) for k, fn in BYTES.items()}
     gbs = {k: bytes_launch[k] / (stage_ms[k] * 1e-3) / 1e9 for k in bytes_launch if stage_ms[k] > 0}
     dominant = max(gbs, key=lambda k: stage_ms[k])
@@ -854,7 +873,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "tets": nt, "particles": int(np0),
-                   "Kn": wl.info.get("Kn"), "velocity_storage": "f32" if wl.run.vel_fp32 else "f64"},
+                   "Kn": wl.info.get("Kn"), "velocity_storage": "f32" if wl.run.vel_fp32 else "f64",
+                   **({"gas": "nitrogen, 2 rotational degrees of freedom"} if wl.species.dof_rot else {}),
+                   **({"cells": wl.info["cells"]} if "cells" in wl.info else {})},
         "launch": "hip_graph" if args.graph else "eager",
         "step_algorithmic_GBps": round(step_bytes / (elapsed / args.steps) / 1e9, 1),
         "hops_per_particle_step": round(hops_pp, 3),

@@ -1867,22 +1867,29 @@ bool collide_fuses_gather(int variant) {
     return variant == kCollideGlobal || variant == kCollideGlobal8 || variant == kCollideG3k || variant == kCollideG2k;
 }
 
+// Waves per SIMD the collide kernels are compiled for.  The chunk's pid
+// table (18.7 KB of LDS at 3072 particles) already holds a one-wave
+// workgroup to two waves per SIMD; the rotating gas's instances ask for two,
+// so that the compiler keeps them within 256 registers (asked for more, they
+// took 263 and ran at one wave per SIMD).
+constexpr int collide_wpe(int w, bool rot) { return rot ? 2 : w; }
+
 template <class VT, bool VSS, bool ROT>
 static void launch_collide_v(hipStream_t s, PartDev<VT> p, const int32_t* offsets, const CollideParams& cp,
                              const Scalars* sc, int32_t* perm, int do_collide, int do_sample, int variant, int gmode,
                              PartDev<VT> src, const int32_t* sortperm) {
     const int nchunk = (cp.nt + kCollideLanes - 1) / kCollideLanes;
     if (variant == kCollideGlobal)
-        launch_collide_g<VT, 4, kCollideCapG, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample,
+        launch_collide_g<VT, collide_wpe(4, ROT), kCollideCapG, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample,
                                                         gmode, src, sortperm);
     else if (variant == kCollideGlobal8)
-        launch_collide_g<VT, 8, kCollideCapG, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample,
+        launch_collide_g<VT, collide_wpe(8, ROT), kCollideCapG, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample,
                                                         gmode, src, sortperm);
     else if (variant == kCollideG3k)
-        launch_collide_g<VT, 4, 3072, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, gmode, src,
+        launch_collide_g<VT, collide_wpe(4, ROT), 3072, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, gmode, src,
                                                 sortperm);
     else if (variant == kCollideG2k)
-        launch_collide_g<VT, 4, 2048, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, gmode, src,
+        launch_collide_g<VT, collide_wpe(4, ROT), 2048, VSS, ROT>(s, nchunk, p, offsets, cp, sc, perm, do_collide, do_sample, gmode, src,
                                                 sortperm);
     else if constexpr (!ROT)
         hipLaunchKernelGGL((k_collide_sample<VT, VSS>), dim3(nchunk), dim3(kCollideLanes), 0, s, p, offsets, cp, sc,

@@ -377,7 +377,7 @@ def cavity(n_hex=6, Kn=1.0, ppc=20, jitter=0.0, lid_speed=50.0, T0=273.0, seed=0
     sp = Species() if species is None else species
     mesh = kuhn_box(n_hex, n_hex, n_hex, jitter=jitter, seed=mesh_seed, grade=grade)
     name = (f"cavity_{n_hex}^3x6_Kn{Kn:g}" + ("" if sp.alpha == 1.0 else f"_vss{sp.alpha:g}") +
-            ("" if grade == 0 else f"_grade{grade:g}"))
+            ("" if not sp.dof_rot else f"_rot{sp.dof_rot}") + ("" if grade == 0 else f"_grade{grade:g}"))
     wl = cavity_on_mesh(mesh, Kn=Kn, ppc=ppc, lid_speed=lid_speed, T0=T0, seed=seed, vel_fp32=vel_fp32,
                         steps=steps, n_ss=n_ss, ewma_on=ewma_on, n_a=n_a, species=sp, name=name)
     wl.info.update(n_hex=n_hex, jitter=jitter, grade=grade)
@@ -421,6 +421,14 @@ def cavity_large(steps=20000, n_ss=10000):
     vertex jitter, Kn=0.1, 30 particles per cell (11.52M particles), FP32
     velocities, FP64 positions and moments."""
     return cavity(n_hex=40, Kn=0.1, ppc=30, jitter=0.1, vel_fp32=1, steps=steps, n_ss=n_ss)
+
+
+def cavity_large_n2(steps=20000, n_ss=10000):
+    """cavity_large with the paper's gas: nitrogen (VHS, omega = 0.74,
+    d_ref = 4.17e-10 m, m = 4.65e-26 kg) with two rotational degrees of
+    freedom exchanged by Borgnakke-Larsen at Z_r = 2.59 (section 5.1)."""
+    sp = Species(mass=4.65e-26, d_ref=4.17e-10, omega=0.74, T_ref=273.0, alpha=1.0, dof_rot=2, z_rot=2.59)
+    return cavity(n_hex=40, Kn=0.1, ppc=30, jitter=0.1, vel_fp32=1, steps=steps, n_ss=n_ss, species=sp)
 
 
 def cavity_ensemble(n_cases=64, seed=0, n_min=6, n_max=24, ppc=20, vel_fp32=1, case_seed=0):
