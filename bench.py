@@ -705,9 +705,26 @@ def bench_dig_bias(args, dsmc, W):
         rep = sim.dig_couple(kn_max=1.0, passes=3, feedback=0, warm_start=0, n_m=200, eps_m=1e-7, cfl=10.0,
                              solver=1, krylov=40)
         t2 = time.perf_counter()
-        half, new = boxed(sim.dig_get("half")), boxed(sim.dig_get("new"))
+        ph, pn = sim.dig_get("half"), sim.dig_get("new")
+        half, new = boxed(ph), boxed(pn)
+        # where the difference lies: cells near the lid's four edges (within
+        # 0.1 of the cavity length), and the boxes of largest difference
+        cen = wl.mesh.xyz[wl.mesh.tets].mean(axis=1)
+        edge = np.minimum.reduce([np.hypot(1 - cen[:, 1], cen[:, 0]), np.hypot(1 - cen[:, 1], 1 - cen[:, 0]),
+                                  np.hypot(1 - cen[:, 1], cen[:, 2]), np.hypot(1 - cen[:, 1], 1 - cen[:, 2])])
+        du2 = vol * ((pn[:, 1:4] - ph[:, 1:4]) ** 2).sum(axis=1)
+        near = edge < 0.1
+        d2 = ((new - half) ** 2).sum(axis=1)
+        top = np.argsort(-d2)[:5]
+        nb = round(G["nbins"] ** (1 / 3))
+        centres = (np.stack(np.unravel_index(top, (nb, nb, nb)), axis=1) + 0.5) / nb
         m = {"n_hex": nh, "tets": sim.nt, "solved_vs_sampled": round(rel(new, half), 5),
              "norm_ratio": round(float(np.linalg.norm(new) / np.linalg.norm(half)), 5),
+             "lid_edge_cells": round(float(near.mean()), 4),
+             "lid_edge_share_of_difference": round(float(du2[near].sum() / du2.sum()), 4),
+             "largest_boxes": [[round(float(x), 2) for x in c] + [round(float(np.sqrt(d2[k])), 3),
+                                                                   round(float(np.linalg.norm(half[k])), 2)]
+                               for c, k in zip(centres, top)],
              "newton_steps": rep["iters"], "krylov_steps": rep["krylov_steps"], "converged": rep["converged"],
              "dsmc_seconds": round(t1 - t0, 1), "solve_seconds": round(t2 - t1, 2)}
         print("# " + json.dumps(m), file=sys.stderr, flush=True)
