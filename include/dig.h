@@ -120,7 +120,7 @@ typedef struct {
 dsmc_status dig_couple(dsmc_ctx ctx, const dig_params* params, dig_report* report);
 
 /* Batch contexts (dsmc_batch_init): one call couples every enabled case at
- * once.  Each case uses its own reference state (n0, T0) for the Knudsen
+ * once (with the pseudo-time marching: params->solver = 1 is refused).  Each case uses its own reference state (n0, T0) for the Knudsen
  * number, its own F_N, generator key and case-local cell subjects and
  * particle ids (a case's next id starts at its largest id + 1 when the
  * coupling state is first built), and its own closed-domain mass rescale,
@@ -157,8 +157,15 @@ dsmc_status dig_get(dsmc_ctx ctx, int32_t which, void* out);
 dsmc_status dig_residual(dsmc_ctx ctx, const double* prim, const double* hot, double* out);
 
 /* Macroscopic solve alone from prim[n][5] (in/out) with frozen hot[n][9]
- * (rotating gas: [n][6] and [n][12]); uses n_m, eps_m, cfl, global_dt and
- * accel of params. */
+ * (rotating gas: [n][6] and [n][12]); uses n_m, eps_m, cfl, global_dt,
+ * accel, solver and krylov of params.  With solver = 1 (Newton-Krylov) the
+ * steady state is the marching's (the same discrete equations), n_m counts
+ * Newton steps and report->krylov_steps the GMRES steps; a perturbed or
+ * updated state that stays non-physical after ten halvings ends the solve
+ * with report->failed.  Both solvers take their stopping test on the
+ * density residual (a rotating gas adds its rotational-energy residual)
+ * against its value at the start, which a warm start from a near solution
+ * makes strict. */
 dsmc_status dig_solve(dsmc_ctx ctx, double* prim, const double* hot, const dig_params* params,
                       dig_report* report);
 
