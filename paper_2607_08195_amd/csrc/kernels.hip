@@ -1011,9 +1011,11 @@ __global__ __launch_bounds__(256) void k_gather(PartDev<VT> src, PartDev<VT> dst
     const double x0 = src.pos[3 * i], x1 = src.pos[3 * i + 1], x2 = src.pos[3 * i + 2];
     const VT v0 = src.vel[3 * i], v1 = src.vel[3 * i + 1], v2 = src.vel[3 * i + 2];
     const uint32_t id = src.pid[i];
-    dst.pos[3 * k] = x0;
-    dst.pos[3 * k + 1] = x1;
-    dst.pos[3 * k + 2] = x2;
+    // positions are next read by the following step's move: stream them past
+    // the L2 (velocities and ids stay cached for the collide kernel)
+    __builtin_nontemporal_store(x0, &dst.pos[3 * k]);
+    __builtin_nontemporal_store(x1, &dst.pos[3 * k + 1]);
+    __builtin_nontemporal_store(x2, &dst.pos[3 * k + 2]);
     dst.vel[3 * k] = v0;
     dst.vel[3 * k + 1] = v1;
     dst.vel[3 * k + 2] = v2;
