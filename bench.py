@@ -346,13 +346,17 @@ def bench_dig(args, dsmc, W, window=50):
     per cell): cycles of `window` DSMC steps followed by one coupling step
     (sampled state, HoT, gate, learned closure, FV solve, feedback).  The
     closure network is first trained on the run's own cell data.  --steps
-    counts DSMC steps (rounded to whole windows)."""
+    counts DSMC steps (rounded to whole windows).  --dig-solver nk takes the
+    Newton-Krylov solve (20 Newton steps, GMRES(40), initial CFL 10) instead
+    of 100 pseudo-time iterations."""
     import torch
     wl = W.cavity(n_hex=40, Kn=0.01, ppc=30, jitter=0.1, vel_fp32=1, ewma_on=1, n_a=1000)
     sim = dsmc.Simulation(wl)
     net = dsmc.Mlp()
     net.init_weights(seed=1)
     prm = dict(kn_max=1.0, passes=3, n_m=100, eps_m=1e-4, cfl=0.5, feedback=1, warm_start=1, unconverged=1)
+    if args.dig_solver == "nk":
+        prm.update(n_m=20, eps_m=1e-3, cfl=10.0, solver=1, krylov=40)
     sim.step(window)
     sim.dig_couple(**dict(prm, n_m=0, feedback=0))
     x, t, v = sim.closure_data()
@@ -819,6 +823,7 @@ def main():
     ap.add_argument("--workload", default="cavity_large",
                     choices=["cavity_large", "cavity_small", "cavity_vss", "cavity_n2", "cavity_mixed",
                              "ensemble64", "dig_cavity40", "time_to_fields", "dig_bias", "coarse_fields", "sphere"])
+    ap.add_argument("--dig-solver", default="march", choices=["march", "nk"], help="solve of dig_cavity40")
     ap.add_argument("--cf-kn", type=float, default=0.05)
     ap.add_argument("--cf-ref-hex", type=int, default=40)
     ap.add_argument("--cf-hex", default="10,20")

@@ -1368,6 +1368,39 @@ __device__ __forceinline__ void nk_block_store(double (*red)[kDigThreads / 64], 
         part[(size_t)i * gridDim.x + blockIdx.x] = ((red[i][0] + red[i][1]) + red[i][2]) + red[i][3];
 }
 
+// Columns 0..j of the block partials of <V_i, w> (V pointing at this lane's
+// cell in basis vector 0, vectors n apart): loads of four vectors at a time,
+// each dot in the order of the variables.
+template <int NV>
+__device__ __forceinline__ void nk_block_dots(double (*red)[kDigThreads / 64], const double* __restrict__ V,
+                                              size_t n, int j, const double* wv, bool live) {
+    int i = 0;
+    for (; i + 4 <= j + 1; i += 4) {
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
+        if (live) {
+            double a[4][NV];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) a[q][v] = V[(size_t)(i + q) * n + v];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) d[q] += a[q][v] * wv[v];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nk_block_column(red, i + q, d[q]);
+    }
+    for (; i <= j; ++i) {
+        double d = 0.0;
+        if (live) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) d += V[(size_t)i * n + v] * wv[v];
+        }
+        nk_block_column(red, i, d);
+    }
+}
+
 // Fixed-order sum over the blocks of column blockIdx.x into out[blockIdx.x].
 __global__ __launch_bounds__(kDigThreads) void k_nk_reduce(const double* part, int nblk, double* out) {
     const double* p = part + (size_t)blockIdx.x * nblk;
@@ -1501,15 +1534,7 @@ __global__ __launch_bounds__(kDigThreads) void k_nk_matvec(DigGeom g, DigWork w,
             nk.w[e] = wv[v];
         }
     }
-    for (int i = 0; i <= j; ++i) {
-        double d = 0.0;
-        if (live) {
-            const double* vi = nk.V + (size_t)i * n + NV * (size_t)c;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) d += vi[v] * wv[v];
-        }
-        nk_block_column(red, i, d);
-    }
+    nk_block_dots<NV>(red, nk.V + NV * (size_t)c, n, j, wv, live);
     nk_block_store(red, j + 1, nk.part);
 }
 
@@ -1521,18 +1546,39 @@ __global__ __launch_bounds__(kDigThreads) void k_nk_orth(DigGeom g, NkWork nk, i
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = c < g.nt;
     const size_t n = (size_t)NV * g.nt;
+    // the basis, the coefficients and w do not overlap: loads of several
+    // basis vectors can be in flight before w is written back
+    const double* __restrict__ V = nk.V + NV * (size_t)c;
+    const double* __restrict__ h = nk.red + off;
+    double* __restrict__ W = nk.w + NV * (size_t)c;
     double wv[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) wv[v] = 0.0;
     if (live) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const size_t e = NV * (size_t)c + v;
-            double t = nk.w[e];
-            for (int i = 0; i <= j; ++i) t -= nk.red[off + i] * nk.V[(size_t)i * n + e];
-            wv[v] = t;
-            nk.w[e] = t;
+        for (int v = 0; v < NV; ++v) wv[v] = W[v];
+        // each element subtracts h_i V_i[e] in ascending i
+        int i = 0;
+        for (; i + 4 <= j + 1; i += 4) {
+            double a[4][NV];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) a[q][v] = V[(size_t)(i + q) * n + v];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double hq = h[i + q];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) wv[v] -= hq * a[q][v];
+            }
         }
+        for (; i <= j; ++i) {
+            const double hi = h[i];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) wv[v] -= hi * V[(size_t)i * n + v];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) W[v] = wv[v];
     }
     if (norm) {
         double d = 0.0;
@@ -1542,15 +1588,7 @@ __global__ __launch_bounds__(kDigThreads) void k_nk_orth(DigGeom g, NkWork nk, i
         nk_block_store(red, 1, nk.part);
         return;
     }
-    for (int i = 0; i <= j; ++i) {
-        double d = 0.0;
-        if (live) {
-            const double* vi = nk.V + (size_t)i * n + NV * (size_t)c;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) d += vi[v] * wv[v];
-        }
-        nk_block_column(red, i, d);
-    }
+    nk_block_dots<NV>(red, V, n, j, wv, live);
     nk_block_store(red, j + 1, nk.part);
 }
 
