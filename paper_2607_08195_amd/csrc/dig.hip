@@ -1625,13 +1625,33 @@ __global__ __launch_bounds__(kDigThreads) void k_nk_try(DigGeom g, DigWork w, Nk
     if (c >= g.nt) return;
     const size_t n = (size_t)NV * g.nt;
     const double pc = g.vol[c] / w.dt[c] * (1.0 + 1.0 / cfl);
+    const double* __restrict__ V = nk.V + NV * (size_t)c;
+    const double* __restrict__ y = nk.y;
+    // z = sum_{i < jn} y_i V_i, each element in ascending i, four basis
+    // vectors in flight
+    double z[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) z[v] = 0.0;
+    int i = 0;
+    for (; i + 4 <= jn; i += 4) {
+        double a[4][NV];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a[q][v] = V[(size_t)(i + q) * n + v];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) z[v] += y[i + q] * a[q][v];
+    }
+    for (; i < jn; ++i)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) z[v] += y[i] * V[(size_t)i * n + v];
     double U[NV], P[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const size_t e = NV * (size_t)c + v;
-        double z = 0.0;
-        for (int i = 0; i < jn; ++i) z += nk.y[i] * nk.V[(size_t)i * n + e];
-        U[v] = nk.U[e] + alpha * (sc.s[v] * z / pc);
+        U[v] = nk.U[e] + alpha * (sc.s[v] * z[v] / pc);
         nk.Ut[e] = U[v];
     }
     if (!prim_of<NV>(g, U, P)) atomicOr(nk.flag, 1);
