@@ -8,7 +8,9 @@ bit-exact cells, (cell, pid) order and pair counts, positions within 1e-12,
 velocities within 1 float32 ulp (FP32) or 1e-12 relative (FP64), sums
 within 1e-12 of the column scale (the single-step criteria of the
 tetrahedral parity tests); the fields of the original cells from
-dsmc_sample_cells within 1e-10 of the oracle's, from the same sums.
+dsmc_sample_cells within 1e-10 of the oracle's, from the same sums.  The
+same with nitrogen's rotational energies (Borgnakke-Larsen on the
+decomposed cells).
 """
 import numpy as np
 import pytest
@@ -71,6 +73,42 @@ def test_mixed_cavity_parity(D, vel_fp32):
     assert np.all(np.nan_to_num(np.abs(gf - of)) <= 1e-10 * scale)
     c0 = o.counters()
     assert c0["lost"] == 0
+    sim.close()
+
+
+@pytest.mark.parametrize("vel_fp32", [0, 1])
+def test_mixed_cavity_rotating_gas_parity(D, vel_fp32):
+    """Nitrogen with two rotational degrees of freedom on the decomposed
+    mixed mesh: three steps from the oracle's state, with the single-step
+    criteria above plus rotational energies within 1e-12 relative (or of
+    k T0) and the rotational sums within 1e-12 of their column scale."""
+    KB = 1.380649e-23
+    m, g, wg, wo, tc = _workloads(D, vel_fp32=vel_fp32, ppc=15)
+    n2 = W.Species(mass=4.65e-26, d_ref=4.17e-10, omega=0.74, T_ref=273.0, alpha=1.0, dof_rot=2, z_rot=2.59)
+    for wl in (wg, wo):
+        wl.species = n2
+        wl.run.n_ss = 3
+    o = Oracle(wo)
+    o.step(3)
+    st = o.particles()
+    sim = D.Simulation(wg, fill=False, capacity=max(4 * o.np, 100000))
+    sim.set_state(st["x"], st["v"], st["cell"], st["pid"], o.step_index, o.next_pid, o.smax(), ir=st["ir"])
+    for _ in range(3):
+        o.step(1)
+        sim.step(1)
+    gs, os_ = sim.state(), o.particles()
+    compare_particles(gs, os_, vel_fp32, ctx=f"mixed n2 fp32={vel_fp32}")
+    d = np.abs(gs["ir"] - os_["ir"])
+    assert np.all(d <= 1e-12 * np.maximum(np.abs(os_["ir"]), KB * wo.run.T0)), d.max()
+    gc, ga = sim.pair_counts()
+    oc, oa = o.pair_counts()
+    assert np.array_equal(gc, oc) and np.array_equal(ga, oa)
+    assert oa.sum() > 0
+    gsum, ns = sim.sums(D.SAMPLE_STEADY)
+    assert ns == o.n_steady == 3
+    compare_sums(gsum, o.sums(0))
+    gr, nr = sim.rot_sums(D.SAMPLE_STEADY)
+    compare_sums(gr, o.rot_sums(0))
     sim.close()
 
 
