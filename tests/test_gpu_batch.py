@@ -7,6 +7,8 @@
   1e-12), and after steps the cell indices, (cell, pid) order and pair
   counts bit-exactly with positions and velocities to the single-step
   criteria.
+* The same with nitrogen: each case's rotational energies and rotational
+  sums match its own oracle run.
 * dsmc_graph_step gives the same particle state as dsmc_step, bit for bit,
   for even and odd step counts, on a single case and on a batch, with
   freestream inflow, and after the particle count has grown past the count
@@ -83,6 +85,47 @@ def test_batch_cases_match_oracle(D, vel_fp32):
         assert np.array_equal(np.isnan(fk), np.isnan(fo))
         scale = np.nanmax(np.abs(fo), axis=0, keepdims=True)
         assert np.all(np.nan_to_num(np.abs(fk - fo)) <= 1e-10 * scale), f"fields of case {k}"
+    g.close()
+
+
+def test_batch_rotating_gas_cases_match_oracle(D):
+    """The batch of test_batch_cases_match_oracle with nitrogen (two
+    rotational degrees of freedom): each case's rotational energies at the
+    fill and after three steps within 1e-12 relative (or of k T0) of the
+    oracle run of that case alone, cells, order and pair counts exact, the
+    rotational sums within 1e-12 of their column scale."""
+    KB = 1.380649e-23
+    n2 = W.Species(mass=4.65e-26, d_ref=4.17e-10, omega=0.74, T_ref=273.0, alpha=1.0, dof_rot=2, z_rot=2.59)
+    cases = _cases(0)
+    for wl in cases:
+        wl.species = n2
+    g = D.Simulation(cases)
+    begin = g.case_cells()
+    oracles = [Oracle(wl) for wl in cases]
+
+    def check(ctx):
+        st = g.state()
+        for k, o in enumerate(oracles):
+            m = (st["cell"] >= begin[k]) & (st["cell"] < begin[k + 1])
+            ok = o.particles()
+            compare_particles(_split(st, begin, k), ok, 0, ctx=f"{ctx} case {k}")
+            d = np.abs(st["ir"][m] - ok["ir"])
+            lim = 1e-12 * np.maximum(np.abs(ok["ir"]), KB * cases[k].run.T0)
+            assert np.all(d <= lim), f"{ctx} case {k}: rotational energies off by {d.max():.3e}"
+
+    check("fill")
+    for step in range(3):
+        g.step(1)
+        for o in oracles:
+            o.step(1)
+    check("after 3 steps")
+    nc, na = g.pair_counts()
+    rs, _ = g.rot_sums(D.SAMPLE_STEADY)
+    for k, o in enumerate(oracles):
+        oc, oa = o.pair_counts()
+        assert np.array_equal(nc[begin[k]:begin[k + 1]], oc) and np.array_equal(na[begin[k]:begin[k + 1]], oa)
+        compare_sums(rs[begin[k]:begin[k + 1]], o.rot_sums(0))
+    assert sum(int(o.pair_counts()[1].sum()) for o in oracles) > 0
     g.close()
 
 
