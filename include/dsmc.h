@@ -96,8 +96,8 @@ typedef struct {
  * with the heat conductivities from heat_relax = (A_tt, A_tr, A_rt, A_rr),
  * the relaxation matrix of eq. thermal_conductivity_matrix (all zero:
  * nitrogen's 0.786, -0.201, -0.059, 0.842; a singular matrix is
- * DSMC_E_INVALID); surface sampling does not take the rotation into
- * account. */
+ * DSMC_E_INVALID); surface sampling adds the rotational energy exchanged
+ * at diffuse walls (dsmc_get_surface_rot). */
 typedef struct {
     double mass;     /* kg */
     double d_ref;    /* reference diameter, m */
@@ -284,6 +284,16 @@ dsmc_status dsmc_surface_sampling(dsmc_ctx ctx, int32_t on);
  * (F_N and dt of the face's case in a batch; zeros without sampled steps).
  * Either pointer may be NULL.  Synchronises. */
 dsmc_status dsmc_get_surface(dsmc_ctx ctx, double* sums, double* fields, int64_t* n_steps);
+
+/* Rotational part of the surface sums of a rotating gas (the rotational
+ * heat flux the paper compares on the sphere, section 5): every diffuse
+ * re-emission adds to its face the incident molecule's rotational energy
+ * minus the re-emitted one's (J; specular faces keep it).  sums[n_bfaces] =
+ * that sum, qr[n_bfaces] = the rotational heat flux into the wall F_N sum /
+ * (A t) (W/m^2), over the *n_steps sampled steps of dsmc_get_surface; the
+ * sums are added with device atomics.  Either pointer may be NULL.
+ * DSMC_E_INVALID for a monatomic gas.  Synchronises. */
+dsmc_status dsmc_get_surface_rot(dsmc_ctx ctx, double* sums, double* qr, int64_t* n_steps);
 
 /* Particle state.  dsmc_get_state fills n_particles, step and next_pid; the
  * arrays (host, may be NULL) receive the particles in (cell, pid) order:

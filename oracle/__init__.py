@@ -51,6 +51,8 @@ def _load():
     lib.oracle_surface_sampling.argtypes = [P, C.c_int]
     lib.oracle_get_surface.argtypes = [P, P]
     lib.oracle_get_surface.restype = i64
+    lib.oracle_get_surface_rot.argtypes = [P, P]
+    lib.oracle_get_surface_rot.restype = i64
     lib.oracle_set_smax.argtypes = [P, P]
     lib.oracle_step_index.restype = u32
     lib.oracle_step_index.argtypes = [P]
@@ -239,6 +241,13 @@ class Oracle:
         (|v_in|^2 - |v_out|^2)/2, hits) and the number of sampled steps."""
         o = np.zeros((self.nb, 5))
         n = self.lib.oracle_get_surface(self.h, _p(o))
+        return o, int(n)
+
+    def surface_rot(self):
+        """Rotational energy given to each boundary face [n_bfaces] (a
+        rotating gas) and the number of sampled steps."""
+        o = np.zeros(self.nb)
+        n = self.lib.oracle_get_surface_rot(self.h, _p(o))
         return o, int(n)
 
     def smax(self):

@@ -136,7 +136,7 @@ void oracle_destroy(osim* s) {
                     s->g_shift, s->in_mean, s->in_a, s->in_beta, s->in_sig, s->in_ut1, s->in_ut2,
                     s->x, s->v, s->cell, s->pid, s->smax, s->ncand, s->nacc, s->start, s->acc,
                     s->ewma, s->ewma_m, s->local_acc, s->inst, s->cen, s->fcen, s->fnu, s->farea,
-                    s->lsq, s->mprev, s->surf, s->ir, s->racc, s->rewma, s->rinst};
+                    s->lsq, s->mprev, s->surf, s->rsurf, s->ir, s->racc, s->rewma, s->rinst};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i) free(ptrs[i]);
     free(s);
 }
@@ -488,7 +488,7 @@ int oracle_init_fill(osim* s, double n0, double T0, const double* u0) {
  * one hit to the face's sums, on the steps after n_ss while sampling is on
  * (the stress and heat flux a surface receives: section 5, sphere surface
  * pressure, shear stress and heat flux). */
-static void surface_hit(osim* s, int bf, uint32_t step, const double* a, const double* b) {
+static void surface_hit(osim* s, int bf, uint32_t step, const double* a, const double* b, double dI) {
     if (!s->surf_on || (int64_t)step <= (int64_t)s->n_ss) return;
     double* q = s->surf + 5 * (size_t)bf;
     q[0] += a[0] - b[0];
@@ -496,6 +496,8 @@ static void surface_hit(osim* s, int bf, uint32_t step, const double* a, const d
     q[2] += a[2] - b[2];
     q[3] += 0.5 * ((a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) - (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]));
     q[4] += 1.0;
+    /* a rotating gas: the rotational energy the molecule leaves at the wall */
+    if (s->rsurf) s->rsurf[bf] += dI;
 }
 
 /* n . a with fused multiply-adds, n0 a0 first: the rounding the tracking
@@ -561,9 +563,10 @@ static int trace(osim* s, double* x, double* v, double* ir, int* cellp, int entr
                 double tang = sw * (g1 * t1[i] + g2 * t2[i]);
                 v[i] = to_store(s, (vn * nin[i] + tang) + uw[i]);
             }
-            surface_hit(s, bf, step, vin, v);
             /* the re-emitted molecule's rotation is in equilibrium at the wall */
-            if (ir) *ir = -(KB * Tw) * log(u01(w[2], w[3]));
+            double inew = ir ? -(KB * Tw) * log(u01(w[2], w[3])) : 0.0;
+            surface_hit(s, bf, step, vin, v, ir ? *ir - inew : 0.0);
+            if (ir) *ir = inew;
             ++hits;
             s->walls++;
             entry = fb;
@@ -576,7 +579,7 @@ static int trace(osim* s, double* x, double* v, double* ir, int* cellp, int entr
             double f2 = 2.0 * (vn / nn);
             const double vin[3] = {v[0], v[1], v[2]};
             for (int i = 0; i < 3; ++i) v[i] = to_store(s, v[i] - f2 * n[i]);
-            surface_hit(s, bf, step, vin, v);
+            surface_hit(s, bf, step, vin, v, 0.0);
             s->walls++;
             entry = fb;
             break;
@@ -1008,6 +1011,11 @@ int oracle_surface_sampling(osim* s, int on) {
         if (!s->surf) s->surf = (double*)malloc(sizeof(double) * 5 * (size_t)(s->nb ? s->nb : 1));
         if (!s->surf) { set_err("out of memory"); return -1; }
         memset(s->surf, 0, sizeof(double) * 5 * (size_t)(s->nb ? s->nb : 1));
+        if (s->dr) {
+            if (!s->rsurf) s->rsurf = (double*)malloc(sizeof(double) * (size_t)(s->nb ? s->nb : 1));
+            if (!s->rsurf) { set_err("out of memory"); return -1; }
+            memset(s->rsurf, 0, sizeof(double) * (size_t)(s->nb ? s->nb : 1));
+        }
         s->surf_on = 1;
         s->surf_from = s->step;
         s->surf_to = -1;
@@ -1016,6 +1024,14 @@ int oracle_surface_sampling(osim* s, int on) {
         s->surf_to = s->step;
     }
     return 0;
+}
+
+int64_t oracle_get_surface_rot(const osim* s, double* sums) {
+    if (!s->rsurf) return 0;
+    if (sums) memcpy(sums, s->rsurf, sizeof(double) * (size_t)s->nb);
+    int64_t end = s->surf_to < 0 ? (int64_t)s->step : s->surf_to;
+    int64_t from = s->surf_from > s->n_ss ? s->surf_from : s->n_ss;
+    return end > from ? end - from : 0;
 }
 
 int64_t oracle_get_surface(const osim* s, double* sums) {

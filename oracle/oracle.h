@@ -83,6 +83,11 @@ uint32_t oracle_step_index(const osim*);
  * steps (steps after n_ss inside the on window). */
 int oracle_surface_sampling(osim*, int on);
 int64_t oracle_get_surface(const osim*, double* sums);
+/* A rotating gas: the rotational energy given to each boundary face,
+ * sums[nb] (incident minus re-emitted I_r at every diffuse re-emission);
+ * returns the sampled step count (0 and nothing copied for a monatomic
+ * gas). */
+int64_t oracle_get_surface_rot(const osim*, double* sums);
 uint32_t oracle_next_pid(const osim*);
 
 /* Per-cell candidate / accepted pair counts of the last collide stage. */

@@ -61,6 +61,7 @@ struct osim {
     /* surface sampling: [nb][5] sums of (v_in - v_out), (|v_in|^2 - |v_out|^2)/2
      * and hits over the sampled steps while on; window start and end steps */
     double* surf;
+    double* rsurf; /* [nb] rotational energy given to each face (rotating gas) */
     int surf_on;
     int64_t surf_from, surf_to;
     /* reference state of the run (initial fill) and DIG coupling state */

@@ -1031,9 +1031,10 @@ dsmc_status dsmc_surface_sampling(dsmc_ctx c, int32_t on) {
     dsmc_status st = sync_scalars(c, &sc);
     if (st != DSMC_OK) return st;
     if (on) {
-        if (!c->d_surf && !alloc_n(c, c->d_surf, 5 * (size_t)c->nb + 5))
+        // five rows, and the rotational-energy row of a rotating gas
+        if (!c->d_surf && !alloc_n(c, c->d_surf, 6 * (size_t)c->nb + 6))
             return fail(c, DSMC_E_OOM, "device allocation failed");
-        launch_fill_f64(c->stream, c->d_surf, 0.0, 5 * (int64_t)c->nb + 5);
+        launch_fill_f64(c->stream, c->d_surf, 0.0, 6 * (int64_t)c->nb + 6);
         HIP_TRY(c, hipGetLastError());
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         c->mesh.surf = c->d_surf;
@@ -1091,6 +1092,42 @@ dsmc_status dsmc_get_surface(dsmc_ctx c, double* sums, double* fields, int64_t* 
             f[1] = s * dn;
             for (int i = 0; i < 3; ++i) f[2 + i] = s * (d[i] - dn * n[i]);
             f[5] = s * h[3 * (size_t)nb + b];
+        }
+    }
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_get_surface_rot(dsmc_ctx c, double* sums, double* qr, int64_t* n_steps) {
+    if (!c) return fail(c, DSMC_E_INVALID, "bad arguments");
+    if (!c->dr) return fail(c, DSMC_E_INVALID, "the gas has no rotational degrees of freedom");
+    Scalars sc;
+    dsmc_status st = sync_scalars(c, &sc);
+    if (st != DSMC_OK) return st;
+    const int nb = c->nb;
+    std::vector<double> h((size_t)nb, 0.0);
+    if (c->d_surf)
+        HIP_TRY(c, hipMemcpy(h.data(), c->d_surf + 5 * (size_t)nb, sizeof(double) * nb, hipMemcpyDeviceToHost));
+    const int64_t end = c->surf_to < 0 ? (int64_t)sc.step : c->surf_to;
+    const int64_t from = std::max<int64_t>(c->surf_from, c->n_ss);
+    const int64_t ns = c->d_surf && end > from ? end - from : 0;
+    if (n_steps) *n_steps = ns;
+    if (sums)
+        for (int b = 0; b < nb; ++b) sums[b] = h[b];
+    if (qr) {
+        std::vector<CaseDev> cases(std::max(1, c->n_cases));
+        if (c->n_cases)
+            HIP_TRY(c, hipMemcpy(cases.data(), c->d_cases, sizeof(CaseDev) * c->n_cases, hipMemcpyDeviceToHost));
+        for (int b = 0; b < nb; ++b) {
+            double FN = c->FN, dt = c->dt;
+            if (c->n_cases) {
+                const int o = c->hm.orig[c->hm.bf_tet[b]];
+                const int k = (int)(std::upper_bound(c->case_cell0.begin(), c->case_cell0.end(), o) -
+                                    c->case_cell0.begin()) - 1;
+                FN = cases[k].FN;
+                dt = cases[k].dt;
+            }
+            const double ta = c->hm.bf_area[b] * ((double)ns * dt);
+            qr[b] = ta > 0 ? FN * h[b] / ta : 0.0;
         }
     }
     return DSMC_OK;

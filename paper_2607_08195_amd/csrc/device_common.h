@@ -166,8 +166,10 @@ struct MeshDev {
 // velocity a into b: the velocity change a - b (momentum given to the wall
 // per unit mass), the energy change (|a|^2 - |b|^2) / 2 and the hit, added to
 // the face's sums on sampled steps.
+// dI: the rotational energy the molecule gives the wall (incident minus
+// re-emitted I_r; a rotating gas only, sixth row).
 __device__ __forceinline__ void surface_hit(const MeshDev& m, int bf, uint32_t step, double a0, double a1,
-                                            double a2, double b0, double b1, double b2) {
+                                            double a2, double b0, double b1, double b2, double dI) {
     if (!m.surf || (int64_t)step <= (int64_t)m.n_ss) return;
     double* s = m.surf + bf;
     const size_t nb = (size_t)m.nb;
@@ -176,6 +178,7 @@ __device__ __forceinline__ void surface_hit(const MeshDev& m, int bf, uint32_t s
     unsafeAtomicAdd(s + 2 * nb, a2 - b2);
     unsafeAtomicAdd(s + 3 * nb, 0.5 * ((a0 * a0 + a1 * a1 + a2 * a2) - (b0 * b0 + b1 * b1 + b2 * b2)));
     unsafeAtomicAdd(s + 4 * nb, 1.0);
+    if (m.rot && dI != 0.0) unsafeAtomicAdd(s + 5 * nb, dI);
 }
 
 // Generator key and time step of the case that owns `cell` (batch mode).
@@ -262,8 +265,10 @@ __device__ __forceinline__ TraceOut trace(const MeshDev& m, double& x0, double& 
             v0 = round_store<VT>((vn * fr[0] + g.sw * (g1 * fr[3] + g2 * fr[6])) + g.u[0]);
             v1 = round_store<VT>((vn * fr[1] + g.sw * (g1 * fr[4] + g2 * fr[7])) + g.u[1]);
             v2 = round_store<VT>((vn * fr[2] + g.sw * (g1 * fr[5] + g2 * fr[8])) + g.u[2]);
-            surface_hit(m, bf, step, a0, a1, a2, v0, v1, v2);
-            if (ir) *ir = -g.kT * log(u01(r1.w[2], r1.w[3]));
+            // the re-emitted molecule's rotation is in equilibrium at the wall
+            const double Inew = ir ? -g.kT * log(u01(r1.w[2], r1.w[3])) : 0.0;
+            surface_hit(m, bf, step, a0, a1, a2, v0, v1, v2, ir ? *ir - Inew : 0.0);
+            if (ir) *ir = Inew;
             ++hits;
             ++out.walls;
             entry = fb;
@@ -276,7 +281,7 @@ __device__ __forceinline__ TraceOut trace(const MeshDev& m, double& x0, double& 
             v0 = round_store<VT>(v0 - f2 * pl.x);
             v1 = round_store<VT>(v1 - f2 * pl.y);
             v2 = round_store<VT>(v2 - f2 * pl.z);
-            surface_hit(m, bf, step, a0, a1, a2, v0, v1, v2);
+            surface_hit(m, bf, step, a0, a1, a2, v0, v1, v2, 0.0);
             ++out.walls;
             entry = fb;
         } else if (g.kind == kBcPeriodic) {
@@ -342,9 +347,10 @@ __device__ __forceinline__ void diffuse_reemit(const MeshDev& m, Walker& w, int 
     w.v0 = round_store<VT>((vn * fr[0] + g.sw * (g1 * fr[3] + g2 * fr[6])) + g.u[0]);
     w.v1 = round_store<VT>((vn * fr[1] + g.sw * (g1 * fr[4] + g2 * fr[7])) + g.u[1]);
     w.v2 = round_store<VT>((vn * fr[2] + g.sw * (g1 * fr[5] + g2 * fr[8])) + g.u[2]);
-    surface_hit(m, bf, step, a0, a1, a2, w.v0, w.v1, w.v2);
     // the re-emitted molecule's rotation is in equilibrium at the wall
-    if (m.rot) w.ir = -g.kT * log(u01(r1.w[2], r1.w[3]));
+    const double Inew = m.rot ? -g.kT * log(u01(r1.w[2], r1.w[3])) : 0.0;
+    surface_hit(m, bf, step, a0, a1, a2, w.v0, w.v1, w.v2, m.rot ? w.ir - Inew : 0.0);
+    if (m.rot) w.ir = Inew;
     ++w.hits;
     ++w.walls;
     w.entry = fb;
@@ -435,7 +441,7 @@ __device__ __forceinline__ int hop_once(const MeshDev& m, Walker& w, uint32_t st
         w.v0 = round_store<VT>(w.v0 - f2 * pl.x);
         w.v1 = round_store<VT>(w.v1 - f2 * pl.y);
         w.v2 = round_store<VT>(w.v2 - f2 * pl.z);
-        if (SURF) surface_hit(m, bf, step, a0, a1, a2, w.v0, w.v1, w.v2);
+        if (SURF) surface_hit(m, bf, step, a0, a1, a2, w.v0, w.v1, w.v2, 0.0);
         ++w.walls;
         w.entry = fb;
     } else if (g.kind == kBcPeriodic) {

@@ -187,6 +187,7 @@ _lib.dig_batch_enable.argtypes = [ctx_t, P]
 _lib.dsmc_surface_sampling.argtypes = [ctx_t, C.c_int32]
 _lib.dsmc_instant_sampling.argtypes = [ctx_t, C.c_int32]
 _lib.dsmc_get_surface.argtypes = [ctx_t, P, P, C.POINTER(C.c_int64)]
+_lib.dsmc_get_surface_rot.argtypes = [ctx_t, P, P, C.POINTER(C.c_int64)]
 for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_rot_sums",
            "dsmc_rot_sample", "dsmc_mesh_decompose", "dsmc_sample_cells", "dsmc_get_state",
            "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
@@ -194,7 +195,7 @@ for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_ge
            "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_set_rot_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
            "dsmc_mlp_get_weights", "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train",
            "dsmc_mlp_init_weights", "dsmc_mlp_backward_noalloc", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_surface_sampling", "dsmc_get_surface",
-           "dsmc_instant_sampling", "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
+           "dsmc_get_surface_rot", "dsmc_instant_sampling", "dsmc_batch_init", "dsmc_batch_cases", "dsmc_graph_step",
            "dsmc_get_tuning", "dsmc_set_tuning", "dsmc_autotune"]:
     getattr(_lib, _f).restype = C.c_int32
 
@@ -208,7 +209,7 @@ EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_g
             "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_backward_noalloc", "dsmc_mlp_adam_step",
             "dsmc_mlp_train", "dsmc_mlp_last_error",
             "dsmc_mlp_destroy", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_surface_sampling",
-            "dsmc_get_surface", "dsmc_instant_sampling"]
+            "dsmc_get_surface", "dsmc_get_surface_rot", "dsmc_instant_sampling"]
 
 
 class DsmcError(RuntimeError):
@@ -475,6 +476,16 @@ class Simulation:
         n = C.c_int64()
         self._c(_lib.dsmc_get_surface(self.ctx, _p(sums), _p(fields), C.byref(n)))
         return sums, fields, int(n.value)
+
+    def surface_rot(self):
+        """Rotational energy given to each boundary face [n_bfaces] (J),
+        the rotational heat flux into it [n_bfaces] (W/m^2) and the sampled
+        step count (dsmc_get_surface_rot; a rotating gas)."""
+        sums = np.zeros(self.nb)
+        qr = np.zeros(self.nb)
+        n = C.c_int64()
+        self._c(_lib.dsmc_get_surface_rot(self.ctx, _p(sums), _p(qr), C.byref(n)))
+        return sums, qr, int(n.value)
 
     def pair_counts(self):
         a = np.zeros(self.nt, np.int32); b = np.zeros(self.nt, np.int32)

@@ -5,7 +5,8 @@ batch of cavities.  Hit counts per face exact; velocity- and energy-change
 sums within 1e-12 of the column's largest magnitude (the device adds them
 with atomics, in hit order); the sampled step count equal; the library's
 fields (number flux, pressure, shear, heat flux) equal to the same formulas
-evaluated on the oracle's sums within 1e-10."""
+evaluated on the oracle's sums within 1e-10.  With nitrogen, the rotational
+energy each face receives and its rotational heat flux as well."""
 import numpy as np
 import pytest
 
@@ -103,6 +104,46 @@ def test_surface_sums_match_oracle(D, case, move):
     gs2, _, gn2 = g.surface()
     assert gn2 == gn and np.array_equal(gs2, gs)
     g.close()
+
+
+@pytest.mark.parametrize("case", ["cavity_lid_fp64", "plates_couette", "sphere_hypersonic"])
+def test_rotational_surface_sums_match_oracle(D, case):
+    """Nitrogen (two rotational degrees of freedom): the rotational energy
+    each face receives within 1e-12 of the largest magnitude, the
+    translational sums and hit counts as above, and the rotational heat
+    flux equal to F_N sum / (A t)."""
+    wl = CASES[case]()
+    wl.species = W.Species(mass=4.65e-26, d_ref=4.17e-10, omega=0.74, T_ref=273.0, alpha=1.0, dof_rot=2,
+                           z_rot=2.59)
+    pre = 3
+    wl.run.n_ss = pre + 1
+    o = Oracle(wl)
+    o.step(pre)
+    st = o.particles()
+    g = D.Simulation(wl, fill=False, capacity=max(4 * o.np, 100000))
+    g.set_state(st["x"], st["v"], st["cell"], st["pid"], o.step_index, o.next_pid, o.smax(), ir=st["ir"])
+    o.surface_sampling(True)
+    g.surface_sampling(True)
+    o.step(5)
+    g.step(5)
+    gs, gf, gn = g.surface()
+    os_, on = o.surface()
+    _compare(gs, gf, gn, os_, on, wl, case)
+    gr, qr, nr = g.surface_rot()
+    orr, onr = o.surface_rot()
+    assert nr == onr == on == 4
+    assert np.abs(orr).max() > 0, case
+    assert np.all(np.abs(gr - orr) <= 1e-12 * np.abs(orr).max()), f"{case}: rotational sums"
+    xyz, bf = wl.mesh.xyz, wl.mesh.bfaces
+    area = 0.5 * np.linalg.norm(np.cross(xyz[bf[:, 1]] - xyz[bf[:, 0]], xyz[bf[:, 2]] - xyz[bf[:, 0]]), axis=1)
+    q_o = wl.run.F_N * orr / (area * on * wl.run.dt)
+    assert np.all(np.abs(qr - q_o) <= 1e-10 * np.abs(q_o).max()), f"{case}: rotational heat flux"
+    g.close()
+    # a monatomic gas has no rotational surface sums
+    a = D.Simulation(W.cavity(n_hex=2, Kn=0.5, ppc=5))
+    with pytest.raises(D.DsmcError):
+        a.surface_rot()
+    a.close()
 
 
 def test_surface_graph_steps_and_restart(D):

@@ -11,7 +11,9 @@ flux compared on the sphere in section 5) pinned to:
   * free-molecular heat transfer between plates at T1 and T2: number flux
     Phi = n sqrt(2k / (pi m)) sqrt(T1 T2) / (sqrt T1 + sqrt T2) on both, heat
     flux 2 k Phi (T2 - T1) into the colder plate; specular side walls take
-    only normal momentum and no energy.
+    only normal momentum and no energy;
+  * the same plates with two rotational degrees of freedom: rotational heat
+    flux Phi k (T2 - T1) into the colder plate (k (T2 - T1) per hit).
 """
 import math
 
@@ -169,6 +171,47 @@ def test_free_molecular_heat_transfer_between_plates():
         for r in res:
             assert np.all(np.abs(r[g]["tau"]) <= 1e-9 * abs(r[g]["p"]))
             assert abs(r[g]["q"]) <= 1e-9 * abs(r[g]["p"]) * 1e3
+
+
+def test_free_molecular_rotational_heat_transfer_between_plates():
+    """A collisionless gas with two rotational degrees of freedom between
+    diffuse plates at T1 and T2: a molecule reaching a plate last left the
+    other one, so it brings a rotational energy of mean k T_other and
+    leaves with mean k T_plate; the rotational heat flux into the colder
+    plate is Phi k (T2 - T1), half the translational 2 k Phi (T2 - T1) (the
+    total (2 + d_r/2) k Phi (T2 - T1) of free-molecular heat transfer in a
+    diatomic gas), the opposite into the hotter one; per hit the rotational
+    energy left is k (T2 - T1) on average; specular side walls take none."""
+    T1, T2 = 200.0, 400.0
+    wl = W.plates(n=(2, 8, 2), T1=T1, T2=T2, ppc=60, periodic=False, vel_fp32=0)
+    wl.species = W.Species(d_ref=1e-25, dof_rot=2, z_rot=2.59)
+    o = Oracle(wl)
+    m = wl.species.mass
+    o.step(150)
+    n = o.np * wl.run.F_N / 1.0
+    area, _ = _face_geometry(wl)
+    phi = n * math.sqrt(2 * KB / (math.pi * m)) * math.sqrt(T1 * T2) / (math.sqrt(T1) + math.sqrt(T2))
+    qr_exp = KB * phi * (T2 - T1)
+    qr = {2: [], 3: []}
+    per_hit = {2: [], 3: []}
+    for _ in range(24):
+        o.surface_sampling(True)
+        o.step(40)
+        sums, ns = o.surface()
+        rs, nr = o.surface_rot()
+        assert ns == nr == 40
+        t = ns * wl.run.dt
+        for g in (0, 1, 4, 5):
+            assert np.all(rs[wl.mesh.bgroup == g] == 0.0)
+        for g in (2, 3):
+            sel = wl.mesh.bgroup == g
+            qr[g].append(wl.run.F_N * rs[sel].sum() / (area[sel].sum() * t))
+            per_hit[g].append(rs[sel].sum() / sums[sel, 4].sum())
+    for g, sign in ((2, 1.0), (3, -1.0)):
+        q, se = batch_stat(qr[g])
+        assert abs(q - sign * qr_exp) < 3.5 * se + 0.01 * qr_exp, (g, q, qr_exp, se)
+        h, seh = batch_stat(per_hit[g])
+        assert abs(h - sign * KB * (T2 - T1)) < 3.5 * seh + 0.01 * KB * (T2 - T1), (g, h, seh)
 
 
 # --------------------------------------------------------------------------
