@@ -174,11 +174,19 @@ def test_surface_graph_steps_and_restart(D):
     b.close()
 
 
-def test_surface_batch_matches_oracle_per_case(D):
+@pytest.mark.parametrize("gas", ["argon", "nitrogen"])
+def test_surface_batch_matches_oracle_per_case(D, gas):
+    """Three cavities of different size, Kn and lid speed in one batch: each
+    case's slice of the surface sums against its own oracle run; with
+    nitrogen also its rotational sums (within 1e-12 of the case's largest)
+    and rotational heat flux (F_N of the case)."""
     specs = [(3, 0.05, 150.0), (4, 0.5, 30.0), (2, 1.0, 80.0)]
     cases = []
     for k, (n, Kn, lid) in enumerate(specs):
         wl = W.cavity(n_hex=n, Kn=Kn, ppc=12, lid_speed=lid, seed=7, vel_fp32=1)
+        if gas == "nitrogen":
+            wl.species = W.Species(mass=4.65e-26, d_ref=4.17e-10, omega=0.74, T_ref=273.0, alpha=1.0, dof_rot=2,
+                                   z_rot=2.59)
         wl.run.case_id = 20 + k
         wl.run.n_ss = 0
         cases.append(wl)
@@ -191,11 +199,24 @@ def test_surface_batch_matches_oracle_per_case(D):
     for o in oracles:
         o.step(3)
     gs, gf, gn = g.surface()
+    if gas == "nitrogen":
+        gr, gq, gnr = g.surface_rot()
+        assert gnr == gn
     b0 = 0
     for k, (o, wl) in enumerate(zip(oracles, cases)):
         os_, on = o.surface()
         nb = len(wl.mesh.bfaces)
         _compare(gs[b0:b0 + nb], gf[b0:b0 + nb], gn, os_, on, wl, f"case {k}")
+        if gas == "nitrogen":
+            orr, onr = o.surface_rot()
+            assert onr == on and np.abs(orr).max() > 0
+            r = gr[b0:b0 + nb]
+            assert np.all(np.abs(r - orr) <= 1e-12 * np.abs(orr).max()), f"case {k}: rotational sums"
+            xyz, bf = wl.mesh.xyz, wl.mesh.bfaces
+            area = 0.5 * np.linalg.norm(np.cross(xyz[bf[:, 1]] - xyz[bf[:, 0]], xyz[bf[:, 2]] - xyz[bf[:, 0]]),
+                                        axis=1)
+            q_o = wl.run.F_N * orr / (area * on * wl.run.dt)
+            assert np.all(np.abs(gq[b0:b0 + nb] - q_o) <= 1e-10 * np.abs(q_o).max()), f"case {k}: flux"
         b0 += nb
     assert b0 == len(gs)
     g.close()
