@@ -51,6 +51,48 @@ __device__ __forceinline__ void block_counters(int a, int b, int c, int d, unsig
     }
 }
 
+// Slot of a particle in its cell's histogram bin, aggregated over the
+// workgroup: the lanes' destination cells go into an LDS hash table
+// (open addressing, twice as many entries as lanes, so a probe always ends),
+// each lane takes its rank among the workgroup's particles of that cell
+// from an LDS counter, then one global atomic per distinct cell reserves the
+// workgroup's run in the bin.  After a step at a mean free path of a few
+// cells a wave's 64 particles land in about 44 different cells, a
+// workgroup's 256 in about 110, so this issues half the global atomics of
+// the per-wave grouping.  Every lane of the workgroup must call it (it
+// synchronises the workgroup); blockDim.x <= kBinLanes.
+constexpr int kBinLanes = 256;
+constexpr int kBinTable = 2 * kBinLanes;
+__device__ __forceinline__ uint32_t block_bin_slot(int32_t* counts, int cell, bool active) {
+    __shared__ int hkey[kBinTable];
+    __shared__ int hcnt[kBinTable];
+    const int t = threadIdx.x;
+    for (int e = t; e < kBinTable; e += blockDim.x) {
+        hkey[e] = -1;
+        hcnt[e] = 0;
+    }
+    __syncthreads();
+    int h = 0, local = 0;
+    if (active) {
+        h = (int)(((uint32_t)cell * 2654435761u) >> 23);  // 9 bits: kBinTable = 512
+        for (int probe = 0; probe < kBinTable; ++probe) {
+            const int old = atomicCAS(&hkey[h], -1, cell);
+            if (old == -1 || old == cell) break;
+            h = (h + 1) & (kBinTable - 1);
+        }
+        local = atomicAdd(&hcnt[h], 1);
+    }
+    __syncthreads();
+    // hcnt now holds each cell's count; the owner of an entry replaces it
+    // by the bin offset the global atomic returns
+    for (int e = t; e < kBinTable; e += blockDim.x) {
+        const int key = hkey[e];
+        if (key >= 0) hcnt[e] = atomicAdd(&counts[key], hcnt[e]);
+    }
+    __syncthreads();
+    return active ? (uint32_t)(hcnt[h] + local) : 0u;
+}
+
 // Wave-aggregated push of the lanes with `park` set into a part of the
 // parked-particle queue (one atomic per wave); by default the part of this
 // workgroup.
@@ -313,7 +355,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     }
     queue_push(q, park, i, w.t, (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22));
     {
-        const uint32_t slot = bin_slot(counts, dest, dest >= 0);
+        const uint32_t slot = block_bin_slot(counts, dest, dest >= 0);
         if (dest >= 0) rank[i] = slot;
     }
     block_counters(hops, walls, rem, lost, &ctr->hops, &ctr->walls, &ctr->removed, &ctr->lost);
@@ -395,7 +437,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
             }
             queue_push(q, park, i, w.t, (w.entry & 3) | (w.hits << 2) | (w.nhop << 12) | (w.walls << 22),
                        (int)(tile % kQueueParts));
-            const uint32_t slot = bin_slot(counts, dest, dest >= 0);
+            // workgroup-uniform: every lane reaches it once per tile
+            const uint32_t slot = block_bin_slot(counts, dest, dest >= 0);
             if (dest >= 0) rank[i] = slot;
         }
     }
