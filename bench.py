@@ -46,8 +46,17 @@ STAGES = {"move": ["move", "move_walls"], "scan": ["scan"], "sort": ["sort_perm"
 # WRITE_SIZE per step, summed over the stage's kernels and scaled by the
 # copy-kernel calibration) and the source digest they were taken on; the
 # traffic figure is reported only while the digest matches.
-TRAFFIC = {"stage": "move", "digest": "91851e4eda388ccf", "bytes_per_launch": 1255277290,
+TRAFFIC = {"stage": "move", "digest": "e71c6d34ff86ff7a", "bytes_per_launch": 1255456291,
            "workload": "cavity_40^3x6_Kn0.1", "source": "profiles/step_kernels_cavity40.md"}
+
+
+# rocprofv3 --pmc TCP_TOTAL_CACHE_ACCESSES_sum of the move kernel (vector
+# L1 line accesses per dispatch, the unit of the line-read calibration) on
+# the same source digest: the move kernel's bound is the L1's line-access
+# rate, set by its divergent 16-byte loads of the cells' planes and
+# neighbour codes.
+L1 = {"kernel": "move", "digest": "e71c6d34ff86ff7a", "accesses_per_launch": 302300000,
+      "workload": "cavity_40^3x6_Kn0.1", "source": "profiles/step_kernels_cavity40.md"}
 
 
 def _kernel_digest():
@@ -149,6 +158,40 @@ def calibrate_copy(dsmc, W, nbytes=2 << 30, reps=10):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     print(json.dumps({"copy_bytes_each_way": nbytes, "ms": dt * 1e3, "GBps_read_plus_write": 2 * nbytes / dt / 1e9}))
+    sim.close()
+
+
+def line_read_rate(sim, shares=(1, 4, 64), iters=256, blocks=8192, reps=3):
+    """Vector-L1 accesses per CU and ns of scattered 16-byte reads from a
+    2 MiB (L2-resident) table, one line per `share` lanes per load: per
+    share the accesses in the unit of rocprofv3's TCP_TOTAL_CACHE_ACCESSES
+    (a 16-byte load counts two per distinct line of a wave instruction, at
+    least eight per instruction; measured with the counter for shares 1, 4
+    and 64), the time and the rate."""
+    import torch
+    nbytes = 2 << 20
+    tab = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    out = {}
+    for share in shares:
+        sim.device_line_reads(tab.data_ptr(), nbytes, sink.data_ptr(), share, iters, blocks)
+        sim.sync()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sim.device_line_reads(tab.data_ptr(), nbytes, sink.data_ptr(), share, iters, blocks)
+        sim.sync()
+        dt = (time.perf_counter() - t0) / reps
+        acc = blocks * 4.0 * iters * 2 * max(64 // share, 4)
+        out[share] = {"ms": round(dt * 1e3, 4), "line_accesses": acc, "per_cu_ns": round(acc / 256 / (dt * 1e9), 4)}
+    del tab, sink
+    return out
+
+
+def calibrate_l1(dsmc, W):
+    sim = dsmc.Simulation(W.cavity(n_hex=2, ppc=2))
+    r = line_read_rate(sim)
+    print(json.dumps({"line_reads": r, "peak_per_cu_ns": max(v["per_cu_ns"] for v in r.values())}))
     sim.close()
 
 
@@ -869,6 +912,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="time a plain device copy of 2 GiB (HBM calibration of the traffic counters)")
+    ap.add_argument("--calibrate-l1", action="store_true",
+                    help="time scattered line reads (vector-L1 access-rate calibration)")
     args = ap.parse_args()
     args.graph = not args.eager
     if args.gpus != 1:
@@ -889,6 +934,8 @@ def main():
 
     if args.calibrate_copy:
         return calibrate_copy(dsmc, W)
+    if args.calibrate_l1:
+        return calibrate_l1(dsmc, W)
     if args.workload == "ensemble64":
         return bench_ensemble(args, dsmc, W)
     if args.workload == "sphere":
@@ -967,6 +1014,15 @@ def main():
                     traffic=None if traffic is None else round(traffic, 1),
                     bytes_per_particle_step=round(bytes_launch[dominant] / npart, 2))
     copy_gbs = copy_rate(sim)
+    # the move kernel against the vector L1's line-access rate, measured here
+    l1 = None
+    if L1 and L1.get("digest") == digest and L1.get("workload") == wl.name and per_launch.get("move", 0) > 0:
+        lr = line_read_rate(sim)
+        peak_l1 = max(v["per_cu_ns"] for v in lr.values())
+        floor_ms = L1["accesses_per_launch"] / 256 / peak_l1 / 1e6
+        l1 = {"kernel": "move", "accesses_per_launch": L1["accesses_per_launch"],
+              "peak_per_cu_ns": peak_l1, "floor_ms": round(floor_ms, 4), "kernel_ms": round(per_launch["move"], 4),
+              "frac": round(floor_ms / per_launch["move"], 4)}
 
     out = {
         "metric": "particle-steps/s",
@@ -993,6 +1049,7 @@ def main():
         "stage_algorithmic_GBps": {k: round(v, 1) for k, v in gbs.items()},
         "step_algorithmic_bytes_per_particle": round(step_bytes / npart, 1),
         "roofline": roofline,
+        "l1_roofline": l1,
         "copy_kernel_GBps": round(copy_gbs, 1),
         "kernel_digest": digest,
     }

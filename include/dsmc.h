@@ -357,6 +357,21 @@ dsmc_status dsmc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out,
  * stream (HBM bandwidth calibration of the traffic counters). */
 dsmc_status dsmc_device_copy(dsmc_ctx ctx, void* dst, const void* src, size_t bytes);
 
+/* Scattered reads for calibrating the vector L1's line-access rate (the
+ * limit of the move kernel's geometry gathers), on the context stream:
+ * `blocks` workgroups of 256 lanes; per iteration each group of `share`
+ * consecutive lanes loads 16 bytes from the start of one pseudo-randomly
+ * chosen 128-byte line among the first 2^k lines of `table` (2^k the
+ * largest power of two with 128 * 2^k <= bytes), so one wave instruction
+ * touches 64 / share lines; `iters` iterations per lane.  table: device
+ * memory, at least 128 bytes, 16-byte aligned, read only.  sink: 4 bytes of
+ * device memory, written only if the sum of the loaded words equals a fixed
+ * constant.  DSMC_E_INVALID for null pointers, a short or misaligned table,
+ * share not a power of two in [1, 64], iters outside [1, 2^20] or blocks
+ * outside [1, 2^24]. */
+dsmc_status dsmc_device_line_reads(dsmc_ctx ctx, const void* table, size_t bytes, void* sink, int share, int iters,
+                                   int blocks);
+
 /* ---- batches, graphs and kernel schedules ------------------------------ */
 
 /* Many independent cases in one context (a batch): the cases' meshes are

@@ -183,6 +183,8 @@ void launch_fields(hipStream_t s, const double* sums, int nt, double ns, double 
                    const CaseDev* cases);
 void launch_philox(hipStream_t s, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n);
 void launch_copy(hipStream_t s, const void* src, void* dst, size_t bytes);
+void launch_line_reads(hipStream_t s, const void* table, uint32_t line_mask, int iters, int share, int blocks,
+                       void* sink);
 void launch_fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n);
 void launch_fill_f64(hipStream_t s, double* p, double v, int64_t n);
 

@@ -1642,6 +1642,23 @@ __global__ __launch_bounds__(256) void k_copy16(const uint4* src, uint4* dst, in
         if (base + 256 * k < n16) dst[base + 256 * k] = v[k];
 }
 
+// Scattered 16-byte loads, one 128-byte line of the table per group of
+// `share` consecutive lanes and iteration, lines drawn by a linear
+// congruential sequence (calibration of the vector L1's line-access rate,
+// the limit of gather-bound kernels).  The sum of the loaded words is
+// stored only if it equals a constant, which keeps the loads.
+__global__ __launch_bounds__(256) void k_line_reads(const uint4* tab, uint32_t line_mask, int iters, int share,
+                                                    uint32_t* sink) {
+    uint32_t h = ((blockIdx.x * 256u + threadIdx.x) / (uint32_t)share) * 2654435761u + 12345u;
+    uint32_t acc = 0;
+    for (int k = 0; k < iters; ++k) {
+        h = h * 1664525u + 1013904223u;
+        const uint4 a = tab[(size_t)((h >> 8) & line_mask) * 8];
+        acc += a.x ^ a.w;
+    }
+    if (acc == 0x9e3779b9u) sink[0] = acc;
+}
+
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -1976,6 +1993,12 @@ void launch_copy(hipStream_t s, const void* src, void* dst, size_t bytes) {
     if (n16 > 0)
         hipLaunchKernelGGL(k_copy16, dim3((unsigned)((n16 + 1023) / 1024)), dim3(256), 0, s, (const uint4*)src,
                            (uint4*)dst, n16);
+}
+
+void launch_line_reads(hipStream_t s, const void* table, uint32_t line_mask, int iters, int share, int blocks,
+                       void* sink) {
+    hipLaunchKernelGGL(k_line_reads, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4*)table, line_mask, iters,
+                       share, (uint32_t*)sink);
 }
 
 void launch_fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n) {

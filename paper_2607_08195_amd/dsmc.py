@@ -152,6 +152,7 @@ _lib.dsmc_profile_name.argtypes = [C.c_int32]
 _lib.dsmc_profile_name.restype = C.c_char_p
 _lib.dsmc_philox.argtypes = [P, P, P, C.c_int64]
 _lib.dsmc_device_copy.argtypes = [ctx_t, P, P, C.c_size_t]
+_lib.dsmc_device_line_reads.argtypes = [ctx_t, P, C.c_size_t, P, C.c_int, C.c_int, C.c_int]
 _lib.dsmc_last_error.argtypes = [ctx_t]
 _lib.dsmc_last_error.restype = C.c_char_p
 _lib.dsmc_destroy.argtypes = [ctx_t]
@@ -191,7 +192,7 @@ _lib.dsmc_get_surface_rot.argtypes = [ctx_t, P, P, C.POINTER(C.c_int64)]
 for _f in ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_get_sums", "dsmc_get_rot_sums",
            "dsmc_rot_sample", "dsmc_mesh_decompose", "dsmc_sample_cells", "dsmc_get_state",
            "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
-           "dsmc_profile", "dsmc_philox", "dsmc_device_copy", "dig_couple", "dig_get", "dig_residual",
+           "dsmc_profile", "dsmc_philox", "dsmc_device_copy", "dsmc_device_line_reads", "dig_couple", "dig_get", "dig_residual",
            "dig_solve", "dig_feedback", "dsmc_set_sums", "dsmc_set_rot_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
            "dsmc_mlp_get_weights", "dsmc_mlp_forward", "dsmc_mlp_backward", "dsmc_mlp_adam_step", "dsmc_mlp_train",
            "dsmc_mlp_init_weights", "dsmc_mlp_backward_noalloc", "dig_set_closure", "dig_closure_data", "dig_batch_enable", "dsmc_surface_sampling", "dsmc_get_surface",
@@ -203,6 +204,7 @@ EXPORTED = ["dsmc_init", "dsmc_step", "dsmc_step_stages", "dsmc_sample", "dsmc_g
             "dsmc_rot_sample", "dsmc_mesh_decompose", "dsmc_mesh_error", "dsmc_sample_cells", "dsmc_get_state",
             "dsmc_set_state", "dsmc_get_pair_counts", "dsmc_stats", "dsmc_sync", "dsmc_set_local_acc",
             "dsmc_profile", "dsmc_profile_read", "dsmc_profile_name", "dsmc_philox", "dsmc_device_copy",
+            "dsmc_device_line_reads",
             "dsmc_last_error", "dsmc_destroy", "dig_couple", "dig_get", "dig_residual", "dig_solve",
             "dig_feedback", "dsmc_set_sums", "dsmc_set_rot_sums", "dsmc_mlp_create", "dsmc_mlp_set_weights",
             "dsmc_mlp_get_weights",
@@ -513,6 +515,10 @@ class Simulation:
 
     def device_copy(self, dst, src, nbytes):
         self._c(_lib.dsmc_device_copy(self.ctx, P(dst), P(src), nbytes))
+
+    def device_line_reads(self, table, nbytes, sink, share, iters, blocks):
+        """Scattered 16-byte reads of 128-byte lines (dsmc_device_line_reads)."""
+        self._c(_lib.dsmc_device_line_reads(self.ctx, P(table), nbytes, P(sink), share, iters, blocks))
 
     def set_sums(self, which, sums, counts=None):
         a = np.ascontiguousarray(sums, np.float64)

@@ -3,7 +3,8 @@ DSMC_E_MESH at init (degenerate tet, a boundary triangle missing or matching
 no exterior face), invalid parameters DSMC_E_INVALID (non-positive time step or VSS exponent,
 particle cells out of range in set_state, negative reconstruction passes or
 acceleration depth, unknown kernel schedule, empty or negative training
-sets), and a context stays usable after an argument error."""
+sets, bad arguments of the line-read calibration), and a context stays
+usable after an argument error."""
 import numpy as np
 import pytest
 
@@ -101,3 +102,23 @@ def test_mlp_rejects_bad_training_sets(D):
     rep = net.train(x, t, steps=2, batch=0)
     assert rep["steps"] == 2
     net.close()
+
+
+def test_line_read_calibration_arguments(D):
+    """dsmc_device_line_reads: a valid call completes; a short or misaligned
+    table, a null sink, share not a power of two in [1, 64] and iters or
+    blocks out of range are DSMC_E_INVALID, and the context steps on."""
+    import torch
+    g = D.Simulation(_wl())
+    tab = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    g.device_line_reads(tab.data_ptr(), tab.numel(), sink.data_ptr(), 4, 8, 16)
+    g.sync()
+    assert int(sink.item()) == 0     # the loaded words are zero: the sum never matches
+    for bad in [dict(nbytes=64), dict(table=tab.data_ptr() + 4), dict(sink=0), dict(share=3), dict(share=128),
+                dict(share=0), dict(iters=0), dict(iters=(1 << 20) + 1), dict(blocks=0)]:
+        a = dict(table=tab.data_ptr(), nbytes=tab.numel(), sink=sink.data_ptr(), share=4, iters=8, blocks=16)
+        a.update(bad)
+        assert _status(D, lambda: g.device_line_reads(**a)) == E_INVALID, bad
+    g.step(1)
+    g.close()
