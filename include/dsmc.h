@@ -367,8 +367,8 @@ dsmc_status dsmc_device_copy(dsmc_ctx ctx, void* dst, const void* src, size_t by
  * memory, at least 128 bytes, 16-byte aligned, read only.  sink: 4 bytes of
  * device memory, written only if the sum of the loaded words equals a fixed
  * constant.  DSMC_E_INVALID for null pointers, a short or misaligned table,
- * share not a power of two in [1, 64], iters outside [1, 2^20] or blocks
- * outside [1, 2^24]. */
+ * share not a power of two in [1, 64], iters outside [1, 4096] or blocks
+ * outside [1, 65536] (at most about 7e10 loads, a fraction of a second). */
 dsmc_status dsmc_device_line_reads(dsmc_ctx ctx, const void* table, size_t bytes, void* sink, int share, int iters,
                                    int blocks);
 

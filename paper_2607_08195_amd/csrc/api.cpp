@@ -1464,8 +1464,8 @@ dsmc_status dsmc_device_line_reads(dsmc_ctx c, const void* table, size_t bytes, 
                                    int blocks) {
     if (!c || !table || !sink || bytes < 128 || ((uintptr_t)table % 16) != 0 || ((uintptr_t)sink % 4) != 0)
         return fail(c, DSMC_E_INVALID, "bad arguments (table of at least 128 bytes, 16-byte aligned; sink)");
-    if (share < 1 || share > 64 || (share & (share - 1)) != 0 || iters < 1 || iters > (1 << 20) || blocks < 1 ||
-        blocks > (1 << 24))
+    if (share < 1 || share > 64 || (share & (share - 1)) != 0 || iters < 1 || iters > 4096 || blocks < 1 ||
+        blocks > 65536)
         return fail(c, DSMC_E_INVALID, "bad arguments (share a power of two in [1, 64], iters, blocks)");
     uint64_t lines = 1;
     while (lines * 2 <= bytes / 128 && lines * 2 <= (1ull << 32)) lines *= 2;

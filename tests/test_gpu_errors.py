@@ -116,7 +116,7 @@ def test_line_read_calibration_arguments(D):
     g.sync()
     assert int(sink.item()) == 0     # the loaded words are zero: the sum never matches
     for bad in [dict(nbytes=64), dict(table=tab.data_ptr() + 4), dict(sink=0), dict(share=3), dict(share=128),
-                dict(share=0), dict(iters=0), dict(iters=(1 << 20) + 1), dict(blocks=0)]:
+                dict(share=0), dict(iters=0), dict(iters=4097), dict(blocks=0), dict(blocks=65537)]:
         a = dict(table=tab.data_ptr(), nbytes=tab.numel(), sink=sink.data_ptr(), share=4, iters=8, blocks=16)
         a.update(bad)
         assert _status(D, lambda: g.device_line_reads(**a)) == E_INVALID, bad
