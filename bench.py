@@ -917,8 +917,8 @@ def main():
     args = ap.parse_args()
     args.graph = not args.eager
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a "
-              "design note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is "
+              "described, not implemented", file=sys.stderr)
         sys.exit(2)
 
     procs = args.cpu_procs or max(1, min(16, os.cpu_count() or 1))

@@ -7,7 +7,8 @@
  * gradients, so that the coupling step (Algorithm 1) can take a smooth
  * prediction where the sampled HoT is noisy.  This closure is an addition
  * of this library, not part of the paper's method; the plain sampled HoT
- * stays the fallback and the judge of every prediction (dig_set_closure).
+ * stays the fallback and the test every prediction must pass
+ * (dig_set_closure).
  *
  * Network: 13 inputs -> 128 -> 128 -> 128 -> 9 outputs, SiLU on the hidden
  * layers.  Inputs per cell, nondimensional: lambda du_i/dx_j / sqrt(RT)
