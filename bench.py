@@ -861,8 +861,8 @@ def bench_dig_bias(args, dsmc, W):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="cavity_large",
                     choices=["cavity_large", "cavity_small", "cavity_vss", "cavity_n2", "cavity_mixed",
                              "ensemble64", "dig_cavity40", "time_to_fields", "dig_bias", "coarse_fields", "sphere"])
