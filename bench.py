@@ -46,7 +46,7 @@ STAGES = {"move": ["move", "move_walls"], "scan": ["scan"], "sort": ["sort_perm"
 # WRITE_SIZE per step, summed over the stage's kernels and scaled by the
 # copy-kernel calibration) and the source digest they were taken on; the
 # traffic figure is reported only while the digest matches.
-TRAFFIC = {"stage": "move", "digest": "e71c6d34ff86ff7a", "bytes_per_launch": 1255456291,
+TRAFFIC = {"stage": "move", "digest": "f678485dc442d1cf", "bytes_per_launch": 1255226834,
            "workload": "cavity_40^3x6_Kn0.1", "source": "profiles/step_kernels_cavity40.md"}
 
 
@@ -55,7 +55,7 @@ TRAFFIC = {"stage": "move", "digest": "e71c6d34ff86ff7a", "bytes_per_launch": 12
 # the same source digest: the move kernel's bound is the L1's line-access
 # rate, set by its divergent 16-byte loads of the cells' planes and
 # neighbour codes.
-L1 = {"kernel": "move", "digest": "e71c6d34ff86ff7a", "accesses_per_launch": 302300000,
+L1 = {"kernel": "move", "digest": "f678485dc442d1cf", "accesses_per_launch": 302200000,
       "workload": "cavity_40^3x6_Kn0.1", "source": "profiles/step_kernels_cavity40.md"}
 
 

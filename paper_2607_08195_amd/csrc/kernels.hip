@@ -295,6 +295,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     double dt, WallQueue q, PartDev<VT> src, const int32_t* gperm) {
     const int64_t i = xcd_block() * 256 + threadIdx.x;
     const int64_t n = sc->np;
+    // A workgroup past the last particle leaves at once (the grid of a
+    // context with inflow covers the whole store); the test is uniform over
+    // the workgroup, so no lane skips a barrier the others reach.
+    if (xcd_block() * 256 >= n) return;
     int hops = 0, walls = 0, rem = 0, lost = 0, dest = -1;
     bool park = false;
     Walker w{};
